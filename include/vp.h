@@ -1,0 +1,295 @@
+/*
+ * vp.h -- C ABI of the MI355X lifted-PROPELLER reconstruction library (libvp.so).
+ *
+ * The library fits a complex (x, y, spectral-offset[, time]) voxel grid to
+ * PROPELLER blade measurements (Ghosh, Wetzstein, Pilanci, Fridovich-Keil,
+ * CVPR 2024). Its operations follow the paper's statement of the problem:
+ *
+ *   volume V[t][s][y][x]    complex, Section 4.1 (static grid; a dense grid of T
+ *                           time knots stands in for the dynamic model)
+ *   forward  A V            Section 4.2: for every blade b, sum over spectral bins
+ *                           s of the bin's image shifted by delta_s along the
+ *                           blade's readout direction (bilinear, zero outside the
+ *                           grid), unitary 2D DFT, blade k-space mask
+ *   objective               Section 4.3: 0.5 sum_b |M_b(A V)_b - M_b y_b|^2
+ *                           + tv_weight TV(V) + l1_weight L1(V)
+ *   optimiser               Section 4.3: Adam (or plain gradient descent)
+ *   outputs                 Section 4.3 render at phi = 0 (sum over s), and the
+ *                           fat/water split of Section 6 (bins below split_bin are
+ *                           water, the rest fat)
+ *
+ * Conventions for every call:
+ *   - Every call returns vp_status: VP_OK (0) or a negative error code. No C++
+ *     exception crosses this boundary. vp_last_error() gives a thread-local
+ *     message for the last failing call on the calling thread.
+ *   - Complex arrays are interleaved (re, im) float32 pairs, C order, x fastest:
+ *     volumes [T][S][n][n], blade arrays [B][n][n], renders [T][n][n].
+ *   - k-space arrays use unshifted DFT order: index j holds the signed frequency
+ *     j for j <= (n-1)/2 and j - n otherwise, on both axes; the DFT is unitary.
+ *   - Angles are radians; shifts are pixels; blade times lie in [0, 1].
+ *   - The caller owns every buffer it passes. Opaque handles are released by
+ *     their *_destroy call, which accepts NULL.
+ *   - Plans are immutable after creation and may be shared between threads.
+ *   - "d_" pointers are device pointers on the current HIP device (for example
+ *     torch tensor storage): contiguous, 8-byte aligned, not aliased with each
+ *     other. Calls that take a `stream` (a hipStream_t, NULL = the null stream)
+ *     are asynchronous on it. All other pointers are host pointers.
+ *   - Device memory exhaustion yields VP_ERR_NOMEM; a failing HIP runtime call
+ *     yields VP_ERR_DEVICE.
+ */
+#ifndef VP_H
+#define VP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t vp_status;
+
+enum {
+    VP_OK = 0,
+    VP_ERR_ARG = -1,          /* NULL, non-finite or out-of-range argument */
+    VP_ERR_UNSUPPORTED = -2,  /* valid problem this build does not handle (size, shift range) */
+    VP_ERR_DEVICE = -3,       /* HIP runtime failure or no usable device */
+    VP_ERR_NONFINITE = -4,    /* non-finite measurement, or the objective became non-finite */
+    VP_ERR_BUDGET = -5,       /* a server request larger than the whole memory budget */
+    VP_ERR_NOMEM = -6,        /* device or host allocation failed */
+    VP_ERR_TIMEOUT = -7,      /* vp_server_wait timed out; the request keeps running */
+    VP_ERR_CANCELLED = -8,    /* the request was cancelled before it finished */
+    VP_ERR_NOT_FOUND = -9,    /* unknown request id */
+    VP_ERR_STATE = -10        /* call not valid in the object's current state */
+};
+
+typedef struct { float re, im; } vp_c64;
+
+typedef struct vp_plan vp_plan;
+typedef struct vp_session vp_session;
+typedef struct vp_server vp_server;
+
+/* Acquisition geometry (Section 4.2 "Projection" and "Blur").
+ *   n              image side; the grid is n x n and each blade's readout has n
+ *                  samples. Supported: 1 <= n <= 512 with no prime factor above 5.
+ *   n_spec         spectral bins S >= 1 (at most 256).
+ *   n_time         time knots T >= 1 (at most 64); 1 = static. Knot k sits at
+ *                  time k/(T-1); a blade at time tau sees the linear blend of
+ *                  knots floor(tau (T-1)) (clamped to T-2) and the next one.
+ *   n_blades       B >= 1 (at most 256).
+ *   angle_rad[B]   blade readout direction u_b = (cos, sin) in (x = column,
+ *                  y = row); finite.
+ *   lines[B]       blade width in k-space lines, 1 <= L <= n. The blade's
+ *                  support is the half-open rotated rectangle of length n along
+ *                  u_b and width L across it, ties broken by a 1e-9 margin.
+ *   blade_time[B]  acquisition time of each blade in [0, 1]; must be NULL iff
+ *                  n_time == 1.
+ *   spec_shift_px[S]  displacement, in pixels along u_b, of spectral bin s
+ *                  (tan(phi) times its off-resonance); finite, |shift| <= 16. */
+typedef struct {
+    int32_t n;
+    int32_t n_spec;
+    int32_t n_time;
+    int32_t n_blades;
+    const double* angle_rad;
+    const int32_t* lines;
+    const double* blade_time;
+    const double* spec_shift_px;
+} vp_geometry;
+
+enum { VP_OPT_ADAM = 0, VP_OPT_GD = 1 };
+enum { VP_SCHED_ALL_BLADES = 0, VP_SCHED_CYCLIC = 1 };
+
+/* Fit settings (Section 4.3). tv_eps is the Charbonnier epsilon of both the TV
+ * and the L1 term. A step is one optimiser update on the gradient summed over
+ * all blades (VP_SCHED_ALL_BLADES) or over blade (t-1) mod B only
+ * (VP_SCHED_CYCLIC, the paper's one-blade-per-iteration schedule). The volume
+ * starts at zero unless an initial volume is given. split_bin < 0 means S/2. */
+typedef struct {
+    float tv_weight;
+    float l1_weight;
+    float tv_eps;
+    int32_t n_steps;
+    int32_t optimizer;
+    float lr;
+    float beta1;
+    float beta2;
+    float adam_eps;
+    int32_t schedule;
+    int32_t split_bin;
+    int32_t device;
+} vp_options;
+
+/* Fills defaults: tv_weight 1e-3, l1_weight 0, tv_eps 1e-3, n_steps 200, Adam
+ * with lr 1e-2, betas (0.9, 0.999), eps 1e-8, all-blades schedule, split S/2,
+ * device 0. */
+vp_status vp_options_default(vp_options* opts);
+
+/* Static description of a status code; never NULL. */
+const char* vp_status_string(vp_status status);
+
+/* Thread-local message for the last failing call on this thread ("" if none). */
+const char* vp_last_error(void);
+
+/* ------------------------------------------------------------------ plans */
+
+/* Validates the geometry and builds the host-side plan: blade masks (evaluated
+ * in FP64), the per-(blade, bin) bilinear shear table, blade-to-knot weights,
+ * DFT twiddles and launch tables. Touches no device. Errors: VP_ERR_ARG for
+ * NULL or non-finite input, sizes below 1, lines outside [1, n], blade times
+ * outside [0, 1] or a blade_time pointer that disagrees with n_time;
+ * VP_ERR_UNSUPPORTED for n, S, T or B above the limits above, n with a prime
+ * factor above 5, or shifts beyond 16 px. *out is set only on success. */
+vp_status vp_plan_create(const vp_geometry* geometry, vp_plan** out);
+
+/* Releases the plan and any per-device tables it holds. NULL is a no-op. The
+ * plan must not be in use by a running call, session or server request. */
+vp_status vp_plan_destroy(vp_plan* plan);
+
+/* Sizes of a plan. Any output pointer may be NULL. */
+vp_status vp_plan_shape(const vp_plan* plan, int32_t* n, int32_t* n_spec, int32_t* n_time, int32_t* n_blades);
+
+/* Blade b's k-space support as n*n bytes (1 = measured), unshifted order. */
+vp_status vp_plan_mask(const vp_plan* plan, int32_t b, uint8_t* out_n_by_n);
+
+/* Shear of blade b, bin s: the blade image at (x, y) takes bilinear taps of bin
+ * s at rows y+oy, y+oy+1 and columns x+ox, x+ox+1 with fractional weights
+ * (fx, fy), where (ox, oy) = floor(-d) and (fx, fy) = -d - floor(-d) for the
+ * displacement d = spec_shift_px[s] * u_b. Any output pointer may be NULL. */
+vp_status vp_plan_shear(const vp_plan* plan, int32_t b, int32_t s, int32_t* ox, int32_t* oy, float* fx, float* fy);
+
+/* Knot index k and blend weight a of blade b (0 and 0 for static plans). */
+vp_status vp_plan_knot(const vp_plan* plan, int32_t b, int32_t* knot, float* alpha);
+
+/* Exact device bytes one reconstruction of this plan allocates with these
+ * options (volume ping-pong, Adam moments, blade work images, measurements,
+ * tables, partial sums). Used for admission by memory budget. */
+vp_status vp_plan_device_bytes(const vp_plan* plan, const vp_options* opts, uint64_t* bytes);
+
+/* ------------------------------------------------------------------ operators (device pointers) */
+
+/* d_out[B][n][n] = M_b . DFT2(P_b V) - (d_y ? M_b . d_y : 0): the forward model
+ * of Section 4.2 applied to d_vol[T][S][n][n]. Device scratch of B*n*n complex
+ * values (twice that when T > 1) is taken from the stream-ordered allocator
+ * and released on the stream. */
+vp_status vp_forward(const vp_plan* plan, const vp_c64* d_vol, const vp_c64* d_y, vp_c64* d_out, void* stream);
+
+/* d_grad[T][S][n][n] (+)= A^H d_kres: blade mask, unitary inverse DFT and the
+ * transpose of the sheared projection (a gather, no atomics), with dynamic
+ * blades split onto their two knots with weights (1-a, a). For a real loss
+ * L(A V) with dL/d(AV) = d_kres (as dL/dRe + i dL/dIm) this is dL/dRe V +
+ * i dL/dIm V. accumulate != 0 adds to d_grad, otherwise overwrites it. */
+vp_status vp_adjoint(const vp_plan* plan, const vp_c64* d_kres, vp_c64* d_grad, int32_t accumulate, void* stream);
+
+/* d_grad (+)= tv_weight * grad TV(d_vol) + l1_weight * grad L1(d_vol)
+ * (Section 4.3: Charbonnier TV over x, y, s and t with forward differences
+ * where the neighbour exists; Charbonnier L1). */
+vp_status vp_tv_grad(const vp_plan* plan, const vp_c64* d_vol, float tv_weight, float l1_weight, float tv_eps,
+                     vp_c64* d_grad, int32_t accumulate, void* stream);
+
+/* Section 4.3 render at phi = 0 and the Section 6 split: d_proj[t] = sum over
+ * all bins, d_water = bins [0, split), d_fat = bins [split, S); split_bin < 0
+ * means S/2. Any output may be NULL. */
+vp_status vp_render(const vp_plan* plan, const vp_c64* d_vol, int32_t split_bin, vp_c64* d_proj, vp_c64* d_water,
+                    vp_c64* d_fat, void* stream);
+
+/* ------------------------------------------------------------------ sessions (resident state) */
+
+/* Uploads kspace[B][n][n] (host; off-mask values are ignored) and the initial
+ * volume (host [T][S][n][n], NULL = zeros) to opts->device and allocates the
+ * optimiser state there. VP_ERR_NONFINITE if kspace holds NaN or Inf. */
+vp_status vp_session_create(const vp_plan* plan, const vp_options* opts, const vp_c64* kspace, const vp_c64* init,
+                            vp_session** out);
+
+/* Runs n_steps optimiser steps on the device (use_graph != 0: one captured
+ * step replayed) and waits for them. */
+vp_status vp_session_step(vp_session* session, int32_t n_steps, int32_t use_graph);
+
+/* Steps taken so far. */
+vp_status vp_session_steps_done(const vp_session* session, int64_t* steps);
+
+/* Copies the current volume and renders to host buffers; any may be NULL. */
+vp_status vp_session_read(vp_session* session, vp_c64* volume_out, vp_c64* proj_out, vp_c64* water_out,
+                          vp_c64* fat_out);
+
+/* Objective (data + weighted TV and L1) at the current volume, over all blades. */
+vp_status vp_session_objective(vp_session* session, double* objective, double* data_term);
+
+/* Checkpoint: copies volume, Adam moments (interleaved (re, im) pairs, each
+ * shaped like the volume) and the step count to host buffers. */
+vp_status vp_session_get_state(vp_session* session, vp_c64* volume, vp_c64* m, vp_c64* v, int64_t* step);
+
+/* Resume: restores what vp_session_get_state returned. */
+vp_status vp_session_set_state(vp_session* session, const vp_c64* volume, const vp_c64* m, const vp_c64* v,
+                               int64_t step);
+
+vp_status vp_session_destroy(vp_session* session);
+
+/* ------------------------------------------------------------------ whole reconstructions */
+
+/* One synchronous reconstruction: opts->n_steps steps from init (NULL = zero)
+ * on opts->device. Outputs (host, any may be NULL): volume [T][S][n][n], proj,
+ * water, fat [T][n][n], and the objective at the returned volume. */
+vp_status vp_reconstruct(const vp_plan* plan, const vp_options* opts, const vp_c64* kspace, const vp_c64* init,
+                         vp_c64* volume_out, vp_c64* proj_out, vp_c64* water_out, vp_c64* fat_out,
+                         double* final_loss);
+
+/* Output slots of one batched or served reconstruction; NULL pointers skip. */
+typedef struct {
+    vp_c64* volume_out;
+    vp_c64* proj_out;
+    vp_c64* water_out;
+    vp_c64* fat_out;
+    double final_loss;
+    int64_t steps_done;
+    vp_status status;
+} vp_result;
+
+/* Many independent slices, possibly of different sizes, reconstructed together
+ * on opts[0]->device: each step is one persistent launch per stage over all
+ * slices, captured once in a HIP graph and replayed. Every slice's result is
+ * the one vp_reconstruct gives it alone (bit for bit: summation orders do not
+ * depend on the batch). Per-slice status goes to results[i]->status; the call
+ * returns the first failure, if any. */
+vp_status vp_batch_reconstruct(int32_t n, const vp_plan* const* plans, const vp_options* const* opts,
+                               const vp_c64* const* kspace, vp_result* const* results);
+
+/* ------------------------------------------------------------------ serving */
+
+/* A reconstruction server on one device: requests are admitted while the sum
+ * of their vp_plan_device_bytes stays within hbm_budget and at most max_slots
+ * run at once; all admitted requests advance together, one step per
+ * super-step, and new requests join between super-steps (continuous batching).
+ * The server is thread-safe. */
+vp_status vp_server_create(int32_t device, uint64_t hbm_budget, int32_t max_slots, vp_server** out);
+
+/* Queues a request. The inputs are copied before the call returns (plan is
+ * referenced and must outlive the request). VP_ERR_BUDGET if the request alone
+ * exceeds the budget; VP_ERR_NONFINITE for a non-finite kspace. */
+vp_status vp_server_submit(vp_server* server, const vp_plan* plan, const vp_options* opts, const vp_c64* kspace,
+                           uint64_t* request_id);
+
+/* Waits up to timeout_us (< 0: forever) for a request, then copies its outputs
+ * into *result and forgets it. Returns the request's status, VP_ERR_TIMEOUT,
+ * or VP_ERR_NOT_FOUND. */
+vp_status vp_server_wait(vp_server* server, uint64_t request_id, int64_t timeout_us, vp_result* result);
+
+/* Non-blocking: *done = 1 when the request has finished (or failed). */
+vp_status vp_server_poll(vp_server* server, uint64_t request_id, int32_t* done);
+
+/* Cancels a queued or running request; its wait returns VP_ERR_CANCELLED. */
+vp_status vp_server_cancel(vp_server* server, uint64_t request_id);
+
+/* Latency statistics in microseconds (completion minus submission) over
+ * finished requests, and completed requests per second of server wall time. */
+vp_status vp_server_stats(vp_server* server, double* p50_us, double* p99_us, double* throughput_rps,
+                          int64_t* completed);
+
+/* Stops the worker after the running super-step; unfinished requests fail
+ * with VP_ERR_CANCELLED. */
+vp_status vp_server_destroy(vp_server* server);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VP_H */

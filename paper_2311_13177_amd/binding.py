@@ -1,0 +1,385 @@
+"""ctypes binding of libvp.so: the C ABI of include/vp.h with the same names.
+
+The functions below only marshal arguments. Every step of the reconstruction runs in
+the HIP library; if the library is missing or cannot load, ``lib()`` raises instead
+of falling back to anything else. Device arrays are torch tensors (PyTorch is used
+for device memory and streams only); host arrays are NumPy arrays.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_double, c_float, c_int32, c_int64, c_uint8, c_uint64, c_void_p
+from typing import Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libvp.so")
+
+VP_OK = 0
+VP_ERR_ARG = -1
+VP_ERR_UNSUPPORTED = -2
+VP_ERR_DEVICE = -3
+VP_ERR_NONFINITE = -4
+VP_ERR_BUDGET = -5
+VP_ERR_NOMEM = -6
+VP_ERR_TIMEOUT = -7
+VP_ERR_CANCELLED = -8
+VP_ERR_NOT_FOUND = -9
+VP_ERR_STATE = -10
+
+VP_OPT_ADAM = 0
+VP_OPT_GD = 1
+VP_SCHED_ALL_BLADES = 0
+VP_SCHED_CYCLIC = 1
+
+
+class VPError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+class vp_geometry(ctypes.Structure):
+    _fields_ = [("n", c_int32), ("n_spec", c_int32), ("n_time", c_int32), ("n_blades", c_int32),
+                ("angle_rad", POINTER(c_double)), ("lines", POINTER(c_int32)),
+                ("blade_time", POINTER(c_double)), ("spec_shift_px", POINTER(c_double))]
+
+
+class vp_options(ctypes.Structure):
+    _fields_ = [("tv_weight", c_float), ("l1_weight", c_float), ("tv_eps", c_float), ("n_steps", c_int32),
+                ("optimizer", c_int32), ("lr", c_float), ("beta1", c_float), ("beta2", c_float),
+                ("adam_eps", c_float), ("schedule", c_int32), ("split_bin", c_int32), ("device", c_int32)]
+
+
+class vp_result(ctypes.Structure):
+    _fields_ = [("volume_out", c_void_p), ("proj_out", c_void_p), ("water_out", c_void_p),
+                ("fat_out", c_void_p), ("final_loss", c_double), ("steps_done", c_int64),
+                ("status", c_int32)]
+
+
+_P = c_void_p
+_PROTOS = {
+    "vp_options_default": (c_int32, [POINTER(vp_options)]),
+    "vp_status_string": (ctypes.c_char_p, [c_int32]),
+    "vp_last_error": (ctypes.c_char_p, []),
+    "vp_plan_create": (c_int32, [POINTER(vp_geometry), POINTER(_P)]),
+    "vp_plan_destroy": (c_int32, [_P]),
+    "vp_plan_shape": (c_int32, [_P, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32), POINTER(c_int32)]),
+    "vp_plan_mask": (c_int32, [_P, c_int32, POINTER(c_uint8)]),
+    "vp_plan_shear": (c_int32, [_P, c_int32, c_int32, POINTER(c_int32), POINTER(c_int32), POINTER(c_float),
+                                POINTER(c_float)]),
+    "vp_plan_knot": (c_int32, [_P, c_int32, POINTER(c_int32), POINTER(c_float)]),
+    "vp_plan_device_bytes": (c_int32, [_P, POINTER(vp_options), POINTER(c_uint64)]),
+    "vp_forward": (c_int32, [_P, _P, _P, _P, _P]),
+    "vp_adjoint": (c_int32, [_P, _P, _P, c_int32, _P]),
+    "vp_tv_grad": (c_int32, [_P, _P, c_float, c_float, c_float, _P, c_int32, _P]),
+    "vp_render": (c_int32, [_P, _P, c_int32, _P, _P, _P, _P]),
+    "vp_session_create": (c_int32, [_P, POINTER(vp_options), _P, _P, POINTER(_P)]),
+    "vp_session_step": (c_int32, [_P, c_int32, c_int32]),
+    "vp_session_steps_done": (c_int32, [_P, POINTER(c_int64)]),
+    "vp_session_read": (c_int32, [_P, _P, _P, _P, _P]),
+    "vp_session_objective": (c_int32, [_P, POINTER(c_double), POINTER(c_double)]),
+    "vp_session_get_state": (c_int32, [_P, _P, _P, _P, POINTER(c_int64)]),
+    "vp_session_set_state": (c_int32, [_P, _P, _P, _P, c_int64]),
+    "vp_session_destroy": (c_int32, [_P]),
+    "vp_reconstruct": (c_int32, [_P, POINTER(vp_options), _P, _P, _P, _P, _P, _P, POINTER(c_double)]),
+    "vp_batch_reconstruct": (c_int32, [c_int32, POINTER(_P), POINTER(POINTER(vp_options)), POINTER(_P),
+                                       POINTER(POINTER(vp_result))]),
+    "vp_server_create": (c_int32, [c_int32, c_uint64, c_int32, POINTER(_P)]),
+    "vp_server_submit": (c_int32, [_P, _P, POINTER(vp_options), _P, POINTER(c_uint64)]),
+    "vp_server_wait": (c_int32, [_P, c_uint64, c_int64, POINTER(vp_result)]),
+    "vp_server_poll": (c_int32, [_P, c_uint64, POINTER(c_int32)]),
+    "vp_server_cancel": (c_int32, [_P, c_uint64]),
+    "vp_server_stats": (c_int32, [_P, POINTER(c_double), POINTER(c_double), POINTER(c_double),
+                                  POINTER(c_int64)]),
+    "vp_server_destroy": (c_int32, [_P]),
+}
+
+_lib: Optional[ctypes.CDLL] = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library. Raises if libvp.so has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(python -m paper_2311_13177_amd.build)")
+        handle = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _PROTOS.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+def exported_names() -> list[str]:
+    return list(_PROTOS)
+
+
+def check(status: int) -> None:
+    if status != VP_OK:
+        msg = lib().vp_last_error().decode() or lib().vp_status_string(status).decode()
+        raise VPError(status, msg)
+
+
+def _dptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(POINTER(ctype))
+
+
+def _host_c64(a: Optional[np.ndarray], shape=None) -> Optional[np.ndarray]:
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=np.complex64)
+    if shape is not None and a.shape != tuple(shape):
+        raise ValueError(f"expected shape {tuple(shape)}, got {a.shape}")
+    return a
+
+
+def _hp(a: Optional[np.ndarray]):
+    return None if a is None else c_void_p(a.ctypes.data)
+
+
+# ------------------------------------------------------------------ options
+
+def vp_options_default(**overrides) -> vp_options:
+    o = vp_options()
+    check(lib().vp_options_default(byref(o)))
+    for k, v in overrides.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+# ------------------------------------------------------------------ plans
+
+class Plan:
+    """Owns a vp_plan built by vp_plan_create from a geometry."""
+
+    def __init__(self, n: int, n_spec: int, n_time: int, angle_rad, lines, blade_time, spec_shift_px):
+        self._angle = np.ascontiguousarray(angle_rad, dtype=np.float64)
+        self._lines = np.ascontiguousarray(lines, dtype=np.int32)
+        self._time = None if blade_time is None else np.ascontiguousarray(blade_time, dtype=np.float64)
+        self._shift = np.ascontiguousarray(spec_shift_px, dtype=np.float64)
+        g = vp_geometry(n=n, n_spec=n_spec, n_time=n_time, n_blades=int(self._angle.shape[0]),
+                        angle_rad=_dptr(self._angle, c_double), lines=_dptr(self._lines, c_int32),
+                        blade_time=None if self._time is None else _dptr(self._time, c_double),
+                        spec_shift_px=_dptr(self._shift, c_double))
+        h = c_void_p()
+        check(lib().vp_plan_create(byref(g), byref(h)))
+        self.handle = h
+        self.n, self.n_spec, self.n_time, self.n_blades = n, n_spec, n_time, int(self._angle.shape[0])
+
+    @classmethod
+    def from_geometry(cls, g: dict) -> "Plan":
+        return cls(int(g["n"]), int(g["n_spec"]), int(g["n_time"]), g["angle_rad"], g["lines"],
+                   g.get("blade_time"), g["spec_shift_px"])
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.vp_plan_destroy(h)
+            self.handle = None
+
+    @property
+    def volume_shape(self):
+        return (self.n_time, self.n_spec, self.n, self.n)
+
+    @property
+    def blade_shape(self):
+        return (self.n_blades, self.n, self.n)
+
+    @property
+    def render_shape(self):
+        return (self.n_time, self.n, self.n)
+
+    def mask(self, b: int) -> np.ndarray:
+        out = np.empty((self.n, self.n), dtype=np.uint8)
+        check(lib().vp_plan_mask(self.handle, b, _dptr(out, c_uint8)))
+        return out.astype(bool)
+
+    def masks(self) -> np.ndarray:
+        return np.stack([self.mask(b) for b in range(self.n_blades)])
+
+    def shear(self, b: int, s: int):
+        ox, oy, fx, fy = c_int32(), c_int32(), c_float(), c_float()
+        check(lib().vp_plan_shear(self.handle, b, s, byref(ox), byref(oy), byref(fx), byref(fy)))
+        return ox.value, oy.value, fx.value, fy.value
+
+    def knot(self, b: int):
+        k, a = c_int32(), c_float()
+        check(lib().vp_plan_knot(self.handle, b, byref(k), byref(a)))
+        return k.value, a.value
+
+    def device_bytes(self, opts: Optional[vp_options] = None) -> int:
+        out = c_uint64()
+        check(lib().vp_plan_device_bytes(self.handle, None if opts is None else byref(opts), byref(out)))
+        return int(out.value)
+
+
+# ------------------------------------------------------------------ operators on torch device tensors
+
+def _dev(t, shape, name):
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.complex64:
+        raise TypeError(f"{name} must be a complex64 GPU tensor")
+    if tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous with shape {tuple(shape)}, got {tuple(t.shape)}")
+    return c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return c_void_p(stream.cuda_stream)
+
+
+def vp_forward(plan: Plan, vol, y=None, out=None, stream=None):
+    """out = M . DFT2(P vol) - M . y on the GPU (torch tensors); returns out."""
+    import torch
+
+    if out is None:
+        out = torch.empty(plan.blade_shape, dtype=torch.complex64, device=vol.device)
+    check(lib().vp_forward(plan.handle, _dev(vol, plan.volume_shape, "vol"),
+                           None if y is None else _dev(y, plan.blade_shape, "y"),
+                           _dev(out, plan.blade_shape, "out"), _stream(stream)))
+    return out
+
+
+def vp_adjoint(plan: Plan, kres, grad=None, accumulate: bool = False, stream=None):
+    """grad (+)= A^H kres on the GPU; returns grad."""
+    import torch
+
+    if grad is None:
+        grad = torch.empty(plan.volume_shape, dtype=torch.complex64, device=kres.device)
+        accumulate = False
+    check(lib().vp_adjoint(plan.handle, _dev(kres, plan.blade_shape, "kres"),
+                           _dev(grad, plan.volume_shape, "grad"), int(bool(accumulate)), _stream(stream)))
+    return grad
+
+
+def vp_tv_grad(plan: Plan, vol, tv_weight: float, l1_weight: float, tv_eps: float, grad=None,
+               accumulate: bool = False, stream=None):
+    import torch
+
+    if grad is None:
+        grad = torch.empty(plan.volume_shape, dtype=torch.complex64, device=vol.device)
+        accumulate = False
+    check(lib().vp_tv_grad(plan.handle, _dev(vol, plan.volume_shape, "vol"), float(tv_weight), float(l1_weight),
+                           float(tv_eps), _dev(grad, plan.volume_shape, "grad"), int(bool(accumulate)),
+                           _stream(stream)))
+    return grad
+
+
+def vp_render(plan: Plan, vol, split_bin: int = -1, stream=None):
+    import torch
+
+    shp = plan.render_shape
+    outs = [torch.empty(shp, dtype=torch.complex64, device=vol.device) for _ in range(3)]
+    check(lib().vp_render(plan.handle, _dev(vol, plan.volume_shape, "vol"), int(split_bin),
+                          *[_dev(o, shp, "render") for o in outs], _stream(stream)))
+    return tuple(outs)
+
+
+# ------------------------------------------------------------------ sessions and reconstructions
+
+class Session:
+    """Resident reconstruction state on one device (vp_session_*)."""
+
+    def __init__(self, plan: Plan, kspace: np.ndarray, opts: Optional[vp_options] = None,
+                 init: Optional[np.ndarray] = None):
+        self.plan = plan
+        self.opts = opts if opts is not None else vp_options_default()
+        self._k = _host_c64(kspace, plan.blade_shape)
+        i = _host_c64(init, plan.volume_shape)
+        h = c_void_p()
+        check(lib().vp_session_create(plan.handle, byref(self.opts), _hp(self._k), _hp(i), byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().vp_session_destroy(self.handle)
+        self.handle = None
+
+    __del__ = close
+
+    def step(self, n_steps: int, use_graph: bool = True):
+        check(lib().vp_session_step(self.handle, int(n_steps), int(bool(use_graph))))
+
+    @property
+    def steps_done(self) -> int:
+        v = c_int64()
+        check(lib().vp_session_steps_done(self.handle, byref(v)))
+        return int(v.value)
+
+    def read(self):
+        p = self.plan
+        vol = np.empty(p.volume_shape, np.complex64)
+        outs = [np.empty(p.render_shape, np.complex64) for _ in range(3)]
+        check(lib().vp_session_read(self.handle, _hp(vol), *[_hp(o) for o in outs]))
+        return dict(vol=vol, proj=outs[0], water=outs[1], fat=outs[2])
+
+    def objective(self):
+        o, d = c_double(), c_double()
+        check(lib().vp_session_objective(self.handle, byref(o), byref(d)))
+        return float(o.value), float(d.value)
+
+    def get_state(self):
+        p = self.plan
+        vol = np.empty(p.volume_shape, np.complex64)
+        m = np.empty(p.volume_shape, np.complex64)
+        v = np.empty(p.volume_shape, np.complex64)
+        st = c_int64()
+        check(lib().vp_session_get_state(self.handle, _hp(vol), _hp(m), _hp(v), byref(st)))
+        return dict(vol=vol, m=m, v=v, step=int(st.value))
+
+    def set_state(self, state: dict):
+        p = self.plan
+        vol = _host_c64(state["vol"], p.volume_shape)
+        m = _host_c64(state.get("m"), p.volume_shape)
+        v = _host_c64(state.get("v"), p.volume_shape)
+        check(lib().vp_session_set_state(self.handle, _hp(vol), _hp(m), _hp(v), int(state["step"])))
+
+
+def vp_reconstruct(plan: Plan, kspace: np.ndarray, opts: Optional[vp_options] = None,
+                   init: Optional[np.ndarray] = None) -> dict:
+    opts = opts if opts is not None else vp_options_default()
+    k = _host_c64(kspace, plan.blade_shape)
+    i = _host_c64(init, plan.volume_shape)
+    vol = np.empty(plan.volume_shape, np.complex64)
+    outs = [np.empty(plan.render_shape, np.complex64) for _ in range(3)]
+    loss = c_double()
+    check(lib().vp_reconstruct(plan.handle, byref(opts), _hp(k), _hp(i), _hp(vol), *[_hp(o) for o in outs],
+                               byref(loss)))
+    return dict(vol=vol, proj=outs[0], water=outs[1], fat=outs[2], final_loss=float(loss.value))
+
+
+def vp_batch_reconstruct(plans: Sequence[Plan], kspaces: Sequence[np.ndarray],
+                         opts: Sequence[vp_options]) -> list[dict]:
+    n = len(plans)
+    ks = [_host_c64(k, p.blade_shape) for p, k in zip(plans, kspaces)]
+    vols = [np.empty(p.volume_shape, np.complex64) for p in plans]
+    rend = [[np.empty(p.render_shape, np.complex64) for _ in range(3)] for p in plans]
+    res = [vp_result(volume_out=v.ctypes.data, proj_out=r[0].ctypes.data, water_out=r[1].ctypes.data,
+                     fat_out=r[2].ctypes.data) for v, r in zip(vols, rend)]
+    plan_arr = (c_void_p * n)(*[p.handle.value for p in plans])
+    opt_arr = (POINTER(vp_options) * n)(*[ctypes.pointer(o) for o in opts])
+    k_arr = (c_void_p * n)(*[k.ctypes.data for k in ks])
+    res_arr = (POINTER(vp_result) * n)(*[ctypes.pointer(r) for r in res])
+    status = lib().vp_batch_reconstruct(n, plan_arr, opt_arr, k_arr, res_arr)
+    out = []
+    for i in range(n):
+        out.append(dict(vol=vols[i], proj=rend[i][0], water=rend[i][1], fat=rend[i][2],
+                        final_loss=float(res[i].final_loss), steps_done=int(res[i].steps_done),
+                        status=int(res[i].status)))
+    if status != VP_OK and all(r["status"] == VP_OK for r in out):
+        check(status)
+    return out

@@ -1,0 +1,202 @@
+// Batched reconstruction: many independent slices of different sizes advance together,
+// one launch per stage over the concatenated work lists of every slice, with the whole
+// step captured once in a HIP graph and replayed. Each slice keeps its own device
+// step counter and stops at its own step count; its arithmetic is the same as alone.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <memory>
+#include <vector>
+
+#include "plan.h"
+#include "runtime.h"
+
+namespace vp {
+
+// Device-resident group of slices sharing one stream: descriptors, concatenated work
+// lists and (optionally) a captured step.
+struct SliceGroup {
+    int device = -1;
+    hipStream_t stream = nullptr;
+    SliceDesc* d_descs = nullptr;
+    Task* d_tasks = nullptr;
+    StageLists lists{};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    ~SliceGroup() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (d_descs) (void)hipFree(d_descs);
+        if (d_tasks) (void)hipFree(d_tasks);
+    }
+};
+
+// Builds descriptors and concatenated work lists for `sessions` (slice i = sessions[i]).
+vp_status group_build(SliceGroup* g, const std::vector<vp_session*>& sessions, const std::vector<int>& limits) {
+    const int ns = (int)sessions.size();
+    std::vector<SliceDesc> descs(ns);
+    std::vector<Task> proj, rows, cols, gath, vox, render, one;
+    StageLists L;
+    for (int i = 0; i < ns; ++i) {
+        const vp_plan* p = sessions[i]->plan;
+        descs[i] = sessions[i]->desc;
+        descs[i].step_limit = limits[i];
+        auto add = [i](std::vector<Task>& dst, const std::vector<Task>& src) {
+            for (Task t : src) {
+                t.slice = i;
+                dst.push_back(t);
+            }
+        };
+        add(proj, p->t_proj);
+        add(rows, p->t_rows);
+        add(cols, p->t_cols);
+        add(gath, p->t_gath);
+        add(vox, p->t_vox);
+        add(render, p->t_render);
+        one.push_back(Task{i, 0, 0, 0});
+        L.lds_proj = std::max(L.lds_proj, p->lds_proj);
+        L.lds_rows = std::max(L.lds_rows, p->lds_rows);
+        L.lds_cols = std::max(L.lds_cols, p->lds_cols);
+        L.lds_gath = std::max(L.lds_gath, p->lds_gath);
+    }
+    std::vector<Task> all;
+    size_t off[7];
+    const std::vector<Task>* parts[7] = {&proj, &rows, &cols, &gath, &vox, &render, &one};
+    for (int k = 0; k < 7; ++k) {
+        off[k] = all.size();
+        all.insert(all.end(), parts[k]->begin(), parts[k]->end());
+    }
+    if (g->d_descs) (void)hipFree(g->d_descs);
+    if (g->d_tasks) (void)hipFree(g->d_tasks);
+    g->d_descs = nullptr;
+    g->d_tasks = nullptr;
+    hipError_t e = hipMalloc((void**)&g->d_descs, std::max<size_t>(1, descs.size()) * sizeof(SliceDesc));
+    if (e == hipSuccess) e = hipMalloc((void**)&g->d_tasks, std::max<size_t>(1, all.size()) * sizeof(Task));
+    if (e == hipSuccess && ns)
+        e = hipMemcpyAsync(g->d_descs, descs.data(), descs.size() * sizeof(SliceDesc), hipMemcpyHostToDevice,
+                           g->stream);
+    if (e == hipSuccess && !all.empty())
+        e = hipMemcpyAsync(g->d_tasks, all.data(), all.size() * sizeof(Task), hipMemcpyHostToDevice, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return hip_status(e, "slice group upload");
+    L.proj = g->d_tasks + off[0]; L.n_proj = (int)proj.size();
+    L.rows = g->d_tasks + off[1]; L.n_rows = (int)rows.size();
+    L.cols = g->d_tasks + off[2]; L.n_cols = (int)cols.size();
+    L.gath = g->d_tasks + off[3]; L.n_gath = (int)gath.size();
+    L.vox = g->d_tasks + off[4]; L.n_vox = (int)vox.size();
+    L.render = g->d_tasks + off[5]; L.n_render = (int)render.size();
+    L.one = g->d_tasks + off[6]; L.n_one = (int)one.size();
+    g->lists = L;
+    return VP_OK;
+}
+
+// Enqueues n_steps steps of every slice in the group; use_graph captures one step once.
+vp_status group_run(SliceGroup* g, int n_steps, bool use_graph) {
+    KArgs a{};
+    a.descs = g->d_descs;
+    hipError_t e;
+    if (use_graph) {
+        if (!g->gexec) {
+            e = hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return hip_status(e, "hipStreamBeginCapture");
+            hipError_t le = hipSuccess;
+            launch_step(a, g->lists, g->stream, &le);
+            e = hipStreamEndCapture(g->stream, &g->graph);
+            if (le != hipSuccess) return hip_status(le, "batched step capture");
+            if (e != hipSuccess) return hip_status(e, "hipStreamEndCapture");
+            e = hipGraphInstantiate(&g->gexec, g->graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) return hip_status(e, "hipGraphInstantiate");
+        }
+        for (int i = 0; i < n_steps; ++i)
+            if ((e = hipGraphLaunch(g->gexec, g->stream)) != hipSuccess) return hip_status(e, "hipGraphLaunch");
+    } else {
+        for (int i = 0; i < n_steps; ++i) {
+            launch_step(a, g->lists, g->stream, &e);
+            if (e != hipSuccess) return hip_status(e, "batched step launch");
+        }
+    }
+    return VP_OK;
+}
+
+}  // namespace vp
+
+using namespace vp;
+
+extern "C" vp_status vp_batch_reconstruct(int32_t n, const vp_plan* const* plans, const vp_options* const* opts,
+                                          const vp_c64* const* kspace, vp_result* const* results) {
+    clear_error();
+    if (n < 0 || (n > 0 && (!plans || !opts || !kspace || !results)))
+        return fail(VP_ERR_ARG, "vp_batch_reconstruct: bad argument");
+    if (n == 0) return VP_OK;
+    for (int i = 0; i < n; ++i)
+        if (!plans[i] || !opts[i] || !kspace[i] || !results[i])
+            return fail(VP_ERR_ARG, "vp_batch_reconstruct: NULL entry %d", i);
+    const int device = opts[0]->device;
+    hipError_t e = hipSetDevice(device);
+    if (e != hipSuccess) return hip_status(e, "hipSetDevice");
+    SliceGroup g;
+    g.device = device;
+    e = hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_status(e, "hipStreamCreate");
+    std::vector<std::unique_ptr<vp_session>> owned;
+    std::vector<vp_session*> sessions;
+    std::vector<int> limits;
+    std::vector<int> slot_of(n, -1);
+    vp_status first_err = VP_OK;
+    int max_steps = 0;
+    {
+        for (int i = 0; i < n; ++i) {
+            vp_options o = *opts[i];
+            o.device = device;
+            vp_session* s = nullptr;
+            vp_status st = session_alloc(plans[i], &o, kspace[i], nullptr, g.stream, &s);
+            results[i]->status = st;
+            results[i]->steps_done = 0;
+            results[i]->final_loss = 0.0;
+            if (st != VP_OK) {
+                if (first_err == VP_OK) first_err = st;
+                continue;
+            }
+            slot_of[i] = (int)sessions.size();
+            owned.emplace_back(s);
+            sessions.push_back(s);
+            limits.push_back(o.n_steps);
+            max_steps = std::max(max_steps, o.n_steps);
+        }
+        if (!sessions.empty()) {
+            vp_status st = group_build(&g, sessions, limits);
+            if (st == VP_OK) st = group_run(&g, max_steps, true);
+            if (st == VP_OK) st = hip_status(hipStreamSynchronize(g.stream), "batched steps");
+            if (st != VP_OK) {
+                owned.clear();
+                (void)hipStreamDestroy(g.stream);
+                g.stream = nullptr;
+                return st;
+            }
+            for (int i = 0; i < n; ++i) {
+                const int k = slot_of[i];
+                if (k < 0) continue;
+                vp_session* s = sessions[k];
+                s->steps_done = limits[k];
+                double obj = 0.0;
+                vp_status st2 = session_objective(s, &obj, nullptr);
+                vp_result* r = results[i];
+                r->final_loss = obj;
+                r->steps_done = limits[k];
+                const vp_status rs = session_read(s, r->volume_out, r->proj_out, r->water_out, r->fat_out);
+                if (st2 == VP_OK) st2 = rs;
+                r->status = st2;
+                if (st2 != VP_OK && first_err == VP_OK) first_err = st2;
+            }
+        }
+    }
+    owned.clear();
+    if (g.gexec) {
+        (void)hipGraphExecDestroy(g.gexec);
+        g.gexec = nullptr;
+    }
+    (void)hipStreamDestroy(g.stream);
+    g.stream = nullptr;
+    return first_err;
+}

@@ -1,0 +1,705 @@
+// HIP kernels (gfx950) of the lifted-PROPELLER hot path.
+//
+// Every kernel walks a list of work items (Task) with a grid-stride loop, so one
+// launch can cover one slice or many slices of different sizes; each item reads its
+// slice descriptor. Per-voxel and per-pixel summation orders depend only on the
+// slice's own plan (bins ascending, blades ascending, fixed tap order), never on
+// the batch or the tile that happens to hold the element.
+//
+// Stages of one optimiser step (Sections 4.2 and 4.3 of the paper):
+//   k_project   sheared spectral projection of a knot's volume for up to kGroup
+//               blade parts, from LDS-staged volume planes
+//   k_rows<FWD> blend of a blade's knot projections, forward DFT of every row
+//   k_cols      forward DFT of every column, 1/n scaling, blade mask, residual
+//               against the measurement, loss partials, inverse DFT of the column
+//   k_rows<INV> inverse DFT of every row: the image-space residual g_b
+//   k_gather    transposed shear as a gather over blades (no atomics) with a fused
+//               epilogue: TV/L1 gradient and the Adam or GD update
+
+#include <hip/hip_runtime.h>
+
+#include "vp.h"
+#include "vp_internal.h"
+
+namespace vp {
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ int step_of(const SliceDesc& d) { return d.step ? *d.step : 0; }
+__device__ __forceinline__ bool slice_done(const SliceDesc& d, int st) { return d.step && st >= d.step_limit; }
+__device__ __forceinline__ bool blade_active(const SliceDesc& d, int st, int b) {
+    return d.schedule != VP_SCHED_CYCLIC || d.step == nullptr || b == st % d.B;
+}
+__device__ __forceinline__ const float2* vol_cur(const SliceDesc& d, int st) {
+    return d.step ? d.vol[st & 1] : d.vol[0];
+}
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// (sign * i) * a
+template <int SIGN>
+__device__ __forceinline__ float2 mul_i(float2 a) {
+    return SIGN > 0 ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+// acc + w * a, one fused multiply-add per component
+__device__ __forceinline__ float2 cfma(float w, float2 a, float2 acc) {
+    return make_float2(__builtin_fmaf(w, a.x, acc.x), __builtin_fmaf(w, a.y, acc.y));
+}
+
+// ------------------------------------------------------------------ DFT in LDS
+//
+// Mixed-radix Stockham autosort (radices 2, 3, 4, 5). `count` transforms of length n
+// live in LDS: element j of transform f at buf[f * fstride + j * estride]. Each stage
+// reads one buffer and writes the other; the result ends in *out. DIR = -1 is the
+// forward transform exp(-2 pi i jk/n), DIR = +1 the unnormalised inverse.
+
+template <int DIR, int R>
+__device__ __forceinline__ void butterfly(float2 (&x)[R]) {
+    if constexpr (R == 2) {
+        const float2 a = x[0], b = x[1];
+        x[0] = cadd(a, b);
+        x[1] = csub(a, b);
+    } else if constexpr (R == 4) {
+        const float2 t0 = cadd(x[0], x[2]), t1 = csub(x[0], x[2]);
+        const float2 t2 = cadd(x[1], x[3]), t3 = mul_i<DIR>(csub(x[1], x[3]));
+        x[0] = cadd(t0, t2);
+        x[1] = cadd(t1, t3);
+        x[2] = csub(t0, t2);
+        x[3] = csub(t1, t3);
+    } else if constexpr (R == 3) {
+        const float s3 = 0.86602540378443864676f;  // sin(2 pi / 3)
+        const float2 t = cadd(x[1], x[2]);
+        const float2 u = mul_i<DIR>(cscale(csub(x[1], x[2]), s3));
+        const float2 h = make_float2(x[0].x - 0.5f * t.x, x[0].y - 0.5f * t.y);
+        x[0] = cadd(x[0], t);
+        x[1] = cadd(h, u);
+        x[2] = csub(h, u);
+    } else if constexpr (R == 5) {
+        const float c1 = 0.30901699437494742410f;   // cos(2 pi / 5)
+        const float c2 = -0.80901699437494742410f;  // cos(4 pi / 5)
+        const float s1 = 0.95105651629515357212f;   // sin(2 pi / 5)
+        const float s2 = 0.58778525229247312917f;   // sin(4 pi / 5)
+        const float2 a1 = cadd(x[1], x[4]), b1 = csub(x[1], x[4]);
+        const float2 a2 = cadd(x[2], x[3]), b2 = csub(x[2], x[3]);
+        const float2 x0 = x[0];
+        const float2 p1 = make_float2(x0.x + c1 * a1.x + c2 * a2.x, x0.y + c1 * a1.y + c2 * a2.y);
+        const float2 p2 = make_float2(x0.x + c2 * a1.x + c1 * a2.x, x0.y + c2 * a1.y + c1 * a2.y);
+        const float2 q1 = mul_i<DIR>(make_float2(s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y));
+        const float2 q2 = mul_i<DIR>(make_float2(s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y));
+        x[0] = cadd(x0, cadd(a1, a2));
+        x[1] = cadd(p1, q1);
+        x[2] = cadd(p2, q2);
+        x[3] = csub(p2, q2);
+        x[4] = csub(p1, q1);
+    }
+}
+
+template <int DIR, int R, bool FFAST>
+__device__ __forceinline__ void stockham_stage(const float2* __restrict__ src, float2* __restrict__ dst, int n,
+                                               int count, int fstride, int estride, int p,
+                                               const float2* __restrict__ tw) {
+    const int m = n / R;
+    const int total = m * count;
+    const int tws = n / (p * R);
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        int f, j;
+        if (FFAST) {
+            f = idx % count;
+            j = idx / count;
+        } else {
+            j = idx % m;
+            f = idx / m;
+        }
+        const int k = j % p;
+        const int bin = f * fstride + j * estride;
+        const int bout = f * fstride + ((j - k) * R + k) * estride;
+        float2 x[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) x[q] = src[bin + q * m * estride];
+#pragma unroll
+        for (int q = 1; q < R; ++q) {
+            float2 w = tw[k * q * tws];
+            if (DIR > 0) w.y = -w.y;
+            x[q] = cmul(x[q], w);
+        }
+        butterfly<DIR, R>(x);
+#pragma unroll
+        for (int q = 0; q < R; ++q) dst[bout + q * p * estride] = x[q];
+    }
+}
+
+template <int DIR, bool FFAST>
+__device__ float2* lds_fft(float2* a, float2* b, int n, int count, int fstride, int estride, const SliceDesc& d) {
+    int p = 1;
+    float2* src = a;
+    float2* dst = b;
+    for (int st = 0; st < d.nstage; ++st) {
+        const int r = d.radix[st];
+        switch (r) {
+            case 4: stockham_stage<DIR, 4, FFAST>(src, dst, n, count, fstride, estride, p, d.tw); break;
+            case 2: stockham_stage<DIR, 2, FFAST>(src, dst, n, count, fstride, estride, p, d.tw); break;
+            case 3: stockham_stage<DIR, 3, FFAST>(src, dst, n, count, fstride, estride, p, d.tw); break;
+            default: stockham_stage<DIR, 5, FFAST>(src, dst, n, count, fstride, estride, p, d.tw); break;
+        }
+        __syncthreads();
+        float2* t = src;
+        src = dst;
+        dst = t;
+        p *= r;
+    }
+    return src;
+}
+
+#define LOAD_DESC(a, tk) ((a).descs ? (a).descs[(tk).slice] : (a).one)
+
+// ------------------------------------------------------------------ projection
+//
+// P_b[y][x] = sum_s sum_taps w * V_s[y + oy + (0|1)][x + ox + (0|1)]   (Section 4.2)
+// Work item: (group of blade parts of one knot, tile row, tile column). Each bin's
+// plane is staged once into LDS (zero outside the grid) and every part of the group
+// takes its bilinear taps from it; each thread owns a vertical strip of PPT pixels
+// so the row below a pixel's taps is reused as the row above the next pixel's.
+
+__global__ __launch_bounds__(kThreads) void k_project(const KArgs a) {
+    extern __shared__ float2 sm[];
+    constexpr int TX = kProjTX, TY = kProjTY, PPT = TX * TY / kThreads;
+    const int lx = threadIdx.x % TX, ly0 = (threadIdx.x / TX) * PPT;
+    const int lane = threadIdx.x % 64, wrow = threadIdx.x / 64;
+    for (int ti = blockIdx.x; ti < a.ntasks; ti += gridDim.x) {
+        const Task tk = a.tasks[ti];
+        const SliceDesc& d = LOAD_DESC(a, tk);
+        const int st = step_of(d);
+        if (slice_done(d, st)) continue;
+        const ProjGroup gr = d.groups[tk.a];
+        const int n = d.n, S = d.S;
+        const size_t nn = (size_t)n * n;
+        const int y0 = tk.b * TY, x0 = tk.c * TX;
+        const int RH = TY + gr.oy_max - gr.oy_min + 1, RW = TX + gr.ox_max - gr.ox_min + 1;
+        const int gy0 = y0 + gr.oy_min, gx0 = x0 + gr.ox_min;
+        int eb[kGroup], ep[kGroup];
+        bool act[kGroup];
+#pragma unroll
+        for (int e = 0; e < kGroup; ++e) {
+            act[e] = false;
+            eb[e] = 0;
+            ep[e] = 0;
+            if (e < gr.ne) {
+                const KnotEntry ke = d.knot_ent[gr.e0 + e];
+                eb[e] = ke.blade;
+                ep[e] = ke.part;
+                act[e] = blade_active(d, st, ke.blade);
+            }
+        }
+        float2 acc[kGroup][PPT];
+#pragma unroll
+        for (int e = 0; e < kGroup; ++e)
+#pragma unroll
+            for (int i = 0; i < PPT; ++i) acc[e][i] = make_float2(0.f, 0.f);
+        const float2* V = vol_cur(d, st) + (size_t)gr.knot * S * nn;
+        for (int s = 0; s < S; ++s) {
+            const float2* Vs = V + (size_t)s * nn;
+            __syncthreads();
+            for (int rr = wrow; rr < RH; rr += kThreads / 64) {
+                const int gy = gy0 + rr;
+                const bool yin = gy >= 0 && gy < n;
+                for (int cc = lane; cc < RW; cc += 64) {
+                    const int gx = gx0 + cc;
+                    float2 v = make_float2(0.f, 0.f);
+                    if (yin && gx >= 0 && gx < n) v = Vs[(size_t)gy * n + gx];
+                    sm[rr * RW + cc] = v;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int e = 0; e < kGroup; ++e) {
+                if (act[e]) {
+                    const ShearEntry sh = d.shear[eb[e] * S + s];
+                    const int row = ly0 + sh.oy - gr.oy_min, col = lx + sh.ox - gr.ox_min;
+                    const float2* L = sm + row * RW + col;
+                    float2 a0 = L[0], a1 = L[1];
+#pragma unroll
+                    for (int i = 0; i < PPT; ++i) {
+                        const float2 b0 = L[(i + 1) * RW], b1 = L[(i + 1) * RW + 1];
+                        float2 t = acc[e][i];
+                        t = cfma(sh.w00, a0, t);
+                        t = cfma(sh.w01, a1, t);
+                        t = cfma(sh.w10, b0, t);
+                        t = cfma(sh.w11, b1, t);
+                        acc[e][i] = t;
+                        a0 = b0;
+                        a1 = b1;
+                    }
+                }
+            }
+        }
+        const int x = x0 + lx;
+#pragma unroll
+        for (int e = 0; e < kGroup; ++e) {
+            if (act[e] && x < n) {
+                float2* out = d.work + ((size_t)eb[e] * d.nparts + ep[e]) * nn;
+#pragma unroll
+                for (int i = 0; i < PPT; ++i) {
+                    const int y = y0 + ly0 + i;
+                    if (y < n) out[(size_t)y * n + x] = acc[e][i];
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ row passes
+//
+// DIR = -1: blend the blade's knot projections, (1 - a) P_k + a P_{k+1}, and take the
+// forward DFT of each row. DIR = +1: inverse DFT of each row (the column pass has
+// already applied both unitary scalings).
+
+template <int DIR>
+__global__ __launch_bounds__(kThreads) void k_rows(const KArgs a) {
+    extern __shared__ float2 sm[];
+    for (int ti = blockIdx.x; ti < a.ntasks; ti += gridDim.x) {
+        const Task tk = a.tasks[ti];
+        const SliceDesc& d = LOAD_DESC(a, tk);
+        const int st = step_of(d);
+        if (slice_done(d, st)) continue;
+        const int b = tk.a;
+        if (!blade_active(d, st, b)) continue;
+        const int n = d.n;
+        const size_t nn = (size_t)n * n;
+        const int fb = fft_rows_per_item(n);
+        const int r0 = tk.b, rows = min(fb, n - r0);
+        float2* A = sm;
+        float2* Bf = sm + fb * n;
+        float2* img = d.work + (size_t)b * d.nparts * nn;
+        const size_t base = (size_t)r0 * n;
+        if (DIR < 0 && d.nparts == 2) {
+            const BladeDev bd = d.blade[b];
+            const float2* p1 = img + nn;
+            for (int i = threadIdx.x; i < rows * n; i += blockDim.x) {
+                float2 v = make_float2(0.f, 0.f);
+                if (bd.has0) v = cscale(img[base + i], bd.w0);
+                if (bd.has1) v = cfma(bd.w1, p1[base + i], v);
+                A[i] = v;
+            }
+        } else {
+            for (int i = threadIdx.x; i < rows * n; i += blockDim.x) A[i] = img[base + i];
+        }
+        __syncthreads();
+        const float2* res = lds_fft<DIR, false>(A, Bf, n, rows, n, 1, d);
+        for (int i = threadIdx.x; i < rows * n; i += blockDim.x) img[base + i] = res[i];
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ column pass
+//
+// COL_STEP:    forward column DFT, K = X / n, R = M (K - y), loss partial sum |R|^2,
+//              Z = R / n, inverse column DFT -> work (one pass per column strip).
+// COL_FORWARD: forward column DFT, out = M (K - y) (y optional), no inverse.
+// COL_ADJOINT: reads caller k-space, Z = M kres / n, inverse column DFT -> work.
+
+__global__ __launch_bounds__(kThreads) void k_cols(const KArgs a) {
+    extern __shared__ float2 sm[];
+    for (int ti = blockIdx.x; ti < a.ntasks; ti += gridDim.x) {
+        const Task tk = a.tasks[ti];
+        const SliceDesc& d = LOAD_DESC(a, tk);
+        const int st = step_of(d);
+        if (slice_done(d, st)) continue;
+        const int b = tk.a;
+        if (!blade_active(d, st, b)) {
+            if (a.mode == COL_STEP && threadIdx.x == 0) d.loss_part[b * d.n_col_items + tk.b] = 0.f;
+            continue;
+        }
+        const int n = d.n;
+        const size_t nn = (size_t)n * n;
+        const int cb = fft_cols_per_item(n);
+        const int c0 = tk.b * cb, cols = min(cb, n - c0);
+        float2* A = sm;
+        float2* Bf = sm + cb * n;
+        float2* img = d.work + (size_t)b * d.nparts * nn;
+        const float2* src = a.mode == COL_ADJOINT ? a.in0 + (size_t)b * nn : img;
+        for (int i = threadIdx.x; i < n * cb; i += blockDim.x) {
+            const int y = i / cb, c = i - (i / cb) * cb;
+            A[i] = c < cols ? src[(size_t)y * n + c0 + c] : make_float2(0.f, 0.f);
+        }
+        __syncthreads();
+        float2* cur = A;
+        if (a.mode != COL_ADJOINT) cur = lds_fft<-1, true>(A, Bf, n, cb, 1, cb, d);
+        float2* other = cur == A ? Bf : A;
+        const float sc = 1.0f / (float)n;
+        const uint8_t* mk = d.mask + (size_t)b * nn;
+        const float2* yb = d.y ? d.y + (size_t)b * nn : nullptr;
+        float lsum = 0.f;
+        for (int i = threadIdx.x; i < n * cb; i += blockDim.x) {
+            const int y = i / cb, c = i - (i / cb) * cb;
+            float2 v = make_float2(0.f, 0.f);
+            if (c < cols) {
+                const size_t gi = (size_t)y * n + c0 + c;
+                const bool on = mk[gi] != 0;
+                const float2 x = cur[i];
+                if (a.mode == COL_ADJOINT) {
+                    if (on) v = cscale(x, sc);
+                } else {
+                    float2 r = make_float2(0.f, 0.f);
+                    if (on) {
+                        r = cscale(x, sc);
+                        if (yb) r = csub(r, yb[gi]);
+                    }
+                    if (a.mode == COL_FORWARD) {
+                        a.out0[(size_t)b * nn + gi] = r;
+                    } else {
+                        lsum = __builtin_fmaf(r.x, r.x, lsum);
+                        lsum = __builtin_fmaf(r.y, r.y, lsum);
+                        v = cscale(r, sc);
+                    }
+                }
+            }
+            cur[i] = v;
+        }
+        __syncthreads();
+        if (a.mode == COL_FORWARD) continue;
+        const float2* res = lds_fft<1, true>(cur, other, n, cb, 1, cb, d);
+        for (int i = threadIdx.x; i < n * cb; i += blockDim.x) {
+            const int y = i / cb, c = i - (i / cb) * cb;
+            if (c < cols) img[(size_t)y * n + c0 + c] = res[i];
+        }
+        if (a.mode == COL_STEP) {
+            __syncthreads();
+            float* red = reinterpret_cast<float*>(sm);
+            red[threadIdx.x] = lsum;
+            __syncthreads();
+            for (int w = kThreads / 2; w > 0; w >>= 1) {
+                if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+                __syncthreads();
+            }
+            if (threadIdx.x == 0) d.loss_part[b * d.n_col_items + tk.b] = red[0];
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ regulariser gradient
+
+__device__ __forceinline__ float2 charb_w(float2 dlt, float eps2) {
+    return cscale(dlt, 1.0f / sqrtf(dlt.x * dlt.x + dlt.y * dlt.y + eps2));
+}
+
+// tv_w * grad TV + l1_w * grad L1 at voxel (t, s, y, x) of a [T][S][n][n] volume.
+__device__ __forceinline__ float2 reg_grad(const float2* __restrict__ V, size_t idx, int t, int s, int y, int x,
+                                           int n, int S, int T, float tv_w, float l1_w, float eps) {
+    const float eps2 = eps * eps;
+    const float2 v0 = V[idx];
+    float2 g = make_float2(0.f, 0.f);
+    if (tv_w != 0.f) {
+        const size_t nn = (size_t)n * n;
+        if (t > 0) g = cadd(g, charb_w(csub(v0, V[idx - (size_t)S * nn]), eps2));
+        if (t + 1 < T) g = csub(g, charb_w(csub(V[idx + (size_t)S * nn], v0), eps2));
+        if (s > 0) g = cadd(g, charb_w(csub(v0, V[idx - nn]), eps2));
+        if (s + 1 < S) g = csub(g, charb_w(csub(V[idx + nn], v0), eps2));
+        if (y > 0) g = cadd(g, charb_w(csub(v0, V[idx - n]), eps2));
+        if (y + 1 < n) g = csub(g, charb_w(csub(V[idx + n], v0), eps2));
+        if (x > 0) g = cadd(g, charb_w(csub(v0, V[idx - 1]), eps2));
+        if (x + 1 < n) g = csub(g, charb_w(csub(V[idx + 1], v0), eps2));
+        g = cscale(g, tv_w);
+    }
+    if (l1_w != 0.f) g = cfma(l1_w, charb_w(v0, eps2), g);
+    return g;
+}
+
+// ------------------------------------------------------------------ adjoint gather + update
+//
+// G[k][s][y][x] = sum over the knot's blade parts e (blades ascending) of
+//   w_e * (w00 g[y-oy][x-ox] + w01 g[y-oy][x-ox-1] + w10 g[y-oy-1][x-ox] + w11 g[y-oy-1][x-ox-1]),
+// the exact transpose of k_project's taps (zero outside the grid). Work item: (knot,
+// spatial tile, chunk of kChunk bins); each blade's image region is staged in LDS once
+// per item. MODE = GATHER_STORE writes (or adds to) the gradient; GATHER_STEP adds the
+// TV/L1 gradient and applies the optimiser, reading volume[step & 1] and writing the
+// other copy.
+
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void k_gather(const KArgs a) {
+    extern __shared__ float2 sm[];
+    constexpr int TX = kGathTX, TY = kGathTY, PPT = TX * TY / kThreads;
+    const int lx = threadIdx.x % TX, ly0 = (threadIdx.x / TX) * PPT;
+    const int lane = threadIdx.x % 64, wrow = threadIdx.x / 64;
+    for (int ti = blockIdx.x; ti < a.ntasks; ti += gridDim.x) {
+        const Task tk = a.tasks[ti];
+        const SliceDesc& d = LOAD_DESC(a, tk);
+        const int st = step_of(d);
+        if (slice_done(d, st)) continue;
+        const int n = d.n, S = d.S, kt = tk.a;
+        const size_t nn = (size_t)n * n;
+        const int gtx = (n + TX - 1) / TX;
+        const int y0 = (tk.b / gtx) * TY, x0 = (tk.b % gtx) * TX;
+        const int s0 = tk.c * kChunk, ns = min(kChunk, S - s0);
+        float2 acc[kChunk][PPT];
+#pragma unroll
+        for (int q = 0; q < kChunk; ++q)
+#pragma unroll
+            for (int i = 0; i < PPT; ++i) acc[q][i] = make_float2(0.f, 0.f);
+        const int e1 = d.knot_ptr[kt + 1];
+        for (int e = d.knot_ptr[kt]; e < e1; ++e) {
+            const KnotEntry ke = d.knot_ent[e];
+            const int b = ke.blade;
+            if (!blade_active(d, st, b)) continue;
+            const BladeDev bd = d.blade[b];
+            const int RH = TY + bd.oy_max - bd.oy_min + 1, RW = TX + bd.ox_max - bd.ox_min + 1;
+            const int gy0 = y0 - bd.oy_max - 1, gx0 = x0 - bd.ox_max - 1;
+            const float2* g = d.work + (size_t)b * d.nparts * nn;
+            __syncthreads();
+            for (int rr = wrow; rr < RH; rr += kThreads / 64) {
+                const int gy = gy0 + rr;
+                const bool yin = gy >= 0 && gy < n;
+                for (int cc = lane; cc < RW; cc += 64) {
+                    const int gx = gx0 + cc;
+                    float2 v = make_float2(0.f, 0.f);
+                    if (yin && gx >= 0 && gx < n) v = g[(size_t)gy * n + gx];
+                    sm[rr * RW + cc] = v;
+                }
+            }
+            __syncthreads();
+            const float wb = ke.weight;
+            const ShearEntry* shb = d.shear + (size_t)b * S + s0;
+#pragma unroll
+            for (int q = 0; q < kChunk; ++q) {
+                if (q < ns) {
+                    const ShearEntry sh = shb[q];
+                    const int row = ly0 - sh.oy + bd.oy_max + 1, col = lx - sh.ox + bd.ox_max + 1;
+                    const float2* L = sm + row * RW + col;
+                    float2 u0 = L[-RW], u1 = L[-RW - 1];
+#pragma unroll
+                    for (int i = 0; i < PPT; ++i) {
+                        const float2 v0 = L[i * RW], v1 = L[i * RW - 1];
+                        float2 t = make_float2(0.f, 0.f);
+                        t = cfma(sh.w00, v0, t);
+                        t = cfma(sh.w01, v1, t);
+                        t = cfma(sh.w10, u0, t);
+                        t = cfma(sh.w11, u1, t);
+                        acc[q][i] = cfma(wb, t, acc[q][i]);
+                        u0 = v0;
+                        u1 = v1;
+                    }
+                }
+            }
+        }
+        const int x = x0 + lx;
+        if (x >= n) continue;
+        if (MODE == GATHER_STORE) {
+#pragma unroll
+            for (int q = 0; q < kChunk; ++q) {
+                if (q < ns) {
+#pragma unroll
+                    for (int i = 0; i < PPT; ++i) {
+                        const int y = y0 + ly0 + i;
+                        if (y < n) {
+                            const size_t idx = (((size_t)kt * S + s0 + q) * n + y) * n + x;
+                            float2 g = acc[q][i];
+                            if (a.accumulate) g = cadd(d.grad[idx], g);
+                            d.grad[idx] = g;
+                        }
+                    }
+                }
+            }
+        } else {
+            const float2* Vin = vol_cur(d, st);
+            float2* Vout = d.vol[(st + 1) & 1];
+            const int t = st + 1;
+            // bias corrections in FP64, once per item
+            const float bc1 = (float)(1.0 - pow((double)d.beta1, (double)t));
+            const float bc2s = (float)sqrt(1.0 - pow((double)d.beta2, (double)t));
+            const float step_size = d.lr / bc1;
+#pragma unroll
+            for (int q = 0; q < kChunk; ++q) {
+                if (q < ns) {
+#pragma unroll
+                    for (int i = 0; i < PPT; ++i) {
+                        const int y = y0 + ly0 + i;
+                        if (y < n) {
+                            const int s = s0 + q;
+                            const size_t idx = (((size_t)kt * S + s) * n + y) * n + x;
+                            const float2 reg = reg_grad(Vin, idx, kt, s, y, x, n, S, d.T, d.tv_w, d.l1_w, d.tv_eps);
+                            const float2 gr = cadd(acc[q][i], reg);
+                            const float2 v0 = Vin[idx];
+                            float2 nv;
+                            if (d.optimizer == VP_OPT_ADAM) {
+                                float2 m = d.m[idx], v = d.v[idx];
+                                m.x = d.beta1 * m.x + (1.0f - d.beta1) * gr.x;
+                                m.y = d.beta1 * m.y + (1.0f - d.beta1) * gr.y;
+                                v.x = d.beta2 * v.x + (1.0f - d.beta2) * gr.x * gr.x;
+                                v.y = d.beta2 * v.y + (1.0f - d.beta2) * gr.y * gr.y;
+                                d.m[idx] = m;
+                                d.v[idx] = v;
+                                const float dx = sqrtf(v.x) / bc2s + d.adam_eps;
+                                const float dy = sqrtf(v.y) / bc2s + d.adam_eps;
+                                nv = make_float2(v0.x - step_size * (m.x / dx), v0.y - step_size * (m.y / dy));
+                            } else {
+                                nv = make_float2(v0.x - d.lr * gr.x, v0.y - d.lr * gr.y);
+                            }
+                            Vout[idx] = nv;
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ voxel-wise kernels
+
+// Operator TV/L1 gradient: grad (+)= tv_w grad TV + l1_w grad L1 (weights from the descriptor).
+__global__ __launch_bounds__(kThreads) void k_tv_grad(const KArgs a) {
+    for (int ti = blockIdx.x; ti < a.ntasks; ti += gridDim.x) {
+        const Task tk = a.tasks[ti];
+        const SliceDesc& d = LOAD_DESC(a, tk);
+        const int n = d.n, S = d.S, T = d.T;
+        const size_t nvox = (size_t)T * S * n * n;
+        const size_t i0 = (size_t)tk.a * kVoxItem;
+        const float2* V = d.vol[0];
+        for (size_t i = i0 + threadIdx.x; i < min(nvox, i0 + kVoxItem); i += blockDim.x) {
+            const int x = (int)(i % n), y = (int)((i / n) % n), s = (int)((i / ((size_t)n * n)) % S);
+            const int t = (int)(i / ((size_t)S * n * n));
+            float2 g = reg_grad(V, i, t, s, y, x, n, S, T, d.tv_w, d.l1_w, d.tv_eps);
+            if (a.accumulate) g = cadd(d.grad[i], g);
+            d.grad[i] = g;
+        }
+    }
+}
+
+// Objective regulariser terms: per work item, sums of the TV terms (forward differences
+// where the neighbour exists) and the L1 terms, each written as |z|^2 / (sqrt(|z|^2 + e^2) + e),
+// the cancellation-free form of sqrt(|z|^2 + e^2) - e. Output a.dpart[2 * item + {0, 1}].
+__global__ __launch_bounds__(kThreads) void k_reg_value(const KArgs a) {
+    __shared__ double red[2][kThreads];
+    for (int ti = blockIdx.x; ti < a.ntasks; ti += gridDim.x) {
+        const Task tk = a.tasks[ti];
+        const SliceDesc& d = LOAD_DESC(a, tk);
+        const int st = step_of(d);
+        const int n = d.n, S = d.S, T = d.T;
+        const size_t nn = (size_t)n * n, nvox = (size_t)T * S * nn;
+        const size_t i0 = (size_t)tk.a * kVoxItem;
+        const float2* V = vol_cur(d, st);
+        const float e = d.tv_eps, e2 = e * e;
+        double tv = 0.0, l1 = 0.0;
+        for (size_t i = i0 + threadIdx.x; i < min(nvox, i0 + kVoxItem); i += blockDim.x) {
+            const int x = (int)(i % n), y = (int)((i / n) % n), s = (int)((i / nn) % S);
+            const int t = (int)(i / ((size_t)S * nn));
+            const float2 v0 = V[i];
+            float part = 0.f;
+            auto term = [&](float2 z) {
+                const float q = z.x * z.x + z.y * z.y;
+                return q / (sqrtf(q + e2) + e);
+            };
+            if (x + 1 < n) part += term(csub(V[i + 1], v0));
+            if (y + 1 < n) part += term(csub(V[i + n], v0));
+            if (s + 1 < S) part += term(csub(V[i + nn], v0));
+            if (t + 1 < T) part += term(csub(V[i + (size_t)S * nn], v0));
+            tv += part;
+            l1 += term(v0);
+        }
+        red[0][threadIdx.x] = tv;
+        red[1][threadIdx.x] = l1;
+        __syncthreads();
+        for (int w = kThreads / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) {
+                red[0][threadIdx.x] += red[0][threadIdx.x + w];
+                red[1][threadIdx.x] += red[1][threadIdx.x + w];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            a.dpart[2 * ti] = red[0][0];
+            a.dpart[2 * ti + 1] = red[1][0];
+        }
+        __syncthreads();
+    }
+}
+
+// Render at phi = 0 and the fat/water split: water = bins [0, split), fat = [split, S),
+// proj = water + fat. One work item per (knot, block of kVoxItem pixels).
+__global__ __launch_bounds__(kThreads) void k_render(const KArgs a) {
+    for (int ti = blockIdx.x; ti < a.ntasks; ti += gridDim.x) {
+        const Task tk = a.tasks[ti];
+        const SliceDesc& d = LOAD_DESC(a, tk);
+        const int st = step_of(d);
+        const int n = d.n, S = d.S;
+        const size_t nn = (size_t)n * n;
+        const int split = a.split_bin < 0 ? S / 2 : min(a.split_bin, S);
+        const float2* V = vol_cur(d, st) + (size_t)tk.a * S * nn;
+        const size_t p0 = (size_t)tk.b * kVoxItem;
+        for (size_t p = p0 + threadIdx.x; p < min(nn, p0 + kVoxItem); p += blockDim.x) {
+            float2 w = make_float2(0.f, 0.f), f = make_float2(0.f, 0.f);
+            for (int s = 0; s < split; ++s) w = cadd(w, V[(size_t)s * nn + p]);
+            for (int s = split; s < S; ++s) f = cadd(f, V[(size_t)s * nn + p]);
+            const size_t o = (size_t)tk.a * nn + p;
+            if (a.out0) a.out0[o] = cadd(w, f);
+            if (a.out1) a.out1[o] = w;
+            if (a.out2) a.out2[o] = f;
+        }
+    }
+}
+
+// Advance the step counter of every unfinished slice (one work item per slice).
+__global__ void k_bump(const KArgs a) {
+    for (int ti = blockIdx.x; ti < a.ntasks; ti += gridDim.x) {
+        if (threadIdx.x != 0) continue;
+        const Task tk = a.tasks[ti];
+        const SliceDesc& d = LOAD_DESC(a, tk);
+        if (d.step && *d.step < d.step_limit) *d.step = *d.step + 1;
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+
+static inline int grid_for(int ntasks) { return ntasks < 1 ? 1 : (ntasks > (1 << 20) ? (1 << 20) : ntasks); }
+
+hipError_t launch_project(const KArgs& a, size_t lds, hipStream_t s) {
+    if (a.ntasks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_project, dim3(grid_for(a.ntasks)), dim3(kThreads), lds, s, a);
+    return hipGetLastError();
+}
+hipError_t launch_rows(const KArgs& a, int dir, size_t lds, hipStream_t s) {
+    if (a.ntasks <= 0) return hipSuccess;
+    if (dir < 0)
+        hipLaunchKernelGGL(k_rows<-1>, dim3(grid_for(a.ntasks)), dim3(kThreads), lds, s, a);
+    else
+        hipLaunchKernelGGL(k_rows<1>, dim3(grid_for(a.ntasks)), dim3(kThreads), lds, s, a);
+    return hipGetLastError();
+}
+hipError_t launch_cols(const KArgs& a, size_t lds, hipStream_t s) {
+    if (a.ntasks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cols, dim3(grid_for(a.ntasks)), dim3(kThreads), lds, s, a);
+    return hipGetLastError();
+}
+hipError_t launch_gather(const KArgs& a, int mode, size_t lds, hipStream_t s) {
+    if (a.ntasks <= 0) return hipSuccess;
+    if (mode == GATHER_STEP)
+        hipLaunchKernelGGL(k_gather<GATHER_STEP>, dim3(grid_for(a.ntasks)), dim3(kThreads), lds, s, a);
+    else
+        hipLaunchKernelGGL(k_gather<GATHER_STORE>, dim3(grid_for(a.ntasks)), dim3(kThreads), lds, s, a);
+    return hipGetLastError();
+}
+hipError_t launch_tv_grad(const KArgs& a, hipStream_t s) {
+    if (a.ntasks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tv_grad, dim3(grid_for(a.ntasks)), dim3(kThreads), 0, s, a);
+    return hipGetLastError();
+}
+hipError_t launch_reg_value(const KArgs& a, hipStream_t s) {
+    if (a.ntasks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reg_value, dim3(grid_for(a.ntasks)), dim3(kThreads), 0, s, a);
+    return hipGetLastError();
+}
+hipError_t launch_render(const KArgs& a, hipStream_t s) {
+    if (a.ntasks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_render, dim3(grid_for(a.ntasks)), dim3(kThreads), 0, s, a);
+    return hipGetLastError();
+}
+hipError_t launch_bump(const KArgs& a, hipStream_t s) {
+    if (a.ntasks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bump, dim3(grid_for(a.ntasks)), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace vp

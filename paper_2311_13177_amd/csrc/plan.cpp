@@ -1,0 +1,349 @@
+// Host-only plan construction for libvp: validation, FP64 tables, launch lists.
+// Nothing here touches a device, so every function is usable on a machine without one.
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+
+#include "plan.h"
+
+namespace vp {
+
+static thread_local std::string g_err;
+
+vp_status fail(vp_status code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+void clear_error() { g_err.clear(); }
+
+// Radix sequence of a length with no prime factor above 5 (radix-4 stages first).
+static bool factor_235(int n, std::vector<int>& radices) {
+    radices.clear();
+    while (n % 4 == 0) { radices.push_back(4); n /= 4; }
+    while (n % 2 == 0) { radices.push_back(2); n /= 2; }
+    while (n % 3 == 0) { radices.push_back(3); n /= 3; }
+    while (n % 5 == 0) { radices.push_back(5); n /= 5; }
+    return n == 1;
+}
+
+// Signed frequency of an unshifted DFT index.
+static double signed_freq(int j, int n) { return j <= (n - 1) / 2 ? (double)j : (double)(j - n); }
+
+// Blade support (Section 4.2 "Blur", Cartesian masks of Section 7): half-open rotated
+// rectangle of length n along the readout and width L across it, 1e-9 tie margin.
+// Evaluated in FP64 without contraction so that every sample lands on the same side
+// of a tie as a plain double-precision evaluation of the same rule.
+#pragma clang fp contract(off)
+static void build_mask(int n, double theta, int lines, uint8_t* out) {
+    const double eps = 1e-9;
+    const double c = std::cos(theta), s = std::sin(theta);
+    const double rlo = -n / 2.0 - eps, rhi = n / 2.0 - eps;
+    const double qlo = -lines / 2.0 - eps, qhi = lines / 2.0 - eps;
+    for (int iy = 0; iy < n; ++iy) {
+        const double ky = signed_freq(iy, n);
+        for (int ix = 0; ix < n; ++ix) {
+            const double kx = signed_freq(ix, n);
+            const double r = kx * c + ky * s;
+            const double q = -kx * s + ky * c;
+            out[(size_t)iy * n + ix] = (r >= rlo && r < rhi && q >= qlo && q < qhi) ? 1 : 0;
+        }
+    }
+}
+
+// Bilinear taps of the sample at (x - dx, y - dy), d = delta * u (Sections 3 and 4.2).
+static void build_shear(double theta, double delta, ShearEntry* e, float* fxo, float* fyo) {
+    const double dx = delta * std::cos(theta);
+    const double dy = delta * std::sin(theta);
+    const double ox = std::floor(-dx), oy = std::floor(-dy);
+    const double fx = -dx - ox, fy = -dy - oy;
+    e->ox = (int)ox;
+    e->oy = (int)oy;
+    e->w00 = (float)((1.0 - fy) * (1.0 - fx));
+    e->w01 = (float)((1.0 - fy) * fx);
+    e->w10 = (float)(fy * (1.0 - fx));
+    e->w11 = (float)(fy * fx);
+    e->pad0 = e->pad1 = 0;
+    *fxo = (float)fx;
+    *fyo = (float)fy;
+}
+#pragma clang fp contract(on)
+
+static int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+}  // namespace vp
+
+using namespace vp;
+
+extern "C" const char* vp_last_error(void) { return vp::g_err.c_str(); }
+
+extern "C" const char* vp_status_string(vp_status s) {
+    switch (s) {
+        case VP_OK: return "ok";
+        case VP_ERR_ARG: return "invalid argument";
+        case VP_ERR_UNSUPPORTED: return "unsupported problem";
+        case VP_ERR_DEVICE: return "device error";
+        case VP_ERR_NONFINITE: return "non-finite value";
+        case VP_ERR_BUDGET: return "request exceeds the memory budget";
+        case VP_ERR_NOMEM: return "out of memory";
+        case VP_ERR_TIMEOUT: return "timed out";
+        case VP_ERR_CANCELLED: return "cancelled";
+        case VP_ERR_NOT_FOUND: return "not found";
+        case VP_ERR_STATE: return "invalid state";
+        default: return "unknown status";
+    }
+}
+
+extern "C" vp_status vp_options_default(vp_options* o) {
+    if (!o) return fail(VP_ERR_ARG, "vp_options_default: NULL options");
+    o->tv_weight = 1e-3f;
+    o->l1_weight = 0.0f;
+    o->tv_eps = 1e-3f;
+    o->n_steps = 200;
+    o->optimizer = VP_OPT_ADAM;
+    o->lr = 1e-2f;
+    o->beta1 = 0.9f;
+    o->beta2 = 0.999f;
+    o->adam_eps = 1e-8f;
+    o->schedule = VP_SCHED_ALL_BLADES;
+    o->split_bin = -1;
+    o->device = 0;
+    return VP_OK;
+}
+
+extern "C" vp_status vp_plan_create(const vp_geometry* g, vp_plan** out) {
+    clear_error();
+    if (!g || !out) return fail(VP_ERR_ARG, "vp_plan_create: NULL geometry or output");
+    if (g->n < 1 || g->n_spec < 1 || g->n_time < 1 || g->n_blades < 1)
+        return fail(VP_ERR_ARG, "vp_plan_create: sizes must be >= 1 (n=%d S=%d T=%d B=%d)", g->n, g->n_spec,
+                    g->n_time, g->n_blades);
+    if (!g->angle_rad || !g->lines || !g->spec_shift_px)
+        return fail(VP_ERR_ARG, "vp_plan_create: NULL angle, lines or shift array");
+    if ((g->n_time == 1) != (g->blade_time == nullptr))
+        return fail(VP_ERR_ARG, "vp_plan_create: blade_time must be NULL exactly when n_time == 1");
+    if (g->n > kMaxN || g->n_spec > kMaxS || g->n_time > kMaxT || g->n_blades > kMaxB)
+        return fail(VP_ERR_UNSUPPORTED, "vp_plan_create: size above the supported maximum (n<=%d S<=%d T<=%d B<=%d)",
+                    kMaxN, kMaxS, kMaxT, kMaxB);
+    std::vector<int> radices;
+    if (!factor_235(g->n, radices))
+        return fail(VP_ERR_UNSUPPORTED, "vp_plan_create: n=%d has a prime factor above 5", g->n);
+    const int n = g->n, S = g->n_spec, T = g->n_time, B = g->n_blades;
+    for (int b = 0; b < B; ++b) {
+        if (!std::isfinite(g->angle_rad[b])) return fail(VP_ERR_ARG, "vp_plan_create: angle %d not finite", b);
+        if (g->lines[b] < 1 || g->lines[b] > n)
+            return fail(VP_ERR_ARG, "vp_plan_create: lines[%d]=%d outside [1, %d]", b, g->lines[b], n);
+        if (g->blade_time) {
+            const double t = g->blade_time[b];
+            if (!std::isfinite(t) || t < 0.0 || t > 1.0)
+                return fail(VP_ERR_ARG, "vp_plan_create: blade_time[%d] outside [0, 1]", b);
+        }
+    }
+    for (int s = 0; s < S; ++s) {
+        const double d = g->spec_shift_px[s];
+        if (!std::isfinite(d)) return fail(VP_ERR_ARG, "vp_plan_create: spec_shift_px[%d] not finite", s);
+        if (std::fabs(d) > kMaxShift)
+            return fail(VP_ERR_UNSUPPORTED, "vp_plan_create: |spec_shift_px[%d]| = %g above %g px", s, d, kMaxShift);
+    }
+
+    std::unique_ptr<vp_plan> p(new (std::nothrow) vp_plan());
+    if (!p) return fail(VP_ERR_NOMEM, "vp_plan_create: out of host memory");
+    try {
+        p->n = n; p->S = S; p->T = T; p->B = B;
+        p->angle.assign(g->angle_rad, g->angle_rad + B);
+        p->lines.assign(g->lines, g->lines + B);
+        p->shift.assign(g->spec_shift_px, g->spec_shift_px + S);
+        p->tau.assign(B, 0.0);
+        if (g->blade_time) p->tau.assign(g->blade_time, g->blade_time + B);
+        p->nstage = (int)radices.size();
+        for (int i = 0; i < p->nstage; ++i) p->radix[i] = radices[i];
+        p->nparts = T > 1 ? 2 : 1;
+
+        // masks
+        p->mask.resize((size_t)B * n * n);
+        for (int b = 0; b < B; ++b) build_mask(n, p->angle[b], p->lines[b], &p->mask[(size_t)b * n * n]);
+
+        // shear table and per-blade extents
+        p->shear.resize((size_t)B * S);
+        p->fx.resize((size_t)B * S);
+        p->fy.resize((size_t)B * S);
+        p->blade.resize(B);
+        p->alpha.assign(B, 0.0f);
+        for (int b = 0; b < B; ++b) {
+            BladeDev& bd = p->blade[b];
+            bd.ox_min = bd.oy_min = std::numeric_limits<int>::max();
+            bd.ox_max = bd.oy_max = std::numeric_limits<int>::min();
+            for (int s = 0; s < S; ++s) {
+                ShearEntry& e = p->shear[(size_t)b * S + s];
+                build_shear(p->angle[b], p->shift[s], &e, &p->fx[(size_t)b * S + s], &p->fy[(size_t)b * S + s]);
+                bd.ox_min = std::min(bd.ox_min, e.ox); bd.ox_max = std::max(bd.ox_max, e.ox);
+                bd.oy_min = std::min(bd.oy_min, e.oy); bd.oy_max = std::max(bd.oy_max, e.oy);
+            }
+            // knot of the blade's time (dense knots at k/(T-1), linear blend)
+            if (T == 1) {
+                bd.knot = 0; bd.has0 = 1; bd.has1 = 0; bd.w0 = 1.0f; bd.w1 = 0.0f;
+            } else {
+                const double u = p->tau[b] * (T - 1);
+                const int k = std::min((int)std::floor(u), T - 2);
+                const double a = u - k;
+                bd.knot = k;
+                bd.has0 = (1.0 - a) != 0.0;
+                bd.has1 = a != 0.0;
+                bd.w0 = (float)(1.0 - a);
+                bd.w1 = (float)a;
+                p->alpha[b] = (float)a;
+            }
+            bd.pad = 0;
+        }
+
+        // knot entry lists, blades ascending within each knot
+        p->knot_ptr.assign(T + 1, 0);
+        for (int kt = 0; kt < T; ++kt) {
+            p->knot_ptr[kt] = (int)p->knot_ent.size();
+            for (int b = 0; b < B; ++b) {
+                const BladeDev& bd = p->blade[b];
+                if (bd.knot == kt && bd.has0) p->knot_ent.push_back(KnotEntry{b, 0, bd.w0, 0});
+                if (T > 1 && bd.knot + 1 == kt && bd.has1) p->knot_ent.push_back(KnotEntry{b, 1, bd.w1, 0});
+            }
+        }
+        p->knot_ptr[T] = (int)p->knot_ent.size();
+
+        // projection groups
+        for (int kt = 0; kt < T; ++kt) {
+            for (int e0 = p->knot_ptr[kt]; e0 < p->knot_ptr[kt + 1]; e0 += kGroup) {
+                ProjGroup gr{};
+                gr.knot = kt;
+                gr.e0 = e0;
+                gr.ne = std::min(kGroup, p->knot_ptr[kt + 1] - e0);
+                gr.ox_min = gr.oy_min = std::numeric_limits<int>::max();
+                gr.ox_max = gr.oy_max = std::numeric_limits<int>::min();
+                for (int e = e0; e < e0 + gr.ne; ++e) {
+                    const BladeDev& bd = p->blade[p->knot_ent[e].blade];
+                    gr.ox_min = std::min(gr.ox_min, bd.ox_min); gr.ox_max = std::max(gr.ox_max, bd.ox_max);
+                    gr.oy_min = std::min(gr.oy_min, bd.oy_min); gr.oy_max = std::max(gr.oy_max, bd.oy_max);
+                }
+                p->groups.push_back(gr);
+            }
+        }
+
+        // twiddles exp(-2 pi i j / n), FP64 then rounded
+        p->tw.resize(n);
+        for (int j = 0; j < n; ++j) {
+            const double ang = -2.0 * M_PI * (double)j / (double)n;
+            p->tw[j] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+        }
+
+        // LDS sizes
+        for (const ProjGroup& gr : p->groups) {
+            const size_t rh = kProjTY + gr.oy_max - gr.oy_min + 1, rw = kProjTX + gr.ox_max - gr.ox_min + 1;
+            p->lds_proj = std::max(p->lds_proj, rh * rw * sizeof(float2));
+        }
+        for (const BladeDev& bd : p->blade) {
+            const size_t rh = kGathTY + bd.oy_max - bd.oy_min + 1, rw = kGathTX + bd.ox_max - bd.ox_min + 1;
+            p->lds_gath = std::max(p->lds_gath, rh * rw * sizeof(float2));
+        }
+        const int fb = fft_rows_per_item(n), cb = fft_cols_per_item(n);
+        p->lds_rows = 2 * (size_t)fb * n * sizeof(float2);
+        // the loss reduction reuses the column buffers (256 floats)
+        p->lds_cols = std::max(2 * (size_t)cb * n * sizeof(float2), kThreads * sizeof(float));
+        p->n_col_items = ceil_div(n, cb);
+
+        // work lists
+        const int pty = ceil_div(n, kProjTY), ptx = ceil_div(n, kProjTX);
+        for (int gi = 0; gi < (int)p->groups.size(); ++gi)
+            for (int ty = 0; ty < pty; ++ty)
+                for (int tx = 0; tx < ptx; ++tx) p->t_proj.push_back(Task{0, gi, ty, tx});
+        for (int b = 0; b < B; ++b)
+            for (int r0 = 0; r0 < n; r0 += fb) p->t_rows.push_back(Task{0, b, r0, 0});
+        for (int b = 0; b < B; ++b)
+            for (int c = 0; c < p->n_col_items; ++c) p->t_cols.push_back(Task{0, b, c, 0});
+        const int gty = ceil_div(n, kGathTY), gtx = ceil_div(n, kGathTX), nch = ceil_div(S, kChunk);
+        for (int kt = 0; kt < T; ++kt)
+            for (int ty = 0; ty < gty; ++ty)
+                for (int tx = 0; tx < gtx; ++tx)
+                    for (int ch = 0; ch < nch; ++ch) p->t_gath.push_back(Task{0, kt, ty * gtx + tx, ch});
+        const uint64_t nvox = p->voxels();
+        for (uint64_t i = 0; i * kVoxItem < nvox; ++i) p->t_vox.push_back(Task{0, (int)i, 0, 0});
+        const int npb = ceil_div(n * n, kVoxItem);
+        for (int kt = 0; kt < T; ++kt)
+            for (int pb = 0; pb < npb; ++pb) p->t_render.push_back(Task{0, kt, pb, 0});
+        p->t_one.push_back(Task{0, 0, 0, 0});
+    } catch (const std::bad_alloc&) {
+        return fail(VP_ERR_NOMEM, "vp_plan_create: out of host memory");
+    }
+    *out = p.release();
+    return VP_OK;
+}
+
+extern "C" vp_status vp_plan_shape(const vp_plan* p, int32_t* n, int32_t* s, int32_t* t, int32_t* b) {
+    if (!p) return fail(VP_ERR_ARG, "vp_plan_shape: NULL plan");
+    if (n) *n = p->n;
+    if (s) *s = p->S;
+    if (t) *t = p->T;
+    if (b) *b = p->B;
+    return VP_OK;
+}
+
+extern "C" vp_status vp_plan_mask(const vp_plan* p, int32_t b, uint8_t* out) {
+    if (!p || !out) return fail(VP_ERR_ARG, "vp_plan_mask: NULL argument");
+    if (b < 0 || b >= p->B) return fail(VP_ERR_ARG, "vp_plan_mask: blade %d outside [0, %d)", b, p->B);
+    std::memcpy(out, &p->mask[(size_t)b * p->n * p->n], (size_t)p->n * p->n);
+    return VP_OK;
+}
+
+extern "C" vp_status vp_plan_shear(const vp_plan* p, int32_t b, int32_t s, int32_t* ox, int32_t* oy, float* fx,
+                                   float* fy) {
+    if (!p) return fail(VP_ERR_ARG, "vp_plan_shear: NULL plan");
+    if (b < 0 || b >= p->B || s < 0 || s >= p->S) return fail(VP_ERR_ARG, "vp_plan_shear: index out of range");
+    const size_t i = (size_t)b * p->S + s;
+    if (ox) *ox = p->shear[i].ox;
+    if (oy) *oy = p->shear[i].oy;
+    if (fx) *fx = p->fx[i];
+    if (fy) *fy = p->fy[i];
+    return VP_OK;
+}
+
+extern "C" vp_status vp_plan_knot(const vp_plan* p, int32_t b, int32_t* knot, float* alpha) {
+    if (!p) return fail(VP_ERR_ARG, "vp_plan_knot: NULL plan");
+    if (b < 0 || b >= p->B) return fail(VP_ERR_ARG, "vp_plan_knot: blade out of range");
+    if (knot) *knot = p->blade[b].knot;
+    if (alpha) *alpha = p->alpha[b];
+    return VP_OK;
+}
+
+namespace vp {
+uint64_t table_bytes(const vp_plan* p) {
+    return p->mask.size() + p->shear.size() * sizeof(ShearEntry) + p->blade.size() * sizeof(BladeDev) +
+           p->knot_ptr.size() * sizeof(int) + p->knot_ent.size() * sizeof(KnotEntry) +
+           p->groups.size() * sizeof(ProjGroup) + p->tw.size() * sizeof(float2) +
+           (p->t_proj.size() + p->t_rows.size() + p->t_cols.size() + p->t_gath.size() + p->t_vox.size() +
+            p->t_render.size() + p->t_one.size()) *
+               sizeof(Task);
+}
+
+uint64_t state_bytes(const vp_plan* p, const vp_options* o) {
+    const uint64_t vox = p->voxels() * sizeof(float2);
+    uint64_t b = 2 * vox;                                         // volume ping-pong
+    if (!o || o->optimizer == VP_OPT_ADAM) b += 2 * vox;          // Adam moments
+    b += (uint64_t)p->nparts * p->blade_px() * sizeof(float2);   // blade work images
+    b += p->blade_px() * sizeof(float2);                          // measurements
+    b += loss_slots(p) * sizeof(float) + 256;                     // loss partials, step counter
+    b += 2 * p->t_vox.size() * sizeof(double);                    // objective partials
+    b += 3 * (uint64_t)p->T * p->n * p->n * sizeof(float2);       // renders
+    return b;
+}
+}  // namespace vp
+
+extern "C" vp_status vp_plan_device_bytes(const vp_plan* p, const vp_options* o, uint64_t* bytes) {
+    if (!p || !bytes) return fail(VP_ERR_ARG, "vp_plan_device_bytes: NULL argument");
+    *bytes = vp::state_bytes(p, o) + vp::table_bytes(p);
+    return VP_OK;
+}

@@ -1,0 +1,73 @@
+// Internal declarations shared by the runtime, batch and server translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "plan.h"
+
+namespace vp {
+
+// Kernel launchers (kernels.hip).
+hipError_t launch_project(const KArgs& a, size_t lds, hipStream_t s);
+hipError_t launch_rows(const KArgs& a, int dir, size_t lds, hipStream_t s);
+hipError_t launch_cols(const KArgs& a, size_t lds, hipStream_t s);
+hipError_t launch_gather(const KArgs& a, int mode, size_t lds, hipStream_t s);
+hipError_t launch_tv_grad(const KArgs& a, hipStream_t s);
+hipError_t launch_reg_value(const KArgs& a, hipStream_t s);
+hipError_t launch_render(const KArgs& a, hipStream_t s);
+hipError_t launch_bump(const KArgs& a, hipStream_t s);
+
+// Device work lists of one optimiser step and the dynamic LDS of each stage.
+struct StageLists {
+    const Task* proj = nullptr;
+    const Task* rows = nullptr;
+    const Task* cols = nullptr;
+    const Task* gath = nullptr;
+    const Task* vox = nullptr;
+    const Task* render = nullptr;
+    const Task* one = nullptr;
+    int n_proj = 0, n_rows = 0, n_cols = 0, n_gath = 0, n_vox = 0, n_render = 0, n_one = 0;
+    size_t lds_proj = 0, lds_rows = 0, lds_cols = 0, lds_gath = 0;
+};
+
+StageLists plan_lists(const vp_plan* p, const DeviceTables* t);
+// Enqueues one optimiser step (project, row DFT, column pass, inverse row DFT,
+// gather + update, step counter) for the descriptors `base` refers to.
+void launch_step(const KArgs& base, const StageLists& L, hipStream_t s, hipError_t* err);
+
+vp_status hip_status(hipError_t e, const char* what);
+vp_status check_options(const vp_plan* p, const vp_options* o);
+
+}  // namespace vp
+
+struct vp_session {
+    const vp_plan* plan = nullptr;
+    vp_options opts{};
+    int device = -1;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    vp::DeviceTables* tabs = nullptr;
+    float2* vol[2] = {nullptr, nullptr};
+    float2* m = nullptr;
+    float2* v = nullptr;
+    float2* work = nullptr;
+    float2* y = nullptr;
+    float* loss_part = nullptr;
+    int* step_dev = nullptr;
+    double* dpart = nullptr;
+    float2* render = nullptr;
+    int64_t steps_done = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    vp::SliceDesc desc{};
+    vp::StageLists lists{};
+    ~vp_session();
+};
+
+namespace vp {
+vp_status session_alloc(const vp_plan* p, const vp_options* o, const vp_c64* kspace, const vp_c64* init,
+                        hipStream_t stream, vp_session** out);
+vp_status session_run(vp_session* s, int32_t n_steps, int32_t use_graph);
+vp_status session_objective(vp_session* s, double* objective, double* data_term);
+vp_status session_read(vp_session* s, vp_c64* volume_out, vp_c64* proj_out, vp_c64* water_out, vp_c64* fat_out);
+}  // namespace vp

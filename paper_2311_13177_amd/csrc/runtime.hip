@@ -1,0 +1,587 @@
+// Host runtime of libvp: per-device plan tables, operator calls, resident sessions
+// (eager or HIP-graph stepping), whole reconstructions and batched reconstructions.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <vector>
+
+#include "plan.h"
+#include "runtime.h"
+
+namespace vp {
+
+// ------------------------------------------------------------------ device tables
+
+DeviceTables::~DeviceTables() {
+    int prev = -1;
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (device >= 0) (void)hipSetDevice(device);
+    void* ptrs[] = {mask, shear, blade, knot_ptr, knot_ent, groups, tw, t_proj, t_rows, t_cols, t_gath, t_vox, t_render,
+                    t_one};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    if (prev >= 0) (void)hipSetDevice(prev);
+}
+
+vp_status hip_status(hipError_t e, const char* what) {
+    if (e == hipSuccess) return VP_OK;
+    if (e == hipErrorOutOfMemory) return fail(VP_ERR_NOMEM, "%s: %s", what, hipGetErrorString(e));
+    return fail(VP_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+template <typename T>
+static hipError_t upload(T** dst, const std::vector<T>& src) {
+    *dst = nullptr;
+    const size_t bytes = std::max<size_t>(sizeof(T), src.size() * sizeof(T));
+    hipError_t e = hipMalloc((void**)dst, bytes);
+    if (e != hipSuccess) return e;
+    if (src.empty()) return hipMemset(*dst, 0, bytes);
+    return hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+vp_status plan_tables(const vp_plan* p, DeviceTables** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_status(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(p->mu);
+    auto it = p->dev.find(dev);
+    if (it != p->dev.end()) {
+        *out = it->second.get();
+        return VP_OK;
+    }
+    std::unique_ptr<DeviceTables> t(new (std::nothrow) DeviceTables());
+    if (!t) return fail(VP_ERR_NOMEM, "plan tables: out of host memory");
+    t->device = dev;
+#define UP(field, vec)                                         \
+    do {                                                       \
+        e = upload(&t->field, vec);                            \
+        if (e != hipSuccess) return hip_status(e, "plan tables"); \
+    } while (0)
+    UP(mask, p->mask);
+    UP(shear, p->shear);
+    UP(blade, p->blade);
+    UP(knot_ptr, p->knot_ptr);
+    UP(knot_ent, p->knot_ent);
+    UP(groups, p->groups);
+    UP(tw, p->tw);
+    UP(t_proj, p->t_proj);
+    UP(t_rows, p->t_rows);
+    UP(t_cols, p->t_cols);
+    UP(t_gath, p->t_gath);
+    UP(t_vox, p->t_vox);
+    UP(t_render, p->t_render);
+    UP(t_one, p->t_one);
+#undef UP
+    *out = t.get();
+    p->dev.emplace(dev, std::move(t));
+    return VP_OK;
+}
+
+void fill_desc(const vp_plan* p, const DeviceTables* t, SliceDesc* d) {
+    std::memset(d, 0, sizeof *d);
+    d->n = p->n;
+    d->S = p->S;
+    d->T = p->T;
+    d->B = p->B;
+    d->nparts = p->nparts;
+    d->nstage = p->nstage;
+    for (int i = 0; i < kMaxStages; ++i) d->radix[i] = p->radix[i];
+    d->n_col_items = p->n_col_items;
+    d->tw = t->tw;
+    d->mask = t->mask;
+    d->shear = t->shear;
+    d->blade = t->blade;
+    d->knot_ptr = t->knot_ptr;
+    d->knot_ent = t->knot_ent;
+    d->groups = t->groups;
+    d->step_limit = 0x7fffffff;
+    d->schedule = VP_SCHED_ALL_BLADES;
+    d->optimizer = VP_OPT_ADAM;
+}
+
+static void set_hyper(SliceDesc* d, const vp_options* o) {
+    d->optimizer = o->optimizer;
+    d->schedule = o->schedule;
+    d->lr = o->lr;
+    d->beta1 = o->beta1;
+    d->beta2 = o->beta2;
+    d->adam_eps = o->adam_eps;
+    d->tv_w = o->tv_weight;
+    d->l1_w = o->l1_weight;
+    d->tv_eps = o->tv_eps;
+}
+
+vp_status check_options(const vp_plan* p, const vp_options* o) {
+    if (!o) return fail(VP_ERR_ARG, "NULL options");
+    const float fs[] = {o->tv_weight, o->l1_weight, o->tv_eps, o->lr, o->beta1, o->beta2, o->adam_eps};
+    for (float f : fs)
+        if (!std::isfinite(f)) return fail(VP_ERR_ARG, "options: non-finite value");
+    if (o->tv_weight < 0 || o->l1_weight < 0 || o->tv_eps <= 0)
+        return fail(VP_ERR_ARG, "options: weights must be >= 0 and tv_eps > 0");
+    if (o->n_steps < 0) return fail(VP_ERR_ARG, "options: n_steps < 0");
+    if (o->optimizer != VP_OPT_ADAM && o->optimizer != VP_OPT_GD) return fail(VP_ERR_ARG, "options: optimizer");
+    if (o->schedule != VP_SCHED_ALL_BLADES && o->schedule != VP_SCHED_CYCLIC)
+        return fail(VP_ERR_ARG, "options: schedule");
+    if (o->optimizer == VP_OPT_ADAM && (o->beta1 < 0 || o->beta1 >= 1 || o->beta2 < 0 || o->beta2 >= 1))
+        return fail(VP_ERR_ARG, "options: betas must lie in [0, 1)");
+    if (o->split_bin > p->S) return fail(VP_ERR_ARG, "options: split_bin above n_spec");
+    return VP_OK;
+}
+
+// ------------------------------------------------------------------ launch sequences
+
+void launch_step(const KArgs& base, const StageLists& L, hipStream_t s, hipError_t* err) {
+    KArgs a = base;
+    hipError_t e;
+    a.tasks = L.proj; a.ntasks = L.n_proj;
+    if ((e = launch_project(a, L.lds_proj, s)) != hipSuccess) { *err = e; return; }
+    a.tasks = L.rows; a.ntasks = L.n_rows;
+    if ((e = launch_rows(a, -1, L.lds_rows, s)) != hipSuccess) { *err = e; return; }
+    a.tasks = L.cols; a.ntasks = L.n_cols; a.mode = COL_STEP;
+    if ((e = launch_cols(a, L.lds_cols, s)) != hipSuccess) { *err = e; return; }
+    a.tasks = L.rows; a.ntasks = L.n_rows;
+    if ((e = launch_rows(a, 1, L.lds_rows, s)) != hipSuccess) { *err = e; return; }
+    a.tasks = L.gath; a.ntasks = L.n_gath;
+    if ((e = launch_gather(a, GATHER_STEP, L.lds_gath, s)) != hipSuccess) { *err = e; return; }
+    a.tasks = L.one; a.ntasks = L.n_one;
+    if ((e = launch_bump(a, s)) != hipSuccess) { *err = e; return; }
+    *err = hipSuccess;
+}
+
+StageLists plan_lists(const vp_plan* p, const DeviceTables* t) {
+    StageLists L;
+    L.proj = t->t_proj; L.n_proj = (int)p->t_proj.size();
+    L.rows = t->t_rows; L.n_rows = (int)p->t_rows.size();
+    L.cols = t->t_cols; L.n_cols = (int)p->t_cols.size();
+    L.gath = t->t_gath; L.n_gath = (int)p->t_gath.size();
+    L.vox = t->t_vox; L.n_vox = (int)p->t_vox.size();
+    L.render = t->t_render; L.n_render = (int)p->t_render.size();
+    L.one = t->t_one; L.n_one = 1;
+    L.lds_proj = p->lds_proj; L.lds_rows = p->lds_rows; L.lds_cols = p->lds_cols; L.lds_gath = p->lds_gath;
+    return L;
+}
+
+}  // namespace vp
+
+using namespace vp;
+
+// ------------------------------------------------------------------ plans
+
+extern "C" vp_status vp_plan_destroy(vp_plan* p) {
+    delete p;
+    return VP_OK;
+}
+
+// ------------------------------------------------------------------ operators
+
+namespace {
+
+struct OpScope {
+    const vp_plan* p;
+    DeviceTables* t = nullptr;
+    hipStream_t s;
+    float2* work = nullptr;
+    explicit OpScope(const vp_plan* plan, void* stream) : p(plan), s((hipStream_t)stream) {}
+    vp_status begin(bool need_work) {
+        vp_status st = plan_tables(p, &t);
+        if (st != VP_OK) return st;
+        if (need_work) {
+            const size_t bytes = (size_t)p->nparts * p->blade_px() * sizeof(float2);
+            hipError_t e = hipMallocAsync((void**)&work, bytes, s);
+            if (e != hipSuccess) return hip_status(e, "workspace");
+        }
+        return VP_OK;
+    }
+    ~OpScope() {
+        if (work) (void)hipFreeAsync(work, s);
+    }
+};
+
+}  // namespace
+
+extern "C" vp_status vp_forward(const vp_plan* p, const vp_c64* d_vol, const vp_c64* d_y, vp_c64* d_out,
+                                void* stream) {
+    clear_error();
+    if (!p || !d_vol || !d_out) return fail(VP_ERR_ARG, "vp_forward: NULL argument");
+    OpScope sc(p, stream);
+    vp_status st = sc.begin(true);
+    if (st != VP_OK) return st;
+    KArgs a{};
+    fill_desc(p, sc.t, &a.one);
+    a.one.vol[0] = (float2*)d_vol;
+    a.one.y = (const float2*)d_y;
+    a.one.work = sc.work;
+    const StageLists L = plan_lists(p, sc.t);
+    hipError_t e;
+    a.tasks = L.proj; a.ntasks = L.n_proj;
+    if ((e = launch_project(a, L.lds_proj, sc.s)) != hipSuccess) return hip_status(e, "vp_forward project");
+    a.tasks = L.rows; a.ntasks = L.n_rows;
+    if ((e = launch_rows(a, -1, L.lds_rows, sc.s)) != hipSuccess) return hip_status(e, "vp_forward rows");
+    a.tasks = L.cols; a.ntasks = L.n_cols; a.mode = COL_FORWARD; a.out0 = (float2*)d_out;
+    if ((e = launch_cols(a, L.lds_cols, sc.s)) != hipSuccess) return hip_status(e, "vp_forward cols");
+    return VP_OK;
+}
+
+extern "C" vp_status vp_adjoint(const vp_plan* p, const vp_c64* d_kres, vp_c64* d_grad, int32_t accumulate,
+                                void* stream) {
+    clear_error();
+    if (!p || !d_kres || !d_grad) return fail(VP_ERR_ARG, "vp_adjoint: NULL argument");
+    OpScope sc(p, stream);
+    vp_status st = sc.begin(true);
+    if (st != VP_OK) return st;
+    KArgs a{};
+    fill_desc(p, sc.t, &a.one);
+    a.one.work = sc.work;
+    a.one.grad = (float2*)d_grad;
+    a.accumulate = accumulate != 0;
+    const StageLists L = plan_lists(p, sc.t);
+    hipError_t e;
+    a.tasks = L.cols; a.ntasks = L.n_cols; a.mode = COL_ADJOINT; a.in0 = (const float2*)d_kres;
+    if ((e = launch_cols(a, L.lds_cols, sc.s)) != hipSuccess) return hip_status(e, "vp_adjoint cols");
+    a.tasks = L.rows; a.ntasks = L.n_rows;
+    if ((e = launch_rows(a, 1, L.lds_rows, sc.s)) != hipSuccess) return hip_status(e, "vp_adjoint rows");
+    a.tasks = L.gath; a.ntasks = L.n_gath;
+    if ((e = launch_gather(a, GATHER_STORE, L.lds_gath, sc.s)) != hipSuccess) return hip_status(e, "vp_adjoint gather");
+    return VP_OK;
+}
+
+extern "C" vp_status vp_tv_grad(const vp_plan* p, const vp_c64* d_vol, float tv_w, float l1_w, float eps,
+                                vp_c64* d_grad, int32_t accumulate, void* stream) {
+    clear_error();
+    if (!p || !d_vol || !d_grad) return fail(VP_ERR_ARG, "vp_tv_grad: NULL argument");
+    if (!std::isfinite(tv_w) || !std::isfinite(l1_w) || !(eps > 0) || !std::isfinite(eps))
+        return fail(VP_ERR_ARG, "vp_tv_grad: weights must be finite and eps > 0");
+    OpScope sc(p, stream);
+    vp_status st = sc.begin(false);
+    if (st != VP_OK) return st;
+    KArgs a{};
+    fill_desc(p, sc.t, &a.one);
+    a.one.vol[0] = (float2*)d_vol;
+    a.one.grad = (float2*)d_grad;
+    a.one.tv_w = tv_w;
+    a.one.l1_w = l1_w;
+    a.one.tv_eps = eps;
+    a.accumulate = accumulate != 0;
+    a.tasks = sc.t->t_vox;
+    a.ntasks = (int)p->t_vox.size();
+    hipError_t e = launch_tv_grad(a, sc.s);
+    return hip_status(e, "vp_tv_grad");
+}
+
+extern "C" vp_status vp_render(const vp_plan* p, const vp_c64* d_vol, int32_t split_bin, vp_c64* d_proj,
+                               vp_c64* d_water, vp_c64* d_fat, void* stream) {
+    clear_error();
+    if (!p || !d_vol) return fail(VP_ERR_ARG, "vp_render: NULL argument");
+    if (split_bin > p->S) return fail(VP_ERR_ARG, "vp_render: split_bin above n_spec");
+    OpScope sc(p, stream);
+    vp_status st = sc.begin(false);
+    if (st != VP_OK) return st;
+    KArgs a{};
+    fill_desc(p, sc.t, &a.one);
+    a.one.vol[0] = (float2*)d_vol;
+    a.split_bin = split_bin;
+    a.out0 = (float2*)d_proj;
+    a.out1 = (float2*)d_water;
+    a.out2 = (float2*)d_fat;
+    a.tasks = sc.t->t_render;
+    a.ntasks = (int)p->t_render.size();
+    return hip_status(launch_render(a, sc.s), "vp_render");
+}
+
+// ------------------------------------------------------------------ sessions
+
+vp_session::~vp_session() {
+    if (device >= 0) (void)hipSetDevice(device);
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (stream) (void)hipStreamSynchronize(stream);
+    void* ptrs[] = {vol[0], vol[1], m, v, work, y, loss_part, step_dev, dpart, render};
+    for (void* q : ptrs)
+        if (q) (void)hipFree(q);
+    if (stream && own_stream) (void)hipStreamDestroy(stream);
+}
+
+namespace vp {
+
+static bool all_finite(const vp_c64* a, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(a[i].re) || !std::isfinite(a[i].im)) return false;
+    return true;
+}
+
+vp_status session_alloc(const vp_plan* p, const vp_options* o, const vp_c64* kspace, const vp_c64* init,
+                        hipStream_t stream, vp_session** out) {
+    vp_status st = check_options(p, o);
+    if (st != VP_OK) return st;
+    if (!kspace) return fail(VP_ERR_ARG, "session: NULL kspace");
+    if (!all_finite(kspace, p->blade_px())) return fail(VP_ERR_NONFINITE, "session: kspace holds NaN or Inf");
+    if (init && !all_finite(init, p->voxels())) return fail(VP_ERR_NONFINITE, "session: init holds NaN or Inf");
+    std::unique_ptr<vp_session> s(new (std::nothrow) vp_session());
+    if (!s) return fail(VP_ERR_NOMEM, "session: out of host memory");
+    s->plan = p;
+    s->opts = *o;
+    hipError_t e = hipSetDevice(o->device);
+    if (e != hipSuccess) return hip_status(e, "hipSetDevice");
+    s->device = o->device;
+    if (stream) {
+        s->stream = stream;
+        s->own_stream = false;
+    } else {
+        e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_status(e, "hipStreamCreate");
+        s->own_stream = true;
+    }
+    st = plan_tables(p, &s->tabs);
+    if (st != VP_OK) return st;
+    const size_t vb = p->voxels() * sizeof(float2);
+    const size_t bb = p->blade_px() * sizeof(float2);
+#define ALLOC(ptr, bytes)                                               \
+    do {                                                                \
+        e = hipMalloc((void**)&(ptr), std::max<size_t>(8, (bytes)));   \
+        if (e != hipSuccess) return hip_status(e, "session allocation"); \
+    } while (0)
+    ALLOC(s->vol[0], vb);
+    ALLOC(s->vol[1], vb);
+    if (o->optimizer == VP_OPT_ADAM) {
+        ALLOC(s->m, vb);
+        ALLOC(s->v, vb);
+    }
+    ALLOC(s->work, (size_t)p->nparts * bb);
+    ALLOC(s->y, bb);
+    ALLOC(s->loss_part, loss_slots(p) * sizeof(float));
+    ALLOC(s->step_dev, 64);
+    ALLOC(s->dpart, 2 * p->t_vox.size() * sizeof(double));
+    ALLOC(s->render, 3 * (size_t)p->T * p->n * p->n * sizeof(float2));
+#undef ALLOC
+    if (init) e = hipMemcpyAsync(s->vol[0], init, vb, hipMemcpyHostToDevice, s->stream);
+    else e = hipMemsetAsync(s->vol[0], 0, vb, s->stream);
+    if (e == hipSuccess && s->m) e = hipMemsetAsync(s->m, 0, vb, s->stream);
+    if (e == hipSuccess && s->v) e = hipMemsetAsync(s->v, 0, vb, s->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(s->y, kspace, bb, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s->step_dev, 0, 64, s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s->loss_part, 0, loss_slots(p) * sizeof(float), s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_status(e, "session upload");
+    fill_desc(p, s->tabs, &s->desc);
+    set_hyper(&s->desc, o);
+    s->desc.vol[0] = s->vol[0];
+    s->desc.vol[1] = s->vol[1];
+    s->desc.m = s->m;
+    s->desc.v = s->v;
+    s->desc.work = s->work;
+    s->desc.y = s->y;
+    s->desc.loss_part = s->loss_part;
+    s->desc.step = s->step_dev;
+    s->lists = plan_lists(p, s->tabs);
+    *out = s.release();
+    return VP_OK;
+}
+
+vp_status session_run(vp_session* s, int32_t n_steps, int32_t use_graph) {
+    hipError_t e = hipSetDevice(s->device);
+    if (e != hipSuccess) return hip_status(e, "hipSetDevice");
+    KArgs a{};
+    a.one = s->desc;
+    if (use_graph && n_steps > 1) {
+        if (!s->gexec) {
+            e = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return hip_status(e, "hipStreamBeginCapture");
+            hipError_t le = hipSuccess;
+            launch_step(a, s->lists, s->stream, &le);
+            e = hipStreamEndCapture(s->stream, &s->graph);
+            if (le != hipSuccess) return hip_status(le, "step capture");
+            if (e != hipSuccess) return hip_status(e, "hipStreamEndCapture");
+            e = hipGraphInstantiate(&s->gexec, s->graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) return hip_status(e, "hipGraphInstantiate");
+        }
+        for (int i = 0; i < n_steps; ++i) {
+            e = hipGraphLaunch(s->gexec, s->stream);
+            if (e != hipSuccess) return hip_status(e, "hipGraphLaunch");
+        }
+    } else {
+        for (int i = 0; i < n_steps; ++i) {
+            launch_step(a, s->lists, s->stream, &e);
+            if (e != hipSuccess) return hip_status(e, "step launch");
+        }
+    }
+    s->steps_done += n_steps;
+    return VP_OK;
+}
+
+vp_status session_objective(vp_session* s, double* objective, double* data_term) {
+    const vp_plan* p = s->plan;
+    hipError_t e = hipSetDevice(s->device);
+    if (e != hipSuccess) return hip_status(e, "hipSetDevice");
+    KArgs a{};
+    a.one = s->desc;
+    a.one.schedule = VP_SCHED_ALL_BLADES;
+    a.one.step_limit = 0x7fffffff;
+    const StageLists& L = s->lists;
+    a.tasks = L.proj; a.ntasks = L.n_proj;
+    if ((e = launch_project(a, L.lds_proj, s->stream)) != hipSuccess) return hip_status(e, "objective");
+    a.tasks = L.rows; a.ntasks = L.n_rows;
+    if ((e = launch_rows(a, -1, L.lds_rows, s->stream)) != hipSuccess) return hip_status(e, "objective");
+    a.tasks = L.cols; a.ntasks = L.n_cols; a.mode = COL_STEP;
+    if ((e = launch_cols(a, L.lds_cols, s->stream)) != hipSuccess) return hip_status(e, "objective");
+    a.tasks = L.vox; a.ntasks = L.n_vox; a.dpart = s->dpart;
+    if ((e = launch_reg_value(a, s->stream)) != hipSuccess) return hip_status(e, "objective");
+    std::vector<float> lp(loss_slots(p));
+    std::vector<double> dp(2 * p->t_vox.size());
+    e = hipMemcpyAsync(lp.data(), s->loss_part, lp.size() * sizeof(float), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dp.data(), s->dpart, dp.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_status(e, "objective readback");
+    double data = 0.0, tv = 0.0, l1 = 0.0;
+    for (float x : lp) data += (double)x;
+    data *= 0.5;
+    for (size_t i = 0; i < p->t_vox.size(); ++i) {
+        tv += dp[2 * i];
+        l1 += dp[2 * i + 1];
+    }
+    const double obj = data + (double)s->opts.tv_weight * tv + (double)s->opts.l1_weight * l1;
+    if (objective) *objective = obj;
+    if (data_term) *data_term = data;
+    if (!std::isfinite(obj)) return fail(VP_ERR_NONFINITE, "objective is not finite");
+    return VP_OK;
+}
+
+vp_status session_read(vp_session* s, vp_c64* volume_out, vp_c64* proj_out, vp_c64* water_out, vp_c64* fat_out) {
+    const vp_plan* p = s->plan;
+    hipError_t e = hipSetDevice(s->device);
+    if (e != hipSuccess) return hip_status(e, "hipSetDevice");
+    const size_t vb = p->voxels() * sizeof(float2);
+    const size_t rb = (size_t)p->T * p->n * p->n * sizeof(float2);
+    float2* cur = s->vol[s->steps_done & 1];
+    if (proj_out || water_out || fat_out) {
+        KArgs a{};
+        a.one = s->desc;
+        a.split_bin = s->opts.split_bin;
+        a.out0 = s->render;
+        a.out1 = s->render + (size_t)p->T * p->n * p->n;
+        a.out2 = s->render + 2 * (size_t)p->T * p->n * p->n;
+        a.tasks = s->lists.render;
+        a.ntasks = s->lists.n_render;
+        if ((e = launch_render(a, s->stream)) != hipSuccess) return hip_status(e, "render");
+        vp_c64* outs[3] = {proj_out, water_out, fat_out};
+        for (int i = 0; i < 3 && e == hipSuccess; ++i)
+            if (outs[i])
+                e = hipMemcpyAsync(outs[i], s->render + (size_t)i * p->T * p->n * p->n, rb, hipMemcpyDeviceToHost,
+                                   s->stream);
+    }
+    if (e == hipSuccess && volume_out) e = hipMemcpyAsync(volume_out, cur, vb, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    return hip_status(e, "session read");
+}
+
+}  // namespace vp
+
+extern "C" vp_status vp_session_create(const vp_plan* p, const vp_options* o, const vp_c64* kspace,
+                                       const vp_c64* init, vp_session** out) {
+    clear_error();
+    if (!p || !o || !out) return fail(VP_ERR_ARG, "vp_session_create: NULL argument");
+    return session_alloc(p, o, kspace, init, nullptr, out);
+}
+
+extern "C" vp_status vp_session_step(vp_session* s, int32_t n_steps, int32_t use_graph) {
+    clear_error();
+    if (!s || n_steps < 0) return fail(VP_ERR_ARG, "vp_session_step: bad argument");
+    vp_status st = session_run(s, n_steps, use_graph);
+    if (st != VP_OK) return st;
+    return hip_status(hipStreamSynchronize(s->stream), "vp_session_step");
+}
+
+extern "C" vp_status vp_session_steps_done(const vp_session* s, int64_t* steps) {
+    if (!s || !steps) return fail(VP_ERR_ARG, "vp_session_steps_done: NULL argument");
+    *steps = s->steps_done;
+    return VP_OK;
+}
+
+extern "C" vp_status vp_session_read(vp_session* s, vp_c64* volume_out, vp_c64* proj_out, vp_c64* water_out,
+                                     vp_c64* fat_out) {
+    clear_error();
+    if (!s) return fail(VP_ERR_ARG, "vp_session_read: NULL session");
+    return session_read(s, volume_out, proj_out, water_out, fat_out);
+}
+
+extern "C" vp_status vp_session_objective(vp_session* s, double* objective, double* data_term) {
+    clear_error();
+    if (!s) return fail(VP_ERR_ARG, "vp_session_objective: NULL session");
+    return session_objective(s, objective, data_term);
+}
+
+extern "C" vp_status vp_session_get_state(vp_session* s, vp_c64* volume, vp_c64* m, vp_c64* v, int64_t* step) {
+    clear_error();
+    if (!s) return fail(VP_ERR_ARG, "vp_session_get_state: NULL session");
+    const vp_plan* p = s->plan;
+    hipError_t e = hipSetDevice(s->device);
+    const size_t vb = p->voxels() * sizeof(float2);
+    if (e == hipSuccess && volume)
+        e = hipMemcpyAsync(volume, s->vol[s->steps_done & 1], vb, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess && m) {
+        if (s->m) e = hipMemcpyAsync(m, s->m, vb, hipMemcpyDeviceToHost, s->stream);
+        else std::memset(m, 0, vb);
+    }
+    if (e == hipSuccess && v) {
+        if (s->v) e = hipMemcpyAsync(v, s->v, vb, hipMemcpyDeviceToHost, s->stream);
+        else std::memset(v, 0, vb);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (step) *step = s->steps_done;
+    return hip_status(e, "vp_session_get_state");
+}
+
+extern "C" vp_status vp_session_set_state(vp_session* s, const vp_c64* volume, const vp_c64* m, const vp_c64* v,
+                                          int64_t step) {
+    clear_error();
+    if (!s || !volume || step < 0 || step > 0x7ffffffe) return fail(VP_ERR_ARG, "vp_session_set_state: bad argument");
+    const vp_plan* p = s->plan;
+    if (!all_finite(volume, p->voxels())) return fail(VP_ERR_NONFINITE, "vp_session_set_state: non-finite volume");
+    hipError_t e = hipSetDevice(s->device);
+    const size_t vb = p->voxels() * sizeof(float2);
+    const int st32 = (int)step;
+    if (e == hipSuccess) e = hipMemcpyAsync(s->vol[step & 1], volume, vb, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess && s->m) {
+        if (m) e = hipMemcpyAsync(s->m, m, vb, hipMemcpyHostToDevice, s->stream);
+        else e = hipMemsetAsync(s->m, 0, vb, s->stream);
+    }
+    if (e == hipSuccess && s->v) {
+        if (v) e = hipMemcpyAsync(s->v, v, vb, hipMemcpyHostToDevice, s->stream);
+        else e = hipMemsetAsync(s->v, 0, vb, s->stream);
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(s->step_dev, &st32, sizeof st32, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e == hipSuccess) s->steps_done = step;
+    return hip_status(e, "vp_session_set_state");
+}
+
+extern "C" vp_status vp_session_destroy(vp_session* s) {
+    delete s;
+    return VP_OK;
+}
+
+// ------------------------------------------------------------------ whole reconstructions
+
+extern "C" vp_status vp_reconstruct(const vp_plan* p, const vp_options* o, const vp_c64* kspace, const vp_c64* init,
+                                    vp_c64* volume_out, vp_c64* proj_out, vp_c64* water_out, vp_c64* fat_out,
+                                    double* final_loss) {
+    clear_error();
+    if (!p || !o || !kspace) return fail(VP_ERR_ARG, "vp_reconstruct: NULL argument");
+    vp_session* raw = nullptr;
+    vp_status st = session_alloc(p, o, kspace, init, nullptr, &raw);
+    if (st != VP_OK) return st;
+    std::unique_ptr<vp_session> s(raw);
+    st = session_run(s.get(), o->n_steps, 1);
+    if (st != VP_OK) return st;
+    double obj = 0.0;
+    st = session_objective(s.get(), &obj, nullptr);
+    if (final_loss) *final_loss = obj;
+    const vp_status rs = session_read(s.get(), volume_out, proj_out, water_out, fat_out);
+    if (st != VP_OK) return st;
+    return rs;
+}

@@ -1,0 +1,120 @@
+// Internal types shared by the host plan/runtime and the HIP kernels of libvp.
+//
+// Device data layout (all complex values are float2 = (re, im)):
+//   volume      [T][S][n][n]   two copies (ping-pong by step parity) during a fit
+//   Adam m, v   [T][S][n][n]   float2 per voxel: moments of Re and of Im
+//   blade work  [B][P][n][n]   P = 1 (static) or 2 (dynamic: the unweighted
+//                              projections of a blade's two knots); part 0 also
+//                              carries the blade image through the FFT passes
+//   measured y  [B][n][n]      unshifted k-space
+//   mask        [B][n][n]      uint8
+#pragma once
+
+#include <cstdint>
+#include <hip/hip_runtime.h>
+
+namespace vp {
+
+constexpr int kMaxN = 512;
+constexpr int kMaxS = 256;
+constexpr int kMaxT = 64;
+constexpr int kMaxB = 256;
+constexpr int kMaxStages = 12;
+constexpr double kMaxShift = 16.0;
+constexpr int kThreads = 256;
+
+// Projection tiles: TX x TY output pixels per work item, up to kGroup blade parts
+// accumulated together (one pass over the knot's spectral planes).
+constexpr int kProjTX = 64;
+constexpr int kProjTY = 16;
+constexpr int kGroup = 8;
+// Adjoint gather tiles: TX x TY voxels, spectral bins in chunks of kChunk.
+constexpr int kGathTX = 32;
+constexpr int kGathTY = 16;
+constexpr int kChunk = 16;
+// Voxel-wise kernels (TV, render, objective): elements per work item.
+constexpr int kVoxItem = 4096;
+
+// Rows per row-FFT work item and columns per column-FFT work item, as functions of n
+// only (never of the batch), so every slice's arithmetic is the same alone or batched.
+__host__ __device__ inline int fft_rows_per_item(int n) { int r = 2048 / n; return r < 1 ? 1 : (r > 16 ? 16 : r); }
+__host__ __device__ inline int fft_cols_per_item(int n) { return n > 256 ? 8 : 16; }
+
+struct ShearEntry {       // one (blade, bin): taps at rows y+oy(+1), columns x+ox(+1)
+    int ox, oy;
+    float w00, w01, w10, w11;  // (1-fy)(1-fx), (1-fy)fx, fy(1-fx), fy fx
+    int pad0, pad1;
+};
+
+struct BladeDev {
+    int knot;            // first knot of the blade's interval (0 for static plans)
+    int has0, has1;      // which unweighted knot projections exist
+    float w0, w1;        // their blend weights (1 - a, a)
+    int ox_min, ox_max, oy_min, oy_max;  // shear offset extents over all bins
+    int pad;
+};
+
+struct KnotEntry {       // a blade part that reads (projection) / feeds (adjoint) a knot
+    int blade, part;
+    float weight;
+    int pad;
+};
+
+struct ProjGroup {       // up to kGroup parts of one knot projected together
+    int knot, e0, ne;
+    int ox_min, ox_max, oy_min, oy_max;
+    int pad;
+};
+
+struct Task {            // one work item; field meaning depends on the kernel
+    int slice, a, b, c;
+};
+
+struct SliceDesc {
+    int n, S, T, B;
+    int nparts;                  // parts per blade in the work buffer (1 or 2)
+    int nstage;
+    int radix[kMaxStages];
+    int n_col_items;             // column work items per blade (loss partials per blade)
+    const float2* tw;            // twiddles exp(-2 pi i j / n), j < n
+    const uint8_t* mask;
+    const ShearEntry* shear;     // [B][S]
+    const BladeDev* blade;       // [B]
+    const int* knot_ptr;         // [T+1] CSR offsets into knot_ent
+    const KnotEntry* knot_ent;
+    const ProjGroup* groups;
+    const float2* y;             // measured k-space or nullptr
+    float2* vol[2];              // current volume = vol[step & 1]
+    float2* m;
+    float2* v;
+    float2* work;
+    float2* grad;                // gradient output of the operator path
+    float* loss_part;            // [B][n_col_items]
+    int* step;                   // device step counter; nullptr for operator calls
+    int step_limit;              // work items of slices with *step >= step_limit exit
+    int optimizer, schedule;
+    float lr, beta1, beta2, adam_eps;
+    float tv_w, l1_w, tv_eps;
+};
+
+struct KArgs {
+    const SliceDesc* descs;      // device array, or nullptr to use `one`
+    SliceDesc one;
+    const Task* tasks;
+    int ntasks;
+    int mode;
+    int split_bin;
+    int accumulate;
+    float2* out0;
+    float2* out1;
+    float2* out2;
+    const float2* in0;
+    double* dpart;
+};
+
+// Column pass modes.
+enum { COL_STEP = 0, COL_FORWARD = 1, COL_ADJOINT = 2 };
+// Gather epilogues.
+enum { GATHER_STORE = 0, GATHER_STEP = 1 };
+
+}  // namespace vp

@@ -1,0 +1,256 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances (relative L2 over the whole array): 1e-4 for the forward model, its
+adjoint and the regulariser gradient; 1e-3 for reconstructions after many Adam
+steps, where FP32 rounding of the gradient is amplified by Adam's per-coordinate
+normalisation.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from synth import configs
+
+pytestmark = pytest.mark.gpu
+
+FWD_TOL = 1e-4
+RECON_TOL = 1e-3
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.complex128)
+    b = np.asarray(b, dtype=np.complex128)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _t(x):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.complex64)).to("cuda")
+
+
+def _np(t):
+    import torch
+
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+SMALL = {
+    "static_48": dict(n=48, n_spec=6, n_blades=4, lines=12),
+    "static_80": dict(n=80, n_spec=5, n_blades=3, lines=10, f=3.0),
+    "static_60": dict(n=60, n_spec=3, n_blades=5, lines=7),
+    "dynamic_40": dict(n=40, n_spec=5, n_time=3, n_blades=6, lines=8),
+    "dynamic_96": dict(n=96, n_spec=4, n_time=4, n_blades=7, lines=12, f=2.5),
+}
+
+
+def small(name, **kw):
+    args = dict(SMALL[name])
+    args.update(kw)
+    return configs.small_case(**args)
+
+
+def _random_volume(case, seed=0):
+    rng = np.random.default_rng(seed)
+    shape = (case.n_time, case.n_spec, case.n, case.n)
+    return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).astype(np.complex64)
+
+
+def _random_kspace(case, seed=1):
+    rng = np.random.default_rng(seed)
+    shape = (case.n_blades, case.n, case.n)
+    return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).astype(np.complex64)
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_forward_and_adjoint_small(gpu_lib, name):
+    from paper_2311_13177_amd import binding as B
+
+    case = small(name)
+    plan = B.Plan.from_geometry(case.geometry())
+    geom = O.Geometry.from_dict(case.geometry())
+    vol = _random_volume(case)
+    y = O.simulate_measurements(case)
+    # forward with and without measurement
+    got = _np(B.vp_forward(plan, _t(vol)))
+    want = O.forward(vol.astype(np.complex128), geom)
+    assert rel(got, want) < FWD_TOL
+    got_r = _np(B.vp_forward(plan, _t(vol), _t(y)))
+    want_r = O.residual(vol.astype(np.complex128), geom, y)
+    assert rel(got_r, want_r) < FWD_TOL
+    # adjoint of an arbitrary k-space array (the mask is part of the operator)
+    k = _random_kspace(case)
+    got_a = _np(B.vp_adjoint(plan, _t(k)))
+    want_a = O.adjoint(k.astype(np.complex128), geom)
+    assert rel(got_a, want_a) < FWD_TOL
+    # accumulate adds
+    g = _t(got_a)
+    B.vp_adjoint(plan, _t(k), g, accumulate=True)
+    assert rel(_np(g), 2 * want_a) < FWD_TOL
+
+
+@pytest.mark.parametrize("name", ["static_64", "static_256", "dynamic_192"])
+def test_forward_and_adjoint_full_size(gpu_lib, name):
+    from paper_2311_13177_amd import binding as B
+
+    case = configs.CONFIGS[name]()
+    plan = B.Plan.from_geometry(case.geometry())
+    geom = O.Geometry.from_dict(case.geometry())
+    vol = _random_volume(case, seed=3)
+    got = _np(B.vp_forward(plan, _t(vol)))
+    want = O.forward(vol.astype(np.complex128), geom)
+    assert rel(got, want) < FWD_TOL
+    k = _random_kspace(case, seed=4)
+    got_a = _np(B.vp_adjoint(plan, _t(k)))
+    assert rel(got_a, O.adjoint(k.astype(np.complex128), geom)) < FWD_TOL
+
+
+@pytest.mark.parametrize("name", ["static_48", "dynamic_40"])
+def test_dot_product_on_gpu(gpu_lib, name):
+    from paper_2311_13177_amd import binding as B
+
+    case = small(name)
+    plan = B.Plan.from_geometry(case.geometry())
+    x = _random_volume(case, seed=5)
+    k = _random_kspace(case, seed=6)
+    masks = plan.masks()
+    k = (k * masks).astype(np.complex64)
+    ax = _np(B.vp_forward(plan, _t(x))).astype(np.complex128)
+    ahk = _np(B.vp_adjoint(plan, _t(k))).astype(np.complex128)
+    lhs = np.vdot(k.astype(np.complex128), ax)
+    rhs = np.vdot(ahk, x.astype(np.complex128))
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+
+
+@pytest.mark.parametrize("name", ["static_48", "dynamic_40"])
+def test_tv_grad_and_render(gpu_lib, name):
+    from paper_2311_13177_amd import binding as B
+
+    case = small(name)
+    plan = B.Plan.from_geometry(case.geometry())
+    vol = _random_volume(case, seed=7) * 0.1
+    v64 = vol.astype(np.complex128)
+    for tv_w, l1_w, eps in ((1e-3, 0.0, 1e-3), (0.5, 0.25, 0.05)):
+        got = _np(B.vp_tv_grad(plan, _t(vol), tv_w, l1_w, eps))
+        want = tv_w * O.tv_grad(v64, eps) + l1_w * O.l1_grad(v64, eps)
+        assert rel(got, want) < FWD_TOL
+    proj, water, fat = (_np(t) for t in B.vp_render(plan, _t(vol), 2))
+    p0, w0, f0 = O.render(v64, 2)
+    assert rel(proj, p0) < 1e-6 and rel(water, w0) < 1e-6 and rel(fat, f0) < 1e-6
+    assert np.array_equal(water + fat, proj)
+
+
+def _oracle_recon(case, y, opts, steps):
+    geom = O.Geometry.from_dict(case.geometry())
+    return O.reconstruct(geom, y, steps, tv_weight=opts.tv_weight, tv_eps=opts.tv_eps, l1_weight=opts.l1_weight,
+                         lr=opts.lr, beta1=opts.beta1, beta2=opts.beta2, adam_eps=opts.adam_eps,
+                         optimizer="adam" if opts.optimizer == 0 else "gd",
+                         schedule="all" if opts.schedule == 0 else "cyclic", split_bin=opts.split_bin)
+
+
+@pytest.mark.parametrize("name,optimizer,steps,schedule", [
+    ("static_48", 1, 5, 0),
+    ("static_48", 0, 30, 0),
+    ("static_80", 0, 20, 1),
+    ("dynamic_40", 1, 5, 0),
+    ("dynamic_96", 0, 25, 0),
+    ("static_60", 0, 20, 0),
+])
+def test_reconstruct_small(gpu_lib, name, optimizer, steps, schedule):
+    from paper_2311_13177_amd import binding as B
+
+    case = small(name)
+    y = O.simulate_measurements(case)
+    plan = B.Plan.from_geometry(case.geometry())
+    lr = 1e-2 if optimizer == 0 else 0.5 / (case.n_spec * case.n_blades)
+    opts = B.vp_options_default(n_steps=steps, optimizer=optimizer, lr=lr, schedule=schedule, l1_weight=1e-4)
+    got = B.vp_reconstruct(plan, y, opts)
+    want = _oracle_recon(case, y, opts, steps)
+    assert rel(got["proj"], want["proj"]) < RECON_TOL
+    assert rel(got["vol"], want["vol"]) < RECON_TOL
+    assert rel(got["water"], want["water"]) < RECON_TOL and rel(got["fat"], want["fat"]) < RECON_TOL
+    assert abs(got["final_loss"] - want["final_loss"]) <= 1e-3 * abs(want["final_loss"])
+
+
+def test_reconstruct_static_64_full(gpu_lib):
+    """The 64x64, S=16, five-blade workload for its full 200 Adam steps."""
+    from paper_2311_13177_amd import binding as B
+
+    case = configs.static_64()
+    y = O.simulate_measurements(case)
+    plan = B.Plan.from_geometry(case.geometry())
+    opts = B.vp_options_default(n_steps=case.n_steps, tv_weight=case.tv_weight, lr=case.lr)
+    got = B.vp_reconstruct(plan, y, opts)
+    want = _oracle_recon(case, y, opts, case.n_steps)
+    assert rel(got["proj"], want["proj"]) < RECON_TOL
+    assert abs(got["final_loss"] - want["final_loss"]) <= 1e-3 * abs(want["final_loss"])
+
+
+@pytest.mark.parametrize("name", ["static_256", "dynamic_192"])
+def test_reconstruct_full_size_first_steps(gpu_lib, name):
+    """Full-size workloads in the benchmark's launch configuration, first steps only."""
+    from paper_2311_13177_amd import binding as B
+
+    case = configs.CONFIGS[name]()
+    y = O.simulate_measurements(case)
+    plan = B.Plan.from_geometry(case.geometry())
+    steps = 3
+    opts = B.vp_options_default(n_steps=steps, tv_weight=case.tv_weight, lr=case.lr)
+    got = B.vp_reconstruct(plan, y, opts)
+    want = _oracle_recon(case, y, opts, steps)
+    assert rel(got["vol"], want["vol"]) < RECON_TOL
+    assert rel(got["proj"], want["proj"]) < RECON_TOL
+
+
+def test_graph_equals_eager_and_resume_is_bitwise(gpu_lib):
+    from paper_2311_13177_amd import binding as B
+
+    case = small("dynamic_40")
+    y = O.simulate_measurements(case)
+    plan = B.Plan.from_geometry(case.geometry())
+    opts = B.vp_options_default(n_steps=12)
+    a = B.Session(plan, y, opts)
+    a.step(12, use_graph=True)
+    b = B.Session(plan, y, opts)
+    b.step(12, use_graph=False)
+    ra, rb = a.read(), b.read()
+    assert np.array_equal(ra["vol"], rb["vol"])
+    c = B.Session(plan, y, opts)
+    c.step(5, use_graph=True)
+    st = c.get_state()
+    d = B.Session(plan, y, opts)
+    d.set_state(st)
+    d.step(7, use_graph=True)
+    assert d.steps_done == 12
+    assert np.array_equal(d.read()["vol"], ra["vol"])
+
+
+def test_nonfinite_measurement_rejected(gpu_lib):
+    from paper_2311_13177_amd import binding as B
+
+    case = small("static_48")
+    y = O.simulate_measurements(case)
+    y[0, 3, 4] = np.nan
+    plan = B.Plan.from_geometry(case.geometry())
+    with pytest.raises(B.VPError) as ei:
+        B.vp_reconstruct(plan, y, B.vp_options_default(n_steps=2))
+    assert ei.value.status == B.VP_ERR_NONFINITE
+
+
+def test_batch_equals_solo_bitwise(gpu_lib):
+    from paper_2311_13177_amd import binding as B
+
+    cases = [small("static_48"), small("dynamic_40"), small("static_80"), small("static_60")]
+    steps = [7, 5, 9, 6]
+    plans = [B.Plan.from_geometry(c.geometry()) for c in cases]
+    ys = [O.simulate_measurements(c) for c in cases]
+    opts = [B.vp_options_default(n_steps=s) for s in steps]
+    res = B.vp_batch_reconstruct(plans, ys, opts)
+    for c, p, y, o, r in zip(cases, plans, ys, opts, res):
+        assert r["status"] == 0 and r["steps_done"] == o.n_steps
+        solo = B.vp_reconstruct(p, y, o)
+        assert np.array_equal(r["vol"], solo["vol"])
+        assert np.array_equal(r["proj"], solo["proj"])
+        assert r["final_loss"] == solo["final_loss"]
