@@ -84,6 +84,7 @@ _PROTOS = {
     "vp_session_objective": (c_int32, [_P, POINTER(c_double), POINTER(c_double)]),
     "vp_session_get_state": (c_int32, [_P, _P, _P, _P, POINTER(c_int64)]),
     "vp_session_set_state": (c_int32, [_P, _P, _P, _P, c_int64]),
+    "vp_session_stage_times": (c_int32, [_P, c_int32, POINTER(c_double)]),
     "vp_session_destroy": (c_int32, [_P]),
     "vp_reconstruct": (c_int32, [_P, POINTER(vp_options), _P, _P, _P, _P, _P, _P, POINTER(c_double)]),
     "vp_batch_reconstruct": (c_int32, [c_int32, POINTER(_P), POINTER(POINTER(vp_options)), POINTER(_P),
@@ -326,6 +327,14 @@ class Session:
         outs = [np.empty(p.render_shape, np.complex64) for _ in range(3)]
         check(lib().vp_session_read(self.handle, _hp(vol), *[_hp(o) for o in outs]))
         return dict(vol=vol, proj=outs[0], water=outs[1], fat=outs[2])
+
+    STAGES = ("project", "rows_fwd", "cols", "rows_inv", "gather_update", "step_counter")
+
+    def stage_times(self, n_steps: int) -> dict:
+        """Mean milliseconds per stage over n_steps eager steps (HIP events on the session stream)."""
+        out = (c_double * len(self.STAGES))()
+        check(lib().vp_session_stage_times(self.handle, int(n_steps), out))
+        return dict(zip(self.STAGES, list(out)))
 
     def objective(self):
         o, d = c_double(), c_double()

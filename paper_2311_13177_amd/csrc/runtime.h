@@ -33,7 +33,9 @@ struct StageLists {
 StageLists plan_lists(const vp_plan* p, const DeviceTables* t);
 // Enqueues one optimiser step (project, row DFT, column pass, inverse row DFT,
 // gather + update, step counter) for the descriptors `base` refers to.
-void launch_step(const KArgs& base, const StageLists& L, hipStream_t s, hipError_t* err);
+// With `ev` (7 events) an event is recorded before each stage and after the last.
+void launch_step(const KArgs& base, const StageLists& L, hipStream_t s, hipError_t* err, hipEvent_t* ev = nullptr);
+constexpr int kStages = 6;
 
 vp_status hip_status(hipError_t e, const char* what);
 vp_status check_options(const vp_plan* p, const vp_options* o);

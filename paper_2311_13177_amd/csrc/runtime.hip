@@ -135,21 +135,33 @@ vp_status check_options(const vp_plan* p, const vp_options* o) {
 
 // ------------------------------------------------------------------ launch sequences
 
-void launch_step(const KArgs& base, const StageLists& L, hipStream_t s, hipError_t* err) {
+void launch_step(const KArgs& base, const StageLists& L, hipStream_t s, hipError_t* err, hipEvent_t* ev) {
     KArgs a = base;
     hipError_t e;
+#define MARK(i)                                                                         \
+    do {                                                                                \
+        if (ev && (e = hipEventRecord(ev[i], s)) != hipSuccess) { *err = e; return; }  \
+    } while (0)
+    MARK(0);
     a.tasks = L.proj; a.ntasks = L.n_proj;
     if ((e = launch_project(a, L.lds_proj, s)) != hipSuccess) { *err = e; return; }
+    MARK(1);
     a.tasks = L.rows; a.ntasks = L.n_rows;
     if ((e = launch_rows(a, -1, L.lds_rows, s)) != hipSuccess) { *err = e; return; }
+    MARK(2);
     a.tasks = L.cols; a.ntasks = L.n_cols; a.mode = COL_STEP;
     if ((e = launch_cols(a, L.lds_cols, s)) != hipSuccess) { *err = e; return; }
+    MARK(3);
     a.tasks = L.rows; a.ntasks = L.n_rows;
     if ((e = launch_rows(a, 1, L.lds_rows, s)) != hipSuccess) { *err = e; return; }
+    MARK(4);
     a.tasks = L.gath; a.ntasks = L.n_gath;
     if ((e = launch_gather(a, GATHER_STEP, L.lds_gath, s)) != hipSuccess) { *err = e; return; }
+    MARK(5);
     a.tasks = L.one; a.ntasks = L.n_one;
     if ((e = launch_bump(a, s)) != hipSuccess) { *err = e; return; }
+    MARK(6);
+#undef MARK
     *err = hipSuccess;
 }
 
@@ -558,6 +570,37 @@ extern "C" vp_status vp_session_set_state(vp_session* s, const vp_c64* volume, c
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e == hipSuccess) s->steps_done = step;
     return hip_status(e, "vp_session_set_state");
+}
+
+extern "C" vp_status vp_session_stage_times(vp_session* s, int32_t n_steps, double* stage_ms) {
+    clear_error();
+    if (!s || !stage_ms || n_steps < 1 || n_steps > 100000)
+        return fail(VP_ERR_ARG, "vp_session_stage_times: bad argument");
+    hipError_t e = hipSetDevice(s->device);
+    if (e != hipSuccess) return hip_status(e, "hipSetDevice");
+    const int ne = (kStages + 1) * n_steps;
+    std::vector<hipEvent_t> ev(ne, nullptr);
+    vp_status st = VP_OK;
+    for (int i = 0; i < ne && st == VP_OK; ++i) st = hip_status(hipEventCreate(&ev[i]), "hipEventCreate");
+    KArgs a{};
+    a.one = s->desc;
+    for (int k = 0; k < n_steps && st == VP_OK; ++k) {
+        launch_step(a, s->lists, s->stream, &e, &ev[(size_t)k * (kStages + 1)]);
+        st = hip_status(e, "stage-timed step");
+        if (st == VP_OK) ++s->steps_done;
+    }
+    if (st == VP_OK) st = hip_status(hipStreamSynchronize(s->stream), "stage-timed steps");
+    for (int j = 0; j < kStages; ++j) stage_ms[j] = 0.0;
+    for (int k = 0; k < n_steps && st == VP_OK; ++k)
+        for (int j = 0; j < kStages && st == VP_OK; ++j) {
+            float ms = 0.f;
+            hipEvent_t* b = &ev[(size_t)k * (kStages + 1)];
+            st = hip_status(hipEventElapsedTime(&ms, b[j], b[j + 1]), "hipEventElapsedTime");
+            stage_ms[j] += ms / n_steps;
+        }
+    for (hipEvent_t x : ev)
+        if (x) (void)hipEventDestroy(x);
+    return st;
 }
 
 extern "C" vp_status vp_session_destroy(vp_session* s) {
