@@ -36,7 +36,7 @@ struct SliceGroup {
 vp_status group_build(SliceGroup* g, const std::vector<vp_session*>& sessions, const std::vector<int>& limits) {
     const int ns = (int)sessions.size();
     std::vector<SliceDesc> descs(ns);
-    std::vector<Task> proj, rows, cols, gath, vox, render, one;
+    std::vector<Task> proj, rows, cols, gath, vox, render;
     StageLists L;
     for (int i = 0; i < ns; ++i) {
         const vp_plan* p = sessions[i]->plan;
@@ -54,16 +54,16 @@ vp_status group_build(SliceGroup* g, const std::vector<vp_session*>& sessions, c
         add(gath, p->t_gath);
         add(vox, p->t_vox);
         add(render, p->t_render);
-        one.push_back(Task{i, 0, 0, 0});
+        L.proj_gw = std::max(L.proj_gw, p->proj_gw);
         L.lds_proj = std::max(L.lds_proj, p->lds_proj);
         L.lds_rows = std::max(L.lds_rows, p->lds_rows);
         L.lds_cols = std::max(L.lds_cols, p->lds_cols);
         L.lds_gath = std::max(L.lds_gath, p->lds_gath);
     }
     std::vector<Task> all;
-    size_t off[7];
-    const std::vector<Task>* parts[7] = {&proj, &rows, &cols, &gath, &vox, &render, &one};
-    for (int k = 0; k < 7; ++k) {
+    size_t off[6];
+    const std::vector<Task>* parts[6] = {&proj, &rows, &cols, &gath, &vox, &render};
+    for (int k = 0; k < 6; ++k) {
         off[k] = all.size();
         all.insert(all.end(), parts[k]->begin(), parts[k]->end());
     }
@@ -86,7 +86,6 @@ vp_status group_build(SliceGroup* g, const std::vector<vp_session*>& sessions, c
     L.gath = g->d_tasks + off[3]; L.n_gath = (int)gath.size();
     L.vox = g->d_tasks + off[4]; L.n_vox = (int)vox.size();
     L.render = g->d_tasks + off[5]; L.n_render = (int)render.size();
-    L.one = g->d_tasks + off[6]; L.n_one = (int)one.size();
     g->lists = L;
     return VP_OK;
 }

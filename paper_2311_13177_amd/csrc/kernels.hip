@@ -3,18 +3,21 @@
 // Every kernel walks a list of work items (Task) with a grid-stride loop, so one
 // launch can cover one slice or many slices of different sizes; each item reads its
 // slice descriptor. Per-voxel and per-pixel summation orders depend only on the
-// slice's own plan (bins ascending, blades ascending, fixed tap order), never on
-// the batch or the tile that happens to hold the element.
+// slice's own plan (bins ascending, blade parts in plan order, fixed tap order), never
+// on the batch, the tile or the wave that happens to hold the element.
 //
 // Stages of one optimiser step (Sections 4.2 and 4.3 of the paper):
-//   k_project   sheared spectral projection of a knot's volume for up to kGroup
-//               blade parts, from LDS-staged volume planes
+//   k_project   sheared spectral projection of a knot's volume for a group of blade
+//               parts; the bin plane is staged in LDS once per block and shared by
+//               the four waves, each accumulating its own parts
 //   k_rows<FWD> blend of a blade's knot projections, forward DFT of every row
 //   k_cols      forward DFT of every column, 1/n scaling, blade mask, residual
 //               against the measurement, loss partials, inverse DFT of the column
 //   k_rows<INV> inverse DFT of every row: the image-space residual g_b
-//   k_gather    transposed shear as a gather over blades (no atomics) with a fused
-//               epilogue: TV/L1 gradient and the Adam or GD update
+//   k_gather    transposed shear as a gather over blade parts (no atomics); each
+//               blade image region is staged in LDS once per block and the four waves
+//               accumulate disjoint bins; fused epilogue: TV/L1 gradient and the Adam
+//               or GD update, and the step counter advanced by the last work item
 
 #include <hip/hip_runtime.h>
 
@@ -50,12 +53,16 @@ __device__ __forceinline__ float2 cfma(float w, float2 a, float2 acc) {
     return make_float2(__builtin_fmaf(w, a.x, acc.x), __builtin_fmaf(w, a.y, acc.y));
 }
 
+#define LOAD_DESC(a, tk) ((a).descs ? (a).descs[(tk).slice] : (a).one)
+
 // ------------------------------------------------------------------ DFT in LDS
 //
-// Mixed-radix Stockham autosort (radices 2, 3, 4, 5). `count` transforms of length n
-// live in LDS: element j of transform f at buf[f * fstride + j * estride]. Each stage
-// reads one buffer and writes the other; the result ends in *out. DIR = -1 is the
-// forward transform exp(-2 pi i jk/n), DIR = +1 the unnormalised inverse.
+// Mixed-radix Stockham autosort (radices 2, 3, 4, 5), in place: in every stage each
+// thread reads the inputs of its butterflies into registers, the block synchronises,
+// and each thread writes its outputs. `count` transforms of length n live in LDS:
+// element j of transform f at buf[f * fstride + j * estride], with n * count <= E *
+// kThreads. Twiddles exp(-2 pi i j / n) are read from an LDS table. DIR = -1 is the
+// forward transform, DIR = +1 the unnormalised inverse.
 
 template <int DIR, int R>
 __device__ __forceinline__ void butterfly(float2 (&x)[R]) {
@@ -98,77 +105,119 @@ __device__ __forceinline__ void butterfly(float2 (&x)[R]) {
     }
 }
 
-template <int DIR, int R, bool FFAST>
-__device__ __forceinline__ void stockham_stage(const float2* __restrict__ src, float2* __restrict__ dst, int n,
-                                               int count, int fstride, int estride, int p,
-                                               const float2* __restrict__ tw) {
+template <int DIR, int R, bool FFAST, int E>
+__device__ __forceinline__ void stockham_stage(float2* buf, const float2* tw, int n, int count, int fstride,
+                                               int estride, int p) {
+    constexpr int MAXB = (E + R - 1) / R;  // butterflies per thread (n * count <= E * kThreads)
     const int m = n / R;
     const int total = m * count;
     const int tws = n / (p * R);
-    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-        int f, j;
-        if (FFAST) {
-            f = idx % count;
-            j = idx / count;
-        } else {
-            j = idx % m;
-            f = idx / m;
+    float2 x[MAXB][R];
+    int bout[MAXB];
+#pragma unroll
+    for (int t = 0; t < MAXB; ++t) {
+        const int idx = threadIdx.x + t * kThreads;
+        bout[t] = -1;
+        if (idx < total) {
+            int f, j;
+            if (FFAST) {
+                f = idx % count;
+                j = idx / count;
+            } else {
+                j = idx % m;
+                f = idx / m;
+            }
+            const int k = j % p;
+            const int bin = f * fstride + j * estride;
+            bout[t] = f * fstride + ((j - k) * R + k) * estride;
+#pragma unroll
+            for (int q = 0; q < R; ++q) x[t][q] = buf[bin + q * m * estride];
+#pragma unroll
+            for (int q = 1; q < R; ++q) {
+                float2 w = tw[k * q * tws];
+                if (DIR > 0) w.y = -w.y;
+                x[t][q] = cmul(x[t][q], w);
+            }
+            butterfly<DIR, R>(x[t]);
         }
-        const int k = j % p;
-        const int bin = f * fstride + j * estride;
-        const int bout = f * fstride + ((j - k) * R + k) * estride;
-        float2 x[R];
-#pragma unroll
-        for (int q = 0; q < R; ++q) x[q] = src[bin + q * m * estride];
-#pragma unroll
-        for (int q = 1; q < R; ++q) {
-            float2 w = tw[k * q * tws];
-            if (DIR > 0) w.y = -w.y;
-            x[q] = cmul(x[q], w);
-        }
-        butterfly<DIR, R>(x);
-#pragma unroll
-        for (int q = 0; q < R; ++q) dst[bout + q * p * estride] = x[q];
     }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < MAXB; ++t) {
+        if (bout[t] >= 0) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) buf[bout[t] + q * p * estride] = x[t][q];
+        }
+    }
+    __syncthreads();
 }
 
-template <int DIR, bool FFAST>
-__device__ float2* lds_fft(float2* a, float2* b, int n, int count, int fstride, int estride, const SliceDesc& d) {
+template <int DIR, bool FFAST, int E>
+__device__ void lds_fft(float2* buf, const float2* tw, int n, int count, int fstride, int estride,
+                        const SliceDesc& d) {
     int p = 1;
-    float2* src = a;
-    float2* dst = b;
     for (int st = 0; st < d.nstage; ++st) {
         const int r = d.radix[st];
         switch (r) {
-            case 4: stockham_stage<DIR, 4, FFAST>(src, dst, n, count, fstride, estride, p, d.tw); break;
-            case 2: stockham_stage<DIR, 2, FFAST>(src, dst, n, count, fstride, estride, p, d.tw); break;
-            case 3: stockham_stage<DIR, 3, FFAST>(src, dst, n, count, fstride, estride, p, d.tw); break;
-            default: stockham_stage<DIR, 5, FFAST>(src, dst, n, count, fstride, estride, p, d.tw); break;
+            case 4: stockham_stage<DIR, 4, FFAST, E>(buf, tw, n, count, fstride, estride, p); break;
+            case 2: stockham_stage<DIR, 2, FFAST, E>(buf, tw, n, count, fstride, estride, p); break;
+            case 3: stockham_stage<DIR, 3, FFAST, E>(buf, tw, n, count, fstride, estride, p); break;
+            default: stockham_stage<DIR, 5, FFAST, E>(buf, tw, n, count, fstride, estride, p); break;
         }
-        __syncthreads();
-        float2* t = src;
-        src = dst;
-        dst = t;
         p *= r;
     }
-    return src;
 }
 
-#define LOAD_DESC(a, tk) ((a).descs ? (a).descs[(tk).slice] : (a).one)
+// ------------------------------------------------------------------ LDS staging
+//
+// A rectangular region (rows x cols) of an n x n image, origin (gy0, gx0), is staged
+// into LDS with zeros outside the image. Each thread owns region elements
+// threadIdx.x + k * kThreads (k < kStageMax); their image offsets are computed once per
+// work item, and the next plane's values are loaded into registers while the current
+// plane is being consumed (double-buffered LDS, one barrier per plane).
+
+struct Stager {
+    int off[kStageMax];
+    __device__ void init(int rows, int cols, int gy0, int gx0, int n) {
+        const int re = rows * cols;
+#pragma unroll
+        for (int k = 0; k < kStageMax; ++k) {
+            const int i = threadIdx.x + k * kThreads;
+            int o = -1;
+            if (i < re) {
+                const int r = i / cols, c = i - (i / cols) * cols;
+                const int gy = gy0 + r, gx = gx0 + c;
+                if (gy >= 0 && gy < n && gx >= 0 && gx < n) o = gy * n + gx;
+            }
+            off[k] = i < re ? o : -2;
+        }
+    }
+    __device__ void fetch(const float2* __restrict__ img, float2 (&pre)[kStageMax]) const {
+#pragma unroll
+        for (int k = 0; k < kStageMax; ++k) {
+            float2 v = make_float2(0.f, 0.f);
+            if (off[k] >= 0) v = img[off[k]];
+            pre[k] = v;
+        }
+    }
+    __device__ void store(float2* buf, const float2 (&pre)[kStageMax]) const {
+#pragma unroll
+        for (int k = 0; k < kStageMax; ++k)
+            if (off[k] != -2) buf[threadIdx.x + k * kThreads] = pre[k];
+    }
+};
 
 // ------------------------------------------------------------------ projection
 //
 // P_b[y][x] = sum_s sum_taps w * V_s[y + oy + (0|1)][x + ox + (0|1)]   (Section 4.2)
-// Work item: (group of blade parts of one knot, tile row, tile column). Each bin's
-// plane is staged once into LDS (zero outside the grid) and every part of the group
-// takes its bilinear taps from it; each thread owns a vertical strip of PPT pixels
-// so the row below a pixel's taps is reused as the row above the next pixel's.
+// Work item: (part group, tile row, tile column), tile = 64 columns x kTileRows rows.
+// Part e of the group belongs to wave e % 4, slot e / 4. Each lane owns one column.
 
+template <int GW>
 __global__ __launch_bounds__(kThreads) void k_project(const KArgs a) {
     extern __shared__ float2 sm[];
-    constexpr int TX = kProjTX, TY = kProjTY, PPT = TX * TY / kThreads;
-    const int lx = threadIdx.x % TX, ly0 = (threadIdx.x / TX) * PPT;
-    const int lane = threadIdx.x % 64, wrow = threadIdx.x / 64;
+    constexpr int PPT = kTileRows;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int ti = blockIdx.x; ti < a.ntasks; ti += gridDim.x) {
         const Task tk = a.tasks[ti];
         const SliceDesc& d = LOAD_DESC(a, tk);
@@ -177,74 +226,70 @@ __global__ __launch_bounds__(kThreads) void k_project(const KArgs a) {
         const ProjGroup gr = d.groups[tk.a];
         const int n = d.n, S = d.S;
         const size_t nn = (size_t)n * n;
-        const int y0 = tk.b * TY, x0 = tk.c * TX;
-        const int RH = TY + gr.oy_max - gr.oy_min + 1, RW = TX + gr.ox_max - gr.ox_min + 1;
-        const int gy0 = y0 + gr.oy_min, gx0 = x0 + gr.ox_min;
-        int eb[kGroup], ep[kGroup];
-        bool act[kGroup];
+        const int y0 = tk.b * PPT, x0 = tk.c * kTileW;
+        const int RH = PPT + gr.oy_max - gr.oy_min + 1, RW = kTileW + gr.ox_max - gr.ox_min + 1;
+        const int RE = RH * RW;
+        int eb[GW], ep[GW];
+        bool act[GW];
 #pragma unroll
-        for (int e = 0; e < kGroup; ++e) {
-            act[e] = false;
-            eb[e] = 0;
-            ep[e] = 0;
+        for (int j = 0; j < GW; ++j) {
+            const int e = j * 4 + wave;
+            act[j] = false;
+            eb[j] = 0;
+            ep[j] = 0;
             if (e < gr.ne) {
                 const KnotEntry ke = d.knot_ent[gr.e0 + e];
-                eb[e] = ke.blade;
-                ep[e] = ke.part;
-                act[e] = blade_active(d, st, ke.blade);
+                eb[j] = ke.blade;
+                ep[j] = ke.part;
+                act[j] = blade_active(d, st, ke.blade);
             }
         }
-        float2 acc[kGroup][PPT];
+        float2 acc[GW][PPT];
 #pragma unroll
-        for (int e = 0; e < kGroup; ++e)
+        for (int j = 0; j < GW; ++j)
 #pragma unroll
-            for (int i = 0; i < PPT; ++i) acc[e][i] = make_float2(0.f, 0.f);
+            for (int i = 0; i < PPT; ++i) acc[j][i] = make_float2(0.f, 0.f);
         const float2* V = vol_cur(d, st) + (size_t)gr.knot * S * nn;
+        Stager sg;
+        sg.init(RH, RW, y0 + gr.oy_min, x0 + gr.ox_min, n);
+        float2 pre[kStageMax];
+        sg.fetch(V, pre);
         for (int s = 0; s < S; ++s) {
-            const float2* Vs = V + (size_t)s * nn;
+            float2* buf = sm + (s & 1) * RE;
+            sg.store(buf, pre);
             __syncthreads();
-            for (int rr = wrow; rr < RH; rr += kThreads / 64) {
-                const int gy = gy0 + rr;
-                const bool yin = gy >= 0 && gy < n;
-                for (int cc = lane; cc < RW; cc += 64) {
-                    const int gx = gx0 + cc;
-                    float2 v = make_float2(0.f, 0.f);
-                    if (yin && gx >= 0 && gx < n) v = Vs[(size_t)gy * n + gx];
-                    sm[rr * RW + cc] = v;
-                }
-            }
-            __syncthreads();
+            if (s + 1 < S) sg.fetch(V + (size_t)(s + 1) * nn, pre);
 #pragma unroll
-            for (int e = 0; e < kGroup; ++e) {
-                if (act[e]) {
-                    const ShearEntry sh = d.shear[eb[e] * S + s];
-                    const int row = ly0 + sh.oy - gr.oy_min, col = lx + sh.ox - gr.ox_min;
-                    const float2* L = sm + row * RW + col;
+            for (int j = 0; j < GW; ++j) {
+                if (act[j]) {
+                    const ShearEntry sh = d.shear[eb[j] * S + s];
+                    const float2* L = buf + (sh.oy - gr.oy_min) * RW + lane + sh.ox - gr.ox_min;
                     float2 a0 = L[0], a1 = L[1];
 #pragma unroll
                     for (int i = 0; i < PPT; ++i) {
                         const float2 b0 = L[(i + 1) * RW], b1 = L[(i + 1) * RW + 1];
-                        float2 t = acc[e][i];
+                        float2 t = acc[j][i];
                         t = cfma(sh.w00, a0, t);
                         t = cfma(sh.w01, a1, t);
                         t = cfma(sh.w10, b0, t);
                         t = cfma(sh.w11, b1, t);
-                        acc[e][i] = t;
+                        acc[j][i] = t;
                         a0 = b0;
                         a1 = b1;
                     }
                 }
             }
         }
-        const int x = x0 + lx;
+        __syncthreads();
+        const int x = x0 + lane;
 #pragma unroll
-        for (int e = 0; e < kGroup; ++e) {
-            if (act[e] && x < n) {
-                float2* out = d.work + ((size_t)eb[e] * d.nparts + ep[e]) * nn;
+        for (int j = 0; j < GW; ++j) {
+            if (act[j] && x < n) {
+                float2* out = d.work + ((size_t)eb[j] * d.nparts + ep[j]) * nn;
 #pragma unroll
                 for (int i = 0; i < PPT; ++i) {
-                    const int y = y0 + ly0 + i;
-                    if (y < n) out[(size_t)y * n + x] = acc[e][i];
+                    const int y = y0 + i;
+                    if (y < n) out[(size_t)y * n + x] = acc[j][i];
                 }
             }
         }
@@ -272,9 +317,10 @@ __global__ __launch_bounds__(kThreads) void k_rows(const KArgs a) {
         const int fb = fft_rows_per_item(n);
         const int r0 = tk.b, rows = min(fb, n - r0);
         float2* A = sm;
-        float2* Bf = sm + fb * n;
+        float2* tw = sm + fb * n;
         float2* img = d.work + (size_t)b * d.nparts * nn;
         const size_t base = (size_t)r0 * n;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = d.tw[i];
         if (DIR < 0 && d.nparts == 2) {
             const BladeDev bd = d.blade[b];
             const float2* p1 = img + nn;
@@ -288,8 +334,8 @@ __global__ __launch_bounds__(kThreads) void k_rows(const KArgs a) {
             for (int i = threadIdx.x; i < rows * n; i += blockDim.x) A[i] = img[base + i];
         }
         __syncthreads();
-        const float2* res = lds_fft<DIR, false>(A, Bf, n, rows, n, 1, d);
-        for (int i = threadIdx.x; i < rows * n; i += blockDim.x) img[base + i] = res[i];
+        lds_fft<DIR, false, 8>(A, tw, n, rows, n, 1, d);
+        for (int i = threadIdx.x; i < rows * n; i += blockDim.x) img[base + i] = A[i];
         __syncthreads();
     }
 }
@@ -303,6 +349,7 @@ __global__ __launch_bounds__(kThreads) void k_rows(const KArgs a) {
 
 __global__ __launch_bounds__(kThreads) void k_cols(const KArgs a) {
     extern __shared__ float2 sm[];
+    __shared__ float red[kThreads];
     for (int ti = blockIdx.x; ti < a.ntasks; ti += gridDim.x) {
         const Task tk = a.tasks[ti];
         const SliceDesc& d = LOAD_DESC(a, tk);
@@ -318,17 +365,16 @@ __global__ __launch_bounds__(kThreads) void k_cols(const KArgs a) {
         const int cb = fft_cols_per_item(n);
         const int c0 = tk.b * cb, cols = min(cb, n - c0);
         float2* A = sm;
-        float2* Bf = sm + cb * n;
+        float2* tw = sm + cb * n;
         float2* img = d.work + (size_t)b * d.nparts * nn;
         const float2* src = a.mode == COL_ADJOINT ? a.in0 + (size_t)b * nn : img;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = d.tw[i];
         for (int i = threadIdx.x; i < n * cb; i += blockDim.x) {
             const int y = i / cb, c = i - (i / cb) * cb;
             A[i] = c < cols ? src[(size_t)y * n + c0 + c] : make_float2(0.f, 0.f);
         }
         __syncthreads();
-        float2* cur = A;
-        if (a.mode != COL_ADJOINT) cur = lds_fft<-1, true>(A, Bf, n, cb, 1, cb, d);
-        float2* other = cur == A ? Bf : A;
+        if (a.mode != COL_ADJOINT) lds_fft<-1, true, 16>(A, tw, n, cb, 1, cb, d);
         const float sc = 1.0f / (float)n;
         const uint8_t* mk = d.mask + (size_t)b * nn;
         const float2* yb = d.y ? d.y + (size_t)b * nn : nullptr;
@@ -339,7 +385,7 @@ __global__ __launch_bounds__(kThreads) void k_cols(const KArgs a) {
             if (c < cols) {
                 const size_t gi = (size_t)y * n + c0 + c;
                 const bool on = mk[gi] != 0;
-                const float2 x = cur[i];
+                const float2 x = A[i];
                 if (a.mode == COL_ADJOINT) {
                     if (on) v = cscale(x, sc);
                 } else {
@@ -357,18 +403,17 @@ __global__ __launch_bounds__(kThreads) void k_cols(const KArgs a) {
                     }
                 }
             }
-            cur[i] = v;
+            A[i] = v;
         }
         __syncthreads();
-        if (a.mode == COL_FORWARD) continue;
-        const float2* res = lds_fft<1, true>(cur, other, n, cb, 1, cb, d);
-        for (int i = threadIdx.x; i < n * cb; i += blockDim.x) {
-            const int y = i / cb, c = i - (i / cb) * cb;
-            if (c < cols) img[(size_t)y * n + c0 + c] = res[i];
+        if (a.mode != COL_FORWARD) {
+            lds_fft<1, true, 16>(A, tw, n, cb, 1, cb, d);
+            for (int i = threadIdx.x; i < n * cb; i += blockDim.x) {
+                const int y = i / cb, c = i - (i / cb) * cb;
+                if (c < cols) img[(size_t)y * n + c0 + c] = A[i];
+            }
         }
         if (a.mode == COL_STEP) {
-            __syncthreads();
-            float* red = reinterpret_cast<float*>(sm);
             red[threadIdx.x] = lsum;
             __syncthreads();
             for (int w = kThreads / 2; w > 0; w >>= 1) {
@@ -411,20 +456,19 @@ __device__ __forceinline__ float2 reg_grad(const float2* __restrict__ V, size_t 
 
 // ------------------------------------------------------------------ adjoint gather + update
 //
-// G[k][s][y][x] = sum over the knot's blade parts e (blades ascending) of
+// G[k][s][y][x] = sum over the knot's blade parts e (plan order, blades ascending) of
 //   w_e * (w00 g[y-oy][x-ox] + w01 g[y-oy][x-ox-1] + w10 g[y-oy-1][x-ox] + w11 g[y-oy-1][x-ox-1]),
 // the exact transpose of k_project's taps (zero outside the grid). Work item: (knot,
-// spatial tile, chunk of kChunk bins); each blade's image region is staged in LDS once
-// per item. MODE = GATHER_STORE writes (or adds to) the gradient; GATHER_STEP adds the
-// TV/L1 gradient and applies the optimiser, reading volume[step & 1] and writing the
-// other copy.
+// tile, chunk of 4 * sc bins); wave w owns bins s0 + w * sc ... s0 + w * sc + sc - 1.
+// MODE = GATHER_STORE writes (or adds to) the gradient; GATHER_STEP adds the TV/L1
+// gradient and applies the optimiser, reading volume[step & 1] and writing the other
+// copy; the last finished work item of the step advances the slice's step counter.
 
 template <int MODE>
 __global__ __launch_bounds__(kThreads) void k_gather(const KArgs a) {
     extern __shared__ float2 sm[];
-    constexpr int TX = kGathTX, TY = kGathTY, PPT = TX * TY / kThreads;
-    const int lx = threadIdx.x % TX, ly0 = (threadIdx.x / TX) * PPT;
-    const int lane = threadIdx.x % 64, wrow = threadIdx.x / 64;
+    constexpr int PPT = kTileRows, SCM = kChunkMax;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int ti = blockIdx.x; ti < a.ntasks; ti += gridDim.x) {
         const Task tk = a.tasks[ti];
         const SliceDesc& d = LOAD_DESC(a, tk);
@@ -432,43 +476,43 @@ __global__ __launch_bounds__(kThreads) void k_gather(const KArgs a) {
         if (slice_done(d, st)) continue;
         const int n = d.n, S = d.S, kt = tk.a;
         const size_t nn = (size_t)n * n;
-        const int gtx = (n + TX - 1) / TX;
-        const int y0 = (tk.b / gtx) * TY, x0 = (tk.b % gtx) * TX;
-        const int s0 = tk.c * kChunk, ns = min(kChunk, S - s0);
-        float2 acc[kChunk][PPT];
+        const int txn = (n + kTileW - 1) / kTileW;
+        const int y0 = (tk.b / txn) * PPT, x0 = (tk.b % txn) * kTileW;
+        const int sc = d.gath_sc;
+        const int sw = tk.c * 4 * sc + wave * sc;
+        const int ns = max(0, min(sc, S - sw));
+        const KnotInfo ki = d.knots[kt];
+        const int RH = PPT + ki.oy_max - ki.oy_min + 1, RW = kTileW + ki.ox_max - ki.ox_min + 1;
+        const int RE = RH * RW;
+        float2 acc[SCM][PPT];
 #pragma unroll
-        for (int q = 0; q < kChunk; ++q)
+        for (int q = 0; q < SCM; ++q)
 #pragma unroll
             for (int i = 0; i < PPT; ++i) acc[q][i] = make_float2(0.f, 0.f);
-        const int e1 = d.knot_ptr[kt + 1];
-        for (int e = d.knot_ptr[kt]; e < e1; ++e) {
+        const int e0 = d.knot_ptr[kt], e1 = d.knot_ptr[kt + 1];
+        Stager sg;
+        sg.init(RH, RW, y0 - ki.oy_max - 1, x0 - ki.ox_max - 1, n);
+        float2 pre[kStageMax];
+        int e = e0;
+        while (e < e1 && !blade_active(d, st, d.knot_ent[e].blade)) ++e;
+        if (e < e1) sg.fetch(d.work + (size_t)d.knot_ent[e].blade * d.nparts * nn, pre);
+        for (int it = 0; e < e1; ++it) {
             const KnotEntry ke = d.knot_ent[e];
             const int b = ke.blade;
-            if (!blade_active(d, st, b)) continue;
-            const BladeDev bd = d.blade[b];
-            const int RH = TY + bd.oy_max - bd.oy_min + 1, RW = TX + bd.ox_max - bd.ox_min + 1;
-            const int gy0 = y0 - bd.oy_max - 1, gx0 = x0 - bd.ox_max - 1;
-            const float2* g = d.work + (size_t)b * d.nparts * nn;
+            float2* buf = sm + (it & 1) * RE;
+            sg.store(buf, pre);
             __syncthreads();
-            for (int rr = wrow; rr < RH; rr += kThreads / 64) {
-                const int gy = gy0 + rr;
-                const bool yin = gy >= 0 && gy < n;
-                for (int cc = lane; cc < RW; cc += 64) {
-                    const int gx = gx0 + cc;
-                    float2 v = make_float2(0.f, 0.f);
-                    if (yin && gx >= 0 && gx < n) v = g[(size_t)gy * n + gx];
-                    sm[rr * RW + cc] = v;
-                }
-            }
-            __syncthreads();
+            int en = e + 1;
+            while (en < e1 && !blade_active(d, st, d.knot_ent[en].blade)) ++en;
+            if (en < e1) sg.fetch(d.work + (size_t)d.knot_ent[en].blade * d.nparts * nn, pre);
             const float wb = ke.weight;
-            const ShearEntry* shb = d.shear + (size_t)b * S + s0;
+            const ShearEntry* shb = d.shear + (size_t)b * S + sw;
 #pragma unroll
-            for (int q = 0; q < kChunk; ++q) {
+            for (int q = 0; q < SCM; ++q) {
                 if (q < ns) {
                     const ShearEntry sh = shb[q];
-                    const int row = ly0 - sh.oy + bd.oy_max + 1, col = lx - sh.ox + bd.ox_max + 1;
-                    const float2* L = sm + row * RW + col;
+                    // row of g[y - oy][.] for pixel row 0, column of g[.][x - ox]
+                    const float2* L = buf + (ki.oy_max - sh.oy + 1) * RW + lane + ki.ox_max - sh.ox + 1;
                     float2 u0 = L[-RW], u1 = L[-RW - 1];
 #pragma unroll
                     for (int i = 0; i < PPT; ++i) {
@@ -484,21 +528,24 @@ __global__ __launch_bounds__(kThreads) void k_gather(const KArgs a) {
                     }
                 }
             }
+            e = en;
         }
-        const int x = x0 + lx;
-        if (x >= n) continue;
+        __syncthreads();
+        const int x = x0 + lane;
         if (MODE == GATHER_STORE) {
+            if (x < n) {
 #pragma unroll
-            for (int q = 0; q < kChunk; ++q) {
-                if (q < ns) {
+                for (int q = 0; q < SCM; ++q) {
+                    if (q < ns) {
 #pragma unroll
-                    for (int i = 0; i < PPT; ++i) {
-                        const int y = y0 + ly0 + i;
-                        if (y < n) {
-                            const size_t idx = (((size_t)kt * S + s0 + q) * n + y) * n + x;
-                            float2 g = acc[q][i];
-                            if (a.accumulate) g = cadd(d.grad[idx], g);
-                            d.grad[idx] = g;
+                        for (int i = 0; i < PPT; ++i) {
+                            const int y = y0 + i;
+                            if (y < n) {
+                                const size_t idx = (((size_t)kt * S + sw + q) * n + y) * n + x;
+                                float2 g = acc[q][i];
+                                if (a.accumulate) g = cadd(d.grad[idx], g);
+                                d.grad[idx] = g;
+                            }
                         }
                     }
                 }
@@ -511,35 +558,51 @@ __global__ __launch_bounds__(kThreads) void k_gather(const KArgs a) {
             const float bc1 = (float)(1.0 - pow((double)d.beta1, (double)t));
             const float bc2s = (float)sqrt(1.0 - pow((double)d.beta2, (double)t));
             const float step_size = d.lr / bc1;
+            if (x < n) {
 #pragma unroll
-            for (int q = 0; q < kChunk; ++q) {
-                if (q < ns) {
+                for (int q = 0; q < SCM; ++q) {
+                    if (q < ns) {
 #pragma unroll
-                    for (int i = 0; i < PPT; ++i) {
-                        const int y = y0 + ly0 + i;
-                        if (y < n) {
-                            const int s = s0 + q;
-                            const size_t idx = (((size_t)kt * S + s) * n + y) * n + x;
-                            const float2 reg = reg_grad(Vin, idx, kt, s, y, x, n, S, d.T, d.tv_w, d.l1_w, d.tv_eps);
-                            const float2 gr = cadd(acc[q][i], reg);
-                            const float2 v0 = Vin[idx];
-                            float2 nv;
-                            if (d.optimizer == VP_OPT_ADAM) {
-                                float2 m = d.m[idx], v = d.v[idx];
-                                m.x = d.beta1 * m.x + (1.0f - d.beta1) * gr.x;
-                                m.y = d.beta1 * m.y + (1.0f - d.beta1) * gr.y;
-                                v.x = d.beta2 * v.x + (1.0f - d.beta2) * gr.x * gr.x;
-                                v.y = d.beta2 * v.y + (1.0f - d.beta2) * gr.y * gr.y;
-                                d.m[idx] = m;
-                                d.v[idx] = v;
-                                const float dx = sqrtf(v.x) / bc2s + d.adam_eps;
-                                const float dy = sqrtf(v.y) / bc2s + d.adam_eps;
-                                nv = make_float2(v0.x - step_size * (m.x / dx), v0.y - step_size * (m.y / dy));
-                            } else {
-                                nv = make_float2(v0.x - d.lr * gr.x, v0.y - d.lr * gr.y);
+                        for (int i = 0; i < PPT; ++i) {
+                            const int y = y0 + i;
+                            if (y < n) {
+                                const int s = sw + q;
+                                const size_t idx = (((size_t)kt * S + s) * n + y) * n + x;
+                                const float2 reg =
+                                    reg_grad(Vin, idx, kt, s, y, x, n, S, d.T, d.tv_w, d.l1_w, d.tv_eps);
+                                const float2 gr = cadd(acc[q][i], reg);
+                                const float2 v0 = Vin[idx];
+                                float2 nv;
+                                if (d.optimizer == VP_OPT_ADAM) {
+                                    float2 m = d.m[idx], v = d.v[idx];
+                                    m.x = d.beta1 * m.x + (1.0f - d.beta1) * gr.x;
+                                    m.y = d.beta1 * m.y + (1.0f - d.beta1) * gr.y;
+                                    v.x = d.beta2 * v.x + (1.0f - d.beta2) * gr.x * gr.x;
+                                    v.y = d.beta2 * v.y + (1.0f - d.beta2) * gr.y * gr.y;
+                                    d.m[idx] = m;
+                                    d.v[idx] = v;
+                                    const float dx = sqrtf(v.x) / bc2s + d.adam_eps;
+                                    const float dy = sqrtf(v.y) / bc2s + d.adam_eps;
+                                    nv = make_float2(v0.x - step_size * (m.x / dx), v0.y - step_size * (m.y / dy));
+                                } else {
+                                    nv = make_float2(v0.x - d.lr * gr.x, v0.y - d.lr * gr.y);
+                                }
+                                Vout[idx] = nv;
                             }
-                            Vout[idx] = nv;
                         }
+                    }
+                }
+            }
+            if (d.sync) {
+                // every work item of the slice read *step before finishing; the last one
+                // to finish advances it for the next step
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    __threadfence();
+                    const unsigned prev = atomicAdd(d.sync, 1u);
+                    if (prev + 1 == (unsigned)d.n_gath_tasks) {
+                        atomicExch(d.sync, 0u);
+                        atomicExch(d.step, st + 1);
                     }
                 }
             }
@@ -641,23 +704,19 @@ __global__ __launch_bounds__(kThreads) void k_render(const KArgs a) {
     }
 }
 
-// Advance the step counter of every unfinished slice (one work item per slice).
-__global__ void k_bump(const KArgs a) {
-    for (int ti = blockIdx.x; ti < a.ntasks; ti += gridDim.x) {
-        if (threadIdx.x != 0) continue;
-        const Task tk = a.tasks[ti];
-        const SliceDesc& d = LOAD_DESC(a, tk);
-        if (d.step && *d.step < d.step_limit) *d.step = *d.step + 1;
-    }
-}
-
 // ------------------------------------------------------------------ launchers
 
 static inline int grid_for(int ntasks) { return ntasks < 1 ? 1 : (ntasks > (1 << 20) ? (1 << 20) : ntasks); }
 
-hipError_t launch_project(const KArgs& a, size_t lds, hipStream_t s) {
+hipError_t launch_project(const KArgs& a, int gw, size_t lds, hipStream_t s) {
     if (a.ntasks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_project, dim3(grid_for(a.ntasks)), dim3(kThreads), lds, s, a);
+    const dim3 g(grid_for(a.ntasks)), b(kThreads);
+    switch (gw) {
+        case 1: hipLaunchKernelGGL(k_project<1>, g, b, lds, s, a); break;
+        case 2: hipLaunchKernelGGL(k_project<2>, g, b, lds, s, a); break;
+        case 4: hipLaunchKernelGGL(k_project<4>, g, b, lds, s, a); break;
+        default: hipLaunchKernelGGL(k_project<8>, g, b, lds, s, a); break;
+    }
     return hipGetLastError();
 }
 hipError_t launch_rows(const KArgs& a, int dir, size_t lds, hipStream_t s) {
@@ -694,11 +753,6 @@ hipError_t launch_reg_value(const KArgs& a, hipStream_t s) {
 hipError_t launch_render(const KArgs& a, hipStream_t s) {
     if (a.ntasks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_render, dim3(grid_for(a.ntasks)), dim3(kThreads), 0, s, a);
-    return hipGetLastError();
-}
-hipError_t launch_bump(const KArgs& a, hipStream_t s) {
-    if (a.ntasks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bump, dim3(grid_for(a.ntasks)), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 

@@ -216,23 +216,37 @@ extern "C" vp_status vp_plan_create(const vp_geometry* g, vp_plan** out) {
         }
         p->knot_ptr[T] = (int)p->knot_ent.size();
 
-        // projection groups
+        // projection groups: a knot's parts in chunks of 4 * GW (GW parts per wave)
+        int max_parts = 0;
+        for (int kt = 0; kt < T; ++kt) max_parts = std::max(max_parts, p->knot_ptr[kt + 1] - p->knot_ptr[kt]);
+        p->proj_gw = max_parts <= 4 ? 1 : max_parts <= 8 ? 2 : max_parts <= 16 ? 4 : 8;
+        const int group_parts = 4 * p->proj_gw;
+        auto extents = [&](int e0, int e1, int* ext) {
+            ext[0] = ext[2] = std::numeric_limits<int>::max();
+            ext[1] = ext[3] = std::numeric_limits<int>::min();
+            for (int e = e0; e < e1; ++e) {
+                const BladeDev& bd = p->blade[p->knot_ent[e].blade];
+                ext[0] = std::min(ext[0], bd.ox_min); ext[1] = std::max(ext[1], bd.ox_max);
+                ext[2] = std::min(ext[2], bd.oy_min); ext[3] = std::max(ext[3], bd.oy_max);
+            }
+            if (e1 <= e0) ext[0] = ext[1] = ext[2] = ext[3] = 0;
+        };
         for (int kt = 0; kt < T; ++kt) {
-            for (int e0 = p->knot_ptr[kt]; e0 < p->knot_ptr[kt + 1]; e0 += kGroup) {
+            for (int e0 = p->knot_ptr[kt]; e0 < p->knot_ptr[kt + 1]; e0 += group_parts) {
                 ProjGroup gr{};
                 gr.knot = kt;
                 gr.e0 = e0;
-                gr.ne = std::min(kGroup, p->knot_ptr[kt + 1] - e0);
-                gr.ox_min = gr.oy_min = std::numeric_limits<int>::max();
-                gr.ox_max = gr.oy_max = std::numeric_limits<int>::min();
-                for (int e = e0; e < e0 + gr.ne; ++e) {
-                    const BladeDev& bd = p->blade[p->knot_ent[e].blade];
-                    gr.ox_min = std::min(gr.ox_min, bd.ox_min); gr.ox_max = std::max(gr.ox_max, bd.ox_max);
-                    gr.oy_min = std::min(gr.oy_min, bd.oy_min); gr.oy_max = std::max(gr.oy_max, bd.oy_max);
-                }
+                gr.ne = std::min(group_parts, p->knot_ptr[kt + 1] - e0);
+                int ext[4];
+                extents(e0, e0 + gr.ne, ext);
+                gr.ox_min = ext[0]; gr.ox_max = ext[1]; gr.oy_min = ext[2]; gr.oy_max = ext[3];
                 p->groups.push_back(gr);
             }
+            int ext[4];
+            extents(p->knot_ptr[kt], p->knot_ptr[kt + 1], ext);
+            p->knots.push_back(KnotInfo{ext[0], ext[1], ext[2], ext[3]});
         }
+        p->gath_sc = std::min(kChunkMax, ceil_div(S, 4));
 
         // twiddles exp(-2 pi i j / n), FP64 then rounded
         p->tw.resize(n);
@@ -241,41 +255,42 @@ extern "C" vp_status vp_plan_create(const vp_geometry* g, vp_plan** out) {
             p->tw[j] = make_float2((float)std::cos(ang), (float)std::sin(ang));
         }
 
-        // LDS sizes
+        // LDS sizes: double-buffered staging regions; FFT data plus the twiddle table
         for (const ProjGroup& gr : p->groups) {
-            const size_t rh = kProjTY + gr.oy_max - gr.oy_min + 1, rw = kProjTX + gr.ox_max - gr.ox_min + 1;
-            p->lds_proj = std::max(p->lds_proj, rh * rw * sizeof(float2));
+            const size_t rh = kTileRows + gr.oy_max - gr.oy_min + 1, rw = kTileW + gr.ox_max - gr.ox_min + 1;
+            p->lds_proj = std::max(p->lds_proj, 2 * rh * rw * sizeof(float2));
         }
-        for (const BladeDev& bd : p->blade) {
-            const size_t rh = kGathTY + bd.oy_max - bd.oy_min + 1, rw = kGathTX + bd.ox_max - bd.ox_min + 1;
-            p->lds_gath = std::max(p->lds_gath, rh * rw * sizeof(float2));
+        for (const KnotInfo& ki : p->knots) {
+            const size_t rh = kTileRows + ki.oy_max - ki.oy_min + 1, rw = kTileW + ki.ox_max - ki.ox_min + 1;
+            p->lds_gath = std::max(p->lds_gath, 2 * rh * rw * sizeof(float2));
         }
+        const size_t stage_cap = 2 * (size_t)kStageMax * kThreads * sizeof(float2);
+        if (p->lds_proj > stage_cap || p->lds_gath > stage_cap)
+            return fail(VP_ERR_UNSUPPORTED, "vp_plan_create: shear extents exceed the staging capacity");
         const int fb = fft_rows_per_item(n), cb = fft_cols_per_item(n);
-        p->lds_rows = 2 * (size_t)fb * n * sizeof(float2);
-        // the loss reduction reuses the column buffers (256 floats)
-        p->lds_cols = std::max(2 * (size_t)cb * n * sizeof(float2), kThreads * sizeof(float));
+        p->lds_rows = ((size_t)fb * n + n) * sizeof(float2);
+        p->lds_cols = ((size_t)cb * n + n) * sizeof(float2);
         p->n_col_items = ceil_div(n, cb);
 
         // work lists
-        const int pty = ceil_div(n, kProjTY), ptx = ceil_div(n, kProjTX);
+        const int tyn = ceil_div(n, kTileRows), txn = ceil_div(n, kTileW);
         for (int gi = 0; gi < (int)p->groups.size(); ++gi)
-            for (int ty = 0; ty < pty; ++ty)
-                for (int tx = 0; tx < ptx; ++tx) p->t_proj.push_back(Task{0, gi, ty, tx});
+            for (int ty = 0; ty < tyn; ++ty)
+                for (int tx = 0; tx < txn; ++tx) p->t_proj.push_back(Task{0, gi, ty, tx});
         for (int b = 0; b < B; ++b)
             for (int r0 = 0; r0 < n; r0 += fb) p->t_rows.push_back(Task{0, b, r0, 0});
         for (int b = 0; b < B; ++b)
             for (int c = 0; c < p->n_col_items; ++c) p->t_cols.push_back(Task{0, b, c, 0});
-        const int gty = ceil_div(n, kGathTY), gtx = ceil_div(n, kGathTX), nch = ceil_div(S, kChunk);
+        const int nch = ceil_div(S, 4 * p->gath_sc);
         for (int kt = 0; kt < T; ++kt)
-            for (int ty = 0; ty < gty; ++ty)
-                for (int tx = 0; tx < gtx; ++tx)
-                    for (int ch = 0; ch < nch; ++ch) p->t_gath.push_back(Task{0, kt, ty * gtx + tx, ch});
+            for (int ty = 0; ty < tyn; ++ty)
+                for (int tx = 0; tx < txn; ++tx)
+                    for (int ch = 0; ch < nch; ++ch) p->t_gath.push_back(Task{0, kt, ty * txn + tx, ch});
         const uint64_t nvox = p->voxels();
         for (uint64_t i = 0; i * kVoxItem < nvox; ++i) p->t_vox.push_back(Task{0, (int)i, 0, 0});
         const int npb = ceil_div(n * n, kVoxItem);
         for (int kt = 0; kt < T; ++kt)
             for (int pb = 0; pb < npb; ++pb) p->t_render.push_back(Task{0, kt, pb, 0});
-        p->t_one.push_back(Task{0, 0, 0, 0});
     } catch (const std::bad_alloc&) {
         return fail(VP_ERR_NOMEM, "vp_plan_create: out of host memory");
     }
@@ -323,9 +338,10 @@ namespace vp {
 uint64_t table_bytes(const vp_plan* p) {
     return p->mask.size() + p->shear.size() * sizeof(ShearEntry) + p->blade.size() * sizeof(BladeDev) +
            p->knot_ptr.size() * sizeof(int) + p->knot_ent.size() * sizeof(KnotEntry) +
-           p->groups.size() * sizeof(ProjGroup) + p->tw.size() * sizeof(float2) +
+           p->groups.size() * sizeof(ProjGroup) + p->knots.size() * sizeof(KnotInfo) +
+           p->tw.size() * sizeof(float2) +
            (p->t_proj.size() + p->t_rows.size() + p->t_cols.size() + p->t_gath.size() + p->t_vox.size() +
-            p->t_render.size() + p->t_one.size()) *
+            p->t_render.size()) *
                sizeof(Task);
 }
 
@@ -335,7 +351,7 @@ uint64_t state_bytes(const vp_plan* p, const vp_options* o) {
     if (!o || o->optimizer == VP_OPT_ADAM) b += 2 * vox;          // Adam moments
     b += (uint64_t)p->nparts * p->blade_px() * sizeof(float2);   // blade work images
     b += p->blade_px() * sizeof(float2);                          // measurements
-    b += loss_slots(p) * sizeof(float) + 256;                     // loss partials, step counter
+    b += loss_slots(p) * sizeof(float) + 256;                     // loss partials, step/sync counters
     b += 2 * p->t_vox.size() * sizeof(double);                    // objective partials
     b += 3 * (uint64_t)p->T * p->n * p->n * sizeof(float2);       // renders
     return b;

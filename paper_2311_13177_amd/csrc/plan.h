@@ -25,6 +25,7 @@ struct DeviceTables {
     int* knot_ptr = nullptr;
     KnotEntry* knot_ent = nullptr;
     ProjGroup* groups = nullptr;
+    KnotInfo* knots = nullptr;
     float2* tw = nullptr;
     Task* t_proj = nullptr;
     Task* t_rows = nullptr;
@@ -32,7 +33,6 @@ struct DeviceTables {
     Task* t_gath = nullptr;
     Task* t_vox = nullptr;
     Task* t_render = nullptr;
-    Task* t_one = nullptr;
     ~DeviceTables();
 };
 
@@ -50,13 +50,16 @@ struct vp_plan {
     std::vector<int> knot_ptr;           // [T+1]
     std::vector<vp::KnotEntry> knot_ent;
     std::vector<vp::ProjGroup> groups;
+    std::vector<vp::KnotInfo> knots;    // [T]
+    int proj_gw = 1;                     // blade parts per wave in a projection item
+    int gath_sc = 1;                     // bins per wave in a gather item
     std::vector<float2> tw;              // [n]
     int nstage = 0;
     int radix[vp::kMaxStages] = {0};
     int nparts = 1;
     int n_col_items = 0;
     // Work lists (slice index 0; batches rebase it).
-    std::vector<vp::Task> t_proj, t_rows, t_cols, t_gath, t_vox, t_render, t_one;
+    std::vector<vp::Task> t_proj, t_rows, t_cols, t_gath, t_vox, t_render;
     // Dynamic LDS bytes per kernel.
     size_t lds_proj = 0, lds_gath = 0, lds_rows = 0, lds_cols = 0;
 

@@ -8,14 +8,13 @@
 namespace vp {
 
 // Kernel launchers (kernels.hip).
-hipError_t launch_project(const KArgs& a, size_t lds, hipStream_t s);
+hipError_t launch_project(const KArgs& a, int gw, size_t lds, hipStream_t s);
 hipError_t launch_rows(const KArgs& a, int dir, size_t lds, hipStream_t s);
 hipError_t launch_cols(const KArgs& a, size_t lds, hipStream_t s);
 hipError_t launch_gather(const KArgs& a, int mode, size_t lds, hipStream_t s);
 hipError_t launch_tv_grad(const KArgs& a, hipStream_t s);
 hipError_t launch_reg_value(const KArgs& a, hipStream_t s);
 hipError_t launch_render(const KArgs& a, hipStream_t s);
-hipError_t launch_bump(const KArgs& a, hipStream_t s);
 
 // Device work lists of one optimiser step and the dynamic LDS of each stage.
 struct StageLists {
@@ -25,17 +24,22 @@ struct StageLists {
     const Task* gath = nullptr;
     const Task* vox = nullptr;
     const Task* render = nullptr;
-    const Task* one = nullptr;
-    int n_proj = 0, n_rows = 0, n_cols = 0, n_gath = 0, n_vox = 0, n_render = 0, n_one = 0;
+    int n_proj = 0, n_rows = 0, n_cols = 0, n_gath = 0, n_vox = 0, n_render = 0;
+    int proj_gw = 1;
     size_t lds_proj = 0, lds_rows = 0, lds_cols = 0, lds_gath = 0;
 };
 
 StageLists plan_lists(const vp_plan* p, const DeviceTables* t);
 // Enqueues one optimiser step (project, row DFT, column pass, inverse row DFT,
-// gather + update, step counter) for the descriptors `base` refers to.
-// With `ev` (7 events) an event is recorded before each stage and after the last.
+// gather + update + step counter) for the descriptors `base` refers to.
+// With `ev` (kStages + 1 events) an event is recorded before each stage and after the last.
 void launch_step(const KArgs& base, const StageLists& L, hipStream_t s, hipError_t* err, hipEvent_t* ev = nullptr);
-constexpr int kStages = 6;
+constexpr int kStages = 5;
+// Per-slice device counter block: the step counter (int at offset 0) and the count of
+// finished gather work items of the running step (unsigned at kSyncOffset words).
+constexpr size_t kCounterBytes = 256;
+constexpr size_t kSyncOffset = 16;
+static_assert((kSyncOffset + 1) * sizeof(unsigned) <= kCounterBytes, "counter block too small");
 
 vp_status hip_status(hipError_t e, const char* what);
 vp_status check_options(const vp_plan* p, const vp_options* o);

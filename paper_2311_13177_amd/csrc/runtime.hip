@@ -21,8 +21,8 @@ DeviceTables::~DeviceTables() {
     int prev = -1;
     if (hipGetDevice(&prev) != hipSuccess) prev = -1;
     if (device >= 0) (void)hipSetDevice(device);
-    void* ptrs[] = {mask, shear, blade, knot_ptr, knot_ent, groups, tw, t_proj, t_rows, t_cols, t_gath, t_vox, t_render,
-                    t_one};
+    void* ptrs[] = {mask, shear, blade, knot_ptr, knot_ent, groups, knots, tw, t_proj, t_rows, t_cols, t_gath, t_vox,
+                    t_render};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (prev >= 0) (void)hipSetDevice(prev);
@@ -68,6 +68,7 @@ vp_status plan_tables(const vp_plan* p, DeviceTables** out) {
     UP(knot_ptr, p->knot_ptr);
     UP(knot_ent, p->knot_ent);
     UP(groups, p->groups);
+    UP(knots, p->knots);
     UP(tw, p->tw);
     UP(t_proj, p->t_proj);
     UP(t_rows, p->t_rows);
@@ -75,7 +76,6 @@ vp_status plan_tables(const vp_plan* p, DeviceTables** out) {
     UP(t_gath, p->t_gath);
     UP(t_vox, p->t_vox);
     UP(t_render, p->t_render);
-    UP(t_one, p->t_one);
 #undef UP
     *out = t.get();
     p->dev.emplace(dev, std::move(t));
@@ -99,6 +99,9 @@ void fill_desc(const vp_plan* p, const DeviceTables* t, SliceDesc* d) {
     d->knot_ptr = t->knot_ptr;
     d->knot_ent = t->knot_ent;
     d->groups = t->groups;
+    d->knots = t->knots;
+    d->n_gath_tasks = (int)p->t_gath.size();
+    d->gath_sc = p->gath_sc;
     d->step_limit = 0x7fffffff;
     d->schedule = VP_SCHED_ALL_BLADES;
     d->optimizer = VP_OPT_ADAM;
@@ -144,7 +147,7 @@ void launch_step(const KArgs& base, const StageLists& L, hipStream_t s, hipError
     } while (0)
     MARK(0);
     a.tasks = L.proj; a.ntasks = L.n_proj;
-    if ((e = launch_project(a, L.lds_proj, s)) != hipSuccess) { *err = e; return; }
+    if ((e = launch_project(a, L.proj_gw, L.lds_proj, s)) != hipSuccess) { *err = e; return; }
     MARK(1);
     a.tasks = L.rows; a.ntasks = L.n_rows;
     if ((e = launch_rows(a, -1, L.lds_rows, s)) != hipSuccess) { *err = e; return; }
@@ -158,9 +161,6 @@ void launch_step(const KArgs& base, const StageLists& L, hipStream_t s, hipError
     a.tasks = L.gath; a.ntasks = L.n_gath;
     if ((e = launch_gather(a, GATHER_STEP, L.lds_gath, s)) != hipSuccess) { *err = e; return; }
     MARK(5);
-    a.tasks = L.one; a.ntasks = L.n_one;
-    if ((e = launch_bump(a, s)) != hipSuccess) { *err = e; return; }
-    MARK(6);
 #undef MARK
     *err = hipSuccess;
 }
@@ -173,7 +173,7 @@ StageLists plan_lists(const vp_plan* p, const DeviceTables* t) {
     L.gath = t->t_gath; L.n_gath = (int)p->t_gath.size();
     L.vox = t->t_vox; L.n_vox = (int)p->t_vox.size();
     L.render = t->t_render; L.n_render = (int)p->t_render.size();
-    L.one = t->t_one; L.n_one = 1;
+    L.proj_gw = p->proj_gw;
     L.lds_proj = p->lds_proj; L.lds_rows = p->lds_rows; L.lds_cols = p->lds_cols; L.lds_gath = p->lds_gath;
     return L;
 }
@@ -231,7 +231,7 @@ extern "C" vp_status vp_forward(const vp_plan* p, const vp_c64* d_vol, const vp_
     const StageLists L = plan_lists(p, sc.t);
     hipError_t e;
     a.tasks = L.proj; a.ntasks = L.n_proj;
-    if ((e = launch_project(a, L.lds_proj, sc.s)) != hipSuccess) return hip_status(e, "vp_forward project");
+    if ((e = launch_project(a, L.proj_gw, L.lds_proj, sc.s)) != hipSuccess) return hip_status(e, "vp_forward project");
     a.tasks = L.rows; a.ntasks = L.n_rows;
     if ((e = launch_rows(a, -1, L.lds_rows, sc.s)) != hipSuccess) return hip_status(e, "vp_forward rows");
     a.tasks = L.cols; a.ntasks = L.n_cols; a.mode = COL_FORWARD; a.out0 = (float2*)d_out;
@@ -366,7 +366,7 @@ vp_status session_alloc(const vp_plan* p, const vp_options* o, const vp_c64* ksp
     ALLOC(s->work, (size_t)p->nparts * bb);
     ALLOC(s->y, bb);
     ALLOC(s->loss_part, loss_slots(p) * sizeof(float));
-    ALLOC(s->step_dev, 64);
+    ALLOC(s->step_dev, kCounterBytes);
     ALLOC(s->dpart, 2 * p->t_vox.size() * sizeof(double));
     ALLOC(s->render, 3 * (size_t)p->T * p->n * p->n * sizeof(float2));
 #undef ALLOC
@@ -375,7 +375,7 @@ vp_status session_alloc(const vp_plan* p, const vp_options* o, const vp_c64* ksp
     if (e == hipSuccess && s->m) e = hipMemsetAsync(s->m, 0, vb, s->stream);
     if (e == hipSuccess && s->v) e = hipMemsetAsync(s->v, 0, vb, s->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(s->y, kspace, bb, hipMemcpyHostToDevice, s->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(s->step_dev, 0, 64, s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s->step_dev, 0, kCounterBytes, s->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s->loss_part, 0, loss_slots(p) * sizeof(float), s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return hip_status(e, "session upload");
@@ -389,6 +389,7 @@ vp_status session_alloc(const vp_plan* p, const vp_options* o, const vp_c64* ksp
     s->desc.y = s->y;
     s->desc.loss_part = s->loss_part;
     s->desc.step = s->step_dev;
+    s->desc.sync = reinterpret_cast<unsigned*>(s->step_dev) + kSyncOffset;
     s->lists = plan_lists(p, s->tabs);
     *out = s.release();
     return VP_OK;
@@ -435,7 +436,7 @@ vp_status session_objective(vp_session* s, double* objective, double* data_term)
     a.one.step_limit = 0x7fffffff;
     const StageLists& L = s->lists;
     a.tasks = L.proj; a.ntasks = L.n_proj;
-    if ((e = launch_project(a, L.lds_proj, s->stream)) != hipSuccess) return hip_status(e, "objective");
+    if ((e = launch_project(a, L.proj_gw, L.lds_proj, s->stream)) != hipSuccess) return hip_status(e, "objective");
     a.tasks = L.rows; a.ntasks = L.n_rows;
     if ((e = launch_rows(a, -1, L.lds_rows, s->stream)) != hipSuccess) return hip_status(e, "objective");
     a.tasks = L.cols; a.ntasks = L.n_cols; a.mode = COL_STEP;

@@ -23,15 +23,15 @@ constexpr int kMaxStages = 12;
 constexpr double kMaxShift = 16.0;
 constexpr int kThreads = 256;
 
-// Projection tiles: TX x TY output pixels per work item, up to kGroup blade parts
-// accumulated together (one pass over the knot's spectral planes).
-constexpr int kProjTX = 64;
-constexpr int kProjTY = 16;
-constexpr int kGroup = 8;
-// Adjoint gather tiles: TX x TY voxels, spectral bins in chunks of kChunk.
-constexpr int kGathTX = 32;
-constexpr int kGathTY = 16;
-constexpr int kChunk = 16;
+// Projection and gather tiles: 64 columns (one per lane of a wave) by kTileRows rows.
+// A projection work item covers one tile for a group of up to 4 * GW blade parts of one
+// knot (parts dealt round-robin to the block's four waves); a gather work item covers
+// one tile for 4 * sc spectral bins (sc consecutive bins per wave, sc <= kChunkMax).
+constexpr int kTileW = 64;
+constexpr int kTileRows = 2;
+constexpr int kChunkMax = 8;
+// Staged region elements per thread (register prefetch depth of the LDS staging).
+constexpr int kStageMax = 16;
 // Voxel-wise kernels (TV, render, objective): elements per work item.
 constexpr int kVoxItem = 4096;
 
@@ -60,10 +60,14 @@ struct KnotEntry {       // a blade part that reads (projection) / feeds (adjoin
     int pad;
 };
 
-struct ProjGroup {       // up to kGroup parts of one knot projected together
+struct ProjGroup {       // up to 4 * GW parts of one knot projected together
     int knot, e0, ne;
     int ox_min, ox_max, oy_min, oy_max;
     int pad;
+};
+
+struct KnotInfo {        // union of the shear extents of the parts feeding a knot
+    int ox_min, ox_max, oy_min, oy_max;
 };
 
 struct Task {            // one work item; field meaning depends on the kernel
@@ -83,6 +87,7 @@ struct SliceDesc {
     const int* knot_ptr;         // [T+1] CSR offsets into knot_ent
     const KnotEntry* knot_ent;
     const ProjGroup* groups;
+    const KnotInfo* knots;       // [T]
     const float2* y;             // measured k-space or nullptr
     float2* vol[2];              // current volume = vol[step & 1]
     float2* m;
@@ -91,6 +96,9 @@ struct SliceDesc {
     float2* grad;                // gradient output of the operator path
     float* loss_part;            // [B][n_col_items]
     int* step;                   // device step counter; nullptr for operator calls
+    unsigned* sync;              // gather work items finished this step (the last one advances *step)
+    int n_gath_tasks;            // gather work items of this slice per step
+    int gath_sc;                 // spectral bins per wave in a gather work item
     int step_limit;              // work items of slices with *step >= step_limit exit
     int optimizer, schedule;
     float lr, beta1, beta2, adam_eps;
