@@ -18,6 +18,9 @@
 //               blade image region is staged in LDS once per block and the four waves
 //               accumulate disjoint bins; fused epilogue: TV/L1 gradient and the Adam
 //               or GD update, and the step counter advanced by the last work item
+//
+// Uniform data (work items, descriptors, shear table, blade and knot tables) is read
+// through constant-address-space pointers so that it lands in scalar registers.
 
 #include <hip/hip_runtime.h>
 
@@ -26,16 +29,17 @@
 
 namespace vp {
 
-// ------------------------------------------------------------------ helpers
+#define AS4 __attribute__((address_space(4)))
 
-__device__ __forceinline__ int step_of(const SliceDesc& d) { return d.step ? *d.step : 0; }
-__device__ __forceinline__ bool slice_done(const SliceDesc& d, int st) { return d.step && st >= d.step_limit; }
-__device__ __forceinline__ bool blade_active(const SliceDesc& d, int st, int b) {
-    return d.schedule != VP_SCHED_CYCLIC || d.step == nullptr || b == st % d.B;
+template <class T>
+__device__ __forceinline__ const AS4 T* cst(const T* p) {
+    return (const AS4 T*)(const void*)p;
 }
-__device__ __forceinline__ const float2* vol_cur(const SliceDesc& d, int st) {
-    return d.step ? d.vol[st & 1] : d.vol[0];
-}
+
+// Field of the work item's slice descriptor (descriptor array or the inline copy).
+#define DF(field) (a.descs ? cst(a.descs + slice)->field : a.one.field)
+
+// ------------------------------------------------------------------ helpers
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -52,8 +56,10 @@ __device__ __forceinline__ float2 mul_i(float2 a) {
 __device__ __forceinline__ float2 cfma(float w, float2 a, float2 acc) {
     return make_float2(__builtin_fmaf(w, a.x, acc.x), __builtin_fmaf(w, a.y, acc.y));
 }
-
-#define LOAD_DESC(a, tk) ((a).descs ? (a).descs[(tk).slice] : (a).one)
+__device__ __forceinline__ bool active_blade(int sched, const int* stepp, int st, int B, int b) {
+    return sched != VP_SCHED_CYCLIC || stepp == nullptr || b == st % B;
+}
+__device__ __forceinline__ int read_step(const int* stepp) { return stepp ? *cst(stepp) : 0; }
 
 // ------------------------------------------------------------------ DFT in LDS
 //
@@ -62,7 +68,8 @@ __device__ __forceinline__ float2 cfma(float w, float2 a, float2 acc) {
 // and each thread writes its outputs. `count` transforms of length n live in LDS:
 // element j of transform f at buf[f * fstride + j * estride], with n * count <= E *
 // kThreads. Twiddles exp(-2 pi i j / n) are read from an LDS table. DIR = -1 is the
-// forward transform, DIR = +1 the unnormalised inverse.
+// forward transform, DIR = +1 the unnormalised inverse. The stage radices come packed
+// three bits per stage.
 
 template <int DIR, int R>
 __device__ __forceinline__ void butterfly(float2 (&x)[R]) {
@@ -153,11 +160,11 @@ __device__ __forceinline__ void stockham_stage(float2* buf, const float2* tw, in
 }
 
 template <int DIR, bool FFAST, int E>
-__device__ void lds_fft(float2* buf, const float2* tw, int n, int count, int fstride, int estride,
-                        const SliceDesc& d) {
+__device__ void lds_fft(float2* buf, const float2* tw, int n, int count, int fstride, int estride, int nstage,
+                        int code) {
     int p = 1;
-    for (int st = 0; st < d.nstage; ++st) {
-        const int r = d.radix[st];
+    for (int st = 0; st < nstage; ++st) {
+        const int r = (code >> (3 * st)) & 7;
         switch (r) {
             case 4: stockham_stage<DIR, 4, FFAST, E>(buf, tw, n, count, fstride, estride, p); break;
             case 2: stockham_stage<DIR, 2, FFAST, E>(buf, tw, n, count, fstride, estride, p); break;
@@ -172,16 +179,17 @@ __device__ void lds_fft(float2* buf, const float2* tw, int n, int count, int fst
 //
 // A rectangular region (rows x cols) of an n x n image, origin (gy0, gx0), is staged
 // into LDS with zeros outside the image. Each thread owns region elements
-// threadIdx.x + k * kThreads (k < kStageMax); their image offsets are computed once per
-// work item, and the next plane's values are loaded into registers while the current
-// plane is being consumed (double-buffered LDS, one barrier per plane).
+// threadIdx.x + k * kThreads (k < SE); their image offsets are computed once per work
+// item, and the next plane's values are loaded into registers while the current plane
+// is being consumed (double-buffered LDS, one barrier per plane).
 
+template <int SE>
 struct Stager {
-    int off[kStageMax];
+    int off[SE];
     __device__ void init(int rows, int cols, int gy0, int gx0, int n) {
         const int re = rows * cols;
 #pragma unroll
-        for (int k = 0; k < kStageMax; ++k) {
+        for (int k = 0; k < SE; ++k) {
             const int i = threadIdx.x + k * kThreads;
             int o = -1;
             if (i < re) {
@@ -192,17 +200,17 @@ struct Stager {
             off[k] = i < re ? o : -2;
         }
     }
-    __device__ void fetch(const float2* __restrict__ img, float2 (&pre)[kStageMax]) const {
+    __device__ void fetch(const float2* __restrict__ img, float2 (&pre)[SE]) const {
 #pragma unroll
-        for (int k = 0; k < kStageMax; ++k) {
+        for (int k = 0; k < SE; ++k) {
             float2 v = make_float2(0.f, 0.f);
             if (off[k] >= 0) v = img[off[k]];
             pre[k] = v;
         }
     }
-    __device__ void store(float2* buf, const float2 (&pre)[kStageMax]) const {
+    __device__ void store(float2* buf, const float2 (&pre)[SE]) const {
 #pragma unroll
-        for (int k = 0; k < kStageMax; ++k)
+        for (int k = 0; k < SE; ++k)
             if (off[k] != -2) buf[threadIdx.x + k * kThreads] = pre[k];
     }
 };
@@ -213,22 +221,30 @@ struct Stager {
 // Work item: (part group, tile row, tile column), tile = 64 columns x kTileRows rows.
 // Part e of the group belongs to wave e % 4, slot e / 4. Each lane owns one column.
 
-template <int GW>
+template <int GW, int SE>
 __global__ __launch_bounds__(kThreads) void k_project(const KArgs a) {
     extern __shared__ float2 sm[];
     constexpr int PPT = kTileRows;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (int ti = blockIdx.x; ti < a.ntasks; ti += gridDim.x) {
-        const Task tk = a.tasks[ti];
-        const SliceDesc& d = LOAD_DESC(a, tk);
-        const int st = step_of(d);
-        if (slice_done(d, st)) continue;
-        const ProjGroup gr = d.groups[tk.a];
-        const int n = d.n, S = d.S;
+        const AS4 Task* tk = cst(a.tasks) + ti;
+        const int slice = tk->slice;
+        int* const stepp = DF(step);
+        const int st = read_step(stepp);
+        if (stepp && st >= DF(step_limit)) continue;
+        const int n = DF(n), S = DF(S), B = DF(B), nparts = DF(nparts), sched = DF(schedule);
         const size_t nn = (size_t)n * n;
-        const int y0 = tk.b * PPT, x0 = tk.c * kTileW;
-        const int RH = PPT + gr.oy_max - gr.oy_min + 1, RW = kTileW + gr.ox_max - gr.ox_min + 1;
+        const AS4 ProjGroup* gr = cst(DF(groups)) + tk->a;
+        const int knot = gr->knot, ge0 = gr->e0, gne = gr->ne;
+        const int oxmin = gr->ox_min, oymin = gr->oy_min;
+        const int RH = PPT + gr->oy_max - oymin + 1, RW = kTileW + gr->ox_max - oxmin + 1;
         const int RE = RH * RW;
+        const int y0 = tk->b * PPT, x0 = tk->c * kTileW;
+        const AS4 KnotEntry* ent = cst(DF(knot_ent));
+        const AS4 ShearEntry* shear = cst(DF(shear));
+        float2* const work = DF(work);
+        const float2* const V = (stepp ? DF(vol[st & 1]) : DF(vol[0])) + (size_t)knot * S * nn;
         int eb[GW], ep[GW];
         bool act[GW];
 #pragma unroll
@@ -237,11 +253,10 @@ __global__ __launch_bounds__(kThreads) void k_project(const KArgs a) {
             act[j] = false;
             eb[j] = 0;
             ep[j] = 0;
-            if (e < gr.ne) {
-                const KnotEntry ke = d.knot_ent[gr.e0 + e];
-                eb[j] = ke.blade;
-                ep[j] = ke.part;
-                act[j] = blade_active(d, st, ke.blade);
+            if (e < gne) {
+                eb[j] = ent[ge0 + e].blade;
+                ep[j] = ent[ge0 + e].part;
+                act[j] = active_blade(sched, stepp, st, B, eb[j]);
             }
         }
         float2 acc[GW][PPT];
@@ -249,10 +264,9 @@ __global__ __launch_bounds__(kThreads) void k_project(const KArgs a) {
         for (int j = 0; j < GW; ++j)
 #pragma unroll
             for (int i = 0; i < PPT; ++i) acc[j][i] = make_float2(0.f, 0.f);
-        const float2* V = vol_cur(d, st) + (size_t)gr.knot * S * nn;
-        Stager sg;
-        sg.init(RH, RW, y0 + gr.oy_min, x0 + gr.ox_min, n);
-        float2 pre[kStageMax];
+        Stager<SE> sg;
+        sg.init(RH, RW, y0 + oymin, x0 + oxmin, n);
+        float2 pre[SE];
         sg.fetch(V, pre);
         for (int s = 0; s < S; ++s) {
             float2* buf = sm + (s & 1) * RE;
@@ -262,17 +276,18 @@ __global__ __launch_bounds__(kThreads) void k_project(const KArgs a) {
 #pragma unroll
             for (int j = 0; j < GW; ++j) {
                 if (act[j]) {
-                    const ShearEntry sh = d.shear[eb[j] * S + s];
-                    const float2* L = buf + (sh.oy - gr.oy_min) * RW + lane + sh.ox - gr.ox_min;
+                    const AS4 ShearEntry* sh = shear + eb[j] * S + s;
+                    const float w00 = sh->w00, w01 = sh->w01, w10 = sh->w10, w11 = sh->w11;
+                    const float2* L = buf + (sh->oy - oymin) * RW + (sh->ox - oxmin) + lane;
                     float2 a0 = L[0], a1 = L[1];
 #pragma unroll
                     for (int i = 0; i < PPT; ++i) {
                         const float2 b0 = L[(i + 1) * RW], b1 = L[(i + 1) * RW + 1];
                         float2 t = acc[j][i];
-                        t = cfma(sh.w00, a0, t);
-                        t = cfma(sh.w01, a1, t);
-                        t = cfma(sh.w10, b0, t);
-                        t = cfma(sh.w11, b1, t);
+                        t = cfma(w00, a0, t);
+                        t = cfma(w01, a1, t);
+                        t = cfma(w10, b0, t);
+                        t = cfma(w11, b1, t);
                         acc[j][i] = t;
                         a0 = b0;
                         a1 = b1;
@@ -285,7 +300,7 @@ __global__ __launch_bounds__(kThreads) void k_project(const KArgs a) {
 #pragma unroll
         for (int j = 0; j < GW; ++j) {
             if (act[j] && x < n) {
-                float2* out = d.work + ((size_t)eb[j] * d.nparts + ep[j]) * nn;
+                float2* out = work + ((size_t)eb[j] * nparts + ep[j]) * nn;
 #pragma unroll
                 for (int i = 0; i < PPT; ++i) {
                     const int y = y0 + i;
@@ -306,35 +321,39 @@ template <int DIR>
 __global__ __launch_bounds__(kThreads) void k_rows(const KArgs a) {
     extern __shared__ float2 sm[];
     for (int ti = blockIdx.x; ti < a.ntasks; ti += gridDim.x) {
-        const Task tk = a.tasks[ti];
-        const SliceDesc& d = LOAD_DESC(a, tk);
-        const int st = step_of(d);
-        if (slice_done(d, st)) continue;
-        const int b = tk.a;
-        if (!blade_active(d, st, b)) continue;
-        const int n = d.n;
+        const AS4 Task* tk = cst(a.tasks) + ti;
+        const int slice = tk->slice;
+        int* const stepp = DF(step);
+        const int st = read_step(stepp);
+        if (stepp && st >= DF(step_limit)) continue;
+        const int b = tk->a;
+        if (!active_blade(DF(schedule), stepp, st, DF(B), b)) continue;
+        const int n = DF(n), nparts = DF(nparts), nstage = DF(nstage), code = DF(radix_code);
         const size_t nn = (size_t)n * n;
         const int fb = fft_rows_per_item(n);
-        const int r0 = tk.b, rows = min(fb, n - r0);
+        const int r0 = tk->b, rows = min(fb, n - r0);
         float2* A = sm;
         float2* tw = sm + fb * n;
-        float2* img = d.work + (size_t)b * d.nparts * nn;
+        float2* img = DF(work) + (size_t)b * nparts * nn;
+        const float2* twg = DF(tw);
         const size_t base = (size_t)r0 * n;
-        for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = d.tw[i];
-        if (DIR < 0 && d.nparts == 2) {
-            const BladeDev bd = d.blade[b];
+        for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = twg[i];
+        if (DIR < 0 && nparts == 2) {
+            const AS4 BladeDev* bd = cst(DF(blade)) + b;
+            const int has0 = bd->has0, has1 = bd->has1;
+            const float w0 = bd->w0, w1 = bd->w1;
             const float2* p1 = img + nn;
             for (int i = threadIdx.x; i < rows * n; i += blockDim.x) {
                 float2 v = make_float2(0.f, 0.f);
-                if (bd.has0) v = cscale(img[base + i], bd.w0);
-                if (bd.has1) v = cfma(bd.w1, p1[base + i], v);
+                if (has0) v = cscale(img[base + i], w0);
+                if (has1) v = cfma(w1, p1[base + i], v);
                 A[i] = v;
             }
         } else {
             for (int i = threadIdx.x; i < rows * n; i += blockDim.x) A[i] = img[base + i];
         }
         __syncthreads();
-        lds_fft<DIR, false, 8>(A, tw, n, rows, n, 1, d);
+        lds_fft<DIR, false, 8>(A, tw, n, rows, n, 1, nstage, code);
         for (int i = threadIdx.x; i < rows * n; i += blockDim.x) img[base + i] = A[i];
         __syncthreads();
     }
@@ -351,33 +370,38 @@ __global__ __launch_bounds__(kThreads) void k_cols(const KArgs a) {
     extern __shared__ float2 sm[];
     __shared__ float red[kThreads];
     for (int ti = blockIdx.x; ti < a.ntasks; ti += gridDim.x) {
-        const Task tk = a.tasks[ti];
-        const SliceDesc& d = LOAD_DESC(a, tk);
-        const int st = step_of(d);
-        if (slice_done(d, st)) continue;
-        const int b = tk.a;
-        if (!blade_active(d, st, b)) {
-            if (a.mode == COL_STEP && threadIdx.x == 0) d.loss_part[b * d.n_col_items + tk.b] = 0.f;
+        const AS4 Task* tk = cst(a.tasks) + ti;
+        const int slice = tk->slice;
+        int* const stepp = DF(step);
+        const int st = read_step(stepp);
+        if (stepp && st >= DF(step_limit)) continue;
+        const int b = tk->a;
+        float* const loss_part = DF(loss_part);
+        const int n_col_items = DF(n_col_items);
+        if (!active_blade(DF(schedule), stepp, st, DF(B), b)) {
+            if (a.mode == COL_STEP && threadIdx.x == 0) loss_part[b * n_col_items + tk->b] = 0.f;
             continue;
         }
-        const int n = d.n;
+        const int n = DF(n), nparts = DF(nparts), nstage = DF(nstage), code = DF(radix_code);
         const size_t nn = (size_t)n * n;
         const int cb = fft_cols_per_item(n);
-        const int c0 = tk.b * cb, cols = min(cb, n - c0);
+        const int c0 = tk->b * cb, cols = min(cb, n - c0);
         float2* A = sm;
         float2* tw = sm + cb * n;
-        float2* img = d.work + (size_t)b * d.nparts * nn;
+        float2* img = DF(work) + (size_t)b * nparts * nn;
+        const float2* twg = DF(tw);
         const float2* src = a.mode == COL_ADJOINT ? a.in0 + (size_t)b * nn : img;
-        for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = d.tw[i];
+        for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = twg[i];
         for (int i = threadIdx.x; i < n * cb; i += blockDim.x) {
             const int y = i / cb, c = i - (i / cb) * cb;
             A[i] = c < cols ? src[(size_t)y * n + c0 + c] : make_float2(0.f, 0.f);
         }
         __syncthreads();
-        if (a.mode != COL_ADJOINT) lds_fft<-1, true, 16>(A, tw, n, cb, 1, cb, d);
+        if (a.mode != COL_ADJOINT) lds_fft<-1, true, 16>(A, tw, n, cb, 1, cb, nstage, code);
         const float sc = 1.0f / (float)n;
-        const uint8_t* mk = d.mask + (size_t)b * nn;
-        const float2* yb = d.y ? d.y + (size_t)b * nn : nullptr;
+        const uint8_t* mk = DF(mask) + (size_t)b * nn;
+        const float2* yy = DF(y);
+        const float2* yb = yy ? yy + (size_t)b * nn : nullptr;
         float lsum = 0.f;
         for (int i = threadIdx.x; i < n * cb; i += blockDim.x) {
             const int y = i / cb, c = i - (i / cb) * cb;
@@ -407,7 +431,7 @@ __global__ __launch_bounds__(kThreads) void k_cols(const KArgs a) {
         }
         __syncthreads();
         if (a.mode != COL_FORWARD) {
-            lds_fft<1, true, 16>(A, tw, n, cb, 1, cb, d);
+            lds_fft<1, true, 16>(A, tw, n, cb, 1, cb, nstage, code);
             for (int i = threadIdx.x; i < n * cb; i += blockDim.x) {
                 const int y = i / cb, c = i - (i / cb) * cb;
                 if (c < cols) img[(size_t)y * n + c0 + c] = A[i];
@@ -420,7 +444,7 @@ __global__ __launch_bounds__(kThreads) void k_cols(const KArgs a) {
                 if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
                 __syncthreads();
             }
-            if (threadIdx.x == 0) d.loss_part[b * d.n_col_items + tk.b] = red[0];
+            if (threadIdx.x == 0) loss_part[b * n_col_items + tk->b] = red[0];
         }
         __syncthreads();
     }
@@ -428,8 +452,9 @@ __global__ __launch_bounds__(kThreads) void k_cols(const KArgs a) {
 
 // ------------------------------------------------------------------ regulariser gradient
 
+// Charbonnier weight d / sqrt(|d|^2 + eps^2): the gradient of sqrt(|d|^2 + eps^2) - eps.
 __device__ __forceinline__ float2 charb_w(float2 dlt, float eps2) {
-    return cscale(dlt, 1.0f / sqrtf(dlt.x * dlt.x + dlt.y * dlt.y + eps2));
+    return cscale(dlt, rsqrtf(dlt.x * dlt.x + dlt.y * dlt.y + eps2));
 }
 
 // tv_w * grad TV + l1_w * grad L1 at voxel (t, s, y, x) of a [T][S][n][n] volume.
@@ -454,6 +479,11 @@ __device__ __forceinline__ float2 reg_grad(const float2* __restrict__ V, size_t 
     return g;
 }
 
+__device__ __forceinline__ float2 shfl_up1(float2 v) { return make_float2(__shfl_up(v.x, 1), __shfl_up(v.y, 1)); }
+__device__ __forceinline__ float2 shfl_down1(float2 v) {
+    return make_float2(__shfl_down(v.x, 1), __shfl_down(v.y, 1));
+}
+
 // ------------------------------------------------------------------ adjoint gather + update
 //
 // G[k][s][y][x] = sum over the knot's blade parts e (plan order, blades ascending) of
@@ -463,65 +493,75 @@ __device__ __forceinline__ float2 reg_grad(const float2* __restrict__ V, size_t 
 // MODE = GATHER_STORE writes (or adds to) the gradient; GATHER_STEP adds the TV/L1
 // gradient and applies the optimiser, reading volume[step & 1] and writing the other
 // copy; the last finished work item of the step advances the slice's step counter.
+// In the update each lane walks its column through the wave's bins with a register
+// window of the previous, current and next bin (rows y0-1 .. y0+kTileRows), taking
+// the x neighbours from the adjacent lanes.
 
-template <int MODE>
+template <int MODE, int SE>
 __global__ __launch_bounds__(kThreads) void k_gather(const KArgs a) {
     extern __shared__ float2 sm[];
-    constexpr int PPT = kTileRows, SCM = kChunkMax;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int PPT = kTileRows, SCM = kChunkMax, WR = PPT + 2;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (int ti = blockIdx.x; ti < a.ntasks; ti += gridDim.x) {
-        const Task tk = a.tasks[ti];
-        const SliceDesc& d = LOAD_DESC(a, tk);
-        const int st = step_of(d);
-        if (slice_done(d, st)) continue;
-        const int n = d.n, S = d.S, kt = tk.a;
+        const AS4 Task* tk = cst(a.tasks) + ti;
+        const int slice = tk->slice;
+        int* const stepp = DF(step);
+        const int st = read_step(stepp);
+        if (stepp && st >= DF(step_limit)) continue;
+        const int n = DF(n), S = DF(S), T = DF(T), B = DF(B), nparts = DF(nparts), sched = DF(schedule);
+        const int kt = tk->a;
         const size_t nn = (size_t)n * n;
         const int txn = (n + kTileW - 1) / kTileW;
-        const int y0 = (tk.b / txn) * PPT, x0 = (tk.b % txn) * kTileW;
-        const int sc = d.gath_sc;
-        const int sw = tk.c * 4 * sc + wave * sc;
+        const int y0 = (tk->b / txn) * PPT, x0 = (tk->b % txn) * kTileW;
+        const int sc = DF(gath_sc);
+        const int sw = tk->c * 4 * sc + wave * sc;
         const int ns = max(0, min(sc, S - sw));
-        const KnotInfo ki = d.knots[kt];
-        const int RH = PPT + ki.oy_max - ki.oy_min + 1, RW = kTileW + ki.ox_max - ki.ox_min + 1;
+        const AS4 KnotInfo* ki = cst(DF(knots)) + kt;
+        const int kox = ki->ox_max, koy = ki->oy_max;
+        const int RH = PPT + koy - ki->oy_min + 1, RW = kTileW + kox - ki->ox_min + 1;
         const int RE = RH * RW;
+        const AS4 KnotEntry* ent = cst(DF(knot_ent));
+        const AS4 ShearEntry* shear = cst(DF(shear));
+        const float2* const work = DF(work);
+        const int* kp = DF(knot_ptr);
+        const int e0 = cst(kp)[kt], e1 = cst(kp)[kt + 1];
         float2 acc[SCM][PPT];
 #pragma unroll
         for (int q = 0; q < SCM; ++q)
 #pragma unroll
             for (int i = 0; i < PPT; ++i) acc[q][i] = make_float2(0.f, 0.f);
-        const int e0 = d.knot_ptr[kt], e1 = d.knot_ptr[kt + 1];
-        Stager sg;
-        sg.init(RH, RW, y0 - ki.oy_max - 1, x0 - ki.ox_max - 1, n);
-        float2 pre[kStageMax];
+        Stager<SE> sg;
+        sg.init(RH, RW, y0 - koy - 1, x0 - kox - 1, n);
+        float2 pre[SE];
         int e = e0;
-        while (e < e1 && !blade_active(d, st, d.knot_ent[e].blade)) ++e;
-        if (e < e1) sg.fetch(d.work + (size_t)d.knot_ent[e].blade * d.nparts * nn, pre);
+        while (e < e1 && !active_blade(sched, stepp, st, B, ent[e].blade)) ++e;
+        if (e < e1) sg.fetch(work + (size_t)ent[e].blade * nparts * nn, pre);
         for (int it = 0; e < e1; ++it) {
-            const KnotEntry ke = d.knot_ent[e];
-            const int b = ke.blade;
+            const int b = ent[e].blade;
+            const float wb = ent[e].weight;
             float2* buf = sm + (it & 1) * RE;
             sg.store(buf, pre);
             __syncthreads();
             int en = e + 1;
-            while (en < e1 && !blade_active(d, st, d.knot_ent[en].blade)) ++en;
-            if (en < e1) sg.fetch(d.work + (size_t)d.knot_ent[en].blade * d.nparts * nn, pre);
-            const float wb = ke.weight;
-            const ShearEntry* shb = d.shear + (size_t)b * S + sw;
+            while (en < e1 && !active_blade(sched, stepp, st, B, ent[en].blade)) ++en;
+            if (en < e1) sg.fetch(work + (size_t)ent[en].blade * nparts * nn, pre);
+            const AS4 ShearEntry* shb = shear + (size_t)b * S + sw;
 #pragma unroll
             for (int q = 0; q < SCM; ++q) {
                 if (q < ns) {
-                    const ShearEntry sh = shb[q];
+                    const float w00 = shb[q].w00, w01 = shb[q].w01, w10 = shb[q].w10, w11 = shb[q].w11;
                     // row of g[y - oy][.] for pixel row 0, column of g[.][x - ox]
-                    const float2* L = buf + (ki.oy_max - sh.oy + 1) * RW + lane + ki.ox_max - sh.ox + 1;
+                    const float2* L = buf + (koy - shb[q].oy + 1) * RW + (kox - shb[q].ox + 1) + lane;
                     float2 u0 = L[-RW], u1 = L[-RW - 1];
 #pragma unroll
                     for (int i = 0; i < PPT; ++i) {
                         const float2 v0 = L[i * RW], v1 = L[i * RW - 1];
                         float2 t = make_float2(0.f, 0.f);
-                        t = cfma(sh.w00, v0, t);
-                        t = cfma(sh.w01, v1, t);
-                        t = cfma(sh.w10, u0, t);
-                        t = cfma(sh.w11, u1, t);
+                        t = cfma(w00, v0, t);
+                        t = cfma(w01, v1, t);
+                        t = cfma(w10, u0, t);
+                        t = cfma(w11, u1, t);
                         acc[q][i] = cfma(wb, t, acc[q][i]);
                         u0 = v0;
                         u1 = v1;
@@ -533,6 +573,7 @@ __global__ __launch_bounds__(kThreads) void k_gather(const KArgs a) {
         __syncthreads();
         const int x = x0 + lane;
         if (MODE == GATHER_STORE) {
+            float2* const grad = DF(grad);
             if (x < n) {
 #pragma unroll
                 for (int q = 0; q < SCM; ++q) {
@@ -543,66 +584,114 @@ __global__ __launch_bounds__(kThreads) void k_gather(const KArgs a) {
                             if (y < n) {
                                 const size_t idx = (((size_t)kt * S + sw + q) * n + y) * n + x;
                                 float2 g = acc[q][i];
-                                if (a.accumulate) g = cadd(d.grad[idx], g);
-                                d.grad[idx] = g;
+                                if (a.accumulate) g = cadd(grad[idx], g);
+                                grad[idx] = g;
                             }
                         }
                     }
                 }
             }
         } else {
-            const float2* Vin = vol_cur(d, st);
-            float2* Vout = d.vol[(st + 1) & 1];
+            const float2* const Vin = stepp ? DF(vol[st & 1]) : DF(vol[0]);
+            float2* const Vout = DF(vol[(st + 1) & 1]);
+            float2* const Mm = DF(m);
+            float2* const Mv = DF(v);
+            const int opt = DF(optimizer);
+            const float lr = DF(lr), beta1 = DF(beta1), beta2 = DF(beta2), aeps = DF(adam_eps);
+            const float tv_w = DF(tv_w), l1_w = DF(l1_w), teps = DF(tv_eps);
+            const float eps2 = teps * teps;
             const int t = st + 1;
             // bias corrections in FP64, once per item
-            const float bc1 = (float)(1.0 - pow((double)d.beta1, (double)t));
-            const float bc2s = (float)sqrt(1.0 - pow((double)d.beta2, (double)t));
-            const float step_size = d.lr / bc1;
-            if (x < n) {
+            const float bc1 = (float)(1.0 - pow((double)beta1, (double)t));
+            const float inv_bc2s = (float)(1.0 / sqrt(1.0 - pow((double)beta2, (double)t)));
+            const float step_size = lr / bc1;
+            const int xc = min(x, n - 1);
+            const size_t kbase = (size_t)kt * S * nn;
+            // window row r holds image row y0 - 1 + r of one bin, zero outside the grid
+            auto load_plane = [&](int s, float2 (&w)[WR]) {
 #pragma unroll
-                for (int q = 0; q < SCM; ++q) {
-                    if (q < ns) {
+                for (int r = 0; r < WR; ++r) {
+                    const int y = y0 - 1 + r;
+                    w[r] = make_float2(0.f, 0.f);
+                    if (s >= 0 && s < S && y >= 0 && y < n) w[r] = Vin[kbase + ((size_t)s * n + y) * n + xc];
+                }
+            };
+            float2 pv[WR], cv[WR], nv[WR];
+            if (ns > 0) {
+                load_plane(sw - 1, pv);
+                load_plane(sw, cv);
+                load_plane(sw + 1, nv);
+            }
 #pragma unroll
-                        for (int i = 0; i < PPT; ++i) {
-                            const int y = y0 + i;
-                            if (y < n) {
-                                const int s = sw + q;
-                                const size_t idx = (((size_t)kt * S + s) * n + y) * n + x;
-                                const float2 reg =
-                                    reg_grad(Vin, idx, kt, s, y, x, n, S, d.T, d.tv_w, d.l1_w, d.tv_eps);
-                                const float2 gr = cadd(acc[q][i], reg);
-                                const float2 v0 = Vin[idx];
-                                float2 nv;
-                                if (d.optimizer == VP_OPT_ADAM) {
-                                    float2 m = d.m[idx], v = d.v[idx];
-                                    m.x = d.beta1 * m.x + (1.0f - d.beta1) * gr.x;
-                                    m.y = d.beta1 * m.y + (1.0f - d.beta1) * gr.y;
-                                    v.x = d.beta2 * v.x + (1.0f - d.beta2) * gr.x * gr.x;
-                                    v.y = d.beta2 * v.y + (1.0f - d.beta2) * gr.y * gr.y;
-                                    d.m[idx] = m;
-                                    d.v[idx] = v;
-                                    const float dx = sqrtf(v.x) / bc2s + d.adam_eps;
-                                    const float dy = sqrtf(v.y) / bc2s + d.adam_eps;
-                                    nv = make_float2(v0.x - step_size * (m.x / dx), v0.y - step_size * (m.y / dy));
+            for (int q = 0; q < SCM; ++q) {
+                if (q < ns) {
+                    const int s = sw + q;
+                    if (q > 0) {
+#pragma unroll
+                        for (int r = 0; r < WR; ++r) {
+                            pv[r] = cv[r];
+                            cv[r] = nv[r];
+                        }
+                        load_plane(s + 1, nv);
+                    }
+#pragma unroll
+                    for (int i = 0; i < PPT; ++i) {
+                        const int y = y0 + i;
+                        if (y < n) {
+                            const size_t idx = kbase + ((size_t)s * n + y) * n + xc;
+                            const float2 v0 = cv[i + 1];
+                            float2 left = shfl_up1(v0), right = shfl_down1(v0);
+                            if (lane == 0) left = x0 > 0 ? Vin[idx - 1] : make_float2(0.f, 0.f);
+                            if (lane == 63) right = x0 + 64 < n ? Vin[idx + 1] : make_float2(0.f, 0.f);
+                            float2 g = make_float2(0.f, 0.f);
+                            if (tv_w != 0.f) {
+                                if (kt > 0) g = cadd(g, charb_w(csub(v0, Vin[idx - (size_t)S * nn]), eps2));
+                                if (kt + 1 < T) g = csub(g, charb_w(csub(Vin[idx + (size_t)S * nn], v0), eps2));
+                                if (s > 0) g = cadd(g, charb_w(csub(v0, pv[i + 1]), eps2));
+                                if (s + 1 < S) g = csub(g, charb_w(csub(nv[i + 1], v0), eps2));
+                                if (y > 0) g = cadd(g, charb_w(csub(v0, cv[i]), eps2));
+                                if (y + 1 < n) g = csub(g, charb_w(csub(cv[i + 2], v0), eps2));
+                                if (x > 0) g = cadd(g, charb_w(csub(v0, left), eps2));
+                                if (x + 1 < n) g = csub(g, charb_w(csub(right, v0), eps2));
+                                g = cscale(g, tv_w);
+                            }
+                            if (l1_w != 0.f) g = cfma(l1_w, charb_w(v0, eps2), g);
+                            const float2 gr = cadd(acc[q][i], g);
+                            if (x < n) {
+                                float2 nvx;
+                                if (opt == VP_OPT_ADAM) {
+                                    float2 m = Mm[idx], v = Mv[idx];
+                                    m.x = beta1 * m.x + (1.0f - beta1) * gr.x;
+                                    m.y = beta1 * m.y + (1.0f - beta1) * gr.y;
+                                    v.x = beta2 * v.x + (1.0f - beta2) * gr.x * gr.x;
+                                    v.y = beta2 * v.y + (1.0f - beta2) * gr.y * gr.y;
+                                    Mm[idx] = m;
+                                    Mv[idx] = v;
+                                    const float dx = sqrtf(v.x) * inv_bc2s + aeps;
+                                    const float dy = sqrtf(v.y) * inv_bc2s + aeps;
+                                    nvx = make_float2(v0.x - step_size * __fdividef(m.x, dx),
+                                                      v0.y - step_size * __fdividef(m.y, dy));
                                 } else {
-                                    nv = make_float2(v0.x - d.lr * gr.x, v0.y - d.lr * gr.y);
+                                    nvx = make_float2(v0.x - lr * gr.x, v0.y - lr * gr.y);
                                 }
-                                Vout[idx] = nv;
+                                Vout[idx] = nvx;
                             }
                         }
                     }
                 }
             }
-            if (d.sync) {
+            unsigned* const sync = DF(sync);
+            if (sync) {
                 // every work item of the slice read *step before finishing; the last one
                 // to finish advances it for the next step
+                const int ntask = DF(n_gath_tasks);
                 __syncthreads();
                 if (threadIdx.x == 0) {
                     __threadfence();
-                    const unsigned prev = atomicAdd(d.sync, 1u);
-                    if (prev + 1 == (unsigned)d.n_gath_tasks) {
-                        atomicExch(d.sync, 0u);
-                        atomicExch(d.step, st + 1);
+                    const unsigned prev = atomicAdd(sync, 1u);
+                    if (prev + 1 == (unsigned)ntask) {
+                        atomicExch(sync, 0u);
+                        atomicExch(stepp, st + 1);
                     }
                 }
             }
@@ -615,18 +704,20 @@ __global__ __launch_bounds__(kThreads) void k_gather(const KArgs a) {
 // Operator TV/L1 gradient: grad (+)= tv_w grad TV + l1_w grad L1 (weights from the descriptor).
 __global__ __launch_bounds__(kThreads) void k_tv_grad(const KArgs a) {
     for (int ti = blockIdx.x; ti < a.ntasks; ti += gridDim.x) {
-        const Task tk = a.tasks[ti];
-        const SliceDesc& d = LOAD_DESC(a, tk);
-        const int n = d.n, S = d.S, T = d.T;
+        const AS4 Task* tk = cst(a.tasks) + ti;
+        const int slice = tk->slice;
+        const int n = DF(n), S = DF(S), T = DF(T);
+        const float tv_w = DF(tv_w), l1_w = DF(l1_w), teps = DF(tv_eps);
+        const float2* V = DF(vol[0]);
+        float2* grad = DF(grad);
         const size_t nvox = (size_t)T * S * n * n;
-        const size_t i0 = (size_t)tk.a * kVoxItem;
-        const float2* V = d.vol[0];
+        const size_t i0 = (size_t)tk->a * kVoxItem;
         for (size_t i = i0 + threadIdx.x; i < min(nvox, i0 + kVoxItem); i += blockDim.x) {
             const int x = (int)(i % n), y = (int)((i / n) % n), s = (int)((i / ((size_t)n * n)) % S);
             const int t = (int)(i / ((size_t)S * n * n));
-            float2 g = reg_grad(V, i, t, s, y, x, n, S, T, d.tv_w, d.l1_w, d.tv_eps);
-            if (a.accumulate) g = cadd(d.grad[i], g);
-            d.grad[i] = g;
+            float2 g = reg_grad(V, i, t, s, y, x, n, S, T, tv_w, l1_w, teps);
+            if (a.accumulate) g = cadd(grad[i], g);
+            grad[i] = g;
         }
     }
 }
@@ -637,14 +728,15 @@ __global__ __launch_bounds__(kThreads) void k_tv_grad(const KArgs a) {
 __global__ __launch_bounds__(kThreads) void k_reg_value(const KArgs a) {
     __shared__ double red[2][kThreads];
     for (int ti = blockIdx.x; ti < a.ntasks; ti += gridDim.x) {
-        const Task tk = a.tasks[ti];
-        const SliceDesc& d = LOAD_DESC(a, tk);
-        const int st = step_of(d);
-        const int n = d.n, S = d.S, T = d.T;
+        const AS4 Task* tk = cst(a.tasks) + ti;
+        const int slice = tk->slice;
+        int* const stepp = DF(step);
+        const int st = read_step(stepp);
+        const int n = DF(n), S = DF(S), T = DF(T);
         const size_t nn = (size_t)n * n, nvox = (size_t)T * S * nn;
-        const size_t i0 = (size_t)tk.a * kVoxItem;
-        const float2* V = vol_cur(d, st);
-        const float e = d.tv_eps, e2 = e * e;
+        const size_t i0 = (size_t)tk->a * kVoxItem;
+        const float2* V = stepp ? DF(vol[st & 1]) : DF(vol[0]);
+        const float e = DF(tv_eps), e2 = e * e;
         double tv = 0.0, l1 = 0.0;
         for (size_t i = i0 + threadIdx.x; i < min(nvox, i0 + kVoxItem); i += blockDim.x) {
             const int x = (int)(i % n), y = (int)((i / n) % n), s = (int)((i / nn) % S);
@@ -684,19 +776,20 @@ __global__ __launch_bounds__(kThreads) void k_reg_value(const KArgs a) {
 // proj = water + fat. One work item per (knot, block of kVoxItem pixels).
 __global__ __launch_bounds__(kThreads) void k_render(const KArgs a) {
     for (int ti = blockIdx.x; ti < a.ntasks; ti += gridDim.x) {
-        const Task tk = a.tasks[ti];
-        const SliceDesc& d = LOAD_DESC(a, tk);
-        const int st = step_of(d);
-        const int n = d.n, S = d.S;
+        const AS4 Task* tk = cst(a.tasks) + ti;
+        const int slice = tk->slice;
+        int* const stepp = DF(step);
+        const int st = read_step(stepp);
+        const int n = DF(n), S = DF(S);
         const size_t nn = (size_t)n * n;
         const int split = a.split_bin < 0 ? S / 2 : min(a.split_bin, S);
-        const float2* V = vol_cur(d, st) + (size_t)tk.a * S * nn;
-        const size_t p0 = (size_t)tk.b * kVoxItem;
+        const float2* V = (stepp ? DF(vol[st & 1]) : DF(vol[0])) + (size_t)tk->a * S * nn;
+        const size_t p0 = (size_t)tk->b * kVoxItem;
         for (size_t p = p0 + threadIdx.x; p < min(nn, p0 + kVoxItem); p += blockDim.x) {
             float2 w = make_float2(0.f, 0.f), f = make_float2(0.f, 0.f);
             for (int s = 0; s < split; ++s) w = cadd(w, V[(size_t)s * nn + p]);
             for (int s = split; s < S; ++s) f = cadd(f, V[(size_t)s * nn + p]);
-            const size_t o = (size_t)tk.a * nn + p;
+            const size_t o = (size_t)tk->a * nn + p;
             if (a.out0) a.out0[o] = cadd(w, f);
             if (a.out1) a.out1[o] = w;
             if (a.out2) a.out2[o] = f;
@@ -708,15 +801,27 @@ __global__ __launch_bounds__(kThreads) void k_render(const KArgs a) {
 
 static inline int grid_for(int ntasks) { return ntasks < 1 ? 1 : (ntasks > (1 << 20) ? (1 << 20) : ntasks); }
 
+// Staging depth (region elements per thread) needed for a double-buffered LDS region.
+static inline int stage_depth(size_t lds_bytes) {
+    return lds_bytes <= 2 * 8 * kThreads * sizeof(float2) ? 8 : 16;
+}
+
 hipError_t launch_project(const KArgs& a, int gw, size_t lds, hipStream_t s) {
     if (a.ntasks <= 0) return hipSuccess;
     const dim3 g(grid_for(a.ntasks)), b(kThreads);
+    const bool deep = stage_depth(lds) > 8;
+#define P(GW)                                                                      \
+    do {                                                                           \
+        if (deep) hipLaunchKernelGGL((k_project<GW, 16>), g, b, lds, s, a);         \
+        else hipLaunchKernelGGL((k_project<GW, 8>), g, b, lds, s, a);               \
+    } while (0)
     switch (gw) {
-        case 1: hipLaunchKernelGGL(k_project<1>, g, b, lds, s, a); break;
-        case 2: hipLaunchKernelGGL(k_project<2>, g, b, lds, s, a); break;
-        case 4: hipLaunchKernelGGL(k_project<4>, g, b, lds, s, a); break;
-        default: hipLaunchKernelGGL(k_project<8>, g, b, lds, s, a); break;
+        case 1: P(1); break;
+        case 2: P(2); break;
+        case 4: P(4); break;
+        default: P(8); break;
     }
+#undef P
     return hipGetLastError();
 }
 hipError_t launch_rows(const KArgs& a, int dir, size_t lds, hipStream_t s) {
@@ -734,10 +839,15 @@ hipError_t launch_cols(const KArgs& a, size_t lds, hipStream_t s) {
 }
 hipError_t launch_gather(const KArgs& a, int mode, size_t lds, hipStream_t s) {
     if (a.ntasks <= 0) return hipSuccess;
-    if (mode == GATHER_STEP)
-        hipLaunchKernelGGL(k_gather<GATHER_STEP>, dim3(grid_for(a.ntasks)), dim3(kThreads), lds, s, a);
-    else
-        hipLaunchKernelGGL(k_gather<GATHER_STORE>, dim3(grid_for(a.ntasks)), dim3(kThreads), lds, s, a);
+    const dim3 g(grid_for(a.ntasks)), b(kThreads);
+    const bool deep = stage_depth(lds) > 8;
+    if (mode == GATHER_STEP) {
+        if (deep) hipLaunchKernelGGL((k_gather<GATHER_STEP, 16>), g, b, lds, s, a);
+        else hipLaunchKernelGGL((k_gather<GATHER_STEP, 8>), g, b, lds, s, a);
+    } else {
+        if (deep) hipLaunchKernelGGL((k_gather<GATHER_STORE, 16>), g, b, lds, s, a);
+        else hipLaunchKernelGGL((k_gather<GATHER_STORE, 8>), g, b, lds, s, a);
+    }
     return hipGetLastError();
 }
 hipError_t launch_tv_grad(const KArgs& a, hipStream_t s) {

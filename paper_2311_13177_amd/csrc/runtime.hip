@@ -91,6 +91,8 @@ void fill_desc(const vp_plan* p, const DeviceTables* t, SliceDesc* d) {
     d->nparts = p->nparts;
     d->nstage = p->nstage;
     for (int i = 0; i < kMaxStages; ++i) d->radix[i] = p->radix[i];
+    d->radix_code = 0;
+    for (int i = 0; i < p->nstage; ++i) d->radix_code |= p->radix[i] << (3 * i);
     d->n_col_items = p->n_col_items;
     d->tw = t->tw;
     d->mask = t->mask;

@@ -79,7 +79,8 @@ struct SliceDesc {
     int nparts;                  // parts per blade in the work buffer (1 or 2)
     int nstage;
     int radix[kMaxStages];
-    int n_col_items;             // column work items per blade (loss partials per blade)
+    int radix_code;              // radix of stage i in bits [3i, 3i+3)
+    int n_col_items;            // column work items per blade (loss partials per blade)
     const float2* tw;            // twiddles exp(-2 pi i j / n), j < n
     const uint8_t* mask;
     const ShearEntry* shear;     // [B][S]
