@@ -55,10 +55,10 @@ vp_status group_build(SliceGroup* g, const std::vector<vp_session*>& sessions, c
         add(vox, p->t_vox);
         add(render, p->t_render);
         L.proj_gw = std::max(L.proj_gw, p->proj_gw);
-        L.lds_proj = std::max(L.lds_proj, p->lds_proj);
+        L.re_proj = std::max(L.re_proj, p->re_proj);
         L.lds_rows = std::max(L.lds_rows, p->lds_rows);
         L.lds_cols = std::max(L.lds_cols, p->lds_cols);
-        L.lds_gath = std::max(L.lds_gath, p->lds_gath);
+        L.re_gath = std::max(L.re_gath, p->re_gath);
     }
     std::vector<Task> all;
     size_t off[6];

@@ -175,6 +175,98 @@ __device__ void lds_fft(float2* buf, const float2* tw, int n, int count, int fst
     }
 }
 
+// Compile-time variant for the common lengths: the radix sequence, strides and index
+// arithmetic are constants (the same factorisation as the plan: 4s, then 2s, 3s, 5s,
+// so results equal the runtime variant's bit for bit).
+__host__ __device__ constexpr int ct_radix(int n, int i) {
+    int st = 0;
+    while (n % 4 == 0) { if (st == i) return 4; n /= 4; ++st; }
+    while (n % 2 == 0) { if (st == i) return 2; n /= 2; ++st; }
+    while (n % 3 == 0) { if (st == i) return 3; n /= 3; ++st; }
+    while (n % 5 == 0) { if (st == i) return 5; n /= 5; ++st; }
+    return 0;
+}
+
+template <int DIR, int R, bool FFAST, int N, int COUNT, int P>
+__device__ __forceinline__ void ct_stage(float2* buf, const float2* tw) {
+    constexpr int m = N / R, total = m * COUNT, tws = N / (P * R);
+    constexpr int FS = FFAST ? 1 : N, ES = FFAST ? COUNT : 1;
+    constexpr int MAXB = (total + kThreads - 1) / kThreads;
+    float2 x[MAXB][R];
+    int bout[MAXB];
+#pragma unroll
+    for (int t = 0; t < MAXB; ++t) {
+        const int idx = threadIdx.x + t * kThreads;
+        bout[t] = -1;
+        if (total % kThreads == 0 || idx < total) {
+            const int f = FFAST ? idx % COUNT : idx / m;
+            const int j = FFAST ? idx / COUNT : idx % m;
+            const int k = j % P;
+            const int bin = f * FS + j * ES;
+            bout[t] = f * FS + ((j - k) * R + k) * ES;
+#pragma unroll
+            for (int q = 0; q < R; ++q) x[t][q] = buf[bin + q * m * ES];
+#pragma unroll
+            for (int q = 1; q < R; ++q) {
+                float2 w = tw[k * q * tws];
+                if (DIR > 0) w.y = -w.y;
+                x[t][q] = cmul(x[t][q], w);
+            }
+            butterfly<DIR, R>(x[t]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < MAXB; ++t) {
+        if (bout[t] >= 0) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) buf[bout[t] + q * P * ES] = x[t][q];
+        }
+    }
+    __syncthreads();
+}
+
+template <int DIR, bool FFAST, int N, int COUNT, int ST = 0, int P = 1>
+__device__ __forceinline__ void ct_fft(float2* buf, const float2* tw) {
+    if constexpr (ct_radix(N, ST) != 0) {
+        constexpr int R = ct_radix(N, ST);
+        ct_stage<DIR, R, FFAST, N, COUNT, P>(buf, tw);
+        ct_fft<DIR, FFAST, N, COUNT, ST + 1, P * R>(buf, tw);
+    }
+}
+
+// Row transforms (count rows of length n, row-major) and column transforms (count
+// columns of length n, element j of column f at j * count + f), dispatched to the
+// compile-time variant for the common lengths.
+template <int DIR>
+__device__ void fft_rows_any(float2* buf, const float2* tw, int n, int nstage, int code) {
+    switch (n) {
+        case 64: ct_fft<DIR, false, 64, fft_rows_per_item(64)>(buf, tw); break;
+        case 128: ct_fft<DIR, false, 128, fft_rows_per_item(128)>(buf, tw); break;
+        case 192: ct_fft<DIR, false, 192, fft_rows_per_item(192)>(buf, tw); break;
+        case 256: ct_fft<DIR, false, 256, fft_rows_per_item(256)>(buf, tw); break;
+        case 320: ct_fft<DIR, false, 320, fft_rows_per_item(320)>(buf, tw); break;
+        case 384: ct_fft<DIR, false, 384, fft_rows_per_item(384)>(buf, tw); break;
+        default: lds_fft<DIR, false, 8>(buf, tw, n, fft_rows_per_item(n), n, 1, nstage, code); break;
+    }
+}
+template <int DIR>
+__device__ void fft_cols_any(float2* buf, const float2* tw, int n, int nstage, int code) {
+    switch (n) {
+        case 64: ct_fft<DIR, true, 64, fft_cols_per_item(64)>(buf, tw); break;
+        case 128: ct_fft<DIR, true, 128, fft_cols_per_item(128)>(buf, tw); break;
+        case 192: ct_fft<DIR, true, 192, fft_cols_per_item(192)>(buf, tw); break;
+        case 256: ct_fft<DIR, true, 256, fft_cols_per_item(256)>(buf, tw); break;
+        case 320: ct_fft<DIR, true, 320, fft_cols_per_item(320)>(buf, tw); break;
+        case 384: ct_fft<DIR, true, 384, fft_cols_per_item(384)>(buf, tw); break;
+        default: {
+            const int cb = fft_cols_per_item(n);
+            lds_fft<DIR, true, 16>(buf, tw, n, cb, 1, cb, nstage, code);
+            break;
+        }
+    }
+}
+
 // ------------------------------------------------------------------ LDS staging
 //
 // A rectangular region (rows x cols) of an n x n image, origin (gy0, gx0), is staged
@@ -183,11 +275,14 @@ __device__ void lds_fft(float2* buf, const float2* tw, int n, int count, int fst
 // item, and the next plane's values are loaded into registers while the current plane
 // is being consumed (double-buffered LDS, one barrier per plane).
 
-template <int SE>
+// P planes (images of the same size, same region) are staged per phase; plane p of a
+// phase occupies buf[p * re, (p + 1) * re). A null plane pointer stages zeros.
+template <int SE, int P>
 struct Stager {
     int off[SE];
+    int re;
     __device__ void init(int rows, int cols, int gy0, int gx0, int n) {
-        const int re = rows * cols;
+        re = rows * cols;
 #pragma unroll
         for (int k = 0; k < SE; ++k) {
             const int i = threadIdx.x + k * kThreads;
@@ -200,18 +295,22 @@ struct Stager {
             off[k] = i < re ? o : -2;
         }
     }
-    __device__ void fetch(const float2* __restrict__ img, float2 (&pre)[SE]) const {
+    __device__ void fetch(const float2* const (&img)[P], float2 (&pre)[P][SE]) const {
 #pragma unroll
-        for (int k = 0; k < SE; ++k) {
-            float2 v = make_float2(0.f, 0.f);
-            if (off[k] >= 0) v = img[off[k]];
-            pre[k] = v;
-        }
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+            for (int k = 0; k < SE; ++k) {
+                float2 v = make_float2(0.f, 0.f);
+                if (img[p] && off[k] >= 0) v = img[p][off[k]];
+                pre[p][k] = v;
+            }
     }
-    __device__ void store(float2* buf, const float2 (&pre)[SE]) const {
+    __device__ void store(float2* buf, const float2 (&pre)[P][SE]) const {
 #pragma unroll
-        for (int k = 0; k < SE; ++k)
-            if (off[k] != -2) buf[threadIdx.x + k * kThreads] = pre[k];
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+            for (int k = 0; k < SE; ++k)
+                if (off[k] != -2) buf[p * re + threadIdx.x + k * kThreads] = pre[p][k];
     }
 };
 
@@ -221,7 +320,7 @@ struct Stager {
 // Work item: (part group, tile row, tile column), tile = 64 columns x kTileRows rows.
 // Part e of the group belongs to wave e % 4, slot e / 4. Each lane owns one column.
 
-template <int GW, int SE>
+template <int GW, int SE, int P>
 __global__ __launch_bounds__(kThreads) void k_project(const KArgs a) {
     extern __shared__ float2 sm[];
     constexpr int PPT = kTileRows;
@@ -264,33 +363,49 @@ __global__ __launch_bounds__(kThreads) void k_project(const KArgs a) {
         for (int j = 0; j < GW; ++j)
 #pragma unroll
             for (int i = 0; i < PPT; ++i) acc[j][i] = make_float2(0.f, 0.f);
-        Stager<SE> sg;
+        Stager<SE, P> sg;
         sg.init(RH, RW, y0 + oymin, x0 + oxmin, n);
-        float2 pre[SE];
-        sg.fetch(V, pre);
-        for (int s = 0; s < S; ++s) {
-            float2* buf = sm + (s & 1) * RE;
+        float2 pre[P][SE];
+        {
+            const float2* planes[P];
+#pragma unroll
+            for (int p = 0; p < P; ++p) planes[p] = p < S ? V + (size_t)p * nn : nullptr;
+            sg.fetch(planes, pre);
+        }
+        for (int s0 = 0, it = 0; s0 < S; s0 += P, ++it) {
+            float2* buf = sm + (it & 1) * P * RE;
             sg.store(buf, pre);
             __syncthreads();
-            if (s + 1 < S) sg.fetch(V + (size_t)(s + 1) * nn, pre);
+            if (s0 + P < S) {
+                const float2* planes[P];
 #pragma unroll
-            for (int j = 0; j < GW; ++j) {
-                if (act[j]) {
-                    const AS4 ShearEntry* sh = shear + eb[j] * S + s;
-                    const float w00 = sh->w00, w01 = sh->w01, w10 = sh->w10, w11 = sh->w11;
-                    const float2* L = buf + (sh->oy - oymin) * RW + (sh->ox - oxmin) + lane;
-                    float2 a0 = L[0], a1 = L[1];
+                for (int p = 0; p < P; ++p) planes[p] = s0 + P + p < S ? V + (size_t)(s0 + P + p) * nn : nullptr;
+                sg.fetch(planes, pre);
+            }
 #pragma unroll
-                    for (int i = 0; i < PPT; ++i) {
-                        const float2 b0 = L[(i + 1) * RW], b1 = L[(i + 1) * RW + 1];
-                        float2 t = acc[j][i];
-                        t = cfma(w00, a0, t);
-                        t = cfma(w01, a1, t);
-                        t = cfma(w10, b0, t);
-                        t = cfma(w11, b1, t);
-                        acc[j][i] = t;
-                        a0 = b0;
-                        a1 = b1;
+            for (int p = 0; p < P; ++p) {
+                const int s = s0 + p;
+                if (s < S) {
+#pragma unroll
+                    for (int j = 0; j < GW; ++j) {
+                        if (act[j]) {
+                            const AS4 ShearEntry* sh = shear + eb[j] * S + s;
+                            const float w00 = sh->w00, w01 = sh->w01, w10 = sh->w10, w11 = sh->w11;
+                            const float2* L = buf + p * RE + (sh->oy - oymin) * RW + (sh->ox - oxmin) + lane;
+                            float2 a0 = L[0], a1 = L[1];
+#pragma unroll
+                            for (int i = 0; i < PPT; ++i) {
+                                const float2 b0 = L[(i + 1) * RW], b1 = L[(i + 1) * RW + 1];
+                                float2 t = acc[j][i];
+                                t = cfma(w00, a0, t);
+                                t = cfma(w01, a1, t);
+                                t = cfma(w10, b0, t);
+                                t = cfma(w11, b1, t);
+                                acc[j][i] = t;
+                                a0 = b0;
+                                a1 = b1;
+                            }
+                        }
                     }
                 }
             }
@@ -343,17 +458,20 @@ __global__ __launch_bounds__(kThreads) void k_rows(const KArgs a) {
             const int has0 = bd->has0, has1 = bd->has1;
             const float w0 = bd->w0, w1 = bd->w1;
             const float2* p1 = img + nn;
-            for (int i = threadIdx.x; i < rows * n; i += blockDim.x) {
+            for (int i = threadIdx.x; i < fb * n; i += blockDim.x) {
                 float2 v = make_float2(0.f, 0.f);
-                if (has0) v = cscale(img[base + i], w0);
-                if (has1) v = cfma(w1, p1[base + i], v);
+                if (i < rows * n) {
+                    if (has0) v = cscale(img[base + i], w0);
+                    if (has1) v = cfma(w1, p1[base + i], v);
+                }
                 A[i] = v;
             }
         } else {
-            for (int i = threadIdx.x; i < rows * n; i += blockDim.x) A[i] = img[base + i];
+            for (int i = threadIdx.x; i < fb * n; i += blockDim.x)
+                A[i] = i < rows * n ? img[base + i] : make_float2(0.f, 0.f);
         }
         __syncthreads();
-        lds_fft<DIR, false, 8>(A, tw, n, rows, n, 1, nstage, code);
+        fft_rows_any<DIR>(A, tw, n, nstage, code);
         for (int i = threadIdx.x; i < rows * n; i += blockDim.x) img[base + i] = A[i];
         __syncthreads();
     }
@@ -397,7 +515,7 @@ __global__ __launch_bounds__(kThreads) void k_cols(const KArgs a) {
             A[i] = c < cols ? src[(size_t)y * n + c0 + c] : make_float2(0.f, 0.f);
         }
         __syncthreads();
-        if (a.mode != COL_ADJOINT) lds_fft<-1, true, 16>(A, tw, n, cb, 1, cb, nstage, code);
+        if (a.mode != COL_ADJOINT) fft_cols_any<-1>(A, tw, n, nstage, code);
         const float sc = 1.0f / (float)n;
         const uint8_t* mk = DF(mask) + (size_t)b * nn;
         const float2* yy = DF(y);
@@ -431,7 +549,7 @@ __global__ __launch_bounds__(kThreads) void k_cols(const KArgs a) {
         }
         __syncthreads();
         if (a.mode != COL_FORWARD) {
-            lds_fft<1, true, 16>(A, tw, n, cb, 1, cb, nstage, code);
+            fft_cols_any<1>(A, tw, n, nstage, code);
             for (int i = threadIdx.x; i < n * cb; i += blockDim.x) {
                 const int y = i / cb, c = i - (i / cb) * cb;
                 if (c < cols) img[(size_t)y * n + c0 + c] = A[i];
@@ -484,6 +602,114 @@ __device__ __forceinline__ float2 shfl_down1(float2 v) {
     return make_float2(__shfl_down(v.x, 1), __shfl_down(v.y, 1));
 }
 
+// ------------------------------------------------------------------ optimiser update of a column
+
+struct UpdateArgs {
+    int n, S, T, kt, y0, x0, lane, sw, ns, opt;
+    float lr, beta1, beta2, aeps, tv_w, l1_w, eps2, inv_bc2s, step_size;
+};
+
+// Adds the TV/L1 gradient to the data gradient acc of one lane's voxels (bins sw ..
+// sw + ns - 1, rows y0 .. y0 + PPT - 1, column x0 + lane of knot kt) and applies Adam
+// or GD, reading Vin and writing Vout (distinct buffers, as are the moments). The lane
+// walks its bins with a register window of the previous, current and next bin (rows
+// y0 - 1 .. y0 + PPT, zero outside the grid); x neighbours come from adjacent lanes.
+// The pointers are restrict-qualified so the loads of later bins can be issued early.
+template <int SCM, int PPT>
+__device__ __forceinline__ void update_column(const float2 (&acc)[SCM][PPT], const float2* __restrict__ Vin,
+                                              float2* __restrict__ Vout, float2* __restrict__ Mm,
+                                              float2* __restrict__ Mv, const UpdateArgs& u) {
+    constexpr int WR = PPT + 2;
+    const int n = u.n, S = u.S;
+    const size_t nn = (size_t)n * n;
+    const int x = u.x0 + u.lane, xc = min(x, n - 1);
+    const size_t kbase = (size_t)u.kt * S * nn;
+    auto load_plane = [&](int s, float2 (&w)[WR]) {
+#pragma unroll
+        for (int r = 0; r < WR; ++r) {
+            const int y = u.y0 - 1 + r;
+            w[r] = make_float2(0.f, 0.f);
+            if (s >= 0 && s < S && y >= 0 && y < n) w[r] = Vin[kbase + ((size_t)s * n + y) * n + xc];
+        }
+    };
+    if (u.ns <= 0) return;
+    float2 pv[WR], cv[WR], nv[WR];
+    load_plane(u.sw - 1, pv);
+    load_plane(u.sw, cv);
+    load_plane(u.sw + 1, nv);
+#pragma unroll
+    for (int q = 0; q < SCM; ++q) {
+        if (q < u.ns) {
+            const int s = u.sw + q;
+            if (q > 0) {
+#pragma unroll
+                for (int r = 0; r < WR; ++r) {
+                    pv[r] = cv[r];
+                    cv[r] = nv[r];
+                }
+                load_plane(s + 1, nv);
+            }
+            // moments first, so their loads overlap the regulariser arithmetic
+            float2 mm[PPT], vv[PPT];
+#pragma unroll
+            for (int i = 0; i < PPT; ++i) {
+                const size_t idx = kbase + ((size_t)s * n + u.y0 + i) * n + xc;
+                mm[i] = make_float2(0.f, 0.f);
+                vv[i] = make_float2(0.f, 0.f);
+                if (u.opt == VP_OPT_ADAM && u.y0 + i < n) {
+                    mm[i] = Mm[idx];
+                    vv[i] = Mv[idx];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < PPT; ++i) {
+                const int y = u.y0 + i;
+                if (y < n) {
+                    const size_t idx = kbase + ((size_t)s * n + y) * n + xc;
+                    const float2 v0 = cv[i + 1];
+                    float2 left = shfl_up1(v0), right = shfl_down1(v0);
+                    if (u.lane == 0) left = u.x0 > 0 ? Vin[idx - 1] : make_float2(0.f, 0.f);
+                    if (u.lane == 63) right = u.x0 + 64 < n ? Vin[idx + 1] : make_float2(0.f, 0.f);
+                    float2 g = make_float2(0.f, 0.f);
+                    const float eps2 = u.eps2;
+                    if (u.tv_w != 0.f) {
+                        if (u.kt > 0) g = cadd(g, charb_w(csub(v0, Vin[idx - (size_t)S * nn]), eps2));
+                        if (u.kt + 1 < u.T) g = csub(g, charb_w(csub(Vin[idx + (size_t)S * nn], v0), eps2));
+                        if (s > 0) g = cadd(g, charb_w(csub(v0, pv[i + 1]), eps2));
+                        if (s + 1 < S) g = csub(g, charb_w(csub(nv[i + 1], v0), eps2));
+                        if (y > 0) g = cadd(g, charb_w(csub(v0, cv[i]), eps2));
+                        if (y + 1 < n) g = csub(g, charb_w(csub(cv[i + 2], v0), eps2));
+                        if (x > 0) g = cadd(g, charb_w(csub(v0, left), eps2));
+                        if (x + 1 < n) g = csub(g, charb_w(csub(right, v0), eps2));
+                        g = cscale(g, u.tv_w);
+                    }
+                    if (u.l1_w != 0.f) g = cfma(u.l1_w, charb_w(v0, eps2), g);
+                    const float2 gr = cadd(acc[q][i], g);
+                    if (x < n) {
+                        float2 nvx;
+                        if (u.opt == VP_OPT_ADAM) {
+                            float2 m = mm[i], v = vv[i];
+                            m.x = u.beta1 * m.x + (1.0f - u.beta1) * gr.x;
+                            m.y = u.beta1 * m.y + (1.0f - u.beta1) * gr.y;
+                            v.x = u.beta2 * v.x + (1.0f - u.beta2) * gr.x * gr.x;
+                            v.y = u.beta2 * v.y + (1.0f - u.beta2) * gr.y * gr.y;
+                            Mm[idx] = m;
+                            Mv[idx] = v;
+                            const float dx = sqrtf(v.x) * u.inv_bc2s + u.aeps;
+                            const float dy = sqrtf(v.y) * u.inv_bc2s + u.aeps;
+                            nvx = make_float2(v0.x - u.step_size * __fdividef(m.x, dx),
+                                              v0.y - u.step_size * __fdividef(m.y, dy));
+                        } else {
+                            nvx = make_float2(v0.x - u.lr * gr.x, v0.y - u.lr * gr.y);
+                        }
+                        Vout[idx] = nvx;
+                    }
+                }
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ adjoint gather + update
 //
 // G[k][s][y][x] = sum over the knot's blade parts e (plan order, blades ascending) of
@@ -497,10 +723,10 @@ __device__ __forceinline__ float2 shfl_down1(float2 v) {
 // window of the previous, current and next bin (rows y0-1 .. y0+kTileRows), taking
 // the x neighbours from the adjacent lanes.
 
-template <int MODE, int SE>
+template <int MODE, int SE, int P>
 __global__ __launch_bounds__(kThreads) void k_gather(const KArgs a) {
     extern __shared__ float2 sm[];
-    constexpr int PPT = kTileRows, SCM = kChunkMax, WR = PPT + 2;
+    constexpr int PPT = kTileRows, SCM = kChunkMax;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (int ti = blockIdx.x; ti < a.ntasks; ti += gridDim.x) {
@@ -531,44 +757,78 @@ __global__ __launch_bounds__(kThreads) void k_gather(const KArgs a) {
         for (int q = 0; q < SCM; ++q)
 #pragma unroll
             for (int i = 0; i < PPT; ++i) acc[q][i] = make_float2(0.f, 0.f);
-        Stager<SE> sg;
+        Stager<SE, P> sg;
         sg.init(RH, RW, y0 - koy - 1, x0 - kox - 1, n);
-        float2 pre[SE];
-        int e = e0;
-        while (e < e1 && !active_blade(sched, stepp, st, B, ent[e].blade)) ++e;
-        if (e < e1) sg.fetch(work + (size_t)ent[e].blade * nparts * nn, pre);
-        for (int it = 0; e < e1; ++it) {
-            const int b = ent[e].blade;
-            const float wb = ent[e].weight;
-            float2* buf = sm + (it & 1) * RE;
+        float2 pre[P][SE];
+        // the knot's active parts in plan order, P per phase: cur[] this phase, nxt[] the next
+        auto next_active = [&](int e) {
+            while (e < e1 && !active_blade(sched, stepp, st, B, ent[e].blade)) ++e;
+            return e;
+        };
+        int cur[P];
+        {
+            int e = e0;
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                e = next_active(e);
+                cur[p] = e;
+                if (e < e1) ++e;
+            }
+            const float2* planes[P];
+#pragma unroll
+            for (int p = 0; p < P; ++p) planes[p] = cur[p] < e1 ? work + (size_t)ent[cur[p]].blade * nparts * nn : nullptr;
+            if (cur[0] < e1) sg.fetch(planes, pre);
+        }
+        for (int it = 0; cur[0] < e1; ++it) {
+            float2* buf = sm + (it & 1) * P * RE;
             sg.store(buf, pre);
             __syncthreads();
-            int en = e + 1;
-            while (en < e1 && !active_blade(sched, stepp, st, B, ent[en].blade)) ++en;
-            if (en < e1) sg.fetch(work + (size_t)ent[en].blade * nparts * nn, pre);
-            const AS4 ShearEntry* shb = shear + (size_t)b * S + sw;
+            int nxt[P];
+            {
+                int e = cur[P - 1] < e1 ? cur[P - 1] + 1 : e1;
 #pragma unroll
-            for (int q = 0; q < SCM; ++q) {
-                if (q < ns) {
-                    const float w00 = shb[q].w00, w01 = shb[q].w01, w10 = shb[q].w10, w11 = shb[q].w11;
-                    // row of g[y - oy][.] for pixel row 0, column of g[.][x - ox]
-                    const float2* L = buf + (koy - shb[q].oy + 1) * RW + (kox - shb[q].ox + 1) + lane;
-                    float2 u0 = L[-RW], u1 = L[-RW - 1];
+                for (int p = 0; p < P; ++p) {
+                    e = next_active(e);
+                    nxt[p] = e;
+                    if (e < e1) ++e;
+                }
+                const float2* planes[P];
 #pragma unroll
-                    for (int i = 0; i < PPT; ++i) {
-                        const float2 v0 = L[i * RW], v1 = L[i * RW - 1];
-                        float2 t = make_float2(0.f, 0.f);
-                        t = cfma(w00, v0, t);
-                        t = cfma(w01, v1, t);
-                        t = cfma(w10, u0, t);
-                        t = cfma(w11, u1, t);
-                        acc[q][i] = cfma(wb, t, acc[q][i]);
-                        u0 = v0;
-                        u1 = v1;
+                for (int p = 0; p < P; ++p)
+                    planes[p] = nxt[p] < e1 ? work + (size_t)ent[nxt[p]].blade * nparts * nn : nullptr;
+                if (nxt[0] < e1) sg.fetch(planes, pre);
+            }
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                if (cur[p] < e1) {
+                    const int b = ent[cur[p]].blade;
+                    const float wb = ent[cur[p]].weight;
+                    const AS4 ShearEntry* shb = shear + (size_t)b * S + sw;
+#pragma unroll
+                    for (int q = 0; q < SCM; ++q) {
+                        if (q < ns) {
+                            const float w00 = shb[q].w00, w01 = shb[q].w01, w10 = shb[q].w10, w11 = shb[q].w11;
+                            // row of g[y - oy][.] for pixel row 0, column of g[.][x - ox]
+                            const float2* L = buf + p * RE + (koy - shb[q].oy + 1) * RW + (kox - shb[q].ox + 1) + lane;
+                            float2 u0 = L[-RW], u1 = L[-RW - 1];
+#pragma unroll
+                            for (int i = 0; i < PPT; ++i) {
+                                const float2 v0 = L[i * RW], v1 = L[i * RW - 1];
+                                float2 t = make_float2(0.f, 0.f);
+                                t = cfma(w00, v0, t);
+                                t = cfma(w01, v1, t);
+                                t = cfma(w10, u0, t);
+                                t = cfma(w11, u1, t);
+                                acc[q][i] = cfma(wb, t, acc[q][i]);
+                                u0 = v0;
+                                u1 = v1;
+                            }
+                        }
                     }
                 }
             }
-            e = en;
+#pragma unroll
+            for (int p = 0; p < P; ++p) cur[p] = nxt[p];
         }
         __syncthreads();
         const int x = x0 + lane;
@@ -605,81 +865,11 @@ __global__ __launch_bounds__(kThreads) void k_gather(const KArgs a) {
             const float bc1 = (float)(1.0 - pow((double)beta1, (double)t));
             const float inv_bc2s = (float)(1.0 / sqrt(1.0 - pow((double)beta2, (double)t)));
             const float step_size = lr / bc1;
-            const int xc = min(x, n - 1);
-            const size_t kbase = (size_t)kt * S * nn;
-            // window row r holds image row y0 - 1 + r of one bin, zero outside the grid
-            auto load_plane = [&](int s, float2 (&w)[WR]) {
-#pragma unroll
-                for (int r = 0; r < WR; ++r) {
-                    const int y = y0 - 1 + r;
-                    w[r] = make_float2(0.f, 0.f);
-                    if (s >= 0 && s < S && y >= 0 && y < n) w[r] = Vin[kbase + ((size_t)s * n + y) * n + xc];
-                }
-            };
-            float2 pv[WR], cv[WR], nv[WR];
-            if (ns > 0) {
-                load_plane(sw - 1, pv);
-                load_plane(sw, cv);
-                load_plane(sw + 1, nv);
-            }
-#pragma unroll
-            for (int q = 0; q < SCM; ++q) {
-                if (q < ns) {
-                    const int s = sw + q;
-                    if (q > 0) {
-#pragma unroll
-                        for (int r = 0; r < WR; ++r) {
-                            pv[r] = cv[r];
-                            cv[r] = nv[r];
-                        }
-                        load_plane(s + 1, nv);
-                    }
-#pragma unroll
-                    for (int i = 0; i < PPT; ++i) {
-                        const int y = y0 + i;
-                        if (y < n) {
-                            const size_t idx = kbase + ((size_t)s * n + y) * n + xc;
-                            const float2 v0 = cv[i + 1];
-                            float2 left = shfl_up1(v0), right = shfl_down1(v0);
-                            if (lane == 0) left = x0 > 0 ? Vin[idx - 1] : make_float2(0.f, 0.f);
-                            if (lane == 63) right = x0 + 64 < n ? Vin[idx + 1] : make_float2(0.f, 0.f);
-                            float2 g = make_float2(0.f, 0.f);
-                            if (tv_w != 0.f) {
-                                if (kt > 0) g = cadd(g, charb_w(csub(v0, Vin[idx - (size_t)S * nn]), eps2));
-                                if (kt + 1 < T) g = csub(g, charb_w(csub(Vin[idx + (size_t)S * nn], v0), eps2));
-                                if (s > 0) g = cadd(g, charb_w(csub(v0, pv[i + 1]), eps2));
-                                if (s + 1 < S) g = csub(g, charb_w(csub(nv[i + 1], v0), eps2));
-                                if (y > 0) g = cadd(g, charb_w(csub(v0, cv[i]), eps2));
-                                if (y + 1 < n) g = csub(g, charb_w(csub(cv[i + 2], v0), eps2));
-                                if (x > 0) g = cadd(g, charb_w(csub(v0, left), eps2));
-                                if (x + 1 < n) g = csub(g, charb_w(csub(right, v0), eps2));
-                                g = cscale(g, tv_w);
-                            }
-                            if (l1_w != 0.f) g = cfma(l1_w, charb_w(v0, eps2), g);
-                            const float2 gr = cadd(acc[q][i], g);
-                            if (x < n) {
-                                float2 nvx;
-                                if (opt == VP_OPT_ADAM) {
-                                    float2 m = Mm[idx], v = Mv[idx];
-                                    m.x = beta1 * m.x + (1.0f - beta1) * gr.x;
-                                    m.y = beta1 * m.y + (1.0f - beta1) * gr.y;
-                                    v.x = beta2 * v.x + (1.0f - beta2) * gr.x * gr.x;
-                                    v.y = beta2 * v.y + (1.0f - beta2) * gr.y * gr.y;
-                                    Mm[idx] = m;
-                                    Mv[idx] = v;
-                                    const float dx = sqrtf(v.x) * inv_bc2s + aeps;
-                                    const float dy = sqrtf(v.y) * inv_bc2s + aeps;
-                                    nvx = make_float2(v0.x - step_size * __fdividef(m.x, dx),
-                                                      v0.y - step_size * __fdividef(m.y, dy));
-                                } else {
-                                    nvx = make_float2(v0.x - lr * gr.x, v0.y - lr * gr.y);
-                                }
-                                Vout[idx] = nvx;
-                            }
-                        }
-                    }
-                }
-            }
+            UpdateArgs u;
+            u.n = n; u.S = S; u.T = T; u.kt = kt; u.y0 = y0; u.x0 = x0; u.lane = lane; u.sw = sw; u.ns = ns;
+            u.opt = opt; u.lr = lr; u.beta1 = beta1; u.beta2 = beta2; u.aeps = aeps;
+            u.tv_w = tv_w; u.l1_w = l1_w; u.eps2 = eps2; u.inv_bc2s = inv_bc2s; u.step_size = step_size;
+            update_column<SCM, PPT>(acc, Vin, Vout, Mm, Mv, u);
             unsigned* const sync = DF(sync);
             if (sync) {
                 // every work item of the slice read *step before finishing; the last one
@@ -801,19 +991,16 @@ __global__ __launch_bounds__(kThreads) void k_render(const KArgs a) {
 
 static inline int grid_for(int ntasks) { return ntasks < 1 ? 1 : (ntasks > (1 << 20) ? (1 << 20) : ntasks); }
 
-// Staging depth (region elements per thread) needed for a double-buffered LDS region.
-static inline int stage_depth(size_t lds_bytes) {
-    return lds_bytes <= 2 * 8 * kThreads * sizeof(float2) ? 8 : 16;
-}
-
-hipError_t launch_project(const KArgs& a, int gw, size_t lds, hipStream_t s) {
+hipError_t launch_project(const KArgs& a, int gw, int re, hipStream_t s) {
     if (a.ntasks <= 0) return hipSuccess;
     const dim3 g(grid_for(a.ntasks)), b(kThreads);
-    const bool deep = stage_depth(lds) > 8;
+    const int depth = stage_depth(re);
+    const size_t lds = stage_lds_bytes(re);
 #define P(GW)                                                                      \
     do {                                                                           \
-        if (deep) hipLaunchKernelGGL((k_project<GW, 16>), g, b, lds, s, a);         \
-        else hipLaunchKernelGGL((k_project<GW, 8>), g, b, lds, s, a);               \
+        if (depth == 5) hipLaunchKernelGGL((k_project<GW, 5, 3>), g, b, lds, s, a); \
+        else if (depth == 8) hipLaunchKernelGGL((k_project<GW, 8, 2>), g, b, lds, s, a); \
+        else hipLaunchKernelGGL((k_project<GW, 16, 1>), g, b, lds, s, a);           \
     } while (0)
     switch (gw) {
         case 1: P(1); break;
@@ -837,17 +1024,20 @@ hipError_t launch_cols(const KArgs& a, size_t lds, hipStream_t s) {
     hipLaunchKernelGGL(k_cols, dim3(grid_for(a.ntasks)), dim3(kThreads), lds, s, a);
     return hipGetLastError();
 }
-hipError_t launch_gather(const KArgs& a, int mode, size_t lds, hipStream_t s) {
+hipError_t launch_gather(const KArgs& a, int mode, int re, hipStream_t s) {
     if (a.ntasks <= 0) return hipSuccess;
     const dim3 g(grid_for(a.ntasks)), b(kThreads);
-    const bool deep = stage_depth(lds) > 8;
-    if (mode == GATHER_STEP) {
-        if (deep) hipLaunchKernelGGL((k_gather<GATHER_STEP, 16>), g, b, lds, s, a);
-        else hipLaunchKernelGGL((k_gather<GATHER_STEP, 8>), g, b, lds, s, a);
-    } else {
-        if (deep) hipLaunchKernelGGL((k_gather<GATHER_STORE, 16>), g, b, lds, s, a);
-        else hipLaunchKernelGGL((k_gather<GATHER_STORE, 8>), g, b, lds, s, a);
-    }
+    const int depth = stage_depth(re);
+    const size_t lds = stage_lds_bytes(re);
+#define G(MODE)                                                                      \
+    do {                                                                             \
+        if (depth == 5) hipLaunchKernelGGL((k_gather<MODE, 5, 3>), g, b, lds, s, a);  \
+        else if (depth == 8) hipLaunchKernelGGL((k_gather<MODE, 8, 2>), g, b, lds, s, a); \
+        else hipLaunchKernelGGL((k_gather<MODE, 16, 1>), g, b, lds, s, a);           \
+    } while (0)
+    if (mode == GATHER_STEP) G(GATHER_STEP);
+    else G(GATHER_STORE);
+#undef G
     return hipGetLastError();
 }
 hipError_t launch_tv_grad(const KArgs& a, hipStream_t s) {

@@ -255,17 +255,16 @@ extern "C" vp_status vp_plan_create(const vp_geometry* g, vp_plan** out) {
             p->tw[j] = make_float2((float)std::cos(ang), (float)std::sin(ang));
         }
 
-        // LDS sizes: double-buffered staging regions; FFT data plus the twiddle table
+        // staged region sizes (elements); FFT LDS: data plus the twiddle table
         for (const ProjGroup& gr : p->groups) {
-            const size_t rh = kTileRows + gr.oy_max - gr.oy_min + 1, rw = kTileW + gr.ox_max - gr.ox_min + 1;
-            p->lds_proj = std::max(p->lds_proj, 2 * rh * rw * sizeof(float2));
+            const int rh = kTileRows + gr.oy_max - gr.oy_min + 1, rw = kTileW + gr.ox_max - gr.ox_min + 1;
+            p->re_proj = std::max(p->re_proj, rh * rw);
         }
         for (const KnotInfo& ki : p->knots) {
-            const size_t rh = kTileRows + ki.oy_max - ki.oy_min + 1, rw = kTileW + ki.ox_max - ki.ox_min + 1;
-            p->lds_gath = std::max(p->lds_gath, 2 * rh * rw * sizeof(float2));
+            const int rh = kTileRows + ki.oy_max - ki.oy_min + 1, rw = kTileW + ki.ox_max - ki.ox_min + 1;
+            p->re_gath = std::max(p->re_gath, rh * rw);
         }
-        const size_t stage_cap = 2 * (size_t)kStageMax * kThreads * sizeof(float2);
-        if (p->lds_proj > stage_cap || p->lds_gath > stage_cap)
+        if (p->re_proj > kStageMax * kThreads || p->re_gath > kStageMax * kThreads)
             return fail(VP_ERR_UNSUPPORTED, "vp_plan_create: shear extents exceed the staging capacity");
         const int fb = fft_rows_per_item(n), cb = fft_cols_per_item(n);
         p->lds_rows = ((size_t)fb * n + n) * sizeof(float2);

@@ -61,7 +61,9 @@ struct vp_plan {
     // Work lists (slice index 0; batches rebase it).
     std::vector<vp::Task> t_proj, t_rows, t_cols, t_gath, t_vox, t_render;
     // Dynamic LDS bytes per kernel.
-    size_t lds_proj = 0, lds_gath = 0, lds_rows = 0, lds_cols = 0;
+    size_t lds_rows = 0, lds_cols = 0;
+    // Largest staged region (elements) of a projection / gather work item.
+    int re_proj = 0, re_gath = 0;
 
     mutable std::mutex mu;
     mutable std::map<int, std::unique_ptr<vp::DeviceTables>> dev;

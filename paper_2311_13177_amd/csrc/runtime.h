@@ -8,10 +8,11 @@
 namespace vp {
 
 // Kernel launchers (kernels.hip).
-hipError_t launch_project(const KArgs& a, int gw, size_t lds, hipStream_t s);
+// re: largest staged region (elements) over the work items' slices.
+hipError_t launch_project(const KArgs& a, int gw, int re, hipStream_t s);
 hipError_t launch_rows(const KArgs& a, int dir, size_t lds, hipStream_t s);
 hipError_t launch_cols(const KArgs& a, size_t lds, hipStream_t s);
-hipError_t launch_gather(const KArgs& a, int mode, size_t lds, hipStream_t s);
+hipError_t launch_gather(const KArgs& a, int mode, int re, hipStream_t s);
 hipError_t launch_tv_grad(const KArgs& a, hipStream_t s);
 hipError_t launch_reg_value(const KArgs& a, hipStream_t s);
 hipError_t launch_render(const KArgs& a, hipStream_t s);
@@ -26,7 +27,8 @@ struct StageLists {
     const Task* render = nullptr;
     int n_proj = 0, n_rows = 0, n_cols = 0, n_gath = 0, n_vox = 0, n_render = 0;
     int proj_gw = 1;
-    size_t lds_proj = 0, lds_rows = 0, lds_cols = 0, lds_gath = 0;
+    size_t lds_rows = 0, lds_cols = 0;
+    int re_proj = 0, re_gath = 0;  // largest staged regions (elements)
 };
 
 StageLists plan_lists(const vp_plan* p, const DeviceTables* t);

@@ -149,7 +149,7 @@ void launch_step(const KArgs& base, const StageLists& L, hipStream_t s, hipError
     } while (0)
     MARK(0);
     a.tasks = L.proj; a.ntasks = L.n_proj;
-    if ((e = launch_project(a, L.proj_gw, L.lds_proj, s)) != hipSuccess) { *err = e; return; }
+    if ((e = launch_project(a, L.proj_gw, L.re_proj, s)) != hipSuccess) { *err = e; return; }
     MARK(1);
     a.tasks = L.rows; a.ntasks = L.n_rows;
     if ((e = launch_rows(a, -1, L.lds_rows, s)) != hipSuccess) { *err = e; return; }
@@ -161,7 +161,7 @@ void launch_step(const KArgs& base, const StageLists& L, hipStream_t s, hipError
     if ((e = launch_rows(a, 1, L.lds_rows, s)) != hipSuccess) { *err = e; return; }
     MARK(4);
     a.tasks = L.gath; a.ntasks = L.n_gath;
-    if ((e = launch_gather(a, GATHER_STEP, L.lds_gath, s)) != hipSuccess) { *err = e; return; }
+    if ((e = launch_gather(a, GATHER_STEP, L.re_gath, s)) != hipSuccess) { *err = e; return; }
     MARK(5);
 #undef MARK
     *err = hipSuccess;
@@ -176,7 +176,7 @@ StageLists plan_lists(const vp_plan* p, const DeviceTables* t) {
     L.vox = t->t_vox; L.n_vox = (int)p->t_vox.size();
     L.render = t->t_render; L.n_render = (int)p->t_render.size();
     L.proj_gw = p->proj_gw;
-    L.lds_proj = p->lds_proj; L.lds_rows = p->lds_rows; L.lds_cols = p->lds_cols; L.lds_gath = p->lds_gath;
+    L.re_proj = p->re_proj; L.lds_rows = p->lds_rows; L.lds_cols = p->lds_cols; L.re_gath = p->re_gath;
     return L;
 }
 
@@ -233,7 +233,7 @@ extern "C" vp_status vp_forward(const vp_plan* p, const vp_c64* d_vol, const vp_
     const StageLists L = plan_lists(p, sc.t);
     hipError_t e;
     a.tasks = L.proj; a.ntasks = L.n_proj;
-    if ((e = launch_project(a, L.proj_gw, L.lds_proj, sc.s)) != hipSuccess) return hip_status(e, "vp_forward project");
+    if ((e = launch_project(a, L.proj_gw, L.re_proj, sc.s)) != hipSuccess) return hip_status(e, "vp_forward project");
     a.tasks = L.rows; a.ntasks = L.n_rows;
     if ((e = launch_rows(a, -1, L.lds_rows, sc.s)) != hipSuccess) return hip_status(e, "vp_forward rows");
     a.tasks = L.cols; a.ntasks = L.n_cols; a.mode = COL_FORWARD; a.out0 = (float2*)d_out;
@@ -260,7 +260,7 @@ extern "C" vp_status vp_adjoint(const vp_plan* p, const vp_c64* d_kres, vp_c64* 
     a.tasks = L.rows; a.ntasks = L.n_rows;
     if ((e = launch_rows(a, 1, L.lds_rows, sc.s)) != hipSuccess) return hip_status(e, "vp_adjoint rows");
     a.tasks = L.gath; a.ntasks = L.n_gath;
-    if ((e = launch_gather(a, GATHER_STORE, L.lds_gath, sc.s)) != hipSuccess) return hip_status(e, "vp_adjoint gather");
+    if ((e = launch_gather(a, GATHER_STORE, L.re_gath, sc.s)) != hipSuccess) return hip_status(e, "vp_adjoint gather");
     return VP_OK;
 }
 
@@ -438,7 +438,7 @@ vp_status session_objective(vp_session* s, double* objective, double* data_term)
     a.one.step_limit = 0x7fffffff;
     const StageLists& L = s->lists;
     a.tasks = L.proj; a.ntasks = L.n_proj;
-    if ((e = launch_project(a, L.proj_gw, L.lds_proj, s->stream)) != hipSuccess) return hip_status(e, "objective");
+    if ((e = launch_project(a, L.proj_gw, L.re_proj, s->stream)) != hipSuccess) return hip_status(e, "objective");
     a.tasks = L.rows; a.ntasks = L.n_rows;
     if ((e = launch_rows(a, -1, L.lds_rows, s->stream)) != hipSuccess) return hip_status(e, "objective");
     a.tasks = L.cols; a.ntasks = L.n_cols; a.mode = COL_STEP;

@@ -32,13 +32,26 @@ constexpr int kTileRows = 2;
 constexpr int kChunkMax = 8;
 // Staged region elements per thread (register prefetch depth of the LDS staging).
 constexpr int kStageMax = 16;
+// A staged region of re elements (re <= kStageMax * kThreads) is loaded several planes
+// (bins or blade images) per barrier phase so that many loads are in flight: three
+// planes of up to 5 elements per thread, two of up to 8, or one of up to 16. The LDS
+// holds two phases (double buffering).
+__host__ __device__ constexpr int stage_planes(int re) {
+    return re <= 5 * kThreads ? 3 : (re <= 8 * kThreads ? 2 : 1);
+}
+__host__ __device__ constexpr int stage_depth(int re) {
+    return re <= 5 * kThreads ? 5 : (re <= 8 * kThreads ? 8 : 16);
+}
+__host__ __device__ constexpr size_t stage_lds_bytes(int re) {
+    return 2 * (size_t)stage_planes(re) * (size_t)re * 8;
+}
 // Voxel-wise kernels (TV, render, objective): elements per work item.
 constexpr int kVoxItem = 4096;
 
 // Rows per row-FFT work item and columns per column-FFT work item, as functions of n
 // only (never of the batch), so every slice's arithmetic is the same alone or batched.
-__host__ __device__ inline int fft_rows_per_item(int n) { int r = 2048 / n; return r < 1 ? 1 : (r > 16 ? 16 : r); }
-__host__ __device__ inline int fft_cols_per_item(int n) { return n > 256 ? 8 : 16; }
+__host__ __device__ constexpr int fft_rows_per_item(int n) { return 2048 / n < 1 ? 1 : (2048 / n > 16 ? 16 : 2048 / n); }
+__host__ __device__ constexpr int fft_cols_per_item(int n) { return n > 256 ? 8 : 16; }
 
 struct ShearEntry {       // one (blade, bin): taps at rows y+oy(+1), columns x+ox(+1)
     int ox, oy;
