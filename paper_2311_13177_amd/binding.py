@@ -371,6 +371,61 @@ def vp_reconstruct(plan: Plan, kspace: np.ndarray, opts: Optional[vp_options] = 
     return dict(vol=vol, proj=outs[0], water=outs[1], fat=outs[2], final_loss=float(loss.value))
 
 
+class Server:
+    """Continuous-batching reconstruction server (vp_server_*)."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 8 << 30, max_slots: int = 64):
+        h = c_void_p()
+        check(lib().vp_server_create(int(device), int(hbm_budget), int(max_slots), byref(h)))
+        self.handle = h
+        self._plans = {}
+        self._opts = {}
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().vp_server_destroy(self.handle)
+        self.handle = None
+
+    __del__ = close
+
+    def submit(self, plan: Plan, kspace: np.ndarray, opts: Optional[vp_options] = None) -> int:
+        opts = opts if opts is not None else vp_options_default()
+        k = _host_c64(kspace, plan.blade_shape)
+        rid = c_uint64()
+        check(lib().vp_server_submit(self.handle, plan.handle, byref(opts), _hp(k), byref(rid)))
+        self._plans[rid.value] = plan
+        self._opts[rid.value] = opts
+        return int(rid.value)
+
+    def poll(self, rid: int) -> bool:
+        d = c_int32()
+        check(lib().vp_server_poll(self.handle, int(rid), byref(d)))
+        return bool(d.value)
+
+    def cancel(self, rid: int) -> None:
+        check(lib().vp_server_cancel(self.handle, int(rid)))
+
+    def wait(self, rid: int, timeout_us: int = -1, raise_on_error: bool = True) -> dict:
+        plan = self._plans[rid]
+        vol = np.empty(plan.volume_shape, np.complex64)
+        rend = [np.empty(plan.render_shape, np.complex64) for _ in range(3)]
+        res = vp_result(volume_out=vol.ctypes.data, proj_out=rend[0].ctypes.data, water_out=rend[1].ctypes.data,
+                        fat_out=rend[2].ctypes.data)
+        st = lib().vp_server_wait(self.handle, int(rid), int(timeout_us), byref(res))
+        if st != VP_ERR_TIMEOUT:
+            self._plans.pop(rid, None)
+            self._opts.pop(rid, None)
+        if st != VP_OK and raise_on_error:
+            check(st)
+        return dict(vol=vol, proj=rend[0], water=rend[1], fat=rend[2], final_loss=float(res.final_loss),
+                    steps_done=int(res.steps_done), status=int(st))
+
+    def stats(self) -> dict:
+        p50, p99, thr, done = c_double(), c_double(), c_double(), c_int64()
+        check(lib().vp_server_stats(self.handle, byref(p50), byref(p99), byref(thr), byref(done)))
+        return dict(p50_us=p50.value, p99_us=p99.value, throughput_rps=thr.value, completed=int(done.value))
+
+
 def vp_batch_reconstruct(plans: Sequence[Plan], kspaces: Sequence[np.ndarray],
                          opts: Sequence[vp_options]) -> list[dict]:
     n = len(plans)

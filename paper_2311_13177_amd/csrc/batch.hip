@@ -14,26 +14,23 @@
 
 namespace vp {
 
-// Device-resident group of slices sharing one stream: descriptors, concatenated work
-// lists and (optionally) a captured step.
-struct SliceGroup {
-    int device = -1;
-    hipStream_t stream = nullptr;
-    SliceDesc* d_descs = nullptr;
-    Task* d_tasks = nullptr;
-    StageLists lists{};
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    ~SliceGroup() {
-        if (gexec) (void)hipGraphExecDestroy(gexec);
-        if (graph) (void)hipGraphDestroy(graph);
-        if (d_descs) (void)hipFree(d_descs);
-        if (d_tasks) (void)hipFree(d_tasks);
-    }
-};
+SliceGroup::~SliceGroup() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (d_descs) (void)hipFree(d_descs);
+    if (d_tasks) (void)hipFree(d_tasks);
+}
+
+void SliceGroup::drop_graph() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+}
 
 // Builds descriptors and concatenated work lists for `sessions` (slice i = sessions[i]).
 vp_status group_build(SliceGroup* g, const std::vector<vp_session*>& sessions, const std::vector<int>& limits) {
+    g->drop_graph();
     const int ns = (int)sessions.size();
     std::vector<SliceDesc> descs(ns);
     std::vector<Task> proj, rows, cols, gath, vox, render;

@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "plan.h"
 
 namespace vp {
@@ -73,6 +75,26 @@ struct vp_session {
 };
 
 namespace vp {
+
+// Device-resident group of slices sharing one stream: descriptors, concatenated work
+// lists and (optionally) a captured step. Used by batched reconstructions and the server.
+struct SliceGroup {
+    int device = -1;
+    hipStream_t stream = nullptr;
+    SliceDesc* d_descs = nullptr;
+    Task* d_tasks = nullptr;
+    StageLists lists{};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    ~SliceGroup();
+    void drop_graph();
+};
+// Builds descriptors and concatenated work lists for `sessions` (slice i = sessions[i],
+// stopping at limits[i] steps); drops any captured graph.
+vp_status group_build(SliceGroup* g, const std::vector<vp_session*>& sessions, const std::vector<int>& limits);
+// Enqueues n_steps steps of every slice of the group (use_graph: capture one step once).
+vp_status group_run(SliceGroup* g, int n_steps, bool use_graph);
+
 vp_status session_alloc(const vp_plan* p, const vp_options* o, const vp_c64* kspace, const vp_c64* init,
                         hipStream_t stream, vp_session** out);
 vp_status session_run(vp_session* s, int32_t n_steps, int32_t use_graph);

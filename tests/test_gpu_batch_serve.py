@@ -1,0 +1,99 @@
+"""Batched and served reconstructions on the GPU.
+
+A slice's arithmetic never depends on the batch or the served mix it runs in, so every
+batched or served result must equal the one vp_reconstruct returns for that slice alone,
+bit for bit; the solo results themselves are checked against the oracle elsewhere.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from synth import configs
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    dict(n=48, n_spec=6, n_blades=4, lines=12),
+    dict(n=40, n_spec=5, n_time=3, n_blades=6, lines=8),
+    dict(n=80, n_spec=5, n_blades=3, lines=10, f=3.0),
+    dict(n=60, n_spec=3, n_blades=5, lines=7),
+    dict(n=64, n_spec=8, n_time=4, n_blades=10, lines=12, seed=11),
+]
+
+
+def _problems(B, steps):
+    out = []
+    for kw, st in zip(CASES, steps):
+        case = configs.small_case(**kw)
+        plan = B.Plan.from_geometry(case.geometry())
+        y = O.simulate_measurements(case)
+        out.append((case, plan, y, B.vp_options_default(n_steps=st)))
+    return out
+
+
+def _same(a, b):
+    return (np.array_equal(a["vol"], b["vol"]) and np.array_equal(a["proj"], b["proj"])
+            and np.array_equal(a["water"], b["water"]) and np.array_equal(a["fat"], b["fat"])
+            and a["final_loss"] == b["final_loss"])
+
+
+def test_served_results_equal_solo_results(gpu_lib):
+    from paper_2311_13177_amd import binding as B
+
+    probs = _problems(B, [9, 17, 4, 12, 23])
+    solo = [B.vp_reconstruct(p, y, o) for _, p, y, o in probs]
+    srv = B.Server(hbm_budget=4 << 30, max_slots=8)
+    ids = [srv.submit(p, y, o) for _, p, y, o in probs]
+    got = [srv.wait(i) for i in ids]
+    for g, s, (_, _, _, o) in zip(got, solo, probs):
+        assert g["status"] == 0 and g["steps_done"] == o.n_steps
+        assert _same(g, s)
+    st = srv.stats()
+    assert st["completed"] == len(probs) and st["p99_us"] >= st["p50_us"] > 0 and st["throughput_rps"] > 0
+    srv.close()
+
+
+def test_small_budget_queues_and_still_matches(gpu_lib):
+    from paper_2311_13177_amd import binding as B
+
+    probs = _problems(B, [6, 7, 5])
+    need = max(p.device_bytes(o) for _, p, _, o in probs)
+    srv = B.Server(hbm_budget=need, max_slots=8)
+    ids = [srv.submit(p, y, o) for _, p, y, o in probs]
+    # requests arriving while others run are admitted as memory frees up
+    late = _problems(B, [0, 0, 0, 8])[3]
+    ids.append(srv.submit(late[1], late[2], late[3]))
+    got = [srv.wait(i) for i in ids]
+    for g, (_, p, y, o) in zip(got, probs + [late]):
+        assert _same(g, B.vp_reconstruct(p, y, o))
+    srv.close()
+
+
+def test_server_errors_and_cancel(gpu_lib):
+    from paper_2311_13177_amd import binding as B
+
+    (_, plan, y, opts), = _problems(B, [40])[:1]
+    srv = B.Server(hbm_budget=plan.device_bytes(opts), max_slots=1)
+    tiny = B.Server(hbm_budget=1024, max_slots=1)
+    with pytest.raises(B.VPError) as ei:
+        tiny.submit(plan, y, opts)
+    assert ei.value.status == B.VP_ERR_BUDGET
+    tiny.close()
+    bad = y.copy()
+    bad[0, 0, 1] = np.inf
+    with pytest.raises(B.VPError) as ei:
+        srv.submit(plan, bad, opts)
+    assert ei.value.status == B.VP_ERR_NONFINITE
+    first = srv.submit(plan, y, B.vp_options_default(n_steps=400))
+    queued = srv.submit(plan, y, opts)     # the budget holds one request: this one waits
+    srv.cancel(queued)
+    r = srv.wait(queued, raise_on_error=False)
+    assert r["status"] == B.VP_ERR_CANCELLED
+    srv.cancel(first)
+    r = srv.wait(first, raise_on_error=False)
+    assert r["status"] in (B.VP_ERR_CANCELLED, B.VP_OK)
+    with pytest.raises(B.VPError) as ei:
+        srv.poll(first)
+    assert ei.value.status == B.VP_ERR_NOT_FOUND
+    srv.close()
