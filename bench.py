@@ -39,6 +39,12 @@ def parse_args(argv=None):
     ap.add_argument("--config", default="static_256", choices=["static_64", "static_256", "dynamic_192"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="approximate CPU oracle time budget")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain-loop leg")
+    ap.add_argument("--batch-slices", type=int, default=64)
+    ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-stream leg")
+    ap.add_argument("--serve-requests", type=int, default=32)
+    ap.add_argument("--serve-steps", type=int, nargs=2, default=[40, 80], metavar=("STATIC", "DYNAMIC"))
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
     return ap.parse_args(argv)
@@ -121,6 +127,94 @@ def cpu_baseline(case, budget_s):
     return {"value": case.n_blades * k / el, "unit": "blades/s", "cores": threads, "kind": "oracle",
             "sample": f"{k} full optimiser steps of {case.name} (each {case.n_blades} blade fwd+adj, "
                       f"TV, Adam) plus one objective evaluation, FP64 NumPy, {el:.1f} s"}
+
+
+def _slice_problem(case, B):
+    plan = B.Plan.from_geometry(case.geometry())
+    y = gpu_measurements(case, plan, B)
+    return plan, y
+
+
+def batched_leg(B, n_slices, steps):
+    """64 independent slices: one-slice-at-a-time loop vs one batched, graph-captured run."""
+    import numpy as np
+    import torch
+
+    from synth import configs
+
+    cases = [configs.batch_slice(j) for j in range(n_slices)]
+    probs = [_slice_problem(c, B) for c in cases]
+    opts = [B.vp_options_default(n_steps=steps, tv_weight=c.tv_weight, lr=c.lr) for c in cases]
+    # warm both paths on the first slice (tables uploaded, kernels loaded)
+    B.vp_reconstruct(probs[0][0], probs[0][1], B.vp_options_default(n_steps=2))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solo = [B.vp_reconstruct(p, y, o) for (p, y), o in zip(probs, opts)]
+    t_plain = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    batch = B.vp_batch_reconstruct([p for p, _ in probs], [y for _, y in probs], opts)
+    t_batch = time.perf_counter() - t0
+    same = all(np.array_equal(a["vol"], b["vol"]) for a, b in zip(solo, batch))
+    blades = sum(c.n_blades for c in cases) * steps
+    voxels = sum(c.n_spec * c.n * c.n for c in cases)
+    return {"workload": f"{n_slices} static slices, n in {{128,192,256}}, S in {{16,32}}, 8-16 blades, "
+                        f"{steps} Adam steps each (seeds 4000+j)",
+            "voxels": voxels, "plain_loop_s": round(t_plain, 4), "batched_s": round(t_batch, 4),
+            "speedup_vs_plain_loop": round(t_plain / t_batch, 3),
+            "blades_per_s_batched": round(blades / t_batch, 1), "blades_per_s_plain_loop": round(blades / t_plain, 1),
+            "batched_equals_solo_bitwise": bool(same)}
+
+
+def served_leg(B, n_req, steps_static, steps_dynamic, seed=5000, slots=8):
+    """A Poisson request stream of mixed static/dynamic reconstructions through the server."""
+    import numpy as np
+    import torch
+
+    from synth import configs
+
+    cases = [configs.serving_request(i, seed) for i in range(n_req)]
+    probs = [_slice_problem(c, B) for c in cases]
+    opts = [B.vp_options_default(n_steps=steps_static if c.n_time == 1 else steps_dynamic,
+                                 tv_weight=c.tv_weight, lr=c.lr) for c in cases]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solo = [B.vp_reconstruct(p, y, o) for (p, y), o in zip(probs, opts)]
+    t_plain = time.perf_counter() - t0
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(0.8 * free)
+    # closed loop: everything submitted at once gives the server's capacity
+    srv = B.Server(device=0, hbm_budget=budget, max_slots=slots)
+    t0 = time.perf_counter()
+    ids = [srv.submit(p, y, o) for (p, y), o in zip(probs, opts)]
+    closed = [srv.wait(i) for i in ids]
+    t_closed = time.perf_counter() - t0
+    srv.close()
+    capacity = n_req / t_closed
+    rate = 0.7 * capacity
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=n_req)
+    srv = B.Server(device=0, hbm_budget=budget, max_slots=slots)
+    t0 = time.perf_counter()
+    ids = []
+    for k, ((p, y), o) in enumerate(zip(probs, opts)):
+        target = t0 + float(np.sum(gaps[:k + 1]))
+        now = time.perf_counter()
+        if target > now:
+            time.sleep(target - now)
+        ids.append(srv.submit(p, y, o))
+    served = [srv.wait(i) for i in ids]
+    t_open = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    same = all(np.array_equal(a["vol"], b["vol"]) and a["final_loss"] == b["final_loss"]
+               for a, b in zip(solo, served)) and all(np.array_equal(a["vol"], b["vol"]) for a, b in zip(solo, closed))
+    return {"workload": f"{n_req} requests (seeds {seed}+i): n 128-384, S 16-64, 8-32 blades, T in {{1,8,16}}; "
+                        f"{steps_static} steps static / {steps_dynamic} dynamic",
+            "plain_loop_s": round(t_plain, 3), "plain_loop_rps": round(n_req / t_plain, 3),
+            "closed_loop_rps": round(capacity, 3), "arrival_rate_rps": round(rate, 3),
+            "open_loop_s": round(t_open, 3), "p50_ms": round(st["p50_us"] / 1e3, 2),
+            "p99_ms": round(st["p99_us"] / 1e3, 2), "served_rps": round(st["throughput_rps"], 3),
+            "served_equals_solo_bitwise": bool(same), "max_slots": slots}
 
 
 def copy_probe():
@@ -232,6 +326,10 @@ def main(argv=None):
         "step_hbm_bytes_algorithmic": int(sum(stage_bytes.values())),
         "roofline": roof,
     }
+    if not args.no_batch:
+        out["batched"] = batched_leg(B, args.batch_slices, args.batch_steps)
+    if not args.no_serve:
+        out["served"] = served_leg(B, args.serve_requests, args.serve_steps[0], args.serve_steps[1])
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
     print(json.dumps(out))

@@ -1,13 +1,16 @@
 // Reconstruction server: continuous batching of requests of mixed sizes on one device.
 //
-// A worker thread owns the device. Between super-steps it retires finished requests
-// (objective, renders and volume copied to host, device state freed), drops cancelled
-// ones and admits queued requests in arrival order while the sum of their device bytes
-// stays within the budget and a slot is free. Every admitted request keeps its volume
-// and optimiser state resident; a super-step advances all of them together with one
-// launch per stage over the concatenated work lists (each request stops at its own
-// step count). A request's arithmetic does not depend on the mix it runs in, so its
-// result equals the one vp_reconstruct computes for it alone.
+// A worker thread owns the batched stepping. Each iteration it launches one super-step
+// (up to kSuperSteps optimiser steps for every resident request, one launch per stage
+// over the concatenated work lists, each request stopping at its own step count) and,
+// while that runs on the device, finalises requests that completed in the previous
+// super-step (objective on the request's own stream) and uploads newly admitted ones
+// (admission in arrival order while the sum of device bytes stays within the budget
+// and a slot is free). Requests join and leave only at super-step boundaries. A
+// finished request keeps its device state until vp_server_wait copies the volume and
+// renders straight into the caller's buffers on the caller's thread and releases it.
+// A request's arithmetic does not depend on the mix it runs in, so its result equals
+// the one vp_reconstruct computes for it alone.
 
 #include <algorithm>
 #include <chrono>
@@ -31,7 +34,7 @@ using Clock = std::chrono::steady_clock;
 // Steps per super-step: requests join and leave only at super-step boundaries.
 constexpr int kSuperSteps = 8;
 
-enum class RState { Queued, Running, Done };
+enum class RState { Queued, Running, Done, Spilling, Collecting };
 
 struct Request {
     uint64_t id = 0;
@@ -44,9 +47,10 @@ struct Request {
     vp_status status = VP_OK;
     double final_loss = 0.0;
     int64_t steps_done = 0;
-    std::vector<vp_c64> vol, proj, water, fat;
     Clock::time_point t_submit, t_done;
     std::unique_ptr<vp_session> session;
+    // results moved to host when the device memory was needed before collection
+    std::vector<vp_c64> h_vol, h_proj, h_water, h_fat;
 };
 
 }  // namespace
@@ -63,56 +67,53 @@ struct vp_server {
     std::deque<uint64_t> queue;
     std::map<uint64_t, std::unique_ptr<Request>> reqs;
     uint64_t next_id = 1;
-    uint64_t used = 0;
+    uint64_t used = 0;     // device bytes of admitted requests not yet collected by wait
     bool stop = false;
     std::vector<double> latencies_us;
     Clock::time_point t_first_submit{}, t_last_done{};
     bool any_submit = false;
     std::thread worker;
     void run();
+    void mark_done(Request* r, vp_status st, bool count);
 };
 
-namespace {
-
-// Copies a finished session's results into the request (worker thread, no lock held).
-void finish_request(Request* r) {
-    vp_session* s = r->session.get();
-    const vp_plan* p = r->plan;
-    double obj = 0.0;
-    vp_status st = session_objective(s, &obj, nullptr);
-    r->final_loss = obj;
-    try {
-        r->vol.resize(p->voxels());
-        const size_t rn = (size_t)p->T * p->n * p->n;
-        r->proj.resize(rn);
-        r->water.resize(rn);
-        r->fat.resize(rn);
-    } catch (const std::bad_alloc&) {
-        st = fail(VP_ERR_NOMEM, "server: out of host memory for results");
-    }
-    if (st == VP_OK || st == VP_ERR_NONFINITE) {
-        const vp_status rs = session_read(s, r->vol.data(), r->proj.data(), r->water.data(), r->fat.data());
-        if (st == VP_OK) st = rs;
-    }
+// Worker thread only; takes the lock.
+void vp_server::mark_done(Request* r, vp_status st, bool count) {
+    std::lock_guard<std::mutex> lk(mu);
     r->status = st;
-    r->steps_done = r->opts.n_steps;
+    r->state = RState::Done;
+    r->t_done = Clock::now();
+    if (!r->session) used -= r->bytes;  // nothing left on the device to collect
+    if (count) {
+        latencies_us.push_back(std::chrono::duration<double, std::micro>(r->t_done - r->t_submit).count());
+        t_last_done = r->t_done;
+    }
+    cv_done.notify_all();
 }
-
-}  // namespace
 
 void vp_server::run() {
     (void)hipSetDevice(device);
     SliceGroup g;
     g.device = device;
     if (hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking) != hipSuccess) g.stream = nullptr;
-    std::vector<Request*> active;
+    std::vector<Request*> active;     // resident and stepping
+    std::vector<Request*> to_finish;  // stepped to completion, objective not yet computed
     bool dirty = false;
     for (;;) {
-        std::vector<Request*> admit;
-        std::vector<Request*> dropped;
+        std::vector<Request*> admit, dropped, spill;
         {
             std::unique_lock<std::mutex> lk(mu);
-            // cancelled running requests leave at this boundary
+            // a finished request holds its device memory until collected; if the queue
+            // head does not fit, move uncollected results to host to make room
+            if (!stop && !queue.empty() && used + reqs[queue.front()]->bytes > budget) {
+                for (auto& kv : reqs) {
+                    Request* r = kv.second.get();
+                    if (r->state == RState::Done && r->session) {
+                        r->state = RState::Spilling;
+                        spill.push_back(r);
+                    }
+                }
+            }
             for (auto it = active.begin(); it != active.end();) {
                 if ((*it)->cancel) {
                     dropped.push_back(*it);
@@ -122,7 +123,6 @@ void vp_server::run() {
                     ++it;
                 }
             }
-            // admission: arrival order, memory budget, free slots
             while (!stop && !queue.empty() && (int)(active.size() + admit.size()) < max_slots) {
                 Request* r = reqs[queue.front()].get();
                 if (used + r->bytes > budget) break;
@@ -131,110 +131,108 @@ void vp_server::run() {
                 r->state = RState::Running;
                 admit.push_back(r);
             }
-            if (active.empty() && admit.empty() && dropped.empty()) {
+            if (active.empty() && admit.empty() && dropped.empty() && to_finish.empty() && spill.empty()) {
                 if (stop) break;
                 cv_work.wait(lk);
                 continue;
             }
         }
-        for (Request* r : dropped) {
+        for (Request* r : spill) {
+            const vp_plan* p = r->plan;
+            vp_status ss = VP_OK;
+            try {
+                const size_t rn = (size_t)p->T * p->n * p->n;
+                r->h_vol.resize(p->voxels());
+                r->h_proj.resize(rn);
+                r->h_water.resize(rn);
+                r->h_fat.resize(rn);
+            } catch (const std::bad_alloc&) {
+                ss = fail(VP_ERR_NOMEM, "server: out of host memory for results");
+            }
+            if (ss == VP_OK)
+                ss = session_read(r->session.get(), r->h_vol.data(), r->h_proj.data(), r->h_water.data(),
+                                  r->h_fat.data());
             r->session.reset();
             std::lock_guard<std::mutex> lk(mu);
             used -= r->bytes;
-            r->status = VP_ERR_CANCELLED;
+            if (r->status == VP_OK) r->status = ss;
             r->state = RState::Done;
-            r->t_done = Clock::now();
             cv_done.notify_all();
         }
+        for (Request* r : dropped) {
+            r->session.reset();
+            mark_done(r, VP_ERR_CANCELLED, false);
+        }
+        // launch the next super-step first, so the host work below overlaps it
+        std::vector<Request*> stepping;
+        int64_t k = 0;
+        vp_status st = g.stream ? VP_OK : fail(VP_ERR_DEVICE, "server: no stream");
+        if (!active.empty() && st == VP_OK) {
+            if (dirty) {
+                std::vector<vp_session*> sess;
+                std::vector<int> limits;
+                for (Request* r : active) {
+                    sess.push_back(r->session.get());
+                    limits.push_back(r->opts.n_steps);
+                }
+                st = group_build(&g, sess, limits);
+                dirty = false;
+            }
+            if (st == VP_OK) {
+                k = kSuperSteps;
+                for (Request* r : active) k = std::min<int64_t>(k, r->opts.n_steps - r->session->steps_done);
+                k = std::max<int64_t>(k, 1);
+                st = group_run(&g, (int)k, false);
+            }
+            stepping = active;
+        }
+        // finalise the requests completed by the previous super-step (own streams)
+        for (Request* r : to_finish) {
+            double obj = 0.0;
+            const vp_status fs = session_objective(r->session.get(), &obj, nullptr);
+            r->final_loss = obj;
+            r->steps_done = r->session->steps_done;
+            mark_done(r, fs, true);
+        }
+        to_finish.clear();
+        // upload newly admitted requests (own streams); they join the next super-step
         for (Request* r : admit) {
             vp_session* s = nullptr;
-            vp_status st = g.stream ? session_alloc(r->plan, &r->opts, r->kspace.data(), nullptr, g.stream, &s)
-                                    : fail(VP_ERR_DEVICE, "server: no stream");
+            const vp_status as = session_alloc(r->plan, &r->opts, r->kspace.data(), nullptr, nullptr, &s);
             std::vector<vp_c64>().swap(r->kspace);
-            if (st != VP_OK) {
-                std::lock_guard<std::mutex> lk(mu);
-                used -= r->bytes;
-                r->status = st;
-                r->state = RState::Done;
-                r->t_done = Clock::now();
-                cv_done.notify_all();
+            if (as != VP_OK) {
+                mark_done(r, as, false);
                 continue;
             }
             r->session.reset(s);
             if (r->opts.n_steps == 0) {
-                finish_request(r);
-                std::lock_guard<std::mutex> lk(mu);
-                r->session.reset();
-                used -= r->bytes;
-                r->state = RState::Done;
-                r->t_done = Clock::now();
-                latencies_us.push_back(std::chrono::duration<double, std::micro>(r->t_done - r->t_submit).count());
-                t_last_done = r->t_done;
-                cv_done.notify_all();
+                to_finish.push_back(r);
                 continue;
             }
             active.push_back(r);
             dirty = true;
         }
-        if (active.empty()) continue;
-        if (dirty) {
-            std::vector<vp_session*> sess;
-            std::vector<int> limits;
-            for (Request* r : active) {
-                sess.push_back(r->session.get());
-                limits.push_back(r->opts.n_steps);
-            }
-            vp_status st = group_build(&g, sess, limits);
-            if (st != VP_OK) {
-                std::lock_guard<std::mutex> lk(mu);
-                for (Request* r : active) {
-                    r->session.reset();
-                    used -= r->bytes;
-                    r->status = st;
-                    r->state = RState::Done;
-                    r->t_done = Clock::now();
-                }
-                active.clear();
-                cv_done.notify_all();
-                continue;
-            }
-            dirty = false;
-        }
-        // one super-step: advance every resident request by up to kSuperSteps steps
-        int64_t k = kSuperSteps;
-        for (Request* r : active) k = std::min<int64_t>(k, r->opts.n_steps - r->session->steps_done);
-        k = std::max<int64_t>(k, 1);
-        vp_status st = group_run(&g, (int)k, false);
+        if (stepping.empty()) continue;
         if (st == VP_OK) st = hip_status(hipStreamSynchronize(g.stream), "server super-step");
-        std::vector<Request*> finished;
-        for (auto it = active.begin(); it != active.end();) {
-            Request* r = *it;
+        for (Request* r : stepping) {
             r->session->steps_done = std::min<int64_t>(r->opts.n_steps, r->session->steps_done + k);
             if (st != VP_OK || r->session->steps_done >= r->opts.n_steps) {
-                finished.push_back(r);
-                it = active.erase(it);
+                active.erase(std::find(active.begin(), active.end(), r));
                 dirty = true;
-            } else {
-                ++it;
+                if (st != VP_OK) {
+                    r->session.reset();
+                    mark_done(r, st, false);
+                } else {
+                    to_finish.push_back(r);
+                }
             }
-        }
-        for (Request* r : finished) {
-            if (st == VP_OK) finish_request(r);
-            else r->status = st;
-            r->session.reset();
-            std::lock_guard<std::mutex> lk(mu);
-            used -= r->bytes;
-            r->state = RState::Done;
-            r->t_done = Clock::now();
-            latencies_us.push_back(std::chrono::duration<double, std::micro>(r->t_done - r->t_submit).count());
-            t_last_done = r->t_done;
-            cv_done.notify_all();
         }
     }
     // shutdown: everything still queued or running is cancelled
     std::lock_guard<std::mutex> lk(mu);
     for (Request* r : active) {
         r->session.reset();
+        used -= r->bytes;
         r->status = VP_ERR_CANCELLED;
         r->state = RState::Done;
     }
@@ -314,7 +312,8 @@ extern "C" vp_status vp_server_wait(vp_server* s, uint64_t id, int64_t timeout_u
     if (!s) return fail(VP_ERR_ARG, "vp_server_wait: NULL server");
     std::unique_lock<std::mutex> lk(s->mu);
     auto it = s->reqs.find(id);
-    if (it == s->reqs.end()) return fail(VP_ERR_NOT_FOUND, "vp_server_wait: unknown request %llu", (unsigned long long)id);
+    if (it == s->reqs.end() || it->second->state == RState::Collecting)
+        return fail(VP_ERR_NOT_FOUND, "vp_server_wait: unknown request %llu", (unsigned long long)id);
     Request* r = it->second.get();
     auto done = [r] { return r->state == RState::Done; };
     if (timeout_us < 0) {
@@ -322,22 +321,35 @@ extern "C" vp_status vp_server_wait(vp_server* s, uint64_t id, int64_t timeout_u
     } else if (!s->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), done)) {
         return fail(VP_ERR_TIMEOUT, "vp_server_wait: request %llu still running", (unsigned long long)id);
     }
-    const vp_status st = r->status;
-    if (result) {
+    r->state = RState::Collecting;
+    std::unique_ptr<vp_session> sess = std::move(r->session);
+    vp_status st = r->status;
+    lk.unlock();
+    // device -> caller buffers on this thread (the request's own stream), then release
+    if (sess && result && st == VP_OK)
+        st = session_read(sess.get(), result->volume_out, result->proj_out, result->water_out, result->fat_out);
+    if (!sess && result && st == VP_OK && !r->h_vol.empty()) {
         auto copy = [](vp_c64* dst, const std::vector<vp_c64>& src) {
-            if (dst && !src.empty()) std::copy(src.begin(), src.end(), dst);
+            if (dst) std::copy(src.begin(), src.end(), dst);
         };
-        copy(result->volume_out, r->vol);
-        copy(result->proj_out, r->proj);
-        copy(result->water_out, r->water);
-        copy(result->fat_out, r->fat);
+        copy(result->volume_out, r->h_vol);
+        copy(result->proj_out, r->h_proj);
+        copy(result->water_out, r->h_water);
+        copy(result->fat_out, r->h_fat);
+    }
+    const bool held = (bool)sess;
+    sess.reset();
+    lk.lock();
+    if (result) {
         result->final_loss = r->final_loss;
         result->steps_done = r->steps_done;
         result->status = st;
     }
-    s->reqs.erase(it);
-    if (st != VP_OK) return fail(st, "vp_server_wait: request %llu failed (%s)", (unsigned long long)id,
-                                 vp_status_string(st));
+    if (held) s->used -= r->bytes;
+    s->reqs.erase(id);
+    s->cv_work.notify_one();
+    if (st != VP_OK)
+        return fail(st, "vp_server_wait: request %llu failed (%s)", (unsigned long long)id, vp_status_string(st));
     return VP_OK;
 }
 
@@ -347,7 +359,7 @@ extern "C" vp_status vp_server_poll(vp_server* s, uint64_t id, int32_t* done) {
     std::lock_guard<std::mutex> lk(s->mu);
     auto it = s->reqs.find(id);
     if (it == s->reqs.end()) return fail(VP_ERR_NOT_FOUND, "vp_server_poll: unknown request");
-    *done = it->second->state == RState::Done;
+    *done = it->second->state == RState::Done || it->second->state == RState::Collecting;
     return VP_OK;
 }
 
@@ -403,6 +415,7 @@ extern "C" vp_status vp_server_destroy(vp_server* s) {
         s->cv_work.notify_all();
     }
     if (s->worker.joinable()) s->worker.join();
+    (void)hipSetDevice(s->device);
     delete s;
     return VP_OK;
 }

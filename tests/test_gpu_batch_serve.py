@@ -67,6 +67,13 @@ def test_small_budget_queues_and_still_matches(gpu_lib):
     got = [srv.wait(i) for i in ids]
     for g, (_, p, y, o) in zip(got, probs + [late]):
         assert _same(g, B.vp_reconstruct(p, y, o))
+    # collected out of order: the finished first request is moved to host to make room
+    a = srv.submit(probs[0][1], probs[0][2], probs[0][3])
+    b = srv.submit(probs[1][1], probs[1][2], probs[1][3])
+    gb = srv.wait(b)
+    ga = srv.wait(a)
+    assert _same(ga, B.vp_reconstruct(probs[0][1], probs[0][2], probs[0][3]))
+    assert _same(gb, B.vp_reconstruct(probs[1][1], probs[1][2], probs[1][3]))
     srv.close()
 
 
