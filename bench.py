@@ -230,8 +230,9 @@ def copy_probe():
     print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "launches": 5}))
 
 
-def counters_for(kernel_name):
-    """HBM traffic per launch from a committed counter summary, if still current."""
+def counters_for(workload, kernel_name):
+    """HBM bytes per launch (scaled FETCH_SIZE + WRITE_SIZE) from the committed counter
+    summary of this workload, or None once the kernel source has changed since."""
     path = os.path.join(ROOT, "profiles", "counters.json")
     if not os.path.exists(path):
         return None
@@ -239,7 +240,7 @@ def counters_for(kernel_name):
         data = json.load(fh)
     src = os.path.join(ROOT, "paper_2311_13177_amd", "csrc", "kernels.hip")
     digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    entry = data.get(kernel_name)
+    entry = data.get(f"{workload}/{kernel_name}")
     if not entry or entry.get("kernels_sha") != digest:
         return None
     return entry.get("bytes_per_launch")
@@ -300,7 +301,7 @@ def main(argv=None):
         ach = bytes_l / dur_s / 1e9
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4)}
-    roof["traffic"] = counters_for(kernel_names[dom])
+    roof["traffic"] = counters_for(case.name, kernel_names[dom])
     roof["kernel"] = kernel_names[dom]
     roof["kernel_ms"] = round(stages[dom], 5)
     roof["algorithmic_bytes_per_launch"] = bytes_l
