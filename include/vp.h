@@ -104,6 +104,24 @@ enum { VP_SCHED_ALL_BLADES = 0, VP_SCHED_CYCLIC = 1 };
  * all blades (VP_SCHED_ALL_BLADES) or over blade (t-1) mod B only
  * (VP_SCHED_CYCLIC, the paper's one-blade-per-iteration schedule). The volume
  * starts at zero unless an initial volume is given. split_bin < 0 means S/2. */
+/* Tile shape of the projection, gather and update kernels: how the work is cut
+ * into work items, never what is computed (every shape gives the same results bit
+ * for bit). proj_rows: rows of a projection tile, in {1, 2, 4, 8}; proj_parts:
+ * blade parts per wave of a projection item, in {1, 2, 4, 8}, with proj_rows *
+ * proj_parts <= 16; gath_rows: rows of a gather tile, in {2, 4}; gath_bins:
+ * spectral bins per wave of a gather item, in {1, 2, 4, 8}, with gath_rows *
+ * gath_bins <= 16; upd_bins: 0 runs the regulariser and optimiser update inside
+ * the gather kernel, 2, 4 or 8 runs it as a separate pass (that many bins per
+ * wave) over a stored data gradient (one more volume-sized device buffer). A tile
+ * is 64 columns wide. */
+typedef struct {
+    int32_t proj_rows;
+    int32_t proj_parts;
+    int32_t gath_rows;
+    int32_t gath_bins;
+    int32_t upd_bins;
+} vp_tiles;
+
 typedef struct {
     float tv_weight;
     float l1_weight;
@@ -117,11 +135,17 @@ typedef struct {
     int32_t schedule;
     int32_t split_bin;
     int32_t device;
+    /* Tile shape. All fields 0: the shape recorded by vp_plan_tune for a plan of
+     * the same sizes on this device if there is one, else (autotune != 0) tune now
+     * and record it, else the plan's built-in choice. Otherwise the shape given,
+     * which must be valid for the plan (VP_ERR_UNSUPPORTED if not). */
+    vp_tiles tiles;
+    int32_t autotune;
 } vp_options;
 
 /* Fills defaults: tv_weight 1e-3, l1_weight 0, tv_eps 1e-3, n_steps 200, Adam
  * with lr 1e-2, betas (0.9, 0.999), eps 1e-8, all-blades schedule, split S/2,
- * device 0. */
+ * device 0, automatic tile shape without tuning. */
 vp_status vp_options_default(vp_options* opts);
 
 /* Static description of a status code; never NULL. */
@@ -164,6 +188,24 @@ vp_status vp_plan_knot(const vp_plan* plan, int32_t b, int32_t* knot, float* alp
  * options (volume ping-pong, Adam moments, blade work images, measurements,
  * tables, partial sums). Used for admission by memory budget. */
 vp_status vp_plan_device_bytes(const vp_plan* plan, const vp_options* opts, uint64_t* bytes);
+
+/* Autotuner: times every compiled tile shape that fits the plan on opts->device
+ * (projection launches per projection shape; the fused gather/update per gather
+ * shape; the gather that stores the data gradient per gather shape and the
+ * separate update pass per update shape; a few repetitions each, on a scratch
+ * reconstruction state with zero measurements; the optimiser and regulariser
+ * settings of opts select the update that is timed),
+ * records the fastest shape for plans of the same sizes, shear extents and
+ * optimiser in a process-wide table and returns it. Sessions, reconstructions,
+ * batches and operators created later pick it up (vp_options.tiles all zero).
+ * Allocates about vp_plan_device_bytes on the device for the duration of the call.
+ * Errors: VP_ERR_ARG for NULL arguments or bad options, VP_ERR_NOMEM,
+ * VP_ERR_DEVICE. */
+vp_status vp_plan_tune(const vp_plan* plan, const vp_options* opts, vp_tiles* out);
+
+/* The tile shape a session created with `opts` would use now (no measuring unless
+ * opts->autotune asks for it and no shape is recorded yet). */
+vp_status vp_plan_tiles(const vp_plan* plan, const vp_options* opts, vp_tiles* out);
 
 /* ------------------------------------------------------------------ operators (device pointers) */
 

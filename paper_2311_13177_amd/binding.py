@@ -48,10 +48,19 @@ class vp_geometry(ctypes.Structure):
                 ("blade_time", POINTER(c_double)), ("spec_shift_px", POINTER(c_double))]
 
 
+class vp_tiles(ctypes.Structure):
+    _fields_ = [("proj_rows", c_int32), ("proj_parts", c_int32), ("gath_rows", c_int32), ("gath_bins", c_int32),
+                ("upd_bins", c_int32)]
+
+    def as_tuple(self):
+        return (self.proj_rows, self.proj_parts, self.gath_rows, self.gath_bins, self.upd_bins)
+
+
 class vp_options(ctypes.Structure):
     _fields_ = [("tv_weight", c_float), ("l1_weight", c_float), ("tv_eps", c_float), ("n_steps", c_int32),
                 ("optimizer", c_int32), ("lr", c_float), ("beta1", c_float), ("beta2", c_float),
-                ("adam_eps", c_float), ("schedule", c_int32), ("split_bin", c_int32), ("device", c_int32)]
+                ("adam_eps", c_float), ("schedule", c_int32), ("split_bin", c_int32), ("device", c_int32),
+                ("tiles", vp_tiles), ("autotune", c_int32)]
 
 
 class vp_result(ctypes.Structure):
@@ -73,6 +82,8 @@ _PROTOS = {
                                 POINTER(c_float)]),
     "vp_plan_knot": (c_int32, [_P, c_int32, POINTER(c_int32), POINTER(c_float)]),
     "vp_plan_device_bytes": (c_int32, [_P, POINTER(vp_options), POINTER(c_uint64)]),
+    "vp_plan_tune": (c_int32, [_P, POINTER(vp_options), POINTER(vp_tiles)]),
+    "vp_plan_tiles": (c_int32, [_P, POINTER(vp_options), POINTER(vp_tiles)]),
     "vp_forward": (c_int32, [_P, _P, _P, _P, _P]),
     "vp_adjoint": (c_int32, [_P, _P, _P, c_int32, _P]),
     "vp_tv_grad": (c_int32, [_P, _P, c_float, c_float, c_float, _P, c_int32, _P]),
@@ -148,11 +159,15 @@ def _hp(a: Optional[np.ndarray]):
 # ------------------------------------------------------------------ options
 
 def vp_options_default(**overrides) -> vp_options:
+    """Default options with fields overridden by keyword; `tiles` takes a 4- or 5-tuple
+    (proj_rows, proj_parts, gath_rows, gath_bins[, upd_bins])."""
     o = vp_options()
     check(lib().vp_options_default(byref(o)))
     for k, v in overrides.items():
         if not hasattr(o, k):
             raise KeyError(k)
+        if k == "tiles":
+            v = vp_tiles(*[int(x) for x in v])
         setattr(o, k, v)
     return o
 
@@ -216,6 +231,18 @@ class Plan:
         k, a = c_int32(), c_float()
         check(lib().vp_plan_knot(self.handle, b, byref(k), byref(a)))
         return k.value, a.value
+
+    def tune(self, opts: Optional[vp_options] = None) -> tuple:
+        """Times the tile shapes on the device (vp_plan_tune); returns the fastest."""
+        t = vp_tiles()
+        check(lib().vp_plan_tune(self.handle, byref(opts if opts is not None else vp_options_default()), byref(t)))
+        return t.as_tuple()
+
+    def tiles(self, opts: Optional[vp_options] = None) -> tuple:
+        """The tile shape a session with these options would use (vp_plan_tiles)."""
+        t = vp_tiles()
+        check(lib().vp_plan_tiles(self.handle, byref(opts if opts is not None else vp_options_default()), byref(t)))
+        return t.as_tuple()
 
     def device_bytes(self, opts: Optional[vp_options] = None) -> int:
         out = c_uint64()

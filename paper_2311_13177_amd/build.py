@@ -13,7 +13,8 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB_PATH = os.path.join(PKG, "libvp.so")
 
-SOURCES = ["plan.cpp", "kernels.hip", "runtime.hip", "batch.hip", "server.cpp"]
+SOURCES = ["plan.cpp", "k_fft.hip", "k_project.hip", "k_gather.hip", "k_vox.hip", "runtime.hip", "batch.hip",
+           "tune.hip", "server.cpp"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950",
@@ -22,6 +23,9 @@ HIP_FLAGS = [
     "-fPIC",
     "-Wall",
     "-Wno-unused-result",
+    # no implicit contraction: a value's bits depend on its expression only, never on
+    # the code around it (every tile shape and batch gives the same results)
+    "-ffp-contract=off",
     # packed FP32 VALU ops stay off: every float op is a plain scalar-lane op
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]

@@ -28,16 +28,48 @@ void SliceGroup::drop_graph() {
     graph = nullptr;
 }
 
+// One tile shape for a whole group (the kernels take it as template parameters): the
+// shape every session already uses if they agree, else the largest slice's shape when it
+// fits every slice, else that shape with two-row tiles, which always fits.
+static Tiles group_tiles(const std::vector<vp_session*>& sessions) {
+    const vp_session* big = sessions[0];
+    bool same = true;
+    for (const vp_session* s : sessions) {
+        same = same && s->layout->tiles == sessions[0]->layout->tiles;
+        if (s->plan->voxels() > big->plan->voxels()) big = s;
+    }
+    Tiles t = big->layout->tiles;
+    if (same) return t;
+    for (const vp_session* s : sessions) {
+        const Layout* L = nullptr;
+        if (plan_layout(s->plan, t, &L) != VP_OK) {
+            clear_error();
+            t.proj_rows = 2;
+            t.gath_rows = 2;
+            break;
+        }
+    }
+    return t;
+}
+
 // Builds descriptors and concatenated work lists for `sessions` (slice i = sessions[i]).
 vp_status group_build(SliceGroup* g, const std::vector<vp_session*>& sessions, const std::vector<int>& limits) {
     g->drop_graph();
     const int ns = (int)sessions.size();
     std::vector<SliceDesc> descs(ns);
-    std::vector<Task> proj, rows, cols, gath, vox, render;
+    std::vector<Task> proj, rows, cols, gath, vox, render, upd;
     StageLists L;
+    if (ns) L.tiles = group_tiles(sessions);
     for (int i = 0; i < ns; ++i) {
         const vp_plan* p = sessions[i]->plan;
+        const Layout* lay = nullptr;
+        const DeviceLayout* dl = nullptr;
+        vp_status st = plan_layout(p, L.tiles, &lay);
+        if (st == VP_OK) st = device_layout(p, sessions[i]->tabs, lay, &dl);
+        if (st != VP_OK) return st;
+        if (L.tiles.upd_sc && (st = session_ensure_grad(sessions[i])) != VP_OK) return st;
         descs[i] = sessions[i]->desc;
+        descs[i].groups = dl->groups;
         descs[i].step_limit = limits[i];
         auto add = [i](std::vector<Task>& dst, const std::vector<Task>& src) {
             for (Task t : src) {
@@ -45,22 +77,22 @@ vp_status group_build(SliceGroup* g, const std::vector<vp_session*>& sessions, c
                 dst.push_back(t);
             }
         };
-        add(proj, p->t_proj);
+        add(proj, lay->t_proj);
         add(rows, p->t_rows);
         add(cols, p->t_cols);
-        add(gath, p->t_gath);
+        add(gath, lay->t_gath);
+        add(upd, lay->t_upd);
         add(vox, p->t_vox);
         add(render, p->t_render);
-        L.proj_gw = std::max(L.proj_gw, p->proj_gw);
-        L.re_proj = std::max(L.re_proj, p->re_proj);
+        L.re_proj = std::max(L.re_proj, lay->re_proj);
         L.lds_rows = std::max(L.lds_rows, p->lds_rows);
         L.lds_cols = std::max(L.lds_cols, p->lds_cols);
-        L.re_gath = std::max(L.re_gath, p->re_gath);
+        L.re_gath = std::max(L.re_gath, lay->re_gath);
     }
     std::vector<Task> all;
-    size_t off[6];
-    const std::vector<Task>* parts[6] = {&proj, &rows, &cols, &gath, &vox, &render};
-    for (int k = 0; k < 6; ++k) {
+    size_t off[7];
+    const std::vector<Task>* parts[7] = {&proj, &rows, &cols, &gath, &vox, &render, &upd};
+    for (int k = 0; k < 7; ++k) {
         off[k] = all.size();
         all.insert(all.end(), parts[k]->begin(), parts[k]->end());
     }
@@ -83,6 +115,8 @@ vp_status group_build(SliceGroup* g, const std::vector<vp_session*>& sessions, c
     L.gath = g->d_tasks + off[3]; L.n_gath = (int)gath.size();
     L.vox = g->d_tasks + off[4]; L.n_vox = (int)vox.size();
     L.render = g->d_tasks + off[5]; L.n_render = (int)render.size();
+    L.upd = g->d_tasks + off[6]; L.n_upd = (int)upd.size();
+    L.n_slices = ns;
     g->lists = L;
     return VP_OK;
 }
@@ -141,10 +175,37 @@ extern "C" vp_status vp_batch_reconstruct(int32_t n, const vp_plan* const* plans
     std::vector<int> slot_of(n, -1);
     vp_status first_err = VP_OK;
     int max_steps = 0;
+    // One tile shape serves the whole batch: when any slice asks for tuning, the
+    // largest slice is tuned (once per plan sizes) and every slice whose regions fit
+    // takes its shape.
+    bool tune = false;
+    int big = 0;
+    for (int i = 0; i < n; ++i) {
+        tune = tune || opts[i]->autotune != 0;
+        if (plans[i]->voxels() > plans[big]->voxels()) big = i;
+    }
+    Tiles shape{};
+    bool have_shape = false;
+    if (tune) {
+        vp_options ob = *opts[big];
+        ob.device = device;
+        ob.autotune = 1;
+        have_shape = check_options(plans[big], &ob) == VP_OK && tiles_for(plans[big], &ob, &shape) == VP_OK;
+        if (!have_shape) clear_error();
+    }
     {
         for (int i = 0; i < n; ++i) {
             vp_options o = *opts[i];
             o.device = device;
+            o.autotune = 0;
+            const vp_tiles& ot = o.tiles;
+            const Layout* lay = nullptr;
+            if (have_shape && !ot.proj_rows && !ot.proj_parts && !ot.gath_rows && !ot.gath_bins && !ot.upd_bins) {
+                if (plan_layout(plans[i], shape, &lay) == VP_OK)
+                    o.tiles = vp_tiles{shape.proj_rows, shape.proj_gw, shape.gath_rows, shape.gath_sc, shape.upd_sc};
+                else
+                    clear_error();
+            }
             vp_session* s = nullptr;
             vp_status st = session_alloc(plans[i], &o, kspace[i], nullptr, g.stream, &s);
             results[i]->status = st;

@@ -1,0 +1,418 @@
+// Adjoint of the projection as a gather, fused with the regulariser gradient and the
+// optimiser update (Sections 4.2 and 4.3).
+
+#include "kcommon.h"
+
+namespace vp {
+
+// Whole-wave lane shifts by one (DPP wave_shr / wave_shl): lane i receives lane i - 1
+// (shfl_up1) or lane i + 1 (shfl_down1); the lane without a source keeps zero.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float2 shfl_up1(float2 v) { return make_float2(dpp_f<0x138>(v.x), dpp_f<0x138>(v.y)); }
+__device__ __forceinline__ float2 shfl_down1(float2 v) { return make_float2(dpp_f<0x130>(v.x), dpp_f<0x130>(v.y)); }
+
+// ------------------------------------------------------------------ optimiser update of a column
+
+struct UpdateArgs {
+    int n, S, T, kt, y0, x0, lane, sw, ns, opt;
+    float lr, beta1, beta2, aeps, tv_w, l1_w, eps2, inv_bc2s, step_size;
+};
+
+// Adds the TV/L1 gradient to the data gradient acc of one lane's voxels (bins sw ..
+// sw + ns - 1, rows y0 .. y0 + PPT - 1, column x0 + lane of knot kt) and applies Adam
+// or GD, reading Vin and writing Vout (distinct buffers, as are the moments). The lane
+// walks its bins with a register window of the previous, current and next bin (rows
+// y0 - 1 .. y0 + PPT, zero outside the grid); x neighbours come from adjacent lanes.
+// Each Charbonnier weight of a forward difference along s or y is computed once and
+// used by both voxels of the pair (the s weight is carried to the next bin), with the
+// same operands as a per-voxel evaluation, so the result is the same either way. Plane
+// addresses are uniform and the per-lane offsets 32-bit; every load has a clamped,
+// valid address and zero is selected outside the grid, so the loads issue together.
+template <int SCM, int PPT>
+__device__ __forceinline__ void update_column(const float2 (&acc)[SCM][PPT], const float2* __restrict__ Vin,
+                                              float2* __restrict__ Vout, float2* __restrict__ Mm,
+                                              float2* __restrict__ Mv, const UpdateArgs& u) {
+    constexpr int WR = PPT + 2;
+    const int n = u.n, S = u.S;
+    const size_t nn = (size_t)n * n;
+    const int x = u.x0 + u.lane, xc = min(x, n - 1);
+    const size_t kbase = (size_t)u.kt * S * nn;
+    const float eps2 = u.eps2;
+    const bool tv = u.tv_w != 0.f;
+    const float2 zero = make_float2(0.f, 0.f);
+    int roff[WR];
+    bool rin[WR];
+#pragma unroll
+    for (int r = 0; r < WR; ++r) {
+        const int y = u.y0 - 1 + r;
+        rin[r] = y >= 0 && y < n;
+        roff[r] = min(max(y, 0), n - 1) * n + xc;
+    }
+    // rows outside the grid and bins outside [0, S) read zero (out-of-range buffer loads)
+    auto load_plane = [&](int s, float2 (&w)[WR]) {
+        const bool sin = s >= 0 && s < S;
+        const __amdgpu_buffer_rsrc_t r = plane_rsrc(Vin + kbase + (size_t)(sin ? s : 0) * nn, sin ? (int)nn : 0);
+#pragma unroll
+        for (int k = 0; k < WR; ++k) w[k] = buffer_c64(r, rin[k] ? roff[k] : -1);
+    };
+    if (u.ns <= 0) return;
+    float2 pv[WR], cv[WR], nv[WR];
+    load_plane(u.sw - 1, pv);
+    load_plane(u.sw, cv);
+    load_plane(u.sw + 1, nv);
+    float2 wsp[PPT];  // weights of the differences between bins s - 1 and s
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) wsp[i] = (tv && u.sw > 0) ? charb_w(csub(cv[i + 1], pv[i + 1]), eps2) : zero;
+#pragma unroll
+    for (int q = 0; q < SCM; ++q) {
+        if (q < u.ns) {
+            const int s = u.sw + q;
+            if (q > 0) {
+#pragma unroll
+                for (int r = 0; r < WR; ++r) {
+                    pv[r] = cv[r];
+                    cv[r] = nv[r];
+                }
+                load_plane(s + 1, nv);
+            }
+            const size_t pbase = kbase + (size_t)s * nn;
+            // moments and time neighbours first, so their loads overlap the arithmetic
+            float2 mm[PPT], vv[PPT], tp[PPT], tn[PPT];
+#pragma unroll
+            for (int i = 0; i < PPT; ++i) {
+                mm[i] = vv[i] = tp[i] = tn[i] = zero;
+                if (u.opt == VP_OPT_ADAM) {
+                    mm[i] = Mm[pbase + roff[i + 1]];
+                    vv[i] = Mv[pbase + roff[i + 1]];
+                }
+                if (tv && u.kt > 0) tp[i] = Vin[pbase - (size_t)S * nn + roff[i + 1]];
+                if (tv && u.kt + 1 < u.T) tn[i] = Vin[pbase + (size_t)S * nn + roff[i + 1]];
+            }
+            float2 wy[PPT + 1], wsn[PPT];
+#pragma unroll
+            for (int r = 0; r <= PPT; ++r) wy[r] = tv ? charb_w(csub(cv[r + 1], cv[r]), eps2) : zero;
+#pragma unroll
+            for (int i = 0; i < PPT; ++i) wsn[i] = (tv && s + 1 < S) ? charb_w(csub(nv[i + 1], cv[i + 1]), eps2) : zero;
+#pragma unroll
+            for (int i = 0; i < PPT; ++i) {
+                const int y = u.y0 + i;
+                if (y < n) {
+                    const size_t idx = pbase + roff[i + 1];
+                    const float2 v0 = cv[i + 1];
+                    float2 left = shfl_up1(v0), right = shfl_down1(v0);
+                    if (u.lane == 0) left = u.x0 > 0 ? Vin[idx - 1] : zero;
+                    if (u.lane == 63) right = u.x0 + 64 < n ? Vin[idx + 1] : zero;
+                    float2 g = zero;
+                    if (tv) {
+                        if (u.kt > 0) g = cadd(g, charb_w(csub(v0, tp[i]), eps2));
+                        if (u.kt + 1 < u.T) g = csub(g, charb_w(csub(tn[i], v0), eps2));
+                        if (s > 0) g = cadd(g, wsp[i]);
+                        if (s + 1 < S) g = csub(g, wsn[i]);
+                        if (y > 0) g = cadd(g, wy[i]);
+                        if (y + 1 < n) g = csub(g, wy[i + 1]);
+                        if (x > 0) g = cadd(g, charb_w(csub(v0, left), eps2));
+                        if (x + 1 < n) g = csub(g, charb_w(csub(right, v0), eps2));
+                        g = cscale(g, u.tv_w);
+                    }
+                    if (u.l1_w != 0.f) g = cfma(u.l1_w, charb_w(v0, eps2), g);
+                    const float2 gr = cadd(acc[q][i], g);
+                    if (x < n) {
+                        float2 nvx;
+                        if (u.opt == VP_OPT_ADAM) {
+                            float2 m = mm[i], v = vv[i];
+                            const float c1 = 1.0f - u.beta1, c2 = 1.0f - u.beta2;
+                            m.x = __builtin_fmaf(u.beta1, m.x, c1 * gr.x);
+                            m.y = __builtin_fmaf(u.beta1, m.y, c1 * gr.y);
+                            v.x = __builtin_fmaf(u.beta2, v.x, (c2 * gr.x) * gr.x);
+                            v.y = __builtin_fmaf(u.beta2, v.y, (c2 * gr.y) * gr.y);
+                            Mm[idx] = m;
+                            Mv[idx] = v;
+                            // hardware square root and reciprocal (about 1 ulp each)
+                            const float dx = __builtin_fmaf(__builtin_amdgcn_sqrtf(v.x), u.inv_bc2s, u.aeps);
+                            const float dy = __builtin_fmaf(__builtin_amdgcn_sqrtf(v.y), u.inv_bc2s, u.aeps);
+                            nvx = make_float2(__builtin_fmaf(-u.step_size, m.x * __builtin_amdgcn_rcpf(dx), v0.x),
+                                              __builtin_fmaf(-u.step_size, m.y * __builtin_amdgcn_rcpf(dy), v0.y));
+                        } else {
+                            nvx = make_float2(__builtin_fmaf(-u.lr, gr.x, v0.x), __builtin_fmaf(-u.lr, gr.y, v0.y));
+                        }
+                        Vout[idx] = nvx;
+                    }
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < PPT; ++i) wsp[i] = wsn[i];
+        }
+    }
+}
+
+// Regulariser gradient and optimiser update of a lane's voxels (update_column) with the
+// slice's hyperparameters (the step counter is advanced by k_advance after the pass).
+template <int SCM, int PPT>
+__device__ __forceinline__ void update_and_finish(const KArgs& a, int slice, int* stepp, int st,
+                                                  const float2 (&acc)[SCM][PPT], int kt, int y0, int x0,
+                                                  int lane, int sw, int ns) {
+    const float2* const Vin = stepp ? DF(vol[st & 1]) : DF(vol[0]);
+    float2* const Vout = DF(vol[(st + 1) & 1]);
+    const float lr = DF(lr), teps = DF(tv_eps);
+    UpdateArgs u;
+    u.n = DF(n); u.S = DF(S); u.T = DF(T); u.kt = kt; u.y0 = y0; u.x0 = x0; u.lane = lane; u.sw = sw; u.ns = ns;
+    u.opt = DF(optimizer); u.lr = lr; u.beta1 = DF(beta1); u.beta2 = DF(beta2); u.aeps = DF(adam_eps);
+    u.tv_w = DF(tv_w); u.l1_w = DF(l1_w); u.eps2 = teps * teps;
+    u.inv_bc2s = 1.f;
+    u.step_size = lr;
+    if (u.opt == VP_OPT_ADAM) {
+        // bias corrections 1 - beta^t = -expm1(t ln beta), t = step + 1, once per item
+        const float tf = (float)(st + 1);
+        const float bc1 = -expm1f(tf * DF(ln_beta1)), bc2 = -expm1f(tf * DF(ln_beta2));
+        u.step_size = lr / bc1;
+        u.inv_bc2s = 1.f / sqrtf(bc2);
+    }
+    update_column<SCM, PPT>(acc, Vin, Vout, DF(m), DF(v), u);
+}
+
+// ------------------------------------------------------------------ adjoint gather + update
+//
+// G[k][s][y][x] = sum over the knot's blade parts e (plan order, blades ascending) of
+//   w_e * (w00 g[y-oy][x-ox] + w01 g[y-oy][x-ox-1] + w10 g[y-oy-1][x-ox] + w11 g[y-oy-1][x-ox-1]),
+// the exact transpose of k_project's taps (zero outside the grid). Work item: (knot,
+// tile of 64 x PPT, chunk of 4 * SCM bins); wave w owns bins s0 + w * SCM ... s0 + w * SCM
+// + SCM - 1.
+// MODE = GATHER_STORE writes (or adds to) the gradient; GATHER_STEP adds the TV/L1
+// gradient and applies the optimiser, reading volume[step & 1] and writing the other
+// copy.
+// In the update each lane walks its column through the wave's bins with a register
+// window of the previous, current and next bin (rows y0-1 .. y0+PPT), taking
+// the x neighbours from the adjacent lanes.
+
+template <int MODE, int PPT, int SCM, int SE, int P>
+__global__ __launch_bounds__(kThreads) void k_gather(const KArgs a) {
+    extern __shared__ float2 sm[];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int ti = xcd_item(blockIdx.x, gridDim.x); ti < a.ntasks; ti += gridDim.x) {
+        const AS4 Task* tk = cst(a.tasks) + ti;
+        const int slice = tk->slice;
+        int* const stepp = DF(step);
+        const int st = read_step(stepp);
+        if (stepp && st >= DF(step_limit)) continue;
+        const int n = DF(n), S = DF(S), T = DF(T), B = DF(B), nparts = DF(nparts), sched = DF(schedule);
+        const int kt = tk->a;
+        const size_t nn = (size_t)n * n;
+        const int txn = (n + kTileW - 1) / kTileW;
+        const int y0 = (tk->b / txn) * PPT, x0 = (tk->b % txn) * kTileW;
+        const int sw = tk->c * 4 * SCM + wave * SCM;
+        const int ns = max(0, min(SCM, S - sw));
+        const AS4 KnotInfo* ki = cst(DF(knots)) + kt;
+        const int kox = ki->ox_max, koy = ki->oy_max;
+        const int RH = PPT + koy - ki->oy_min + 1, RW = kTileW + kox - ki->ox_min + 1;
+        const int RE = RH * RW;
+        const AS4 KnotEntry* ent = cst(DF(knot_ent));
+        const AS4 ShearEntry* shear = cst(DF(shear));
+        const float2* const work = DF(work);
+        const int* kp = DF(knot_ptr);
+        const int e0 = cst(kp)[kt], e1 = cst(kp)[kt + 1];
+        float2 acc[SCM][PPT];
+#pragma unroll
+        for (int q = 0; q < SCM; ++q)
+#pragma unroll
+            for (int i = 0; i < PPT; ++i) acc[q][i] = make_float2(0.f, 0.f);
+        Stager<SE, P> sg;
+        sg.init(RH, RW, y0 - koy - 1, x0 - kox - 1, n);
+        float2 pre[P][SE];
+        // the knot's active parts in plan order, P per phase: cur[] this phase, nxt[] the next
+        auto next_active = [&](int e) {
+            while (e < e1 && !active_blade(sched, stepp, st, B, ent[e].blade)) ++e;
+            return e;
+        };
+        int cur[P];
+        {
+            int e = e0;
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                e = next_active(e);
+                cur[p] = e;
+                if (e < e1) ++e;
+            }
+            const float2* planes[P];
+#pragma unroll
+            for (int p = 0; p < P; ++p) planes[p] = cur[p] < e1 ? work + (size_t)ent[cur[p]].blade * nparts * nn : nullptr;
+            if (cur[0] < e1) sg.fetch(planes, (int)nn, pre);
+        }
+        for (int it = 0; cur[0] < e1; ++it) {
+            float2* buf = sm + (it & 1) * P * RE;
+            sg.store(buf, pre);
+            __syncthreads();
+            int nxt[P];
+            {
+                int e = cur[P - 1] < e1 ? cur[P - 1] + 1 : e1;
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    e = next_active(e);
+                    nxt[p] = e;
+                    if (e < e1) ++e;
+                }
+                const float2* planes[P];
+#pragma unroll
+                for (int p = 0; p < P; ++p)
+                    planes[p] = nxt[p] < e1 ? work + (size_t)ent[nxt[p]].blade * nparts * nn : nullptr;
+                if (nxt[0] < e1) sg.fetch(planes, (int)nn, pre);
+            }
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                if (cur[p] < e1) {
+                    const int b = ent[cur[p]].blade;
+                    const float wb = ent[cur[p]].weight;
+                    // taps of all of the wave's bins, loaded before any is used (bins past
+                    // S read the last bin's entry and are skipped)
+                    const AS4 ShearEntry* shb = shear + (size_t)b * S;
+                    int tox[SCM], toy[SCM];
+                    float tw[SCM][4];
+#pragma unroll
+                    for (int q = 0; q < SCM; ++q) {
+                        const AS4 ShearEntry* sh = shb + min(sw + q, S - 1);
+                        tox[q] = sh->ox;
+                        toy[q] = sh->oy;
+                        tw[q][0] = sh->w00;
+                        tw[q][1] = sh->w01;
+                        tw[q][2] = sh->w10;
+                        tw[q][3] = sh->w11;
+                    }
+#pragma unroll
+                    for (int q = 0; q < SCM; ++q) {
+                        if (q < ns) {
+                            const float w00 = tw[q][0], w01 = tw[q][1], w10 = tw[q][2], w11 = tw[q][3];
+                            // row of g[y - oy][.] for pixel row 0, column of g[.][x - ox]
+                            const float2* L = buf + p * RE + (koy - toy[q] + 1) * RW + (kox - tox[q] + 1) + lane;
+                            float2 u0 = L[-RW], u1 = L[-RW - 1];
+#pragma unroll
+                            for (int i = 0; i < PPT; ++i) {
+                                const float2 v0 = L[i * RW], v1 = L[i * RW - 1];
+                                float2 t = make_float2(0.f, 0.f);
+                                t = cfma(w00, v0, t);
+                                t = cfma(w01, v1, t);
+                                t = cfma(w10, u0, t);
+                                t = cfma(w11, u1, t);
+                                acc[q][i] = cfma(wb, t, acc[q][i]);
+                                u0 = v0;
+                                u1 = v1;
+                            }
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int p = 0; p < P; ++p) cur[p] = nxt[p];
+        }
+        __syncthreads();
+        const int x = x0 + lane;
+        if (MODE == GATHER_STORE) {
+            float2* const grad = DF(grad);
+            if (x < n) {
+#pragma unroll
+                for (int q = 0; q < SCM; ++q) {
+                    if (q < ns) {
+#pragma unroll
+                        for (int i = 0; i < PPT; ++i) {
+                            const int y = y0 + i;
+                            if (y < n) {
+                                const size_t idx = (((size_t)kt * S + sw + q) * n + y) * n + x;
+                                float2 g = acc[q][i];
+                                if (a.accumulate) g = cadd(grad[idx], g);
+                                grad[idx] = g;
+                            }
+                        }
+                    }
+                }
+            }
+        } else {
+            update_and_finish<SCM, PPT>(a, slice, stepp, st, acc, kt, y0, x0, lane, sw, ns);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ separate update pass
+//
+// The same update as the fused epilogue, for a data gradient G that the gather has
+// stored ([T][S][n][n], in DF(grad)): G is read back exactly, and update_column does the
+// same arithmetic, so the result equals the fused one bit for bit. Work item: (knot,
+// block of 4 rows x 64 columns, chunk of SC bins); wave w takes row 4 * b + w. Its light
+// register footprint keeps many waves in flight on what is a streaming pass.
+
+template <int SC>
+__global__ __launch_bounds__(kThreads) void k_update(const KArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int ti = xcd_item(blockIdx.x, gridDim.x); ti < a.ntasks; ti += gridDim.x) {
+        const AS4 Task* tk = cst(a.tasks) + ti;
+        const int slice = tk->slice;
+        int* const stepp = DF(step);
+        const int st = read_step(stepp);
+        if (stepp && st >= DF(step_limit)) continue;
+        const int n = DF(n), S = DF(S);
+        const int kt = tk->a;
+        const int txn = (n + kTileW - 1) / kTileW;
+        const int y = (tk->b / txn) * 4 + wave, x0 = (tk->b % txn) * kTileW;
+        const int sw = tk->c * SC;
+        const int ns = y < n ? max(0, min(SC, S - sw)) : 0;
+        const size_t nn = (size_t)n * n;
+        const int off = min(y, n - 1) * n + min(x0 + lane, n - 1);
+        const float2* const G = DF(grad) + (size_t)kt * S * nn;
+        float2 acc[SC][1];
+#pragma unroll
+        for (int q = 0; q < SC; ++q) acc[q][0] = G[(size_t)min(sw + q, S - 1) * nn + off];
+        update_and_finish<SC, 1>(a, slice, stepp, st, acc, kt, y, x0, lane, sw, ns);
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+
+static inline int grid_for(int ntasks) { return ntasks < 1 ? 1 : (ntasks > (1 << 20) ? (1 << 20) : ntasks); }
+
+template <int MODE, int PPT, int SCM>
+static void gather_variant(const KArgs& a, int re, hipStream_t s) {
+    const dim3 g(grid_for(a.ntasks)), b(kThreads);
+    const int depth = stage_depth(re);
+    const size_t lds = stage_lds_bytes(re);
+    if (depth == 5) hipLaunchKernelGGL((k_gather<MODE, PPT, SCM, 5, 3>), g, b, lds, s, a);
+    else if (depth == 8) hipLaunchKernelGGL((k_gather<MODE, PPT, SCM, 8, 2>), g, b, lds, s, a);
+    else hipLaunchKernelGGL((k_gather<MODE, PPT, SCM, 16, 1>), g, b, lds, s, a);
+}
+
+template <int MODE>
+static hipError_t gather_mode(const KArgs& a, int rows, int sc, int re, hipStream_t s) {
+#define GV(R, C)                                   \
+    case R * 16 + C:                               \
+        gather_variant<MODE, R, C>(a, re, s);      \
+        break
+    switch (rows * 16 + sc) {
+        GV(2, 1); GV(2, 2); GV(2, 4); GV(2, 8);
+        GV(4, 1); GV(4, 2); GV(4, 4);
+        default: return hipErrorInvalidValue;
+    }
+#undef GV
+    return hipGetLastError();
+}
+
+hipError_t launch_update(const KArgs& a, int sc, hipStream_t s) {
+    if (a.ntasks <= 0) return hipSuccess;
+    const dim3 g(grid_for(a.ntasks)), b(kThreads);
+    switch (sc) {
+        case 2: hipLaunchKernelGGL(k_update<2>, g, b, 0, s, a); break;
+        case 4: hipLaunchKernelGGL(k_update<4>, g, b, 0, s, a); break;
+        case 8: hipLaunchKernelGGL(k_update<8>, g, b, 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const KArgs& a, int mode, int rows, int sc, int re, hipStream_t s) {
+    if (a.ntasks <= 0) return hipSuccess;
+    if (!gath_tiles_ok(rows, sc) || re < 1 || re > kStageMax * kThreads) return hipErrorInvalidValue;
+    return mode == GATHER_STEP ? gather_mode<GATHER_STEP>(a, rows, sc, re, s)
+                               : gather_mode<GATHER_STORE>(a, rows, sc, re, s);
+}
+
+}  // namespace vp

@@ -1,0 +1,136 @@
+// Device-side helpers shared by the HIP kernels of libvp (gfx950).
+//
+// Every kernel walks a list of work items (Task) with a grid-stride loop, so one
+// launch can cover one slice or many slices of different sizes; each item reads its
+// slice descriptor. Per-voxel and per-pixel summation orders depend only on the
+// slice's own plan (bins ascending, blade parts in plan order, fixed tap order), never
+// on the batch, the tile shape or the wave that happens to hold the element, so every
+// tile shape gives the same bits.
+//
+// Uniform data (work items, descriptors, shear table, blade and knot tables) is read
+// through constant-address-space pointers so that it lands in scalar registers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "vp.h"
+#include "vp_internal.h"
+
+namespace vp {
+#define AS4 __attribute__((address_space(4)))
+
+template <class T>
+__device__ __forceinline__ const AS4 T* cst(const T* p) {
+    return (const AS4 T*)(const void*)p;
+}
+
+// Field of the work item's slice descriptor (descriptor array or the inline copy).
+#define DF(field) (a.descs ? cst(a.descs + slice)->field : a.one.field)
+
+// ------------------------------------------------------------------ helpers
+
+// Floating-point contraction is off for every kernel (no fusing the compiler chooses by
+// context), so a value's bits depend only on the source expression; the fused
+// multiply-adds are written out.
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(__builtin_fmaf(a.x, b.x, -(a.y * b.y)), __builtin_fmaf(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// (sign * i) * a
+template <int SIGN>
+__device__ __forceinline__ float2 mul_i(float2 a) {
+    return SIGN > 0 ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+// acc + w * a, one fused multiply-add per component
+__device__ __forceinline__ float2 cfma(float w, float2 a, float2 acc) {
+    return make_float2(__builtin_fmaf(w, a.x, acc.x), __builtin_fmaf(w, a.y, acc.y));
+}
+__device__ __forceinline__ bool active_blade(int sched, const int* stepp, int st, int B, int b) {
+    return sched != VP_SCHED_CYCLIC || stepp == nullptr || b == st % B;
+}
+__device__ __forceinline__ int read_step(const int* stepp) { return stepp ? *cst(stepp) : 0; }
+
+// Charbonnier weight d / sqrt(|d|^2 + eps^2): the gradient of sqrt(|d|^2 + eps^2) - eps.
+// The hardware reciprocal square root (about 1 ulp); its argument is kept a normal
+// number, so no denormal handling is needed.
+__device__ __forceinline__ float2 charb_w(float2 dlt, float eps2) {
+    const float q = __builtin_fmaf(dlt.x, dlt.x, __builtin_fmaf(dlt.y, dlt.y, eps2));
+    return cscale(dlt, __builtin_amdgcn_rsqf(fmaxf(q, 1.17549435e-38f)));
+}
+
+// Work-item index of a block. The dispatcher deals consecutive blocks to the eight XCDs
+// in turn, each XCD with its own L2; renumbering gives every XCD a contiguous run of
+// work items, so neighbouring items (adjacent tiles, the bin chunks and knots of one
+// tile) share their halos and blade regions in one L2. A bijection on [0, grid).
+// Word 3 of a raw buffer resource on this architecture, and a byte offset beyond any
+// buffer used here (loads there return zero).
+constexpr int kBufferFlags = 0x00020000;
+constexpr int kBufferOut = 0x7ffffff0;
+
+__device__ __forceinline__ int xcd_item(int block, int grid) {
+    const int g8 = grid & ~(kXcds - 1);
+    if (block >= g8) return block;
+    return (block % kXcds) * (g8 / kXcds) + block / kXcds;
+}
+
+// Buffer resource over a plane of `count` complex values (count 0: an empty buffer).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const float2* base, int count) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, count * (int)sizeof(float2), kBufferFlags);
+}
+// Element `idx` of a buffer of complex values; a negative index reads zero (out of range).
+__device__ __forceinline__ float2 buffer_c64(__amdgpu_buffer_rsrc_t r, int idx) {
+    const int byte = idx >= 0 ? idx * (int)sizeof(float2) : kBufferOut;
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, byte, 0, 0));
+}
+
+// ------------------------------------------------------------------ LDS staging
+//
+// A rectangular region (rows x cols) of an n x n image, origin (gy0, gx0), is staged
+// into LDS with zeros outside the image. Each thread owns region elements
+// threadIdx.x + k * kThreads (k < SE); their image offsets are computed once per work
+// item, and the next plane's values are loaded into registers while the current plane
+// is being consumed (double-buffered LDS, one barrier per plane).
+
+// P planes (images of the same size, same region) are staged per phase; plane p of a
+// phase occupies buf[p * re, (p + 1) * re). A null plane pointer stages zeros.
+template <int SE, int P>
+struct Stager {
+    int off[SE];
+    int re;
+    __device__ void init(int rows, int cols, int gy0, int gx0, int n) {
+        re = rows * cols;
+#pragma unroll
+        for (int k = 0; k < SE; ++k) {
+            const int i = threadIdx.x + k * kThreads;
+            int o = -1;
+            if (i < re) {
+                const int r = i / cols, c = i - (i / cols) * cols;
+                const int gy = gy0 + r, gx = gx0 + c;
+                if (gy >= 0 && gy < n && gx >= 0 && gx < n) o = gy * n + gx;
+            }
+            off[k] = i < re ? o : -2;
+        }
+    }
+    // Buffer loads with the plane as the buffer: an element outside the image (or a null
+    // plane, whose buffer is empty) is out of range and reads as zero without a branch
+    // or a memory access.
+    __device__ void fetch(const float2* const (&img)[P], int nn, float2 (&pre)[P][SE]) const {
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const __amdgpu_buffer_rsrc_t r = plane_rsrc(img[p], img[p] ? nn : 0);
+#pragma unroll
+            for (int k = 0; k < SE; ++k) pre[p][k] = buffer_c64(r, off[k]);
+        }
+    }
+    __device__ void store(float2* buf, const float2 (&pre)[P][SE]) const {
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+            for (int k = 0; k < SE; ++k)
+                if (off[k] != -2) buf[p * re + threadIdx.x + k * kThreads] = pre[p][k];
+    }
+};
+
+}  // namespace vp

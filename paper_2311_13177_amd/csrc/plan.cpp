@@ -80,6 +80,116 @@ static void build_shear(double theta, double delta, ShearEntry* e, float* fxo, f
 
 static int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
+// Union of the shear offset extents of knot entries [e0, e1): {ox_min, ox_max, oy_min, oy_max}.
+static void part_extents(const vp_plan* p, int e0, int e1, int* ext) {
+    ext[0] = ext[2] = std::numeric_limits<int>::max();
+    ext[1] = ext[3] = std::numeric_limits<int>::min();
+    for (int e = e0; e < e1; ++e) {
+        const BladeDev& bd = p->blade[p->knot_ent[e].blade];
+        ext[0] = std::min(ext[0], bd.ox_min); ext[1] = std::max(ext[1], bd.ox_max);
+        ext[2] = std::min(ext[2], bd.oy_min); ext[3] = std::max(ext[3], bd.oy_max);
+    }
+    if (e1 <= e0) ext[0] = ext[1] = ext[2] = ext[3] = 0;
+}
+
+// Elements of the region staged for a tile of `rows` x 64 outputs whose taps reach
+// offsets [ox_min, ox_max + 1] x [oy_min, oy_max + 1].
+static int region(int rows, int ox_min, int ox_max, int oy_min, int oy_max) {
+    return (rows + oy_max - oy_min + 1) * (kTileW + ox_max - ox_min + 1);
+}
+
+// Work items of one tile shape. Projection items are ordered tile-major so that the
+// groups of one tile (which read the same volume region) run side by side; gather items
+// are ordered tile-major, then knot, then bin chunk, so that the items sharing a tile's
+// blade regions and its neighbouring knots run side by side (see xcd_item).
+static vp_status build_layout(const vp_plan* p, const Tiles& t, Layout* L) {
+    if (!proj_tiles_ok(t.proj_rows, t.proj_gw) || !gath_tiles_ok(t.gath_rows, t.gath_sc) || !upd_tiles_ok(t.upd_sc))
+        return fail(VP_ERR_UNSUPPORTED, "tile shape (%d, %d, %d, %d, %d) is not compiled", t.proj_rows, t.proj_gw,
+                    t.gath_rows, t.gath_sc, t.upd_sc);
+    const int n = p->n, S = p->S, T = p->T;
+    L->tiles = t;
+    L->groups.clear();
+    L->t_proj.clear();
+    L->t_gath.clear();
+    L->t_upd.clear();
+    const int group_parts = 4 * t.proj_gw;
+    for (int kt = 0; kt < T; ++kt) {
+        for (int e0 = p->knot_ptr[kt]; e0 < p->knot_ptr[kt + 1]; e0 += group_parts) {
+            ProjGroup gr{};
+            gr.knot = kt;
+            gr.e0 = e0;
+            gr.ne = std::min(group_parts, p->knot_ptr[kt + 1] - e0);
+            int ext[4];
+            part_extents(p, e0, e0 + gr.ne, ext);
+            gr.ox_min = ext[0]; gr.ox_max = ext[1]; gr.oy_min = ext[2]; gr.oy_max = ext[3];
+            L->groups.push_back(gr);
+        }
+    }
+    L->re_proj = 1;
+    for (const ProjGroup& gr : L->groups)
+        L->re_proj = std::max(L->re_proj, region(t.proj_rows, gr.ox_min, gr.ox_max, gr.oy_min, gr.oy_max));
+    L->re_gath = 1;
+    for (const KnotInfo& ki : p->knots)
+        L->re_gath = std::max(L->re_gath, region(t.gath_rows, ki.ox_min, ki.ox_max, ki.oy_min, ki.oy_max));
+    if (L->re_proj > kStageMax * kThreads || L->re_gath > kStageMax * kThreads)
+        return fail(VP_ERR_UNSUPPORTED, "tile shape (%d, %d, %d, %d): staged region exceeds the LDS staging",
+                    t.proj_rows, t.proj_gw, t.gath_rows, t.gath_sc);
+    const int txn = ceil_div(n, kTileW);
+    const int typ = ceil_div(n, t.proj_rows), tyg = ceil_div(n, t.gath_rows);
+    for (int ty = 0; ty < typ; ++ty)
+        for (int tx = 0; tx < txn; ++tx)
+            for (int gi = 0; gi < (int)L->groups.size(); ++gi) L->t_proj.push_back(Task{0, gi, ty, tx});
+    const int nch = ceil_div(S, 4 * t.gath_sc);
+    for (int ty = 0; ty < tyg; ++ty)
+        for (int tx = 0; tx < txn; ++tx)
+            for (int kt = 0; kt < T; ++kt)
+                for (int ch = 0; ch < nch; ++ch) L->t_gath.push_back(Task{0, kt, ty * txn + tx, ch});
+    if (t.upd_sc) {
+        const int nuc = ceil_div(S, t.upd_sc), tyu = ceil_div(n, 4);
+        for (int ty = 0; ty < tyu; ++ty)
+            for (int tx = 0; tx < txn; ++tx)
+                for (int kt = 0; kt < T; ++kt)
+                    for (int ch = 0; ch < nuc; ++ch) L->t_upd.push_back(Task{0, kt, ty * txn + tx, ch});
+    }
+    return VP_OK;
+}
+
+static int pow2_ceil(int v) {
+    int r = 1;
+    while (r < v) r <<= 1;
+    return r;
+}
+
+Tiles heuristic_tiles(const vp_plan* p) {
+    Tiles t;
+    // every wave of a projection group busy; enough gather items to fill the chip
+    t.proj_gw = std::min(8, pow2_ceil(ceil_div(std::max(1, p->max_knot_parts), 4)));
+    t.proj_rows = 2;
+    t.gath_rows = 2;
+    t.gath_sc = std::min(8, pow2_ceil(ceil_div(p->S, 4)));
+    return t;
+}
+
+vp_status plan_layout(const vp_plan* p, const Tiles& t, const Layout** out) {
+    std::lock_guard<std::mutex> lk(p->mu);
+    auto it = p->layouts.find(t.key());
+    if (it != p->layouts.end()) {
+        *out = it->second.get();
+        return VP_OK;
+    }
+    std::unique_ptr<Layout> L(new (std::nothrow) Layout());
+    if (!L) return fail(VP_ERR_NOMEM, "layout: out of host memory");
+    try {
+        const vp_status st = build_layout(p, t, L.get());
+        if (st != VP_OK) return st;
+    } catch (const std::bad_alloc&) {
+        return fail(VP_ERR_NOMEM, "layout: out of host memory");
+    }
+    *out = L.get();
+    p->layouts.emplace(t.key(), std::move(L));
+    return VP_OK;
+}
+
 }  // namespace vp
 
 using namespace vp;
@@ -117,6 +227,8 @@ extern "C" vp_status vp_options_default(vp_options* o) {
     o->schedule = VP_SCHED_ALL_BLADES;
     o->split_bin = -1;
     o->device = 0;
+    o->tiles = vp_tiles{0, 0, 0, 0};
+    o->autotune = 0;
     return VP_OK;
 }
 
@@ -216,37 +328,13 @@ extern "C" vp_status vp_plan_create(const vp_geometry* g, vp_plan** out) {
         }
         p->knot_ptr[T] = (int)p->knot_ent.size();
 
-        // projection groups: a knot's parts in chunks of 4 * GW (GW parts per wave)
-        int max_parts = 0;
-        for (int kt = 0; kt < T; ++kt) max_parts = std::max(max_parts, p->knot_ptr[kt + 1] - p->knot_ptr[kt]);
-        p->proj_gw = max_parts <= 4 ? 1 : max_parts <= 8 ? 2 : max_parts <= 16 ? 4 : 8;
-        const int group_parts = 4 * p->proj_gw;
-        auto extents = [&](int e0, int e1, int* ext) {
-            ext[0] = ext[2] = std::numeric_limits<int>::max();
-            ext[1] = ext[3] = std::numeric_limits<int>::min();
-            for (int e = e0; e < e1; ++e) {
-                const BladeDev& bd = p->blade[p->knot_ent[e].blade];
-                ext[0] = std::min(ext[0], bd.ox_min); ext[1] = std::max(ext[1], bd.ox_max);
-                ext[2] = std::min(ext[2], bd.oy_min); ext[3] = std::max(ext[3], bd.oy_max);
-            }
-            if (e1 <= e0) ext[0] = ext[1] = ext[2] = ext[3] = 0;
-        };
+        // union of the shear extents of each knot's parts (the gather's staged halo)
         for (int kt = 0; kt < T; ++kt) {
-            for (int e0 = p->knot_ptr[kt]; e0 < p->knot_ptr[kt + 1]; e0 += group_parts) {
-                ProjGroup gr{};
-                gr.knot = kt;
-                gr.e0 = e0;
-                gr.ne = std::min(group_parts, p->knot_ptr[kt + 1] - e0);
-                int ext[4];
-                extents(e0, e0 + gr.ne, ext);
-                gr.ox_min = ext[0]; gr.ox_max = ext[1]; gr.oy_min = ext[2]; gr.oy_max = ext[3];
-                p->groups.push_back(gr);
-            }
             int ext[4];
-            extents(p->knot_ptr[kt], p->knot_ptr[kt + 1], ext);
+            part_extents(p.get(), p->knot_ptr[kt], p->knot_ptr[kt + 1], ext);
             p->knots.push_back(KnotInfo{ext[0], ext[1], ext[2], ext[3]});
+            p->max_knot_parts = std::max(p->max_knot_parts, p->knot_ptr[kt + 1] - p->knot_ptr[kt]);
         }
-        p->gath_sc = std::min(kChunkMax, ceil_div(S, 4));
 
         // twiddles exp(-2 pi i j / n), FP64 then rounded
         p->tw.resize(n);
@@ -255,41 +343,35 @@ extern "C" vp_status vp_plan_create(const vp_geometry* g, vp_plan** out) {
             p->tw[j] = make_float2((float)std::cos(ang), (float)std::sin(ang));
         }
 
-        // staged region sizes (elements); FFT LDS: data plus the twiddle table
-        for (const ProjGroup& gr : p->groups) {
-            const int rh = kTileRows + gr.oy_max - gr.oy_min + 1, rw = kTileW + gr.ox_max - gr.ox_min + 1;
-            p->re_proj = std::max(p->re_proj, rh * rw);
-        }
-        for (const KnotInfo& ki : p->knots) {
-            const int rh = kTileRows + ki.oy_max - ki.oy_min + 1, rw = kTileW + ki.ox_max - ki.ox_min + 1;
-            p->re_gath = std::max(p->re_gath, rh * rw);
-        }
-        if (p->re_proj > kStageMax * kThreads || p->re_gath > kStageMax * kThreads)
-            return fail(VP_ERR_UNSUPPORTED, "vp_plan_create: shear extents exceed the staging capacity");
+        // Two-row tiles hold the smallest staged regions of every shape with two rows: a
+        // projection group's extents lie within its knot's, whatever the group size.
+        for (const KnotInfo& ki : p->knots)
+            if (region(2, ki.ox_min, ki.ox_max, ki.oy_min, ki.oy_max) > kStageMax * kThreads)
+                return fail(VP_ERR_UNSUPPORTED, "vp_plan_create: shear extents exceed the staging capacity");
+        // FFT LDS: data plus the twiddle table
         const int fb = fft_rows_per_item(n), cb = fft_cols_per_item(n);
         p->lds_rows = ((size_t)fb * n + n) * sizeof(float2);
         p->lds_cols = ((size_t)cb * n + n) * sizeof(float2);
         p->n_col_items = ceil_div(n, cb);
 
-        // work lists
-        const int tyn = ceil_div(n, kTileRows), txn = ceil_div(n, kTileW);
-        for (int gi = 0; gi < (int)p->groups.size(); ++gi)
-            for (int ty = 0; ty < tyn; ++ty)
-                for (int tx = 0; tx < txn; ++tx) p->t_proj.push_back(Task{0, gi, ty, tx});
+        // work lists of the tile-independent stages
         for (int b = 0; b < B; ++b)
             for (int r0 = 0; r0 < n; r0 += fb) p->t_rows.push_back(Task{0, b, r0, 0});
         for (int b = 0; b < B; ++b)
             for (int c = 0; c < p->n_col_items; ++c) p->t_cols.push_back(Task{0, b, c, 0});
-        const int nch = ceil_div(S, 4 * p->gath_sc);
-        for (int kt = 0; kt < T; ++kt)
-            for (int ty = 0; ty < tyn; ++ty)
-                for (int tx = 0; tx < txn; ++tx)
-                    for (int ch = 0; ch < nch; ++ch) p->t_gath.push_back(Task{0, kt, ty * txn + tx, ch});
         const uint64_t nvox = p->voxels();
         for (uint64_t i = 0; i * kVoxItem < nvox; ++i) p->t_vox.push_back(Task{0, (int)i, 0, 0});
         const int npb = ceil_div(n * n, kVoxItem);
         for (int kt = 0; kt < T; ++kt)
             for (int pb = 0; pb < npb; ++pb) p->t_render.push_back(Task{0, kt, pb, 0});
+        p->base_tiles = heuristic_tiles(p.get());
+        const Layout* L = nullptr;
+        vp_status st = plan_layout(p.get(), p->base_tiles, &L);
+        if (st != VP_OK) {
+            p->base_tiles = Tiles{};
+            st = plan_layout(p.get(), p->base_tiles, &L);
+        }
+        if (st != VP_OK) return st;
     } catch (const std::bad_alloc&) {
         return fail(VP_ERR_NOMEM, "vp_plan_create: out of host memory");
     }
@@ -335,11 +417,16 @@ extern "C" vp_status vp_plan_knot(const vp_plan* p, int32_t b, int32_t* knot, fl
 
 namespace vp {
 uint64_t table_bytes(const vp_plan* p) {
+    // the largest layout a plan can take: one-row projection tiles with one part per
+    // wave and two-row gather tiles with one bin per wave (the most work items)
+    const uint64_t tiles_proj = (uint64_t)p->n * ceil_div(p->n, kTileW);
+    const uint64_t groups = (uint64_t)p->T + ceil_div(p->knot_ent.size(), 4);
+    const uint64_t t_gath = (uint64_t)p->T * ceil_div(p->n, 2) * ceil_div(p->n, kTileW) * ceil_div(p->S, 4) +
+                            (uint64_t)p->T * ceil_div(p->n, 4) * ceil_div(p->n, kTileW) * ceil_div(p->S, 2);
     return p->mask.size() + p->shear.size() * sizeof(ShearEntry) + p->blade.size() * sizeof(BladeDev) +
            p->knot_ptr.size() * sizeof(int) + p->knot_ent.size() * sizeof(KnotEntry) +
-           p->groups.size() * sizeof(ProjGroup) + p->knots.size() * sizeof(KnotInfo) +
-           p->tw.size() * sizeof(float2) +
-           (p->t_proj.size() + p->t_rows.size() + p->t_cols.size() + p->t_gath.size() + p->t_vox.size() +
+           groups * sizeof(ProjGroup) + p->knots.size() * sizeof(KnotInfo) + p->tw.size() * sizeof(float2) +
+           (groups * tiles_proj + t_gath + p->t_rows.size() + p->t_cols.size() + p->t_vox.size() +
             p->t_render.size()) *
                sizeof(Task);
 }
@@ -350,9 +437,10 @@ uint64_t state_bytes(const vp_plan* p, const vp_options* o) {
     if (!o || o->optimizer == VP_OPT_ADAM) b += 2 * vox;          // Adam moments
     b += (uint64_t)p->nparts * p->blade_px() * sizeof(float2);   // blade work images
     b += p->blade_px() * sizeof(float2);                          // measurements
-    b += loss_slots(p) * sizeof(float) + 256;                     // loss partials, step/sync counters
+    b += loss_slots(p) * sizeof(float) + 256;                     // loss partials, step counter block
     b += 2 * p->t_vox.size() * sizeof(double);                    // objective partials
     b += 3 * (uint64_t)p->T * p->n * p->n * sizeof(float2);       // renders
+    b += vox;                                                     // data gradient (separate update pass)
     return b;
 }
 }  // namespace vp

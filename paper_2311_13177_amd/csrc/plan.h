@@ -16,6 +16,32 @@ namespace vp {
 vp_status fail(vp_status code, const char* fmt, ...);
 void clear_error();
 
+// Tile shape of the projection and gather work items (see vp_internal.h). Results never
+// depend on it: only the work decomposition changes.
+struct Tiles {
+    int proj_rows = 2, proj_gw = 1, gath_rows = 2, gath_sc = 1;
+    int upd_sc = 0;  // 0: update fused into the gather; else bins per wave of the update pass
+    int key() const { return proj_rows | proj_gw << 4 | gath_rows << 8 | gath_sc << 12 | upd_sc << 16; }
+    bool operator==(const Tiles& o) const { return key() == o.key(); }
+};
+
+// Projection groups and work lists of one tile shape.
+struct Layout {
+    Tiles tiles;
+    std::vector<ProjGroup> groups;
+    std::vector<Task> t_proj, t_gath, t_upd;
+    int re_proj = 0, re_gath = 0;  // largest staged region (elements) of an item
+};
+
+// A layout's tables on one device.
+struct DeviceLayout {
+    ProjGroup* groups = nullptr;
+    Task* t_proj = nullptr;
+    Task* t_gath = nullptr;
+    Task* t_upd = nullptr;
+    ~DeviceLayout();
+};
+
 // Per-device copies of a plan's constant tables and work lists.
 struct DeviceTables {
     int device = -1;
@@ -24,15 +50,13 @@ struct DeviceTables {
     BladeDev* blade = nullptr;
     int* knot_ptr = nullptr;
     KnotEntry* knot_ent = nullptr;
-    ProjGroup* groups = nullptr;
     KnotInfo* knots = nullptr;
     float2* tw = nullptr;
-    Task* t_proj = nullptr;
     Task* t_rows = nullptr;
     Task* t_cols = nullptr;
-    Task* t_gath = nullptr;
     Task* t_vox = nullptr;
     Task* t_render = nullptr;
+    std::map<int, std::unique_ptr<DeviceLayout>> layouts;  // by Tiles::key()
     ~DeviceTables();
 };
 
@@ -49,23 +73,22 @@ struct vp_plan {
     std::vector<float> alpha;            // [B]
     std::vector<int> knot_ptr;           // [T+1]
     std::vector<vp::KnotEntry> knot_ent;
-    std::vector<vp::ProjGroup> groups;
     std::vector<vp::KnotInfo> knots;    // [T]
-    int proj_gw = 1;                     // blade parts per wave in a projection item
-    int gath_sc = 1;                     // bins per wave in a gather item
+    int max_knot_parts = 0;              // most blade parts feeding one knot
     std::vector<float2> tw;              // [n]
     int nstage = 0;
     int radix[vp::kMaxStages] = {0};
     int nparts = 1;
     int n_col_items = 0;
-    // Work lists (slice index 0; batches rebase it).
-    std::vector<vp::Task> t_proj, t_rows, t_cols, t_gath, t_vox, t_render;
+    // Work lists of the tile-independent stages (slice index 0; batches rebase it).
+    std::vector<vp::Task> t_rows, t_cols, t_vox, t_render;
     // Dynamic LDS bytes per kernel.
     size_t lds_rows = 0, lds_cols = 0;
-    // Largest staged region (elements) of a projection / gather work item.
-    int re_proj = 0, re_gath = 0;
+    // The layout of the default tile shape, built and checked at creation.
+    vp::Tiles base_tiles;
 
     mutable std::mutex mu;
+    mutable std::map<int, std::unique_ptr<vp::Layout>> layouts;  // host layouts by Tiles::key()
     mutable std::map<int, std::unique_ptr<vp::DeviceTables>> dev;
 
     uint64_t voxels() const { return (uint64_t)T * S * n * n; }
@@ -77,8 +100,16 @@ namespace vp {
 // Device tables of `plan` on the current device, uploading them on first use.
 vp_status plan_tables(const vp_plan* plan, DeviceTables** out);
 
-// Fills the plan-constant part of a slice descriptor from device tables.
-void fill_desc(const vp_plan* plan, const DeviceTables* t, SliceDesc* d);
+// Host layout of `plan` for tile shape `t` (built on first use and kept with the plan).
+// VP_ERR_UNSUPPORTED if the shape is not compiled or a staged region would not fit.
+vp_status plan_layout(const vp_plan* plan, const Tiles& t, const Layout** out);
+// A layout's tables on the device of `tabs`, uploaded on first use.
+vp_status device_layout(const vp_plan* plan, DeviceTables* tabs, const Layout* L, const DeviceLayout** out);
+// Tile shape chosen without measuring, from the plan's sizes.
+Tiles heuristic_tiles(const vp_plan* plan);
+
+// Fills the plan-constant part of a slice descriptor from device tables and a layout.
+void fill_desc(const vp_plan* plan, const DeviceTables* t, const Layout* L, const DeviceLayout* dl, SliceDesc* d);
 
 // Loss partial slots (floats) per reconstruction.
 inline uint64_t loss_slots(const vp_plan* p) { return (uint64_t)p->B * p->n_col_items; }

@@ -11,10 +11,12 @@ namespace vp {
 
 // Kernel launchers (kernels.hip).
 // re: largest staged region (elements) over the work items' slices.
-hipError_t launch_project(const KArgs& a, int gw, int re, hipStream_t s);
+hipError_t launch_project(const KArgs& a, int rows, int gw, int re, hipStream_t s);
 hipError_t launch_rows(const KArgs& a, int dir, size_t lds, hipStream_t s);
 hipError_t launch_cols(const KArgs& a, size_t lds, hipStream_t s);
-hipError_t launch_gather(const KArgs& a, int mode, int re, hipStream_t s);
+hipError_t launch_gather(const KArgs& a, int mode, int rows, int sc, int re, hipStream_t s);
+hipError_t launch_update(const KArgs& a, int sc, hipStream_t s);
+hipError_t launch_advance(const KArgs& a, int nslices, hipStream_t s);
 hipError_t launch_tv_grad(const KArgs& a, hipStream_t s);
 hipError_t launch_reg_value(const KArgs& a, hipStream_t s);
 hipError_t launch_render(const KArgs& a, hipStream_t s);
@@ -27,23 +29,30 @@ struct StageLists {
     const Task* gath = nullptr;
     const Task* vox = nullptr;
     const Task* render = nullptr;
-    int n_proj = 0, n_rows = 0, n_cols = 0, n_gath = 0, n_vox = 0, n_render = 0;
-    int proj_gw = 1;
+    const Task* upd = nullptr;
+    int n_slices = 1;  // slices whose step counters the step advances
+    int n_proj = 0, n_rows = 0, n_cols = 0, n_gath = 0, n_vox = 0, n_render = 0, n_upd = 0;
+    Tiles tiles;
     size_t lds_rows = 0, lds_cols = 0;
     int re_proj = 0, re_gath = 0;  // largest staged regions (elements)
 };
 
-StageLists plan_lists(const vp_plan* p, const DeviceTables* t);
+StageLists plan_lists(const vp_plan* p, const DeviceTables* t, const Layout* L, const DeviceLayout* dl);
+// Tile shape for a plan under options: explicit tiles from the options, else the tuned
+// shape recorded for this plan's sizes on the device (tuning first when the options ask
+// for it and none is recorded), else the plan's heuristic shape.
+vp_status tiles_for(const vp_plan* p, const vp_options* o, Tiles* out);
+// Tuned shape recorded for the plan's sizes on `device`, if any.
+bool tuned_tiles(const vp_plan* p, int device, int optimizer, Tiles* out);
+// Measures the candidate tile shapes on the current device and records the fastest.
+vp_status tune_plan(const vp_plan* p, const vp_options* o, Tiles* out);
 // Enqueues one optimiser step (project, row DFT, column pass, inverse row DFT,
-// gather + update + step counter) for the descriptors `base` refers to.
+// gather + update, step counter advance) for the descriptors `base` refers to.
 // With `ev` (kStages + 1 events) an event is recorded before each stage and after the last.
 void launch_step(const KArgs& base, const StageLists& L, hipStream_t s, hipError_t* err, hipEvent_t* ev = nullptr);
 constexpr int kStages = 5;
-// Per-slice device counter block: the step counter (int at offset 0) and the count of
-// finished gather work items of the running step (unsigned at kSyncOffset words).
+// Per-slice device counter block: the step counter (int at offset 0).
 constexpr size_t kCounterBytes = 256;
-constexpr size_t kSyncOffset = 16;
-static_assert((kSyncOffset + 1) * sizeof(unsigned) <= kCounterBytes, "counter block too small");
 
 vp_status hip_status(hipError_t e, const char* what);
 vp_status check_options(const vp_plan* p, const vp_options* o);
@@ -57,6 +66,8 @@ struct vp_session {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     vp::DeviceTables* tabs = nullptr;
+    const vp::Layout* layout = nullptr;
+    const vp::DeviceLayout* dlayout = nullptr;
     float2* vol[2] = {nullptr, nullptr};
     float2* m = nullptr;
     float2* v = nullptr;
@@ -66,6 +77,7 @@ struct vp_session {
     int* step_dev = nullptr;
     double* dpart = nullptr;
     float2* render = nullptr;
+    float2* grad = nullptr;  // data gradient, allocated when a separate update pass runs
     int64_t steps_done = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -98,6 +110,8 @@ vp_status group_run(SliceGroup* g, int n_steps, bool use_graph);
 vp_status session_alloc(const vp_plan* p, const vp_options* o, const vp_c64* kspace, const vp_c64* init,
                         hipStream_t stream, vp_session** out);
 vp_status session_run(vp_session* s, int32_t n_steps, int32_t use_graph);
+// Allocates the session's data-gradient buffer (for a separate update pass) if missing.
+vp_status session_ensure_grad(vp_session* s);
 vp_status session_objective(vp_session* s, double* objective, double* data_term);
 vp_status session_read(vp_session* s, vp_c64* volume_out, vp_c64* proj_out, vp_c64* water_out, vp_c64* fat_out);
 }  // namespace vp

@@ -17,12 +17,18 @@ namespace vp {
 
 // ------------------------------------------------------------------ device tables
 
+DeviceLayout::~DeviceLayout() {
+    void* ptrs[] = {groups, t_proj, t_gath, t_upd};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+}
+
 DeviceTables::~DeviceTables() {
     int prev = -1;
     if (hipGetDevice(&prev) != hipSuccess) prev = -1;
     if (device >= 0) (void)hipSetDevice(device);
-    void* ptrs[] = {mask, shear, blade, knot_ptr, knot_ent, groups, knots, tw, t_proj, t_rows, t_cols, t_gath, t_vox,
-                    t_render};
+    layouts.clear();
+    void* ptrs[] = {mask, shear, blade, knot_ptr, knot_ent, knots, tw, t_rows, t_cols, t_vox, t_render};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (prev >= 0) (void)hipSetDevice(prev);
@@ -67,13 +73,10 @@ vp_status plan_tables(const vp_plan* p, DeviceTables** out) {
     UP(blade, p->blade);
     UP(knot_ptr, p->knot_ptr);
     UP(knot_ent, p->knot_ent);
-    UP(groups, p->groups);
     UP(knots, p->knots);
     UP(tw, p->tw);
-    UP(t_proj, p->t_proj);
     UP(t_rows, p->t_rows);
     UP(t_cols, p->t_cols);
-    UP(t_gath, p->t_gath);
     UP(t_vox, p->t_vox);
     UP(t_render, p->t_render);
 #undef UP
@@ -82,7 +85,31 @@ vp_status plan_tables(const vp_plan* p, DeviceTables** out) {
     return VP_OK;
 }
 
-void fill_desc(const vp_plan* p, const DeviceTables* t, SliceDesc* d) {
+vp_status device_layout(const vp_plan* p, DeviceTables* t, const Layout* L, const DeviceLayout** out) {
+    std::lock_guard<std::mutex> lk(p->mu);
+    auto it = t->layouts.find(L->tiles.key());
+    if (it != t->layouts.end()) {
+        *out = it->second.get();
+        return VP_OK;
+    }
+    int prev = -1;
+    hipError_t e = hipGetDevice(&prev);
+    if (e != hipSuccess) return hip_status(e, "hipGetDevice");
+    if (prev != t->device && (e = hipSetDevice(t->device)) != hipSuccess) return hip_status(e, "hipSetDevice");
+    std::unique_ptr<DeviceLayout> d(new (std::nothrow) DeviceLayout());
+    if (!d) return fail(VP_ERR_NOMEM, "layout tables: out of host memory");
+    e = upload(&d->groups, L->groups);
+    if (e == hipSuccess) e = upload(&d->t_proj, L->t_proj);
+    if (e == hipSuccess) e = upload(&d->t_gath, L->t_gath);
+    if (e == hipSuccess) e = upload(&d->t_upd, L->t_upd);
+    if (prev != t->device) (void)hipSetDevice(prev);
+    if (e != hipSuccess) return hip_status(e, "layout tables");
+    *out = d.get();
+    t->layouts.emplace(L->tiles.key(), std::move(d));
+    return VP_OK;
+}
+
+void fill_desc(const vp_plan* p, const DeviceTables* t, const Layout* L, const DeviceLayout* dl, SliceDesc* d) {
     std::memset(d, 0, sizeof *d);
     d->n = p->n;
     d->S = p->S;
@@ -100,10 +127,8 @@ void fill_desc(const vp_plan* p, const DeviceTables* t, SliceDesc* d) {
     d->blade = t->blade;
     d->knot_ptr = t->knot_ptr;
     d->knot_ent = t->knot_ent;
-    d->groups = t->groups;
+    d->groups = dl->groups;
     d->knots = t->knots;
-    d->n_gath_tasks = (int)p->t_gath.size();
-    d->gath_sc = p->gath_sc;
     d->step_limit = 0x7fffffff;
     d->schedule = VP_SCHED_ALL_BLADES;
     d->optimizer = VP_OPT_ADAM;
@@ -115,6 +140,8 @@ static void set_hyper(SliceDesc* d, const vp_options* o) {
     d->lr = o->lr;
     d->beta1 = o->beta1;
     d->beta2 = o->beta2;
+    d->ln_beta1 = (float)std::log((double)o->beta1);
+    d->ln_beta2 = (float)std::log((double)o->beta2);
     d->adam_eps = o->adam_eps;
     d->tv_w = o->tv_weight;
     d->l1_w = o->l1_weight;
@@ -135,6 +162,12 @@ vp_status check_options(const vp_plan* p, const vp_options* o) {
     if (o->optimizer == VP_OPT_ADAM && (o->beta1 < 0 || o->beta1 >= 1 || o->beta2 < 0 || o->beta2 >= 1))
         return fail(VP_ERR_ARG, "options: betas must lie in [0, 1)");
     if (o->split_bin > p->S) return fail(VP_ERR_ARG, "options: split_bin above n_spec");
+    const vp_tiles& t = o->tiles;
+    const bool none = !t.proj_rows && !t.proj_parts && !t.gath_rows && !t.gath_bins && !t.upd_bins;
+    if (!none && (!proj_tiles_ok(t.proj_rows, t.proj_parts) || !gath_tiles_ok(t.gath_rows, t.gath_bins) ||
+                  !upd_tiles_ok(t.upd_bins)))
+        return fail(VP_ERR_UNSUPPORTED, "options: tile shape (%d, %d, %d, %d, %d) is not compiled", t.proj_rows,
+                    t.proj_parts, t.gath_rows, t.gath_bins, t.upd_bins);
     return VP_OK;
 }
 
@@ -149,7 +182,7 @@ void launch_step(const KArgs& base, const StageLists& L, hipStream_t s, hipError
     } while (0)
     MARK(0);
     a.tasks = L.proj; a.ntasks = L.n_proj;
-    if ((e = launch_project(a, L.proj_gw, L.re_proj, s)) != hipSuccess) { *err = e; return; }
+    if ((e = launch_project(a, L.tiles.proj_rows, L.tiles.proj_gw, L.re_proj, s)) != hipSuccess) { *err = e; return; }
     MARK(1);
     a.tasks = L.rows; a.ntasks = L.n_rows;
     if ((e = launch_rows(a, -1, L.lds_rows, s)) != hipSuccess) { *err = e; return; }
@@ -161,22 +194,35 @@ void launch_step(const KArgs& base, const StageLists& L, hipStream_t s, hipError
     if ((e = launch_rows(a, 1, L.lds_rows, s)) != hipSuccess) { *err = e; return; }
     MARK(4);
     a.tasks = L.gath; a.ntasks = L.n_gath;
-    if ((e = launch_gather(a, GATHER_STEP, L.re_gath, s)) != hipSuccess) { *err = e; return; }
+    if (L.tiles.upd_sc == 0) {
+        e = launch_gather(a, GATHER_STEP, L.tiles.gath_rows, L.tiles.gath_sc, L.re_gath, s);
+    } else {
+        a.accumulate = 0;
+        e = launch_gather(a, GATHER_STORE, L.tiles.gath_rows, L.tiles.gath_sc, L.re_gath, s);
+        a.tasks = L.upd; a.ntasks = L.n_upd;
+        if (e == hipSuccess) e = launch_update(a, L.tiles.upd_sc, s);
+    }
+    if (e == hipSuccess) e = launch_advance(base, L.n_slices, s);
+    if (e != hipSuccess) {
+        *err = e;
+        return;
+    }
     MARK(5);
 #undef MARK
     *err = hipSuccess;
 }
 
-StageLists plan_lists(const vp_plan* p, const DeviceTables* t) {
+StageLists plan_lists(const vp_plan* p, const DeviceTables* t, const Layout* lay, const DeviceLayout* dl) {
     StageLists L;
-    L.proj = t->t_proj; L.n_proj = (int)p->t_proj.size();
+    L.proj = dl->t_proj; L.n_proj = (int)lay->t_proj.size();
     L.rows = t->t_rows; L.n_rows = (int)p->t_rows.size();
     L.cols = t->t_cols; L.n_cols = (int)p->t_cols.size();
-    L.gath = t->t_gath; L.n_gath = (int)p->t_gath.size();
+    L.gath = dl->t_gath; L.n_gath = (int)lay->t_gath.size();
+    L.upd = dl->t_upd; L.n_upd = (int)lay->t_upd.size();
     L.vox = t->t_vox; L.n_vox = (int)p->t_vox.size();
     L.render = t->t_render; L.n_render = (int)p->t_render.size();
-    L.proj_gw = p->proj_gw;
-    L.re_proj = p->re_proj; L.lds_rows = p->lds_rows; L.lds_cols = p->lds_cols; L.re_gath = p->re_gath;
+    L.tiles = lay->tiles;
+    L.re_proj = lay->re_proj; L.lds_rows = p->lds_rows; L.lds_cols = p->lds_cols; L.re_gath = lay->re_gath;
     return L;
 }
 
@@ -195,14 +241,24 @@ extern "C" vp_status vp_plan_destroy(vp_plan* p) {
 
 namespace {
 
+// Operator calls use the tuned tile shape recorded for the plan's sizes on the current
+// device, else the plan's heuristic shape.
 struct OpScope {
     const vp_plan* p;
     DeviceTables* t = nullptr;
+    const Layout* lay = nullptr;
+    const DeviceLayout* dl = nullptr;
     hipStream_t s;
     float2* work = nullptr;
     explicit OpScope(const vp_plan* plan, void* stream) : p(plan), s((hipStream_t)stream) {}
     vp_status begin(bool need_work) {
         vp_status st = plan_tables(p, &t);
+        if (st != VP_OK) return st;
+        Tiles tl = p->base_tiles;
+        (void)tuned_tiles(p, t->device, VP_OPT_ADAM, &tl);
+        st = plan_layout(p, tl, &lay);
+        if (st != VP_OK) st = plan_layout(p, p->base_tiles, &lay);
+        if (st == VP_OK) st = device_layout(p, t, lay, &dl);
         if (st != VP_OK) return st;
         if (need_work) {
             const size_t bytes = (size_t)p->nparts * p->blade_px() * sizeof(float2);
@@ -226,14 +282,15 @@ extern "C" vp_status vp_forward(const vp_plan* p, const vp_c64* d_vol, const vp_
     vp_status st = sc.begin(true);
     if (st != VP_OK) return st;
     KArgs a{};
-    fill_desc(p, sc.t, &a.one);
+    fill_desc(p, sc.t, sc.lay, sc.dl, &a.one);
     a.one.vol[0] = (float2*)d_vol;
     a.one.y = (const float2*)d_y;
     a.one.work = sc.work;
-    const StageLists L = plan_lists(p, sc.t);
+    const StageLists L = plan_lists(p, sc.t, sc.lay, sc.dl);
     hipError_t e;
     a.tasks = L.proj; a.ntasks = L.n_proj;
-    if ((e = launch_project(a, L.proj_gw, L.re_proj, sc.s)) != hipSuccess) return hip_status(e, "vp_forward project");
+    if ((e = launch_project(a, L.tiles.proj_rows, L.tiles.proj_gw, L.re_proj, sc.s)) != hipSuccess)
+        return hip_status(e, "vp_forward project");
     a.tasks = L.rows; a.ntasks = L.n_rows;
     if ((e = launch_rows(a, -1, L.lds_rows, sc.s)) != hipSuccess) return hip_status(e, "vp_forward rows");
     a.tasks = L.cols; a.ntasks = L.n_cols; a.mode = COL_FORWARD; a.out0 = (float2*)d_out;
@@ -249,18 +306,19 @@ extern "C" vp_status vp_adjoint(const vp_plan* p, const vp_c64* d_kres, vp_c64* 
     vp_status st = sc.begin(true);
     if (st != VP_OK) return st;
     KArgs a{};
-    fill_desc(p, sc.t, &a.one);
+    fill_desc(p, sc.t, sc.lay, sc.dl, &a.one);
     a.one.work = sc.work;
     a.one.grad = (float2*)d_grad;
     a.accumulate = accumulate != 0;
-    const StageLists L = plan_lists(p, sc.t);
+    const StageLists L = plan_lists(p, sc.t, sc.lay, sc.dl);
     hipError_t e;
     a.tasks = L.cols; a.ntasks = L.n_cols; a.mode = COL_ADJOINT; a.in0 = (const float2*)d_kres;
     if ((e = launch_cols(a, L.lds_cols, sc.s)) != hipSuccess) return hip_status(e, "vp_adjoint cols");
     a.tasks = L.rows; a.ntasks = L.n_rows;
     if ((e = launch_rows(a, 1, L.lds_rows, sc.s)) != hipSuccess) return hip_status(e, "vp_adjoint rows");
     a.tasks = L.gath; a.ntasks = L.n_gath;
-    if ((e = launch_gather(a, GATHER_STORE, L.re_gath, sc.s)) != hipSuccess) return hip_status(e, "vp_adjoint gather");
+    if ((e = launch_gather(a, GATHER_STORE, L.tiles.gath_rows, L.tiles.gath_sc, L.re_gath, sc.s)) != hipSuccess)
+        return hip_status(e, "vp_adjoint gather");
     return VP_OK;
 }
 
@@ -274,7 +332,7 @@ extern "C" vp_status vp_tv_grad(const vp_plan* p, const vp_c64* d_vol, float tv_
     vp_status st = sc.begin(false);
     if (st != VP_OK) return st;
     KArgs a{};
-    fill_desc(p, sc.t, &a.one);
+    fill_desc(p, sc.t, sc.lay, sc.dl, &a.one);
     a.one.vol[0] = (float2*)d_vol;
     a.one.grad = (float2*)d_grad;
     a.one.tv_w = tv_w;
@@ -296,7 +354,7 @@ extern "C" vp_status vp_render(const vp_plan* p, const vp_c64* d_vol, int32_t sp
     vp_status st = sc.begin(false);
     if (st != VP_OK) return st;
     KArgs a{};
-    fill_desc(p, sc.t, &a.one);
+    fill_desc(p, sc.t, sc.lay, sc.dl, &a.one);
     a.one.vol[0] = (float2*)d_vol;
     a.split_bin = split_bin;
     a.out0 = (float2*)d_proj;
@@ -314,7 +372,7 @@ vp_session::~vp_session() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
     if (stream) (void)hipStreamSynchronize(stream);
-    void* ptrs[] = {vol[0], vol[1], m, v, work, y, loss_part, step_dev, dpart, render};
+    void* ptrs[] = {vol[0], vol[1], m, v, work, y, loss_part, step_dev, dpart, render, grad};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     if (stream && own_stream) (void)hipStreamDestroy(stream);
@@ -352,6 +410,11 @@ vp_status session_alloc(const vp_plan* p, const vp_options* o, const vp_c64* ksp
     }
     st = plan_tables(p, &s->tabs);
     if (st != VP_OK) return st;
+    Tiles tl;
+    st = tiles_for(p, o, &tl);
+    if (st == VP_OK) st = plan_layout(p, tl, &s->layout);
+    if (st == VP_OK) st = device_layout(p, s->tabs, s->layout, &s->dlayout);
+    if (st != VP_OK) return st;
     const size_t vb = p->voxels() * sizeof(float2);
     const size_t bb = p->blade_px() * sizeof(float2);
 #define ALLOC(ptr, bytes)                                               \
@@ -381,7 +444,7 @@ vp_status session_alloc(const vp_plan* p, const vp_options* o, const vp_c64* ksp
     if (e == hipSuccess) e = hipMemsetAsync(s->loss_part, 0, loss_slots(p) * sizeof(float), s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return hip_status(e, "session upload");
-    fill_desc(p, s->tabs, &s->desc);
+    fill_desc(p, s->tabs, s->layout, s->dlayout, &s->desc);
     set_hyper(&s->desc, o);
     s->desc.vol[0] = s->vol[0];
     s->desc.vol[1] = s->vol[1];
@@ -391,9 +454,18 @@ vp_status session_alloc(const vp_plan* p, const vp_options* o, const vp_c64* ksp
     s->desc.y = s->y;
     s->desc.loss_part = s->loss_part;
     s->desc.step = s->step_dev;
-    s->desc.sync = reinterpret_cast<unsigned*>(s->step_dev) + kSyncOffset;
-    s->lists = plan_lists(p, s->tabs);
+    s->lists = plan_lists(p, s->tabs, s->layout, s->dlayout);
+    if (tl.upd_sc && (st = session_ensure_grad(s.get())) != VP_OK) return st;
     *out = s.release();
+    return VP_OK;
+}
+
+vp_status session_ensure_grad(vp_session* s) {
+    if (s->grad) return VP_OK;
+    hipError_t e = hipSetDevice(s->device);
+    if (e == hipSuccess) e = hipMalloc((void**)&s->grad, std::max<size_t>(8, s->plan->voxels() * sizeof(float2)));
+    if (e != hipSuccess) return hip_status(e, "data gradient allocation");
+    s->desc.grad = s->grad;
     return VP_OK;
 }
 
@@ -438,7 +510,8 @@ vp_status session_objective(vp_session* s, double* objective, double* data_term)
     a.one.step_limit = 0x7fffffff;
     const StageLists& L = s->lists;
     a.tasks = L.proj; a.ntasks = L.n_proj;
-    if ((e = launch_project(a, L.proj_gw, L.re_proj, s->stream)) != hipSuccess) return hip_status(e, "objective");
+    if ((e = launch_project(a, L.tiles.proj_rows, L.tiles.proj_gw, L.re_proj, s->stream)) != hipSuccess)
+        return hip_status(e, "objective");
     a.tasks = L.rows; a.ntasks = L.n_rows;
     if ((e = launch_rows(a, -1, L.lds_rows, s->stream)) != hipSuccess) return hip_status(e, "objective");
     a.tasks = L.cols; a.ntasks = L.n_cols; a.mode = COL_STEP;

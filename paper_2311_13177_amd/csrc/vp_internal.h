@@ -23,13 +23,24 @@ constexpr int kMaxStages = 12;
 constexpr double kMaxShift = 16.0;
 constexpr int kThreads = 256;
 
-// Projection and gather tiles: 64 columns (one per lane of a wave) by kTileRows rows.
-// A projection work item covers one tile for a group of up to 4 * GW blade parts of one
-// knot (parts dealt round-robin to the block's four waves); a gather work item covers
-// one tile for 4 * sc spectral bins (sc consecutive bins per wave, sc <= kChunkMax).
+// Projection and gather tiles: 64 columns (one per lane of a wave) by a per-layout
+// number of rows. A projection work item covers one tile for a group of up to 4 * GW
+// blade parts of one knot (parts dealt round-robin to the block's four waves); a gather
+// work item covers one tile for 4 * SC spectral bins (SC consecutive bins per wave).
+// Rows, GW and SC are template parameters of the kernels; these are the compiled
+// combinations (at most 16 accumulators per lane).
 constexpr int kTileW = 64;
-constexpr int kTileRows = 2;
-constexpr int kChunkMax = 8;
+constexpr int kXcds = 8;  // accelerator complex dies, each with its own L2
+__host__ __device__ constexpr bool pow2_le(int v, int hi) { return v >= 1 && v <= hi && (v & (v - 1)) == 0; }
+__host__ __device__ constexpr bool proj_tiles_ok(int rows, int gw) {
+    return pow2_le(rows, 8) && pow2_le(gw, 8) && rows * gw <= 16;
+}
+__host__ __device__ constexpr bool gath_tiles_ok(int rows, int sc) {
+    return pow2_le(rows, 4) && rows >= 2 && pow2_le(sc, 8) && rows * sc <= 16;
+}
+// The optimiser update runs fused into the gather (0) or as a separate pass over the
+// stored data gradient with 2, 4 or 8 bins per wave.
+__host__ __device__ constexpr bool upd_tiles_ok(int sc) { return sc == 0 || sc == 2 || sc == 4 || sc == 8; }
 // Staged region elements per thread (register prefetch depth of the LDS staging).
 constexpr int kStageMax = 16;
 // A staged region of re elements (re <= kStageMax * kThreads) is loaded several planes
@@ -107,15 +118,14 @@ struct SliceDesc {
     float2* m;
     float2* v;
     float2* work;
-    float2* grad;                // gradient output of the operator path
+    float2* grad;                // gradient output of the operator path, or the data
+                                 // gradient a step stores for a separate update pass
     float* loss_part;            // [B][n_col_items]
     int* step;                   // device step counter; nullptr for operator calls
-    unsigned* sync;              // gather work items finished this step (the last one advances *step)
-    int n_gath_tasks;            // gather work items of this slice per step
-    int gath_sc;                 // spectral bins per wave in a gather work item
     int step_limit;              // work items of slices with *step >= step_limit exit
     int optimizer, schedule;
     float lr, beta1, beta2, adam_eps;
+    float ln_beta1, ln_beta2;    // log(beta) in FP64, rounded: bias corrections -expm1(t ln beta)
     float tv_w, l1_w, tv_eps;
 };
 

@@ -117,9 +117,9 @@ def test_device_bytes_formula(B):
     got = plan.device_bytes(opts)
     vox = 32 * 256 * 256 * 8
     blade = 12 * 256 * 256 * 8
-    # volume ping-pong + Adam moments + blade work + measurements
-    assert got >= 4 * vox + 2 * blade
-    assert got < 4 * vox + 2 * blade + 4 * 1024 * 1024
+    # volume ping-pong + Adam moments + data gradient + blade work + measurements
+    assert got >= 5 * vox + 2 * blade
+    assert got < 5 * vox + 2 * blade + 4 * 1024 * 1024
     gd = B.vp_options_default(optimizer=B.VP_OPT_GD)
     assert plan.device_bytes(gd) == got - 2 * vox
 
