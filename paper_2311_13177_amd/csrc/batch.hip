@@ -56,7 +56,8 @@ static Tiles group_tiles(const std::vector<vp_session*>& sessions) {
 vp_status group_build(SliceGroup* g, const std::vector<vp_session*>& sessions, const std::vector<int>& limits) {
     g->drop_graph();
     const int ns = (int)sessions.size();
-    std::vector<SliceDesc> descs(ns);
+    std::vector<SliceDesc>& descs = g->h_descs;
+    descs.assign(ns, SliceDesc{});
     std::vector<Task> proj, rows, cols, gath, vox, render, upd;
     StageLists L;
     if (ns) L.tiles = group_tiles(sessions);
@@ -89,25 +90,40 @@ vp_status group_build(SliceGroup* g, const std::vector<vp_session*>& sessions, c
         L.lds_cols = std::max(L.lds_cols, p->lds_cols);
         L.re_gath = std::max(L.re_gath, lay->re_gath);
     }
-    std::vector<Task> all;
+    std::vector<Task>& all = g->h_tasks;
+    all.clear();
     size_t off[7];
     const std::vector<Task>* parts[7] = {&proj, &rows, &cols, &gath, &vox, &render, &upd};
     for (int k = 0; k < 7; ++k) {
         off[k] = all.size();
         all.insert(all.end(), parts[k]->begin(), parts[k]->end());
     }
-    if (g->d_descs) (void)hipFree(g->d_descs);
-    if (g->d_tasks) (void)hipFree(g->d_tasks);
-    g->d_descs = nullptr;
-    g->d_tasks = nullptr;
-    hipError_t e = hipMalloc((void**)&g->d_descs, std::max<size_t>(1, descs.size()) * sizeof(SliceDesc));
-    if (e == hipSuccess) e = hipMalloc((void**)&g->d_tasks, std::max<size_t>(1, all.size()) * sizeof(Task));
+    hipError_t e = hipSuccess;
+    // device buffers only grow (a reallocation waits for the stream to finish the old one)
+    if (descs.size() > g->cap_descs || all.size() > g->cap_tasks) {
+        e = hipStreamSynchronize(g->stream);
+        if (e == hipSuccess && descs.size() > g->cap_descs) {
+            if (g->d_descs) (void)hipFree(g->d_descs);
+            g->d_descs = nullptr;
+            g->cap_descs = 0;
+            const size_t cap = std::max<size_t>(8, 2 * descs.size());
+            e = hipMalloc((void**)&g->d_descs, cap * sizeof(SliceDesc));
+            if (e == hipSuccess) g->cap_descs = cap;
+        }
+        if (e == hipSuccess && all.size() > g->cap_tasks) {
+            if (g->d_tasks) (void)hipFree(g->d_tasks);
+            g->d_tasks = nullptr;
+            g->cap_tasks = 0;
+            const size_t cap = std::max<size_t>(1024, all.size() + all.size() / 2);
+            e = hipMalloc((void**)&g->d_tasks, cap * sizeof(Task));
+            if (e == hipSuccess) g->cap_tasks = cap;
+        }
+    }
     if (e == hipSuccess && ns)
         e = hipMemcpyAsync(g->d_descs, descs.data(), descs.size() * sizeof(SliceDesc), hipMemcpyHostToDevice,
                            g->stream);
     if (e == hipSuccess && !all.empty())
         e = hipMemcpyAsync(g->d_tasks, all.data(), all.size() * sizeof(Task), hipMemcpyHostToDevice, g->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
     if (e != hipSuccess) return hip_status(e, "slice group upload");
     L.proj = g->d_tasks + off[0]; L.n_proj = (int)proj.size();
     L.rows = g->d_tasks + off[1]; L.n_rows = (int)rows.size();

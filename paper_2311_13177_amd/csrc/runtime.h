@@ -78,6 +78,7 @@ struct vp_session {
     double* dpart = nullptr;
     float2* render = nullptr;
     float2* grad = nullptr;  // data gradient, allocated when a separate update pass runs
+    void* h_part = nullptr;  // pinned objective partials (doubles, then loss floats)
     int64_t steps_done = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -95,6 +96,9 @@ struct SliceGroup {
     hipStream_t stream = nullptr;
     SliceDesc* d_descs = nullptr;
     Task* d_tasks = nullptr;
+    size_t cap_descs = 0, cap_tasks = 0;  // device capacities (grow only)
+    std::vector<SliceDesc> h_descs;       // host copies, kept until the stream has read them
+    std::vector<Task> h_tasks;
     StageLists lists{};
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -102,16 +106,25 @@ struct SliceGroup {
     void drop_graph();
 };
 // Builds descriptors and concatenated work lists for `sessions` (slice i = sessions[i],
-// stopping at limits[i] steps); drops any captured graph.
+// stopping at limits[i] steps) and enqueues their upload on the group's stream (no
+// wait); drops any captured graph. Call it only once the stream has passed the previous
+// upload (the host copies are reused).
 vp_status group_build(SliceGroup* g, const std::vector<vp_session*>& sessions, const std::vector<int>& limits);
 // Enqueues n_steps steps of every slice of the group (use_graph: capture one step once).
 vp_status group_run(SliceGroup* g, int n_steps, bool use_graph);
 
+// Allocates and uploads a session on `stream` (nullptr: a stream of its own). The initial
+// state is enqueued on `upload` (nullptr: the session stream) and waited for if `wait`;
+// otherwise the caller keeps kspace and init alive until that stream has passed them.
 vp_status session_alloc(const vp_plan* p, const vp_options* o, const vp_c64* kspace, const vp_c64* init,
-                        hipStream_t stream, vp_session** out);
+                        hipStream_t stream, vp_session** out, hipStream_t upload = nullptr, bool wait = true);
 vp_status session_run(vp_session* s, int32_t n_steps, int32_t use_graph);
 // Allocates the session's data-gradient buffer (for a separate update pass) if missing.
 vp_status session_ensure_grad(vp_session* s);
 vp_status session_objective(vp_session* s, double* objective, double* data_term);
+// The objective in two halves: kernels and pinned read-back enqueued on `stream`, then
+// (after the caller has synchronised that stream) the host reduction.
+vp_status session_objective_enqueue(vp_session* s, hipStream_t stream);
+vp_status session_objective_finish(vp_session* s, double* objective, double* data_term);
 vp_status session_read(vp_session* s, vp_c64* volume_out, vp_c64* proj_out, vp_c64* water_out, vp_c64* fat_out);
 }  // namespace vp

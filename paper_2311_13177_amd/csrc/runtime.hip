@@ -375,6 +375,7 @@ vp_session::~vp_session() {
     void* ptrs[] = {vol[0], vol[1], m, v, work, y, loss_part, step_dev, dpart, render, grad};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
+    if (h_part) (void)hipHostFree(h_part);
     if (stream && own_stream) (void)hipStreamDestroy(stream);
 }
 
@@ -387,7 +388,7 @@ static bool all_finite(const vp_c64* a, size_t n) {
 }
 
 vp_status session_alloc(const vp_plan* p, const vp_options* o, const vp_c64* kspace, const vp_c64* init,
-                        hipStream_t stream, vp_session** out) {
+                        hipStream_t stream, vp_session** out, hipStream_t upload, bool wait) {
     vp_status st = check_options(p, o);
     if (st != VP_OK) return st;
     if (!kspace) return fail(VP_ERR_ARG, "session: NULL kspace");
@@ -435,14 +436,17 @@ vp_status session_alloc(const vp_plan* p, const vp_options* o, const vp_c64* ksp
     ALLOC(s->dpart, 2 * p->t_vox.size() * sizeof(double));
     ALLOC(s->render, 3 * (size_t)p->T * p->n * p->n * sizeof(float2));
 #undef ALLOC
-    if (init) e = hipMemcpyAsync(s->vol[0], init, vb, hipMemcpyHostToDevice, s->stream);
-    else e = hipMemsetAsync(s->vol[0], 0, vb, s->stream);
-    if (e == hipSuccess && s->m) e = hipMemsetAsync(s->m, 0, vb, s->stream);
-    if (e == hipSuccess && s->v) e = hipMemsetAsync(s->v, 0, vb, s->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(s->y, kspace, bb, hipMemcpyHostToDevice, s->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(s->step_dev, 0, kCounterBytes, s->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(s->loss_part, 0, loss_slots(p) * sizeof(float), s->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    // initial state on `upload` (else the session stream); waited for unless the caller
+    // relies on stream order
+    hipStream_t us = upload ? upload : s->stream;
+    if (init) e = hipMemcpyAsync(s->vol[0], init, vb, hipMemcpyHostToDevice, us);
+    else e = hipMemsetAsync(s->vol[0], 0, vb, us);
+    if (e == hipSuccess && s->m) e = hipMemsetAsync(s->m, 0, vb, us);
+    if (e == hipSuccess && s->v) e = hipMemsetAsync(s->v, 0, vb, us);
+    if (e == hipSuccess) e = hipMemcpyAsync(s->y, kspace, bb, hipMemcpyHostToDevice, us);
+    if (e == hipSuccess) e = hipMemsetAsync(s->step_dev, 0, kCounterBytes, us);
+    if (e == hipSuccess) e = hipMemsetAsync(s->loss_part, 0, loss_slots(p) * sizeof(float), us);
+    if (e == hipSuccess && wait) e = hipStreamSynchronize(us);
     if (e != hipSuccess) return hip_status(e, "session upload");
     fill_desc(p, s->tabs, s->layout, s->dlayout, &s->desc);
     set_hyper(&s->desc, o);
@@ -501,36 +505,59 @@ vp_status session_run(vp_session* s, int32_t n_steps, int32_t use_graph) {
 }
 
 vp_status session_objective(vp_session* s, double* objective, double* data_term) {
+    vp_status st = session_objective_enqueue(s, s->stream);
+    if (st != VP_OK) return st;
+    st = hip_status(hipStreamSynchronize(s->stream), "objective readback");
+    if (st != VP_OK) return st;
+    return session_objective_finish(s, objective, data_term);
+}
+
+vp_status session_objective_enqueue(vp_session* s, hipStream_t stream) {
     const vp_plan* p = s->plan;
     hipError_t e = hipSetDevice(s->device);
     if (e != hipSuccess) return hip_status(e, "hipSetDevice");
+    if (!s->h_part) {
+        // pinned, so that the copies below are truly asynchronous
+        const size_t bytes = loss_slots(p) * sizeof(float) + 2 * p->t_vox.size() * sizeof(double);
+        e = hipHostMalloc((void**)&s->h_part, std::max<size_t>(16, bytes + 8), hipHostMallocDefault);
+        if (e != hipSuccess) {
+            s->h_part = nullptr;
+            return hip_status(e, "objective staging");
+        }
+    }
     KArgs a{};
     a.one = s->desc;
     a.one.schedule = VP_SCHED_ALL_BLADES;
     a.one.step_limit = 0x7fffffff;
     const StageLists& L = s->lists;
     a.tasks = L.proj; a.ntasks = L.n_proj;
-    if ((e = launch_project(a, L.tiles.proj_rows, L.tiles.proj_gw, L.re_proj, s->stream)) != hipSuccess)
+    if ((e = launch_project(a, L.tiles.proj_rows, L.tiles.proj_gw, L.re_proj, stream)) != hipSuccess)
         return hip_status(e, "objective");
     a.tasks = L.rows; a.ntasks = L.n_rows;
-    if ((e = launch_rows(a, -1, L.lds_rows, s->stream)) != hipSuccess) return hip_status(e, "objective");
+    if ((e = launch_rows(a, -1, L.lds_rows, stream)) != hipSuccess) return hip_status(e, "objective");
     a.tasks = L.cols; a.ntasks = L.n_cols; a.mode = COL_STEP;
-    if ((e = launch_cols(a, L.lds_cols, s->stream)) != hipSuccess) return hip_status(e, "objective");
+    if ((e = launch_cols(a, L.lds_cols, stream)) != hipSuccess) return hip_status(e, "objective");
     a.tasks = L.vox; a.ntasks = L.n_vox; a.dpart = s->dpart;
-    if ((e = launch_reg_value(a, s->stream)) != hipSuccess) return hip_status(e, "objective");
-    std::vector<float> lp(loss_slots(p));
-    std::vector<double> dp(2 * p->t_vox.size());
-    e = hipMemcpyAsync(lp.data(), s->loss_part, lp.size() * sizeof(float), hipMemcpyDeviceToHost, s->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(dp.data(), s->dpart, dp.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-    if (e != hipSuccess) return hip_status(e, "objective readback");
+    if ((e = launch_reg_value(a, stream)) != hipSuccess) return hip_status(e, "objective");
+    const size_t nl = loss_slots(p), nd = 2 * p->t_vox.size();
+    double* hd = reinterpret_cast<double*>(s->h_part);
+    float* hl = reinterpret_cast<float*>(hd + nd);
+    e = hipMemcpyAsync(hl, s->loss_part, nl * sizeof(float), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(hd, s->dpart, nd * sizeof(double), hipMemcpyDeviceToHost, stream);
+    return hip_status(e, "objective readback");
+}
+
+vp_status session_objective_finish(vp_session* s, double* objective, double* data_term) {
+    const vp_plan* p = s->plan;
+    const size_t nl = loss_slots(p), nd = 2 * p->t_vox.size();
+    const double* hd = reinterpret_cast<const double*>(s->h_part);
+    const float* hl = reinterpret_cast<const float*>(hd + nd);
     double data = 0.0, tv = 0.0, l1 = 0.0;
-    for (float x : lp) data += (double)x;
+    for (size_t i = 0; i < nl; ++i) data += (double)hl[i];
     data *= 0.5;
     for (size_t i = 0; i < p->t_vox.size(); ++i) {
-        tv += dp[2 * i];
-        l1 += dp[2 * i + 1];
+        tv += hd[2 * i];
+        l1 += hd[2 * i + 1];
     }
     const double obj = data + (double)s->opts.tv_weight * tv + (double)s->opts.l1_weight * l1;
     if (objective) *objective = obj;

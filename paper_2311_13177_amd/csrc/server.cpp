@@ -1,18 +1,21 @@
 // Reconstruction server: continuous batching of requests of mixed sizes on one device.
 //
-// A worker thread owns the batched stepping. Each iteration it launches one super-step
-// (up to kSuperSteps optimiser steps for every resident request, one launch per stage
-// over the concatenated work lists, each request stopping at its own step count) and,
-// while that runs on the device, finalises requests that completed in the previous
-// super-step (objective on the request's own stream) and uploads newly admitted ones
-// (admission in arrival order while the sum of device bytes stays within the budget
-// and a slot is free). Requests join and leave only at super-step boundaries. A
+// A worker thread admits queued requests in arrival order while a slot is free and the
+// sum of their device bytes stays within the budget; each admitted request keeps its
+// optimiser state resident and advances on its own stream, replaying its captured step
+// (its own tuned tile shape, the same kernels as alone). The oldest resident requests
+// step at a time (as many as fill the device), their work overlapping on it; the worker
+// keeps up to kDepth super-steps (kSuperSteps optimiser steps each) enqueued for each,
+// with the objective behind the last one, and handles completions in enqueue order,
+// topping the queues up as it goes. Requests that arrive while others run are admitted (state
+// uploaded) as soon as a slot and memory free up, and start stepping without delay. A
 // finished request keeps its device state until vp_server_wait copies the volume and
 // renders straight into the caller's buffers on the caller's thread and releases it.
 // A request's arithmetic does not depend on the mix it runs in, so its result equals
 // the one vp_reconstruct computes for it alone.
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -31,8 +34,16 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
-// Steps per super-step: requests join and leave only at super-step boundaries.
+// Steps per super-step; super-steps kept enqueued per stepping request. Resident
+// requests with work still to enqueue step together, the oldest first, up to kStepping
+// of them and until their volumes reach kFillVoxels (at least one): a large
+// reconstruction saturates the device's memory system on its own, and several at once
+// would only thrash each other's caches, while small ones share the device. The others
+// wait with their state uploaded.
 constexpr int kSuperSteps = 8;
+constexpr int kDepth = 2;
+constexpr int kStepping = 4;
+constexpr uint64_t kFillVoxels = uint64_t(1) << 23;
 
 enum class RState { Queued, Running, Done, Spilling, Collecting };
 
@@ -43,14 +54,43 @@ struct Request {
     std::vector<vp_c64> kspace;
     uint64_t bytes = 0;
     RState state = RState::Queued;
-    bool cancel = false;
+    std::atomic<bool> cancel{false};
     vp_status status = VP_OK;
     double final_loss = 0.0;
     int64_t steps_done = 0;
     Clock::time_point t_submit, t_done;
     std::unique_ptr<vp_session> session;
+    // worker bookkeeping while resident
+    int64_t queued = 0;        // steps enqueued so far
+    int inflight = 0;          // enqueued super-steps not yet waited for
+    bool final_sent = false;   // the objective has been enqueued
+    bool failed = false;
+    vp_status fail_status = VP_OK;
+    hipEvent_t ev[kDepth] = {};
+    unsigned evi = 0;
+    vp_status make_events() {
+        for (hipEvent_t& e : ev)
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+                e = nullptr;
+                return fail(VP_ERR_DEVICE, "server: hipEventCreate failed");
+            }
+        return VP_OK;
+    }
+    void release_events() {
+        for (hipEvent_t& e : ev) {
+            if (e) (void)hipEventDestroy(e);
+            e = nullptr;
+        }
+    }
     // results moved to host when the device memory was needed before collection
     std::vector<vp_c64> h_vol, h_proj, h_water, h_fat;
+};
+
+struct Inflight {
+    Request* r;
+    hipEvent_t ev;
+    bool final;
+    vp_status st;  // status of enqueueing it
 };
 
 }  // namespace
@@ -93,12 +133,8 @@ void vp_server::mark_done(Request* r, vp_status st, bool count) {
 
 void vp_server::run() {
     (void)hipSetDevice(device);
-    SliceGroup g;
-    g.device = device;
-    if (hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking) != hipSuccess) g.stream = nullptr;
-    std::vector<Request*> active;     // resident and stepping
-    std::vector<Request*> to_finish;  // stepped to completion, objective not yet computed
-    bool dirty = false;
+    std::vector<Request*> active;  // resident: state on the device, work enqueued or to enqueue
+    std::deque<Inflight> fifo;     // enqueued super-steps of every resident request, in order
     for (;;) {
         std::vector<Request*> admit, dropped, spill;
         {
@@ -114,11 +150,11 @@ void vp_server::run() {
                     }
                 }
             }
+            // cancelled requests leave once their enqueued work has drained
             for (auto it = active.begin(); it != active.end();) {
-                if ((*it)->cancel) {
+                if ((*it)->cancel && (*it)->inflight == 0) {
                     dropped.push_back(*it);
                     it = active.erase(it);
-                    dirty = true;
                 } else {
                     ++it;
                 }
@@ -131,7 +167,7 @@ void vp_server::run() {
                 r->state = RState::Running;
                 admit.push_back(r);
             }
-            if (active.empty() && admit.empty() && dropped.empty() && to_finish.empty() && spill.empty()) {
+            if (active.empty() && admit.empty() && dropped.empty() && spill.empty() && fifo.empty()) {
                 if (stop) break;
                 cv_work.wait(lk);
                 continue;
@@ -160,77 +196,84 @@ void vp_server::run() {
             cv_done.notify_all();
         }
         for (Request* r : dropped) {
+            r->release_events();
             r->session.reset();
             mark_done(r, VP_ERR_CANCELLED, false);
         }
-        // launch the next super-step first, so the host work below overlaps it
-        std::vector<Request*> stepping;
-        int64_t k = 0;
-        vp_status st = g.stream ? VP_OK : fail(VP_ERR_DEVICE, "server: no stream");
-        if (!active.empty() && st == VP_OK) {
-            if (dirty) {
-                std::vector<vp_session*> sess;
-                std::vector<int> limits;
-                for (Request* r : active) {
-                    sess.push_back(r->session.get());
-                    limits.push_back(r->opts.n_steps);
-                }
-                st = group_build(&g, sess, limits);
-                dirty = false;
-            }
-            if (st == VP_OK) {
-                k = kSuperSteps;
-                for (Request* r : active) k = std::min<int64_t>(k, r->opts.n_steps - r->session->steps_done);
-                k = std::max<int64_t>(k, 1);
-                st = group_run(&g, (int)k, false);
-            }
-            stepping = active;
-        }
-        // finalise the requests completed by the previous super-step (own streams)
-        for (Request* r : to_finish) {
-            double obj = 0.0;
-            const vp_status fs = session_objective(r->session.get(), &obj, nullptr);
-            r->final_loss = obj;
-            r->steps_done = r->session->steps_done;
-            mark_done(r, fs, true);
-        }
-        to_finish.clear();
-        // upload newly admitted requests (own streams); they join the next super-step
+        // newly admitted requests: state uploaded on their own streams, not waited for
         for (Request* r : admit) {
             vp_session* s = nullptr;
-            const vp_status as = session_alloc(r->plan, &r->opts, r->kspace.data(), nullptr, nullptr, &s);
-            std::vector<vp_c64>().swap(r->kspace);
+            vp_status as = session_alloc(r->plan, &r->opts, r->kspace.data(), nullptr, nullptr, &s, nullptr, false);
+            if (as == VP_OK) {
+                r->session.reset(s);
+                as = r->make_events();
+            }
             if (as != VP_OK) {
+                r->session.reset();
+                r->release_events();
                 mark_done(r, as, false);
                 continue;
             }
-            r->session.reset(s);
-            if (r->opts.n_steps == 0) {
-                to_finish.push_back(r);
-                continue;
-            }
             active.push_back(r);
-            dirty = true;
         }
-        if (stepping.empty()) continue;
-        if (st == VP_OK) st = hip_status(hipStreamSynchronize(g.stream), "server super-step");
-        for (Request* r : stepping) {
-            r->session->steps_done = std::min<int64_t>(r->opts.n_steps, r->session->steps_done + k);
-            if (st != VP_OK || r->session->steps_done >= r->opts.n_steps) {
+        // keep up to kDepth super-steps enqueued per resident request, each on the
+        // request's own stream (step graph replays); the last one carries the objective
+        int feeding = 0;
+        uint64_t feeding_vox = 0;
+        for (Request* r : active) {
+            // only requests with work left to enqueue count: the next one starts while
+            // the previous one's last super-steps still run
+            if (r->cancel || r->final_sent) continue;
+            if (feeding > 0 && (feeding >= kStepping || feeding_vox >= kFillVoxels)) break;
+            ++feeding;
+            feeding_vox += r->plan->voxels();
+            while (!r->cancel && r->inflight < kDepth && (r->queued < r->opts.n_steps || !r->final_sent)) {
+                vp_session* s = r->session.get();
+                const int64_t k = std::min<int64_t>(kSuperSteps, r->opts.n_steps - r->queued);
+                vp_status st = k > 0 ? session_run(s, (int32_t)k, 1) : VP_OK;
+                r->queued += k;
+                const bool final = r->queued >= r->opts.n_steps;
+                if (st == VP_OK && final) st = session_objective_enqueue(s, s->stream);
+                hipEvent_t ev = r->ev[r->evi++ % kDepth];
+                if (st == VP_OK) st = hip_status(hipEventRecord(ev, s->stream), "server event");
+                fifo.push_back(Inflight{r, ev, final, st});
+                r->inflight++;
+                if (final) r->final_sent = true;
+            }
+        }
+        if (fifo.empty()) continue;
+        // the oldest enqueued super-step
+        Inflight it = fifo.front();
+        fifo.pop_front();
+        Request* r = it.r;
+        vp_status st = it.st;
+        if (st == VP_OK) st = hip_status(hipEventSynchronize(it.ev), "server super-step");
+        r->inflight--;
+        // the initial upload precedes every enqueued super-step on the request's stream
+        if (!r->kspace.empty() && st == VP_OK) std::vector<vp_c64>().swap(r->kspace);
+        if (st != VP_OK && !r->failed) {
+            r->failed = true;
+            r->cancel = true;  // stop feeding; leaves when drained
+            r->fail_status = st;
+        }
+        if (it.final || (r->failed && r->inflight == 0)) {
+            if (r->inflight == 0 || !r->failed) {
+                double obj = 0.0;
+                vp_status fs = r->failed ? r->fail_status : session_objective_finish(r->session.get(), &obj, nullptr);
+                r->final_loss = obj;
+                r->steps_done = r->session->steps_done;
+                if (r->failed) r->session.reset();
+                r->release_events();
                 active.erase(std::find(active.begin(), active.end(), r));
-                dirty = true;
-                if (st != VP_OK) {
-                    r->session.reset();
-                    mark_done(r, st, false);
-                } else {
-                    to_finish.push_back(r);
-                }
+                mark_done(r, fs, !r->failed);
             }
         }
     }
-    // shutdown: everything still queued or running is cancelled
+    // shutdown: wait for enqueued work, then cancel everything still queued or running
+    for (Inflight& it : fifo) (void)hipEventSynchronize(it.ev);
     std::lock_guard<std::mutex> lk(mu);
     for (Request* r : active) {
+        r->release_events();
         r->session.reset();
         used -= r->bytes;
         r->status = VP_ERR_CANCELLED;
@@ -242,7 +285,6 @@ void vp_server::run() {
     }
     queue.clear();
     cv_done.notify_all();
-    if (g.stream) (void)hipStreamDestroy(g.stream);
 }
 
 extern "C" vp_status vp_server_create(int32_t device, uint64_t hbm_budget, int32_t max_slots, vp_server** out) {

@@ -60,9 +60,10 @@ __host__ __device__ constexpr size_t stage_lds_bytes(int re) {
 constexpr int kVoxItem = 4096;
 
 // Rows per row-FFT work item and columns per column-FFT work item, as functions of n
-// only (never of the batch), so every slice's arithmetic is the same alone or batched.
-__host__ __device__ constexpr int fft_rows_per_item(int n) { return 2048 / n < 1 ? 1 : (2048 / n > 16 ? 16 : 2048 / n); }
-__host__ __device__ constexpr int fft_cols_per_item(int n) { return n > 256 ? 8 : 16; }
+// only (each transform is independent, so they never change a result): small enough
+// items that a blade set spreads over the whole chip.
+__host__ __device__ constexpr int fft_rows_per_item(int n) { return 1024 / n < 1 ? 1 : (1024 / n > 16 ? 16 : 1024 / n); }
+__host__ __device__ constexpr int fft_cols_per_item(int n) { return n > 256 ? 4 : (n == 256 ? 8 : 16); }
 
 struct ShearEntry {       // one (blade, bin): taps at rows y+oy(+1), columns x+ox(+1)
     int ox, oy;
