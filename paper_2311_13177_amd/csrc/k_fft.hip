@@ -275,7 +275,7 @@ __global__ __launch_bounds__(kThreads) void k_rows(const KArgs a) {
 
 __global__ __launch_bounds__(kThreads) void k_cols(const KArgs a) {
     extern __shared__ float2 sm[];
-    __shared__ float red[kThreads];
+    __shared__ float red[kThreads / 64];
     for (int ti = blockIdx.x; ti < a.ntasks; ti += gridDim.x) {
         const AS4 Task* tk = cst(a.tasks) + ti;
         const int slice = tk->slice;
@@ -293,40 +293,50 @@ __global__ __launch_bounds__(kThreads) void k_cols(const KArgs a) {
         const size_t nn = (size_t)n * n;
         const int cb = fft_cols_per_item(n);
         const int c0 = tk->b * cb, cols = min(cb, n - c0);
+        // LDS: the strip (cb columns of n), the twiddles, and the strip's measurement and
+        // mask, all loaded in one pass so that their latencies overlap
         float2* A = sm;
         float2* tw = sm + cb * n;
+        float2* Y = tw + n;
+        uint8_t* M = reinterpret_cast<uint8_t*>(Y + cb * n);
         float2* img = DF(work) + (size_t)b * nparts * nn;
         const float2* twg = DF(tw);
         const float2* src = a.mode == COL_ADJOINT ? a.in0 + (size_t)b * nn : img;
+        const uint8_t* mk = DF(mask) + (size_t)b * nn;
+        const float2* yy = DF(y);
+        const float2* yb = (yy && a.mode != COL_ADJOINT) ? yy + (size_t)b * nn : nullptr;
         for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = twg[i];
         for (int i = threadIdx.x; i < n * cb; i += blockDim.x) {
             const int y = i / cb, c = i - (i / cb) * cb;
-            A[i] = c < cols ? src[(size_t)y * n + c0 + c] : make_float2(0.f, 0.f);
+            float2 v = make_float2(0.f, 0.f), w = v;
+            uint8_t m = 0;
+            if (c < cols) {
+                const size_t gi = (size_t)y * n + c0 + c;
+                v = src[gi];
+                m = mk[gi];
+                if (yb) w = yb[gi];
+            }
+            A[i] = v;
+            Y[i] = w;
+            M[i] = m;
         }
         __syncthreads();
         if (a.mode != COL_ADJOINT) fft_cols_any<-1>(A, tw, n, nstage, code);
         const float sc = 1.0f / (float)n;
-        const uint8_t* mk = DF(mask) + (size_t)b * nn;
-        const float2* yy = DF(y);
-        const float2* yb = yy ? yy + (size_t)b * nn : nullptr;
         float lsum = 0.f;
         for (int i = threadIdx.x; i < n * cb; i += blockDim.x) {
             const int y = i / cb, c = i - (i / cb) * cb;
             float2 v = make_float2(0.f, 0.f);
             if (c < cols) {
-                const size_t gi = (size_t)y * n + c0 + c;
-                const bool on = mk[gi] != 0;
+                const bool on = M[i] != 0;
                 const float2 x = A[i];
                 if (a.mode == COL_ADJOINT) {
                     if (on) v = cscale(x, sc);
                 } else {
                     float2 r = make_float2(0.f, 0.f);
-                    if (on) {
-                        r = cscale(x, sc);
-                        if (yb) r = csub(r, yb[gi]);
-                    }
+                    if (on) r = csub(cscale(x, sc), Y[i]);
                     if (a.mode == COL_FORWARD) {
-                        a.out0[(size_t)b * nn + gi] = r;
+                        a.out0[(size_t)b * nn + (size_t)y * n + c0 + c] = r;
                     } else {
                         lsum = __builtin_fmaf(r.x, r.x, lsum);
                         lsum = __builtin_fmaf(r.y, r.y, lsum);
@@ -345,13 +355,12 @@ __global__ __launch_bounds__(kThreads) void k_cols(const KArgs a) {
             }
         }
         if (a.mode == COL_STEP) {
-            red[threadIdx.x] = lsum;
+            // loss partial: butterfly sum within each wave, then the four wave sums in order
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off);
+            if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = lsum;
             __syncthreads();
-            for (int w = kThreads / 2; w > 0; w >>= 1) {
-                if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-                __syncthreads();
-            }
-            if (threadIdx.x == 0) loss_part[b * n_col_items + tk->b] = red[0];
+            if (threadIdx.x == 0) loss_part[b * n_col_items + tk->b] = (red[0] + red[1]) + (red[2] + red[3]);
         }
         __syncthreads();
     }

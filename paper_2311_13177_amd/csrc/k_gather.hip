@@ -187,8 +187,10 @@ __device__ __forceinline__ void update_and_finish(const KArgs& a, int slice, int
 // window of the previous, current and next bin (rows y0-1 .. y0+PPT), taking
 // the x neighbours from the adjacent lanes.
 
+// At least four waves per SIMD (at most 128 VGPRs): enough loads in flight for the
+// streaming epilogue; more waves would force spills.
 template <int MODE, int PPT, int SCM, int SE, int P>
-__global__ __launch_bounds__(kThreads) void k_gather(const KArgs a) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_gather(const KArgs a) {
     extern __shared__ float2 sm[];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);

@@ -351,7 +351,8 @@ extern "C" vp_status vp_plan_create(const vp_geometry* g, vp_plan** out) {
         // FFT LDS: data plus the twiddle table
         const int fb = fft_rows_per_item(n), cb = fft_cols_per_item(n);
         p->lds_rows = ((size_t)fb * n + n) * sizeof(float2);
-        p->lds_cols = ((size_t)cb * n + n) * sizeof(float2);
+        // column strip, twiddles, the strip's measurement and mask
+        p->lds_cols = ((size_t)cb * n + n) * sizeof(float2) + (size_t)cb * n * (sizeof(float2) + 1);
         p->n_col_items = ceil_div(n, cb);
 
         // work lists of the tile-independent stages
