@@ -61,6 +61,9 @@ vp_status group_build(SliceGroup* g, const std::vector<vp_session*>& sessions, c
     std::vector<Task> proj, rows, cols, gath, vox, render, upd;
     StageLists L;
     if (ns) L.tiles = group_tiles(sessions);
+    L.fft_n = ns ? sessions[0]->plan->n : 0;
+    for (const vp_session* s : sessions)
+        if (s->plan->n != L.fft_n) L.fft_n = 0;
     for (int i = 0; i < ns; ++i) {
         const vp_plan* p = sessions[i]->plan;
         const Layout* lay = nullptr;

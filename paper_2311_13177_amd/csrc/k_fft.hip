@@ -186,8 +186,14 @@ __device__ __forceinline__ void ct_fft(float2* buf, const float2* tw) {
 // Row transforms (count rows of length n, row-major) and column transforms (count
 // columns of length n, element j of column f at j * count + f), dispatched to the
 // compile-time variant for the common lengths.
-template <int DIR>
+// NC != 0: the launch holds slices of length NC only, and its compile-time plan is the
+// whole transform (a kernel with just that variant needs far fewer registers).
+template <int DIR, int NC = 0>
 __device__ void fft_rows_any(float2* buf, const float2* tw, int n, int nstage, int code) {
+    if constexpr (NC != 0) {
+        ct_fft<DIR, false, NC, fft_rows_per_item(NC)>(buf, tw);
+        return;
+    }
     switch (n) {
         case 64: ct_fft<DIR, false, 64, fft_rows_per_item(64)>(buf, tw); break;
         case 128: ct_fft<DIR, false, 128, fft_rows_per_item(128)>(buf, tw); break;
@@ -198,8 +204,12 @@ __device__ void fft_rows_any(float2* buf, const float2* tw, int n, int nstage, i
         default: lds_fft<DIR, false, 8>(buf, tw, n, fft_rows_per_item(n), n, 1, nstage, code); break;
     }
 }
-template <int DIR>
+template <int DIR, int NC = 0>
 __device__ void fft_cols_any(float2* buf, const float2* tw, int n, int nstage, int code) {
+    if constexpr (NC != 0) {
+        ct_fft<DIR, true, NC, fft_cols_per_item(NC)>(buf, tw);
+        return;
+    }
     switch (n) {
         case 64: ct_fft<DIR, true, 64, fft_cols_per_item(64)>(buf, tw); break;
         case 128: ct_fft<DIR, true, 128, fft_cols_per_item(128)>(buf, tw); break;
@@ -221,7 +231,7 @@ __device__ void fft_cols_any(float2* buf, const float2* tw, int n, int nstage, i
 // forward DFT of each row. DIR = +1: inverse DFT of each row (the column pass has
 // already applied both unitary scalings).
 
-template <int DIR>
+template <int DIR, int NC>
 __global__ __launch_bounds__(kThreads) void k_rows(const KArgs a) {
     extern __shared__ float2 sm[];
     for (int ti = blockIdx.x; ti < a.ntasks; ti += gridDim.x) {
@@ -260,7 +270,7 @@ __global__ __launch_bounds__(kThreads) void k_rows(const KArgs a) {
                 A[i] = i < rows * n ? img[base + i] : make_float2(0.f, 0.f);
         }
         __syncthreads();
-        fft_rows_any<DIR>(A, tw, n, nstage, code);
+        fft_rows_any<DIR, NC>(A, tw, n, nstage, code);
         for (int i = threadIdx.x; i < rows * n; i += blockDim.x) img[base + i] = A[i];
         __syncthreads();
     }
@@ -273,6 +283,7 @@ __global__ __launch_bounds__(kThreads) void k_rows(const KArgs a) {
 // COL_FORWARD: forward column DFT, out = M (K - y) (y optional), no inverse.
 // COL_ADJOINT: reads caller k-space, Z = M kres / n, inverse column DFT -> work.
 
+template <int NC>
 __global__ __launch_bounds__(kThreads) void k_cols(const KArgs a) {
     extern __shared__ float2 sm[];
     __shared__ float red[kThreads / 64];
@@ -321,7 +332,7 @@ __global__ __launch_bounds__(kThreads) void k_cols(const KArgs a) {
             M[i] = m;
         }
         __syncthreads();
-        if (a.mode != COL_ADJOINT) fft_cols_any<-1>(A, tw, n, nstage, code);
+        if (a.mode != COL_ADJOINT) fft_cols_any<-1, NC>(A, tw, n, nstage, code);
         const float sc = 1.0f / (float)n;
         float lsum = 0.f;
         for (int i = threadIdx.x; i < n * cb; i += blockDim.x) {
@@ -348,7 +359,7 @@ __global__ __launch_bounds__(kThreads) void k_cols(const KArgs a) {
         }
         __syncthreads();
         if (a.mode != COL_FORWARD) {
-            fft_cols_any<1>(A, tw, n, nstage, code);
+            fft_cols_any<1, NC>(A, tw, n, nstage, code);
             for (int i = threadIdx.x; i < n * cb; i += blockDim.x) {
                 const int y = i / cb, c = i - (i / cb) * cb;
                 if (c < cols) img[(size_t)y * n + c0 + c] = A[i];
@@ -370,17 +381,34 @@ __global__ __launch_bounds__(kThreads) void k_cols(const KArgs a) {
 
 static inline int grid_for(int ntasks) { return ntasks < 1 ? 1 : (ntasks > (1 << 20) ? (1 << 20) : ntasks); }
 
-hipError_t launch_rows(const KArgs& a, int dir, size_t lds, hipStream_t s) {
+// n: the common length of every slice of the launch (0 if they differ).
+hipError_t launch_rows(const KArgs& a, int dir, int n, size_t lds, hipStream_t s) {
     if (a.ntasks <= 0) return hipSuccess;
-    if (dir < 0)
-        hipLaunchKernelGGL(k_rows<-1>, dim3(grid_for(a.ntasks)), dim3(kThreads), lds, s, a);
-    else
-        hipLaunchKernelGGL(k_rows<1>, dim3(grid_for(a.ntasks)), dim3(kThreads), lds, s, a);
+    const dim3 g(grid_for(a.ntasks)), b(kThreads);
+#define RV(N)                                                                      \
+    case N:                                                                        \
+        if (dir < 0) hipLaunchKernelGGL((k_rows<-1, N>), g, b, lds, s, a);         \
+        else hipLaunchKernelGGL((k_rows<1, N>), g, b, lds, s, a);                  \
+        break
+    switch (n) {
+        RV(64); RV(128); RV(192); RV(256); RV(320); RV(384);
+        default: RV(0);
+    }
+#undef RV
     return hipGetLastError();
 }
-hipError_t launch_cols(const KArgs& a, size_t lds, hipStream_t s) {
+hipError_t launch_cols(const KArgs& a, int n, size_t lds, hipStream_t s) {
     if (a.ntasks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_cols, dim3(grid_for(a.ntasks)), dim3(kThreads), lds, s, a);
+    const dim3 g(grid_for(a.ntasks)), b(kThreads);
+#define CV(N)                                                  \
+    case N:                                                    \
+        hipLaunchKernelGGL((k_cols<N>), g, b, lds, s, a);      \
+        break
+    switch (n) {
+        CV(64); CV(128); CV(192); CV(256); CV(320); CV(384);
+        default: CV(0);
+    }
+#undef CV
     return hipGetLastError();
 }
 

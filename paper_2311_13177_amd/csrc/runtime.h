@@ -12,8 +12,9 @@ namespace vp {
 // Kernel launchers (kernels.hip).
 // re: largest staged region (elements) over the work items' slices.
 hipError_t launch_project(const KArgs& a, int rows, int gw, int re, hipStream_t s);
-hipError_t launch_rows(const KArgs& a, int dir, size_t lds, hipStream_t s);
-hipError_t launch_cols(const KArgs& a, size_t lds, hipStream_t s);
+// n: the common length of every slice of the launch (0 if they differ).
+hipError_t launch_rows(const KArgs& a, int dir, int n, size_t lds, hipStream_t s);
+hipError_t launch_cols(const KArgs& a, int n, size_t lds, hipStream_t s);
 hipError_t launch_gather(const KArgs& a, int mode, int rows, int sc, int re, hipStream_t s);
 hipError_t launch_update(const KArgs& a, int sc, hipStream_t s);
 hipError_t launch_advance(const KArgs& a, int nslices, hipStream_t s);
@@ -33,6 +34,7 @@ struct StageLists {
     int n_slices = 1;  // slices whose step counters the step advances
     int n_proj = 0, n_rows = 0, n_cols = 0, n_gath = 0, n_vox = 0, n_render = 0, n_upd = 0;
     Tiles tiles;
+    int fft_n = 0;  // common length of every slice (0 if they differ)
     size_t lds_rows = 0, lds_cols = 0;
     int re_proj = 0, re_gath = 0;  // largest staged regions (elements)
 };

@@ -185,13 +185,13 @@ void launch_step(const KArgs& base, const StageLists& L, hipStream_t s, hipError
     if ((e = launch_project(a, L.tiles.proj_rows, L.tiles.proj_gw, L.re_proj, s)) != hipSuccess) { *err = e; return; }
     MARK(1);
     a.tasks = L.rows; a.ntasks = L.n_rows;
-    if ((e = launch_rows(a, -1, L.lds_rows, s)) != hipSuccess) { *err = e; return; }
+    if ((e = launch_rows(a, -1, L.fft_n, L.lds_rows, s)) != hipSuccess) { *err = e; return; }
     MARK(2);
     a.tasks = L.cols; a.ntasks = L.n_cols; a.mode = COL_STEP;
-    if ((e = launch_cols(a, L.lds_cols, s)) != hipSuccess) { *err = e; return; }
+    if ((e = launch_cols(a, L.fft_n, L.lds_cols, s)) != hipSuccess) { *err = e; return; }
     MARK(3);
     a.tasks = L.rows; a.ntasks = L.n_rows;
-    if ((e = launch_rows(a, 1, L.lds_rows, s)) != hipSuccess) { *err = e; return; }
+    if ((e = launch_rows(a, 1, L.fft_n, L.lds_rows, s)) != hipSuccess) { *err = e; return; }
     MARK(4);
     a.tasks = L.gath; a.ntasks = L.n_gath;
     if (L.tiles.upd_sc == 0) {
@@ -222,6 +222,7 @@ StageLists plan_lists(const vp_plan* p, const DeviceTables* t, const Layout* lay
     L.vox = t->t_vox; L.n_vox = (int)p->t_vox.size();
     L.render = t->t_render; L.n_render = (int)p->t_render.size();
     L.tiles = lay->tiles;
+    L.fft_n = p->n;
     L.re_proj = lay->re_proj; L.lds_rows = p->lds_rows; L.lds_cols = p->lds_cols; L.re_gath = lay->re_gath;
     return L;
 }
@@ -292,9 +293,9 @@ extern "C" vp_status vp_forward(const vp_plan* p, const vp_c64* d_vol, const vp_
     if ((e = launch_project(a, L.tiles.proj_rows, L.tiles.proj_gw, L.re_proj, sc.s)) != hipSuccess)
         return hip_status(e, "vp_forward project");
     a.tasks = L.rows; a.ntasks = L.n_rows;
-    if ((e = launch_rows(a, -1, L.lds_rows, sc.s)) != hipSuccess) return hip_status(e, "vp_forward rows");
+    if ((e = launch_rows(a, -1, L.fft_n, L.lds_rows, sc.s)) != hipSuccess) return hip_status(e, "vp_forward rows");
     a.tasks = L.cols; a.ntasks = L.n_cols; a.mode = COL_FORWARD; a.out0 = (float2*)d_out;
-    if ((e = launch_cols(a, L.lds_cols, sc.s)) != hipSuccess) return hip_status(e, "vp_forward cols");
+    if ((e = launch_cols(a, L.fft_n, L.lds_cols, sc.s)) != hipSuccess) return hip_status(e, "vp_forward cols");
     return VP_OK;
 }
 
@@ -313,9 +314,9 @@ extern "C" vp_status vp_adjoint(const vp_plan* p, const vp_c64* d_kres, vp_c64* 
     const StageLists L = plan_lists(p, sc.t, sc.lay, sc.dl);
     hipError_t e;
     a.tasks = L.cols; a.ntasks = L.n_cols; a.mode = COL_ADJOINT; a.in0 = (const float2*)d_kres;
-    if ((e = launch_cols(a, L.lds_cols, sc.s)) != hipSuccess) return hip_status(e, "vp_adjoint cols");
+    if ((e = launch_cols(a, L.fft_n, L.lds_cols, sc.s)) != hipSuccess) return hip_status(e, "vp_adjoint cols");
     a.tasks = L.rows; a.ntasks = L.n_rows;
-    if ((e = launch_rows(a, 1, L.lds_rows, sc.s)) != hipSuccess) return hip_status(e, "vp_adjoint rows");
+    if ((e = launch_rows(a, 1, L.fft_n, L.lds_rows, sc.s)) != hipSuccess) return hip_status(e, "vp_adjoint rows");
     a.tasks = L.gath; a.ntasks = L.n_gath;
     if ((e = launch_gather(a, GATHER_STORE, L.tiles.gath_rows, L.tiles.gath_sc, L.re_gath, sc.s)) != hipSuccess)
         return hip_status(e, "vp_adjoint gather");
@@ -534,9 +535,9 @@ vp_status session_objective_enqueue(vp_session* s, hipStream_t stream) {
     if ((e = launch_project(a, L.tiles.proj_rows, L.tiles.proj_gw, L.re_proj, stream)) != hipSuccess)
         return hip_status(e, "objective");
     a.tasks = L.rows; a.ntasks = L.n_rows;
-    if ((e = launch_rows(a, -1, L.lds_rows, stream)) != hipSuccess) return hip_status(e, "objective");
+    if ((e = launch_rows(a, -1, L.fft_n, L.lds_rows, stream)) != hipSuccess) return hip_status(e, "objective");
     a.tasks = L.cols; a.ntasks = L.n_cols; a.mode = COL_STEP;
-    if ((e = launch_cols(a, L.lds_cols, stream)) != hipSuccess) return hip_status(e, "objective");
+    if ((e = launch_cols(a, L.fft_n, L.lds_cols, stream)) != hipSuccess) return hip_status(e, "objective");
     a.tasks = L.vox; a.ntasks = L.n_vox; a.dpart = s->dpart;
     if ((e = launch_reg_value(a, stream)) != hipSuccess) return hip_status(e, "objective");
     const size_t nl = loss_slots(p), nd = 2 * p->t_vox.size();
