@@ -28,89 +28,104 @@ struct UpdateArgs {
 // y0 - 1 .. y0 + PPT, zero outside the grid); x neighbours come from adjacent lanes.
 // Each Charbonnier weight of a forward difference along s or y is computed once and
 // used by both voxels of the pair (the s weight is carried to the next bin), with the
-// same operands as a per-voxel evaluation, so the result is the same either way. Plane
-// addresses are uniform and the per-lane offsets 32-bit; every load has a clamped,
-// valid address and zero is selected outside the grid, so the loads issue together.
+// same operands as a per-voxel evaluation, so the result is the same either way.
 template <int SCM, int PPT>
 __device__ __forceinline__ void update_column(const float2 (&acc)[SCM][PPT], const float2* __restrict__ Vin,
                                               float2* __restrict__ Vout, float2* __restrict__ Mm,
                                               float2* __restrict__ Mv, const UpdateArgs& u) {
     constexpr int WR = PPT + 2;
     const int n = u.n, S = u.S;
-    const size_t nn = (size_t)n * n;
+    const int nn = n * n;
+    const int kvol = S * nn;  // elements of one knot's volume (at most 2^26)
+    const size_t kbase = (size_t)u.kt * kvol;
     const int x = u.x0 + u.lane, xc = min(x, n - 1);
-    const size_t kbase = (size_t)u.kt * S * nn;
     const float eps2 = u.eps2;
     const bool tv = u.tv_w != 0.f;
+    const bool adam = u.opt == VP_OPT_ADAM;
     const float2 zero = make_float2(0.f, 0.f);
-    int roff[WR];
-    bool rin[WR];
+    // Buffers over this knot's volume in each array (and the neighbouring knots' volumes):
+    // a bin's offset is scalar (soffset) and a row's lane offset a fixed 32-bit voffset,
+    // so no load or store needs 64-bit address arithmetic. Rows outside the grid read
+    // zero through an out-of-range voffset.
+    const __amdgpu_buffer_rsrc_t rV = plane_rsrc(Vin + kbase, kvol);
+    const __amdgpu_buffer_rsrc_t rP = plane_rsrc(u.kt > 0 ? Vin + kbase - kvol : Vin, u.kt > 0 ? kvol : 0);
+    const __amdgpu_buffer_rsrc_t rN = plane_rsrc(u.kt + 1 < u.T ? Vin + kbase + kvol : Vin, u.kt + 1 < u.T ? kvol : 0);
+    const __amdgpu_buffer_rsrc_t rO = plane_rsrc(Vout + kbase, kvol);
+    const __amdgpu_buffer_rsrc_t rM = plane_rsrc(adam ? Mm + kbase : Vin, adam ? kvol : 0);
+    const __amdgpu_buffer_rsrc_t rW = plane_rsrc(adam ? Mv + kbase : Vin, adam ? kvol : 0);
+    auto ld = [](__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+        return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    };
+    auto st = [](__amdgpu_buffer_rsrc_t r, float2 v, int voff, int soff) {
+        using v2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2, v), r, voff, soff, 0);
+    };
+    int rb[WR];  // byte offsets of the window rows y0 - 1 .. y0 + PPT (out of range outside the grid)
 #pragma unroll
     for (int r = 0; r < WR; ++r) {
         const int y = u.y0 - 1 + r;
-        rin[r] = y >= 0 && y < n;
-        roff[r] = min(max(y, 0), n - 1) * n + xc;
+        rb[r] = (y >= 0 && y < n) ? (y * n + xc) * (int)sizeof(float2) : kBufferOut;
     }
-    // rows outside the grid and bins outside [0, S) read zero (out-of-range buffer loads)
     auto load_plane = [&](int s, float2 (&w)[WR]) {
-        const bool sin = s >= 0 && s < S;
-        const __amdgpu_buffer_rsrc_t r = plane_rsrc(Vin + kbase + (size_t)(sin ? s : 0) * nn, sin ? (int)nn : 0);
+        if (s >= 0 && s < S) {
 #pragma unroll
-        for (int k = 0; k < WR; ++k) w[k] = buffer_c64(r, rin[k] ? roff[k] : -1);
+            for (int k = 0; k < WR; ++k) w[k] = ld(rV, rb[k], s * nn * (int)sizeof(float2));
+        } else {
+#pragma unroll
+            for (int k = 0; k < WR; ++k) w[k] = zero;
+        }
     };
     if (u.ns <= 0) return;
-    float2 pv[WR], cv[WR], nv[WR];
-    load_plane(u.sw - 1, pv);
-    load_plane(u.sw, cv);
-    load_plane(u.sw + 1, nv);
-    float2 wsp[PPT];  // weights of the differences between bins s - 1 and s
+    // win[k]: rows of bin sw - 1 + k; the loop over bins is unrolled, so bin q reads
+    // win[q], win[q + 1], win[q + 2] in place (no register copies between bins)
+    float2 win[SCM + 2][WR];
+    load_plane(u.sw - 1, win[0]);
+    load_plane(u.sw, win[1]);
+    load_plane(u.sw + 1, win[2]);
+    float2 ws[SCM + 1][PPT];  // ws[k]: weights of the differences between bins sw - 1 + k and sw + k
 #pragma unroll
-    for (int i = 0; i < PPT; ++i) wsp[i] = (tv && u.sw > 0) ? charb_w(csub(cv[i + 1], pv[i + 1]), eps2) : zero;
+    for (int i = 0; i < PPT; ++i) ws[0][i] = (tv && u.sw > 0) ? charb_w(csub(win[1][i + 1], win[0][i + 1]), eps2) : zero;
 #pragma unroll
     for (int q = 0; q < SCM; ++q) {
         if (q < u.ns) {
             const int s = u.sw + q;
-            if (q > 0) {
-#pragma unroll
-                for (int r = 0; r < WR; ++r) {
-                    pv[r] = cv[r];
-                    cv[r] = nv[r];
-                }
-                load_plane(s + 1, nv);
-            }
-            const size_t pbase = kbase + (size_t)s * nn;
+            if (q > 0) load_plane(s + 1, win[q + 2]);
+            const float2(&cv)[WR] = win[q + 1];
+            const float2(&nv)[WR] = win[q + 2];
+            const int so = s * nn * (int)sizeof(float2);
             // moments and time neighbours first, so their loads overlap the arithmetic
             float2 mm[PPT], vv[PPT], tp[PPT], tn[PPT];
 #pragma unroll
             for (int i = 0; i < PPT; ++i) {
                 mm[i] = vv[i] = tp[i] = tn[i] = zero;
-                if (u.opt == VP_OPT_ADAM) {
-                    mm[i] = Mm[pbase + roff[i + 1]];
-                    vv[i] = Mv[pbase + roff[i + 1]];
+                if (adam) {
+                    mm[i] = ld(rM, rb[i + 1], so);
+                    vv[i] = ld(rW, rb[i + 1], so);
                 }
-                if (tv && u.kt > 0) tp[i] = Vin[pbase - (size_t)S * nn + roff[i + 1]];
-                if (tv && u.kt + 1 < u.T) tn[i] = Vin[pbase + (size_t)S * nn + roff[i + 1]];
+                if (tv && u.kt > 0) tp[i] = ld(rP, rb[i + 1], so);
+                if (tv && u.kt + 1 < u.T) tn[i] = ld(rN, rb[i + 1], so);
             }
-            float2 wy[PPT + 1], wsn[PPT];
+            float2 wy[PPT + 1];
 #pragma unroll
             for (int r = 0; r <= PPT; ++r) wy[r] = tv ? charb_w(csub(cv[r + 1], cv[r]), eps2) : zero;
 #pragma unroll
-            for (int i = 0; i < PPT; ++i) wsn[i] = (tv && s + 1 < S) ? charb_w(csub(nv[i + 1], cv[i + 1]), eps2) : zero;
+            for (int i = 0; i < PPT; ++i)
+                ws[q + 1][i] = (tv && s + 1 < S) ? charb_w(csub(nv[i + 1], cv[i + 1]), eps2) : zero;
 #pragma unroll
             for (int i = 0; i < PPT; ++i) {
                 const int y = u.y0 + i;
                 if (y < n) {
-                    const size_t idx = pbase + roff[i + 1];
+                    const int vo = rb[i + 1];
                     const float2 v0 = cv[i + 1];
                     float2 left = shfl_up1(v0), right = shfl_down1(v0);
-                    if (u.lane == 0) left = u.x0 > 0 ? Vin[idx - 1] : zero;
-                    if (u.lane == 63) right = u.x0 + 64 < n ? Vin[idx + 1] : zero;
+                    if (u.lane == 0) left = u.x0 > 0 ? ld(rV, vo - (int)sizeof(float2), so) : zero;
+                    if (u.lane == 63) right = u.x0 + 64 < n ? ld(rV, vo + (int)sizeof(float2), so) : zero;
                     float2 g = zero;
                     if (tv) {
                         if (u.kt > 0) g = cadd(g, charb_w(csub(v0, tp[i]), eps2));
                         if (u.kt + 1 < u.T) g = csub(g, charb_w(csub(tn[i], v0), eps2));
-                        if (s > 0) g = cadd(g, wsp[i]);
-                        if (s + 1 < S) g = csub(g, wsn[i]);
+                        if (s > 0) g = cadd(g, ws[q][i]);
+                        if (s + 1 < S) g = csub(g, ws[q + 1][i]);
                         if (y > 0) g = cadd(g, wy[i]);
                         if (y + 1 < n) g = csub(g, wy[i + 1]);
                         if (x > 0) g = cadd(g, charb_w(csub(v0, left), eps2));
@@ -121,15 +136,15 @@ __device__ __forceinline__ void update_column(const float2 (&acc)[SCM][PPT], con
                     const float2 gr = cadd(acc[q][i], g);
                     if (x < n) {
                         float2 nvx;
-                        if (u.opt == VP_OPT_ADAM) {
+                        if (adam) {
                             float2 m = mm[i], v = vv[i];
                             const float c1 = 1.0f - u.beta1, c2 = 1.0f - u.beta2;
                             m.x = __builtin_fmaf(u.beta1, m.x, c1 * gr.x);
                             m.y = __builtin_fmaf(u.beta1, m.y, c1 * gr.y);
                             v.x = __builtin_fmaf(u.beta2, v.x, (c2 * gr.x) * gr.x);
                             v.y = __builtin_fmaf(u.beta2, v.y, (c2 * gr.y) * gr.y);
-                            Mm[idx] = m;
-                            Mv[idx] = v;
+                            st(rM, m, vo, so);
+                            st(rW, v, vo, so);
                             // hardware square root and reciprocal (about 1 ulp each)
                             const float dx = __builtin_fmaf(__builtin_amdgcn_sqrtf(v.x), u.inv_bc2s, u.aeps);
                             const float dy = __builtin_fmaf(__builtin_amdgcn_sqrtf(v.y), u.inv_bc2s, u.aeps);
@@ -138,12 +153,10 @@ __device__ __forceinline__ void update_column(const float2 (&acc)[SCM][PPT], con
                         } else {
                             nvx = make_float2(__builtin_fmaf(-u.lr, gr.x, v0.x), __builtin_fmaf(-u.lr, gr.y, v0.y));
                         }
-                        Vout[idx] = nvx;
+                        st(rO, nvx, vo, so);
                     }
                 }
             }
-#pragma unroll
-            for (int i = 0; i < PPT; ++i) wsp[i] = wsn[i];
         }
     }
 }
