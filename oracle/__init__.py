@@ -41,6 +41,7 @@ from .lifted import (  # noqa: F401
     reconstruct,
     render,
     coverage_baseline,
+    window_baseline,
     psnr,
     simulate_measurements,
 )

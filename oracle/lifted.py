@@ -405,6 +405,18 @@ def coverage_baseline(y: np.ndarray, masks: np.ndarray) -> np.ndarray:
     return np.fft.ifft2(acc / np.maximum(1.0, cover), norm="ortho")
 
 
+def window_baseline(y: np.ndarray, masks: np.ndarray, window: int) -> np.ndarray:
+    """Section 6, dynamic baseline: frame i is the coverage-weighted average, in k-space,
+    of the blades i - window + 1 .. i (those that exist), then the unitary inverse DFT.
+    Frames [B][n][n]; with window >= B the last frame is the static baseline."""
+    B = y.shape[0]
+    frames = np.zeros(y.shape, dtype=np.complex128)
+    for i in range(B):
+        lo = max(0, i - window + 1)
+        frames[i] = coverage_baseline(y[lo:i + 1], masks[lo:i + 1])
+    return frames
+
+
 def psnr(image: np.ndarray, truth: np.ndarray) -> float:
     """PSNR on magnitudes with the peak of the truth (quality context only)."""
     err = np.mean((np.abs(image) - np.abs(truth)) ** 2)

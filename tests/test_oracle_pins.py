@@ -328,6 +328,80 @@ def test_zero_offresonance_gd_reduces_to_multiblade_dft_fit():
     assert np.allclose(far["proj"][0], O.coverage_baseline(y, masks), atol=1e-10)
 
 
+# ------------------------------------------------------------------ baselines and PSNR (Section 6)
+
+def _dft_matrix(n):
+    j = np.arange(n)
+    return np.exp(-2j * np.pi * np.outer(j, j) / n) / math.sqrt(n)
+
+
+@pytest.mark.parametrize("window", [1, 2, 3, 4])
+def test_window_baseline_keeps_the_covered_spectrum_of_a_static_image(window):
+    # every blade of a static image carries the same values where it is measured, so
+    # averaging over the blades of a window returns the image's own spectrum on the union
+    # of their masks and zero elsewhere (brute-force DFT matrices, not the FFT)
+    n = 12
+    geom = _geom(n=n, s=2, angles=(0.0, 0.6, 1.5, 2.4), lines=(3, 4, 5, 2))
+    masks = O.blade_masks(geom)
+    rng = np.random.default_rng(40 + window)
+    x = _crandn(rng, n, n)
+    f = _dft_matrix(n)
+    spec = f @ x @ f.T
+    y = masks * spec
+    frames = O.window_baseline(y, masks, window)
+    for i in range(4):
+        union = masks[max(0, i - window + 1):i + 1].any(axis=0)
+        want = np.conj(f).T @ (union * spec) @ np.conj(f)
+        assert np.allclose(frames[i], want, atol=1e-12)
+
+
+def test_window_baseline_weights_overlaps_by_coverage():
+    # two blades that disagree on a shared sample average to their mean there, and a
+    # sample seen by one blade only keeps that blade's value
+    n = 8
+    geom = _geom(n=n, s=1, angles=(0.0, 0.0), lines=(4, 2))
+    masks = O.blade_masks(geom)
+    rng = np.random.default_rng(44)
+    y = masks * _crandn(rng, 2, n, n)
+    frame = O.window_baseline(y, masks, 2)[1]
+    got = _dft_matrix(n) @ frame @ _dft_matrix(n).T
+    both, one = masks[0] & masks[1], masks[0] & ~masks[1]
+    assert both.any() and one.any()
+    assert np.allclose(got[both], 0.5 * (y[0] + y[1])[both], atol=1e-12)
+    assert np.allclose(got[one], y[0][one], atol=1e-12)
+    assert np.allclose(got[~masks.any(axis=0)], 0.0, atol=1e-12)
+
+
+def test_window_baseline_frames_see_only_their_window():
+    n, B, w = 10, 6, 3
+    geom = _geom(n=n, s=1, angles=np.linspace(0.0, 2.5, B), lines=(3, 4, 5, 3, 4, 5))
+    masks = O.blade_masks(geom)
+    rng = np.random.default_rng(45)
+    y = masks * _crandn(rng, B, n, n)
+    ref = O.window_baseline(y, masks, w)
+    j = 2
+    y2 = y.copy()
+    y2[j] += masks[j] * 0.7
+    got = O.window_baseline(y2, masks, w)
+    for i in range(B):
+        inside = i - w + 1 <= j <= i
+        assert np.array_equal(got[i], ref[i]) != inside, i
+    # a window of every blade ending at the last frame is the static baseline
+    assert np.allclose(O.window_baseline(y, masks, B)[-1], O.coverage_baseline(y, masks), atol=1e-14)
+
+
+def test_psnr_closed_form():
+    rng = np.random.default_rng(46)
+    truth = _crandn(rng, 9, 11)
+    c = 0.03
+    image = truth * (1.0 + c / np.abs(truth))  # every magnitude off by exactly c
+    peak = np.abs(truth).max()
+    assert math.isclose(O.psnr(image, truth), 20.0 * math.log10(peak / c), rel_tol=1e-12)
+    # the phase does not count
+    assert O.psnr(1j * truth, truth) == float("inf") and O.psnr(-truth, truth) == float("inf")
+    assert O.psnr(np.abs(truth) * np.exp(1j * rng.uniform(0, 6, truth.shape)), truth) > 250.0
+
+
 # ------------------------------------------------------------------ data and outputs
 
 def test_noise_free_ground_truth_has_zero_data_loss():
