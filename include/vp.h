@@ -234,6 +234,32 @@ vp_status vp_tv_grad(const vp_plan* plan, const vp_c64* d_vol, float tv_weight, 
 vp_status vp_render(const vp_plan* plan, const vp_c64* d_vol, int32_t split_bin, vp_c64* d_proj, vp_c64* d_water,
                     vp_c64* d_fat, void* stream);
 
+/* ------------------------------------------------------------------ evaluation (device pointers) */
+
+/* Baseline reconstructions of Section 6 (evaluation): frame f is the unitary
+ * inverse DFT of the coverage-weighted k-space average of the blades
+ * max(0, f - window + 1) .. f, i.e. at each sample the mean of the values of those
+ * blades whose mask holds it (zero where none does). window <= 0 takes every blade
+ * up to f, so window = B (or 0) and f = B - 1 is the static baseline that combines
+ * all blades, and window = 5 the dynamic one over the five most recent blades.
+ * d_kspace: device [B][n][n] measurements (off-mask values are ignored).
+ * d_out: device [n_frames][n][n], frames first_frame .. first_frame + n_frames - 1,
+ * image space; it must not overlap d_kspace. Asynchronous on `stream`; allocates
+ * nothing. Errors: VP_ERR_ARG for NULL pointers (with n_frames > 0), first_frame < 0,
+ * n_frames < 0, first_frame + n_frames > B, or overlapping buffers. */
+vp_status vp_baseline(const vp_plan* plan, const vp_c64* d_kspace, int32_t window, int32_t first_frame,
+                      int32_t n_frames, vp_c64* d_out, void* stream);
+
+/* PSNR on magnitudes (Section 6, quantitative results): for each of n_images
+ * consecutive images of n_px complex samples in d_image and d_truth (device),
+ * d_terms[3 i + 0] = mean over samples of (|image| - |truth|)^2 (FP64),
+ * d_terms[3 i + 1] = peak = max |truth|, d_terms[3 i + 2] = 10 log10(peak^2 / mse)
+ * (+inf when mse = 0). Deterministic; runs on the current device, asynchronous on
+ * `stream`; allocates nothing. Errors: VP_ERR_ARG for NULL pointers (with
+ * n_images > 0), n_px < 1 or n_images < 0. */
+vp_status vp_psnr(const vp_c64* d_image, const vp_c64* d_truth, int64_t n_px, int32_t n_images, double* d_terms,
+                  void* stream);
+
 /* ------------------------------------------------------------------ sessions (resident state) */
 
 /* Uploads kspace[B][n][n] (host; off-mask values are ignored) and the initial

@@ -88,6 +88,8 @@ _PROTOS = {
     "vp_adjoint": (c_int32, [_P, _P, _P, c_int32, _P]),
     "vp_tv_grad": (c_int32, [_P, _P, c_float, c_float, c_float, _P, c_int32, _P]),
     "vp_render": (c_int32, [_P, _P, c_int32, _P, _P, _P, _P]),
+    "vp_baseline": (c_int32, [_P, _P, c_int32, c_int32, c_int32, _P, _P]),
+    "vp_psnr": (c_int32, [_P, _P, c_int64, c_int32, _P, _P]),
     "vp_session_create": (c_int32, [_P, POINTER(vp_options), _P, _P, POINTER(_P)]),
     "vp_session_step": (c_int32, [_P, c_int32, c_int32]),
     "vp_session_steps_done": (c_int32, [_P, POINTER(c_int64)]),
@@ -315,6 +317,42 @@ def vp_render(plan: Plan, vol, split_bin: int = -1, stream=None):
     check(lib().vp_render(plan.handle, _dev(vol, plan.volume_shape, "vol"), int(split_bin),
                           *[_dev(o, shp, "render") for o in outs], _stream(stream)))
     return tuple(outs)
+
+
+def vp_baseline(plan: Plan, kspace, window: int = 0, first_frame: Optional[int] = None,
+                n_frames: Optional[int] = None, out=None, stream=None):
+    """Coverage-weighted k-space average of blades max(0, f - window + 1) .. f, inverse
+    DFT, for frames f = first_frame .. first_frame + n_frames - 1 (GPU tensors).
+    Defaults: window 0 (every blade up to the frame), the last frame only."""
+    import torch
+
+    B = plan.blade_shape[0]
+    if first_frame is None:
+        first_frame = B - 1 if n_frames is None else B - n_frames
+    if n_frames is None:
+        n_frames = B - first_frame
+    shp = (n_frames,) + tuple(plan.blade_shape[1:])
+    if out is None:
+        out = torch.empty(shp, dtype=torch.complex64, device=kspace.device)
+    check(lib().vp_baseline(plan.handle, _dev(kspace, plan.blade_shape, "kspace"), int(window),
+                            int(first_frame), int(n_frames), _dev(out, shp, "out"), _stream(stream)))
+    return out
+
+
+def vp_psnr(image, truth, stream=None):
+    """PSNR on magnitudes of each leading-axis image of `image` against `truth` (GPU
+    tensors of equal shape; a 2-D pair is one image). Returns (psnr, mse, peak) as
+    float64 tensors on the device, one entry per image."""
+    import torch
+
+    if tuple(image.shape) != tuple(truth.shape) or image.dim() < 2:
+        raise ValueError("image and truth must share a shape of two or more axes")
+    n_images = 1 if image.dim() == 2 else int(np.prod(image.shape[:-2]))
+    n_px = int(image.shape[-2] * image.shape[-1])
+    terms = torch.empty((n_images, 3), dtype=torch.float64, device=image.device)
+    check(lib().vp_psnr(_dev(image, image.shape, "image"), _dev(truth, truth.shape, "truth"), n_px, n_images,
+                        c_void_p(terms.data_ptr()), _stream(stream)))
+    return terms[:, 2], terms[:, 0], terms[:, 1]
 
 
 # ------------------------------------------------------------------ sessions and reconstructions

@@ -248,7 +248,7 @@ __global__ __launch_bounds__(kThreads) void k_rows(const KArgs a) {
         const int r0 = tk->b, rows = min(fb, n - r0);
         float2* A = sm;
         float2* tw = sm + fb * n;
-        float2* img = DF(work) + (size_t)b * nparts * nn;
+        float2* img = a.mode == COL_INVERSE ? a.out0 + (size_t)b * nn : DF(work) + (size_t)b * nparts * nn;
         const float2* twg = DF(tw);
         const size_t base = (size_t)r0 * n;
         for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = twg[i];
@@ -282,6 +282,7 @@ __global__ __launch_bounds__(kThreads) void k_rows(const KArgs a) {
 //              Z = R / n, inverse column DFT -> work (one pass per column strip).
 // COL_FORWARD: forward column DFT, out = M (K - y) (y optional), no inverse.
 // COL_ADJOINT: reads caller k-space, Z = M kres / n, inverse column DFT -> work.
+// COL_INVERSE: inverse column DFT of caller frames, unmasked and unscaled, -> a.out0.
 
 template <int NC>
 __global__ __launch_bounds__(kThreads) void k_cols(const KArgs a) {
@@ -312,10 +313,12 @@ __global__ __launch_bounds__(kThreads) void k_cols(const KArgs a) {
         uint8_t* M = reinterpret_cast<uint8_t*>(Y + cb * n);
         float2* img = DF(work) + (size_t)b * nparts * nn;
         const float2* twg = DF(tw);
-        const float2* src = a.mode == COL_ADJOINT ? a.in0 + (size_t)b * nn : img;
+        const bool from_in = a.mode == COL_ADJOINT || a.mode == COL_INVERSE;
+        const float2* src = from_in ? a.in0 + (size_t)b * nn : img;
+        float2* dst = a.mode == COL_INVERSE ? a.out0 + (size_t)b * nn : img;
         const uint8_t* mk = DF(mask) + (size_t)b * nn;
         const float2* yy = DF(y);
-        const float2* yb = (yy && a.mode != COL_ADJOINT) ? yy + (size_t)b * nn : nullptr;
+        const float2* yb = (yy && !from_in) ? yy + (size_t)b * nn : nullptr;
         for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = twg[i];
         for (int i = threadIdx.x; i < n * cb; i += blockDim.x) {
             const int y = i / cb, c = i - (i / cb) * cb;
@@ -332,10 +335,10 @@ __global__ __launch_bounds__(kThreads) void k_cols(const KArgs a) {
             M[i] = m;
         }
         __syncthreads();
-        if (a.mode != COL_ADJOINT) fft_cols_any<-1, NC>(A, tw, n, nstage, code);
+        if (!from_in) fft_cols_any<-1, NC>(A, tw, n, nstage, code);
         const float sc = 1.0f / (float)n;
         float lsum = 0.f;
-        for (int i = threadIdx.x; i < n * cb; i += blockDim.x) {
+        for (int i = threadIdx.x; i < n * cb && a.mode != COL_INVERSE; i += blockDim.x) {
             const int y = i / cb, c = i - (i / cb) * cb;
             float2 v = make_float2(0.f, 0.f);
             if (c < cols) {
@@ -362,7 +365,7 @@ __global__ __launch_bounds__(kThreads) void k_cols(const KArgs a) {
             fft_cols_any<1, NC>(A, tw, n, nstage, code);
             for (int i = threadIdx.x; i < n * cb; i += blockDim.x) {
                 const int y = i / cb, c = i - (i / cb) * cb;
-                if (c < cols) img[(size_t)y * n + c0 + c] = A[i];
+                if (c < cols) dst[(size_t)y * n + c0 + c] = A[i];
             }
         }
         if (a.mode == COL_STEP) {

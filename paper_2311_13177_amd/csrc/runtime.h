@@ -21,6 +21,10 @@ hipError_t launch_advance(const KArgs& a, int nslices, hipStream_t s);
 hipError_t launch_tv_grad(const KArgs& a, hipStream_t s);
 hipError_t launch_reg_value(const KArgs& a, hipStream_t s);
 hipError_t launch_render(const KArgs& a, hipStream_t s);
+hipError_t launch_baseline_avg(const uint8_t* mask, const float2* y, float2* out, int n, int window, int first,
+                               int n_frames, hipStream_t s);
+hipError_t launch_psnr(const float2* img, const float2* truth, long long npx, int n_images, double* terms,
+                       hipStream_t s);
 
 // Device work lists of one optimiser step and the dynamic LDS of each stage.
 struct StageLists {

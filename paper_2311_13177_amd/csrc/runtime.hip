@@ -323,6 +323,50 @@ extern "C" vp_status vp_adjoint(const vp_plan* p, const vp_c64* d_kres, vp_c64* 
     return VP_OK;
 }
 
+// Section 6 baselines: the coverage-weighted average (scaled by 1/n) into d_out, then the
+// inverse column and row DFTs in place, over the frames' prefix of the work lists.
+extern "C" vp_status vp_baseline(const vp_plan* p, const vp_c64* d_kspace, int32_t window, int32_t first_frame,
+                                 int32_t n_frames, vp_c64* d_out, void* stream) {
+    clear_error();
+    if (!p) return fail(VP_ERR_ARG, "vp_baseline: NULL plan");
+    if (first_frame < 0 || n_frames < 0 || (int64_t)first_frame + n_frames > p->B)
+        return fail(VP_ERR_ARG, "vp_baseline: frames outside [0, B)");
+    if (n_frames == 0) return VP_OK;
+    if (!d_kspace || !d_out) return fail(VP_ERR_ARG, "vp_baseline: NULL argument");
+    const size_t nn = (size_t)p->n * p->n;
+    const uintptr_t k0 = (uintptr_t)d_kspace, k1 = k0 + (size_t)p->B * nn * sizeof(vp_c64);
+    const uintptr_t o0 = (uintptr_t)d_out, o1 = o0 + (size_t)n_frames * nn * sizeof(vp_c64);
+    if (o0 < k1 && k0 < o1) return fail(VP_ERR_ARG, "vp_baseline: d_out overlaps d_kspace");
+    OpScope sc(p, stream);
+    vp_status st = sc.begin(false);
+    if (st != VP_OK) return st;
+    KArgs a{};
+    fill_desc(p, sc.t, sc.lay, sc.dl, &a.one);
+    const StageLists L = plan_lists(p, sc.t, sc.lay, sc.dl);
+    hipError_t e = launch_baseline_avg(sc.t->mask, (const float2*)d_kspace, (float2*)d_out, p->n, window,
+                                       first_frame, n_frames, sc.s);
+    if (e != hipSuccess) return hip_status(e, "vp_baseline average");
+    a.mode = COL_INVERSE;
+    a.in0 = (const float2*)d_out;
+    a.out0 = (float2*)d_out;
+    a.tasks = L.cols; a.ntasks = n_frames * (L.n_cols / p->B);
+    if ((e = launch_cols(a, L.fft_n, L.lds_cols, sc.s)) != hipSuccess) return hip_status(e, "vp_baseline cols");
+    a.tasks = L.rows; a.ntasks = n_frames * (L.n_rows / p->B);
+    if ((e = launch_rows(a, 1, L.fft_n, L.lds_rows, sc.s)) != hipSuccess) return hip_status(e, "vp_baseline rows");
+    return VP_OK;
+}
+
+extern "C" vp_status vp_psnr(const vp_c64* d_image, const vp_c64* d_truth, int64_t n_px, int32_t n_images,
+                             double* d_terms, void* stream) {
+    clear_error();
+    if (n_px < 1 || n_images < 0) return fail(VP_ERR_ARG, "vp_psnr: n_px < 1 or n_images < 0");
+    if (n_images == 0) return VP_OK;
+    if (!d_image || !d_truth || !d_terms) return fail(VP_ERR_ARG, "vp_psnr: NULL argument");
+    const hipError_t e = launch_psnr((const float2*)d_image, (const float2*)d_truth, (long long)n_px, n_images,
+                                     d_terms, (hipStream_t)stream);
+    return e == hipSuccess ? VP_OK : hip_status(e, "vp_psnr");
+}
+
 extern "C" vp_status vp_tv_grad(const vp_plan* p, const vp_c64* d_vol, float tv_w, float l1_w, float eps,
                                 vp_c64* d_grad, int32_t accumulate, void* stream) {
     clear_error();

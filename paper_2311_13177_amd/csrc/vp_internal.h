@@ -146,7 +146,9 @@ struct KArgs {
 };
 
 // Column pass modes.
-enum { COL_STEP = 0, COL_FORWARD = 1, COL_ADJOINT = 2 };
+// COL_INVERSE (column and inverse row pass): in-place unscaled inverse DFT of the frames at
+// a.out0 (frame = the task's blade index), read from a.in0.
+enum { COL_STEP = 0, COL_FORWARD = 1, COL_ADJOINT = 2, COL_INVERSE = 3 };
 // Gather epilogues.
 enum { GATHER_STORE = 0, GATHER_STEP = 1 };
 
