@@ -136,6 +136,9 @@ vp_status group_build(SliceGroup* g, const std::vector<vp_session*>& sessions, c
     L.render = g->d_tasks + off[5]; L.n_render = (int)render.size();
     L.upd = g->d_tasks + off[6]; L.n_upd = (int)upd.size();
     L.n_slices = ns;
+    L.epi = EPI_ADAM_TV;
+    for (const vp_session* se : sessions)
+        if (se->lists.epi != EPI_ADAM_TV) L.epi = EPI_GENERIC;
     g->lists = L;
     return VP_OK;
 }

@@ -18,8 +18,9 @@ __device__ __forceinline__ float2 shfl_down1(float2 v) { return make_float2(dpp_
 
 struct UpdateArgs {
     int n, S, T, kt, y0, x0, lane, sw, ns, opt;
-    float lr, beta1, beta2, aeps, tv_w, l1_w, eps2, inv_bc2s, step_size;
+    float lr, beta1, beta2, c1, c2, aeps, tv_w, l1_w, eps2, inv_bc2s, step_size;
 };
+
 
 // Adds the TV/L1 gradient to the data gradient acc of one lane's voxels (bins sw ..
 // sw + ns - 1, rows y0 .. y0 + PPT - 1, column x0 + lane of knot kt) and applies Adam
@@ -28,8 +29,10 @@ struct UpdateArgs {
 // y0 - 1 .. y0 + PPT, zero outside the grid); x neighbours come from adjacent lanes.
 // Each Charbonnier weight of a forward difference along s or y is computed once and
 // used by both voxels of the pair (the s weight is carried to the next bin), with the
-// same operands as a per-voxel evaluation, so the result is the same either way.
-template <int SCM, int PPT>
+// same operands as a per-voxel evaluation, so the result is the same either way. The s
+// weights of the first and last bins' outer differences are zero, so they are added
+// unconditionally; the sums start from -0, which adds exactly.
+template <int SCM, int PPT, int EPI>
 __device__ __forceinline__ void update_column(const float2 (&acc)[SCM][PPT], const float2* __restrict__ Vin,
                                               float2* __restrict__ Vout, float2* __restrict__ Mm,
                                               float2* __restrict__ Mv, const UpdateArgs& u) {
@@ -40,8 +43,10 @@ __device__ __forceinline__ void update_column(const float2 (&acc)[SCM][PPT], con
     const size_t kbase = (size_t)u.kt * kvol;
     const int x = u.x0 + u.lane, xc = min(x, n - 1);
     const float eps2 = u.eps2;
-    const bool tv = u.tv_w != 0.f;
-    const bool adam = u.opt == VP_OPT_ADAM;
+    const bool tv = EPI == EPI_ADAM_TV || u.tv_w != 0.f;
+    const bool adam = EPI == EPI_ADAM_TV || u.opt == VP_OPT_ADAM;
+    const bool l1 = EPI != EPI_ADAM_TV && u.l1_w != 0.f;
+    const float2 nzero = make_float2(-0.f, -0.f);
     const float2 zero = make_float2(0.f, 0.f);
     // Buffers over this knot's volume in each array (and the neighbouring knots' volumes):
     // a bin's offset is scalar (soffset) and a row's lane offset a fixed 32-bit voffset,
@@ -120,25 +125,25 @@ __device__ __forceinline__ void update_column(const float2 (&acc)[SCM][PPT], con
                     float2 left = shfl_up1(v0), right = shfl_down1(v0);
                     if (u.lane == 0) left = u.x0 > 0 ? ld(rV, vo - (int)sizeof(float2), so) : zero;
                     if (u.lane == 63) right = u.x0 + 64 < n ? ld(rV, vo + (int)sizeof(float2), so) : zero;
-                    float2 g = zero;
+                    float2 g = nzero;
                     if (tv) {
                         if (u.kt > 0) g = cadd(g, charb_w(csub(v0, tp[i]), eps2));
                         if (u.kt + 1 < u.T) g = csub(g, charb_w(csub(tn[i], v0), eps2));
-                        if (s > 0) g = cadd(g, ws[q][i]);
-                        if (s + 1 < S) g = csub(g, ws[q + 1][i]);
+                        g = cadd(g, ws[q][i]);
+                        g = csub(g, ws[q + 1][i]);
                         if (y > 0) g = cadd(g, wy[i]);
                         if (y + 1 < n) g = csub(g, wy[i + 1]);
                         if (x > 0) g = cadd(g, charb_w(csub(v0, left), eps2));
                         if (x + 1 < n) g = csub(g, charb_w(csub(right, v0), eps2));
                         g = cscale(g, u.tv_w);
                     }
-                    if (u.l1_w != 0.f) g = cfma(u.l1_w, charb_w(v0, eps2), g);
+                    if (l1) g = cfma(u.l1_w, charb_w(v0, eps2), g);
                     const float2 gr = cadd(acc[q][i], g);
                     if (x < n) {
                         float2 nvx;
                         if (adam) {
                             float2 m = mm[i], v = vv[i];
-                            const float c1 = 1.0f - u.beta1, c2 = 1.0f - u.beta2;
+                            const float c1 = u.c1, c2 = u.c2;
                             m.x = __builtin_fmaf(u.beta1, m.x, c1 * gr.x);
                             m.y = __builtin_fmaf(u.beta1, m.y, c1 * gr.y);
                             v.x = __builtin_fmaf(u.beta2, v.x, (c2 * gr.x) * gr.x);
@@ -163,7 +168,7 @@ __device__ __forceinline__ void update_column(const float2 (&acc)[SCM][PPT], con
 
 // Regulariser gradient and optimiser update of a lane's voxels (update_column) with the
 // slice's hyperparameters (the step counter is advanced by k_advance after the pass).
-template <int SCM, int PPT>
+template <int SCM, int PPT, int EPI>
 __device__ __forceinline__ void update_and_finish(const KArgs& a, int slice, int* stepp, int st,
                                                   const float2 (&acc)[SCM][PPT], int kt, int y0, int x0,
                                                   int lane, int sw, int ns) {
@@ -173,6 +178,8 @@ __device__ __forceinline__ void update_and_finish(const KArgs& a, int slice, int
     UpdateArgs u;
     u.n = DF(n); u.S = DF(S); u.T = DF(T); u.kt = kt; u.y0 = y0; u.x0 = x0; u.lane = lane; u.sw = sw; u.ns = ns;
     u.opt = DF(optimizer); u.lr = lr; u.beta1 = DF(beta1); u.beta2 = DF(beta2); u.aeps = DF(adam_eps);
+    u.c1 = 1.0f - u.beta1;
+    u.c2 = 1.0f - u.beta2;
     u.tv_w = DF(tv_w); u.l1_w = DF(l1_w); u.eps2 = teps * teps;
     u.inv_bc2s = 1.f;
     u.step_size = lr;
@@ -183,7 +190,7 @@ __device__ __forceinline__ void update_and_finish(const KArgs& a, int slice, int
         u.step_size = lr / bc1;
         u.inv_bc2s = 1.f / sqrtf(bc2);
     }
-    update_column<SCM, PPT>(acc, Vin, Vout, DF(m), DF(v), u);
+    update_column<SCM, PPT, EPI>(acc, Vin, Vout, DF(m), DF(v), u);
 }
 
 // ------------------------------------------------------------------ adjoint gather + update
@@ -202,7 +209,7 @@ __device__ __forceinline__ void update_and_finish(const KArgs& a, int slice, int
 
 // At least four waves per SIMD (at most 128 VGPRs): enough loads in flight for the
 // streaming epilogue; more waves would force spills.
-template <int MODE, int PPT, int SCM, int SE, int P>
+template <int MODE, int PPT, int SCM, int SE, int P, int EPI>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_gather(const KArgs a) {
     extern __shared__ float2 sm[];
     const int lane = threadIdx.x & 63;
@@ -343,7 +350,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
                 }
             }
         } else {
-            update_and_finish<SCM, PPT>(a, slice, stepp, st, acc, kt, y0, x0, lane, sw, ns);
+            update_and_finish<SCM, PPT, EPI>(a, slice, stepp, st, acc, kt, y0, x0, lane, sw, ns);
         }
     }
 }
@@ -356,7 +363,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
 // block of 4 rows x 64 columns, chunk of SC bins); wave w takes row 4 * b + w. Its light
 // register footprint keeps many waves in flight on what is a streaming pass.
 
-template <int SC>
+template <int SC, int EPI>
 __global__ __launch_bounds__(kThreads) void k_update(const KArgs a) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -378,7 +385,7 @@ __global__ __launch_bounds__(kThreads) void k_update(const KArgs a) {
         float2 acc[SC][1];
 #pragma unroll
         for (int q = 0; q < SC; ++q) acc[q][0] = G[(size_t)min(sw + q, S - 1) * nn + off];
-        update_and_finish<SC, 1>(a, slice, stepp, st, acc, kt, y, x0, lane, sw, ns);
+        update_and_finish<SC, 1, EPI>(a, slice, stepp, st, acc, kt, y, x0, lane, sw, ns);
     }
 }
 
@@ -386,21 +393,28 @@ __global__ __launch_bounds__(kThreads) void k_update(const KArgs a) {
 
 static inline int grid_for(int ntasks) { return ntasks < 1 ? 1 : (ntasks > (1 << 20) ? (1 << 20) : ntasks); }
 
-template <int MODE, int PPT, int SCM>
+template <int MODE, int PPT, int SCM, int EPI>
 static void gather_variant(const KArgs& a, int re, hipStream_t s) {
     const dim3 g(grid_for(a.ntasks)), b(kThreads);
     const int depth = stage_depth(re);
     const size_t lds = stage_lds_bytes(re);
-    if (depth == 5) hipLaunchKernelGGL((k_gather<MODE, PPT, SCM, 5, 3>), g, b, lds, s, a);
-    else if (depth == 8) hipLaunchKernelGGL((k_gather<MODE, PPT, SCM, 8, 2>), g, b, lds, s, a);
-    else hipLaunchKernelGGL((k_gather<MODE, PPT, SCM, 16, 1>), g, b, lds, s, a);
+    if (depth == 5) hipLaunchKernelGGL((k_gather<MODE, PPT, SCM, 5, 3, EPI>), g, b, lds, s, a);
+    else if (depth == 8) hipLaunchKernelGGL((k_gather<MODE, PPT, SCM, 8, 2, EPI>), g, b, lds, s, a);
+    else hipLaunchKernelGGL((k_gather<MODE, PPT, SCM, 16, 1, EPI>), g, b, lds, s, a);
 }
 
 template <int MODE>
 static hipError_t gather_mode(const KArgs& a, int rows, int sc, int re, hipStream_t s) {
-#define GV(R, C)                                   \
-    case R * 16 + C:                               \
-        gather_variant<MODE, R, C>(a, re, s);      \
+#define GV(R, C)                                                     \
+    case R * 16 + C:                                                 \
+        if constexpr (MODE == GATHER_STEP) {                         \
+            if (a.epi == EPI_ADAM_TV)                                \
+                gather_variant<MODE, R, C, EPI_ADAM_TV>(a, re, s);   \
+            else                                                     \
+                gather_variant<MODE, R, C, EPI_GENERIC>(a, re, s);   \
+        } else {                                                     \
+            gather_variant<MODE, R, C, EPI_GENERIC>(a, re, s);       \
+        }                                                            \
         break
     switch (rows * 16 + sc) {
         GV(2, 1); GV(2, 2); GV(2, 4); GV(2, 8);
@@ -414,12 +428,17 @@ static hipError_t gather_mode(const KArgs& a, int rows, int sc, int re, hipStrea
 hipError_t launch_update(const KArgs& a, int sc, hipStream_t s) {
     if (a.ntasks <= 0) return hipSuccess;
     const dim3 g(grid_for(a.ntasks)), b(kThreads);
+    const bool fast = a.epi == EPI_ADAM_TV;
+#define UV(SC)                                                                          \
+    case SC:                                                                            \
+        if (fast) hipLaunchKernelGGL((k_update<SC, EPI_ADAM_TV>), g, b, 0, s, a);       \
+        else hipLaunchKernelGGL((k_update<SC, EPI_GENERIC>), g, b, 0, s, a);            \
+        break
     switch (sc) {
-        case 2: hipLaunchKernelGGL(k_update<2>, g, b, 0, s, a); break;
-        case 4: hipLaunchKernelGGL(k_update<4>, g, b, 0, s, a); break;
-        case 8: hipLaunchKernelGGL(k_update<8>, g, b, 0, s, a); break;
+        UV(2); UV(4); UV(8);
         default: return hipErrorInvalidValue;
     }
+#undef UV
     return hipGetLastError();
 }
 

@@ -41,6 +41,7 @@ struct StageLists {
     int fft_n = 0;  // common length of every slice (0 if they differ)
     size_t lds_rows = 0, lds_cols = 0;
     int re_proj = 0, re_gath = 0;  // largest staged regions (elements)
+    int epi = EPI_GENERIC;         // optimiser epilogue every slice of the step can take
 };
 
 StageLists plan_lists(const vp_plan* p, const DeviceTables* t, const Layout* L, const DeviceLayout* dl);

@@ -175,6 +175,7 @@ vp_status check_options(const vp_plan* p, const vp_options* o) {
 
 void launch_step(const KArgs& base, const StageLists& L, hipStream_t s, hipError_t* err, hipEvent_t* ev) {
     KArgs a = base;
+    a.epi = L.epi;
     hipError_t e;
 #define MARK(i)                                                                         \
     do {                                                                                \
@@ -504,6 +505,7 @@ vp_status session_alloc(const vp_plan* p, const vp_options* o, const vp_c64* ksp
     s->desc.loss_part = s->loss_part;
     s->desc.step = s->step_dev;
     s->lists = plan_lists(p, s->tabs, s->layout, s->dlayout);
+    s->lists.epi = epi_for(o->optimizer, o->tv_weight, o->l1_weight);
     if (tl.upd_sc && (st = session_ensure_grad(s.get())) != VP_OK) return st;
     *out = s.release();
     return VP_OK;

@@ -168,6 +168,7 @@ vp_status tune_plan(const vp_plan* p, const vp_options* o, Tiles* out) {
                 if ((st = device_layout(p, tabs, L, &dl)) != VP_OK) return st;
                 KArgs a{};
                 a.one = s->desc;
+                a.epi = s->lists.epi;
                 a.tasks = dl->t_gath;
                 a.ntasks = (int)L->t_gath.size();
                 float ms = 0.f;
@@ -196,6 +197,7 @@ vp_status tune_plan(const vp_plan* p, const vp_options* o, Tiles* out) {
         if ((st = device_layout(p, tabs, L, &dl)) != VP_OK) return st;
         KArgs a{};
         a.one = s->desc;
+        a.epi = s->lists.epi;
         a.tasks = dl->t_upd;
         a.ntasks = (int)L->t_upd.size();
         float ms = 0.f;

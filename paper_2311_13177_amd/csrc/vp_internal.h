@@ -143,6 +143,7 @@ struct KArgs {
     float2* out2;
     const float2* in0;
     double* dpart;
+    int epi;                     // optimiser epilogue of GATHER_STEP and the update pass (EPI_*)
 };
 
 // Column pass modes.
@@ -151,5 +152,12 @@ struct KArgs {
 enum { COL_STEP = 0, COL_FORWARD = 1, COL_ADJOINT = 2, COL_INVERSE = 3 };
 // Gather epilogues.
 enum { GATHER_STORE = 0, GATHER_STEP = 1 };
+// Optimiser epilogue variants: EPI_GENERIC takes the optimiser and the regulariser
+// weights from each slice's descriptor at run time; EPI_ADAM_TV is the same arithmetic
+// compiled for slices that all run Adam with TV on and L1 off.
+enum { EPI_GENERIC = 0, EPI_ADAM_TV = 1 };
+__host__ __device__ constexpr int epi_for(int optimizer, float tv_w, float l1_w) {
+    return (optimizer == VP_OPT_ADAM && tv_w != 0.f && l1_w == 0.f) ? EPI_ADAM_TV : EPI_GENERIC;
+}
 
 }  // namespace vp

@@ -104,3 +104,17 @@ def test_autotune_option_tunes_once(gpu_lib):
     r2 = B.vp_reconstruct(plan, y, B.vp_options_default(n_steps=5))
     assert plan.tiles(B.vp_options_default()) == shape
     assert _same(r1, r2)
+
+
+def test_compiled_adam_tv_epilogue_equals_the_generic_one(gpu_lib):
+    # alone, Adam with TV and no L1 runs the epilogue compiled for it; batched with a slice
+    # that needs run-time options (GD, or L1) the whole group takes the generic epilogue
+    from paper_2311_13177_amd import binding as B
+
+    probs = [_problem(B, name, 0) for name in ("static_80", "dynamic_72", "dynamic_40")]
+    opts = [B.vp_options_default(n_steps=8), B.vp_options_default(n_steps=8, tiles=(2, 2, 2, 4, 2)),
+            B.vp_options_default(n_steps=8, l1_weight=1e-4)]
+    solo = [B.vp_reconstruct(p, y, o) for (_, p, y), o in zip(probs, opts)]
+    got = B.vp_batch_reconstruct([p for _, p, _ in probs], [y for _, _, y in probs], opts)
+    for g, s in zip(got, solo):
+        assert g["status"] == 0 and _same(g, s)
