@@ -6,10 +6,10 @@
 namespace vp {
 
 // Whole-wave lane shifts by one (DPP wave_shr / wave_shl): lane i receives lane i - 1
-// (shfl_up1) or lane i + 1 (shfl_down1); the lane without a source keeps zero.
+// (shfl_up1) or lane i + 1 (shfl_down1); the lane without a source reads zero.
 template <int CTRL>
 __device__ __forceinline__ float dpp_f(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, true));
 }
 __device__ __forceinline__ float2 shfl_up1(float2 v) { return make_float2(dpp_f<0x138>(v.x), dpp_f<0x138>(v.y)); }
 __device__ __forceinline__ float2 shfl_down1(float2 v) { return make_float2(dpp_f<0x130>(v.x), dpp_f<0x130>(v.y)); }
@@ -180,7 +180,7 @@ __device__ __forceinline__ void update_and_finish(const KArgs& a, int slice, int
     u.opt = DF(optimizer); u.lr = lr; u.beta1 = DF(beta1); u.beta2 = DF(beta2); u.aeps = DF(adam_eps);
     u.c1 = 1.0f - u.beta1;
     u.c2 = 1.0f - u.beta2;
-    u.tv_w = DF(tv_w); u.l1_w = DF(l1_w); u.eps2 = teps * teps;
+    u.tv_w = DF(tv_w); u.l1_w = DF(l1_w); u.eps2 = charb_eps2(teps);
     u.inv_bc2s = 1.f;
     u.step_size = lr;
     if (u.opt == VP_OPT_ADAM) {
@@ -197,7 +197,8 @@ __device__ __forceinline__ void update_and_finish(const KArgs& a, int slice, int
 //
 // G[k][s][y][x] = sum over the knot's blade parts e (plan order, blades ascending) of
 //   w_e * (w00 g[y-oy][x-ox] + w01 g[y-oy][x-ox-1] + w10 g[y-oy-1][x-ox] + w11 g[y-oy-1][x-ox-1]),
-// the exact transpose of k_project's taps (zero outside the grid). Work item: (knot,
+// the exact transpose of k_project's taps (zero outside the grid), accumulated tap by
+// tap with the products w_e w.. from the plan's per-entry tap table. Work item: (knot,
 // tile of 64 x PPT, chunk of 4 * SCM bins); wave w owns bins s0 + w * SCM ... s0 + w * SCM
 // + SCM - 1.
 // MODE = GATHER_STORE writes (or adds to) the gradient; GATHER_STEP adds the TV/L1
@@ -232,7 +233,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
         const int RH = PPT + koy - ki->oy_min + 1, RW = kTileW + kox - ki->ox_min + 1;
         const int RE = RH * RW;
         const AS4 KnotEntry* ent = cst(DF(knot_ent));
-        const AS4 ShearEntry* shear = cst(DF(shear));
+        const AS4 ShearEntry* ktap = cst(DF(knot_tap));
         const float2* const work = DF(work);
         const int* kp = DF(knot_ptr);
         const int e0 = cst(kp)[kt], e1 = cst(kp)[kt + 1];
@@ -285,11 +286,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 if (cur[p] < e1) {
-                    const int b = ent[cur[p]].blade;
-                    const float wb = ent[cur[p]].weight;
-                    // taps of all of the wave's bins, loaded before any is used (bins past
-                    // S read the last bin's entry and are skipped)
-                    const AS4 ShearEntry* shb = shear + (size_t)b * S;
+                    // taps of all of the wave's bins, already times the part's time weight,
+                    // loaded before any is used (bins past S read the last bin's entry and
+                    // are skipped)
+                    const AS4 ShearEntry* shb = ktap + (size_t)cur[p] * S;
                     int tox[SCM], toy[SCM];
                     float tw[SCM][4];
 #pragma unroll
@@ -312,12 +312,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
 #pragma unroll
                             for (int i = 0; i < PPT; ++i) {
                                 const float2 v0 = L[i * RW], v1 = L[i * RW - 1];
-                                float2 t = make_float2(0.f, 0.f);
+                                float2 t = acc[q][i];
                                 t = cfma(w00, v0, t);
                                 t = cfma(w01, v1, t);
                                 t = cfma(w10, u0, t);
                                 t = cfma(w11, u1, t);
-                                acc[q][i] = cfma(wb, t, acc[q][i]);
+                                acc[q][i] = t;
                                 u0 = v0;
                                 u1 = v1;
                             }

@@ -8,7 +8,7 @@ namespace vp {
 // tv_w * grad TV + l1_w * grad L1 at voxel (t, s, y, x) of a [T][S][n][n] volume.
 __device__ __forceinline__ float2 reg_grad(const float2* __restrict__ V, size_t idx, int t, int s, int y, int x,
                                            int n, int S, int T, float tv_w, float l1_w, float eps) {
-    const float eps2 = eps * eps;
+    const float eps2 = charb_eps2(eps);
     const float2 v0 = V[idx];
     float2 g = make_float2(0.f, 0.f);
     if (tv_w != 0.f) {

@@ -53,11 +53,12 @@ __device__ __forceinline__ bool active_blade(int sched, const int* stepp, int st
 __device__ __forceinline__ int read_step(const int* stepp) { return stepp ? *cst(stepp) : 0; }
 
 // Charbonnier weight d / sqrt(|d|^2 + eps^2): the gradient of sqrt(|d|^2 + eps^2) - eps.
-// The hardware reciprocal square root (about 1 ulp); its argument is kept a normal
-// number, so no denormal handling is needed.
+// The hardware reciprocal square root (about 1 ulp). Callers pass eps2 = max(eps^2,
+// FLT_MIN) (charb_eps2), so its argument is a normal number and needs no clamp.
+__device__ __forceinline__ float charb_eps2(float eps) { return fmaxf(eps * eps, 1.17549435e-38f); }
 __device__ __forceinline__ float2 charb_w(float2 dlt, float eps2) {
     const float q = __builtin_fmaf(dlt.x, dlt.x, __builtin_fmaf(dlt.y, dlt.y, eps2));
-    return cscale(dlt, __builtin_amdgcn_rsqf(fmaxf(q, 1.17549435e-38f)));
+    return cscale(dlt, __builtin_amdgcn_rsqf(q));
 }
 
 // Work-item index of a block. The dispatcher deals consecutive blocks to the eight XCDs

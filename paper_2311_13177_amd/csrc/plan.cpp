@@ -327,6 +327,20 @@ extern "C" vp_status vp_plan_create(const vp_geometry* g, vp_plan** out) {
             }
         }
         p->knot_ptr[T] = (int)p->knot_ent.size();
+        // the adjoint's taps per knot entry: bilinear weights times the entry's time
+        // weight (exact product of the two rounded weights, rounded once)
+        p->knot_tap.resize(p->knot_ent.size() * (size_t)S);
+        for (size_t e = 0; e < p->knot_ent.size(); ++e) {
+            const double w = p->knot_ent[e].weight;
+            for (int s = 0; s < S; ++s) {
+                ShearEntry t = p->shear[(size_t)p->knot_ent[e].blade * S + s];
+                t.w00 = (float)(w * t.w00);
+                t.w01 = (float)(w * t.w01);
+                t.w10 = (float)(w * t.w10);
+                t.w11 = (float)(w * t.w11);
+                p->knot_tap[e * S + s] = t;
+            }
+        }
 
         // union of the shear extents of each knot's parts (the gather's staged halo)
         for (int kt = 0; kt < T; ++kt) {
@@ -425,7 +439,7 @@ uint64_t table_bytes(const vp_plan* p) {
     const uint64_t t_gath = (uint64_t)p->T * ceil_div(p->n, 2) * ceil_div(p->n, kTileW) * ceil_div(p->S, 4) +
                             (uint64_t)p->T * ceil_div(p->n, 4) * ceil_div(p->n, kTileW) * ceil_div(p->S, 2);
     return p->mask.size() + p->shear.size() * sizeof(ShearEntry) + p->blade.size() * sizeof(BladeDev) +
-           p->knot_ptr.size() * sizeof(int) + p->knot_ent.size() * sizeof(KnotEntry) +
+           p->knot_ptr.size() * sizeof(int) + p->knot_ent.size() * sizeof(KnotEntry) + p->knot_tap.size() * sizeof(ShearEntry) +
            groups * sizeof(ProjGroup) + p->knots.size() * sizeof(KnotInfo) + p->tw.size() * sizeof(float2) +
            (groups * tiles_proj + t_gath + p->t_rows.size() + p->t_cols.size() + p->t_vox.size() +
             p->t_render.size()) *

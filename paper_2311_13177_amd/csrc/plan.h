@@ -50,6 +50,7 @@ struct DeviceTables {
     BladeDev* blade = nullptr;
     int* knot_ptr = nullptr;
     KnotEntry* knot_ent = nullptr;
+    ShearEntry* knot_tap = nullptr;
     KnotInfo* knots = nullptr;
     float2* tw = nullptr;
     Task* t_rows = nullptr;
@@ -73,6 +74,7 @@ struct vp_plan {
     std::vector<float> alpha;            // [B]
     std::vector<int> knot_ptr;           // [T+1]
     std::vector<vp::KnotEntry> knot_ent;
+    std::vector<vp::ShearEntry> knot_tap;  // [entries][S]: the blade's taps times the entry weight
     std::vector<vp::KnotInfo> knots;    // [T]
     int max_knot_parts = 0;              // most blade parts feeding one knot
     std::vector<float2> tw;              // [n]

@@ -28,7 +28,7 @@ DeviceTables::~DeviceTables() {
     if (hipGetDevice(&prev) != hipSuccess) prev = -1;
     if (device >= 0) (void)hipSetDevice(device);
     layouts.clear();
-    void* ptrs[] = {mask, shear, blade, knot_ptr, knot_ent, knots, tw, t_rows, t_cols, t_vox, t_render};
+    void* ptrs[] = {mask, shear, blade, knot_ptr, knot_ent, knot_tap, knots, tw, t_rows, t_cols, t_vox, t_render};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (prev >= 0) (void)hipSetDevice(prev);
@@ -73,6 +73,7 @@ vp_status plan_tables(const vp_plan* p, DeviceTables** out) {
     UP(blade, p->blade);
     UP(knot_ptr, p->knot_ptr);
     UP(knot_ent, p->knot_ent);
+    UP(knot_tap, p->knot_tap);
     UP(knots, p->knots);
     UP(tw, p->tw);
     UP(t_rows, p->t_rows);
@@ -127,6 +128,7 @@ void fill_desc(const vp_plan* p, const DeviceTables* t, const Layout* L, const D
     d->blade = t->blade;
     d->knot_ptr = t->knot_ptr;
     d->knot_ent = t->knot_ent;
+    d->knot_tap = t->knot_tap;
     d->groups = dl->groups;
     d->knots = t->knots;
     d->step_limit = 0x7fffffff;

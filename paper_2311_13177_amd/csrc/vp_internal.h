@@ -112,6 +112,7 @@ struct SliceDesc {
     const BladeDev* blade;       // [B]
     const int* knot_ptr;         // [T+1] CSR offsets into knot_ent
     const KnotEntry* knot_ent;
+    const ShearEntry* knot_tap;  // [entries][S] shear taps times the entry's weight
     const ProjGroup* groups;
     const KnotInfo* knots;       // [T]
     const float2* y;             // measured k-space or nullptr
