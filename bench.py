@@ -40,6 +40,7 @@ def parse_args(argv=None):
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="approximate CPU oracle time budget")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain-loop leg")
+    ap.add_argument("--no-kplanes", action="store_true", help="skip the K-Planes dynamic model leg")
     ap.add_argument("--no-dynamic", action="store_true", help="skip the dynamic 192^2 x 32 x 16 leg")
     ap.add_argument("--batch-slices", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=200)
@@ -169,6 +170,61 @@ def batched_leg(B, n_slices, steps):
             "tiles": "batch: autotuned on its largest slice; plain loop: each plan's built-in shape"}
 
 
+KP_MODEL = dict(features=8, tv_weight=1e-3, smooth_weight=1e-2, sparse_weight=1e-3, eps=1e-3)
+
+
+def kplanes_leg(B, steps, warmup):
+    """The K-Planes dynamic model (Section 4.1: six grids of 8 complex features, two scales
+    at the image and half resolution, time nodes = the dense model's knots) fitted to the
+    dynamic 192^2 workload: step throughput, per-kernel stage times, the roofline of the
+    dominant kernel (vector ALU: a product of six factors per voxel, blade and feature) and
+    the PSNR of the fitted video."""
+    import numpy as np
+    import torch
+
+    from synth import configs
+    from synth.kplanes_init import init_params
+
+    case = configs.dynamic_192()
+    plan = B.Plan.from_geometry(case.geometry())
+    y = gpu_measurements(case, plan, B)
+    res = (case.n, case.n // 2)
+    model = B.vp_kplanes.make(KP_MODEL["features"], case.n_time, res, KP_MODEL["tv_weight"],
+                              KP_MODEL["smooth_weight"], KP_MODEL["sparse_weight"], KP_MODEL["eps"])
+    init = init_params(case.n_spec, KP_MODEL["features"], case.n_time, res, seed=case.seed)
+    opts = B.vp_options_default(n_steps=case.n_steps, lr=case.lr, device=0)
+    sess = B.KPlanesSession(plan, model, y, init, opts)
+    sess.step(warmup, use_graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sess.step(steps, use_graph=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    stages = sess.stage_times(max(3, steps // 4))
+    sess.close()
+    # flops per launch of the heavy kernels: one complex product and one complex
+    # multiply-add (14 flops) per voxel, blade, scale and feature
+    vb = case.n_blades * case.n_spec * case.n * case.n
+    fl = 14 * KP_MODEL["features"] * len(res) * vb
+    heavy = {k: v for k, v in stages.items() if k in ("grad_z", "grad_x", "grad_y")}
+    dom = max(heavy, key=lambda k: heavy[k])
+    ach = fl / (heavy[dom] * 1e-3) / 1e12
+    # quality: a whole fit, frames at the blade times against the phantom there
+    r = B.vp_kplanes_reconstruct(plan, model, y, init, opts, frame_times=case.blade_time)
+    truth = np.stack([sum(case.layers_at(float(t))) for t in case.blade_time]).astype(np.complex64)
+    p_fit = B.vp_psnr(torch.from_numpy(r["proj"]).cuda(), torch.from_numpy(truth).cuda())[0].cpu().numpy()
+    return {"workload": f"dynamic_192 geometry; K-Planes F {KP_MODEL['features']}, time nodes {case.n_time}, "
+                        f"scales {res[0]} and {res[1]}",
+            "value": round(case.n_blades * steps / el, 1), "unit": "blade fwd+adjoint/s",
+            "ms_per_step": round(el * 1e3 / steps, 5), "steps": steps,
+            "stage_ms": {k: round(v, 5) for k, v in stages.items()},
+            "roofline": {"bound": "alu", "achieved": round(ach, 3), "peak": FP32_VALU_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(ach / FP32_VALU_TFLOPS, 4), "traffic": None, "kernel": f"k_kp_{dom}",
+                         "kernel_ms": round(heavy[dom], 5), "algorithmic_flops_per_launch": fl},
+            "quality": {"psnr_db": round(float(np.mean(p_fit)), 2), "frames": int(len(case.blade_time)),
+                        "steps": case.n_steps, "model": KP_MODEL}}
+
+
 def served_leg(B, n_req, steps_static, steps_dynamic, seed=5000, slots=8):
     """A Poisson request stream of mixed static/dynamic reconstructions through the server."""
     import numpy as np
@@ -261,6 +317,37 @@ def counters_for(workload, kernel_name):
     return entry.get("bytes_per_launch")
 
 
+def quality(case, plan, B, y, rec):
+    """PSNR on magnitudes (HIP reduction) of the reconstruction and of the Section 6
+    baseline against the phantom: static, the projection against W + F and the baseline
+    over all blades; dynamic, the knot frames against the phantom at the knot times and
+    the five-blade baseline frames against it at the blade times (means over frames)."""
+    import numpy as np
+    import torch
+
+    def truth(tau):
+        w, f = case.layers_at(float(tau))
+        return (w + f).astype(np.complex64)
+
+    d_y = torch.from_numpy(y).cuda()
+    if case.n_time == 1:
+        t = torch.from_numpy(truth(0.0)[None]).cuda()
+        base = B.vp_baseline(plan, d_y)
+        kind, times = "coverage-weighted average of all blades", None
+    else:
+        t = torch.from_numpy(np.stack([truth(k / (case.n_time - 1)) for k in range(case.n_time)])).cuda()
+        base = B.vp_baseline(plan, d_y, window=5, first_frame=0, n_frames=case.n_blades)
+        times = case.blade_time
+        kind = "coverage-weighted average of the 5 most recent blades per frame"
+    ours = torch.from_numpy(np.ascontiguousarray(rec["proj"]).astype(np.complex64)).cuda()
+    p_ours = B.vp_psnr(ours, t)[0].cpu().numpy()
+    tb = t if times is None else torch.from_numpy(np.stack([truth(tau) for tau in times])).cuda()
+    p_base = B.vp_psnr(base, tb)[0].cpu().numpy()
+    return {"psnr_db": round(float(np.mean(p_ours)), 2), "baseline_psnr_db": round(float(np.mean(p_base)), 2),
+            "baseline": kind, "frames": int(p_ours.shape[0]), "baseline_frames": int(p_base.shape[0]),
+            "steps": case.n_steps}
+
+
 def measure_workload(case, B, steps, warmup):
     """Autotuned steps of one workload: throughput, per-stage times and the roofline of
     the dominant stage's kernel."""
@@ -293,6 +380,7 @@ def measure_workload(case, B, steps, warmup):
 
     stages = sess.stage_times(steps)
     sess.close()
+    qual = quality(case, plan, B, y, rec)
     stage_bytes, stage_flops, parts = algorithmic(case)
     dom = max(stages, key=lambda k: stages[k])
     dur_s = stages[dom] * 1e-3
@@ -326,6 +414,7 @@ def measure_workload(case, B, steps, warmup):
         "stage_ms": {k: round(v, 5) for k, v in stages.items()},
         "step_hbm_bytes_algorithmic": int(sum(stage_bytes.values())),
         "roofline": roof,
+        "quality": qual,
     }
 
 
@@ -366,12 +455,15 @@ def main(argv=None):
         "stage_ms": m["stage_ms"],
         "step_hbm_bytes_algorithmic": m["step_hbm_bytes_algorithmic"],
         "roofline": m["roofline"],
+        "quality": m["quality"],
     }
     if not args.no_dynamic and case.name != "dynamic_192":
         # the workload whose volume exceeds the Infinity Cache: where the HBM roofline binds
         d = measure_workload(configs.CONFIGS["dynamic_192"](), B, max(20, args.steps // 4), args.warmup)
         d.pop("recon_wall_s")
         out["dynamic_192"] = d
+    if not args.no_kplanes:
+        out["kplanes_192"] = kplanes_leg(B, max(20, args.steps // 8), 3)
     if not args.no_batch:
         out["batched"] = batched_leg(B, args.batch_slices, args.batch_steps)
     if not args.no_serve:

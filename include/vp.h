@@ -67,6 +67,7 @@ typedef struct { float re, im; } vp_c64;
 typedef struct vp_plan vp_plan;
 typedef struct vp_session vp_session;
 typedef struct vp_server vp_server;
+typedef struct vp_kplanes_session vp_kplanes_session;
 
 /* Acquisition geometry (Section 4.2 "Projection" and "Blur").
  *   n              image side; the grid is n x n and each blade's readout has n
@@ -327,6 +328,85 @@ typedef struct {
  * returns the first failure, if any. */
 vp_status vp_batch_reconstruct(int32_t n, const vp_plan* const* plans, const vp_options* const* opts,
                                const vp_c64* const* kspace, vp_result* const* results);
+
+/* ------------------------------------------------------------------ K-Planes dynamic model */
+
+/* The complex K-Planes volume model of Section 4.1 (its equation and the paragraph
+ * after it). For each scale c, six complex grids of F features,
+ *   xy [R_c][R_c][F] (row y), x-omega [S][R_c][F], y-omega [S][R_c][F],
+ *   xt [R_t][R_c][F], yt [R_t][R_c][F], omega-t [R_t][S][F],
+ * stored in this order, scale after scale, in one flat complex vector followed by the
+ * weight vector a [F]. The value at voxel (x, y, s) and time tau is
+ *   sum_c sum_f a_f * prod over the six grids of feature f read there,
+ * each grid read by linear interpolation along its axes: index i of an axis of m
+ * samples sits at i (R - 1) / (m - 1) on an axis of R nodes, tau at tau (R_t - 1); bins
+ * are read at the S nodes of the omega axis. A fit step evaluates the model at every
+ * blade's time (the plan's blade times, 0 for a static plan), projects and blurs it as
+ * in Section 4.2 and minimises the data term of Section 4.3 plus the grid regularisers
+ * below by Adam or GD on (Re, Im) of every parameter. */
+#define VP_KP_MAX_SCALES 2
+typedef struct {
+    int32_t features;                       /* F: 1, 2, 4, 8 or 16 */
+    int32_t time_res;                       /* R_t >= 1 */
+    int32_t n_scales;                       /* 1 .. VP_KP_MAX_SCALES */
+    int32_t spatial_res[VP_KP_MAX_SCALES];  /* R_c in [1, n] */
+    float tv_weight;                        /* Charbonnier TV along the grids' x, y and omega axes */
+    float smooth_weight;                    /* squared second differences along t of the time grids */
+    float sparse_weight;                    /* Charbonnier modulus of (p - 1) on the time grids */
+    float eps;                              /* Charbonnier epsilon, > 0 */
+} vp_kplanes;
+
+/* Number of complex parameters of the model for the plan's n and S. Host only.
+ * Errors: VP_ERR_ARG for NULL arguments or an invalid model (sizes out of range,
+ * non-finite weights, eps <= 0). */
+vp_status vp_kplanes_param_count(const vp_plan* plan, const vp_kplanes* model, int64_t* count);
+
+/* d_vol[n_times][S][n][n] = the model d_params at the host times[n_times] (each in
+ * [0, 1]). Device pointers on the current device; runs on `stream` and returns when it
+ * has finished (it stages small tables through host memory). */
+vp_status vp_kplanes_decode(const vp_plan* plan, const vp_kplanes* model, const vp_c64* d_params,
+                            const double* times, int32_t n_times, vp_c64* d_vol, void* stream);
+
+/* d_grad = gradient (dL/dRe + i dL/dIm) with respect to d_params of
+ * L = 0.5 sum_b |M_b DFT2(P_b f(., tau_b)) - M_b y_b|^2 + the grid regularisers, for
+ * device k-space d_kspace[B][n][n]; *objective = L and *data_term = the first sum (either
+ * may be NULL). Runs on `stream` and returns when it has finished. Device scratch (two
+ * dense [B][S][n][n] volumes and the factors) comes from the stream-ordered allocator. */
+vp_status vp_kplanes_gradient(const vp_plan* plan, const vp_kplanes* model, const vp_c64* d_params,
+                              const vp_c64* d_kspace, vp_c64* d_grad, double* objective, double* data_term,
+                              void* stream);
+
+/* Resident fit: uploads kspace[B][n][n] and the initial parameters init[count] (host)
+ * to opts->device. opts gives n_steps (unused here), optimizer, lr, beta1, beta2,
+ * adam_eps and device; tv_weight / l1_weight are ignored (the model carries its own
+ * weights); only VP_SCHED_ALL_BLADES is supported (VP_ERR_UNSUPPORTED otherwise). */
+vp_status vp_kplanes_session_create(const vp_plan* plan, const vp_kplanes* model, const vp_options* opts,
+                                    const vp_c64* kspace, const vp_c64* init, vp_kplanes_session** out);
+
+/* n_steps optimiser steps (use_graph != 0: one captured step replayed); waits. */
+vp_status vp_kplanes_session_step(vp_kplanes_session* session, int32_t n_steps, int32_t use_graph);
+
+/* Copies the parameters (params_out[count], may be NULL) and renders the model at the
+ * host frame_times[n_frames]: proj_out = sum over bins, water_out = bins below
+ * opts->split_bin (S/2 if negative), fat_out = the rest, each [n_frames][n][n] and may
+ * be NULL; *objective (may be NULL) = L at the current parameters. */
+vp_status vp_kplanes_session_read(vp_kplanes_session* session, vp_c64* params_out, int32_t n_frames,
+                                  const double* frame_times, vp_c64* proj_out, vp_c64* water_out, vp_c64* fat_out,
+                                  double* objective);
+
+/* Profiling: n_steps more eager steps with HIP events around each stage; stage_ms[6] =
+ * mean milliseconds of: factors and dense decode; projection, DFT passes and adjoint
+ * gather; the gradient of the xy factor; of the x factor; of the y factor; grid
+ * gradients, regularisers and update. */
+vp_status vp_kplanes_session_stage_times(vp_kplanes_session* session, int32_t n_steps, double* stage_ms);
+
+vp_status vp_kplanes_session_destroy(vp_kplanes_session* session);
+
+/* Whole fit: session_create, opts->n_steps graph-replayed steps, session_read, destroy. */
+vp_status vp_kplanes_reconstruct(const vp_plan* plan, const vp_kplanes* model, const vp_options* opts,
+                                 const vp_c64* kspace, const vp_c64* init, vp_c64* params_out, int32_t n_frames,
+                                 const double* frame_times, vp_c64* proj_out, vp_c64* water_out, vp_c64* fat_out,
+                                 double* final_loss);
 
 /* ------------------------------------------------------------------ serving */
 

@@ -63,6 +63,28 @@ class vp_options(ctypes.Structure):
                 ("tiles", vp_tiles), ("autotune", c_int32)]
 
 
+VP_KP_MAX_SCALES = 2
+
+
+class vp_kplanes(ctypes.Structure):
+    """K-Planes model (Section 4.1): features F, time nodes R_t, the x/y nodes of each scale
+    and the grid regulariser weights."""
+    _fields_ = [("features", c_int32), ("time_res", c_int32), ("n_scales", c_int32),
+                ("spatial_res", c_int32 * VP_KP_MAX_SCALES), ("tv_weight", c_float), ("smooth_weight", c_float),
+                ("sparse_weight", c_float), ("eps", c_float)]
+
+    @classmethod
+    def make(cls, features: int, time_res: int, spatial_res, tv_weight: float = 0.0, smooth_weight: float = 0.0,
+             sparse_weight: float = 0.0, eps: float = 1e-3) -> "vp_kplanes":
+        res = list(spatial_res)
+        m = cls()
+        m.features, m.time_res, m.n_scales = int(features), int(time_res), len(res)
+        for i, r in enumerate(res[:VP_KP_MAX_SCALES]):
+            m.spatial_res[i] = int(r)
+        m.tv_weight, m.smooth_weight, m.sparse_weight, m.eps = tv_weight, smooth_weight, sparse_weight, eps
+        return m
+
+
 class vp_result(ctypes.Structure):
     _fields_ = [("volume_out", c_void_p), ("proj_out", c_void_p), ("water_out", c_void_p),
                 ("fat_out", c_void_p), ("final_loss", c_double), ("steps_done", c_int64),
@@ -102,6 +124,17 @@ _PROTOS = {
     "vp_reconstruct": (c_int32, [_P, POINTER(vp_options), _P, _P, _P, _P, _P, _P, POINTER(c_double)]),
     "vp_batch_reconstruct": (c_int32, [c_int32, POINTER(_P), POINTER(POINTER(vp_options)), POINTER(_P),
                                        POINTER(POINTER(vp_result))]),
+    "vp_kplanes_param_count": (c_int32, [_P, POINTER(vp_kplanes), POINTER(c_int64)]),
+    "vp_kplanes_decode": (c_int32, [_P, POINTER(vp_kplanes), _P, POINTER(c_double), c_int32, _P, _P]),
+    "vp_kplanes_gradient": (c_int32, [_P, POINTER(vp_kplanes), _P, _P, _P, POINTER(c_double),
+                                      POINTER(c_double), _P]),
+    "vp_kplanes_session_create": (c_int32, [_P, POINTER(vp_kplanes), POINTER(vp_options), _P, _P, POINTER(_P)]),
+    "vp_kplanes_session_step": (c_int32, [_P, c_int32, c_int32]),
+    "vp_kplanes_session_read": (c_int32, [_P, _P, c_int32, POINTER(c_double), _P, _P, _P, POINTER(c_double)]),
+    "vp_kplanes_session_stage_times": (c_int32, [_P, c_int32, POINTER(c_double)]),
+    "vp_kplanes_session_destroy": (c_int32, [_P]),
+    "vp_kplanes_reconstruct": (c_int32, [_P, POINTER(vp_kplanes), POINTER(vp_options), _P, _P, _P, c_int32,
+                                         POINTER(c_double), _P, _P, _P, POINTER(c_double)]),
     "vp_server_create": (c_int32, [c_int32, c_uint64, c_int32, POINTER(_P)]),
     "vp_server_submit": (c_int32, [_P, _P, POINTER(vp_options), _P, POINTER(c_uint64)]),
     "vp_server_wait": (c_int32, [_P, c_uint64, c_int64, POINTER(vp_result)]),
@@ -512,3 +545,111 @@ def vp_batch_reconstruct(plans: Sequence[Plan], kspaces: Sequence[np.ndarray],
     if status != VP_OK and all(r["status"] == VP_OK for r in out):
         check(status)
     return out
+
+
+# ------------------------------------------------------------------ K-Planes dynamic model
+
+def kplanes_param_count(plan: Plan, model: vp_kplanes) -> int:
+    out = c_int64()
+    check(lib().vp_kplanes_param_count(plan.handle, byref(model), byref(out)))
+    return int(out.value)
+
+
+def _times(times):
+    t = np.ascontiguousarray(np.asarray(times, dtype=np.float64).reshape(-1))
+    return t, t.ctypes.data_as(POINTER(c_double))
+
+
+def vp_kplanes_decode(plan: Plan, model: vp_kplanes, params, times, out=None, stream=None):
+    """The model at each time: a [len(times)][S][n][n] complex64 GPU tensor."""
+    import torch
+
+    t, tp = _times(times)
+    np_ = kplanes_param_count(plan, model)
+    shp = (len(t), plan.n_spec, plan.n, plan.n)
+    if out is None:
+        out = torch.empty(shp, dtype=torch.complex64, device=params.device)
+    check(lib().vp_kplanes_decode(plan.handle, byref(model), _dev(params, (np_,), "params"), tp, len(t),
+                                  _dev(out, shp, "out"), _stream(stream)))
+    return out
+
+
+def vp_kplanes_gradient(plan: Plan, model: vp_kplanes, params, kspace, grad=None, stream=None):
+    """Returns (grad, objective, data_term) for GPU tensors params [count] and kspace [B][n][n]."""
+    import torch
+
+    np_ = kplanes_param_count(plan, model)
+    if grad is None:
+        grad = torch.empty((np_,), dtype=torch.complex64, device=params.device)
+    obj, data = c_double(), c_double()
+    check(lib().vp_kplanes_gradient(plan.handle, byref(model), _dev(params, (np_,), "params"),
+                                    _dev(kspace, plan.blade_shape, "kspace"), _dev(grad, (np_,), "grad"),
+                                    byref(obj), byref(data), _stream(stream)))
+    return grad, obj.value, data.value
+
+
+class KPlanesSession:
+    """Resident K-Planes fit on one device (vp_kplanes_session_*)."""
+
+    def __init__(self, plan: Plan, model: vp_kplanes, kspace: np.ndarray, init: np.ndarray,
+                 opts: Optional[vp_options] = None):
+        self.plan, self.model = plan, model
+        self.opts = opts if opts is not None else vp_options_default()
+        self.count = kplanes_param_count(plan, model)
+        self._k = _host_c64(kspace, plan.blade_shape)
+        self._i = _host_c64(init, (self.count,))
+        h = c_void_p()
+        check(lib().vp_kplanes_session_create(plan.handle, byref(model), byref(self.opts), _hp(self._k),
+                                              _hp(self._i), byref(h)))
+        self.handle = h
+
+    def step(self, n_steps: int, use_graph: bool = True) -> None:
+        check(lib().vp_kplanes_session_step(self.handle, int(n_steps), int(bool(use_graph))))
+
+    def read(self, frame_times=(), objective: bool = False):
+        t, tp = _times(frame_times)
+        n = self.plan.blade_shape[1]
+        params = np.empty(self.count, dtype=np.complex64)
+        outs = [np.empty((len(t), n, n), dtype=np.complex64) for _ in range(3)]
+        obj = c_double()
+        check(lib().vp_kplanes_session_read(self.handle, _hp(params), len(t), tp if len(t) else None,
+                                            *[_hp(o) if len(t) else None for o in outs],
+                                            byref(obj) if objective else None))
+        res = dict(params=params, proj=outs[0], water=outs[1], fat=outs[2])
+        if objective:
+            res["objective"] = obj.value
+        return res
+
+    def stage_times(self, n_steps: int = 10):
+        ms = (c_double * 6)()
+        check(lib().vp_kplanes_session_stage_times(self.handle, int(n_steps), ms))
+        return dict(zip(("decode", "blade_fwd_adj", "grad_z", "grad_x", "grad_y", "grids_update"), list(ms)))
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            lib().vp_kplanes_session_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def vp_kplanes_reconstruct(plan: Plan, model: vp_kplanes, kspace: np.ndarray, init: np.ndarray,
+                           opts: Optional[vp_options] = None, frame_times=(0.0,)):
+    """Whole K-Planes fit: dict(params, proj, water, fat, final_loss)."""
+    opts = opts if opts is not None else vp_options_default()
+    count = kplanes_param_count(plan, model)
+    k = _host_c64(kspace, plan.blade_shape)
+    i = _host_c64(init, (count,))
+    t, tp = _times(frame_times)
+    n = plan.blade_shape[1]
+    params = np.empty(count, dtype=np.complex64)
+    outs = [np.empty((len(t), n, n), dtype=np.complex64) for _ in range(3)]
+    loss = c_double()
+    check(lib().vp_kplanes_reconstruct(plan.handle, byref(model), byref(opts), _hp(k), _hp(i), _hp(params),
+                                       len(t), tp if len(t) else None, *[_hp(o) if len(t) else None for o in outs],
+                                       byref(loss)))
+    return dict(params=params, proj=outs[0], water=outs[1], fat=outs[2], final_loss=loss.value)

@@ -1,0 +1,619 @@
+// Kernels of the complex K-Planes dynamic model (Section 4.1): the separable factors,
+// the dense per-blade decode, the gradient back through the factors (gather form, fixed
+// summation orders), the grid regularisers of Section 4.3 and the optimiser update.
+
+#include "kcommon.h"
+#include "kplanes.h"
+
+namespace vp {
+
+namespace {
+
+// a * b + c and conj(a) * b + c with explicit fused multiply-adds
+__device__ __forceinline__ float2 cmad(float2 a, float2 b, float2 c) {
+    return make_float2(__builtin_fmaf(a.x, b.x, __builtin_fmaf(-a.y, b.y, c.x)),
+                       __builtin_fmaf(a.x, b.y, __builtin_fmaf(a.y, b.x, c.y)));
+}
+__device__ __forceinline__ float2 cjmad(float2 a, float2 b, float2 c) {
+    return make_float2(__builtin_fmaf(a.x, b.x, __builtin_fmaf(a.y, b.y, c.x)),
+                       __builtin_fmaf(a.x, b.y, __builtin_fmaf(-a.y, b.x, c.y)));
+}
+// (1 - w) a + w b
+__device__ __forceinline__ float2 clerp(float2 a, float2 b, float w) { return cfma(w, b, cscale(a, 1.0f - w)); }
+
+__device__ __forceinline__ long long gtid() { return (long long)blockIdx.x * blockDim.x + threadIdx.x; }
+__device__ __forceinline__ long long gstride() { return (long long)gridDim.x * blockDim.x; }
+
+// Grid value of scale c along one spatial axis at sample i: p[stride * node] rows.
+__device__ __forceinline__ float2 read_x(const float2* p, long long stride, const KPDesc& d, int c, int i) {
+    const int i0 = d.nd0[c * d.n + i];
+    const int i1 = min(i0 + 1, d.R[c] - 1);
+    return clerp(p[i0 * stride], p[i1 * stride], d.ndw[c * d.n + i]);
+}
+
+// ------------------------------------------------------------------ factors
+
+// Xs, Ys [ns][S][n][F]
+__global__ __launch_bounds__(kThreads) void k_kp_fac_s(const KPDesc d) {
+    const long long total = (long long)d.ns * d.S * d.n * d.F;
+    for (long long e = gtid(); e < total; e += gstride()) {
+        const int f = (int)(e % d.F);
+        const int i = (int)((e / d.F) % d.n);
+        const int s = (int)((e / ((long long)d.F * d.n)) % d.S);
+        const int c = (int)(e / ((long long)d.F * d.n * d.S));
+        const int R = d.R[c];
+        const float2* xs = d.params + d.off[c][KP_XS] + (long long)s * R * d.F + f;
+        const float2* ys = d.params + d.off[c][KP_YS] + (long long)s * R * d.F + f;
+        d.Xs[e] = read_x(xs, d.F, d, c, i);
+        d.Ys[e] = read_x(ys, d.F, d, c, i);
+    }
+}
+
+// qx, qy [ns][B][n][F] and qs [ns][B][S][F]: time grids at each time
+__global__ __launch_bounds__(kThreads) void k_kp_fac_t(const KPDesc d) {
+    const long long nq = (long long)d.ns * d.B * d.n * d.F;
+    const long long total = nq + (long long)d.ns * d.B * d.S * d.F;
+    for (long long e = gtid(); e < total; e += gstride()) {
+        if (e < nq) {
+            const int f = (int)(e % d.F);
+            const int i = (int)((e / d.F) % d.n);
+            const int b = (int)((e / ((long long)d.F * d.n)) % d.B);
+            const int c = (int)(e / ((long long)d.F * d.n * d.B));
+            const int R = d.R[c];
+            const int k0 = d.tk[b], k1 = min(k0 + 1, d.Rt - 1);
+            const float a = d.ta[b];
+            const float2* xt = d.params + d.off[c][KP_XT] + f;
+            const float2* yt = d.params + d.off[c][KP_YT] + f;
+            const long long row = (long long)R * d.F;
+            d.qx[e] = clerp(read_x(xt + k0 * row, d.F, d, c, i), read_x(xt + k1 * row, d.F, d, c, i), a);
+            d.qy[e] = clerp(read_x(yt + k0 * row, d.F, d, c, i), read_x(yt + k1 * row, d.F, d, c, i), a);
+        } else {
+            const long long r = e - nq;
+            const int f = (int)(r % d.F);
+            const int s = (int)((r / d.F) % d.S);
+            const int b = (int)((r / ((long long)d.F * d.S)) % d.B);
+            const int c = (int)(r / ((long long)d.F * d.S * d.B));
+            const int k0 = d.tk[b], k1 = min(k0 + 1, d.Rt - 1);
+            const float2* st = d.params + d.off[c][KP_ST] + (long long)s * d.F + f;
+            const long long row = (long long)d.S * d.F;
+            d.qs[r] = clerp(st[k0 * row], st[k1 * row], d.ta[b]);
+        }
+    }
+}
+
+// Z [ns][n][n][F]: the xy grid at (y, x), along x first
+__global__ __launch_bounds__(kThreads) void k_kp_fac_z(const KPDesc d) {
+    const long long total = (long long)d.ns * d.n * d.n * d.F;
+    for (long long e = gtid(); e < total; e += gstride()) {
+        const int f = (int)(e % d.F);
+        const int x = (int)((e / d.F) % d.n);
+        const int y = (int)((e / ((long long)d.F * d.n)) % d.n);
+        const int c = (int)(e / ((long long)d.F * d.n * d.n));
+        const int R = d.R[c];
+        const float2* xy = d.params + d.off[c][KP_XY] + f;
+        const int j0 = d.nd0[c * d.n + y], j1 = min(j0 + 1, R - 1);
+        const float2 r0 = read_x(xy + (long long)j0 * R * d.F, d.F, d, c, x);
+        const float2 r1 = read_x(xy + (long long)j1 * R * d.F, d.F, d, c, x);
+        d.Z[e] = clerp(r0, r1, d.ndw[c * d.n + y]);
+    }
+}
+
+// XA = a Xs qx qs and Yf = Ys qy, [ns][B][S][n][F]
+__global__ __launch_bounds__(kThreads) void k_kp_prod(const KPDesc d) {
+    const long long total = (long long)d.ns * d.B * d.S * d.n * d.F;
+    for (long long e = gtid(); e < total; e += gstride()) {
+        const int f = (int)(e % d.F);
+        const int i = (int)((e / d.F) % d.n);
+        const int s = (int)((e / ((long long)d.F * d.n)) % d.S);
+        const int b = (int)((e / ((long long)d.F * d.n * d.S)) % d.B);
+        const int c = (int)(e / ((long long)d.F * d.n * d.S * d.B));
+        const long long xs = (((long long)c * d.S + s) * d.n + i) * d.F + f;
+        const long long qi = (((long long)c * d.B + b) * d.n + i) * d.F + f;
+        const long long qsi = (((long long)c * d.B + b) * d.S + s) * d.F + f;
+        const float2 a = d.params[d.a_off + f];
+        d.XA[e] = cmul(cmul(cmul(a, d.Xs[xs]), d.qx[qi]), d.qs[qsi]);
+        d.Yf[e] = cmul(d.Ys[xs], d.qy[qi]);
+    }
+}
+
+// ------------------------------------------------------------------ decode
+
+// vol[b][s][y][x] = sum_c sum_f Z[c][y][x][f] XA[c][b][s][x][f] Yf[c][b][s][y][f]
+template <int F>
+__global__ __launch_bounds__(kThreads) void k_kp_decode(const KPDesc d) {
+    const int n = d.n, S = d.S;
+    const long long total = (long long)d.B * S * n * n;
+    for (long long e = gtid(); e < total; e += gstride()) {
+        const int x = (int)(e % n);
+        const int y = (int)((e / n) % n);
+        const long long bs = e / ((long long)n * n);  // b * S + s
+        float2 v = make_float2(0.f, 0.f);
+        for (int c = 0; c < d.ns; ++c) {
+            const float2* z = d.Z + (((long long)c * n + y) * n + x) * F;
+            const long long cb = (long long)c * d.B * S + bs;
+            const float2* xa = d.XA + (cb * n + x) * F;
+            const float2* yf = d.Yf + (cb * n + y) * F;
+#pragma unroll
+            for (int f = 0; f < F; ++f) v = cmad(cmul(z[f], xa[f]), yf[f], v);
+        }
+        d.vol[e] = v;
+    }
+}
+
+// ------------------------------------------------------------------ gradient through the factors
+
+// gZ[c][y][x][f] = sum_b sum_s conj(XA Yf) G[b][s][y][x]
+template <int F>
+__global__ __launch_bounds__(kThreads) void k_kp_grad_z(const KPDesc d) {
+    const int n = d.n, S = d.S;
+    const long long nn = (long long)n * n;
+    for (long long e = gtid(); e < nn; e += gstride()) {
+        const int x = (int)(e % n), y = (int)(e / n);
+        for (int c = 0; c < d.ns; ++c) {
+            float2 acc[F];
+#pragma unroll
+            for (int f = 0; f < F; ++f) acc[f] = make_float2(0.f, 0.f);
+            for (int bs = 0; bs < d.B * S; ++bs) {
+                const float2 g = d.G[(long long)bs * nn + e];
+                const long long cb = (long long)c * d.B * S + bs;
+                const float2* xa = d.XA + (cb * n + x) * F;
+                const float2* yf = d.Yf + (cb * n + y) * F;
+#pragma unroll
+                for (int f = 0; f < F; ++f) acc[f] = cjmad(cmul(xa[f], yf[f]), g, acc[f]);
+            }
+            float2* out = d.gZ + ((long long)c * nn + e) * F;
+#pragma unroll
+            for (int f = 0; f < F; ++f) out[f] = acc[f];
+        }
+    }
+}
+
+// gXA[c][b][s][x][f] = sum_y conj(Z Yf) G[b][s][y][x]
+template <int F>
+__global__ __launch_bounds__(kThreads) void k_kp_grad_x(const KPDesc d) {
+    const int n = d.n, S = d.S;
+    const long long nn = (long long)n * n;
+    const long long total = (long long)d.B * S * n;
+    for (long long e = gtid(); e < total; e += gstride()) {
+        const int x = (int)(e % n);
+        const long long bs = e / n;
+        const float2* gp = d.G + bs * nn + x;
+        for (int c = 0; c < d.ns; ++c) {
+            float2 acc[F];
+#pragma unroll
+            for (int f = 0; f < F; ++f) acc[f] = make_float2(0.f, 0.f);
+            const long long cb = (long long)c * d.B * S + bs;
+            for (int y = 0; y < n; ++y) {
+                const float2 g = gp[(long long)y * n];
+                const float2* z = d.Z + (((long long)c * n + y) * n + x) * F;
+                const float2* yf = d.Yf + (cb * n + y) * F;
+#pragma unroll
+                for (int f = 0; f < F; ++f) acc[f] = cjmad(cmul(z[f], yf[f]), g, acc[f]);
+            }
+            float2* out = d.gXA + (cb * n + x) * F;
+#pragma unroll
+            for (int f = 0; f < F; ++f) out[f] = acc[f];
+        }
+    }
+}
+
+// gY[c][b][s][y][f] = sum_x conj(Z XA) G[b][s][y][x]: one wave per row (b, s, y), lanes
+// over x, then a butterfly sum in a fixed order
+template <int F>
+__global__ __launch_bounds__(kThreads) void k_kp_grad_y(const KPDesc d) {
+    const int n = d.n, S = d.S;
+    const int lane = threadIdx.x & 63;
+    const long long rows = (long long)d.B * S * n;
+    for (long long r = (long long)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); r < rows;
+         r += (long long)gridDim.x * (kThreads / 64)) {
+        const int y = (int)(r % n);
+        const long long bs = r / n;
+        const float2* gp = d.G + r * n;
+        for (int c = 0; c < d.ns; ++c) {
+            float2 acc[F];
+#pragma unroll
+            for (int f = 0; f < F; ++f) acc[f] = make_float2(0.f, 0.f);
+            const long long cb = (long long)c * d.B * S + bs;
+            for (int x = lane; x < n; x += 64) {
+                const float2 g = gp[x];
+                const float2* z = d.Z + (((long long)c * n + y) * n + x) * F;
+                const float2* xa = d.XA + (cb * n + x) * F;
+#pragma unroll
+                for (int f = 0; f < F; ++f) acc[f] = cjmad(cmul(z[f], xa[f]), g, acc[f]);
+            }
+#pragma unroll
+            for (int f = 0; f < F; ++f) {
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) {
+                    acc[f].x += __shfl_xor(acc[f].x, o);
+                    acc[f].y += __shfl_xor(acc[f].y, o);
+                }
+            }
+            if (lane == 0) {
+                float2* out = d.gY + (cb * n + y) * F;
+#pragma unroll
+                for (int f = 0; f < F; ++f) out[f] = acc[f];
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ chain to the grids
+
+// Independent sums over one index each:
+//   gXs[c][s][x][f] = sum_b conj(a qx qs) gXA        gqx[c][b][x][f] = sum_s conj(a Xs qs) gXA
+//   h[c][b][s][f]   = sum_x conj(Xs qx) gXA          gqs = conj(a) h
+//   gYs[c][s][y][f] = sum_b conj(qy) gY              gqy[c][b][y][f] = sum_s conj(Ys) gY
+__global__ __launch_bounds__(kThreads) void k_kp_chain1(const KPDesc d) {
+    const int n = d.n, S = d.S, B = d.B, F = d.F;
+    const long long n_sn = (long long)d.ns * S * n * F;   // gXs, gYs
+    const long long n_bn = (long long)d.ns * B * n * F;   // gqx, gqy
+    const long long n_bs = (long long)d.ns * B * S * F;   // h, gqs
+    const long long total = 2 * n_sn + 2 * n_bn + n_bs;
+    for (long long e = gtid(); e < total; e += gstride()) {
+        float2 acc = make_float2(0.f, 0.f);
+        if (e < 2 * n_sn) {
+            const bool isx = e < n_sn;
+            const long long r = isx ? e : e - n_sn;
+            const int f = (int)(r % F);
+            const int i = (int)((r / F) % n);
+            const int s = (int)((r / ((long long)F * n)) % S);
+            const int c = (int)(r / ((long long)F * n * S));
+            const float2 a = d.params[d.a_off + f];
+            for (int b = 0; b < B; ++b) {
+                const long long cbs = ((long long)c * B + b) * S + s;
+                const long long qi = (((long long)c * B + b) * n + i) * F + f;
+                const float2 gv = (isx ? d.gXA : d.gY)[(cbs * n + i) * F + f];
+                const float2 w = isx ? cmul(cmul(a, d.qx[qi]), d.qs[cbs * F + f]) : d.qy[qi];
+                acc = cjmad(w, gv, acc);
+            }
+            (isx ? d.gXs : d.gYs)[r] = acc;
+        } else if (e < 2 * n_sn + 2 * n_bn) {
+            const long long e2 = e - 2 * n_sn;
+            const bool isx = e2 < n_bn;
+            const long long r = isx ? e2 : e2 - n_bn;
+            const int f = (int)(r % F);
+            const int i = (int)((r / F) % n);
+            const int b = (int)((r / ((long long)F * n)) % B);
+            const int c = (int)(r / ((long long)F * n * B));
+            const float2 a = d.params[d.a_off + f];
+            for (int s = 0; s < S; ++s) {
+                const long long cbs = ((long long)c * B + b) * S + s;
+                const long long si = (((long long)c * S + s) * n + i) * F + f;
+                const float2 gv = (isx ? d.gXA : d.gY)[(cbs * n + i) * F + f];
+                const float2 w = isx ? cmul(cmul(a, d.Xs[si]), d.qs[cbs * F + f]) : d.Ys[si];
+                acc = cjmad(w, gv, acc);
+            }
+            (isx ? d.gqx : d.gqy)[r] = acc;
+        } else {
+            const long long r = e - 2 * n_sn - 2 * n_bn;
+            const int f = (int)(r % F);
+            const long long cbs = r / F;
+            const int s = (int)(cbs % S);
+            const int b = (int)((cbs / S) % B);
+            const int c = (int)(cbs / ((long long)S * B));
+            for (int x = 0; x < n; ++x) {
+                const float2 w = cmul(d.Xs[(((long long)c * S + s) * n + x) * F + f],
+                                      d.qx[(((long long)c * B + b) * n + x) * F + f]);
+                acc = cjmad(w, d.gXA[(cbs * n + x) * F + f], acc);
+            }
+            d.h[r] = acc;
+            d.gqs[r] = cjmad(d.params[d.a_off + f], acc, make_float2(0.f, 0.f));
+        }
+    }
+}
+
+// ga[f] = sum_c sum_b sum_s conj(qs) h
+__global__ __launch_bounds__(kThreads) void k_kp_chain_a(const KPDesc d) {
+    for (int f = threadIdx.x; f < d.F; f += blockDim.x) {
+        float2 acc = make_float2(0.f, 0.f);
+        const long long nbs = (long long)d.ns * d.B * d.S;
+        for (long long cbs = 0; cbs < nbs; ++cbs) acc = cjmad(d.qs[cbs * d.F + f], d.h[cbs * d.F + f], acc);
+        d.ga[f] = acc;
+    }
+}
+
+// Which grid holds flat element e, and its index within the grid (a: plane KP_PLANES).
+__device__ __forceinline__ void locate(const KPDesc& d, long long e, int* c, int* pl, long long* idx) {
+    if (e >= d.a_off) {
+        *c = 0; *pl = KP_PLANES; *idx = e - d.a_off;
+        return;
+    }
+    for (int cc = d.ns - 1; cc >= 0; --cc)
+        for (int p = KP_PLANES - 1; p >= 0; --p)
+            if (e >= d.off[cc][p]) {
+                *c = cc; *pl = p; *idx = e - d.off[cc][p];
+                return;
+            }
+    *c = 0; *pl = 0; *idx = e;
+}
+
+// Length of a grid's first and second axes (F is the third).
+__device__ __forceinline__ void grid_dims(const KPDesc& d, int c, int pl, int* d0, int* d1) {
+    const int R = d.R[c];
+    switch (pl) {
+        case KP_XY: *d0 = R; *d1 = R; break;
+        case KP_XS: case KP_YS: *d0 = d.S; *d1 = R; break;
+        case KP_XT: case KP_YT: *d0 = d.Rt; *d1 = R; break;
+        default: *d0 = d.Rt; *d1 = d.S; break;
+    }
+}
+
+// Grid regulariser gradient (Section 4.3 readings): Charbonnier TV along the grid's x, y
+// and omega axes, squared second differences along t and Charbonnier sparsity of p - 1
+// on the time grids.
+__device__ float2 reg_grad(const KPDesc& d, int c, int pl, int i0, int i1, int f, const float2* p) {
+    int d0, d1;
+    grid_dims(d, c, pl, &d0, &d1);
+    const long long s0 = (long long)d1 * d.F, s1 = d.F;  // strides of the two axes
+    const float2 v = p[0];
+    float2 g = make_float2(-0.f, -0.f);
+    const bool time = pl == KP_XT || pl == KP_YT || pl == KP_ST;
+    if (d.tv_w != 0.f) {
+        float2 t = make_float2(-0.f, -0.f);
+        if (!time) {  // axis 0 is x, y or omega for the static grids
+            if (i0 > 0) t = cadd(t, charb_w(csub(v, p[-s0]), d.eps2));
+            if (i0 + 1 < d0) t = csub(t, charb_w(csub(p[s0], v), d.eps2));
+        }
+        if (i1 > 0) t = cadd(t, charb_w(csub(v, p[-s1]), d.eps2));
+        if (i1 + 1 < d1) t = csub(t, charb_w(csub(p[s1], v), d.eps2));
+        g = cfma(d.tv_w, t, g);
+    }
+    if (time && d.smooth_w != 0.f) {
+        // d2_m = p[m+1] - 2 p[m] + p[m-1], m in [1, d0 - 2]; p[k] appears in m = k-1, k, k+1
+        float2 t = make_float2(-0.f, -0.f);
+        for (int m = i0 - 1; m <= i0 + 1; ++m) {
+            if (m < 1 || m > d0 - 2) continue;
+            const float2* q = p + (long long)(m - i0) * s0;
+            const float2 d2 = cadd(csub(q[s0], cscale(q[0], 2.f)), q[-s0]);
+            const float coef = m == i0 ? -4.f : 2.f;
+            t = cfma(coef, d2, t);
+        }
+        g = cfma(d.smooth_w, t, g);
+    }
+    if (time && d.sparse_w != 0.f) g = cfma(d.sparse_w, charb_w(make_float2(v.x - 1.f, v.y), d.eps2), g);
+    return g;
+}
+
+// Data gradient of every grid element (transposed interpolation, gather form) plus the
+// regulariser gradient -> grad.
+__global__ __launch_bounds__(kThreads) void k_kp_grid(const KPDesc d) {
+    const int n = d.n, S = d.S, F = d.F;
+    for (long long e = gtid(); e < d.n_params; e += gstride()) {
+        int c, pl;
+        long long idx;
+        locate(d, e, &c, &pl, &idx);
+        if (pl == KP_PLANES) {
+            d.grad[e] = d.ga[idx];
+            continue;
+        }
+        int d0, d1;
+        grid_dims(d, c, pl, &d0, &d1);
+        const int f = (int)(idx % F);
+        const int i1 = (int)((idx / F) % d1);
+        const int i0 = (int)(idx / ((long long)F * d1));
+        const int* tp = d.tr_ptr + c * (n + 1);
+        float2 acc = make_float2(0.f, 0.f);
+        switch (pl) {
+            case KP_XY:  // rows i0 (y nodes), columns i1 (x nodes)
+                for (int a = tp[i0]; a < tp[i0 + 1]; ++a) {
+                    const int y = d.tr_smp[a];
+                    float2 row = make_float2(0.f, 0.f);
+                    for (int q = tp[i1]; q < tp[i1 + 1]; ++q)
+                        row = cfma(d.tr_w[q], d.gZ[(((long long)c * n + y) * n + d.tr_smp[q]) * F + f], row);
+                    acc = cfma(d.tr_w[a], row, acc);
+                }
+                break;
+            case KP_XS:
+            case KP_YS: {
+                const float2* src = pl == KP_XS ? d.gXs : d.gYs;
+                for (int q = tp[i1]; q < tp[i1 + 1]; ++q)
+                    acc = cfma(d.tr_w[q], src[(((long long)c * S + i0) * n + d.tr_smp[q]) * F + f], acc);
+                break;
+            }
+            case KP_XT:
+            case KP_YT: {
+                const float2* src = pl == KP_XT ? d.gqx : d.gqy;
+                for (int t = d.tt_ptr[i0]; t < d.tt_ptr[i0 + 1]; ++t) {
+                    const int b = d.tt_b[t];
+                    float2 part = make_float2(0.f, 0.f);
+                    for (int q = tp[i1]; q < tp[i1 + 1]; ++q)
+                        part = cfma(d.tr_w[q], src[(((long long)c * d.B + b) * n + d.tr_smp[q]) * F + f], part);
+                    acc = cfma(d.tt_w[t], part, acc);
+                }
+                break;
+            }
+            default:  // omega-t: rows i0 (time nodes), columns i1 (bins)
+                for (int t = d.tt_ptr[i0]; t < d.tt_ptr[i0 + 1]; ++t)
+                    acc = cfma(d.tt_w[t], d.gqs[(((long long)c * d.B + d.tt_b[t]) * S + i1) * F + f], acc);
+                break;
+        }
+        d.grad[e] = cadd(acc, reg_grad(d, c, pl, i0, i1, f, d.params + e));
+    }
+}
+
+// Regulariser value: per element its forward differences (TV), the second difference
+// centred on it (smoothness) and its sparsity term, as |z|^2 / (sqrt(|z|^2 + e^2) + e) for
+// the Charbonnier terms; FP64 block sums in a fixed order -> rpart[block].
+__global__ __launch_bounds__(kThreads) void k_kp_reg_value(const KPDesc d) {
+    __shared__ double red[kThreads];
+    const double e2 = (double)d.eps2, ep = sqrt(e2);
+    auto charb = [&](float2 z) {
+        const double q = (double)z.x * z.x + (double)z.y * z.y;
+        return q / (sqrt(q + e2) + ep);
+    };
+    double acc = 0.0;
+    for (long long e = gtid(); e < d.a_off; e += gstride()) {
+        int c, pl;
+        long long idx;
+        locate(d, e, &c, &pl, &idx);
+        int d0, d1;
+        grid_dims(d, c, pl, &d0, &d1);
+        const int i1 = (int)((idx / d.F) % d1);
+        const int i0 = (int)(idx / ((long long)d.F * d1));
+        const long long s0 = (long long)d1 * d.F, s1 = d.F;
+        const float2* p = d.params + e;
+        const bool time = pl == KP_XT || pl == KP_YT || pl == KP_ST;
+        if (d.tv_w != 0.f) {
+            double t = 0.0;
+            if (!time && i0 + 1 < d0) t += charb(csub(p[s0], p[0]));
+            if (i1 + 1 < d1) t += charb(csub(p[s1], p[0]));
+            acc += (double)d.tv_w * t;
+        }
+        if (time && d.smooth_w != 0.f && i0 >= 1 && i0 <= d0 - 2) {
+            const double rx = ((double)p[s0].x - 2.0 * p[0].x) + p[-s0].x;
+            const double ry = ((double)p[s0].y - 2.0 * p[0].y) + p[-s0].y;
+            acc += (double)d.smooth_w * (rx * rx + ry * ry);
+        }
+        if (time && d.sparse_w != 0.f) acc += (double)d.sparse_w * charb(make_float2(p[0].x - 1.f, p[0].y));
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = kThreads / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) d.rpart[blockIdx.x] = red[0];
+}
+
+// Adam (or GD) on every parameter, (Re, Im) as independent reals; step t = counter + 1.
+__global__ __launch_bounds__(kThreads) void k_kp_update(const KPDesc d) {
+    const int st = d.step ? *d.step : 0;
+    const bool adam = d.optimizer == VP_OPT_ADAM;
+    float step_size = d.lr, inv_bc2s = 1.f;
+    if (adam) {
+        const float tf = (float)(st + 1);
+        const float bc1 = -expm1f(tf * d.ln_beta1), bc2 = -expm1f(tf * d.ln_beta2);
+        step_size = d.lr / bc1;
+        inv_bc2s = 1.f / sqrtf(bc2);
+    }
+    float2* p = const_cast<float2*>(d.params);
+    for (long long e = gtid(); e < d.n_params; e += gstride()) {
+        const float2 g = d.grad[e], v0 = p[e];
+        if (adam) {
+            float2 m = d.m[e], v = d.v[e];
+            m.x = __builtin_fmaf(d.beta1, m.x, d.c1 * g.x);
+            m.y = __builtin_fmaf(d.beta1, m.y, d.c1 * g.y);
+            v.x = __builtin_fmaf(d.beta2, v.x, (d.c2 * g.x) * g.x);
+            v.y = __builtin_fmaf(d.beta2, v.y, (d.c2 * g.y) * g.y);
+            d.m[e] = m;
+            d.v[e] = v;
+            const float dx = __builtin_fmaf(__builtin_amdgcn_sqrtf(v.x), inv_bc2s, d.aeps);
+            const float dy = __builtin_fmaf(__builtin_amdgcn_sqrtf(v.y), inv_bc2s, d.aeps);
+            p[e] = make_float2(__builtin_fmaf(-step_size, m.x * __builtin_amdgcn_rcpf(dx), v0.x),
+                               __builtin_fmaf(-step_size, m.y * __builtin_amdgcn_rcpf(dy), v0.y));
+        } else {
+            p[e] = make_float2(__builtin_fmaf(-d.lr, g.x, v0.x), __builtin_fmaf(-d.lr, g.y, v0.y));
+        }
+    }
+}
+
+__global__ void k_kp_advance(int* step) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *step = *step + 1;
+}
+
+// proj / water / fat of vol [B][S][n][n]
+__global__ __launch_bounds__(kThreads) void k_kp_render(const KPDesc d, int split, float2* proj, float2* water,
+                                                        float2* fat) {
+    const long long nn = (long long)d.n * d.n;
+    const long long total = (long long)d.B * nn;
+    for (long long e = gtid(); e < total; e += gstride()) {
+        const long long b = e / nn, px = e % nn;
+        float2 w = make_float2(0.f, 0.f), ft = w;
+        for (int s = 0; s < d.S; ++s) {
+            const float2 v = d.vol[(b * d.S + s) * nn + px];
+            if (s < split) w = cadd(w, v);
+            else ft = cadd(ft, v);
+        }
+        if (proj) proj[e] = cadd(w, ft);
+        if (water) water[e] = w;
+        if (fat) fat[e] = ft;
+    }
+}
+
+inline unsigned grid_of(long long total) {
+    const long long g = (total + kThreads - 1) / kThreads;
+    return (unsigned)(g < 1 ? 1 : (g > (1 << 20) ? (1 << 20) : g));
+}
+
+}  // namespace
+
+bool kp_features_ok(int f) { return f == 1 || f == 2 || f == 4 || f == 8 || f == 16; }
+
+hipError_t kp_launch_factors(const KPDesc& d, hipStream_t s) {
+    const dim3 b(kThreads);
+    hipLaunchKernelGGL(k_kp_fac_s, dim3(grid_of((long long)d.ns * d.S * d.n * d.F)), b, 0, s, d);
+    hipLaunchKernelGGL(k_kp_fac_t, dim3(grid_of((long long)d.ns * d.B * (d.n + d.S) * d.F)), b, 0, s, d);
+    hipLaunchKernelGGL(k_kp_fac_z, dim3(grid_of((long long)d.ns * d.n * d.n * d.F)), b, 0, s, d);
+    hipLaunchKernelGGL(k_kp_prod, dim3(grid_of((long long)d.ns * d.B * d.S * d.n * d.F)), b, 0, s, d);
+    return hipGetLastError();
+}
+
+#define KP_F_SWITCH(KERNEL, GRID)                                                   \
+    switch (d.F) {                                                                  \
+        case 1: hipLaunchKernelGGL(KERNEL<1>, GRID, dim3(kThreads), 0, s, d); break;   \
+        case 2: hipLaunchKernelGGL(KERNEL<2>, GRID, dim3(kThreads), 0, s, d); break;   \
+        case 4: hipLaunchKernelGGL(KERNEL<4>, GRID, dim3(kThreads), 0, s, d); break;   \
+        case 8: hipLaunchKernelGGL(KERNEL<8>, GRID, dim3(kThreads), 0, s, d); break;   \
+        case 16: hipLaunchKernelGGL(KERNEL<16>, GRID, dim3(kThreads), 0, s, d); break; \
+        default: return hipErrorInvalidValue;                                       \
+    }
+
+hipError_t kp_launch_decode(const KPDesc& d, hipStream_t s) {
+    KP_F_SWITCH(k_kp_decode, dim3(grid_of((long long)d.B * d.S * d.n * d.n)));
+    return hipGetLastError();
+}
+
+hipError_t kp_launch_back_z(const KPDesc& d, hipStream_t s) {
+    KP_F_SWITCH(k_kp_grad_z, dim3(grid_of((long long)d.n * d.n)));
+    return hipGetLastError();
+}
+hipError_t kp_launch_back_x(const KPDesc& d, hipStream_t s) {
+    KP_F_SWITCH(k_kp_grad_x, dim3(grid_of((long long)d.B * d.S * d.n)));
+    return hipGetLastError();
+}
+hipError_t kp_launch_back_y(const KPDesc& d, hipStream_t s) {
+    const long long rows = (long long)d.B * d.S * d.n;
+    const long long blocks = (rows + kThreads / 64 - 1) / (kThreads / 64);
+    KP_F_SWITCH(k_kp_grad_y, dim3((unsigned)(blocks > (1 << 20) ? (1 << 20) : blocks)));
+    return hipGetLastError();
+}
+hipError_t kp_launch_back(const KPDesc& d, hipStream_t s) {
+    hipError_t e = kp_launch_back_z(d, s);
+    if (e == hipSuccess) e = kp_launch_back_x(d, s);
+    if (e == hipSuccess) e = kp_launch_back_y(d, s);
+    return e;
+}
+#undef KP_F_SWITCH
+
+hipError_t kp_launch_chain(const KPDesc& d, hipStream_t s) {
+    const long long total = 2LL * d.ns * d.S * d.n * d.F + 2LL * d.ns * d.B * d.n * d.F + (long long)d.ns * d.B * d.S * d.F;
+    hipLaunchKernelGGL(k_kp_chain1, dim3(grid_of(total)), dim3(kThreads), 0, s, d);
+    hipLaunchKernelGGL(k_kp_chain_a, dim3(1), dim3(kThreads), 0, s, d);
+    hipLaunchKernelGGL(k_kp_grid, dim3(grid_of(d.n_params)), dim3(kThreads), 0, s, d);
+    return hipGetLastError();
+}
+
+hipError_t kp_launch_update(const KPDesc& d, hipStream_t s) {
+    hipLaunchKernelGGL(k_kp_update, dim3(grid_of(d.n_params)), dim3(kThreads), 0, s, d);
+    if (d.step) hipLaunchKernelGGL(k_kp_advance, dim3(1), dim3(64), 0, s, d.step);
+    return hipGetLastError();
+}
+
+int kp_reg_blocks(const KPDesc& d) {
+    const long long g = (d.a_off + kThreads - 1) / kThreads;
+    return (int)(g < 1 ? 1 : (g > 1024 ? 1024 : g));
+}
+
+hipError_t kp_launch_reg_value(const KPDesc& d, hipStream_t s) {
+    hipLaunchKernelGGL(k_kp_reg_value, dim3(kp_reg_blocks(d)), dim3(kThreads), 0, s, d);
+    return hipGetLastError();
+}
+
+hipError_t kp_launch_render(const KPDesc& d, int split, float2* proj, float2* water, float2* fat, hipStream_t s) {
+    hipLaunchKernelGGL(k_kp_render, dim3(grid_of((long long)d.B * d.n * d.n)), dim3(kThreads), 0, s, d, split, proj,
+                       water, fat);
+    return hipGetLastError();
+}
+
+}  // namespace vp

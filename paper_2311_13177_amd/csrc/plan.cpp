@@ -232,8 +232,34 @@ extern "C" vp_status vp_options_default(vp_options* o) {
     return VP_OK;
 }
 
+namespace vp {
+// per_blade: every blade gets a knot of its own (knot b, weight 1); n_time must be B.
+static vp_status plan_create(const vp_geometry* g, bool per_blade, vp_plan** out);
+}  // namespace vp
+
 extern "C" vp_status vp_plan_create(const vp_geometry* g, vp_plan** out) {
     clear_error();
+    return vp::plan_create(g, false, out);
+}
+
+namespace vp {
+
+vp_status plan_per_blade(const vp_plan* p, const vp_plan** out) {
+    std::lock_guard<std::mutex> lk(p->mu_derived);
+    if (!p->per_blade) {
+        std::vector<double> times(p->B, 0.0);
+        const vp_geometry g{p->n, p->S, p->B, p->B, p->angle.data(), p->lines.data(),
+                            p->B > 1 ? times.data() : nullptr, p->shift.data()};
+        vp_plan* q = nullptr;
+        const vp_status st = plan_create(&g, true, &q);
+        if (st != VP_OK) return st;
+        p->per_blade.reset(q);
+    }
+    *out = p->per_blade.get();
+    return VP_OK;
+}
+
+static vp_status plan_create(const vp_geometry* g, bool per_blade, vp_plan** out) {
     if (!g || !out) return fail(VP_ERR_ARG, "vp_plan_create: NULL geometry or output");
     if (g->n < 1 || g->n_spec < 1 || g->n_time < 1 || g->n_blades < 1)
         return fail(VP_ERR_ARG, "vp_plan_create: sizes must be >= 1 (n=%d S=%d T=%d B=%d)", g->n, g->n_spec,
@@ -242,7 +268,8 @@ extern "C" vp_status vp_plan_create(const vp_geometry* g, vp_plan** out) {
         return fail(VP_ERR_ARG, "vp_plan_create: NULL angle, lines or shift array");
     if ((g->n_time == 1) != (g->blade_time == nullptr))
         return fail(VP_ERR_ARG, "vp_plan_create: blade_time must be NULL exactly when n_time == 1");
-    if (g->n > kMaxN || g->n_spec > kMaxS || g->n_time > kMaxT || g->n_blades > kMaxB)
+    if (per_blade && g->n_time != g->n_blades) return fail(VP_ERR_ARG, "per-blade plan: n_time must equal n_blades");
+    if (g->n > kMaxN || g->n_spec > kMaxS || (!per_blade && g->n_time > kMaxT) || g->n_blades > kMaxB)
         return fail(VP_ERR_UNSUPPORTED, "vp_plan_create: size above the supported maximum (n<=%d S<=%d T<=%d B<=%d)",
                     kMaxN, kMaxS, kMaxT, kMaxB);
     std::vector<int> radices;
@@ -277,7 +304,7 @@ extern "C" vp_status vp_plan_create(const vp_geometry* g, vp_plan** out) {
         if (g->blade_time) p->tau.assign(g->blade_time, g->blade_time + B);
         p->nstage = (int)radices.size();
         for (int i = 0; i < p->nstage; ++i) p->radix[i] = radices[i];
-        p->nparts = T > 1 ? 2 : 1;
+        p->nparts = (T > 1 && !per_blade) ? 2 : 1;
 
         // masks
         p->mask.resize((size_t)B * n * n);
@@ -300,8 +327,9 @@ extern "C" vp_status vp_plan_create(const vp_geometry* g, vp_plan** out) {
                 bd.oy_min = std::min(bd.oy_min, e.oy); bd.oy_max = std::max(bd.oy_max, e.oy);
             }
             // knot of the blade's time (dense knots at k/(T-1), linear blend)
-            if (T == 1) {
-                bd.knot = 0; bd.has0 = 1; bd.has1 = 0; bd.w0 = 1.0f; bd.w1 = 0.0f;
+            // (a per-blade plan: the blade's own knot, weight 1)
+            if (T == 1 || per_blade) {
+                bd.knot = per_blade ? b : 0; bd.has0 = 1; bd.has1 = 0; bd.w0 = 1.0f; bd.w1 = 0.0f;
             } else {
                 const double u = p->tau[b] * (T - 1);
                 const int k = std::min((int)std::floor(u), T - 2);
@@ -393,6 +421,8 @@ extern "C" vp_status vp_plan_create(const vp_geometry* g, vp_plan** out) {
     *out = p.release();
     return VP_OK;
 }
+
+}  // namespace vp
 
 extern "C" vp_status vp_plan_shape(const vp_plan* p, int32_t* n, int32_t* s, int32_t* t, int32_t* b) {
     if (!p) return fail(VP_ERR_ARG, "vp_plan_shape: NULL plan");

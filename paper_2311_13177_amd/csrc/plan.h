@@ -92,12 +92,19 @@ struct vp_plan {
     mutable std::mutex mu;
     mutable std::map<int, std::unique_ptr<vp::Layout>> layouts;  // host layouts by Tiles::key()
     mutable std::map<int, std::unique_ptr<vp::DeviceTables>> dev;
+    // The same geometry with a knot per blade (built on first use; K-Planes fits).
+    mutable std::mutex mu_derived;
+    mutable std::unique_ptr<vp_plan> per_blade;
 
     uint64_t voxels() const { return (uint64_t)T * S * n * n; }
     uint64_t blade_px() const { return (uint64_t)B * n * n; }
 };
 
 namespace vp {
+
+// The plan's geometry with one knot per blade (knot b holds blade b with weight 1, one
+// work part per blade), built on first use and kept with the plan.
+vp_status plan_per_blade(const vp_plan* plan, const vp_plan** out);
 
 // Device tables of `plan` on the current device, uploading them on first use.
 vp_status plan_tables(const vp_plan* plan, DeviceTables** out);

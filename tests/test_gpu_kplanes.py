@@ -1,0 +1,124 @@
+"""The K-Planes dynamic model (Section 4.1) on the GPU against the FP64 oracle.
+
+Decode is a product of six interpolated FP32 factors summed over features and scales
+(relative error about 1e-6), so it is held to 1e-5 relative over the whole volume; the
+gradient goes through the FP32 DFTs as well and takes the operator tolerance, 1e-4;
+short fits compare the parameters (GD, 1e-4) and the rendered frames (Adam, 1e-3).
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import kplanes as K
+from synth import configs
+from synth.kplanes_init import init_params
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    # dynamic golden-angle blades, two scales (one coarser than the grid), ragged tiles
+    "dyn_80": dict(case=dict(n=80, n_spec=4, n_time=3, n_blades=5, lines=10, f=3.0), F=4, Rt=3, res=(80, 40)),
+    "dyn_64": dict(case=dict(n=64, n_spec=3, n_time=4, n_blades=6, lines=12), F=2, Rt=4, res=(64, 21)),
+    # static plan: every blade at time 0, one scale
+    "static_48": dict(case=dict(n=48, n_spec=4, n_blades=4, lines=12), F=8, Rt=2, res=(48,)),
+}
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - b) / np.linalg.norm(b))
+
+
+def _setup(name, regs=(0.0, 0.0, 0.0)):
+    import torch
+    from paper_2311_13177_amd import binding as B
+
+    c = CASES[name]
+    case = configs.small_case(**c["case"])
+    plan = B.Plan.from_geometry(case.geometry())
+    geom = O.Geometry.from_dict(case.geometry())
+    cfg = K.KPConfig(features=c["F"], time_res=c["Rt"], spatial_res=tuple(c["res"]))
+    tv, smooth, sparse = regs
+    model = B.vp_kplanes.make(c["F"], c["Rt"], c["res"], tv, smooth, sparse, 1e-2)
+    y = O.simulate_measurements(case)
+    return B, torch, case, plan, geom, cfg, model, y
+
+
+def _kp_geom(geom):
+    # the K-Planes fit reads each blade's time; a static plan has every blade at 0
+    return O.Geometry(n=geom.n, n_spec=geom.n_spec, n_time=1, angle_rad=geom.angle_rad, lines=geom.lines,
+                      blade_time=geom.blade_time if geom.blade_time is not None else np.zeros(geom.n_blades),
+                      spec_shift_px=geom.spec_shift_px)
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_param_count_and_decode(gpu_lib, name):
+    B, torch, case, plan, geom, cfg, model, y = _setup(name)
+    _, _, total = K.layout(geom.n_spec, cfg)
+    assert B.kplanes_param_count(plan, model) == total
+    rng = np.random.default_rng(21)
+    p = (rng.standard_normal(total) + 1j * rng.standard_normal(total)).astype(np.complex64)
+    times = [0.0, 0.3, 0.5, 0.77, 1.0]
+    got = B.vp_kplanes_decode(plan, model, torch.from_numpy(p).cuda(), times).cpu().numpy()
+    for i, t in enumerate(times):
+        want = K.decode(p.astype(np.complex128), geom.n, geom.n_spec, cfg, t)
+        assert _rel(got[i], want) <= 1e-5, (i, t)
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_gradient_matches_oracle(gpu_lib, name):
+    regs = (0.02, 0.05, 0.01)
+    B, torch, case, plan, geom, cfg, model, y = _setup(name, regs)
+    _, _, total = K.layout(geom.n_spec, cfg)
+    rng = np.random.default_rng(22)
+    p = (0.5 * (rng.standard_normal(total) + 1j * rng.standard_normal(total))).astype(np.complex64)
+    g, obj, data = B.vp_kplanes_gradient(plan, model, torch.from_numpy(p).cuda(), torch.from_numpy(y).cuda())
+    wv, wg, wd = K.objective_and_gradient(p.astype(np.complex128), _kp_geom(geom), y, cfg, *regs, 1e-2)
+    assert _rel(g.cpu().numpy(), wg) <= 1e-4
+    assert math.isclose(obj, wv, rel_tol=1e-5) and math.isclose(data, wd, rel_tol=1e-5)
+
+
+def test_gd_fit_matches_oracle(gpu_lib):
+    regs = (0.01, 0.02, 0.005)
+    B, torch, case, plan, geom, cfg, model, y = _setup("dyn_80", regs)
+    init = init_params(geom.n_spec, cfg.features, cfg.time_res, cfg.spatial_res, seed=3, decoder_scale=0.1)
+    # the model is of degree seven in its parameters: GD needs a small step (the loss falls
+    # by 12% over these six steps in the oracle)
+    opts = B.vp_options_default(n_steps=6, optimizer=B.VP_OPT_GD, lr=2e-5)
+    r = B.vp_kplanes_reconstruct(plan, model, y, init, opts, frame_times=(0.0, 0.5, 1.0))
+    want, val, _ = K.reconstruct(_kp_geom(geom), y, cfg, init, 6, *regs, 1e-2, lr=2e-5, optimizer="gd")
+    assert _rel(r["params"] - init, want - init) <= 1e-4
+    assert math.isclose(r["final_loss"], val, rel_tol=1e-4)
+    proj, water, fat = K.render(want, geom.n, geom.n_spec, cfg, (0.0, 0.5, 1.0))
+    assert _rel(r["proj"], proj) <= 1e-4 and _rel(r["water"] + r["fat"], proj) <= 1e-5
+
+
+def test_adam_fit_matches_oracle(gpu_lib):
+    regs = (0.01, 0.02, 0.005)
+    B, torch, case, plan, geom, cfg, model, y = _setup("dyn_64", regs)
+    init = init_params(geom.n_spec, cfg.features, cfg.time_res, cfg.spatial_res, seed=4)
+    steps = 12
+    opts = B.vp_options_default(n_steps=steps, lr=1e-2)
+    times = (0.0, 0.4, 1.0)
+    r = B.vp_kplanes_reconstruct(plan, model, y, init, opts, frame_times=times)
+    want, val, _ = K.reconstruct(_kp_geom(geom), y, cfg, init, steps, *regs, 1e-2, lr=1e-2)
+    proj, _, _ = K.render(want, geom.n, geom.n_spec, cfg, times)
+    assert _rel(r["proj"], proj) <= 1e-3
+    assert math.isclose(r["final_loss"], val, rel_tol=1e-3)
+
+
+def test_graph_equals_eager_and_stage_times(gpu_lib):
+    B, torch, case, plan, geom, cfg, model, y = _setup("dyn_64", (0.01, 0.02, 0.005))
+    init = init_params(geom.n_spec, cfg.features, cfg.time_res, cfg.spatial_res, seed=5)
+    a = B.KPlanesSession(plan, model, y, init)
+    b = B.KPlanesSession(plan, model, y, init)
+    a.step(5, use_graph=True)
+    b.step(5, use_graph=False)
+    ra, rb = a.read((0.25,), objective=True), b.read((0.25,), objective=True)
+    assert np.array_equal(ra["params"], rb["params"]) and ra["objective"] == rb["objective"]
+    st = a.stage_times(3)
+    assert all(v > 0 for v in st.values())
+    a.close()
+    b.close()

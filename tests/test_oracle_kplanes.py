@@ -205,3 +205,17 @@ def test_gd_descends_and_adam_first_step():
     step = p0 - p2
     assert np.allclose(step.real, 1e-2 * g.real / (np.abs(g.real) + 1e-8), atol=1e-12)
     assert np.allclose(step.imag, 1e-2 * g.imag / (np.abs(g.imag) + 1e-8), atol=1e-12)
+
+
+def test_seeded_init_follows_the_oracle_layout():
+    from synth.kplanes_init import grid_sizes, init_params
+
+    cfg = K.KPConfig(features=4, time_res=5, spatial_res=(12, 6))
+    scales, a_off, total = K.layout(3, cfg)
+    sizes = grid_sizes(3, 4, 5, (12, 6))
+    assert sum(sz for _, sz in sizes) == total
+    p = init_params(3, 4, 5, (12, 6), seed=1)
+    grids, a = K.unpack(p, 3, cfg)
+    for g in grids:
+        assert np.all((g["xy"].real >= 0.1) & (g["xy"].real < 0.5)) and np.all(g["xt"] == 1.0)
+    assert np.all(a == 0)

@@ -184,3 +184,23 @@ def test_uncompiled_tile_shapes_are_rejected(B, tiles):
     with pytest.raises(B.VPError) as ei:
         plan.tiles(B.vp_options_default(tiles=tiles))
     assert ei.value.status == B.VP_ERR_UNSUPPORTED
+
+
+def test_kplanes_param_count_and_model_checks():
+    import ctypes
+
+    from oracle import kplanes as K
+    from paper_2311_13177_amd import binding as B
+
+    case = configs.small_case(n=40, n_spec=5, n_time=3, n_blades=4)
+    plan = B.Plan.from_geometry(case.geometry())
+    m = B.vp_kplanes.make(8, 6, (40, 20), 1e-3, 1e-2, 1e-3, 1e-3)
+    _, _, total = K.layout(5, K.KPConfig(features=8, time_res=6, spatial_res=(40, 20)))
+    assert B.kplanes_param_count(plan, m) == total
+    out = ctypes.c_int64()
+    for bad in (B.vp_kplanes.make(3, 6, (40,)), B.vp_kplanes.make(8, 0, (40,)), B.vp_kplanes.make(8, 6, (41,)),
+                B.vp_kplanes.make(8, 6, (40,), eps=0.0), B.vp_kplanes.make(8, 6, (40,), tv_weight=float("inf"))):
+        assert B.lib().vp_kplanes_param_count(plan.handle, ctypes.byref(bad), ctypes.byref(out)) == B.VP_ERR_ARG
+    three = B.vp_kplanes.make(8, 6, (40, 20))
+    three.n_scales = 3
+    assert B.lib().vp_kplanes_param_count(plan.handle, ctypes.byref(three), ctypes.byref(out)) == B.VP_ERR_ARG
