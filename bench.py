@@ -290,10 +290,20 @@ def copy_probe():
     print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "launches": 5}))
 
 
-def kernel_digest():
-    """sha256 (first 16 hex) over the device sources, in name order."""
+# Source files of each kernel family (plus the shared device headers).
+KERNEL_SOURCES = {"k_gather": ["k_gather.hip"], "k_update": ["k_gather.hip"], "k_project": ["k_project.hip"],
+                  "k_rows": ["k_fft.hip"], "k_cols": ["k_fft.hip"]}
+
+
+def kernel_digest(kernel=None):
+    """sha256 (first 16 hex) over the sources of one kernel family (by kernel name, e.g.
+    "k_gather<1>") and the shared device headers, or over every device source."""
     csrc = os.path.join(ROOT, "paper_2311_13177_amd", "csrc")
-    names = sorted(f for f in os.listdir(csrc) if f.startswith("k") and f.endswith((".hip", ".h")))
+    fam = None if kernel is None else kernel.split("<")[0]
+    if fam in KERNEL_SOURCES:
+        names = sorted(KERNEL_SOURCES[fam]) + ["kcommon.h"]
+    else:
+        names = sorted(f for f in os.listdir(csrc) if f.startswith("k") and f.endswith((".hip", ".h")))
     names.append("vp_internal.h")
     h = hashlib.sha256()
     for f in names:
@@ -304,15 +314,14 @@ def kernel_digest():
 
 def counters_for(workload, kernel_name):
     """HBM bytes per launch (scaled FETCH_SIZE + WRITE_SIZE) from the committed counter
-    summary of this workload, or None once the device sources have changed since."""
+    summary of this workload, or None once the kernel's sources have changed since."""
     path = os.path.join(ROOT, "profiles", "counters.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         data = json.load(fh)
-    digest = kernel_digest()
     entry = data.get(f"{workload}/{kernel_name}")
-    if not entry or entry.get("kernels_sha") != digest:
+    if not entry or entry.get("kernels_sha") != kernel_digest(kernel_name):
         return None
     return entry.get("bytes_per_launch")
 
