@@ -118,53 +118,98 @@ __global__ __launch_bounds__(kThreads) void k_kp_prod(const KPDesc d) {
 
 // ------------------------------------------------------------------ decode
 
-// vol[b][s][y][x] = sum_c sum_f Z[c][y][x][f] XA[c][b][s][x][f] Yf[c][b][s][y][f]
+// vol[b][s][y][x] = sum_c sum_f Z[c][y][x][f] XA[c][b][s][x][f] Yf[c][b][s][y][f]; a thread
+// takes kDecBins consecutive bins of one pixel, reusing the pixel's Z
+constexpr int kDecBins = 4;
+
 template <int F>
 __global__ __launch_bounds__(kThreads) void k_kp_decode(const KPDesc d) {
     const int n = d.n, S = d.S;
-    const long long total = (long long)d.B * S * n * n;
+    const long long nn = (long long)n * n;
+    const int sq = (S + kDecBins - 1) / kDecBins;
+    const long long total = (long long)d.B * sq * nn;
     for (long long e = gtid(); e < total; e += gstride()) {
-        const int x = (int)(e % n);
-        const int y = (int)((e / n) % n);
-        const long long bs = e / ((long long)n * n);  // b * S + s
-        float2 v = make_float2(0.f, 0.f);
-        for (int c = 0; c < d.ns; ++c) {
-            const float2* z = d.Z + (((long long)c * n + y) * n + x) * F;
-            const long long cb = (long long)c * d.B * S + bs;
-            const float2* xa = d.XA + (cb * n + x) * F;
-            const float2* yf = d.Yf + (cb * n + y) * F;
+        const long long px = e % nn;
+        const int x = (int)(px % n), y = (int)(px / n);
+        const int q = (int)((e / nn) % sq);
+        const int b = (int)(e / (nn * sq));
+        const int s0 = q * kDecBins, ns = min(kDecBins, S - s0);
+        float2 v[kDecBins];
 #pragma unroll
-            for (int f = 0; f < F; ++f) v = cmad(cmul(z[f], xa[f]), yf[f], v);
+        for (int k = 0; k < kDecBins; ++k) v[k] = make_float2(0.f, 0.f);
+        for (int c = 0; c < d.ns; ++c) {
+            float2 z[F];
+            const float2* zp = d.Z + ((long long)c * nn + px) * F;
+#pragma unroll
+            for (int f = 0; f < F; ++f) z[f] = zp[f];
+#pragma unroll
+            for (int k = 0; k < kDecBins; ++k) {
+                if (k < ns) {
+                    const long long cb = ((long long)c * d.B + b) * S + s0 + k;
+                    const float2* xa = d.XA + (cb * n + x) * F;
+                    const float2* yf = d.Yf + (cb * n + y) * F;
+#pragma unroll
+                    for (int f = 0; f < F; ++f) v[k] = cmad(cmul(z[f], xa[f]), yf[f], v[k]);
+                }
+            }
         }
-        d.vol[e] = v;
+#pragma unroll
+        for (int k = 0; k < kDecBins; ++k)
+            if (k < ns) d.vol[((long long)b * S + s0 + k) * nn + px] = v[k];
     }
 }
 
 // ------------------------------------------------------------------ gradient through the factors
 
-// gZ[c][y][x][f] = sum_b sum_s conj(XA Yf) G[b][s][y][x]
+// gZ[c][y][x][f] = sum_b sum_s conj(XA Yf) G[b][s][y][x], in two passes: partial sums over
+// consecutive (b, s) chunks for every pixel and both scales (G read once), then the
+// chunks summed in order
 template <int F>
 __global__ __launch_bounds__(kThreads) void k_kp_grad_z(const KPDesc d) {
     const int n = d.n, S = d.S;
     const long long nn = (long long)n * n;
-    for (long long e = gtid(); e < nn; e += gstride()) {
-        const int x = (int)(e % n), y = (int)(e / n);
-        for (int c = 0; c < d.ns; ++c) {
-            float2 acc[F];
+    const int nbs = d.B * S, cs = (nbs + d.zchunks - 1) / d.zchunks;
+    const long long total = (long long)d.zchunks * nn;
+    for (long long e = gtid(); e < total; e += gstride()) {
+        const long long px = e % nn;
+        const int ch = (int)(e / nn);
+        const int x = (int)(px % n), y = (int)(px / n);
+        float2 acc[kKpMaxScales][F];
 #pragma unroll
-            for (int f = 0; f < F; ++f) acc[f] = make_float2(0.f, 0.f);
-            for (int bs = 0; bs < d.B * S; ++bs) {
-                const float2 g = d.G[(long long)bs * nn + e];
-                const long long cb = (long long)c * d.B * S + bs;
-                const float2* xa = d.XA + (cb * n + x) * F;
-                const float2* yf = d.Yf + (cb * n + y) * F;
+        for (int c = 0; c < kKpMaxScales; ++c)
 #pragma unroll
-                for (int f = 0; f < F; ++f) acc[f] = cjmad(cmul(xa[f], yf[f]), g, acc[f]);
+            for (int f = 0; f < F; ++f) acc[c][f] = make_float2(0.f, 0.f);
+        const int bs1 = min(nbs, (ch + 1) * cs);
+        for (int bs = ch * cs; bs < bs1; ++bs) {
+            const float2 g = d.G[(long long)bs * nn + px];
+#pragma unroll
+            for (int c = 0; c < kKpMaxScales; ++c) {
+                if (c < d.ns) {
+                    const long long cb = (long long)c * nbs + bs;
+                    const float2* xa = d.XA + (cb * n + x) * F;
+                    const float2* yf = d.Yf + (cb * n + y) * F;
+#pragma unroll
+                    for (int f = 0; f < F; ++f) acc[c][f] = cjmad(cmul(xa[f], yf[f]), g, acc[c][f]);
+                }
             }
-            float2* out = d.gZ + ((long long)c * nn + e) * F;
-#pragma unroll
-            for (int f = 0; f < F; ++f) out[f] = acc[f];
         }
+#pragma unroll
+        for (int c = 0; c < kKpMaxScales; ++c) {
+            if (c < d.ns) {
+                float2* out = d.zpart + (((long long)ch * d.ns + c) * nn + px) * F;
+#pragma unroll
+                for (int f = 0; f < F; ++f) out[f] = acc[c][f];
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_kp_grad_z_sum(const KPDesc d) {
+    const long long per = (long long)d.ns * d.n * d.n * d.F;
+    for (long long e = gtid(); e < per; e += gstride()) {
+        float2 acc = make_float2(0.f, 0.f);
+        for (int ch = 0; ch < d.zchunks; ++ch) acc = cadd(acc, d.zpart[(long long)ch * per + e]);
+        d.gZ[e] = acc;
     }
 }
 
@@ -197,42 +242,62 @@ __global__ __launch_bounds__(kThreads) void k_kp_grad_x(const KPDesc d) {
     }
 }
 
-// gY[c][b][s][y][f] = sum_x conj(Z XA) G[b][s][y][x]: one wave per row (b, s, y), lanes
-// over x, then a butterfly sum in a fixed order
+// gY[c][b][s][y][f] = sum_x conj(Z XA) G[b][s][y][x]: one wave per 32/F consecutive rows
+// (b, s, y), lanes over x; the wave's 64 partial sums per lane (rows x features x re/im)
+// are reduced across lanes by recursive halving, each step sending the half a lane gives
+// up to its partner, so that lane L ends with the total of value L (a fixed order).
 template <int F>
 __global__ __launch_bounds__(kThreads) void k_kp_grad_y(const KPDesc d) {
+    constexpr int RW = 32 / F;  // rows per wave: 2 F RW = 64 values
     const int n = d.n, S = d.S;
     const int lane = threadIdx.x & 63;
     const long long rows = (long long)d.B * S * n;
-    for (long long r = (long long)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); r < rows;
-         r += (long long)gridDim.x * (kThreads / 64)) {
-        const int y = (int)(r % n);
-        const long long bs = r / n;
-        const float2* gp = d.G + r * n;
+    const long long groups = (rows + RW - 1) / RW;
+    for (long long gi = (long long)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); gi < groups;
+         gi += (long long)gridDim.x * (kThreads / 64)) {
         for (int c = 0; c < d.ns; ++c) {
-            float2 acc[F];
+            float v[64];
 #pragma unroll
-            for (int f = 0; f < F; ++f) acc[f] = make_float2(0.f, 0.f);
-            const long long cb = (long long)c * d.B * S + bs;
-            for (int x = lane; x < n; x += 64) {
-                const float2 g = gp[x];
-                const float2* z = d.Z + (((long long)c * n + y) * n + x) * F;
-                const float2* xa = d.XA + (cb * n + x) * F;
+            for (int i = 0; i < 64; ++i) v[i] = 0.f;
 #pragma unroll
-                for (int f = 0; f < F; ++f) acc[f] = cjmad(cmul(z[f], xa[f]), g, acc[f]);
-            }
+            for (int r = 0; r < RW; ++r) {
+                const long long row = gi * RW + r;
+                if (row < rows) {
+                    const int y = (int)(row % n);
+                    const long long bs = row / n;
+                    const long long cb = (long long)c * d.B * S + bs;
+                    const float2* gp = d.G + row * n;
+                    for (int x = lane; x < n; x += 64) {
+                        const float2 g = gp[x];
+                        const float2* z = d.Z + (((long long)c * n + y) * n + x) * F;
+                        const float2* xa = d.XA + (cb * n + x) * F;
 #pragma unroll
-            for (int f = 0; f < F; ++f) {
-#pragma unroll
-                for (int o = 32; o > 0; o >>= 1) {
-                    acc[f].x += __shfl_xor(acc[f].x, o);
-                    acc[f].y += __shfl_xor(acc[f].y, o);
+                        for (int f = 0; f < F; ++f) {
+                            const float2 t = cjmad(cmul(z[f], xa[f]), g, make_float2(v[(r * F + f) * 2], v[(r * F + f) * 2 + 1]));
+                            v[(r * F + f) * 2] = t.x;
+                            v[(r * F + f) * 2 + 1] = t.y;
+                        }
+                    }
                 }
             }
-            if (lane == 0) {
-                float2* out = d.gY + (cb * n + y) * F;
 #pragma unroll
-                for (int f = 0; f < F; ++f) out[f] = acc[f];
+            for (int o = 32; o > 0; o >>= 1) {
+                const bool up = (lane & o) != 0;
+#pragma unroll
+                for (int i = 0; i < o; ++i) {
+                    const float send = up ? v[i] : v[i + o];
+                    const float keep = up ? v[i + o] : v[i];
+                    v[i] = keep + __shfl_xor(send, o);
+                }
+            }
+            // lane L holds value L: row L / (2F), feature (L / 2) % F, component L % 2
+            const long long row = gi * RW + lane / (2 * F);
+            if (row < rows) {
+                const int y = (int)(row % n);
+                const long long bs = row / n;
+                const long long cb = (long long)c * d.B * S + bs;
+                float* out = reinterpret_cast<float*>(d.gY + (cb * n + y) * F);
+                out[lane % (2 * F)] = v[0];
             }
         }
     }
@@ -303,14 +368,21 @@ __global__ __launch_bounds__(kThreads) void k_kp_chain1(const KPDesc d) {
     }
 }
 
-// ga[f] = sum_c sum_b sum_s conj(qs) h
+// ga[f] = sum_c sum_b sum_s conj(qs) h: one block per feature, strided partial sums then
+// a tree in a fixed order
 __global__ __launch_bounds__(kThreads) void k_kp_chain_a(const KPDesc d) {
-    for (int f = threadIdx.x; f < d.F; f += blockDim.x) {
-        float2 acc = make_float2(0.f, 0.f);
-        const long long nbs = (long long)d.ns * d.B * d.S;
-        for (long long cbs = 0; cbs < nbs; ++cbs) acc = cjmad(d.qs[cbs * d.F + f], d.h[cbs * d.F + f], acc);
-        d.ga[f] = acc;
+    __shared__ float2 red[kThreads];
+    const int f = blockIdx.x;
+    float2 acc = make_float2(0.f, 0.f);
+    const long long nbs = (long long)d.ns * d.B * d.S;
+    for (long long cbs = threadIdx.x; cbs < nbs; cbs += kThreads) acc = cjmad(d.qs[cbs * d.F + f], d.h[cbs * d.F + f], acc);
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = kThreads / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] = cadd(red[threadIdx.x], red[threadIdx.x + h]);
+        __syncthreads();
     }
+    if (threadIdx.x == 0) d.ga[f] = red[0];
 }
 
 // Which grid holds flat element e, and its index within the grid (a: plane KP_PLANES).
@@ -560,12 +632,13 @@ hipError_t kp_launch_factors(const KPDesc& d, hipStream_t s) {
     }
 
 hipError_t kp_launch_decode(const KPDesc& d, hipStream_t s) {
-    KP_F_SWITCH(k_kp_decode, dim3(grid_of((long long)d.B * d.S * d.n * d.n)));
+    KP_F_SWITCH(k_kp_decode, dim3(grid_of((long long)d.B * ((d.S + kDecBins - 1) / kDecBins) * d.n * d.n)));
     return hipGetLastError();
 }
 
 hipError_t kp_launch_back_z(const KPDesc& d, hipStream_t s) {
-    KP_F_SWITCH(k_kp_grad_z, dim3(grid_of((long long)d.n * d.n)));
+    KP_F_SWITCH(k_kp_grad_z, dim3(grid_of((long long)d.zchunks * d.n * d.n)));
+    hipLaunchKernelGGL(k_kp_grad_z_sum, dim3(grid_of((long long)d.ns * d.n * d.n * d.F)), dim3(kThreads), 0, s, d);
     return hipGetLastError();
 }
 hipError_t kp_launch_back_x(const KPDesc& d, hipStream_t s) {
@@ -574,7 +647,8 @@ hipError_t kp_launch_back_x(const KPDesc& d, hipStream_t s) {
 }
 hipError_t kp_launch_back_y(const KPDesc& d, hipStream_t s) {
     const long long rows = (long long)d.B * d.S * d.n;
-    const long long blocks = (rows + kThreads / 64 - 1) / (kThreads / 64);
+    const long long groups = (rows + 32 / d.F - 1) / (32 / d.F);
+    const long long blocks = (groups + kThreads / 64 - 1) / (kThreads / 64);
     KP_F_SWITCH(k_kp_grad_y, dim3((unsigned)(blocks > (1 << 20) ? (1 << 20) : blocks)));
     return hipGetLastError();
 }
@@ -589,7 +663,7 @@ hipError_t kp_launch_back(const KPDesc& d, hipStream_t s) {
 hipError_t kp_launch_chain(const KPDesc& d, hipStream_t s) {
     const long long total = 2LL * d.ns * d.S * d.n * d.F + 2LL * d.ns * d.B * d.n * d.F + (long long)d.ns * d.B * d.S * d.F;
     hipLaunchKernelGGL(k_kp_chain1, dim3(grid_of(total)), dim3(kThreads), 0, s, d);
-    hipLaunchKernelGGL(k_kp_chain_a, dim3(1), dim3(kThreads), 0, s, d);
+    hipLaunchKernelGGL(k_kp_chain_a, dim3(d.F), dim3(kThreads), 0, s, d);
     hipLaunchKernelGGL(k_kp_grid, dim3(grid_of(d.n_params)), dim3(kThreads), 0, s, d);
     return hipGetLastError();
 }

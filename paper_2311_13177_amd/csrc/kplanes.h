@@ -54,6 +54,8 @@ struct KPDesc {
     float2* Z;           // [ns][n][n][F]
     float2 *XA, *Yf;     // [ns][B][S][n][F]
     float2 *gZ, *gXA, *gY;
+    float2* zpart;       // [zchunks][ns][n][n][F] partial sums of gZ over (b, s) chunks
+    int zchunks;
     float2 *gXs, *gYs, *gqx, *gqy, *gqs, *h;  // h: [ns][B][S][F]
     float2* ga;          // [F]
     // dense per-blade volumes and their gradient [B][S][n][n]
