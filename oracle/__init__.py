@@ -39,6 +39,8 @@ from .lifted import (  # noqa: F401
     adam_update,
     gd_update,
     reconstruct,
+    splitmix64,
+    random_blade,
     render,
     coverage_baseline,
     window_baseline,

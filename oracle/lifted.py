@@ -41,10 +41,15 @@ Readings where the paper is silent (each one also listed in the design notes):
   R9  Adam with torch's defaults acts on (Re, Im) as independent real parameters;
       t counts from 1; the volume starts at zero. GD is an option.
   R10 A step is one update on the gradient summed over all blades; the paper's
-      one-blade-per-iteration schedule ("cyclic", blade (t-1) mod B) is an option.
+      one-blade-per-iteration schedule is an option, either in turn ("cyclic", blade
+      (t-1) mod B) or drawn at random ("random": blade splitmix64(seed * 2^32 + t - 1)
+      mod B, the SplitMix64 generator of Steele, Lea and Flood, 2014).
   R11 Dynamic: a dense grid of T time knots at k/(T-1); a blade at time tau sees
       (1-a) V[k] + a V[k+1] with k = floor(tau (T-1)) clamped to T-2, a = tau (T-1) - k.
   R12 Fat/water split at bin S/2 by default; water = bins below it, fat = the rest.
+  R16 The image-space and k-space squared errors (Section 4.3) are the same number
+      under a unitary DFT (R7), so their weighted sum is data_weight * 0.5 * sum |R|^2
+      with data_weight = w_image + w_kspace (1 by default).
 """
 
 from __future__ import annotations
@@ -296,9 +301,9 @@ def l1_grad(vol: np.ndarray, eps: float) -> np.ndarray:
 
 
 def objective(vol: np.ndarray, geom: Geometry, y: np.ndarray, tv_weight: float, tv_eps: float,
-              l1_weight: float = 0.0, blades: Optional[Sequence[int]] = None) -> float:
-    """Data term plus weighted TV and L1 (Section 4.3)."""
-    val = data_loss(residual(vol, geom, y, blades))
+              l1_weight: float = 0.0, blades: Optional[Sequence[int]] = None, data_weight: float = 1.0) -> float:
+    """Weighted data term plus weighted TV and L1 (Section 4.3, R16)."""
+    val = data_weight * data_loss(residual(vol, geom, y, blades))
     if tv_weight != 0.0:
         val += tv_weight * tv_value(vol, tv_eps)
     if l1_weight != 0.0:
@@ -307,15 +312,16 @@ def objective(vol: np.ndarray, geom: Geometry, y: np.ndarray, tv_weight: float, 
 
 
 def gradient(vol: np.ndarray, geom: Geometry, y: np.ndarray, tv_weight: float, tv_eps: float,
-             l1_weight: float = 0.0, blades: Optional[Sequence[int]] = None) -> tuple[np.ndarray, float]:
-    """Gradient of ``objective`` and the data term at ``vol``."""
+             l1_weight: float = 0.0, blades: Optional[Sequence[int]] = None,
+             data_weight: float = 1.0) -> tuple[np.ndarray, float]:
+    """Gradient of ``objective`` and the (weighted) data term at ``vol``."""
     res = residual(vol, geom, y, blades)
-    g = adjoint(res, geom, blades)
+    g = data_weight * adjoint(res, geom, blades)
     if tv_weight != 0.0:
         g += tv_weight * tv_grad(vol, tv_eps)
     if l1_weight != 0.0:
         g += l1_weight * l1_grad(vol, tv_eps)
-    return g, data_loss(res)
+    return g, data_weight * data_loss(res)
 
 
 # --------------------------------------------------------------------------- optimiser
@@ -340,11 +346,29 @@ def gd_update(vol: np.ndarray, grad: np.ndarray, lr: float) -> np.ndarray:
     return vol - lr * grad
 
 
+_M64 = (1 << 64) - 1
+
+
+def splitmix64(x: int) -> int:
+    """SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): the output for state x, i.e. the
+    mix of x + 0x9E3779B97F4A7C15."""
+    z = (x + 0x9E3779B97F4A7C15) & _M64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+    return z ^ (z >> 31)
+
+
+def random_blade(seed: int, step_index: int, n_blades: int) -> int:
+    """Blade of the random one-blade schedule at 0-based step index (R10)."""
+    return splitmix64(((seed & 0xFFFFFFFF) << 32) | (step_index & 0xFFFFFFFF)) % n_blades
+
+
 def reconstruct(geom: Geometry, y: np.ndarray, n_steps: int, tv_weight: float = 1e-3,
                 tv_eps: float = 1e-3, l1_weight: float = 0.0, lr: float = 1e-2,
                 beta1: float = 0.9, beta2: float = 0.999, adam_eps: float = 1e-8,
                 optimizer: str = "adam", schedule: str = "all", init: Optional[np.ndarray] = None,
-                split_bin: int = -1, state: Optional[dict] = None) -> dict:
+                split_bin: int = -1, state: Optional[dict] = None, seed: int = 0,
+                data_weight: float = 1.0) -> dict:
     """The iterative fit of Section 4.3, from zero (or ``init``) for ``n_steps`` updates.
 
     ``state`` resumes a previous run: a dict with keys vol, m, v, step.
@@ -365,8 +389,13 @@ def reconstruct(geom: Geometry, y: np.ndarray, n_steps: int, tv_weight: float = 
     y = y.astype(np.complex128)
     history = []
     for t in range(t0 + 1, t0 + n_steps + 1):
-        blades = None if schedule == "all" else [(t - 1) % geom.n_blades]
-        g, ld = gradient(vol, geom, y, tv_weight, tv_eps, l1_weight, blades)
+        if schedule == "all":
+            blades = None
+        elif schedule == "cyclic":
+            blades = [(t - 1) % geom.n_blades]
+        else:
+            blades = [random_blade(seed, t - 1, geom.n_blades)]
+        g, ld = gradient(vol, geom, y, tv_weight, tv_eps, l1_weight, blades, data_weight)
         obj = ld
         if tv_weight != 0.0:
             obj += tv_weight * tv_value(vol, tv_eps)
@@ -380,7 +409,7 @@ def reconstruct(geom: Geometry, y: np.ndarray, n_steps: int, tv_weight: float = 
     proj, water, fat = render(vol, split_bin)
     return dict(vol=vol, m=m, v=v, step=t0 + n_steps, proj=proj, water=water, fat=fat,
                 history=np.asarray(history),
-                final_loss=objective(vol, geom, y, tv_weight, tv_eps, l1_weight))
+                final_loss=objective(vol, geom, y, tv_weight, tv_eps, l1_weight, data_weight=data_weight))
 
 
 # --------------------------------------------------------------------------- outputs

@@ -478,3 +478,48 @@ def test_cyclic_schedule_uses_one_blade_per_step():
     r = O.reconstruct(geom, y, 1, schedule="cyclic", tv_weight=0.0, lr=0.3, optimizer="gd")
     g = O.adjoint(O.residual(np.zeros((1, 3, 24, 24)), geom, y, [0]), geom, [0])
     assert np.allclose(r["vol"], -0.3 * g, atol=1e-15)
+
+
+# ------------------------------------------------------------------ schedules and data weight (Section 4.3)
+
+def test_splitmix64_published_outputs():
+    # the generator's first three outputs from state 0 (each output advances the state
+    # by the golden gamma), as published with the algorithm
+    g = 0x9E3779B97F4A7C15
+    assert [O.splitmix64(0), O.splitmix64(g), O.splitmix64((2 * g) & ((1 << 64) - 1))] == \
+        [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+def test_random_schedule_draws_every_blade_about_equally():
+    B, n = 7, 7000
+    counts = np.bincount([O.random_blade(5, t, B) for t in range(n)], minlength=B)
+    chi2 = float(np.sum((counts - n / B) ** 2 / (n / B)))
+    assert chi2 < 30.0  # 6 degrees of freedom: p < 1e-4 beyond 30
+    assert [O.random_blade(5, t, B) for t in range(20)] != [O.random_blade(6, t, B) for t in range(20)]
+
+
+def test_random_schedule_steps_use_their_blade_alone():
+    n = 16
+    geom = _geom(n=n, s=2, angles=(0.0, 0.8, 1.7, 2.5), lines=(4, 5, 6, 3))
+    rng = np.random.default_rng(50)
+    y = O.blade_masks(geom) * _crandn(rng, 4, n, n)
+    r = O.reconstruct(geom, y, 3, tv_weight=0.0, lr=0.1, optimizer="gd", schedule="random", seed=9)
+    vol = np.zeros((1, 2, n, n), dtype=np.complex128)
+    for t in range(3):
+        g, _ = O.gradient(vol, geom, y, 0.0, 1e-3, 0.0, [O.random_blade(9, t, 4)])
+        vol = vol - 0.1 * g
+    assert np.allclose(r["vol"], vol, atol=1e-14)
+
+
+def test_data_weight_scales_the_data_term_only():
+    n = 12
+    geom = _geom(n=n, s=3)
+    rng = np.random.default_rng(51)
+    vol = _crandn(rng, 1, 3, n, n)
+    y = O.blade_masks(geom) * _crandn(rng, 3, n, n)
+    g1, d1 = O.gradient(vol, geom, y, 0.0, 1e-3)
+    g3, d3 = O.gradient(vol, geom, y, 0.0, 1e-3, data_weight=3.0)
+    assert np.allclose(g3, 3.0 * g1, rtol=1e-13) and math.isclose(d3, 3.0 * d1, rel_tol=1e-13)
+    tv = O.tv_grad(vol, 1e-3)
+    gt, _ = O.gradient(vol, geom, y, 0.5, 1e-3, data_weight=2.0)
+    assert np.allclose(gt, 2.0 * g1 + 0.5 * tv, rtol=1e-12)
