@@ -170,7 +170,7 @@ def batched_leg(B, n_slices, steps):
             "tiles": "batch: autotuned on its largest slice; plain loop: each plan's built-in shape"}
 
 
-KP_MODEL = dict(features=8, tv_weight=1e-3, smooth_weight=1e-2, sparse_weight=1e-3, eps=1e-3)
+KP_MODEL = dict(features=8, tv_weight=1e-1, smooth_weight=1e-2, sparse_weight=1e-3, eps=1e-3)
 
 
 def kplanes_leg(B, steps, warmup):

@@ -98,13 +98,17 @@ typedef struct {
 } vp_geometry;
 
 enum { VP_OPT_ADAM = 0, VP_OPT_GD = 1 };
-enum { VP_SCHED_ALL_BLADES = 0, VP_SCHED_CYCLIC = 1 };
+enum { VP_SCHED_ALL_BLADES = 0, VP_SCHED_CYCLIC = 1, VP_SCHED_RANDOM = 2 };
 
 /* Fit settings (Section 4.3). tv_eps is the Charbonnier epsilon of both the TV
  * and the L1 term. A step is one optimiser update on the gradient summed over
- * all blades (VP_SCHED_ALL_BLADES) or over blade (t-1) mod B only
- * (VP_SCHED_CYCLIC, the paper's one-blade-per-iteration schedule). The volume
- * starts at zero unless an initial volume is given. split_bin < 0 means S/2. */
+ * all blades (VP_SCHED_ALL_BLADES) or over one blade, the paper's one-blade-per-
+ * iteration schedule: blade (t-1) mod B (VP_SCHED_CYCLIC) or a blade drawn at
+ * random, splitmix64(seed * 2^32 + t - 1) mod B with SplitMix64 of Steele, Lea and
+ * Flood (VP_SCHED_RANDOM). data_weight multiplies the data term: the image-space
+ * and k-space squared errors of Section 4.3 are the same number under the unitary
+ * DFT, so their weights add up to this one factor (default 1, must be > 0). The
+ * volume starts at zero unless an initial volume is given. split_bin < 0 means S/2. */
 /* Tile shape of the projection, gather and update kernels: how the work is cut
  * into work items, never what is computed (every shape gives the same results bit
  * for bit). proj_rows: rows of a projection tile, in {1, 2, 4, 8}; proj_parts:
@@ -142,6 +146,8 @@ typedef struct {
      * which must be valid for the plan (VP_ERR_UNSUPPORTED if not). */
     vp_tiles tiles;
     int32_t autotune;
+    uint32_t seed;       /* VP_SCHED_RANDOM */
+    float data_weight;   /* > 0 */
 } vp_options;
 
 /* Fills defaults: tv_weight 1e-3, l1_weight 0, tv_eps 1e-3, n_steps 200, Adam
@@ -378,8 +384,9 @@ vp_status vp_kplanes_gradient(const vp_plan* plan, const vp_kplanes* model, cons
 
 /* Resident fit: uploads kspace[B][n][n] and the initial parameters init[count] (host)
  * to opts->device. opts gives n_steps (unused here), optimizer, lr, beta1, beta2,
- * adam_eps and device; tv_weight / l1_weight are ignored (the model carries its own
- * weights); only VP_SCHED_ALL_BLADES is supported (VP_ERR_UNSUPPORTED otherwise). */
+ * adam_eps, data_weight and device; tv_weight / l1_weight are ignored (the model
+ * carries its own weights); only VP_SCHED_ALL_BLADES is supported
+ * (VP_ERR_UNSUPPORTED otherwise). */
 vp_status vp_kplanes_session_create(const vp_plan* plan, const vp_kplanes* model, const vp_options* opts,
                                     const vp_c64* kspace, const vp_c64* init, vp_kplanes_session** out);
 

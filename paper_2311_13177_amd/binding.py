@@ -34,6 +34,7 @@ VP_OPT_ADAM = 0
 VP_OPT_GD = 1
 VP_SCHED_ALL_BLADES = 0
 VP_SCHED_CYCLIC = 1
+VP_SCHED_RANDOM = 2
 
 
 class VPError(RuntimeError):
@@ -60,7 +61,7 @@ class vp_options(ctypes.Structure):
     _fields_ = [("tv_weight", c_float), ("l1_weight", c_float), ("tv_eps", c_float), ("n_steps", c_int32),
                 ("optimizer", c_int32), ("lr", c_float), ("beta1", c_float), ("beta2", c_float),
                 ("adam_eps", c_float), ("schedule", c_int32), ("split_bin", c_int32), ("device", c_int32),
-                ("tiles", vp_tiles), ("autotune", c_int32)]
+                ("tiles", vp_tiles), ("autotune", c_int32), ("seed", ctypes.c_uint32), ("data_weight", c_float)]
 
 
 VP_KP_MAX_SCALES = 2

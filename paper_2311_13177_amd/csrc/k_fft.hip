@@ -241,7 +241,7 @@ __global__ __launch_bounds__(kThreads) void k_rows(const KArgs a) {
         const int st = read_step(stepp);
         if (stepp && st >= DF(step_limit)) continue;
         const int b = tk->a;
-        if (!active_blade(DF(schedule), stepp, st, DF(B), b)) continue;
+        if (!active_blade(DF(schedule), DF(sched_seed), stepp, st, DF(B), b)) continue;
         const int n = DF(n), nparts = DF(nparts), nstage = DF(nstage), code = DF(radix_code);
         const size_t nn = (size_t)n * n;
         const int fb = fft_rows_per_item(n);
@@ -278,8 +278,9 @@ __global__ __launch_bounds__(kThreads) void k_rows(const KArgs a) {
 
 // ------------------------------------------------------------------ column pass
 //
-// COL_STEP:    forward column DFT, K = X / n, R = M (K - y), loss partial sum |R|^2,
-//              Z = R / n, inverse column DFT -> work (one pass per column strip).
+// COL_STEP:    forward column DFT, K = X / n, R = M (K - y), loss partial w |R|^2,
+//              Z = w R / n, inverse column DFT -> work (one pass per column strip; w is
+//              the slice's data-term weight).
 // COL_FORWARD: forward column DFT, out = M (K - y) (y optional), no inverse.
 // COL_ADJOINT: reads caller k-space, Z = M kres / n, inverse column DFT -> work.
 // COL_INVERSE: inverse column DFT of caller frames, unmasked and unscaled, -> a.out0.
@@ -297,7 +298,7 @@ __global__ __launch_bounds__(kThreads) void k_cols(const KArgs a) {
         const int b = tk->a;
         float* const loss_part = DF(loss_part);
         const int n_col_items = DF(n_col_items);
-        if (!active_blade(DF(schedule), stepp, st, DF(B), b)) {
+        if (!active_blade(DF(schedule), DF(sched_seed), stepp, st, DF(B), b)) {
             if (a.mode == COL_STEP && threadIdx.x == 0) loss_part[b * n_col_items + tk->b] = 0.f;
             continue;
         }
@@ -337,6 +338,9 @@ __global__ __launch_bounds__(kThreads) void k_cols(const KArgs a) {
         __syncthreads();
         if (!from_in) fft_cols_any<-1, NC>(A, tw, n, nstage, code);
         const float sc = 1.0f / (float)n;
+        // the step's residual and loss carry the data-term weight
+        const float dw = a.mode == COL_STEP ? DF(data_w) : 1.0f;
+        const float sc_res = dw * sc;
         float lsum = 0.f;
         for (int i = threadIdx.x; i < n * cb && a.mode != COL_INVERSE; i += blockDim.x) {
             const int y = i / cb, c = i - (i / cb) * cb;
@@ -354,7 +358,7 @@ __global__ __launch_bounds__(kThreads) void k_cols(const KArgs a) {
                     } else {
                         lsum = __builtin_fmaf(r.x, r.x, lsum);
                         lsum = __builtin_fmaf(r.y, r.y, lsum);
-                        v = cscale(r, sc);
+                        v = cscale(r, sc_res);
                     }
                 }
             }
@@ -374,7 +378,7 @@ __global__ __launch_bounds__(kThreads) void k_cols(const KArgs a) {
             for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off);
             if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = lsum;
             __syncthreads();
-            if (threadIdx.x == 0) loss_part[b * n_col_items + tk->b] = (red[0] + red[1]) + (red[2] + red[3]);
+            if (threadIdx.x == 0) loss_part[b * n_col_items + tk->b] = dw * ((red[0] + red[1]) + (red[2] + red[3]));
         }
         __syncthreads();
     }

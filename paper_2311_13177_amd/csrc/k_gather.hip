@@ -222,6 +222,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
         const int st = read_step(stepp);
         if (stepp && st >= DF(step_limit)) continue;
         const int n = DF(n), S = DF(S), T = DF(T), B = DF(B), nparts = DF(nparts), sched = DF(schedule);
+        const unsigned sseed = DF(sched_seed);
         const int kt = tk->a;
         const size_t nn = (size_t)n * n;
         const int txn = (n + kTileW - 1) / kTileW;
@@ -247,7 +248,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
         float2 pre[P][SE];
         // the knot's active parts in plan order, P per phase: cur[] this phase, nxt[] the next
         auto next_active = [&](int e) {
-            while (e < e1 && !active_blade(sched, stepp, st, B, ent[e].blade)) ++e;
+            while (e < e1 && !active_blade(sched, sseed, stepp, st, B, ent[e].blade)) ++e;
             return e;
         };
         int cur[P];

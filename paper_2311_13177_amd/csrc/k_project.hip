@@ -23,6 +23,7 @@ __global__ __launch_bounds__(kThreads) void k_project(const KArgs a) {
         const int st = read_step(stepp);
         if (stepp && st >= DF(step_limit)) continue;
         const int n = DF(n), S = DF(S), B = DF(B), nparts = DF(nparts), sched = DF(schedule);
+        const unsigned sseed = DF(sched_seed);
         const size_t nn = (size_t)n * n;
         const AS4 ProjGroup* gr = cst(DF(groups)) + tk->a;
         const int knot = gr->knot, ge0 = gr->e0, gne = gr->ne;
@@ -45,7 +46,7 @@ __global__ __launch_bounds__(kThreads) void k_project(const KArgs a) {
             if (e < gne) {
                 eb[j] = ent[ge0 + e].blade;
                 ep[j] = ent[ge0 + e].part;
-                act[j] = active_blade(sched, stepp, st, B, eb[j]);
+                act[j] = active_blade(sched, sseed, stepp, st, B, eb[j]);
             }
         }
         float2 acc[GW][PPT];

@@ -47,8 +47,20 @@ __device__ __forceinline__ float2 mul_i(float2 a) {
 __device__ __forceinline__ float2 cfma(float w, float2 a, float2 acc) {
     return make_float2(__builtin_fmaf(w, a.x, acc.x), __builtin_fmaf(w, a.y, acc.y));
 }
-__device__ __forceinline__ bool active_blade(int sched, const int* stepp, int st, int B, int b) {
-    return sched != VP_SCHED_CYCLIC || stepp == nullptr || b == st % B;
+// SplitMix64 (Steele, Lea and Flood, 2014): the output for state x.
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long x) {
+    unsigned long long z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+// Whether blade b takes part in the step with 0-based index st (operator calls, with no
+// step counter, take every blade).
+__device__ __forceinline__ bool active_blade(int sched, unsigned seed, const int* stepp, int st, int B, int b) {
+    if (sched == VP_SCHED_ALL_BLADES || stepp == nullptr) return true;
+    if (sched == VP_SCHED_CYCLIC) return b == st % B;
+    const unsigned long long x = ((unsigned long long)seed << 32) | (unsigned)st;
+    return (unsigned long long)b == splitmix64(x) % (unsigned long long)B;
 }
 __device__ __forceinline__ int read_step(const int* stepp) { return stepp ? *cst(stepp) : 0; }
 

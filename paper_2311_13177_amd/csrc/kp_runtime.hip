@@ -432,6 +432,7 @@ extern "C" vp_status vp_kplanes_session_create(const vp_plan* p, const vp_kplane
     if ((e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking)) != hipSuccess)
         return hip_status(e, "stream");
     if ((st = dense_setup(p, &s->ds)) != VP_OK) return st;
+    s->ds.a.one.data_w = o->data_weight;
     build_tables(p, m, p->tau.data(), p->B, &s->tab);
     KPDesc& d = s->tab.d;
     set_regs(&d, m);

@@ -229,6 +229,8 @@ extern "C" vp_status vp_options_default(vp_options* o) {
     o->device = 0;
     o->tiles = vp_tiles{0, 0, 0, 0};
     o->autotune = 0;
+    o->seed = 0;
+    o->data_weight = 1.0f;
     return VP_OK;
 }
 

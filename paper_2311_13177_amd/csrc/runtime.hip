@@ -133,12 +133,16 @@ void fill_desc(const vp_plan* p, const DeviceTables* t, const Layout* L, const D
     d->knots = t->knots;
     d->step_limit = 0x7fffffff;
     d->schedule = VP_SCHED_ALL_BLADES;
+    d->sched_seed = 0;
+    d->data_w = 1.0f;
     d->optimizer = VP_OPT_ADAM;
 }
 
 static void set_hyper(SliceDesc* d, const vp_options* o) {
     d->optimizer = o->optimizer;
     d->schedule = o->schedule;
+    d->sched_seed = o->seed;
+    d->data_w = o->data_weight;
     d->lr = o->lr;
     d->beta1 = o->beta1;
     d->beta2 = o->beta2;
@@ -152,15 +156,16 @@ static void set_hyper(SliceDesc* d, const vp_options* o) {
 
 vp_status check_options(const vp_plan* p, const vp_options* o) {
     if (!o) return fail(VP_ERR_ARG, "NULL options");
-    const float fs[] = {o->tv_weight, o->l1_weight, o->tv_eps, o->lr, o->beta1, o->beta2, o->adam_eps};
+    const float fs[] = {o->tv_weight, o->l1_weight, o->tv_eps, o->lr, o->beta1, o->beta2, o->adam_eps, o->data_weight};
     for (float f : fs)
         if (!std::isfinite(f)) return fail(VP_ERR_ARG, "options: non-finite value");
     if (o->tv_weight < 0 || o->l1_weight < 0 || o->tv_eps <= 0)
         return fail(VP_ERR_ARG, "options: weights must be >= 0 and tv_eps > 0");
     if (o->n_steps < 0) return fail(VP_ERR_ARG, "options: n_steps < 0");
     if (o->optimizer != VP_OPT_ADAM && o->optimizer != VP_OPT_GD) return fail(VP_ERR_ARG, "options: optimizer");
-    if (o->schedule != VP_SCHED_ALL_BLADES && o->schedule != VP_SCHED_CYCLIC)
+    if (o->schedule != VP_SCHED_ALL_BLADES && o->schedule != VP_SCHED_CYCLIC && o->schedule != VP_SCHED_RANDOM)
         return fail(VP_ERR_ARG, "options: schedule");
+    if (!(o->data_weight > 0)) return fail(VP_ERR_ARG, "options: data_weight must be > 0");
     if (o->optimizer == VP_OPT_ADAM && (o->beta1 < 0 || o->beta1 >= 1 || o->beta2 < 0 || o->beta2 >= 1))
         return fail(VP_ERR_ARG, "options: betas must lie in [0, 1)");
     if (o->split_bin > p->S) return fail(VP_ERR_ARG, "options: split_bin above n_spec");

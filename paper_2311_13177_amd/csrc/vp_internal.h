@@ -126,6 +126,8 @@ struct SliceDesc {
     int* step;                   // device step counter; nullptr for operator calls
     int step_limit;              // work items of slices with *step >= step_limit exit
     int optimizer, schedule;
+    unsigned sched_seed;         // VP_SCHED_RANDOM
+    float data_w;                // weight of the data term (residual and loss partials)
     float lr, beta1, beta2, adam_eps;
     float ln_beta1, ln_beta2;    // log(beta) in FP64, rounded: bias corrections -expm1(t ln beta)
     float tv_w, l1_w, tv_eps;

@@ -147,7 +147,8 @@ def _oracle_recon(case, y, opts, steps):
     return O.reconstruct(geom, y, steps, tv_weight=opts.tv_weight, tv_eps=opts.tv_eps, l1_weight=opts.l1_weight,
                          lr=opts.lr, beta1=opts.beta1, beta2=opts.beta2, adam_eps=opts.adam_eps,
                          optimizer="adam" if opts.optimizer == 0 else "gd",
-                         schedule="all" if opts.schedule == 0 else "cyclic", split_bin=opts.split_bin)
+                         schedule={0: "all", 1: "cyclic", 2: "random"}[opts.schedule], split_bin=opts.split_bin,
+                         seed=opts.seed, data_weight=opts.data_weight)
 
 
 @pytest.mark.parametrize("name,optimizer,steps,schedule", [
@@ -172,6 +173,38 @@ def test_reconstruct_small(gpu_lib, name, optimizer, steps, schedule):
     assert rel(got["vol"], want["vol"]) < RECON_TOL
     assert rel(got["water"], want["water"]) < RECON_TOL and rel(got["fat"], want["fat"]) < RECON_TOL
     assert abs(got["final_loss"] - want["final_loss"]) <= 1e-3 * abs(want["final_loss"])
+
+
+@pytest.mark.parametrize("name,optimizer,steps,seed,weight", [
+    ("static_80", 1, 9, 7, 1.0),
+    ("dynamic_40", 0, 15, 123, 1.0),
+    ("static_48", 0, 12, 0, 2.5),
+    ("dynamic_96", 1, 6, 0, 0.5),
+])
+def test_random_schedule_and_data_weight(gpu_lib, name, optimizer, steps, seed, weight):
+    # the random one-blade schedule draws each step's blade on the device from the step
+    # counter (SplitMix64) and the data-term weight scales the residual and the loss
+    from paper_2311_13177_amd import binding as B
+
+    case = small(name)
+    y = O.simulate_measurements(case)
+    plan = B.Plan.from_geometry(case.geometry())
+    lr = 1e-2 if optimizer == 0 else 0.5 / (case.n_spec * case.n_blades * weight)
+    sched = B.VP_SCHED_RANDOM if seed else B.VP_SCHED_ALL_BLADES
+    opts = B.vp_options_default(n_steps=steps, optimizer=optimizer, lr=lr, schedule=sched, seed=seed,
+                                data_weight=weight)
+    got = B.vp_reconstruct(plan, y, opts)
+    want = _oracle_recon(case, y, opts, steps)
+    assert rel(got["proj"], want["proj"]) < RECON_TOL
+    assert rel(got["vol"], want["vol"]) < RECON_TOL
+    assert abs(got["final_loss"] - want["final_loss"]) <= 1e-3 * abs(want["final_loss"])
+    # graph replays draw the same blades as eager steps
+    s1, s2 = B.Session(plan, y, opts), B.Session(plan, y, opts)
+    s1.step(steps, use_graph=True)
+    s2.step(steps, use_graph=False)
+    assert np.array_equal(s1.read()["vol"], s2.read()["vol"])
+    s1.close()
+    s2.close()
 
 
 def test_reconstruct_static_64_full(gpu_lib):
