@@ -192,7 +192,8 @@ def kplanes_leg(B, steps, warmup):
     model = B.vp_kplanes.make(KP_MODEL["features"], case.n_time, res, KP_MODEL["tv_weight"],
                               KP_MODEL["smooth_weight"], KP_MODEL["sparse_weight"], KP_MODEL["eps"])
     init = init_params(case.n_spec, KP_MODEL["features"], case.n_time, res, seed=case.seed)
-    opts = B.vp_options_default(n_steps=case.n_steps, lr=case.lr, device=0)
+    # the blade kernels of the per-blade plan take the autotuned tile shape
+    opts = B.vp_options_default(n_steps=case.n_steps, lr=case.lr, device=0, autotune=1)
     sess = B.KPlanesSession(plan, model, y, init, opts)
     sess.step(warmup, use_graph=True)
     torch.cuda.synchronize()

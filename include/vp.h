@@ -384,7 +384,9 @@ vp_status vp_kplanes_gradient(const vp_plan* plan, const vp_kplanes* model, cons
 
 /* Resident fit: uploads kspace[B][n][n] and the initial parameters init[count] (host)
  * to opts->device. opts gives n_steps (unused here), optimizer, lr, beta1, beta2,
- * adam_eps, data_weight and device; tv_weight / l1_weight are ignored (the model
+ * adam_eps, data_weight, device and autotune (the blade kernels of the fit take the
+ * tile shape recorded for the geometry with one knot per blade, tuned first when
+ * autotune is set and none is recorded); tv_weight / l1_weight are ignored (the model
  * carries its own weights); only VP_SCHED_ALL_BLADES is supported
  * (VP_ERR_UNSUPPORTED otherwise). */
 vp_status vp_kplanes_session_create(const vp_plan* plan, const vp_kplanes* model, const vp_options* opts,

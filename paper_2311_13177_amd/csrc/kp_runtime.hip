@@ -215,10 +215,19 @@ struct DenseStep {
     KArgs a{};
 };
 
-vp_status dense_setup(const vp_plan* p, DenseStep* ds) {
+// The per-blade plan's tile shape: the one recorded by the autotuner for its sizes, else
+// (opts asking for it) tuned now, else the plan's heuristic shape.
+vp_status dense_setup(const vp_plan* p, DenseStep* ds, const vp_options* o = nullptr) {
     vp_status st = plan_per_blade(p, &ds->q);
     if (st == VP_OK) st = plan_tables(ds->q, &ds->tabs);
-    if (st == VP_OK) st = plan_layout(ds->q, ds->q->base_tiles, &ds->lay);
+    Tiles t = ds->q->base_tiles;
+    if (st == VP_OK && !tuned_tiles(ds->q, ds->tabs->device, o ? o->optimizer : VP_OPT_ADAM, &t) && o &&
+        o->autotune) {
+        vp_options to = *o;
+        to.tiles = vp_tiles{0, 0, 0, 0, 0};
+        st = tune_plan(ds->q, &to, &t);
+    }
+    if (st == VP_OK) st = plan_layout(ds->q, t, &ds->lay);
     if (st == VP_OK) st = device_layout(ds->q, ds->tabs, ds->lay, &ds->dl);
     if (st != VP_OK) return st;
     ds->L = plan_lists(ds->q, ds->tabs, ds->lay, ds->dl);
@@ -431,7 +440,7 @@ extern "C" vp_status vp_kplanes_session_create(const vp_plan* p, const vp_kplane
     s->device = o->device;
     if ((e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking)) != hipSuccess)
         return hip_status(e, "stream");
-    if ((st = dense_setup(p, &s->ds)) != VP_OK) return st;
+    if ((st = dense_setup(p, &s->ds, o)) != VP_OK) return st;
     s->ds.a.one.data_w = o->data_weight;
     build_tables(p, m, p->tau.data(), p->B, &s->tab);
     KPDesc& d = s->tab.d;

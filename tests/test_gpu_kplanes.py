@@ -122,3 +122,32 @@ def test_graph_equals_eager_and_stage_times(gpu_lib):
     assert all(v > 0 for v in st.values())
     a.close()
     b.close()
+
+
+def test_degenerate_grids_and_a_single_blade(gpu_lib):
+    # one time node, an x/y axis of a single node, and a plan of one blade (its per-blade
+    # plan is static); decode and gradient still follow the oracle
+    import torch
+    from paper_2311_13177_amd import binding as B
+
+    case = configs.small_case(n=40, n_spec=3, n_time=2, n_blades=3, lines=8)
+    g = case.geometry()
+    for key in ("angle_rad", "lines", "blade_time"):
+        g[key] = g[key][:1]
+    g["blade_time"] = np.asarray([0.6])
+    plan = B.Plan.from_geometry(g)
+    geom = O.Geometry.from_dict(g)
+    y = O.simulate_measurements(case)[:1]
+    for F, Rt, res in ((2, 1, (40, 1)), (1, 3, (1,)), (4, 2, (40, 40))):
+        cfg = K.KPConfig(features=F, time_res=Rt, spatial_res=res)
+        model = B.vp_kplanes.make(F, Rt, res, 0.01, 0.02, 0.005, 1e-2)
+        _, _, total = K.layout(geom.n_spec, cfg)
+        rng = np.random.default_rng(F * 10 + Rt)
+        p = (0.5 * (rng.standard_normal(total) + 1j * rng.standard_normal(total))).astype(np.complex64)
+        dp = torch.from_numpy(p).cuda()
+        got = B.vp_kplanes_decode(plan, model, dp, [0.0, 0.6]).cpu().numpy()
+        for i, t in enumerate((0.0, 0.6)):
+            assert _rel(got[i], K.decode(p.astype(np.complex128), geom.n, geom.n_spec, cfg, t)) <= 1e-5
+        gr, obj, _ = B.vp_kplanes_gradient(plan, model, dp, torch.from_numpy(np.ascontiguousarray(y)).cuda())
+        wv, wg, _ = K.objective_and_gradient(p.astype(np.complex128), _kp_geom(geom), y, cfg, 0.01, 0.02, 0.005, 1e-2)
+        assert _rel(gr.cpu().numpy(), wg) <= 1e-4 and math.isclose(obj, wv, rel_tol=1e-5), (F, Rt, res)
