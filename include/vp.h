@@ -229,6 +229,21 @@ vp_status vp_forward(const vp_plan* plan, const vp_c64* d_vol, const vp_c64* d_y
  * i dL/dIm V. accumulate != 0 adds to d_grad, otherwise overwrites it. */
 vp_status vp_adjoint(const vp_plan* plan, const vp_c64* d_kres, vp_c64* d_grad, int32_t accumulate, void* stream);
 
+/* Blade-aligned sampling (the non-uniform DFT that the paper's discussion names for
+ * real PROPELLER data, in place of the Cartesian mask and DFT). Blade b's samples sit
+ * on its rotated lattice k = r u_b + q n_b, r = j - n/2 (j < n), q = l - L_b/2
+ * (l < L_b), u_b = (cos, sin), n_b = (-sin, cos); sample arrays are [B][Lmax][n]
+ * (Lmax = the largest L_b, lines l >= L_b unused: written as 0, read as ignored).
+ * Forward: d_out = (1/n) sum_x P_b(x) exp(-2 pi i k.x / n) - d_y (d_y may be NULL), by
+ * gridding (Kaiser-Bessel kernel of width 6 on a grid oversampled 2x; about 1e-5 of the
+ * definition). Adjoint: d_grad (+)= the exact transpose of the forward (gather form, no
+ * atomics). Device pointers on the plan's device, asynchronous on `stream`; scratch of
+ * B (2n)^2 complex values plus the blade images comes from the stream-ordered
+ * allocator. VP_ERR_UNSUPPORTED if 2n is above the largest transform length (512). */
+vp_status vp_nu_forward(const vp_plan* plan, const vp_c64* d_vol, const vp_c64* d_y, vp_c64* d_out, void* stream);
+vp_status vp_nu_adjoint(const vp_plan* plan, const vp_c64* d_samples, vp_c64* d_grad, int32_t accumulate,
+                        void* stream);
+
 /* d_grad (+)= tv_weight * grad TV(d_vol) + l1_weight * grad L1(d_vol)
  * (Section 4.3: Charbonnier TV over x, y, s and t with forward differences
  * where the neighbour exists; Charbonnier L1). */

@@ -112,6 +112,8 @@ _PROTOS = {
     "vp_tv_grad": (c_int32, [_P, _P, c_float, c_float, c_float, _P, c_int32, _P]),
     "vp_render": (c_int32, [_P, _P, c_int32, _P, _P, _P, _P]),
     "vp_baseline": (c_int32, [_P, _P, c_int32, c_int32, c_int32, _P, _P]),
+    "vp_nu_forward": (c_int32, [_P, _P, _P, _P, _P]),
+    "vp_nu_adjoint": (c_int32, [_P, _P, _P, c_int32, _P]),
     "vp_psnr": (c_int32, [_P, _P, c_int64, c_int32, _P, _P]),
     "vp_session_create": (c_int32, [_P, POINTER(vp_options), _P, _P, POINTER(_P)]),
     "vp_session_step": (c_int32, [_P, c_int32, c_int32]),
@@ -351,6 +353,35 @@ def vp_render(plan: Plan, vol, split_bin: int = -1, stream=None):
     check(lib().vp_render(plan.handle, _dev(vol, plan.volume_shape, "vol"), int(split_bin),
                           *[_dev(o, shp, "render") for o in outs], _stream(stream)))
     return tuple(outs)
+
+
+def nu_shape(plan: Plan):
+    """Shape [B][Lmax][n] of blade-aligned sample arrays."""
+    return (plan.n_blades, int(np.max(plan._lines)), plan.n)
+
+
+def vp_nu_forward(plan: Plan, vol, y=None, out=None, stream=None):
+    """Blade-aligned samples of the projected volume (GPU tensors), minus y if given."""
+    import torch
+
+    shp = nu_shape(plan)
+    if out is None:
+        out = torch.empty(shp, dtype=torch.complex64, device=vol.device)
+    check(lib().vp_nu_forward(plan.handle, _dev(vol, plan.volume_shape, "vol"),
+                              None if y is None else _dev(y, shp, "y"), _dev(out, shp, "out"), _stream(stream)))
+    return out
+
+
+def vp_nu_adjoint(plan: Plan, samples, grad=None, accumulate: bool = False, stream=None):
+    """grad (+)= the transpose of vp_nu_forward applied to samples [B][Lmax][n]."""
+    import torch
+
+    if grad is None:
+        grad = torch.empty(plan.volume_shape, dtype=torch.complex64, device=samples.device)
+        accumulate = False
+    check(lib().vp_nu_adjoint(plan.handle, _dev(samples, nu_shape(plan), "samples"),
+                              _dev(grad, plan.volume_shape, "grad"), int(bool(accumulate)), _stream(stream)))
+    return grad
 
 
 def vp_baseline(plan: Plan, kspace, window: int = 0, first_frame: Optional[int] = None,

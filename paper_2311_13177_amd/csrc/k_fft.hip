@@ -248,7 +248,8 @@ __global__ __launch_bounds__(kThreads) void k_rows(const KArgs a) {
         const int r0 = tk->b, rows = min(fb, n - r0);
         float2* A = sm;
         float2* tw = sm + fb * n;
-        float2* img = a.mode == COL_INVERSE ? a.out0 + (size_t)b * nn : DF(work) + (size_t)b * nparts * nn;
+        float2* img = (a.mode == COL_INVERSE || a.mode == COL_RAW_FWD) ? a.out0 + (size_t)b * nn
+                                                                         : DF(work) + (size_t)b * nparts * nn;
         const float2* twg = DF(tw);
         const size_t base = (size_t)r0 * n;
         for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = twg[i];
@@ -284,6 +285,7 @@ __global__ __launch_bounds__(kThreads) void k_rows(const KArgs a) {
 // COL_FORWARD: forward column DFT, out = M (K - y) (y optional), no inverse.
 // COL_ADJOINT: reads caller k-space, Z = M kres / n, inverse column DFT -> work.
 // COL_INVERSE: inverse column DFT of caller frames, unmasked and unscaled, -> a.out0.
+// COL_RAW_FWD: forward column DFT of caller frames, unmasked and unscaled, -> a.out0.
 
 template <int NC>
 __global__ __launch_bounds__(kThreads) void k_cols(const KArgs a) {
@@ -314,9 +316,10 @@ __global__ __launch_bounds__(kThreads) void k_cols(const KArgs a) {
         uint8_t* M = reinterpret_cast<uint8_t*>(Y + cb * n);
         float2* img = DF(work) + (size_t)b * nparts * nn;
         const float2* twg = DF(tw);
-        const bool from_in = a.mode == COL_ADJOINT || a.mode == COL_INVERSE;
+        const bool raw = a.mode == COL_INVERSE || a.mode == COL_RAW_FWD;
+        const bool from_in = a.mode == COL_ADJOINT || raw;
         const float2* src = from_in ? a.in0 + (size_t)b * nn : img;
-        float2* dst = a.mode == COL_INVERSE ? a.out0 + (size_t)b * nn : img;
+        float2* dst = raw ? a.out0 + (size_t)b * nn : img;
         const uint8_t* mk = DF(mask) + (size_t)b * nn;
         const float2* yy = DF(y);
         const float2* yb = (yy && !from_in) ? yy + (size_t)b * nn : nullptr;
@@ -336,13 +339,13 @@ __global__ __launch_bounds__(kThreads) void k_cols(const KArgs a) {
             M[i] = m;
         }
         __syncthreads();
-        if (!from_in) fft_cols_any<-1, NC>(A, tw, n, nstage, code);
+        if (!from_in || a.mode == COL_RAW_FWD) fft_cols_any<-1, NC>(A, tw, n, nstage, code);
         const float sc = 1.0f / (float)n;
         // the step's residual and loss carry the data-term weight
         const float dw = a.mode == COL_STEP ? DF(data_w) : 1.0f;
         const float sc_res = dw * sc;
         float lsum = 0.f;
-        for (int i = threadIdx.x; i < n * cb && a.mode != COL_INVERSE; i += blockDim.x) {
+        for (int i = threadIdx.x; i < n * cb && !raw; i += blockDim.x) {
             const int y = i / cb, c = i - (i / cb) * cb;
             float2 v = make_float2(0.f, 0.f);
             if (c < cols) {
@@ -366,7 +369,7 @@ __global__ __launch_bounds__(kThreads) void k_cols(const KArgs a) {
         }
         __syncthreads();
         if (a.mode != COL_FORWARD) {
-            fft_cols_any<1, NC>(A, tw, n, nstage, code);
+            if (a.mode != COL_RAW_FWD) fft_cols_any<1, NC>(A, tw, n, nstage, code);
             for (int i = threadIdx.x; i < n * cb; i += blockDim.x) {
                 const int y = i / cb, c = i - (i / cb) * cb;
                 if (c < cols) dst[(size_t)y * n + c0 + c] = A[i];

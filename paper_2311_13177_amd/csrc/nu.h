@@ -1,0 +1,33 @@
+// Blade-aligned sampling by gridding: kernel arguments and launchers (k_nu.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "vp_internal.h"
+
+namespace vp {
+
+struct NuArgs {
+    int n, M, B, lmax, nparts;
+    float kmax;             // bound on |kNuSigma k| over every sample (grid units)
+    const int* lines;       // [B]
+    const float2* cs;       // [B] (cos, sin) of the blade angle
+    const float* dea;       // [n] 1 / (kernel transform) at the centred index x - n/2
+    const float* kb;        // [kNuTable + 1] kernel on [0, W/2]
+    const float2* k;        // [B][lmax][n] sample positions (kx, ky)
+    const float2* ph;       // [B][lmax][n] exp(-i pi (kx + ky) 2 floor(n/2) / n) / n
+    const BladeDev* blade;  // knot blend of dynamic blades (pad)
+    const float2* work;     // projection parts [B][nparts][n][n] (pad)
+    float2* img_out;        // adjoint images, part 0 of [B][nparts][n][n] (crop)
+    float2* grid;           // oversampled grids [B][M][M]
+    const float2* y;        // measured samples [B][lmax][n] (interp; may be null)
+    float2* out;            // samples [B][lmax][n] (interp)
+    const float2* s_in;     // samples [B][lmax][n] (spread)
+};
+
+hipError_t nu_launch_pad(const NuArgs& d, hipStream_t s);
+hipError_t nu_launch_interp(const NuArgs& d, hipStream_t s);
+hipError_t nu_launch_spread(const NuArgs& d, hipStream_t s);
+hipError_t nu_launch_crop(const NuArgs& d, hipStream_t s);
+
+}  // namespace vp

@@ -261,6 +261,79 @@ vp_status plan_per_blade(const vp_plan* p, const vp_plan** out) {
     return VP_OK;
 }
 
+// Modified Bessel function I0 by its power series (converges for the arguments used).
+static double bessel_i0(double x) {
+    double sum = 1.0, term = 1.0;
+    const double q = 0.25 * x * x;
+    for (int k = 1; k < 200; ++k) {
+        term *= q / ((double)k * k);
+        sum += term;
+        if (term < 1e-17 * sum) break;
+    }
+    return sum;
+}
+
+vp_status plan_nu(const vp_plan* p, const NuHost** host, const vp_plan** over) {
+    std::lock_guard<std::mutex> lk(p->mu_derived);
+    const int n = p->n, B = p->B, M = kNuSigma * n;
+    if (M > kMaxN) return fail(VP_ERR_UNSUPPORTED, "blade sampling: 2n = %d above %d", M, kMaxN);
+    if (!p->over) {
+        const std::vector<double> zero(1, 0.0);
+        std::vector<int> lines(p->lines);
+        const vp_geometry g{M, 1, 1, B, p->angle.data(), lines.data(), nullptr, zero.data()};
+        vp_plan* q = nullptr;
+        const vp_status st = plan_create(&g, false, &q);
+        if (st != VP_OK) return st;
+        p->over.reset(q);
+    }
+    if (!p->nu_host) {
+        std::unique_ptr<NuHost> h(new (std::nothrow) NuHost());
+        if (!h) return fail(VP_ERR_NOMEM, "blade sampling: out of host memory");
+        const double W = kNuWidth, sig = kNuSigma;
+        const double beta = M_PI * std::sqrt((W / sig) * (W / sig) * (sig - 0.5) * (sig - 0.5) - 0.8);
+        h->lines = p->lines;
+        h->lmax = *std::max_element(p->lines.begin(), p->lines.end());
+        h->cs.resize(B);
+        h->k.assign((size_t)B * h->lmax * n, make_float2(0.f, 0.f));
+        h->ph.assign((size_t)B * h->lmax * n, make_float2(0.f, 0.f));
+        const double half = (double)(2 * (n / 2)) / n;
+        double kmax = 0.0;
+        for (int b = 0; b < B; ++b) {
+            const double c = std::cos(p->angle[b]), s = std::sin(p->angle[b]);
+            h->cs[b] = make_float2((float)c, (float)s);
+            for (int l = 0; l < p->lines[b]; ++l)
+                for (int j = 0; j < n; ++j) {
+                    const double r = j - 0.5 * n, q = l - 0.5 * p->lines[b];
+                    const double kx = r * c - q * s, ky = r * s + q * c;
+                    const size_t i = ((size_t)b * h->lmax + l) * n + j;
+                    h->k[i] = make_float2((float)kx, (float)ky);
+                    const double a = -M_PI * (kx + ky) * half;
+                    h->ph[i] = make_float2((float)(std::cos(a) / n), (float)(std::sin(a) / n));
+                    kmax = std::max(kmax, std::max(std::fabs(sig * kx), std::fabs(sig * ky)));
+                }
+        }
+        h->kmax = (float)(kmax + 1.0);
+        // 1 / (kernel transform) at the centred index x - floor(n/2): W sinh(z)/z, z^2 =
+        // beta^2 - (pi W x / M)^2
+        h->dea.resize(n);
+        for (int x = 0; x < n; ++x) {
+            const double w = M_PI * W * (double)(x - n / 2) / M;
+            const double z2 = beta * beta - w * w, z = std::sqrt(std::fabs(z2));
+            const double c = z == 0.0 ? W : (z2 > 0 ? W * std::sinh(z) / z : W * std::sin(z) / z);
+            h->dea[x] = (float)(1.0 / c);
+        }
+        h->kb.resize(kNuTable + 1);
+        for (int i = 0; i <= kNuTable; ++i) {
+            const double t = (double)i / kNuTable;  // u / (W / 2)
+            h->kb[i] = (float)bessel_i0(beta * std::sqrt(std::max(0.0, 1.0 - t * t)));
+        }
+        p->nu_host = std::move(h);
+    }
+    *host = p->nu_host.get();
+    *over = p->over.get();
+    return VP_OK;
+}
+
 static vp_status plan_create(const vp_geometry* g, bool per_blade, vp_plan** out) {
     if (!g || !out) return fail(VP_ERR_ARG, "vp_plan_create: NULL geometry or output");
     if (g->n < 1 || g->n_spec < 1 || g->n_time < 1 || g->n_blades < 1)

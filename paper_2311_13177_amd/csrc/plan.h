@@ -58,7 +58,23 @@ struct DeviceTables {
     Task* t_vox = nullptr;
     Task* t_render = nullptr;
     std::map<int, std::unique_ptr<DeviceLayout>> layouts;  // by Tiles::key()
+    // blade-aligned sampling tables (uploaded on first use)
+    int* nu_lines = nullptr;
+    float2* nu_cs = nullptr;
+    float2* nu_k = nullptr;
+    float2* nu_ph = nullptr;
+    float* nu_dea = nullptr;
+    float* nu_kb = nullptr;
     ~DeviceTables();
+};
+
+// Host tables of blade-aligned sampling (see the blade-sampling kernels).
+struct NuHost {
+    int lmax = 0;
+    float kmax = 0.f;
+    std::vector<int> lines;
+    std::vector<float2> cs, k, ph;   // [B], [B][lmax][n], [B][lmax][n]
+    std::vector<float> dea, kb;      // [n], [kNuTable + 1]
 };
 
 }  // namespace vp
@@ -95,6 +111,10 @@ struct vp_plan {
     // The same geometry with a knot per blade (built on first use; K-Planes fits).
     mutable std::mutex mu_derived;
     mutable std::unique_ptr<vp_plan> per_blade;
+    // Blade-aligned sampling: its host tables and the plan of the oversampled grid
+    // (2n x 2n, the same blades; its DFT passes only), built on first use.
+    mutable std::unique_ptr<vp::NuHost> nu_host;
+    mutable std::unique_ptr<vp_plan> over;
 
     uint64_t voxels() const { return (uint64_t)T * S * n * n; }
     uint64_t blade_px() const { return (uint64_t)B * n * n; }
@@ -105,6 +125,11 @@ namespace vp {
 // The plan's geometry with one knot per blade (knot b holds blade b with weight 1, one
 // work part per blade), built on first use and kept with the plan.
 vp_status plan_per_blade(const vp_plan* plan, const vp_plan** out);
+// Blade-aligned sampling: host tables and the oversampled grid's plan (VP_ERR_UNSUPPORTED
+// if 2n exceeds the largest transform length).
+vp_status plan_nu(const vp_plan* plan, const NuHost** host, const vp_plan** over);
+// The tables of plan_nu on the device of `t`, uploaded on first use.
+vp_status nu_tables(const vp_plan* plan, const NuHost* host, DeviceTables* t);
 
 // Device tables of `plan` on the current device, uploading them on first use.
 vp_status plan_tables(const vp_plan* plan, DeviceTables** out);

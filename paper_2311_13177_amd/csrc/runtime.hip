@@ -12,6 +12,7 @@
 
 #include "plan.h"
 #include "runtime.h"
+#include "nu.h"
 
 namespace vp {
 
@@ -28,7 +29,8 @@ DeviceTables::~DeviceTables() {
     if (hipGetDevice(&prev) != hipSuccess) prev = -1;
     if (device >= 0) (void)hipSetDevice(device);
     layouts.clear();
-    void* ptrs[] = {mask, shear, blade, knot_ptr, knot_ent, knot_tap, knots, tw, t_rows, t_cols, t_vox, t_render};
+    void* ptrs[] = {mask, shear, blade, knot_ptr, knot_ent, knot_tap, knots, tw, t_rows, t_cols, t_vox, t_render,
+                    nu_lines, nu_cs, nu_k, nu_ph, nu_dea, nu_kb};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (prev >= 0) (void)hipSetDevice(prev);
@@ -373,6 +375,135 @@ extern "C" vp_status vp_psnr(const vp_c64* d_image, const vp_c64* d_truth, int64
     const hipError_t e = launch_psnr((const float2*)d_image, (const float2*)d_truth, (long long)n_px, n_images,
                                      d_terms, (hipStream_t)stream);
     return e == hipSuccess ? VP_OK : hip_status(e, "vp_psnr");
+}
+
+// ------------------------------------------------------------------ blade-aligned sampling
+
+namespace vp {
+
+vp_status nu_tables(const vp_plan* p, const NuHost* h, DeviceTables* t) {
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (t->nu_kb) return VP_OK;
+    hipError_t e = upload(&t->nu_lines, h->lines);
+    if (e == hipSuccess) e = upload(&t->nu_cs, h->cs);
+    if (e == hipSuccess) e = upload(&t->nu_k, h->k);
+    if (e == hipSuccess) e = upload(&t->nu_ph, h->ph);
+    if (e == hipSuccess) e = upload(&t->nu_dea, h->dea);
+    if (e == hipSuccess) e = upload(&t->nu_kb, h->kb);
+    return hip_status(e, "blade sampling tables");
+}
+
+}  // namespace vp
+
+namespace {
+
+// The oversampled grid's plan and its DFT passes, plus the gridding arguments.
+struct NuScope {
+    const vp_plan* q = nullptr;
+    DeviceTables* tq = nullptr;
+    const Layout* lq = nullptr;
+    const DeviceLayout* dq = nullptr;
+    const NuHost* h = nullptr;
+    float2* grid = nullptr;
+    hipStream_t s;
+    NuArgs d{};
+    explicit NuScope(hipStream_t stream) : s(stream) {}
+    vp_status begin(const vp_plan* p, DeviceTables* t) {
+        vp_status st = plan_nu(p, &h, &q);
+        if (st == VP_OK) st = nu_tables(p, h, t);
+        if (st == VP_OK) st = plan_tables(q, &tq);
+        if (st == VP_OK) st = plan_layout(q, q->base_tiles, &lq);
+        if (st == VP_OK) st = device_layout(q, tq, lq, &dq);
+        if (st != VP_OK) return st;
+        const size_t bytes = (size_t)p->B * q->n * q->n * sizeof(float2);
+        hipError_t e = hipMallocAsync((void**)&grid, bytes, s);
+        if (e != hipSuccess) return hip_status(e, "oversampled grids");
+        d.n = p->n; d.M = q->n; d.B = p->B; d.lmax = h->lmax; d.nparts = p->nparts; d.kmax = h->kmax;
+        d.lines = t->nu_lines; d.cs = t->nu_cs; d.dea = t->nu_dea; d.kb = t->nu_kb; d.k = t->nu_k; d.ph = t->nu_ph;
+        d.blade = t->blade;
+        d.grid = grid;
+        return VP_OK;
+    }
+    // unscaled 2D DFT of the grids in place: forward (dir -1) or inverse (dir +1)
+    hipError_t dft(int dir) {
+        KArgs a{};
+        fill_desc(q, tq, lq, dq, &a.one);
+        const StageLists L = plan_lists(q, tq, lq, dq);
+        a.in0 = grid;
+        a.out0 = grid;
+        hipError_t e;
+        if (dir < 0) {
+            a.mode = COL_RAW_FWD;
+            a.tasks = L.rows; a.ntasks = L.n_rows;
+            if ((e = launch_rows(a, -1, L.fft_n, L.lds_rows, s)) != hipSuccess) return e;
+            a.tasks = L.cols; a.ntasks = L.n_cols;
+            return launch_cols(a, L.fft_n, L.lds_cols, s);
+        }
+        a.mode = COL_INVERSE;
+        a.tasks = L.cols; a.ntasks = L.n_cols;
+        if ((e = launch_cols(a, L.fft_n, L.lds_cols, s)) != hipSuccess) return e;
+        a.tasks = L.rows; a.ntasks = L.n_rows;
+        return launch_rows(a, 1, L.fft_n, L.lds_rows, s);
+    }
+    ~NuScope() {
+        if (grid) (void)hipFreeAsync(grid, s);
+    }
+};
+
+}  // namespace
+
+extern "C" vp_status vp_nu_forward(const vp_plan* p, const vp_c64* d_vol, const vp_c64* d_y, vp_c64* d_out,
+                                   void* stream) {
+    clear_error();
+    if (!p || !d_vol || !d_out) return fail(VP_ERR_ARG, "vp_nu_forward: NULL argument");
+    OpScope sc(p, stream);
+    vp_status st = sc.begin(true);
+    if (st != VP_OK) return st;
+    NuScope nu(sc.s);
+    if ((st = nu.begin(p, sc.t)) != VP_OK) return st;
+    KArgs a{};
+    fill_desc(p, sc.t, sc.lay, sc.dl, &a.one);
+    a.one.vol[0] = (float2*)d_vol;
+    a.one.work = sc.work;
+    const StageLists L = plan_lists(p, sc.t, sc.lay, sc.dl);
+    hipError_t e;
+    a.tasks = L.proj; a.ntasks = L.n_proj;
+    if ((e = launch_project(a, L.tiles.proj_rows, L.tiles.proj_gw, L.re_proj, sc.s)) != hipSuccess)
+        return hip_status(e, "vp_nu_forward project");
+    nu.d.work = sc.work;
+    nu.d.y = (const float2*)d_y;
+    nu.d.out = (float2*)d_out;
+    if ((e = nu_launch_pad(nu.d, sc.s)) != hipSuccess) return hip_status(e, "vp_nu_forward pad");
+    if ((e = nu.dft(-1)) != hipSuccess) return hip_status(e, "vp_nu_forward DFT");
+    if ((e = nu_launch_interp(nu.d, sc.s)) != hipSuccess) return hip_status(e, "vp_nu_forward interpolation");
+    return VP_OK;
+}
+
+extern "C" vp_status vp_nu_adjoint(const vp_plan* p, const vp_c64* d_samples, vp_c64* d_grad, int32_t accumulate,
+                                   void* stream) {
+    clear_error();
+    if (!p || !d_samples || !d_grad) return fail(VP_ERR_ARG, "vp_nu_adjoint: NULL argument");
+    OpScope sc(p, stream);
+    vp_status st = sc.begin(true);
+    if (st != VP_OK) return st;
+    NuScope nu(sc.s);
+    if ((st = nu.begin(p, sc.t)) != VP_OK) return st;
+    hipError_t e;
+    nu.d.s_in = (const float2*)d_samples;
+    nu.d.img_out = sc.work;
+    if ((e = nu_launch_spread(nu.d, sc.s)) != hipSuccess) return hip_status(e, "vp_nu_adjoint spread");
+    if ((e = nu.dft(1)) != hipSuccess) return hip_status(e, "vp_nu_adjoint DFT");
+    if ((e = nu_launch_crop(nu.d, sc.s)) != hipSuccess) return hip_status(e, "vp_nu_adjoint crop");
+    KArgs a{};
+    fill_desc(p, sc.t, sc.lay, sc.dl, &a.one);
+    a.one.work = sc.work;
+    a.one.grad = (float2*)d_grad;
+    a.accumulate = accumulate != 0;
+    const StageLists L = plan_lists(p, sc.t, sc.lay, sc.dl);
+    a.tasks = L.gath; a.ntasks = L.n_gath;
+    if ((e = launch_gather(a, GATHER_STORE, L.tiles.gath_rows, L.tiles.gath_sc, L.re_gath, sc.s)) != hipSuccess)
+        return hip_status(e, "vp_nu_adjoint gather");
+    return VP_OK;
 }
 
 extern "C" vp_status vp_tv_grad(const vp_plan* p, const vp_c64* d_vol, float tv_w, float l1_w, float eps,

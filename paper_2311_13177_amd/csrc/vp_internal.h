@@ -151,8 +151,14 @@ struct KArgs {
 
 // Column pass modes.
 // COL_INVERSE (column and inverse row pass): in-place unscaled inverse DFT of the frames at
-// a.out0 (frame = the task's blade index), read from a.in0.
-enum { COL_STEP = 0, COL_FORWARD = 1, COL_ADJOINT = 2, COL_INVERSE = 3 };
+// a.out0 (frame = the task's blade index), read from a.in0. COL_RAW_FWD: the same for the
+// forward DFT (column pass and forward row pass).
+enum { COL_STEP = 0, COL_FORWARD = 1, COL_ADJOINT = 2, COL_INVERSE = 3, COL_RAW_FWD = 4 };
+// Blade-aligned sampling by gridding: Kaiser-Bessel kernel of width kNuWidth on a grid
+// oversampled by kNuSigma, tabulated at kNuTable + 1 points over [0, kNuWidth / 2].
+constexpr int kNuSigma = 2;
+constexpr float kNuWidth = 6.0f;
+constexpr int kNuTable = 4096;
 // Gather epilogues.
 enum { GATHER_STORE = 0, GATHER_STEP = 1 };
 // Optimiser epilogue variants: EPI_GENERIC takes the optimiser and the regulariser
