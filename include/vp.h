@@ -244,6 +244,19 @@ vp_status vp_nu_forward(const vp_plan* plan, const vp_c64* d_vol, const vp_c64* 
 vp_status vp_nu_adjoint(const vp_plan* plan, const vp_c64* d_samples, vp_c64* d_grad, int32_t accumulate,
                         void* stream);
 
+/* The fit of Section 4.3 on blade-aligned samples: vp_reconstruct with the gridding
+ * passes above in place of the masked Cartesian DFT (projection, fused gather and
+ * update, regularisers, schedule of steps and outputs as there). samples: host
+ * [B][Lmax][n] (the layout above; lines l >= L_b ignored). init, outputs and
+ * final_loss as in vp_reconstruct; final_loss = 0.5 data_weight sum |r|^2 + TV + L1 at
+ * the returned volume. Only VP_SCHED_ALL_BLADES (VP_ERR_UNSUPPORTED otherwise);
+ * VP_ERR_NONFINITE if a used sample is NaN or Inf; VP_ERR_UNSUPPORTED if 2n is above
+ * 512. Blocking; device memory is the session's plus B (2n)^2 complex values and two
+ * sample arrays, all freed on return. */
+vp_status vp_nu_reconstruct(const vp_plan* plan, const vp_options* opts, const vp_c64* samples, const vp_c64* init,
+                            vp_c64* volume_out, vp_c64* proj_out, vp_c64* water_out, vp_c64* fat_out,
+                            double* final_loss);
+
 /* d_grad (+)= tv_weight * grad TV(d_vol) + l1_weight * grad L1(d_vol)
  * (Section 4.3: Charbonnier TV over x, y, s and t with forward differences
  * where the neighbour exists; Charbonnier L1). */

@@ -26,7 +26,8 @@ import math
 import numpy as np
 import scipy.special
 
-from .lifted import Geometry, displacement, project_blade, shear_transpose, volume_at, knot_weights
+from .lifted import (Geometry, adam_update, displacement, knot_weights, l1_grad, l1_value, project_blade, render,
+                     shear_transpose, tv_grad, tv_value, volume_at)
 
 KB_WIDTH = 6.0
 KB_SIGMA = 2.0
@@ -158,3 +159,54 @@ def gradient_nu(vol: np.ndarray, geom: Geometry, y: list, exact: bool = True):
             grad[k] += (1.0 - a) * per_bin
             grad[k + 1] += a * per_bin
     return grad, total
+
+
+def reconstruct_nu(geom: Geometry, y: list, n_steps: int, tv_weight: float = 1e-3, tv_eps: float = 1e-3,
+                   l1_weight: float = 0.0, lr: float = 1e-2, beta1: float = 0.9, beta2: float = 0.999,
+                   adam_eps: float = 1e-8, optimizer: str = "adam", exact: bool = True,
+                   data_weight: float = 1.0, split_bin: int = -1) -> dict:
+    """The fit of Section 4.3 on blade-aligned samples: every step the gradient of the
+    weighted data term over all blades plus TV and L1, then Adam or GD; from zero."""
+    vol = np.zeros((geom.n_time, geom.n_spec, geom.n, geom.n), dtype=np.complex128)
+    m = np.zeros(vol.shape + (2,))
+    v = np.zeros(vol.shape + (2,))
+
+    def value(vv):
+        _, d = gradient_nu(vv, geom, y, exact)
+        out = data_weight * d
+        if tv_weight != 0.0:
+            out += tv_weight * tv_value(vv, tv_eps)
+        if l1_weight != 0.0:
+            out += l1_weight * l1_value(vv, tv_eps)
+        return out
+
+    for t in range(1, n_steps + 1):
+        g, _ = gradient_nu(vol, geom, y, exact)
+        g = data_weight * g
+        if tv_weight != 0.0:
+            g = g + tv_weight * tv_grad(vol, tv_eps)
+        if l1_weight != 0.0:
+            g = g + l1_weight * l1_grad(vol, tv_eps)
+        if optimizer == "adam":
+            vol, m, v = adam_update(vol, g, m, v, t, lr, beta1, beta2, adam_eps)
+        else:
+            vol = vol - lr * g
+    proj, water, fat = render(vol, split_bin)
+    return dict(vol=vol, proj=proj, water=water, fat=fat, final_loss=value(vol))
+
+
+def simulate_samples(case) -> list:
+    """Section 5's measurement on blade-aligned samples: blade b's lattice samples of the
+    projected ground truth at its time (the definition), plus sigma times the case's noise
+    on its first L_b rows; [L_b][n] per blade, complex128."""
+    from synth.phantom import ground_truth_volume
+
+    geom = Geometry.from_dict(case.geometry())
+    out = []
+    for b in range(geom.n_blades):
+        w, f = case.layers_at(geom.tau(b))
+        gt = ground_truth_volume(w, f, geom.n_spec)
+        L = int(geom.lines[b])
+        kx, ky = blade_samples(geom.n, float(geom.angle_rad[b]), L)
+        out.append(ndft_forward(project_blade(gt, geom, b), kx, ky) + case.sigma * case.noise[b][:L, :])
+    return out

@@ -114,6 +114,7 @@ _PROTOS = {
     "vp_baseline": (c_int32, [_P, _P, c_int32, c_int32, c_int32, _P, _P]),
     "vp_nu_forward": (c_int32, [_P, _P, _P, _P, _P]),
     "vp_nu_adjoint": (c_int32, [_P, _P, _P, c_int32, _P]),
+    "vp_nu_reconstruct": (c_int32, [_P, POINTER(vp_options), _P, _P, _P, _P, _P, _P, POINTER(c_double)]),
     "vp_psnr": (c_int32, [_P, _P, c_int64, c_int32, _P, _P]),
     "vp_session_create": (c_int32, [_P, POINTER(vp_options), _P, _P, POINTER(_P)]),
     "vp_session_step": (c_int32, [_P, c_int32, c_int32]),
@@ -382,6 +383,20 @@ def vp_nu_adjoint(plan: Plan, samples, grad=None, accumulate: bool = False, stre
     check(lib().vp_nu_adjoint(plan.handle, _dev(samples, nu_shape(plan), "samples"),
                               _dev(grad, plan.volume_shape, "grad"), int(bool(accumulate)), _stream(stream)))
     return grad
+
+
+def vp_nu_reconstruct(plan: Plan, samples: np.ndarray, opts: Optional[vp_options] = None,
+                      init: Optional[np.ndarray] = None) -> dict:
+    """vp_reconstruct on blade-aligned samples [B][Lmax][n] (host arrays)."""
+    opts = opts if opts is not None else vp_options_default()
+    y = _host_c64(samples, nu_shape(plan))
+    i = _host_c64(init, plan.volume_shape)
+    vol = np.empty(plan.volume_shape, np.complex64)
+    outs = [np.empty(plan.render_shape, np.complex64) for _ in range(3)]
+    loss = c_double()
+    check(lib().vp_nu_reconstruct(plan.handle, byref(opts), _hp(y), _hp(i), _hp(vol), *[_hp(o) for o in outs],
+                                  byref(loss)))
+    return dict(vol=vol, proj=outs[0], water=outs[1], fat=outs[2], final_loss=float(loss.value))
 
 
 def vp_baseline(plan: Plan, kspace, window: int = 0, first_frame: Optional[int] = None,

@@ -61,8 +61,11 @@ __global__ __launch_bounds__(kThreads) void k_nu_pad(const NuArgs d) {
     }
 }
 
-// out[b][l][j] = (sum over the grid points within W/2 of 2k of C C grid) * phase / n - y
+// out[b][l][j] = (sum over the grid points within W/2 of 2k of C C grid) * phase / n - y;
+// with d.loss, each block also writes the sum of |out|^2 over its samples (fixed order)
 __global__ __launch_bounds__(kThreads) void k_nu_interp(const NuArgs d) {
+    __shared__ float red[kThreads];
+    float lsum = 0.f;
     const int n = d.n, M = d.M;
     const long long per = (long long)d.lmax * n;
     const long long total = (long long)d.B * per;
@@ -72,22 +75,33 @@ __global__ __launch_bounds__(kThreads) void k_nu_interp(const NuArgs d) {
         const int l = (int)((e % per) / n);
         float2 v = make_float2(0.f, 0.f);
         if (l < d.lines[b]) {
-            const float2 k = d.k[e];
-            const float gx = (float)kNuSigma * k.x, gy = (float)kNuSigma * k.y;
-            const int x0 = (int)ceilf(gx - h), x1 = (int)floorf(gx + h);
-            const int y0 = (int)ceilf(gy - h), y1 = (int)floorf(gy + h);
+            // offsets to grid point m: (kg - m) + kf, exact integer plus fraction
+            const int2 kg = d.kg[e];
+            const float2 kf = d.kf[e];
+            const int x0 = kg.x + (int)ceilf(kf.x - h), x1 = kg.x + (int)floorf(kf.x + h);
+            const int y0 = kg.y + (int)ceilf(kf.y - h), y1 = kg.y + (int)floorf(kf.y + h);
             const float2* g = d.grid + (long long)b * M * M;
             for (int my = y0; my <= y1; ++my) {
-                const float cy = kb(d.kb, gy - (float)my);
+                const float cy = kb(d.kb, (float)(kg.y - my) + kf.y);
                 const float2* row = g + (long long)wrap(my, M) * M;
                 float2 r = make_float2(0.f, 0.f);
-                for (int mx = x0; mx <= x1; ++mx) r = cfma(kb(d.kb, gx - (float)mx), row[wrap(mx, M)], r);
+                for (int mx = x0; mx <= x1; ++mx) r = cfma(kb(d.kb, (float)(kg.x - mx) + kf.x), row[wrap(mx, M)], r);
                 v = cfma(cy, r, v);
             }
             v = cmul(v, d.ph[e]);
             if (d.y) v = csub(v, d.y[e]);
         }
         d.out[e] = v;
+        lsum = __builtin_fmaf(v.x, v.x, __builtin_fmaf(v.y, v.y, lsum));
+    }
+    if (d.loss) {
+        red[threadIdx.x] = lsum;
+        __syncthreads();
+        for (int hh = kThreads / 2; hh > 0; hh >>= 1) {
+            if ((int)threadIdx.x < hh) red[threadIdx.x] += red[threadIdx.x + hh];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) d.loss[blockIdx.x] = red[0];
     }
 }
 
@@ -105,7 +119,8 @@ __global__ __launch_bounds__(kThreads) void k_nu_spread(const NuArgs d) {
         const int py = (int)((e % MM) / M), px = (int)(e % M);
         const float c = d.cs[b].x, s = d.cs[b].y;
         const int L = d.lines[b];
-        const float2* kk = d.k + (long long)b * d.lmax * n;
+        const int2* kg = d.kg + (long long)b * d.lmax * n;
+        const float2* kf = d.kf + (long long)b * d.lmax * n;
         const float2* sv = d.s_in + (long long)b * d.lmax * n;
         const float2* ph = d.ph + (long long)b * d.lmax * n;
         float2 acc = make_float2(0.f, 0.f);
@@ -123,12 +138,14 @@ __global__ __launch_bounds__(kThreads) void k_nu_spread(const NuArgs d) {
                 for (int l = l0; l <= l1; ++l) {
                     for (int j = j0; j <= j1; ++j) {
                         const long long i = (long long)l * n + j;
-                        const float2 k = kk[i];
-                        const float dx = (float)kNuSigma * k.x - (float)Px;
-                        const float dy = (float)kNuSigma * k.y - (float)Py;
+                        // the offsets k_nu_interp weighs this pair with, bit for bit
+                        const int2 g = kg[i];
+                        const float2 f = kf[i];
+                        const float dx = (float)(g.x - Px) + f.x;
+                        const float dy = (float)(g.y - Py) + f.y;
                         if (fabsf(dx) <= h && fabsf(dy) <= h) {
                             const float2 p = ph[i];
-                            const float2 v = cmul(sv[i], make_float2(p.x, -p.y));
+                            const float2 v = cscale(cmul(sv[i], make_float2(p.x, -p.y)), d.dw);
                             acc = cfma(kb(d.kb, dy) * kb(d.kb, dx), v, acc);
                         }
                     }
@@ -164,8 +181,9 @@ hipError_t nu_launch_pad(const NuArgs& d, hipStream_t s) {
     hipLaunchKernelGGL(k_nu_pad, dim3(grid_of((long long)d.B * d.M * d.M)), dim3(kThreads), 0, s, d);
     return hipGetLastError();
 }
+int nu_interp_blocks(const NuArgs& d) { return (int)grid_of((long long)d.B * d.lmax * d.n); }
 hipError_t nu_launch_interp(const NuArgs& d, hipStream_t s) {
-    hipLaunchKernelGGL(k_nu_interp, dim3(grid_of((long long)d.B * d.lmax * d.n)), dim3(kThreads), 0, s, d);
+    hipLaunchKernelGGL(k_nu_interp, dim3(nu_interp_blocks(d)), dim3(kThreads), 0, s, d);
     return hipGetLastError();
 }
 hipError_t nu_launch_spread(const NuArgs& d, hipStream_t s) {

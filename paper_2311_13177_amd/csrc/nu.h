@@ -14,7 +14,8 @@ struct NuArgs {
     const float2* cs;       // [B] (cos, sin) of the blade angle
     const float* dea;       // [n] 1 / (kernel transform) at the centred index x - n/2
     const float* kb;        // [kNuTable + 1] kernel on [0, W/2]
-    const float2* k;        // [B][lmax][n] sample positions (kx, ky)
+    const int2* kg;         // [B][lmax][n] floor(kNuSigma k): the grid point below each sample
+    const float2* kf;       // [B][lmax][n] kNuSigma k - kg, in [0, 1)
     const float2* ph;       // [B][lmax][n] exp(-i pi (kx + ky) 2 floor(n/2) / n) / n
     const BladeDev* blade;  // knot blend of dynamic blades (pad)
     const float2* work;     // projection parts [B][nparts][n][n] (pad)
@@ -23,10 +24,14 @@ struct NuArgs {
     const float2* y;        // measured samples [B][lmax][n] (interp; may be null)
     float2* out;            // samples [B][lmax][n] (interp)
     const float2* s_in;     // samples [B][lmax][n] (spread)
+    float dw;               // spread weight (the data-term weight of a fit; 1 for the operator)
+    float* loss;            // per-block sums of |out|^2 (interp with loss), or null
 };
 
 hipError_t nu_launch_pad(const NuArgs& d, hipStream_t s);
 hipError_t nu_launch_interp(const NuArgs& d, hipStream_t s);
+// Blocks of the interpolation launch (the length of d.loss).
+int nu_interp_blocks(const NuArgs& d);
 hipError_t nu_launch_spread(const NuArgs& d, hipStream_t s);
 hipError_t nu_launch_crop(const NuArgs& d, hipStream_t s);
 

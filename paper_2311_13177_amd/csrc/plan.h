@@ -61,7 +61,8 @@ struct DeviceTables {
     // blade-aligned sampling tables (uploaded on first use)
     int* nu_lines = nullptr;
     float2* nu_cs = nullptr;
-    float2* nu_k = nullptr;
+    int2* nu_kg = nullptr;
+    float2* nu_kf = nullptr;
     float2* nu_ph = nullptr;
     float* nu_dea = nullptr;
     float* nu_kb = nullptr;
@@ -73,7 +74,8 @@ struct NuHost {
     int lmax = 0;
     float kmax = 0.f;
     std::vector<int> lines;
-    std::vector<float2> cs, k, ph;   // [B], [B][lmax][n], [B][lmax][n]
+    std::vector<float2> cs, kf, ph;  // [B], [B][lmax][n], [B][lmax][n]
+    std::vector<int2> kg;            // [B][lmax][n]
     std::vector<float> dea, kb;      // [n], [kNuTable + 1]
 };
 

@@ -30,7 +30,7 @@ DeviceTables::~DeviceTables() {
     if (device >= 0) (void)hipSetDevice(device);
     layouts.clear();
     void* ptrs[] = {mask, shear, blade, knot_ptr, knot_ent, knot_tap, knots, tw, t_rows, t_cols, t_vox, t_render,
-                    nu_lines, nu_cs, nu_k, nu_ph, nu_dea, nu_kb};
+                    nu_lines, nu_cs, nu_kg, nu_kf, nu_ph, nu_dea, nu_kb};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (prev >= 0) (void)hipSetDevice(prev);
@@ -386,7 +386,8 @@ vp_status nu_tables(const vp_plan* p, const NuHost* h, DeviceTables* t) {
     if (t->nu_kb) return VP_OK;
     hipError_t e = upload(&t->nu_lines, h->lines);
     if (e == hipSuccess) e = upload(&t->nu_cs, h->cs);
-    if (e == hipSuccess) e = upload(&t->nu_k, h->k);
+    if (e == hipSuccess) e = upload(&t->nu_kg, h->kg);
+    if (e == hipSuccess) e = upload(&t->nu_kf, h->kf);
     if (e == hipSuccess) e = upload(&t->nu_ph, h->ph);
     if (e == hipSuccess) e = upload(&t->nu_dea, h->dea);
     if (e == hipSuccess) e = upload(&t->nu_kb, h->kb);
@@ -406,8 +407,9 @@ struct NuScope {
     const NuHost* h = nullptr;
     float2* grid = nullptr;
     hipStream_t s;
+    bool persistent = false;  // grids from hipMalloc (a fit), else stream-ordered (an operator call)
     NuArgs d{};
-    explicit NuScope(hipStream_t stream) : s(stream) {}
+    explicit NuScope(hipStream_t stream, bool keep = false) : s(stream), persistent(keep) {}
     vp_status begin(const vp_plan* p, DeviceTables* t) {
         vp_status st = plan_nu(p, &h, &q);
         if (st == VP_OK) st = nu_tables(p, h, t);
@@ -416,10 +418,11 @@ struct NuScope {
         if (st == VP_OK) st = device_layout(q, tq, lq, &dq);
         if (st != VP_OK) return st;
         const size_t bytes = (size_t)p->B * q->n * q->n * sizeof(float2);
-        hipError_t e = hipMallocAsync((void**)&grid, bytes, s);
+        hipError_t e = persistent ? hipMalloc((void**)&grid, bytes) : hipMallocAsync((void**)&grid, bytes, s);
         if (e != hipSuccess) return hip_status(e, "oversampled grids");
         d.n = p->n; d.M = q->n; d.B = p->B; d.lmax = h->lmax; d.nparts = p->nparts; d.kmax = h->kmax;
-        d.lines = t->nu_lines; d.cs = t->nu_cs; d.dea = t->nu_dea; d.kb = t->nu_kb; d.k = t->nu_k; d.ph = t->nu_ph;
+        d.dw = 1.0f;
+        d.lines = t->nu_lines; d.cs = t->nu_cs; d.dea = t->nu_dea; d.kb = t->nu_kb; d.kg = t->nu_kg; d.kf = t->nu_kf; d.ph = t->nu_ph;
         d.blade = t->blade;
         d.grid = grid;
         return VP_OK;
@@ -446,7 +449,13 @@ struct NuScope {
         return launch_rows(a, 1, L.fft_n, L.lds_rows, s);
     }
     ~NuScope() {
-        if (grid) (void)hipFreeAsync(grid, s);
+        if (!grid) return;
+        if (persistent) {
+            (void)hipStreamSynchronize(s);
+            (void)hipFree(grid);
+        } else {
+            (void)hipFreeAsync(grid, s);
+        }
     }
 };
 
@@ -504,6 +513,138 @@ extern "C" vp_status vp_nu_adjoint(const vp_plan* p, const vp_c64* d_samples, vp
     if ((e = launch_gather(a, GATHER_STORE, L.tiles.gath_rows, L.tiles.gath_sc, L.re_gath, sc.s)) != hipSuccess)
         return hip_status(e, "vp_nu_adjoint gather");
     return VP_OK;
+}
+
+// A fit on blade-aligned samples: the session's projection, gather and fused update with
+// the gridding passes in place of the Cartesian DFT passes (all blades every step).
+extern "C" vp_status vp_nu_reconstruct(const vp_plan* p, const vp_options* o, const vp_c64* samples,
+                                       const vp_c64* init, vp_c64* volume_out, vp_c64* proj_out, vp_c64* water_out,
+                                       vp_c64* fat_out, double* final_loss) {
+    clear_error();
+    if (!p || !o || !samples) return fail(VP_ERR_ARG, "vp_nu_reconstruct: NULL argument");
+    vp_status st = check_options(p, o);
+    if (st != VP_OK) return st;
+    if (o->schedule != VP_SCHED_ALL_BLADES)
+        return fail(VP_ERR_UNSUPPORTED, "vp_nu_reconstruct: only the all-blades schedule is supported");
+    const NuHost* h = nullptr;
+    const vp_plan* q = nullptr;
+    if ((st = plan_nu(p, &h, &q)) != VP_OK) return st;
+    const size_t ns = (size_t)p->B * h->lmax * p->n;
+    for (int b = 0; b < p->B; ++b)
+        for (size_t i = (size_t)b * h->lmax * p->n; i < ((size_t)b * h->lmax + p->lines[b]) * p->n; ++i)
+            if (!std::isfinite(samples[i].re) || !std::isfinite(samples[i].im))
+                return fail(VP_ERR_NONFINITE, "vp_nu_reconstruct: samples hold NaN or Inf");
+    hipError_t e = hipSetDevice(o->device);
+    if (e != hipSuccess) return hip_status(e, "hipSetDevice");
+    std::vector<vp_c64> zeros;
+    try {
+        zeros.assign(p->blade_px(), vp_c64{0.f, 0.f});
+    } catch (const std::bad_alloc&) {
+        return fail(VP_ERR_NOMEM, "vp_nu_reconstruct: out of host memory");
+    }
+    vp_session* raw = nullptr;
+    if ((st = session_alloc(p, o, zeros.data(), init, nullptr, &raw)) != VP_OK) return st;
+    std::unique_ptr<vp_session> s(raw);
+    NuScope nu(s->stream, true);
+    if ((st = nu.begin(p, s->tabs)) != VP_OK) return st;
+    float2 *res = nullptr, *ys = nullptr;
+    float* loss = nullptr;
+    const int nblk = nu_interp_blocks(nu.d);
+    struct Bufs {
+        hipStream_t st;
+        std::vector<void*> v;
+        ~Bufs() {
+            (void)hipStreamSynchronize(st);
+            for (void* q : v) (void)hipFree(q);
+        }
+    } bufs{s->stream, {}};
+    e = hipMalloc((void**)&res, ns * sizeof(float2));
+    if (e == hipSuccess) { bufs.v.push_back(res); e = hipMalloc((void**)&ys, ns * sizeof(float2)); }
+    if (e == hipSuccess) { bufs.v.push_back(ys); e = hipMalloc((void**)&loss, nblk * sizeof(float)); }
+    if (e == hipSuccess) bufs.v.push_back(loss);
+    if (e == hipSuccess) e = hipMemcpyAsync(ys, samples, ns * sizeof(float2), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_status(e, "vp_nu_reconstruct buffers");
+    NuArgs& d = nu.d;
+    d.work = s->work;
+    d.img_out = s->work;
+    d.y = ys;
+    d.out = res;
+    d.s_in = res;
+    d.dw = o->data_weight;
+    d.loss = loss;
+    const StageLists& L = s->lists;
+    // forward to the residual (and its loss partials) at the current volume
+    auto forward = [&](hipStream_t str) {
+        KArgs a{};
+        a.one = s->desc;
+        a.tasks = L.proj; a.ntasks = L.n_proj;
+        hipError_t r = launch_project(a, L.tiles.proj_rows, L.tiles.proj_gw, L.re_proj, str);
+        if (r == hipSuccess) r = nu_launch_pad(d, str);
+        if (r == hipSuccess) r = nu.dft(-1);
+        if (r == hipSuccess) r = nu_launch_interp(d, str);
+        return r;
+    };
+    auto step = [&](hipStream_t str) {
+        hipError_t r = forward(str);
+        if (r == hipSuccess) r = nu_launch_spread(d, str);
+        if (r == hipSuccess) r = nu.dft(1);
+        if (r == hipSuccess) r = nu_launch_crop(d, str);
+        KArgs a{};
+        a.one = s->desc;
+        a.epi = L.epi;
+        a.tasks = L.gath; a.ntasks = L.n_gath;
+        if (r == hipSuccess) {
+            if (L.tiles.upd_sc == 0) {
+                r = launch_gather(a, GATHER_STEP, L.tiles.gath_rows, L.tiles.gath_sc, L.re_gath, str);
+            } else {
+                r = launch_gather(a, GATHER_STORE, L.tiles.gath_rows, L.tiles.gath_sc, L.re_gath, str);
+                a.tasks = L.upd; a.ntasks = L.n_upd;
+                if (r == hipSuccess) r = launch_update(a, L.tiles.upd_sc, str);
+            }
+        }
+        if (r == hipSuccess) r = launch_advance(a, 1, str);
+        return r;
+    };
+    const int n_steps = o->n_steps;
+    if (n_steps > 1) {
+        e = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal);
+        hipError_t le = e == hipSuccess ? step(s->stream) : e;
+        hipGraph_t g = nullptr;
+        const hipError_t ce = hipStreamEndCapture(s->stream, &g);
+        if (e == hipSuccess) e = le != hipSuccess ? le : ce;
+        if (e == hipSuccess) e = hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0);
+        s->graph = g;
+        for (int i = 0; i < n_steps && e == hipSuccess; ++i) e = hipGraphLaunch(s->gexec, s->stream);
+    } else if (n_steps == 1) {
+        e = step(s->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_status(e, "vp_nu_reconstruct steps");
+    s->steps_done = n_steps;
+    if (final_loss) {
+        e = forward(s->stream);
+        KArgs a{};
+        a.one = s->desc;
+        a.tasks = L.vox; a.ntasks = L.n_vox; a.dpart = s->dpart;
+        if (e == hipSuccess) e = launch_reg_value(a, s->stream);
+        std::vector<float> hl(nblk);
+        std::vector<double> hd(2 * p->t_vox.size());
+        if (e == hipSuccess) e = hipMemcpyAsync(hl.data(), loss, nblk * sizeof(float), hipMemcpyDeviceToHost, s->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(hd.data(), s->dpart, hd.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) return hip_status(e, "vp_nu_reconstruct objective");
+        double data = 0.0, tv = 0.0, l1 = 0.0;
+        for (float v : hl) data += (double)v;
+        for (size_t i = 0; i < p->t_vox.size(); ++i) {
+            tv += hd[2 * i];
+            l1 += hd[2 * i + 1];
+        }
+        *final_loss = 0.5 * (double)o->data_weight * data + (double)o->tv_weight * tv + (double)o->l1_weight * l1;
+        if (!std::isfinite(*final_loss)) return fail(VP_ERR_NONFINITE, "vp_nu_reconstruct: objective is not finite");
+    }
+    return session_read(s.get(), volume_out, proj_out, water_out, fat_out);
 }
 
 extern "C" vp_status vp_tv_grad(const vp_plan* p, const vp_c64* d_vol, float tv_w, float l1_w, float eps,

@@ -115,3 +115,52 @@ def test_too_large_for_the_oversampled_grid(gpu_lib):
     with pytest.raises(B.VPError) as ex:
         B.vp_nu_forward(plan, vol)
     assert ex.value.status == B.VP_ERR_UNSUPPORTED
+
+
+FIT_CASES = {
+    "static_48": dict(n=48, n_spec=4, n_blades=4, lines=12),
+    "dynamic_40": dict(n=40, n_spec=3, n_time=3, n_blades=5, lines=10),
+}
+
+
+@pytest.mark.parametrize("name,optimizer,steps", [
+    ("static_48", 1, 8),
+    ("static_48", 0, 10),
+    ("dynamic_40", 1, 8),
+    ("dynamic_40", 0, 8),
+])
+def test_fit_on_blade_samples_matches_the_oracle(gpu_lib, name, optimizer, steps):
+    # the oracle fits with the same gridding (FP64, exact kernel); the GPU's tabulated FP32
+    # kernel and FP32 sample offsets move each operator by about 1e-6 relative, and Adam's
+    # normalisation amplifies that on small gradients: a short fit stays below 1e-3
+    from paper_2311_13177_amd import binding as B
+
+    case = configs.small_case(**FIT_CASES[name])
+    geom = O.Geometry.from_dict(case.geometry())
+    plan = B.Plan.from_geometry(case.geometry())
+    y = N.simulate_samples(case)
+    lr = 1e-2 if optimizer == 0 else 0.5 / (case.n_spec * case.n_blades)
+    opts = B.vp_options_default(n_steps=steps, optimizer=optimizer, lr=lr, l1_weight=1e-4, data_weight=1.25)
+    got = B.vp_nu_reconstruct(plan, _pack(y, B.nu_shape(plan)).astype(np.complex64), opts)
+    want = N.reconstruct_nu(geom, y, steps, tv_weight=opts.tv_weight, tv_eps=opts.tv_eps, l1_weight=opts.l1_weight,
+                            lr=opts.lr, beta1=opts.beta1, beta2=opts.beta2, adam_eps=opts.adam_eps,
+                            optimizer="adam" if optimizer == 0 else "gd", exact=False,
+                            data_weight=opts.data_weight, split_bin=opts.split_bin)
+    for k in ("vol", "proj", "water", "fat"):
+        assert _rel(got[k], want[k]) < 1e-3, k
+    assert abs(got["final_loss"] - want["final_loss"]) <= 1e-3 * abs(want["final_loss"])
+
+
+def test_fit_rejects_other_schedules_and_bad_samples(gpu_lib):
+    from paper_2311_13177_amd import binding as B
+
+    case = configs.small_case(**FIT_CASES["static_48"])
+    plan = B.Plan.from_geometry(case.geometry())
+    y = _pack(N.simulate_samples(case), B.nu_shape(plan)).astype(np.complex64)
+    with pytest.raises(B.VPError) as ex:
+        B.vp_nu_reconstruct(plan, y, B.vp_options_default(n_steps=2, schedule=B.VP_SCHED_CYCLIC))
+    assert ex.value.status == B.VP_ERR_UNSUPPORTED
+    y[1, 3, 5] = np.nan
+    with pytest.raises(B.VPError) as ex:
+        B.vp_nu_reconstruct(plan, y, B.vp_options_default(n_steps=2))
+    assert ex.value.status == B.VP_ERR_NONFINITE

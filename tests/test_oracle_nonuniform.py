@@ -100,3 +100,20 @@ def test_axis_aligned_gradient_is_the_cartesian_gradient():
     g, val = N.gradient_nu(vol, geom, y)
     gc, vc = O.gradient(vol, geom, ygrid, 0.0, 1e-3)
     assert np.allclose(g, gc, atol=1e-11) and math.isclose(val, vc, rel_tol=1e-12)
+
+
+def test_fit_on_axis_aligned_blades_is_the_cartesian_fit():
+    # with blades at 0 and 90 degrees the blade-aligned fit is the Cartesian fit
+    rng = np.random.default_rng(6)
+    n = 12
+    geom = _geom(n=n, angles=(0.0, math.pi / 2), lines=(4, 6))
+    masks = O.blade_masks(geom)
+    ygrid = masks * _crandn(rng, 2, n, n)
+    y = []
+    for b in range(2):
+        kx, ky = N.blade_samples(n, float(geom.angle_rad[b]), int(geom.lines[b]))
+        y.append(ygrid[b][np.rint(ky).astype(int) % n, np.rint(kx).astype(int) % n])
+    a = N.reconstruct_nu(geom, y, 4, tv_weight=0.01, data_weight=1.5)
+    c = O.reconstruct(geom, ygrid, 4, tv_weight=0.01, data_weight=1.5)
+    assert np.allclose(a["vol"], c["vol"], atol=1e-10)
+    assert math.isclose(a["final_loss"], c["final_loss"], rel_tol=1e-10)
