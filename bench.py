@@ -42,6 +42,7 @@ def parse_args(argv=None):
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain-loop leg")
     ap.add_argument("--no-kplanes", action="store_true", help="skip the K-Planes dynamic model leg")
     ap.add_argument("--no-dynamic", action="store_true", help="skip the dynamic 192^2 x 32 x 16 leg")
+    ap.add_argument("--no-nu", action="store_true", help="skip the blade-aligned sampling fit leg")
     ap.add_argument("--batch-slices", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--no-serve", action="store_true", help="skip the served-stream leg")
@@ -224,6 +225,79 @@ def kplanes_leg(B, steps, warmup):
                          "kernel_ms": round(heavy[dom], 5), "algorithmic_flops_per_launch": fl},
             "quality": {"psnr_db": round(float(np.mean(p_fit)), 2), "frames": int(len(case.blade_time)),
                         "steps": case.n_steps, "model": KP_MODEL}}
+
+
+def gpu_samples(case, plan, B):
+    """Blade-aligned samples y_b = A_b(P_b V_GT(tau_b)) + sigma n_b[:L_b] with the HIP
+    gridding forward model, [B][Lmax][n] (lines beyond L_b zero)."""
+    import numpy as np
+    import torch
+
+    from synth.phantom import ground_truth_volume
+
+    S = case.n_spec
+    shp = B.nu_shape(plan)
+    y = np.zeros(shp, dtype=np.complex64)
+    for b in range(case.n_blades):
+        t = 0.0 if case.n_time == 1 else float(case.blade_time[b])
+        pb = B.Plan(case.n, S, 1, case.angle_rad[b:b + 1], case.lines[b:b + 1], None, case.spec_shift_px)
+        w, f = case.layers_at(t)
+        gt = torch.from_numpy(ground_truth_volume(w, f, S)[None].astype(np.complex64)).cuda()
+        L = int(case.lines[b])
+        y[b, :L] = B.vp_nu_forward(pb, gt).cpu().numpy()[0, :L] + case.sigma * case.noise[b][:L, :]
+    return y
+
+
+def nu_leg(B, name, steps, warmup):
+    """The fit on blade-aligned samples (gridding in place of the masked Cartesian DFT) on a
+    workload's geometry: step throughput, per-stage times, the HBM roofline of the dominant
+    stage and the PSNR of the fit against the phantom."""
+    import numpy as np
+    import torch
+
+    from synth import configs
+
+    case = configs.CONFIGS[name]()
+    plan = B.Plan.from_geometry(case.geometry())
+    y = gpu_samples(case, plan, B)
+    opts = B.vp_options_default(**configs.config_options(case), device=0)
+    sess = B.NuSession(plan, y, opts)
+    sess.step(warmup, use_graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sess.step(steps, use_graph=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    stages = sess.stage_times(max(3, steps // 4))
+    sess.close()
+    # algorithmic HBM bytes per launch of each gridding stage (complex64 = 8 bytes): the
+    # B (2n)^2 grids once in and once out per DFT pass pair, once out of pad and spread and
+    # once into interp and crop; per sample interp reads y, base, fraction and phase and
+    # writes the residual, spread reads residual, base, fraction and phase
+    n, Bn = case.n, case.n_blades
+    M2 = (2 * n) ** 2
+    ns = Bn * int(np.max(case.lines)) * n
+    parts = 2 if case.n_time > 1 else 1
+    per = {"pad": 8 * Bn * (M2 + parts * n * n), "dft_fwd": 4 * 8 * Bn * M2, "interp": 8 * Bn * M2 + 40 * ns,
+           "spread": 8 * Bn * M2 + 32 * ns, "dft_inv": 4 * 8 * Bn * M2, "crop": 8 * Bn * (M2 // 4 + n * n)}
+    dom = max(per, key=lambda k: stages[k])
+    ach = per[dom] / (stages[dom] * 1e-3) / 1e9
+    # quality: a whole fit from zero at the workload's step count
+    r = B.vp_nu_reconstruct(plan, y, opts)
+    if case.n_time == 1:
+        truth = np.asarray(sum(case.layers_at(0.0)), dtype=np.complex64)[None]
+    else:
+        truth = np.stack([sum(case.layers_at(k / (case.n_time - 1))) for k in range(case.n_time)])
+    p_fit = B.vp_psnr(torch.from_numpy(r["proj"]).cuda(),
+                      torch.from_numpy(truth.astype(np.complex64)).cuda())[0].cpu().numpy()
+    return {"workload": f"{name} geometry, blade-aligned samples (Kaiser-Bessel gridding, width 6, grid 2n)",
+            "value": round(case.n_blades * steps / el, 1), "unit": "blade fwd+adjoint/s",
+            "ms_per_step": round(el * 1e3 / steps, 5), "steps": steps,
+            "stage_ms": {k: round(v, 5) for k, v in stages.items()},
+            "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                         "kernel_ms": round(stages[dom], 5), "algorithmic_bytes_per_launch": per[dom]},
+            "quality": {"psnr_db": round(float(np.mean(p_fit)), 2), "steps": case.n_steps}}
 
 
 def served_leg(B, n_req, steps_static, steps_dynamic, seed=5000, slots=8):
@@ -474,6 +548,8 @@ def main(argv=None):
         out["dynamic_192"] = d
     if not args.no_kplanes:
         out["kplanes_192"] = kplanes_leg(B, max(20, args.steps // 8), 3)
+    if not args.no_nu:
+        out["nu_256"] = nu_leg(B, "static_256", max(20, args.steps // 4), 3)
     if not args.no_batch:
         out["batched"] = batched_leg(B, args.batch_slices, args.batch_steps)
     if not args.no_serve:

@@ -68,6 +68,7 @@ typedef struct vp_plan vp_plan;
 typedef struct vp_session vp_session;
 typedef struct vp_server vp_server;
 typedef struct vp_kplanes_session vp_kplanes_session;
+typedef struct vp_nu_session vp_nu_session;
 
 /* Acquisition geometry (Section 4.2 "Projection" and "Blur").
  *   n              image side; the grid is n x n and each blade's readout has n
@@ -244,15 +245,35 @@ vp_status vp_nu_forward(const vp_plan* plan, const vp_c64* d_vol, const vp_c64* 
 vp_status vp_nu_adjoint(const vp_plan* plan, const vp_c64* d_samples, vp_c64* d_grad, int32_t accumulate,
                         void* stream);
 
-/* The fit of Section 4.3 on blade-aligned samples: vp_reconstruct with the gridding
- * passes above in place of the masked Cartesian DFT (projection, fused gather and
- * update, regularisers, schedule of steps and outputs as there). samples: host
- * [B][Lmax][n] (the layout above; lines l >= L_b ignored). init, outputs and
- * final_loss as in vp_reconstruct; final_loss = 0.5 data_weight sum |r|^2 + TV + L1 at
- * the returned volume. Only VP_SCHED_ALL_BLADES (VP_ERR_UNSUPPORTED otherwise);
+/* The fit of Section 4.3 on blade-aligned samples, as a resident session: the Cartesian
+ * session's projection, fused gather and update, regularisers and step counter, with
+ * the gridding passes above in place of the masked Cartesian DFT. samples: host
+ * [B][Lmax][n] (the layout above; lines l >= L_b ignored); init as in
+ * vp_session_create. Only VP_SCHED_ALL_BLADES (VP_ERR_UNSUPPORTED otherwise);
  * VP_ERR_NONFINITE if a used sample is NaN or Inf; VP_ERR_UNSUPPORTED if 2n is above
- * 512. Blocking; device memory is the session's plus B (2n)^2 complex values and two
- * sample arrays, all freed on return. */
+ * 512. Device memory: the Cartesian session's plus B (2n)^2 complex values and two
+ * sample arrays, freed by vp_nu_session_destroy. */
+vp_status vp_nu_session_create(const vp_plan* plan, const vp_options* opts, const vp_c64* samples,
+                               const vp_c64* init, vp_nu_session** out);
+
+/* n_steps optimiser steps (use_graph != 0: one captured step replayed), then waits. */
+vp_status vp_nu_session_step(vp_nu_session* session, int32_t n_steps, int32_t use_graph);
+
+/* Profiling: n_steps more steps eagerly with a HIP event around every stage; mean
+ * milliseconds to stage_ms[8]: projection, pad, forward DFT of the grids,
+ * interpolation (residual and loss partials), spread, inverse DFT, crop, and the
+ * gather with the regulariser gradient, update and step counter. */
+vp_status vp_nu_session_stage_times(vp_nu_session* session, int32_t n_steps, double* stage_ms);
+
+/* Current volume and renders to host buffers (any may be NULL) and, if objective is
+ * not NULL, 0.5 data_weight sum |r|^2 + TV + L1 at the current volume. */
+vp_status vp_nu_session_read(vp_nu_session* session, vp_c64* volume_out, vp_c64* proj_out, vp_c64* water_out,
+                             vp_c64* fat_out, double* objective);
+
+vp_status vp_nu_session_destroy(vp_nu_session* session);
+
+/* One synchronous fit on blade-aligned samples: create, opts->n_steps steps, read
+ * (final_loss is the objective there), destroy. */
 vp_status vp_nu_reconstruct(const vp_plan* plan, const vp_options* opts, const vp_c64* samples, const vp_c64* init,
                             vp_c64* volume_out, vp_c64* proj_out, vp_c64* water_out, vp_c64* fat_out,
                             double* final_loss);

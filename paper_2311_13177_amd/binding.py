@@ -115,6 +115,11 @@ _PROTOS = {
     "vp_nu_forward": (c_int32, [_P, _P, _P, _P, _P]),
     "vp_nu_adjoint": (c_int32, [_P, _P, _P, c_int32, _P]),
     "vp_nu_reconstruct": (c_int32, [_P, POINTER(vp_options), _P, _P, _P, _P, _P, _P, POINTER(c_double)]),
+    "vp_nu_session_create": (c_int32, [_P, POINTER(vp_options), _P, _P, POINTER(c_void_p)]),
+    "vp_nu_session_step": (c_int32, [_P, c_int32, c_int32]),
+    "vp_nu_session_stage_times": (c_int32, [_P, c_int32, POINTER(c_double)]),
+    "vp_nu_session_read": (c_int32, [_P, _P, _P, _P, _P, POINTER(c_double)]),
+    "vp_nu_session_destroy": (c_int32, [_P]),
     "vp_psnr": (c_int32, [_P, _P, c_int64, c_int32, _P, _P]),
     "vp_session_create": (c_int32, [_P, POINTER(vp_options), _P, _P, POINTER(_P)]),
     "vp_session_step": (c_int32, [_P, c_int32, c_int32]),
@@ -397,6 +402,53 @@ def vp_nu_reconstruct(plan: Plan, samples: np.ndarray, opts: Optional[vp_options
     check(lib().vp_nu_reconstruct(plan.handle, byref(opts), _hp(y), _hp(i), _hp(vol), *[_hp(o) for o in outs],
                                   byref(loss)))
     return dict(vol=vol, proj=outs[0], water=outs[1], fat=outs[2], final_loss=float(loss.value))
+
+
+NU_STAGES = ("project", "pad", "dft_fwd", "interp", "spread", "dft_inv", "crop", "gather_update")
+
+
+class NuSession:
+    """Resident fit on blade-aligned samples [B][Lmax][n] (vp_nu_session_*)."""
+
+    def __init__(self, plan: Plan, samples: np.ndarray, opts: Optional[vp_options] = None,
+                 init: Optional[np.ndarray] = None):
+        self.plan = plan
+        self.opts = opts if opts is not None else vp_options_default()
+        y = _host_c64(samples, nu_shape(plan))
+        i = _host_c64(init, plan.volume_shape)
+        h = c_void_p()
+        check(lib().vp_nu_session_create(plan.handle, byref(self.opts), _hp(y), _hp(i), byref(h)))
+        self.handle = h
+
+    def step(self, n_steps: int, use_graph: bool = True) -> None:
+        check(lib().vp_nu_session_step(self.handle, int(n_steps), int(bool(use_graph))))
+
+    def stage_times(self, n_steps: int = 10) -> dict:
+        ms = (c_double * len(NU_STAGES))()
+        check(lib().vp_nu_session_stage_times(self.handle, int(n_steps), ms))
+        return dict(zip(NU_STAGES, list(ms)))
+
+    def read(self, objective: bool = False) -> dict:
+        vol = np.empty(self.plan.volume_shape, np.complex64)
+        outs = [np.empty(self.plan.render_shape, np.complex64) for _ in range(3)]
+        obj = c_double()
+        check(lib().vp_nu_session_read(self.handle, _hp(vol), *[_hp(o) for o in outs],
+                                       byref(obj) if objective else None))
+        res = dict(vol=vol, proj=outs[0], water=outs[1], fat=outs[2])
+        if objective:
+            res["objective"] = obj.value
+        return res
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            lib().vp_nu_session_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def vp_baseline(plan: Plan, kspace, window: int = 0, first_frame: Optional[int] = None,

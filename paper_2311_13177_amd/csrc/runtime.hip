@@ -517,79 +517,67 @@ extern "C" vp_status vp_nu_adjoint(const vp_plan* p, const vp_c64* d_samples, vp
 
 // A fit on blade-aligned samples: the session's projection, gather and fused update with
 // the gridding passes in place of the Cartesian DFT passes (all blades every step).
-extern "C" vp_status vp_nu_reconstruct(const vp_plan* p, const vp_options* o, const vp_c64* samples,
-                                       const vp_c64* init, vp_c64* volume_out, vp_c64* proj_out, vp_c64* water_out,
-                                       vp_c64* fat_out, double* final_loss) {
-    clear_error();
-    if (!p || !o || !samples) return fail(VP_ERR_ARG, "vp_nu_reconstruct: NULL argument");
-    vp_status st = check_options(p, o);
-    if (st != VP_OK) return st;
-    if (o->schedule != VP_SCHED_ALL_BLADES)
-        return fail(VP_ERR_UNSUPPORTED, "vp_nu_reconstruct: only the all-blades schedule is supported");
-    const NuHost* h = nullptr;
-    const vp_plan* q = nullptr;
-    if ((st = plan_nu(p, &h, &q)) != VP_OK) return st;
-    const size_t ns = (size_t)p->B * h->lmax * p->n;
-    for (int b = 0; b < p->B; ++b)
-        for (size_t i = (size_t)b * h->lmax * p->n; i < ((size_t)b * h->lmax + p->lines[b]) * p->n; ++i)
-            if (!std::isfinite(samples[i].re) || !std::isfinite(samples[i].im))
-                return fail(VP_ERR_NONFINITE, "vp_nu_reconstruct: samples hold NaN or Inf");
-    hipError_t e = hipSetDevice(o->device);
-    if (e != hipSuccess) return hip_status(e, "hipSetDevice");
-    std::vector<vp_c64> zeros;
-    try {
-        zeros.assign(p->blade_px(), vp_c64{0.f, 0.f});
-    } catch (const std::bad_alloc&) {
-        return fail(VP_ERR_NOMEM, "vp_nu_reconstruct: out of host memory");
+// ------------------------------------------------------------------ fits on blade-aligned samples
+
+namespace {
+constexpr int kNuStages = 8;  // project, pad, forward DFT, interp, spread, inverse DFT, crop, gather+update
+}
+
+// A Cartesian session (volume, optimiser state, projection and gather lists, step counter)
+// whose data term runs through the gridding passes: per step project, pad, forward DFT,
+// interpolate minus the samples (with loss partials), spread, inverse DFT, crop, then the
+// fused gather with the regulariser gradient and update, and the counter.
+struct vp_nu_session {
+    std::unique_ptr<vp_session> s;
+    NuScope nu;
+    float2* res = nullptr;  // residual samples [B][Lmax][n]
+    float2* ys = nullptr;   // measured samples [B][Lmax][n]
+    float* loss = nullptr;  // per-block sums of |residual|^2 of the last forward pass
+    int nblk = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    explicit vp_nu_session(vp_session* raw) : s(raw), nu(raw->stream, true) {}
+    ~vp_nu_session() {
+        (void)hipSetDevice(s->device);
+        (void)hipStreamSynchronize(s->stream);
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        void* bufs[] = {res, ys, loss};
+        for (void* q : bufs)
+            if (q) (void)hipFree(q);
     }
-    vp_session* raw = nullptr;
-    if ((st = session_alloc(p, o, zeros.data(), init, nullptr, &raw)) != VP_OK) return st;
-    std::unique_ptr<vp_session> s(raw);
-    NuScope nu(s->stream, true);
-    if ((st = nu.begin(p, s->tabs)) != VP_OK) return st;
-    float2 *res = nullptr, *ys = nullptr;
-    float* loss = nullptr;
-    const int nblk = nu_interp_blocks(nu.d);
-    struct Bufs {
-        hipStream_t st;
-        std::vector<void*> v;
-        ~Bufs() {
-            (void)hipStreamSynchronize(st);
-            for (void* q : v) (void)hipFree(q);
-        }
-    } bufs{s->stream, {}};
-    e = hipMalloc((void**)&res, ns * sizeof(float2));
-    if (e == hipSuccess) { bufs.v.push_back(res); e = hipMalloc((void**)&ys, ns * sizeof(float2)); }
-    if (e == hipSuccess) { bufs.v.push_back(ys); e = hipMalloc((void**)&loss, nblk * sizeof(float)); }
-    if (e == hipSuccess) bufs.v.push_back(loss);
-    if (e == hipSuccess) e = hipMemcpyAsync(ys, samples, ns * sizeof(float2), hipMemcpyHostToDevice, s->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-    if (e != hipSuccess) return hip_status(e, "vp_nu_reconstruct buffers");
-    NuArgs& d = nu.d;
-    d.work = s->work;
-    d.img_out = s->work;
-    d.y = ys;
-    d.out = res;
-    d.s_in = res;
-    d.dw = o->data_weight;
-    d.loss = loss;
-    const StageLists& L = s->lists;
-    // forward to the residual (and its loss partials) at the current volume
-    auto forward = [&](hipStream_t str) {
+
+    // projection to residual samples (and their loss partials) at the current volume;
+    // ev (may be null) gets events 0..3 before the first four stages
+    hipError_t forward(hipEvent_t* ev) {
+        const StageLists& L = s->lists;
+        const hipStream_t str = s->stream;
         KArgs a{};
         a.one = s->desc;
         a.tasks = L.proj; a.ntasks = L.n_proj;
-        hipError_t r = launch_project(a, L.tiles.proj_rows, L.tiles.proj_gw, L.re_proj, str);
-        if (r == hipSuccess) r = nu_launch_pad(d, str);
+        hipError_t r = ev ? hipEventRecord(ev[0], str) : hipSuccess;
+        if (r == hipSuccess) r = launch_project(a, L.tiles.proj_rows, L.tiles.proj_gw, L.re_proj, str);
+        if (r == hipSuccess && ev) r = hipEventRecord(ev[1], str);
+        if (r == hipSuccess) r = nu_launch_pad(nu.d, str);
+        if (r == hipSuccess && ev) r = hipEventRecord(ev[2], str);
         if (r == hipSuccess) r = nu.dft(-1);
-        if (r == hipSuccess) r = nu_launch_interp(d, str);
+        if (r == hipSuccess && ev) r = hipEventRecord(ev[3], str);
+        if (r == hipSuccess) r = nu_launch_interp(nu.d, str);
         return r;
-    };
-    auto step = [&](hipStream_t str) {
-        hipError_t r = forward(str);
-        if (r == hipSuccess) r = nu_launch_spread(d, str);
+    }
+
+    // one optimiser step; ev (may be null) gets kNuStages + 1 events around the stages
+    hipError_t step(hipEvent_t* ev) {
+        const StageLists& L = s->lists;
+        const hipStream_t str = s->stream;
+        hipError_t r = forward(ev);
+        if (r == hipSuccess && ev) r = hipEventRecord(ev[4], str);
+        if (r == hipSuccess) r = nu_launch_spread(nu.d, str);
+        if (r == hipSuccess && ev) r = hipEventRecord(ev[5], str);
         if (r == hipSuccess) r = nu.dft(1);
-        if (r == hipSuccess) r = nu_launch_crop(d, str);
+        if (r == hipSuccess && ev) r = hipEventRecord(ev[6], str);
+        if (r == hipSuccess) r = nu_launch_crop(nu.d, str);
+        if (r == hipSuccess && ev) r = hipEventRecord(ev[7], str);
         KArgs a{};
         a.one = s->desc;
         a.epi = L.epi;
@@ -604,47 +592,162 @@ extern "C" vp_status vp_nu_reconstruct(const vp_plan* p, const vp_options* o, co
             }
         }
         if (r == hipSuccess) r = launch_advance(a, 1, str);
+        if (r == hipSuccess && ev) r = hipEventRecord(ev[kNuStages], str);
         return r;
-    };
-    const int n_steps = o->n_steps;
-    if (n_steps > 1) {
-        e = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal);
-        hipError_t le = e == hipSuccess ? step(s->stream) : e;
-        hipGraph_t g = nullptr;
-        const hipError_t ce = hipStreamEndCapture(s->stream, &g);
-        if (e == hipSuccess) e = le != hipSuccess ? le : ce;
-        if (e == hipSuccess) e = hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0);
-        s->graph = g;
-        for (int i = 0; i < n_steps && e == hipSuccess; ++i) e = hipGraphLaunch(s->gexec, s->stream);
-    } else if (n_steps == 1) {
-        e = step(s->stream);
     }
-    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-    if (e != hipSuccess) return hip_status(e, "vp_nu_reconstruct steps");
-    s->steps_done = n_steps;
-    if (final_loss) {
-        e = forward(s->stream);
+};
+
+extern "C" vp_status vp_nu_session_create(const vp_plan* p, const vp_options* o, const vp_c64* samples,
+                                          const vp_c64* init, vp_nu_session** out) {
+    clear_error();
+    if (!p || !o || !samples || !out) return fail(VP_ERR_ARG, "vp_nu_session_create: NULL argument");
+    *out = nullptr;
+    vp_status st = check_options(p, o);
+    if (st != VP_OK) return st;
+    if (o->schedule != VP_SCHED_ALL_BLADES)
+        return fail(VP_ERR_UNSUPPORTED, "vp_nu_session_create: only the all-blades schedule is supported");
+    const NuHost* h = nullptr;
+    const vp_plan* q = nullptr;
+    if ((st = plan_nu(p, &h, &q)) != VP_OK) return st;
+    const size_t ns = (size_t)p->B * h->lmax * p->n;
+    for (int b = 0; b < p->B; ++b)
+        for (size_t i = (size_t)b * h->lmax * p->n; i < ((size_t)b * h->lmax + p->lines[b]) * p->n; ++i)
+            if (!std::isfinite(samples[i].re) || !std::isfinite(samples[i].im))
+                return fail(VP_ERR_NONFINITE, "vp_nu_session_create: samples hold NaN or Inf");
+    hipError_t e = hipSetDevice(o->device);
+    if (e != hipSuccess) return hip_status(e, "hipSetDevice");
+    std::vector<vp_c64> zeros;
+    try {
+        zeros.assign(p->blade_px(), vp_c64{0.f, 0.f});
+    } catch (const std::bad_alloc&) {
+        return fail(VP_ERR_NOMEM, "vp_nu_session_create: out of host memory");
+    }
+    vp_session* raw = nullptr;
+    if ((st = session_alloc(p, o, zeros.data(), init, nullptr, &raw)) != VP_OK) return st;
+    std::unique_ptr<vp_nu_session> ns_(new (std::nothrow) vp_nu_session(raw));
+    if (!ns_) {
+        delete raw;
+        return fail(VP_ERR_NOMEM, "vp_nu_session_create: out of host memory");
+    }
+    vp_nu_session* x = ns_.get();
+    if ((st = x->nu.begin(p, x->s->tabs)) != VP_OK) return st;
+    x->nblk = nu_interp_blocks(x->nu.d);
+    e = hipMalloc((void**)&x->res, ns * sizeof(float2));
+    if (e == hipSuccess) e = hipMalloc((void**)&x->ys, ns * sizeof(float2));
+    if (e == hipSuccess) e = hipMalloc((void**)&x->loss, x->nblk * sizeof(float));
+    if (e == hipSuccess) e = hipMemcpyAsync(x->ys, samples, ns * sizeof(float2), hipMemcpyHostToDevice, x->s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(x->s->stream);
+    if (e != hipSuccess) return hip_status(e, "vp_nu_session_create buffers");
+    NuArgs& d = x->nu.d;
+    d.work = x->s->work;
+    d.img_out = x->s->work;
+    d.y = x->ys;
+    d.out = x->res;
+    d.s_in = x->res;
+    d.dw = o->data_weight;
+    d.loss = x->loss;
+    *out = ns_.release();
+    return VP_OK;
+}
+
+extern "C" vp_status vp_nu_session_step(vp_nu_session* x, int32_t n_steps, int32_t use_graph) {
+    clear_error();
+    if (!x || n_steps < 0) return fail(VP_ERR_ARG, "vp_nu_session_step: bad argument");
+    hipError_t e = hipSetDevice(x->s->device);
+    if (e != hipSuccess) return hip_status(e, "hipSetDevice");
+    const hipStream_t str = x->s->stream;
+    if (use_graph && n_steps > 1 && !x->gexec) {
+        e = hipStreamBeginCapture(str, hipStreamCaptureModeThreadLocal);
+        const hipError_t le = e == hipSuccess ? x->step(nullptr) : e;
+        hipGraph_t g = nullptr;
+        const hipError_t ce = hipStreamEndCapture(str, &g);
+        if (e == hipSuccess) e = le != hipSuccess ? le : ce;
+        x->graph = g;
+        if (e == hipSuccess) e = hipGraphInstantiate(&x->gexec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) return hip_status(e, "vp_nu_session_step capture");
+    }
+    for (int i = 0; i < n_steps && e == hipSuccess; ++i)
+        e = (use_graph && x->gexec) ? hipGraphLaunch(x->gexec, str) : x->step(nullptr);
+    if (e == hipSuccess) e = hipStreamSynchronize(str);
+    if (e != hipSuccess) return hip_status(e, "vp_nu_session_step");
+    x->s->steps_done += n_steps;
+    return VP_OK;
+}
+
+extern "C" vp_status vp_nu_session_stage_times(vp_nu_session* x, int32_t n_steps, double* stage_ms) {
+    clear_error();
+    if (!x || !stage_ms || n_steps < 1) return fail(VP_ERR_ARG, "vp_nu_session_stage_times: bad argument");
+    hipError_t e = hipSetDevice(x->s->device);
+    if (e != hipSuccess) return hip_status(e, "hipSetDevice");
+    std::vector<hipEvent_t> ev((size_t)n_steps * (kNuStages + 1), nullptr);
+    for (auto& v : ev)
+        if (e == hipSuccess) e = hipEventCreate(&v);
+    for (int k = 0; k < n_steps && e == hipSuccess; ++k) e = x->step(&ev[(size_t)k * (kNuStages + 1)]);
+    if (e == hipSuccess) e = hipStreamSynchronize(x->s->stream);
+    for (int i = 0; i < kNuStages; ++i) stage_ms[i] = 0.0;
+    for (int k = 0; k < n_steps && e == hipSuccess; ++k)
+        for (int i = 0; i < kNuStages && e == hipSuccess; ++i) {
+            float ms = 0.f;
+            e = hipEventElapsedTime(&ms, ev[(size_t)k * (kNuStages + 1) + i], ev[(size_t)k * (kNuStages + 1) + i + 1]);
+            stage_ms[i] += ms / n_steps;
+        }
+    for (auto& v : ev)
+        if (v) (void)hipEventDestroy(v);
+    if (e != hipSuccess) return hip_status(e, "vp_nu_session_stage_times");
+    x->s->steps_done += n_steps;
+    return VP_OK;
+}
+
+extern "C" vp_status vp_nu_session_read(vp_nu_session* x, vp_c64* volume_out, vp_c64* proj_out, vp_c64* water_out,
+                                        vp_c64* fat_out, double* objective) {
+    clear_error();
+    if (!x) return fail(VP_ERR_ARG, "vp_nu_session_read: NULL session");
+    hipError_t e = hipSetDevice(x->s->device);
+    if (e != hipSuccess) return hip_status(e, "hipSetDevice");
+    if (objective) {
+        vp_session* s = x->s.get();
+        const vp_plan* p = s->plan;
+        e = x->forward(nullptr);
         KArgs a{};
         a.one = s->desc;
-        a.tasks = L.vox; a.ntasks = L.n_vox; a.dpart = s->dpart;
+        a.tasks = s->lists.vox; a.ntasks = s->lists.n_vox; a.dpart = s->dpart;
         if (e == hipSuccess) e = launch_reg_value(a, s->stream);
-        std::vector<float> hl(nblk);
+        std::vector<float> hl(x->nblk);
         std::vector<double> hd(2 * p->t_vox.size());
-        if (e == hipSuccess) e = hipMemcpyAsync(hl.data(), loss, nblk * sizeof(float), hipMemcpyDeviceToHost, s->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(hl.data(), x->loss, x->nblk * sizeof(float), hipMemcpyDeviceToHost, s->stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(hd.data(), s->dpart, hd.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-        if (e != hipSuccess) return hip_status(e, "vp_nu_reconstruct objective");
+        if (e != hipSuccess) return hip_status(e, "vp_nu_session_read objective");
         double data = 0.0, tv = 0.0, l1 = 0.0;
         for (float v : hl) data += (double)v;
         for (size_t i = 0; i < p->t_vox.size(); ++i) {
             tv += hd[2 * i];
             l1 += hd[2 * i + 1];
         }
-        *final_loss = 0.5 * (double)o->data_weight * data + (double)o->tv_weight * tv + (double)o->l1_weight * l1;
-        if (!std::isfinite(*final_loss)) return fail(VP_ERR_NONFINITE, "vp_nu_reconstruct: objective is not finite");
+        const vp_options& o = s->opts;
+        *objective = 0.5 * (double)o.data_weight * data + (double)o.tv_weight * tv + (double)o.l1_weight * l1;
+        if (!std::isfinite(*objective)) return fail(VP_ERR_NONFINITE, "vp_nu_session_read: objective is not finite");
     }
-    return session_read(s.get(), volume_out, proj_out, water_out, fat_out);
+    return session_read(x->s.get(), volume_out, proj_out, water_out, fat_out);
+}
+
+extern "C" vp_status vp_nu_session_destroy(vp_nu_session* x) {
+    delete x;
+    return VP_OK;
+}
+
+extern "C" vp_status vp_nu_reconstruct(const vp_plan* p, const vp_options* o, const vp_c64* samples,
+                                       const vp_c64* init, vp_c64* volume_out, vp_c64* proj_out, vp_c64* water_out,
+                                       vp_c64* fat_out, double* final_loss) {
+    vp_nu_session* x = nullptr;
+    vp_status st = vp_nu_session_create(p, o, samples, init, &x);
+    if (st != VP_OK) return st;
+    st = vp_nu_session_step(x, o->n_steps, 1);
+    if (st == VP_OK) st = vp_nu_session_read(x, volume_out, proj_out, water_out, fat_out, final_loss);
+    (void)vp_nu_session_destroy(x);
+    return st;
 }
 
 extern "C" vp_status vp_tv_grad(const vp_plan* p, const vp_c64* d_vol, float tv_w, float l1_w, float eps,

@@ -164,3 +164,25 @@ def test_fit_rejects_other_schedules_and_bad_samples(gpu_lib):
     with pytest.raises(B.VPError) as ex:
         B.vp_nu_reconstruct(plan, y, B.vp_options_default(n_steps=2))
     assert ex.value.status == B.VP_ERR_NONFINITE
+
+
+def test_session_steps_in_parts_equal_one_fit(gpu_lib):
+    # eager and graph-replayed steps, and steps under stage timing, run the same kernels on
+    # the same data in the same order: bit for bit the one-shot fit
+    from paper_2311_13177_amd import binding as B
+
+    case = configs.small_case(**FIT_CASES["dynamic_40"])
+    plan = B.Plan.from_geometry(case.geometry())
+    y = _pack(N.simulate_samples(case), B.nu_shape(plan)).astype(np.complex64)
+    opts = B.vp_options_default(n_steps=9, lr=1e-2, l1_weight=1e-4)
+    one = B.vp_nu_reconstruct(plan, y, opts)
+    sess = B.NuSession(plan, y, opts)
+    sess.step(2, use_graph=False)
+    sess.step(4, use_graph=True)
+    st = sess.stage_times(3)
+    got = sess.read(objective=True)
+    sess.close()
+    assert set(st) == set(B.NU_STAGES) and all(v > 0 for v in st.values())
+    for k in ("vol", "proj", "water", "fat"):
+        assert np.array_equal(got[k], one[k]), k
+    assert got["objective"] == one["final_loss"]
