@@ -270,16 +270,17 @@ def nu_leg(B, name, steps, warmup):
     el = time.perf_counter() - t0
     stages = sess.stage_times(max(3, steps // 4))
     sess.close()
-    # algorithmic HBM bytes per launch of each gridding stage (complex64 = 8 bytes): the
-    # B (2n)^2 grids once in and once out per DFT pass pair, once out of pad and spread and
-    # once into interp and crop; per sample interp reads y, base, fraction and phase and
-    # writes the residual, spread reads residual, base, fraction and phase
+    # algorithmic HBM bytes per launch of each gridding stage (complex64 = 8 bytes): a DFT
+    # of the B (2n)^2 grids reads and writes the n image rows in its row pass and the whole
+    # grid in its column pass (3 grids' worth each way); pad and spread write the grids
+    # once, interp reads them once, crop reads the image's quarter; per sample interp reads
+    # y, base, fraction and phase and writes the residual, spread reads all but y
     n, Bn = case.n, case.n_blades
     M2 = (2 * n) ** 2
     ns = Bn * int(np.max(case.lines)) * n
     parts = 2 if case.n_time > 1 else 1
-    per = {"pad": 8 * Bn * (M2 + parts * n * n), "dft_fwd": 4 * 8 * Bn * M2, "interp": 8 * Bn * M2 + 40 * ns,
-           "spread": 8 * Bn * M2 + 32 * ns, "dft_inv": 4 * 8 * Bn * M2, "crop": 8 * Bn * (M2 // 4 + n * n)}
+    per = {"pad": 8 * Bn * (M2 + parts * n * n), "dft_fwd": 3 * 8 * Bn * M2, "interp": 8 * Bn * M2 + 40 * ns,
+           "spread": 8 * Bn * M2 + 32 * ns, "dft_inv": 3 * 8 * Bn * M2, "crop": 8 * Bn * (M2 // 4 + n * n)}
     dom = max(per, key=lambda k: stages[k])
     ach = per[dom] / (stages[dom] * 1e-3) / 1e9
     # quality: a whole fit from zero at the workload's step count

@@ -333,6 +333,12 @@ vp_status plan_nu(const vp_plan* p, const NuHost** host, const vp_plan** over) {
             const double t = (double)i / kNuTable;  // u / (W / 2)
             h->kb[i] = (float)bessel_i0(beta * std::sqrt(std::max(0.0, 1.0 - t * t)));
         }
+        // the centred image occupies grid rows [0, n - n/2) and [M - n/2, M): the other
+        // rows are zero before the forward row pass and unread after the inverse one
+        for (const Task& tk : p->over->t_rows) {
+            const int r0 = tk.b, r1 = std::min(M, r0 + fft_rows_per_item(M));
+            if (r0 < n - n / 2 || r1 > M - n / 2) h->rows.push_back(tk);
+        }
         p->nu_host = std::move(h);
     }
     *host = p->nu_host.get();

@@ -66,6 +66,7 @@ struct DeviceTables {
     float2* nu_ph = nullptr;
     float* nu_dea = nullptr;
     float* nu_kb = nullptr;
+    Task* nu_rows = nullptr;
     ~DeviceTables();
 };
 
@@ -77,6 +78,7 @@ struct NuHost {
     std::vector<float2> cs, kf, ph;  // [B], [B][lmax][n], [B][lmax][n]
     std::vector<int2> kg;            // [B][lmax][n]
     std::vector<float> dea, kb;      // [n], [kNuTable + 1]
+    std::vector<Task> rows;          // row-pass tasks of the oversampled plan that touch the image's rows
 };
 
 }  // namespace vp

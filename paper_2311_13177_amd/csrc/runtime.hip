@@ -30,7 +30,7 @@ DeviceTables::~DeviceTables() {
     if (device >= 0) (void)hipSetDevice(device);
     layouts.clear();
     void* ptrs[] = {mask, shear, blade, knot_ptr, knot_ent, knot_tap, knots, tw, t_rows, t_cols, t_vox, t_render,
-                    nu_lines, nu_cs, nu_kg, nu_kf, nu_ph, nu_dea, nu_kb};
+                    nu_lines, nu_cs, nu_kg, nu_kf, nu_ph, nu_dea, nu_kb, nu_rows};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (prev >= 0) (void)hipSetDevice(prev);
@@ -391,6 +391,7 @@ vp_status nu_tables(const vp_plan* p, const NuHost* h, DeviceTables* t) {
     if (e == hipSuccess) e = upload(&t->nu_ph, h->ph);
     if (e == hipSuccess) e = upload(&t->nu_dea, h->dea);
     if (e == hipSuccess) e = upload(&t->nu_kb, h->kb);
+    if (e == hipSuccess) e = upload(&t->nu_rows, h->rows);
     return hip_status(e, "blade sampling tables");
 }
 
@@ -406,6 +407,7 @@ struct NuScope {
     const DeviceLayout* dq = nullptr;
     const NuHost* h = nullptr;
     float2* grid = nullptr;
+    const Task* t_img_rows = nullptr;  // row-pass tasks over the image's rows only
     hipStream_t s;
     bool persistent = false;  // grids from hipMalloc (a fit), else stream-ordered (an operator call)
     NuArgs d{};
@@ -425,6 +427,7 @@ struct NuScope {
         d.lines = t->nu_lines; d.cs = t->nu_cs; d.dea = t->nu_dea; d.kb = t->nu_kb; d.kg = t->nu_kg; d.kf = t->nu_kf; d.ph = t->nu_ph;
         d.blade = t->blade;
         d.grid = grid;
+        t_img_rows = t->nu_rows;
         return VP_OK;
     }
     // unscaled 2D DFT of the grids in place: forward (dir -1) or inverse (dir +1)
@@ -435,9 +438,11 @@ struct NuScope {
         a.in0 = grid;
         a.out0 = grid;
         hipError_t e;
+        const Task* rows = t_img_rows;
+        const int nrows = (int)h->rows.size();
         if (dir < 0) {
             a.mode = COL_RAW_FWD;
-            a.tasks = L.rows; a.ntasks = L.n_rows;
+            a.tasks = rows; a.ntasks = nrows;
             if ((e = launch_rows(a, -1, L.fft_n, L.lds_rows, s)) != hipSuccess) return e;
             a.tasks = L.cols; a.ntasks = L.n_cols;
             return launch_cols(a, L.fft_n, L.lds_cols, s);
@@ -445,7 +450,7 @@ struct NuScope {
         a.mode = COL_INVERSE;
         a.tasks = L.cols; a.ntasks = L.n_cols;
         if ((e = launch_cols(a, L.fft_n, L.lds_cols, s)) != hipSuccess) return e;
-        a.tasks = L.rows; a.ntasks = L.n_rows;
+        a.tasks = rows; a.ntasks = nrows;
         return launch_rows(a, 1, L.fft_n, L.lds_rows, s);
     }
     ~NuScope() {
