@@ -61,38 +61,84 @@ __global__ __launch_bounds__(kThreads) void k_nu_pad(const NuArgs d) {
     }
 }
 
-// out[b][l][j] = (sum over the grid points within W/2 of 2k of C C grid) * phase / n - y;
-// with d.loss, each block also writes the sum of |out|^2 over its samples (fixed order)
+// Sample (j, l) of blade b in grid units: kNuSigma (r u_b + q n_b), r = j - n/2,
+// q = l - L_b/2, in FP64 (exact to far below FP32's rounding of an offset). The
+// interpolation and the spread evaluate this same expression, so a (sample, grid point)
+// pair gets the same offsets, the same inclusion test and the same weights in both.
+__device__ __forceinline__ double2 sample_pos(double2 cs, int j, int l, int n, int L) {
+    const double r = (double)j - 0.5 * (double)n, q = (double)l - 0.5 * (double)L;
+    return make_double2((double)kNuSigma * (r * cs.x - q * cs.y), (double)kNuSigma * (r * cs.y + q * cs.x));
+}
+
+// Grid points m0..m1 along one axis with |g - m| <= h as evaluated in FP64 (the test the
+// spread applies): ceil/floor of g -+ h, moved by one where rounding puts them off.
+__device__ __forceinline__ void axis_window(double g, double h, int& m0, int& m1) {
+    m0 = (int)ceil(g - h);
+    m1 = (int)floor(g + h);
+    if (fabs(g - (double)(m0 - 1)) <= h) --m0;
+    else if (fabs(g - (double)m0) > h) ++m0;
+    if (fabs(g - (double)(m1 + 1)) <= h) ++m1;
+    else if (fabs(g - (double)m1) > h) --m1;
+}
+
+// Lanes per sample in k_nu_interp: one per grid row of the window (at most 7 rows).
+constexpr int kRowLanes = 8;
+constexpr int kSamplesPerBlock = kThreads / kRowLanes;
+
+// out[b][l][j] = (sum over the grid points within W/2 of 2k of C C grid) * phase / n - y.
+// Each sample has kRowLanes lanes; lane r sums the window's r-th grid row (and r + 8, ...)
+// times its row weight, and the sample's first lane adds the lanes' partials in lane
+// order. With d.loss, each block also writes the sum of |out|^2 over its samples (fixed
+// order).
 __global__ __launch_bounds__(kThreads) void k_nu_interp(const NuArgs d) {
+    __shared__ float2 part[kThreads];
     __shared__ float red[kThreads];
     float lsum = 0.f;
     const int n = d.n, M = d.M;
     const long long per = (long long)d.lmax * n;
     const long long total = (long long)d.B * per;
-    const float h = 0.5f * kNuWidth;
-    for (long long e = gtid(); e < total; e += gstride()) {
-        const int b = (int)(e / per);
-        const int l = (int)((e % per) / n);
-        float2 v = make_float2(0.f, 0.f);
-        if (l < d.lines[b]) {
-            // offsets to grid point m: (kg - m) + kf, exact integer plus fraction
-            const int2 kg = d.kg[e];
-            const float2 kf = d.kf[e];
-            const int x0 = kg.x + (int)ceilf(kf.x - h), x1 = kg.x + (int)floorf(kf.x + h);
-            const int y0 = kg.y + (int)ceilf(kf.y - h), y1 = kg.y + (int)floorf(kf.y + h);
-            const float2* g = d.grid + (long long)b * M * M;
-            for (int my = y0; my <= y1; ++my) {
-                const float cy = kb(d.kb, (float)(kg.y - my) + kf.y);
-                const float2* row = g + (long long)wrap(my, M) * M;
-                float2 r = make_float2(0.f, 0.f);
-                for (int mx = x0; mx <= x1; ++mx) r = cfma(kb(d.kb, (float)(kg.x - mx) + kf.x), row[wrap(mx, M)], r);
-                v = cfma(cy, r, v);
-            }
-            v = cmul(v, d.ph[e]);
-            if (d.y) v = csub(v, d.y[e]);
+    const double h = 0.5 * (double)kNuWidth;
+    const int sub = threadIdx.x % kRowLanes, slot = threadIdx.x / kRowLanes;
+    // block-uniform loop: every lane reaches every barrier
+    for (long long base = (long long)blockIdx.x * kSamplesPerBlock; base < total;
+         base += (long long)gridDim.x * kSamplesPerBlock) {
+        const long long e = base + slot;
+        int L = 0, b = 0, l = 0, j = 0;
+        if (e < total) {
+            b = (int)(e / per);
+            l = (int)((e % per) / n);
+            j = (int)(e % n);
+            L = d.lines[b];
         }
-        d.out[e] = v;
-        lsum = __builtin_fmaf(v.x, v.x, __builtin_fmaf(v.y, v.y, lsum));
+        float2 acc = make_float2(0.f, 0.f);
+        if (e < total && l < L) {
+            const double2 g = sample_pos(d.cs[b], j, l, n, L);
+            int x0, x1, y0, y1;
+            axis_window(g.x, h, x0, x1);
+            axis_window(g.y, h, y0, y1);
+            const float2* grid = d.grid + (long long)b * M * M;
+            for (int my = y0 + sub; my <= y1; my += kRowLanes) {
+                const float cy = kb(d.kb, (float)(g.y - (double)my));
+                const float2* row = grid + (long long)wrap(my, M) * M;
+                float2 r = make_float2(0.f, 0.f);
+                for (int mx = x0; mx <= x1; ++mx) r = cfma(kb(d.kb, (float)(g.x - (double)mx)), row[wrap(mx, M)], r);
+                acc = cfma(cy, r, acc);
+            }
+        }
+        part[threadIdx.x] = acc;
+        __syncthreads();
+        if (sub == 0 && e < total) {
+            float2 v = make_float2(0.f, 0.f);
+            if (l < L) {
+#pragma unroll
+                for (int r = 0; r < kRowLanes; ++r) v = cadd(v, part[threadIdx.x + r]);
+                v = cmul(v, d.ph[e]);
+                if (d.y) v = csub(v, d.y[e]);
+            }
+            d.out[e] = v;
+            lsum = __builtin_fmaf(v.x, v.x, __builtin_fmaf(v.y, v.y, lsum));
+        }
+        __syncthreads();
     }
     if (d.loss) {
         red[threadIdx.x] = lsum;
@@ -105,48 +151,62 @@ __global__ __launch_bounds__(kThreads) void k_nu_interp(const NuArgs d) {
     }
 }
 
+// Readout range [lo, hi] of line q whose samples can lie within H (lattice units) of
+// (X, Y) along one grid axis: |r a + q b - Z| <= H with (a, b) = (c, -s) for x and
+// (s, c) for y (ia = 1/a). Returns false when no r can.
+__device__ __forceinline__ bool axis_range(double a, double ia, double bq, double Z, double H, double& lo,
+                                           double& hi) {
+    if (fabs(a) < 1e-12) return fabs(bq - Z) <= H + 1e-9;
+    const double u = (Z - bq - H) * ia, w = (Z - bq + H) * ia;
+    lo = fmax(lo, fmin(u, w));
+    hi = fmin(hi, fmax(u, w));
+    return true;
+}
+
 // grid[b][gy][gx] = sum over the samples within W/2 (in both axes) of 2k - (gx, gy), at
-// every wrap of the grid point, of C C s conj(phase): the transpose of k_nu_interp.
+// every wrap of the grid point, of C C s conj(phase): the transpose of k_nu_interp. The
+// samples near a point are found from the lattice: the lines within reach, and on each
+// the readout interval that meets both axis windows.
 __global__ __launch_bounds__(kThreads) void k_nu_spread(const NuArgs d) {
     const int n = d.n, M = d.M;
     const long long MM = (long long)M * M;
     const long long total = (long long)d.B * MM;
-    const float h = 0.5f * kNuWidth;
-    // lattice half-window: the W x W box around a grid point, in lattice units
-    const float hw = h / (float)kNuSigma * 1.41421356f + 1e-3f;
+    const double h = 0.5 * (double)kNuWidth;
+    const double H = h / (double)kNuSigma;  // the window's half-width in lattice units
     for (long long e = gtid(); e < total; e += gstride()) {
         const int b = (int)(e / MM);
         const int py = (int)((e % MM) / M), px = (int)(e % M);
-        const float c = d.cs[b].x, s = d.cs[b].y;
+        const double2 cs = d.cs[b];
+        const double c = cs.x, s = cs.y;
+        const double ic = fabs(c) < 1e-12 ? 0.0 : 1.0 / c, is = fabs(s) < 1e-12 ? 0.0 : 1.0 / s;
         const int L = d.lines[b];
-        const int2* kg = d.kg + (long long)b * d.lmax * n;
-        const float2* kf = d.kf + (long long)b * d.lmax * n;
+        const double qh = H * (fabs(c) + fabs(s)) + 1e-9;
         const float2* sv = d.s_in + (long long)b * d.lmax * n;
         const float2* ph = d.ph + (long long)b * d.lmax * n;
         float2 acc = make_float2(0.f, 0.f);
         for (int ty = -1; ty <= 1; ++ty) {
             const int Py = py + ty * M;
-            if ((float)abs(Py) > d.kmax + h) continue;
+            if ((float)abs(Py) > d.kmax + (float)h) continue;
             for (int tx = -1; tx <= 1; ++tx) {
                 const int Px = px + tx * M;
-                if ((float)abs(Px) > d.kmax + h) continue;
-                const float kx = (float)Px / (float)kNuSigma, ky = (float)Py / (float)kNuSigma;
-                const float r0 = kx * c + ky * s + 0.5f * (float)n;   // readout index of the point
-                const float q0 = -kx * s + ky * c + 0.5f * (float)L;  // line index of the point
-                const int j0 = max(0, (int)ceilf(r0 - hw)), j1 = min(n - 1, (int)floorf(r0 + hw));
-                const int l0 = max(0, (int)ceilf(q0 - hw)), l1 = min(L - 1, (int)floorf(q0 + hw));
+                if ((float)abs(Px) > d.kmax + (float)h) continue;
+                const double X = (double)Px / (double)kNuSigma, Y = (double)Py / (double)kNuSigma;
+                const double q0 = -X * s + Y * c + 0.5 * (double)L;  // line index of the point
+                const int l0 = max(0, (int)ceil(q0 - qh)), l1 = min(L - 1, (int)floor(q0 + qh));
                 for (int l = l0; l <= l1; ++l) {
+                    const double q = (double)l - 0.5 * (double)L;
+                    double lo = -1e30, hi = 1e30;
+                    if (!axis_range(c, ic, -q * s, X, H, lo, hi) || !axis_range(s, is, q * c, Y, H, lo, hi)) continue;
+                    const int j0 = max(0, (int)ceil(lo + 0.5 * (double)n - 1e-9));
+                    const int j1 = min(n - 1, (int)floor(hi + 0.5 * (double)n + 1e-9));
                     for (int j = j0; j <= j1; ++j) {
-                        const long long i = (long long)l * n + j;
-                        // the offsets k_nu_interp weighs this pair with, bit for bit
-                        const int2 g = kg[i];
-                        const float2 f = kf[i];
-                        const float dx = (float)(g.x - Px) + f.x;
-                        const float dy = (float)(g.y - Py) + f.y;
-                        if (fabsf(dx) <= h && fabsf(dy) <= h) {
+                        const double2 g = sample_pos(cs, j, l, n, L);
+                        const double dx = g.x - (double)Px, dy = g.y - (double)Py;
+                        if (fabs(dx) <= h && fabs(dy) <= h) {
+                            const int i = l * n + j;
                             const float2 p = ph[i];
                             const float2 v = cscale(cmul(sv[i], make_float2(p.x, -p.y)), d.dw);
-                            acc = cfma(kb(d.kb, dy) * kb(d.kb, dx), v, acc);
+                            acc = cfma(kb(d.kb, (float)dy) * kb(d.kb, (float)dx), v, acc);
                         }
                     }
                 }
@@ -181,7 +241,7 @@ hipError_t nu_launch_pad(const NuArgs& d, hipStream_t s) {
     hipLaunchKernelGGL(k_nu_pad, dim3(grid_of((long long)d.B * d.M * d.M)), dim3(kThreads), 0, s, d);
     return hipGetLastError();
 }
-int nu_interp_blocks(const NuArgs& d) { return (int)grid_of((long long)d.B * d.lmax * d.n); }
+int nu_interp_blocks(const NuArgs& d) { return (int)grid_of((long long)d.B * d.lmax * d.n * kRowLanes); }
 hipError_t nu_launch_interp(const NuArgs& d, hipStream_t s) {
     hipLaunchKernelGGL(k_nu_interp, dim3(nu_interp_blocks(d)), dim3(kThreads), 0, s, d);
     return hipGetLastError();

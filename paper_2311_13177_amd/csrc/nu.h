@@ -11,11 +11,9 @@ struct NuArgs {
     int n, M, B, lmax, nparts;
     float kmax;             // bound on |kNuSigma k| over every sample (grid units)
     const int* lines;       // [B]
-    const float2* cs;       // [B] (cos, sin) of the blade angle
+    const double2* cs;      // [B] (cos, sin) of the blade angle, FP64
     const float* dea;       // [n] 1 / (kernel transform) at the centred index x - n/2
     const float* kb;        // [kNuTable + 1] kernel on [0, W/2]
-    const int2* kg;         // [B][lmax][n] floor(kNuSigma k): the grid point below each sample
-    const float2* kf;       // [B][lmax][n] kNuSigma k - kg, in [0, 1)
     const float2* ph;       // [B][lmax][n] exp(-i pi (kx + ky) 2 floor(n/2) / n) / n
     const BladeDev* blade;  // knot blend of dynamic blades (pad)
     const float2* work;     // projection parts [B][nparts][n][n] (pad)

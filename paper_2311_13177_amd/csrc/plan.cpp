@@ -294,25 +294,17 @@ vp_status plan_nu(const vp_plan* p, const NuHost** host, const vp_plan** over) {
         h->lines = p->lines;
         h->lmax = *std::max_element(p->lines.begin(), p->lines.end());
         h->cs.resize(B);
-        h->kg.assign((size_t)B * h->lmax * n, make_int2(0, 0));
-        h->kf.assign((size_t)B * h->lmax * n, make_float2(0.f, 0.f));
         h->ph.assign((size_t)B * h->lmax * n, make_float2(0.f, 0.f));
         const double half = (double)(2 * (n / 2)) / n;
         double kmax = 0.0;
         for (int b = 0; b < B; ++b) {
             const double c = std::cos(p->angle[b]), s = std::sin(p->angle[b]);
-            h->cs[b] = make_float2((float)c, (float)s);
+            h->cs[b] = make_double2(c, s);
             for (int l = 0; l < p->lines[b]; ++l)
                 for (int j = 0; j < n; ++j) {
                     const double r = j - 0.5 * n, q = l - 0.5 * p->lines[b];
                     const double kx = r * c - q * s, ky = r * s + q * c;
                     const size_t i = ((size_t)b * h->lmax + l) * n + j;
-                    // sigma k as an integer grid point plus a fraction in [0, 1): the
-                    // kernel offsets then carry FP32's relative precision of the fraction,
-                    // not of the position
-                    const double gx = std::floor(sig * kx), gy = std::floor(sig * ky);
-                    h->kg[i] = make_int2((int)gx, (int)gy);
-                    h->kf[i] = make_float2((float)(sig * kx - gx), (float)(sig * ky - gy));
                     const double a = -M_PI * (kx + ky) * half;
                     h->ph[i] = make_float2((float)(std::cos(a) / n), (float)(std::sin(a) / n));
                     kmax = std::max(kmax, std::max(std::fabs(sig * kx), std::fabs(sig * ky)));

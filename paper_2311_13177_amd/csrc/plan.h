@@ -60,9 +60,7 @@ struct DeviceTables {
     std::map<int, std::unique_ptr<DeviceLayout>> layouts;  // by Tiles::key()
     // blade-aligned sampling tables (uploaded on first use)
     int* nu_lines = nullptr;
-    float2* nu_cs = nullptr;
-    int2* nu_kg = nullptr;
-    float2* nu_kf = nullptr;
+    double2* nu_cs = nullptr;
     float2* nu_ph = nullptr;
     float* nu_dea = nullptr;
     float* nu_kb = nullptr;
@@ -75,8 +73,8 @@ struct NuHost {
     int lmax = 0;
     float kmax = 0.f;
     std::vector<int> lines;
-    std::vector<float2> cs, kf, ph;  // [B], [B][lmax][n], [B][lmax][n]
-    std::vector<int2> kg;            // [B][lmax][n]
+    std::vector<double2> cs;         // [B]
+    std::vector<float2> ph;          // [B][lmax][n]
     std::vector<float> dea, kb;      // [n], [kNuTable + 1]
     std::vector<Task> rows;          // row-pass tasks of the oversampled plan that touch the image's rows
 };

@@ -30,7 +30,7 @@ DeviceTables::~DeviceTables() {
     if (device >= 0) (void)hipSetDevice(device);
     layouts.clear();
     void* ptrs[] = {mask, shear, blade, knot_ptr, knot_ent, knot_tap, knots, tw, t_rows, t_cols, t_vox, t_render,
-                    nu_lines, nu_cs, nu_kg, nu_kf, nu_ph, nu_dea, nu_kb, nu_rows};
+                    nu_lines, nu_cs, nu_ph, nu_dea, nu_kb, nu_rows};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (prev >= 0) (void)hipSetDevice(prev);
@@ -386,8 +386,6 @@ vp_status nu_tables(const vp_plan* p, const NuHost* h, DeviceTables* t) {
     if (t->nu_kb) return VP_OK;
     hipError_t e = upload(&t->nu_lines, h->lines);
     if (e == hipSuccess) e = upload(&t->nu_cs, h->cs);
-    if (e == hipSuccess) e = upload(&t->nu_kg, h->kg);
-    if (e == hipSuccess) e = upload(&t->nu_kf, h->kf);
     if (e == hipSuccess) e = upload(&t->nu_ph, h->ph);
     if (e == hipSuccess) e = upload(&t->nu_dea, h->dea);
     if (e == hipSuccess) e = upload(&t->nu_kb, h->kb);
@@ -424,7 +422,7 @@ struct NuScope {
         if (e != hipSuccess) return hip_status(e, "oversampled grids");
         d.n = p->n; d.M = q->n; d.B = p->B; d.lmax = h->lmax; d.nparts = p->nparts; d.kmax = h->kmax;
         d.dw = 1.0f;
-        d.lines = t->nu_lines; d.cs = t->nu_cs; d.dea = t->nu_dea; d.kb = t->nu_kb; d.kg = t->nu_kg; d.kf = t->nu_kf; d.ph = t->nu_ph;
+        d.lines = t->nu_lines; d.cs = t->nu_cs; d.dea = t->nu_dea; d.kb = t->nu_kb;  d.ph = t->nu_ph;
         d.blade = t->blade;
         d.grid = grid;
         t_img_rows = t->nu_rows;
