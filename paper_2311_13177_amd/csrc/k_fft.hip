@@ -201,6 +201,7 @@ __device__ void fft_rows_any(float2* buf, const float2* tw, int n, int nstage, i
         case 256: ct_fft<DIR, false, 256, fft_rows_per_item(256)>(buf, tw); break;
         case 320: ct_fft<DIR, false, 320, fft_rows_per_item(320)>(buf, tw); break;
         case 384: ct_fft<DIR, false, 384, fft_rows_per_item(384)>(buf, tw); break;
+        case 512: ct_fft<DIR, false, 512, fft_rows_per_item(512)>(buf, tw); break;
         default: lds_fft<DIR, false, 8>(buf, tw, n, fft_rows_per_item(n), n, 1, nstage, code); break;
     }
 }
@@ -217,6 +218,7 @@ __device__ void fft_cols_any(float2* buf, const float2* tw, int n, int nstage, i
         case 256: ct_fft<DIR, true, 256, fft_cols_per_item(256)>(buf, tw); break;
         case 320: ct_fft<DIR, true, 320, fft_cols_per_item(320)>(buf, tw); break;
         case 384: ct_fft<DIR, true, 384, fft_cols_per_item(384)>(buf, tw); break;
+        case 512: ct_fft<DIR, true, 512, fft_cols_per_item(512)>(buf, tw); break;
         default: {
             const int cb = fft_cols_per_item(n);
             lds_fft<DIR, true, 16>(buf, tw, n, cb, 1, cb, nstage, code);
@@ -323,6 +325,8 @@ __global__ __launch_bounds__(kThreads) void k_cols(const KArgs a) {
         const uint8_t* mk = DF(mask) + (size_t)b * nn;
         const float2* yy = DF(y);
         const float2* yb = (yy && !from_in) ? yy + (size_t)b * nn : nullptr;
+        // rows of a centred image of size live_n (all rows when 0)
+        const int lv = raw ? a.live_n : 0, lv_lo = lv - lv / 2, lv_hi = n - lv / 2;
         for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = twg[i];
         for (int i = threadIdx.x; i < n * cb; i += blockDim.x) {
             const int y = i / cb, c = i - (i / cb) * cb;
@@ -330,13 +334,20 @@ __global__ __launch_bounds__(kThreads) void k_cols(const KArgs a) {
             uint8_t m = 0;
             if (c < cols) {
                 const size_t gi = (size_t)y * n + c0 + c;
-                v = src[gi];
-                m = mk[gi];
-                if (yb) w = yb[gi];
+                if (raw) {
+                    // a raw forward pass of a centred image reads only its rows
+                    if (a.mode == COL_INVERSE || lv == 0 || y < lv_lo || y >= lv_hi) v = src[gi];
+                } else {
+                    v = src[gi];
+                    m = mk[gi];
+                    if (yb) w = yb[gi];
+                }
             }
             A[i] = v;
-            Y[i] = w;
-            M[i] = m;
+            if (!raw) {
+                Y[i] = w;
+                M[i] = m;
+            }
         }
         __syncthreads();
         if (!from_in || a.mode == COL_RAW_FWD) fft_cols_any<-1, NC>(A, tw, n, nstage, code);
@@ -370,9 +381,11 @@ __global__ __launch_bounds__(kThreads) void k_cols(const KArgs a) {
         __syncthreads();
         if (a.mode != COL_FORWARD) {
             if (a.mode != COL_RAW_FWD) fft_cols_any<1, NC>(A, tw, n, nstage, code);
+            // a raw inverse pass feeding a centred crop writes only its rows
+            const bool all = a.mode != COL_INVERSE || lv == 0;
             for (int i = threadIdx.x; i < n * cb; i += blockDim.x) {
                 const int y = i / cb, c = i - (i / cb) * cb;
-                if (c < cols) dst[(size_t)y * n + c0 + c] = A[i];
+                if (c < cols && (all || y < lv_lo || y >= lv_hi)) dst[(size_t)y * n + c0 + c] = A[i];
             }
         }
         if (a.mode == COL_STEP) {
@@ -401,7 +414,7 @@ hipError_t launch_rows(const KArgs& a, int dir, int n, size_t lds, hipStream_t s
         else hipLaunchKernelGGL((k_rows<1, N>), g, b, lds, s, a);                  \
         break
     switch (n) {
-        RV(64); RV(128); RV(192); RV(256); RV(320); RV(384);
+        RV(64); RV(128); RV(192); RV(256); RV(320); RV(384); RV(512);
         default: RV(0);
     }
 #undef RV
@@ -415,7 +428,7 @@ hipError_t launch_cols(const KArgs& a, int n, size_t lds, hipStream_t s) {
         hipLaunchKernelGGL((k_cols<N>), g, b, lds, s, a);      \
         break
     switch (n) {
-        CV(64); CV(128); CV(192); CV(256); CV(320); CV(384);
+        CV(64); CV(128); CV(192); CV(256); CV(320); CV(384); CV(512);
         default: CV(0);
     }
 #undef CV

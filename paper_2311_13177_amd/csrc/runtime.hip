@@ -435,6 +435,7 @@ struct NuScope {
         const StageLists L = plan_lists(q, tq, lq, dq);
         a.in0 = grid;
         a.out0 = grid;
+        a.live_n = d.n;
         hipError_t e;
         const Task* rows = t_img_rows;
         const int nrows = (int)h->rows.size();

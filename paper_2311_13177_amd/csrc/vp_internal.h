@@ -147,6 +147,9 @@ struct KArgs {
     const float2* in0;
     double* dpart;
     int epi;                     // optimiser epilogue of GATHER_STEP and the update pass (EPI_*)
+    int live_n;                  // COL_RAW_FWD / COL_INVERSE: 0, or the size m of a centred image
+                                 // in the frame: only rows [0, m - m/2) and [n - m/2, n) are
+                                 // nonzero on input (forward) or needed on output (inverse)
 };
 
 // Column pass modes.
