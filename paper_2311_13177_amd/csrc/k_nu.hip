@@ -17,12 +17,16 @@ namespace {
 __device__ __forceinline__ long long gtid() { return (long long)blockIdx.x * blockDim.x + threadIdx.x; }
 __device__ __forceinline__ long long gstride() { return (long long)gridDim.x * blockDim.x; }
 
-// Kernel value at offset u (grid units) from the table over [0, W/2]; 0 beyond W/2.
+// Kernel value at offset u (grid units) from the table over [0, W/2]; 0 beyond W/2 (and
+// for NaN). Branch-free, so the loads of several lookups and of the data they weigh
+// can be in flight together.
 __device__ __forceinline__ float kb(const float* tab, float u) {
     const float a = fabsf(u) * ((float)kNuTable / (0.5f * kNuWidth));
-    if (!(a <= (float)kNuTable)) return 0.f;
-    const int i = min((int)a, kNuTable - 1);
-    return __builtin_fmaf(a - (float)i, tab[i + 1] - tab[i], tab[i]);
+    const bool in = a <= (float)kNuTable;
+    const float ac = in ? a : 0.f;
+    const int i = min((int)ac, kNuTable - 1);
+    const float v = __builtin_fmaf(ac - (float)i, tab[i + 1] - tab[i], tab[i]);
+    return in ? v : 0.f;
 }
 
 __device__ __forceinline__ int wrap(int m, int M) { return ((m % M) + M) % M; }
@@ -128,14 +132,17 @@ __global__ __launch_bounds__(kThreads) void k_nu_interp(const NuArgs d) {
         part[threadIdx.x] = acc;
         __syncthreads();
         if (sub == 0 && e < total) {
-            float2 v = make_float2(0.f, 0.f);
+            float2 v = make_float2(0.f, 0.f), w = v;
             if (l < L) {
 #pragma unroll
                 for (int r = 0; r < kRowLanes; ++r) v = cadd(v, part[threadIdx.x + r]);
-                v = cmul(v, d.ph[e]);
+                const float2 p = d.ph[e];
+                v = cmul(v, p);
                 if (d.y) v = csub(v, d.y[e]);
+                w = cscale(cmul(v, make_float2(p.x, -p.y)), d.dw);
             }
             d.out[e] = v;
+            if (d.pre) d.pre[e] = w;
             lsum = __builtin_fmaf(v.x, v.x, __builtin_fmaf(v.y, v.y, lsum));
         }
         __syncthreads();
@@ -181,8 +188,7 @@ __global__ __launch_bounds__(kThreads) void k_nu_spread(const NuArgs d) {
         const double ic = fabs(c) < 1e-12 ? 0.0 : 1.0 / c, is = fabs(s) < 1e-12 ? 0.0 : 1.0 / s;
         const int L = d.lines[b];
         const double qh = H * (fabs(c) + fabs(s)) + 1e-9;
-        const float2* sv = d.s_in + (long long)b * d.lmax * n;
-        const float2* ph = d.ph + (long long)b * d.lmax * n;
+        const float2* sv = d.pre + (long long)b * d.lmax * n;
         float2 acc = make_float2(0.f, 0.f);
         for (int ty = -1; ty <= 1; ++ty) {
             const int Py = py + ty * M;
@@ -203,16 +209,28 @@ __global__ __launch_bounds__(kThreads) void k_nu_spread(const NuArgs d) {
                         const double2 g = sample_pos(cs, j, l, n, L);
                         const double dx = g.x - (double)Px, dy = g.y - (double)Py;
                         if (fabs(dx) <= h && fabs(dy) <= h) {
-                            const int i = l * n + j;
-                            const float2 p = ph[i];
-                            const float2 v = cscale(cmul(sv[i], make_float2(p.x, -p.y)), d.dw);
-                            acc = cfma(kb(d.kb, (float)dy) * kb(d.kb, (float)dx), v, acc);
+                            acc = cfma(kb(d.kb, (float)dy) * kb(d.kb, (float)dx), sv[l * n + j], acc);
                         }
                     }
                 }
             }
         }
         d.grid[e] = acc;
+    }
+}
+
+// pre[b][l][j] = dw conj(phase) s_in (0 on lines l >= L_b)
+__global__ __launch_bounds__(kThreads) void k_nu_prep(const NuArgs d) {
+    const long long per = (long long)d.lmax * d.n;
+    const long long total = (long long)d.B * per;
+    for (long long e = gtid(); e < total; e += gstride()) {
+        const int b = (int)(e / per), l = (int)((e % per) / d.n);
+        float2 w = make_float2(0.f, 0.f);
+        if (l < d.lines[b]) {
+            const float2 p = d.ph[e];
+            w = cscale(cmul(d.s_in[e], make_float2(p.x, -p.y)), d.dw);
+        }
+        d.pre[e] = w;
     }
 }
 
@@ -244,6 +262,10 @@ hipError_t nu_launch_pad(const NuArgs& d, hipStream_t s) {
 int nu_interp_blocks(const NuArgs& d) { return (int)grid_of((long long)d.B * d.lmax * d.n * kRowLanes); }
 hipError_t nu_launch_interp(const NuArgs& d, hipStream_t s) {
     hipLaunchKernelGGL(k_nu_interp, dim3(nu_interp_blocks(d)), dim3(kThreads), 0, s, d);
+    return hipGetLastError();
+}
+hipError_t nu_launch_prep(const NuArgs& d, hipStream_t s) {
+    hipLaunchKernelGGL(k_nu_prep, dim3(grid_of((long long)d.B * d.lmax * d.n)), dim3(kThreads), 0, s, d);
     return hipGetLastError();
 }
 hipError_t nu_launch_spread(const NuArgs& d, hipStream_t s) {

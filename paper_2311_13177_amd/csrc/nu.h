@@ -21,8 +21,10 @@ struct NuArgs {
     float2* grid;           // oversampled grids [B][M][M]
     const float2* y;        // measured samples [B][lmax][n] (interp; may be null)
     float2* out;            // samples [B][lmax][n] (interp)
-    const float2* s_in;     // samples [B][lmax][n] (spread)
-    float dw;               // spread weight (the data-term weight of a fit; 1 for the operator)
+    const float2* s_in;     // samples [B][lmax][n] (prep)
+    float2* pre;            // [B][lmax][n] dw conj(phase) times the samples the spread takes:
+                            // written by interp (of its residual, when not null) or prep
+    float dw;               // data-term weight of a fit; 1 for the operator
     float* loss;            // per-block sums of |out|^2 (interp with loss), or null
 };
 
@@ -30,6 +32,8 @@ hipError_t nu_launch_pad(const NuArgs& d, hipStream_t s);
 hipError_t nu_launch_interp(const NuArgs& d, hipStream_t s);
 // Blocks of the interpolation launch (the length of d.loss).
 int nu_interp_blocks(const NuArgs& d);
+// pre = dw conj(phase) s_in (the adjoint operator's input to the spread)
+hipError_t nu_launch_prep(const NuArgs& d, hipStream_t s);
 hipError_t nu_launch_spread(const NuArgs& d, hipStream_t s);
 hipError_t nu_launch_crop(const NuArgs& d, hipStream_t s);
 

@@ -417,7 +417,9 @@ struct NuScope {
         if (st == VP_OK) st = plan_layout(q, q->base_tiles, &lq);
         if (st == VP_OK) st = device_layout(q, tq, lq, &dq);
         if (st != VP_OK) return st;
-        const size_t bytes = (size_t)p->B * q->n * q->n * sizeof(float2);
+        // the grids, then the premultiplied samples the spread reads
+        const size_t ngrid = (size_t)p->B * q->n * q->n, nsamp = (size_t)p->B * h->lmax * p->n;
+        const size_t bytes = (ngrid + nsamp) * sizeof(float2);
         hipError_t e = persistent ? hipMalloc((void**)&grid, bytes) : hipMallocAsync((void**)&grid, bytes, s);
         if (e != hipSuccess) return hip_status(e, "oversampled grids");
         d.n = p->n; d.M = q->n; d.B = p->B; d.lmax = h->lmax; d.nparts = p->nparts; d.kmax = h->kmax;
@@ -425,6 +427,7 @@ struct NuScope {
         d.lines = t->nu_lines; d.cs = t->nu_cs; d.dea = t->nu_dea; d.kb = t->nu_kb;  d.ph = t->nu_ph;
         d.blade = t->blade;
         d.grid = grid;
+        d.pre = grid + ngrid;
         t_img_rows = t->nu_rows;
         return VP_OK;
     }
@@ -486,6 +489,7 @@ extern "C" vp_status vp_nu_forward(const vp_plan* p, const vp_c64* d_vol, const 
     nu.d.work = sc.work;
     nu.d.y = (const float2*)d_y;
     nu.d.out = (float2*)d_out;
+    nu.d.pre = nullptr;
     if ((e = nu_launch_pad(nu.d, sc.s)) != hipSuccess) return hip_status(e, "vp_nu_forward pad");
     if ((e = nu.dft(-1)) != hipSuccess) return hip_status(e, "vp_nu_forward DFT");
     if ((e = nu_launch_interp(nu.d, sc.s)) != hipSuccess) return hip_status(e, "vp_nu_forward interpolation");
@@ -504,6 +508,7 @@ extern "C" vp_status vp_nu_adjoint(const vp_plan* p, const vp_c64* d_samples, vp
     hipError_t e;
     nu.d.s_in = (const float2*)d_samples;
     nu.d.img_out = sc.work;
+    if ((e = nu_launch_prep(nu.d, sc.s)) != hipSuccess) return hip_status(e, "vp_nu_adjoint prep");
     if ((e = nu_launch_spread(nu.d, sc.s)) != hipSuccess) return hip_status(e, "vp_nu_adjoint spread");
     if ((e = nu.dft(1)) != hipSuccess) return hip_status(e, "vp_nu_adjoint DFT");
     if ((e = nu_launch_crop(nu.d, sc.s)) != hipSuccess) return hip_status(e, "vp_nu_adjoint crop");
@@ -647,8 +652,7 @@ extern "C" vp_status vp_nu_session_create(const vp_plan* p, const vp_options* o,
     d.img_out = x->s->work;
     d.y = x->ys;
     d.out = x->res;
-    d.s_in = x->res;
-    d.dw = o->data_weight;
+    d.dw = o->data_weight;  // interp writes the spread's input to d.pre
     d.loss = x->loss;
     *out = ns_.release();
     return VP_OK;
