@@ -270,17 +270,23 @@ def nu_leg(B, name, steps, warmup):
     el = time.perf_counter() - t0
     stages = sess.stage_times(max(3, steps // 4))
     sess.close()
-    # algorithmic HBM bytes per launch of each gridding stage (complex64 = 8 bytes): a DFT
-    # of the B (2n)^2 grids reads and writes the n image rows in its row pass and the whole
-    # grid in its column pass (3 grids' worth each way); pad and spread write the grids
-    # once, interp reads them once, crop reads the image's quarter; per sample interp reads
-    # y, base, fraction and phase and writes the residual, spread reads all but y
+    # algorithmic HBM bytes per launch of each blade-aligned kernel (complex64 = 8 bytes),
+    # per blade: the forward row pass reads the blade image(s) and writes the n image rows
+    # of the 2n x 2n grid; the forward column pass reads those rows and writes the grid;
+    # interp reads the grid points within W/2 of the blade's lattice (a (2n + 6) x
+    # (2L + 6) strip) and per sample y and the phase, and writes the residual and the
+    # spread's input; spread reads that input and writes the grid; the inverse column pass
+    # reads the grid and writes the image rows; the inverse row pass reads them and writes
+    # the blade image
     n, Bn = case.n, case.n_blades
-    M2 = (2 * n) ** 2
-    ns = Bn * int(np.max(case.lines)) * n
+    M = 2 * n
+    L = int(np.max(case.lines))
+    ns = Bn * L * n
     parts = 2 if case.n_time > 1 else 1
-    per = {"pad": 8 * Bn * (M2 + parts * n * n), "dft_fwd": 3 * 8 * Bn * M2, "interp": 8 * Bn * M2 + 40 * ns,
-           "spread": 8 * Bn * M2 + 32 * ns, "dft_inv": 3 * 8 * Bn * M2, "crop": 8 * Bn * (M2 // 4 + n * n)}
+    strip = min(M * M, (M + 6) * (2 * L + 6))
+    per = {"rows_fwd": 8 * Bn * (parts * n * n + n * M), "cols_fwd": 8 * Bn * (n * M + M * M),
+           "interp": 8 * Bn * strip + 32 * ns, "spread": 8 * Bn * M * M + 8 * ns,
+           "cols_inv": 8 * Bn * (M * M + n * M), "rows_inv": 8 * Bn * (n * M + n * n)}
     dom = max(per, key=lambda k: stages[k])
     ach = per[dom] / (stages[dom] * 1e-3) / 1e9
     # quality: a whole fit from zero at the workload's step count

@@ -260,8 +260,9 @@ vp_status vp_nu_session_create(const vp_plan* plan, const vp_options* opts, cons
 vp_status vp_nu_session_step(vp_nu_session* session, int32_t n_steps, int32_t use_graph);
 
 /* Profiling: n_steps more steps eagerly with a HIP event around every stage; mean
- * milliseconds to stage_ms[8]: projection, pad, forward DFT of the grids,
- * interpolation (residual and loss partials), spread, inverse DFT, crop, and the
+ * milliseconds to stage_ms[8]: projection, forward row DFT of the grids (built from the
+ * blade images), forward column DFT, interpolation (residual and loss partials), spread,
+ * inverse column DFT, inverse row DFT (written back into the blade images), and the
  * gather with the regulariser gradient, update and step counter. */
 vp_status vp_nu_session_stage_times(vp_nu_session* session, int32_t n_steps, double* stage_ms);
 

@@ -404,7 +404,7 @@ def vp_nu_reconstruct(plan: Plan, samples: np.ndarray, opts: Optional[vp_options
     return dict(vol=vol, proj=outs[0], water=outs[1], fat=outs[2], final_loss=float(loss.value))
 
 
-NU_STAGES = ("project", "pad", "dft_fwd", "interp", "spread", "dft_inv", "crop", "gather_update")
+NU_STAGES = ("project", "rows_fwd", "cols_fwd", "interp", "spread", "cols_inv", "rows_inv", "gather_update")
 
 
 class NuSession:

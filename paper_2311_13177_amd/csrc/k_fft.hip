@@ -255,7 +255,33 @@ __global__ __launch_bounds__(kThreads) void k_rows(const KArgs a) {
         const float2* twg = DF(tw);
         const size_t base = (size_t)r0 * n;
         for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = twg[i];
-        if (DIR < 0 && nparts == 2) {
+        // blade-aligned passes: grid row g holds image row (or column) g + m/2 (g < m - m/2)
+        // or g - n + m/2 (g >= n - m/2) of a centred m x m image, else zero
+        const int m = a.live_n, mh = m / 2;
+        const bool edge = m != 0 && (a.mode == COL_INVERSE || a.mode == COL_RAW_FWD);
+        if (DIR < 0 && edge) {
+            const NuEdge& ne = a.nue;
+            const size_t mm = (size_t)m * m;
+            const float2* src = ne.img_in + (size_t)b * ne.parts * mm;
+            const BladeDev bd = ne.blade[b];
+            for (int i = threadIdx.x; i < fb * n; i += blockDim.x) {
+                const int k = i / n, g = i - k * n, gy = r0 + k;
+                const int y = gy < m - mh ? gy + mh : (gy >= n - mh ? gy - n + mh : -1);
+                const int x = g < m - mh ? g + mh : (g >= n - mh ? g - n + mh : -1);
+                float2 v = make_float2(0.f, 0.f);
+                if (k < rows && y >= 0 && x >= 0) {
+                    const float2* p = src + (size_t)y * m + x;
+                    if (ne.parts == 2) {
+                        if (bd.has0) v = cscale(p[0], bd.w0);
+                        if (bd.has1) v = cfma(bd.w1, p[mm], v);
+                    } else {
+                        v = p[0];
+                    }
+                    v = cscale(v, ne.dea[x] * ne.dea[y]);
+                }
+                A[i] = v;
+            }
+        } else if (DIR < 0 && nparts == 2) {
             const AS4 BladeDev* bd = cst(DF(blade)) + b;
             const int has0 = bd->has0, has1 = bd->has1;
             const float w0 = bd->w0, w1 = bd->w1;
@@ -274,7 +300,18 @@ __global__ __launch_bounds__(kThreads) void k_rows(const KArgs a) {
         }
         __syncthreads();
         fft_rows_any<DIR, NC>(A, tw, n, nstage, code);
-        for (int i = threadIdx.x; i < rows * n; i += blockDim.x) img[base + i] = A[i];
+        if (DIR > 0 && edge) {
+            const NuEdge& ne = a.nue;
+            float2* dst = ne.img_out + (size_t)b * ne.parts * m * m;
+            for (int i = threadIdx.x; i < rows * m; i += blockDim.x) {
+                const int k = i / m, x = i - k * m, gy = r0 + k;
+                const int y = gy < m - mh ? gy + mh : (gy >= n - mh ? gy - n + mh : -1);
+                const int g = x < mh ? x - mh + n : x - mh;
+                if (y >= 0) dst[(size_t)y * m + x] = cscale(A[k * n + g], ne.dea[x] * ne.dea[y]);
+            }
+        } else {
+            for (int i = threadIdx.x; i < rows * n; i += blockDim.x) img[base + i] = A[i];
+        }
         __syncthreads();
     }
 }

@@ -1,11 +1,13 @@
 // Blade-aligned (non-Cartesian) k-space sampling by gridding: blade b's samples lie on its
 // rotated lattice k = r u_b + q n_b (readout r = j - n/2, line q = l - L_b/2). Forward:
 // the projected image, centred and divided by the Kaiser-Bessel kernel's transform, is
-// zero-padded onto a grid oversampled by kNuSigma, DFT'd (the plan's row and column
-// passes on the oversampled grid), and every sample interpolated from the W x W grid
-// points around it. Adjoint: the same weights gathered back onto every grid point (the
-// lattice makes the samples near a grid point enumerable, so no atomics), inverse DFT,
-// crop and divide (Beatty, Nishimura and Pauly 2005, for the kernel and its transform).
+// zero-padded onto a grid oversampled by kNuSigma and DFT'd (the row and column passes
+// of an oversampled plan; its forward row pass builds the padded rows from the blade
+// image), and every sample interpolated from the W x W grid points around it. Adjoint:
+// the same weights gathered back onto every grid point (the lattice makes the samples
+// near a grid point enumerable, so no atomics), inverse DFT, crop and divide (the
+// inverse row pass writes the divided centre back) (Beatty, Nishimura and Pauly 2005,
+// for the kernel and its transform).
 
 #include "kcommon.h"
 #include "nu.h"
@@ -30,40 +32,6 @@ __device__ __forceinline__ float kb(const float* tab, float u) {
 }
 
 __device__ __forceinline__ int wrap(int m, int M) { return ((m % M) + M) % M; }
-
-// Image index of oversampled grid index g (centred image, wrapped), or -1.
-__device__ __forceinline__ int img_index(int g, int n, int M) {
-    const int h = n / 2;
-    if (g < n - h) return g + h;
-    if (g >= M - h) return g - M + h;
-    return -1;
-}
-
-// pad[b][gy][gx] = P_b[y][x] / (c(x) c(y)) at the centred, wrapped position; P_b blends a
-// dynamic blade's two knot projections.
-__global__ __launch_bounds__(kThreads) void k_nu_pad(const NuArgs d) {
-    const int n = d.n, M = d.M;
-    const long long MM = (long long)M * M, nn = (long long)n * n;
-    const long long total = (long long)d.B * MM;
-    for (long long e = gtid(); e < total; e += gstride()) {
-        const int b = (int)(e / MM);
-        const int gy = (int)((e % MM) / M), gx = (int)(e % M);
-        const int x = img_index(gx, n, M), y = img_index(gy, n, M);
-        float2 v = make_float2(0.f, 0.f);
-        if (x >= 0 && y >= 0) {
-            const float2* p = d.work + (long long)b * d.nparts * nn + (long long)y * n + x;
-            if (d.nparts == 2) {
-                const BladeDev bd = d.blade[b];
-                if (bd.has0) v = cscale(p[0], bd.w0);
-                if (bd.has1) v = cfma(bd.w1, p[nn], v);
-            } else {
-                v = p[0];
-            }
-            v = cscale(v, d.dea[x] * d.dea[y]);
-        }
-        d.grid[e] = v;
-    }
-}
 
 // Sample (j, l) of blade b in grid units: kNuSigma (r u_b + q n_b), r = j - n/2,
 // q = l - L_b/2, in FP64 (exact to far below FP32's rounding of an offset). The
@@ -234,20 +202,6 @@ __global__ __launch_bounds__(kThreads) void k_nu_prep(const NuArgs d) {
     }
 }
 
-// img[b][y][x] (work part 0) = grid at the wrapped centred position / (c(x) c(y))
-__global__ __launch_bounds__(kThreads) void k_nu_crop(const NuArgs d) {
-    const int n = d.n, M = d.M, hh = n / 2;
-    const long long nn = (long long)n * n;
-    const long long total = (long long)d.B * nn;
-    for (long long e = gtid(); e < total; e += gstride()) {
-        const int b = (int)(e / nn);
-        const int y = (int)((e % nn) / n), x = (int)(e % n);
-        const int gx = wrap(x - hh, M), gy = wrap(y - hh, M);
-        const float2 v = d.grid[((long long)b * M + gy) * M + gx];
-        d.img_out[(long long)b * d.nparts * nn + (long long)y * n + x] = cscale(v, d.dea[x] * d.dea[y]);
-    }
-}
-
 inline unsigned grid_of(long long total) {
     const long long g = (total + kThreads - 1) / kThreads;
     return (unsigned)(g < 1 ? 1 : (g > (1 << 20) ? (1 << 20) : g));
@@ -255,10 +209,6 @@ inline unsigned grid_of(long long total) {
 
 }  // namespace
 
-hipError_t nu_launch_pad(const NuArgs& d, hipStream_t s) {
-    hipLaunchKernelGGL(k_nu_pad, dim3(grid_of((long long)d.B * d.M * d.M)), dim3(kThreads), 0, s, d);
-    return hipGetLastError();
-}
 int nu_interp_blocks(const NuArgs& d) { return (int)grid_of((long long)d.B * d.lmax * d.n * kRowLanes); }
 hipError_t nu_launch_interp(const NuArgs& d, hipStream_t s) {
     hipLaunchKernelGGL(k_nu_interp, dim3(nu_interp_blocks(d)), dim3(kThreads), 0, s, d);
@@ -270,10 +220,6 @@ hipError_t nu_launch_prep(const NuArgs& d, hipStream_t s) {
 }
 hipError_t nu_launch_spread(const NuArgs& d, hipStream_t s) {
     hipLaunchKernelGGL(k_nu_spread, dim3(grid_of((long long)d.B * d.M * d.M)), dim3(kThreads), 0, s, d);
-    return hipGetLastError();
-}
-hipError_t nu_launch_crop(const NuArgs& d, hipStream_t s) {
-    hipLaunchKernelGGL(k_nu_crop, dim3(grid_of((long long)d.B * d.n * d.n)), dim3(kThreads), 0, s, d);
     return hipGetLastError();
 }
 

@@ -15,9 +15,9 @@ struct NuArgs {
     const float* dea;       // [n] 1 / (kernel transform) at the centred index x - n/2
     const float* kb;        // [kNuTable + 1] kernel on [0, W/2]
     const float2* ph;       // [B][lmax][n] exp(-i pi (kx + ky) 2 floor(n/2) / n) / n
-    const BladeDev* blade;  // knot blend of dynamic blades (pad)
-    const float2* work;     // projection parts [B][nparts][n][n] (pad)
-    float2* img_out;        // adjoint images, part 0 of [B][nparts][n][n] (crop)
+    const BladeDev* blade;  // knot blend of dynamic blades (forward row pass)
+    const float2* work;     // projection parts [B][nparts][n][n] (forward row pass)
+    float2* img_out;        // adjoint images, part 0 of [B][nparts][n][n] (inverse row pass)
     float2* grid;           // oversampled grids [B][M][M]
     const float2* y;        // measured samples [B][lmax][n] (interp; may be null)
     float2* out;            // samples [B][lmax][n] (interp)
@@ -28,13 +28,11 @@ struct NuArgs {
     float* loss;            // per-block sums of |out|^2 (interp with loss), or null
 };
 
-hipError_t nu_launch_pad(const NuArgs& d, hipStream_t s);
 hipError_t nu_launch_interp(const NuArgs& d, hipStream_t s);
 // Blocks of the interpolation launch (the length of d.loss).
 int nu_interp_blocks(const NuArgs& d);
 // pre = dw conj(phase) s_in (the adjoint operator's input to the spread)
 hipError_t nu_launch_prep(const NuArgs& d, hipStream_t s);
 hipError_t nu_launch_spread(const NuArgs& d, hipStream_t s);
-hipError_t nu_launch_crop(const NuArgs& d, hipStream_t s);
 
 }  // namespace vp

@@ -431,30 +431,32 @@ struct NuScope {
         t_img_rows = t->nu_rows;
         return VP_OK;
     }
-    // unscaled 2D DFT of the grids in place: forward (dir -1) or inverse (dir +1)
-    hipError_t dft(int dir) {
+    // The unscaled 2D DFT of the grids, in four passes: the forward row pass builds the
+    // image rows of the grids from the blade images (centred, deapodised; the other rows
+    // stay unread), the forward column pass completes the DFT in place; the inverse column
+    // pass writes only the image rows, and the inverse row pass writes their centres,
+    // deapodised, into the blade images (part 0).
+    hipError_t pass(int which) {
         KArgs a{};
         fill_desc(q, tq, lq, dq, &a.one);
         const StageLists L = plan_lists(q, tq, lq, dq);
         a.in0 = grid;
         a.out0 = grid;
         a.live_n = d.n;
-        hipError_t e;
-        const Task* rows = t_img_rows;
-        const int nrows = (int)h->rows.size();
-        if (dir < 0) {
-            a.mode = COL_RAW_FWD;
-            a.tasks = rows; a.ntasks = nrows;
-            if ((e = launch_rows(a, -1, L.fft_n, L.lds_rows, s)) != hipSuccess) return e;
+        a.nue.img_in = d.work;
+        a.nue.img_out = d.img_out;
+        a.nue.blade = d.blade;
+        a.nue.dea = d.dea;
+        a.nue.parts = d.nparts;
+        a.mode = which < 2 ? COL_RAW_FWD : COL_INVERSE;
+        if (which == 1 || which == 2) {
             a.tasks = L.cols; a.ntasks = L.n_cols;
             return launch_cols(a, L.fft_n, L.lds_cols, s);
         }
-        a.mode = COL_INVERSE;
-        a.tasks = L.cols; a.ntasks = L.n_cols;
-        if ((e = launch_cols(a, L.fft_n, L.lds_cols, s)) != hipSuccess) return e;
-        a.tasks = rows; a.ntasks = nrows;
-        return launch_rows(a, 1, L.fft_n, L.lds_rows, s);
+        a.tasks = t_img_rows; a.ntasks = (int)h->rows.size();
+        return launch_rows(a, which == 0 ? -1 : 1, L.fft_n, L.lds_rows, s);
     }
+    enum { ROWS_FWD = 0, COLS_FWD = 1, COLS_INV = 2, ROWS_INV = 3 };
     ~NuScope() {
         if (!grid) return;
         if (persistent) {
@@ -490,8 +492,8 @@ extern "C" vp_status vp_nu_forward(const vp_plan* p, const vp_c64* d_vol, const 
     nu.d.y = (const float2*)d_y;
     nu.d.out = (float2*)d_out;
     nu.d.pre = nullptr;
-    if ((e = nu_launch_pad(nu.d, sc.s)) != hipSuccess) return hip_status(e, "vp_nu_forward pad");
-    if ((e = nu.dft(-1)) != hipSuccess) return hip_status(e, "vp_nu_forward DFT");
+    if ((e = nu.pass(NuScope::ROWS_FWD)) != hipSuccess || (e = nu.pass(NuScope::COLS_FWD)) != hipSuccess)
+        return hip_status(e, "vp_nu_forward DFT");
     if ((e = nu_launch_interp(nu.d, sc.s)) != hipSuccess) return hip_status(e, "vp_nu_forward interpolation");
     return VP_OK;
 }
@@ -510,8 +512,8 @@ extern "C" vp_status vp_nu_adjoint(const vp_plan* p, const vp_c64* d_samples, vp
     nu.d.img_out = sc.work;
     if ((e = nu_launch_prep(nu.d, sc.s)) != hipSuccess) return hip_status(e, "vp_nu_adjoint prep");
     if ((e = nu_launch_spread(nu.d, sc.s)) != hipSuccess) return hip_status(e, "vp_nu_adjoint spread");
-    if ((e = nu.dft(1)) != hipSuccess) return hip_status(e, "vp_nu_adjoint DFT");
-    if ((e = nu_launch_crop(nu.d, sc.s)) != hipSuccess) return hip_status(e, "vp_nu_adjoint crop");
+    if ((e = nu.pass(NuScope::COLS_INV)) != hipSuccess || (e = nu.pass(NuScope::ROWS_INV)) != hipSuccess)
+        return hip_status(e, "vp_nu_adjoint DFT");
     KArgs a{};
     fill_desc(p, sc.t, sc.lay, sc.dl, &a.one);
     a.one.work = sc.work;
@@ -529,13 +531,16 @@ extern "C" vp_status vp_nu_adjoint(const vp_plan* p, const vp_c64* d_samples, vp
 // ------------------------------------------------------------------ fits on blade-aligned samples
 
 namespace {
-constexpr int kNuStages = 8;  // project, pad, forward DFT, interp, spread, inverse DFT, crop, gather+update
+// project, forward rows, forward columns, interp, spread, inverse columns, inverse rows,
+// gather+update
+constexpr int kNuStages = 8;
 }
 
 // A Cartesian session (volume, optimiser state, projection and gather lists, step counter)
-// whose data term runs through the gridding passes: per step project, pad, forward DFT,
-// interpolate minus the samples (with loss partials), spread, inverse DFT, crop, then the
-// fused gather with the regulariser gradient and update, and the counter.
+// whose data term runs through the gridding passes: per step project, the forward DFT of
+// the grids (its row pass builds the grid rows from the blade images), interpolate minus
+// the samples (with loss partials), spread, the inverse DFT (its row pass writes the blade
+// images), then the fused gather with the regulariser gradient and update, and the counter.
 struct vp_nu_session {
     std::unique_ptr<vp_session> s;
     NuScope nu;
@@ -567,9 +572,9 @@ struct vp_nu_session {
         hipError_t r = ev ? hipEventRecord(ev[0], str) : hipSuccess;
         if (r == hipSuccess) r = launch_project(a, L.tiles.proj_rows, L.tiles.proj_gw, L.re_proj, str);
         if (r == hipSuccess && ev) r = hipEventRecord(ev[1], str);
-        if (r == hipSuccess) r = nu_launch_pad(nu.d, str);
+        if (r == hipSuccess) r = nu.pass(NuScope::ROWS_FWD);
         if (r == hipSuccess && ev) r = hipEventRecord(ev[2], str);
-        if (r == hipSuccess) r = nu.dft(-1);
+        if (r == hipSuccess) r = nu.pass(NuScope::COLS_FWD);
         if (r == hipSuccess && ev) r = hipEventRecord(ev[3], str);
         if (r == hipSuccess) r = nu_launch_interp(nu.d, str);
         return r;
@@ -583,9 +588,9 @@ struct vp_nu_session {
         if (r == hipSuccess && ev) r = hipEventRecord(ev[4], str);
         if (r == hipSuccess) r = nu_launch_spread(nu.d, str);
         if (r == hipSuccess && ev) r = hipEventRecord(ev[5], str);
-        if (r == hipSuccess) r = nu.dft(1);
+        if (r == hipSuccess) r = nu.pass(NuScope::COLS_INV);
         if (r == hipSuccess && ev) r = hipEventRecord(ev[6], str);
-        if (r == hipSuccess) r = nu_launch_crop(nu.d, str);
+        if (r == hipSuccess) r = nu.pass(NuScope::ROWS_INV);
         if (r == hipSuccess && ev) r = hipEventRecord(ev[7], str);
         KArgs a{};
         a.one = s->desc;

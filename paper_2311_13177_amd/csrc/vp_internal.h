@@ -133,6 +133,19 @@ struct SliceDesc {
     float tv_w, l1_w, tv_eps;
 };
 
+// The blade images at the two ends of the blade-aligned DFT passes (k_rows in
+// COL_RAW_FWD / COL_INVERSE with live_n != 0): the forward row pass builds each grid row
+// from row y of the blade image (knots blended, centred, divided by the kernel
+// transform) instead of reading it, and the inverse row pass writes the row's centre,
+// divided the same way, into the blade image instead of the grid.
+struct NuEdge {
+    const float2* img_in;   // blade images [B][parts][m][m] (forward)
+    float2* img_out;        // blade images, part 0 of [B][parts][m][m] (inverse)
+    const BladeDev* blade;  // knot blend of dynamic blades (forward, parts == 2)
+    const float* dea;       // [m] 1 / (kernel transform) at the centred index x - m/2
+    int parts;
+};
+
 struct KArgs {
     const SliceDesc* descs;      // device array, or nullptr to use `one`
     SliceDesc one;
@@ -150,6 +163,7 @@ struct KArgs {
     int live_n;                  // COL_RAW_FWD / COL_INVERSE: 0, or the size m of a centred image
                                  // in the frame: only rows [0, m - m/2) and [n - m/2, n) are
                                  // nonzero on input (forward) or needed on output (inverse)
+    NuEdge nue;                  // with live_n != 0: the row passes' blade-image ends
 };
 
 // Column pass modes.
