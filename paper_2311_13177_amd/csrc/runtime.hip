@@ -451,7 +451,7 @@ struct NuScope {
         a.mode = which < 2 ? COL_RAW_FWD : COL_INVERSE;
         if (which == 1 || which == 2) {
             a.tasks = L.cols; a.ntasks = L.n_cols;
-            return launch_cols(a, L.fft_n, L.lds_cols, s);
+            return launch_cols(a, L.fft_n, (size_t)fft_cols_raw_lds(q->n), s);
         }
         a.tasks = t_img_rows; a.ntasks = (int)h->rows.size();
         return launch_rows(a, which == 0 ? -1 : 1, L.fft_n, L.lds_rows, s);
