@@ -186,3 +186,62 @@ def test_session_steps_in_parts_equal_one_fit(gpu_lib):
     for k in ("vol", "proj", "water", "fat"):
         assert np.array_equal(got[k], one[k]), k
     assert got["objective"] == one["final_loss"]
+
+
+@pytest.mark.parametrize("name", ["static_256", "dynamic_192"])
+def test_full_size_sampled_forward_and_transpose(gpu_lib, name):
+    # the benchmark's geometries in the benchmark's launch configuration: sampled outputs
+    # against the definition (each sample is one sum over the projected image), the
+    # forward/adjoint pair against each other by a dot test over every sample and voxel
+    import torch
+    from oracle import lifted as OL
+    from paper_2311_13177_amd import binding as B
+
+    case = configs.CONFIGS[name]()
+    plan = B.Plan.from_geometry(case.geometry())
+    geom = O.Geometry.from_dict(case.geometry())
+    rng = np.random.default_rng(12)
+    shp = plan.volume_shape
+    vol = (rng.standard_normal(shp) + 1j * rng.standard_normal(shp)).astype(np.complex64)
+    dv = torch.from_numpy(vol).cuda()
+    got = B.vp_nu_forward(plan, dv).cpu().numpy()
+    v64 = vol.astype(np.complex128)
+    num = den = 0.0
+    for b in range(geom.n_blades):
+        L = int(geom.lines[b])
+        p = OL.project_blade(OL.volume_at(v64, geom.tau(b)), geom, b)
+        kx, ky = N.blade_samples(geom.n, float(geom.angle_rad[b]), L)
+        sel = rng.choice(L * geom.n, 12, replace=False)
+        want = N.ndft_forward(p, kx.reshape(-1)[sel], ky.reshape(-1)[sel])
+        g = got[b, :L].reshape(-1)[sel]
+        num += float(np.sum(np.abs(g - want) ** 2))
+        den += float(np.sum(np.abs(want) ** 2))
+    assert (num / den) ** 0.5 <= 1e-4
+    s = (rng.standard_normal(got.shape) + 1j * rng.standard_normal(got.shape)).astype(np.complex64)
+    for b in range(geom.n_blades):
+        s[b, int(geom.lines[b]):] = 0
+    adj = B.vp_nu_adjoint(plan, torch.from_numpy(s).cuda()).cpu().numpy()
+    lhs = np.vdot(s.astype(np.complex128), got.astype(np.complex128))
+    rhs = np.vdot(adj.astype(np.complex128), v64)
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+
+
+def test_full_size_gd_descends(gpu_lib):
+    # 256^2 geometry: with a step below 1 / (Lipschitz bound) gradient descent lowers the
+    # objective at every step (a property at any size)
+    from paper_2311_13177_amd import binding as B
+
+    case = configs.CONFIGS["static_256"]()
+    plan = B.Plan.from_geometry(case.geometry())
+    rng = np.random.default_rng(13)
+    shp = B.nu_shape(plan)
+    y = (rng.standard_normal(shp) + 1j * rng.standard_normal(shp)).astype(np.complex64)
+    opts = B.vp_options_default(optimizer=B.VP_OPT_GD, lr=0.25 / (case.n_spec * case.n_blades),
+                                tv_weight=case.tv_weight)
+    sess = B.NuSession(plan, y, opts)
+    vals = [sess.read(objective=True)["objective"]]
+    for _ in range(4):
+        sess.step(1, use_graph=False)
+        vals.append(sess.read(objective=True)["objective"])
+    sess.close()
+    assert all(b < a for a, b in zip(vals, vals[1:])), vals
