@@ -118,44 +118,96 @@ __global__ __launch_bounds__(kThreads) void k_kp_prod(const KPDesc d) {
 
 // ------------------------------------------------------------------ decode
 
-// vol[b][s][y][x] = sum_c sum_f Z[c][y][x][f] XA[c][b][s][x][f] Yf[c][b][s][y][f]; a thread
-// takes kDecBins consecutive bins of one pixel, reusing the pixel's Z
+// vol[b][s][y][x] = sum_c sum_f Z[c][y][x][f] XA[c][b][s][x][f] Yf[c][b][s][y][f]
 constexpr int kDecBins = 4;
 
+// Lane l's complex value, read by every lane (v_readlane: a wave-uniform value in SGPRs,
+// no memory access). Values that are the same for a whole wave are loaded spread over its
+// lanes, one vector load for up to 64 of them, and read back this way.
+__device__ __forceinline__ float2 lane_c(float2 v, int l) {
+    return make_float2(__builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v.x), l)),
+                       __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v.y), l)));
+}
+constexpr int kDecRows = 4;
+
+// A wave task is (blade, kDecBins bins, kDecRows rows, 64 columns): its XA values (per
+// column) are loaded once for all kDecRows rows, its Yf values (per row, the same in
+// every lane) once for the wave spread over the lanes, and Z (per pixel) once per row for
+// all kDecBins bins. The sums run in the same order as a per-voxel loop (scales, then
+// features), so every shape of this task gives the same bits.
 template <int F>
 __global__ __launch_bounds__(kThreads) void k_kp_decode(const KPDesc d) {
+    constexpr int NY = kDecRows * kKpMaxScales * kDecBins * F;  // Yf entries of one wave task
+    constexpr int NL = (NY + 63) / 64;
     const int n = d.n, S = d.S;
     const long long nn = (long long)n * n;
     const int sq = (S + kDecBins - 1) / kDecBins;
-    const long long total = (long long)d.B * sq * nn;
-    for (long long e = gtid(); e < total; e += gstride()) {
-        const long long px = e % nn;
-        const int x = (int)(px % n), y = (int)(px / n);
-        const int q = (int)((e / nn) % sq);
-        const int b = (int)(e / (nn * sq));
+    const int nseg = (n + 63) / 64, nrg = (n + kDecRows - 1) / kDecRows;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const long long W = (long long)d.B * sq * nrg * nseg;
+    for (long long w = (long long)blockIdx.x * (kThreads / 64) + wave; w < W; w += (long long)gridDim.x * (kThreads / 64)) {
+        const int seg = (int)(w % nseg);
+        const int rg = (int)((w / nseg) % nrg);
+        const int q = (int)((w / ((long long)nseg * nrg)) % sq);
+        const int b = (int)(w / ((long long)nseg * nrg * sq));
         const int s0 = q * kDecBins, ns = min(kDecBins, S - s0);
-        float2 v[kDecBins];
+        const int y0 = rg * kDecRows;
+        // Yf of the task, one entry per lane: ((r kKpMaxScales + c) kDecBins + k) F + f
+        float2 yl[NL];
 #pragma unroll
-        for (int k = 0; k < kDecBins; ++k) v[k] = make_float2(0.f, 0.f);
-        for (int c = 0; c < d.ns; ++c) {
-            float2 z[F];
-            const float2* zp = d.Z + ((long long)c * nn + px) * F;
+        for (int t = 0; t < NL; ++t) {
+            const int ei = t * 64 + lane;
+            const int f = ei % F, k = (ei / F) % kDecBins, c = (ei / (F * kDecBins)) % kKpMaxScales;
+            const int r = ei / (F * kDecBins * kKpMaxScales);
+            yl[t] = make_float2(0.f, 0.f);
+            if (ei < NY && c < d.ns && k < ns && y0 + r < n)
+                yl[t] = d.Yf[((((long long)c * d.B + b) * S + s0 + k) * n + y0 + r) * F + f];
+        }
+        const int x = seg * 64 + lane;
+        const bool live = x < n;
+        const int xs = live ? x : 0;
+        float2 v[kDecRows][kDecBins];
 #pragma unroll
-            for (int f = 0; f < F; ++f) z[f] = zp[f];
+        for (int r = 0; r < kDecRows; ++r)
 #pragma unroll
-            for (int k = 0; k < kDecBins; ++k) {
-                if (k < ns) {
-                    const long long cb = ((long long)c * d.B + b) * S + s0 + k;
-                    const float2* xa = d.XA + (cb * n + x) * F;
-                    const float2* yf = d.Yf + (cb * n + y) * F;
+            for (int k = 0; k < kDecBins; ++k) v[r][k] = make_float2(0.f, 0.f);
 #pragma unroll
-                    for (int f = 0; f < F; ++f) v[k] = cmad(cmul(z[f], xa[f]), yf[f], v[k]);
+        for (int c = 0; c < kKpMaxScales; ++c) {
+            if (c < d.ns) {
+                float2 xa[kDecBins][F];
+#pragma unroll
+                for (int k = 0; k < kDecBins; ++k) {
+                    const long long cb = ((long long)c * d.B + b) * S + s0 + min(k, ns - 1);
+                    const float2* xp = d.XA + (cb * n + xs) * F;
+#pragma unroll
+                    for (int f = 0; f < F; ++f) xa[k][f] = xp[f];
+                }
+#pragma unroll
+                for (int r = 0; r < kDecRows; ++r) {
+                    const int y = min(y0 + r, n - 1);
+                    float2 z[F];
+                    const float2* zp = d.Z + ((long long)c * nn + (long long)y * n + xs) * F;
+#pragma unroll
+                    for (int f = 0; f < F; ++f) z[f] = zp[f];
+#pragma unroll
+                    for (int k = 0; k < kDecBins; ++k) {
+#pragma unroll
+                        for (int f = 0; f < F; ++f) {
+                            const int ei = ((r * kKpMaxScales + c) * kDecBins + k) * F + f;
+                            v[r][k] = cmad(cmul(z[f], xa[k][f]), lane_c(yl[ei / 64], ei % 64), v[r][k]);
+                        }
+                    }
                 }
             }
         }
+        if (live) {
 #pragma unroll
-        for (int k = 0; k < kDecBins; ++k)
-            if (k < ns) d.vol[((long long)b * S + s0 + k) * nn + px] = v[k];
+            for (int r = 0; r < kDecRows; ++r)
+#pragma unroll
+                for (int k = 0; k < kDecBins; ++k)
+                    if (k < ns && y0 + r < n) d.vol[((long long)b * S + s0 + k) * nn + (long long)(y0 + r) * n + x] = v[r][k];
+        }
     }
 }
 
@@ -163,42 +215,87 @@ __global__ __launch_bounds__(kThreads) void k_kp_decode(const KPDesc d) {
 
 // gZ[c][y][x][f] = sum_b sum_s conj(XA Yf) G[b][s][y][x], in two passes: partial sums over
 // consecutive (b, s) chunks for every pixel and both scales (G read once), then the
-// chunks summed in order
+// chunks summed in order. A wave task of the first pass is (chunk, kGzRows rows, 64
+// columns): each XA value (per column) serves all kGzRows rows, and the Yf values (per
+// row, the same in every lane) of 64 / (kGzRows kKpMaxScales F) consecutive (b, s) are
+// loaded at once spread over the lanes. Each sum runs over (b, s) in order.
+constexpr int kGzRows = 2;
+
 template <int F>
 __global__ __launch_bounds__(kThreads) void k_kp_grad_z(const KPDesc d) {
-    const int n = d.n, S = d.S;
+    constexpr int NYB = kGzRows * kKpMaxScales * F;  // Yf entries per (b, s)
+    constexpr int BPL = NYB >= 64 ? 1 : 64 / NYB;     // (b, s) per lane-spread load
+    const int n = d.n;
     const long long nn = (long long)n * n;
-    const int nbs = d.B * S, cs = (nbs + d.zchunks - 1) / d.zchunks;
-    const long long total = (long long)d.zchunks * nn;
-    for (long long e = gtid(); e < total; e += gstride()) {
-        const long long px = e % nn;
-        const int ch = (int)(e / nn);
-        const int x = (int)(px % n), y = (int)(px / n);
-        float2 acc[kKpMaxScales][F];
+    const int nbs = d.B * d.S, cs = (nbs + d.zchunks - 1) / d.zchunks;
+    const int nseg = (n + 63) / 64, nrg = (n + kGzRows - 1) / kGzRows;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const long long W = (long long)d.zchunks * nrg * nseg;
+    for (long long w = (long long)blockIdx.x * (kThreads / 64) + wave; w < W; w += (long long)gridDim.x * (kThreads / 64)) {
+        const int seg = (int)(w % nseg);
+        const int y0 = (int)((w / nseg) % nrg) * kGzRows;
+        const int ch = (int)(w / ((long long)nseg * nrg));
+        const int x = seg * 64 + lane;
+        const bool live = x < n;
+        const int xs = live ? x : 0;
+        float2 acc[kGzRows][kKpMaxScales][F];
 #pragma unroll
-        for (int c = 0; c < kKpMaxScales; ++c)
+        for (int r = 0; r < kGzRows; ++r)
 #pragma unroll
-            for (int f = 0; f < F; ++f) acc[c][f] = make_float2(0.f, 0.f);
+            for (int c = 0; c < kKpMaxScales; ++c)
+#pragma unroll
+                for (int f = 0; f < F; ++f) acc[r][c][f] = make_float2(0.f, 0.f);
         const int bs1 = min(nbs, (ch + 1) * cs);
-        for (int bs = ch * cs; bs < bs1; ++bs) {
-            const float2 g = d.G[(long long)bs * nn + px];
+        for (int bs = ch * cs; bs < bs1; bs += BPL) {
+            float2 yl;
+            {
+                const int bq = bs + lane / NYB, ei = lane % NYB;
+                const int r = ei / (kKpMaxScales * F), c = (ei / F) % kKpMaxScales, f = ei % F;
+                yl = make_float2(0.f, 0.f);
+                if (lane < BPL * NYB && bq < bs1 && c < d.ns && y0 + r < n)
+                    yl = d.Yf[(((long long)c * nbs + bq) * n + y0 + r) * F + f];
+            }
 #pragma unroll
-            for (int c = 0; c < kKpMaxScales; ++c) {
-                if (c < d.ns) {
-                    const long long cb = (long long)c * nbs + bs;
-                    const float2* xa = d.XA + (cb * n + x) * F;
-                    const float2* yf = d.Yf + (cb * n + y) * F;
+            for (int u = 0; u < BPL; ++u) {
+                const int bu = bs + u;
+                if (bu < bs1) {
+                    float2 xa[kKpMaxScales][F];
 #pragma unroll
-                    for (int f = 0; f < F; ++f) acc[c][f] = cjmad(cmul(xa[f], yf[f]), g, acc[c][f]);
+                    for (int c = 0; c < kKpMaxScales; ++c) {
+                        const float2* xp = d.XA + (((long long)min(c, d.ns - 1) * nbs + bu) * n + xs) * F;
+#pragma unroll
+                        for (int f = 0; f < F; ++f) xa[c][f] = xp[f];
+                    }
+#pragma unroll
+                    for (int r = 0; r < kGzRows; ++r) {
+                        if (y0 + r < n) {
+                            const float2 g = d.G[(long long)bu * nn + (long long)(y0 + r) * n + xs];
+#pragma unroll
+                            for (int c = 0; c < kKpMaxScales; ++c) {
+                                if (c < d.ns) {
+#pragma unroll
+                                    for (int f = 0; f < F; ++f)
+                                        acc[r][c][f] = cjmad(cmul(xa[c][f], lane_c(yl, u * NYB + (r * kKpMaxScales + c) * F + f)),
+                                                             g, acc[r][c][f]);
+                                }
+                            }
+                        }
+                    }
                 }
             }
         }
+        if (live) {
 #pragma unroll
-        for (int c = 0; c < kKpMaxScales; ++c) {
-            if (c < d.ns) {
-                float2* out = d.zpart + (((long long)ch * d.ns + c) * nn + px) * F;
+            for (int r = 0; r < kGzRows; ++r) {
 #pragma unroll
-                for (int f = 0; f < F; ++f) out[f] = acc[c][f];
+                for (int c = 0; c < kKpMaxScales; ++c) {
+                    if (c < d.ns && y0 + r < n) {
+                        float2* out = d.zpart + (((long long)ch * d.ns + c) * nn + (long long)(y0 + r) * n + x) * F;
+#pragma unroll
+                        for (int f = 0; f < F; ++f) out[f] = acc[r][c][f];
+                    }
+                }
             }
         }
     }
@@ -213,31 +310,73 @@ __global__ __launch_bounds__(kThreads) void k_kp_grad_z_sum(const KPDesc d) {
     }
 }
 
-// gXA[c][b][s][x][f] = sum_y conj(Z Yf) G[b][s][y][x]
+// gXA[c][b][s][x][f] = sum_y conj(Z Yf) G[b][s][y][x]. A wave task is (kGxBs consecutive
+// (b, s), 64 columns): each Z value (per pixel) serves all kGxBs of them, and the Yf values
+// (per row, the same in every lane) are loaded 64 / F rows at a time spread over the lanes.
+// Each sum runs over y in order.
+constexpr int kGxBs = 2;
+
 template <int F>
 __global__ __launch_bounds__(kThreads) void k_kp_grad_x(const KPDesc d) {
-    const int n = d.n, S = d.S;
+    constexpr int YB = 64 / F;  // rows per lane-spread Yf load
+    const int n = d.n;
     const long long nn = (long long)n * n;
-    const long long total = (long long)d.B * S * n;
-    for (long long e = gtid(); e < total; e += gstride()) {
-        const int x = (int)(e % n);
-        const long long bs = e / n;
-        const float2* gp = d.G + bs * nn + x;
+    const int nbs = d.B * d.S;
+    const int nseg = (n + 63) / 64, ngr = (nbs + kGxBs - 1) / kGxBs;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const long long W = (long long)ngr * nseg;
+    for (long long w = (long long)blockIdx.x * (kThreads / 64) + wave; w < W; w += (long long)gridDim.x * (kThreads / 64)) {
+        const int seg = (int)(w % nseg);
+        const int bs0 = (int)(w / nseg) * kGxBs;
+        const int x = seg * 64 + lane;
+        const bool live = x < n;
+        const int xs = live ? x : 0;
         for (int c = 0; c < d.ns; ++c) {
-            float2 acc[F];
+            float2 acc[kGxBs][F];
 #pragma unroll
-            for (int f = 0; f < F; ++f) acc[f] = make_float2(0.f, 0.f);
-            const long long cb = (long long)c * d.B * S + bs;
-            for (int y = 0; y < n; ++y) {
-                const float2 g = gp[(long long)y * n];
-                const float2* z = d.Z + (((long long)c * n + y) * n + x) * F;
-                const float2* yf = d.Yf + (cb * n + y) * F;
+            for (int j = 0; j < kGxBs; ++j)
 #pragma unroll
-                for (int f = 0; f < F; ++f) acc[f] = cjmad(cmul(z[f], yf[f]), g, acc[f]);
+                for (int f = 0; f < F; ++f) acc[j][f] = make_float2(0.f, 0.f);
+            for (int y0 = 0; y0 < n; y0 += YB) {
+                float2 yl[kGxBs];
+                const int yy = y0 + lane / F;
+#pragma unroll
+                for (int j = 0; j < kGxBs; ++j) {
+                    const int bs = bs0 + j;
+                    yl[j] = make_float2(0.f, 0.f);
+                    if (bs < nbs && yy < n) yl[j] = d.Yf[(((long long)c * nbs + bs) * n + yy) * F + lane % F];
+                }
+#pragma unroll
+                for (int t = 0; t < YB; ++t) {
+                    const int y = y0 + t;
+                    if (y < n) {
+                        float2 z[F];
+                        const float2* zp = d.Z + (((long long)c * n + y) * n + xs) * F;
+#pragma unroll
+                        for (int f = 0; f < F; ++f) z[f] = zp[f];
+#pragma unroll
+                        for (int j = 0; j < kGxBs; ++j) {
+                            if (bs0 + j < nbs) {
+                                const float2 g = d.G[(long long)(bs0 + j) * nn + (long long)y * n + xs];
+#pragma unroll
+                                for (int f = 0; f < F; ++f)
+                                    acc[j][f] = cjmad(cmul(z[f], lane_c(yl[j], t * F + f)), g, acc[j][f]);
+                            }
+                        }
+                    }
+                }
             }
-            float2* out = d.gXA + (cb * n + x) * F;
+            if (live) {
 #pragma unroll
-            for (int f = 0; f < F; ++f) out[f] = acc[f];
+                for (int j = 0; j < kGxBs; ++j) {
+                    if (bs0 + j < nbs) {
+                        float2* out = d.gXA + (((long long)c * nbs + bs0 + j) * n + x) * F;
+#pragma unroll
+                        for (int f = 0; f < F; ++f) out[f] = acc[j][f];
+                    }
+                }
+            }
         }
     }
 }
@@ -255,25 +394,41 @@ __global__ __launch_bounds__(kThreads) void k_kp_grad_y(const KPDesc d) {
     const long long groups = (rows + RW - 1) / RW;
     for (long long gi = (long long)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); gi < groups;
          gi += (long long)gridDim.x * (kThreads / 64)) {
+        // the wave's rows usually share one (b, s), and with it their XA values (per x):
+        // then those are loaded once per column for all RW rows
+        const long long row0 = gi * RW;
+        const bool one_bs = (min(row0 + RW, rows) - 1) / n == row0 / n;
         for (int c = 0; c < d.ns; ++c) {
             float v[64];
 #pragma unroll
             for (int i = 0; i < 64; ++i) v[i] = 0.f;
+            for (int x = lane; x < n; x += 64) {
+                float2 xs[F];
+                if (one_bs) {
+                    const float2* xa = d.XA + (((long long)c * d.B * S + row0 / n) * n + x) * F;
 #pragma unroll
-            for (int r = 0; r < RW; ++r) {
-                const long long row = gi * RW + r;
-                if (row < rows) {
-                    const int y = (int)(row % n);
-                    const long long bs = row / n;
-                    const long long cb = (long long)c * d.B * S + bs;
-                    const float2* gp = d.G + row * n;
-                    for (int x = lane; x < n; x += 64) {
-                        const float2 g = gp[x];
+                    for (int f = 0; f < F; ++f) xs[f] = xa[f];
+                }
+#pragma unroll
+                for (int r = 0; r < RW; ++r) {
+                    const long long row = row0 + r;
+                    if (row < rows) {
+                        const int y = (int)(row % n);
+                        const long long cb = (long long)c * d.B * S + row / n;
+                        const float2 g = d.G[row * n + x];
                         const float2* z = d.Z + (((long long)c * n + y) * n + x) * F;
-                        const float2* xa = d.XA + (cb * n + x) * F;
+                        float2 xr[F];
+                        if (one_bs) {
+#pragma unroll
+                            for (int f = 0; f < F; ++f) xr[f] = xs[f];
+                        } else {
+                            const float2* xa = d.XA + (cb * n + x) * F;
+#pragma unroll
+                            for (int f = 0; f < F; ++f) xr[f] = xa[f];
+                        }
 #pragma unroll
                         for (int f = 0; f < F; ++f) {
-                            const float2 t = cjmad(cmul(z[f], xa[f]), g, make_float2(v[(r * F + f) * 2], v[(r * F + f) * 2 + 1]));
+                            const float2 t = cjmad(cmul(z[f], xr[f]), g, make_float2(v[(r * F + f) * 2], v[(r * F + f) * 2 + 1]));
                             v[(r * F + f) * 2] = t.x;
                             v[(r * F + f) * 2 + 1] = t.y;
                         }
@@ -632,17 +787,17 @@ hipError_t kp_launch_factors(const KPDesc& d, hipStream_t s) {
     }
 
 hipError_t kp_launch_decode(const KPDesc& d, hipStream_t s) {
-    KP_F_SWITCH(k_kp_decode, dim3(grid_of((long long)d.B * ((d.S + kDecBins - 1) / kDecBins) * d.n * d.n)));
+    KP_F_SWITCH(k_kp_decode, dim3(grid_of((long long)d.B * ((d.S + kDecBins - 1) / kDecBins) * ((d.n + kDecRows - 1) / kDecRows) * ((d.n + 63) / 64) * 64)));
     return hipGetLastError();
 }
 
 hipError_t kp_launch_back_z(const KPDesc& d, hipStream_t s) {
-    KP_F_SWITCH(k_kp_grad_z, dim3(grid_of((long long)d.zchunks * d.n * d.n)));
+    KP_F_SWITCH(k_kp_grad_z, dim3(grid_of((long long)d.zchunks * ((d.n + kGzRows - 1) / kGzRows) * ((d.n + 63) / 64) * 64)));
     hipLaunchKernelGGL(k_kp_grad_z_sum, dim3(grid_of((long long)d.ns * d.n * d.n * d.F)), dim3(kThreads), 0, s, d);
     return hipGetLastError();
 }
 hipError_t kp_launch_back_x(const KPDesc& d, hipStream_t s) {
-    KP_F_SWITCH(k_kp_grad_x, dim3(grid_of((long long)d.B * d.S * d.n)));
+    KP_F_SWITCH(k_kp_grad_x, dim3(grid_of((long long)((d.B * d.S + kGxBs - 1) / kGxBs) * ((d.n + 63) / 64) * 64)));
     return hipGetLastError();
 }
 hipError_t kp_launch_back_y(const KPDesc& d, hipStream_t s) {
