@@ -313,8 +313,9 @@ __global__ __launch_bounds__(kThreads) void k_kp_grad_z_sum(const KPDesc d) {
 // gXA[c][b][s][x][f] = sum_y conj(Z Yf) G[b][s][y][x]. A wave task is (kGxBs consecutive
 // (b, s), 64 columns): each Z value (per pixel) serves all kGxBs of them, and the Yf values
 // (per row, the same in every lane) are loaded 64 / F rows at a time spread over the lanes.
-// Each sum runs over y in order.
-constexpr int kGxBs = 2;
+// Each sum runs over y in order. One (b, s) per task: sharing Z across two halves the
+// tasks, and the pass needs the waves more than the loads.
+constexpr int kGxBs = 1;
 
 template <int F>
 __global__ __launch_bounds__(kThreads) void k_kp_grad_x(const KPDesc d) {

@@ -179,8 +179,9 @@ hipError_t kp_device(KPTables* t, DevArena* ar, bool with_grad, hipStream_t s) {
     ok(ar->alloc(&d.Yf, ns * B * S * n * F));
     if (with_grad) {
         ok(ar->alloc(&d.gZ, ns * n * n * F));
-        // enough (b, s) chunks for about 2^18 threads in the xy-gradient pass
-        d.zchunks = (int)std::max<size_t>(1, std::min<size_t>(B * S, (262144 + n * n - 1) / (n * n)));
+        // enough (b, s) chunks for about 4096 wave tasks (two rows by 64 columns) in the
+        // xy-gradient pass
+        d.zchunks = (int)std::max<size_t>(1, std::min<size_t>(B * S, (524288 + n * n - 1) / (n * n)));
         ok(ar->alloc(&d.zpart, (size_t)d.zchunks * ns * n * n * F));
         ok(ar->alloc(&d.gXA, ns * B * S * n * F));
         ok(ar->alloc(&d.gY, ns * B * S * n * F));
