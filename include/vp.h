@@ -246,12 +246,11 @@ vp_status vp_nu_adjoint(const vp_plan* plan, const vp_c64* d_samples, vp_c64* d_
                         void* stream);
 
 /* The fit of Section 4.3 on blade-aligned samples, as a resident session: the Cartesian
- * session's projection, fused gather and update, regularisers and step counter, with
- * the gridding passes above in place of the masked Cartesian DFT. samples: host
- * [B][Lmax][n] (the layout above; lines l >= L_b ignored); init as in
- * vp_session_create. Only VP_SCHED_ALL_BLADES (VP_ERR_UNSUPPORTED otherwise);
- * VP_ERR_NONFINITE if a used sample is NaN or Inf; VP_ERR_UNSUPPORTED if 2n is above
- * 512. Device memory: the Cartesian session's plus B (2n)^2 complex values and two
+ * session's projection, fused gather and update, regularisers, schedules (all blades or
+ * one per step, as in vp_reconstruct) and step counter, with the gridding passes above in
+ * place of the masked Cartesian DFT. samples: host [B][Lmax][n] (the layout above; lines
+ * l >= L_b ignored); init as in vp_session_create. VP_ERR_NONFINITE if a used sample is
+ * NaN or Inf; VP_ERR_UNSUPPORTED if 2n is above 512. Device memory: the Cartesian session's plus B (2n)^2 complex values and two
  * sample arrays, freed by vp_nu_session_destroy. */
 vp_status vp_nu_session_create(const vp_plan* plan, const vp_options* opts, const vp_c64* samples,
                                const vp_c64* init, vp_nu_session** out);

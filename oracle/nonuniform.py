@@ -26,8 +26,8 @@ import math
 import numpy as np
 import scipy.special
 
-from .lifted import (Geometry, adam_update, displacement, knot_weights, l1_grad, l1_value, project_blade, render,
-                     shear_transpose, tv_grad, tv_value, volume_at)
+from .lifted import (Geometry, adam_update, displacement, knot_weights, l1_grad, l1_value, project_blade,
+                     random_blade, render, shear_transpose, tv_grad, tv_value, volume_at)
 
 KB_WIDTH = 6.0
 KB_SIGMA = 2.0
@@ -138,12 +138,15 @@ def forward_nu(vol: np.ndarray, geom: Geometry, exact: bool = True) -> list:
     return out
 
 
-def gradient_nu(vol: np.ndarray, geom: Geometry, y: list, exact: bool = True):
-    """Gradient (dL/dRe + i dL/dIm) of 0.5 sum_b |samples_b(V) - y_b|^2 and its value."""
+def gradient_nu(vol: np.ndarray, geom: Geometry, y: list, exact: bool = True, blades=None):
+    """Gradient (dL/dRe + i dL/dIm) of 0.5 sum_b |samples_b(V) - y_b|^2 and its value, over
+    all blades or the listed ones."""
     n = geom.n
     grad = np.zeros((geom.n_time, geom.n_spec, n, n), dtype=np.complex128)
     total = 0.0
     for b, yb in enumerate(y):
+        if blades is not None and b not in blades:
+            continue
         theta = float(geom.angle_rad[b])
         kx, ky = blade_samples(n, theta, int(geom.lines[b]))
         p = project_blade(volume_at(vol, geom.tau(b)), geom, b)
@@ -164,9 +167,12 @@ def gradient_nu(vol: np.ndarray, geom: Geometry, y: list, exact: bool = True):
 def reconstruct_nu(geom: Geometry, y: list, n_steps: int, tv_weight: float = 1e-3, tv_eps: float = 1e-3,
                    l1_weight: float = 0.0, lr: float = 1e-2, beta1: float = 0.9, beta2: float = 0.999,
                    adam_eps: float = 1e-8, optimizer: str = "adam", exact: bool = True,
-                   data_weight: float = 1.0, split_bin: int = -1) -> dict:
+                   data_weight: float = 1.0, split_bin: int = -1, schedule: str = "all",
+                   seed: int = 0) -> dict:
     """The fit of Section 4.3 on blade-aligned samples: every step the gradient of the
-    weighted data term over all blades plus TV and L1, then Adam or GD; from zero."""
+    weighted data term plus TV and L1, then Adam or GD; from zero. The data term of step t
+    covers all blades, or one (blade (t - 1) mod B, or the seeded random draw of step t - 1,
+    as in the Cartesian fit); the final loss covers all blades."""
     vol = np.zeros((geom.n_time, geom.n_spec, geom.n, geom.n), dtype=np.complex128)
     m = np.zeros(vol.shape + (2,))
     v = np.zeros(vol.shape + (2,))
@@ -181,7 +187,13 @@ def reconstruct_nu(geom: Geometry, y: list, n_steps: int, tv_weight: float = 1e-
         return out
 
     for t in range(1, n_steps + 1):
-        g, _ = gradient_nu(vol, geom, y, exact)
+        if schedule == "all":
+            blades = None
+        elif schedule == "cyclic":
+            blades = [(t - 1) % geom.n_blades]
+        else:
+            blades = [random_blade(seed, t - 1, geom.n_blades)]
+        g, _ = gradient_nu(vol, geom, y, exact, blades)
         g = data_weight * g
         if tv_weight != 0.0:
             g = g + tv_weight * tv_grad(vol, tv_eps)

@@ -71,6 +71,7 @@ __global__ __launch_bounds__(kThreads) void k_nu_interp(const NuArgs d) {
     const long long total = (long long)d.B * per;
     const double h = 0.5 * (double)kNuWidth;
     const int sub = threadIdx.x % kRowLanes, slot = threadIdx.x / kRowLanes;
+    const int st = read_step(d.stepp);
     // block-uniform loop: every lane reaches every barrier
     for (long long base = (long long)blockIdx.x * kSamplesPerBlock; base < total;
          base += (long long)gridDim.x * kSamplesPerBlock) {
@@ -83,7 +84,8 @@ __global__ __launch_bounds__(kThreads) void k_nu_interp(const NuArgs d) {
             L = d.lines[b];
         }
         float2 acc = make_float2(0.f, 0.f);
-        if (e < total && l < L) {
+        const bool act = e < total && active_blade(d.sched, d.sseed, d.stepp, st, d.B, b);
+        if (act && l < L) {
             const double2 g = sample_pos(d.cs[b], j, l, n, L);
             int x0, x1, y0, y1;
             axis_window(g.x, h, x0, x1);
@@ -101,7 +103,7 @@ __global__ __launch_bounds__(kThreads) void k_nu_interp(const NuArgs d) {
         __syncthreads();
         if (sub == 0 && e < total) {
             float2 v = make_float2(0.f, 0.f), w = v;
-            if (l < L) {
+            if (act && l < L) {
 #pragma unroll
                 for (int r = 0; r < kRowLanes; ++r) v = cadd(v, part[threadIdx.x + r]);
                 const float2 p = d.ph[e];
@@ -148,8 +150,11 @@ __global__ __launch_bounds__(kThreads) void k_nu_spread(const NuArgs d) {
     const long long total = (long long)d.B * MM;
     const double h = 0.5 * (double)kNuWidth;
     const double H = h / (double)kNuSigma;  // the window's half-width in lattice units
+    const int st = read_step(d.stepp);
     for (long long e = gtid(); e < total; e += gstride()) {
         const int b = (int)(e / MM);
+        // an inactive blade's grid is never read (its inverse passes and gather skip it)
+        if (!active_blade(d.sched, d.sseed, d.stepp, st, d.B, b)) continue;
         const int py = (int)((e % MM) / M), px = (int)(e % M);
         const double2 cs = d.cs[b];
         const double c = cs.x, s = cs.y;

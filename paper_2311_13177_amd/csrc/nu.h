@@ -26,6 +26,11 @@ struct NuArgs {
                             // written by interp (of its residual, when not null) or prep
     float dw;               // data-term weight of a fit; 1 for the operator
     float* loss;            // per-block sums of |out|^2 (interp with loss), or null
+    // one-blade schedules of a fit: interp and spread skip the blades that are not active
+    // at the device step counter (all blades when stepp is null or sched is all-blades)
+    int sched;
+    unsigned sseed;
+    const int* stepp;
 };
 
 hipError_t nu_launch_interp(const NuArgs& d, hipStream_t s);

@@ -406,6 +406,10 @@ struct NuScope {
     const NuHost* h = nullptr;
     float2* grid = nullptr;
     const Task* t_img_rows = nullptr;  // row-pass tasks over the image's rows only
+    // a fit's one-blade schedule: the DFT passes skip inactive blades as the other passes do
+    int sched = VP_SCHED_ALL_BLADES;
+    unsigned sseed = 0;
+    int* stepp = nullptr;
     hipStream_t s;
     bool persistent = false;  // grids from hipMalloc (a fit), else stream-ordered (an operator call)
     NuArgs d{};
@@ -448,6 +452,10 @@ struct NuScope {
         a.nue.blade = d.blade;
         a.nue.dea = d.dea;
         a.nue.parts = d.nparts;
+        a.one.schedule = sched;
+        a.one.sched_seed = sseed;
+        a.one.step = stepp;
+        a.one.step_limit = 0x7fffffff;
         a.mode = which < 2 ? COL_RAW_FWD : COL_INVERSE;
         if (which == 1 || which == 2) {
             a.tasks = L.cols; a.ntasks = L.n_cols;
@@ -561,13 +569,28 @@ struct vp_nu_session {
             if (q) (void)hipFree(q);
     }
 
-    // projection to residual samples (and their loss partials) at the current volume;
-    // ev (may be null) gets events 0..3 before the first four stages
-    hipError_t forward(hipEvent_t* ev) {
+    // the schedule the gridding passes follow: the fit's, or all blades (the objective)
+    void schedule(bool all) {
+        nu.sched = all ? (int)VP_SCHED_ALL_BLADES : s->opts.schedule;
+        nu.sseed = s->opts.seed;
+        nu.stepp = s->desc.step;
+        nu.d.sched = nu.sched;
+        nu.d.sseed = nu.sseed;
+        nu.d.stepp = nu.stepp;
+    }
+
+    // projection to residual samples (and their loss partials) at the current volume, over
+    // the fit's blades or all of them; ev (may be null) gets events 0..3 before the first
+    // four stages
+    hipError_t forward(hipEvent_t* ev, bool all = false) {
         const StageLists& L = s->lists;
         const hipStream_t str = s->stream;
         KArgs a{};
         a.one = s->desc;
+        if (all) {
+            a.one.schedule = VP_SCHED_ALL_BLADES;
+            a.one.step_limit = 0x7fffffff;
+        }
         a.tasks = L.proj; a.ntasks = L.n_proj;
         hipError_t r = ev ? hipEventRecord(ev[0], str) : hipSuccess;
         if (r == hipSuccess) r = launch_project(a, L.tiles.proj_rows, L.tiles.proj_gw, L.re_proj, str);
@@ -618,8 +641,6 @@ extern "C" vp_status vp_nu_session_create(const vp_plan* p, const vp_options* o,
     *out = nullptr;
     vp_status st = check_options(p, o);
     if (st != VP_OK) return st;
-    if (o->schedule != VP_SCHED_ALL_BLADES)
-        return fail(VP_ERR_UNSUPPORTED, "vp_nu_session_create: only the all-blades schedule is supported");
     const NuHost* h = nullptr;
     const vp_plan* q = nullptr;
     if ((st = plan_nu(p, &h, &q)) != VP_OK) return st;
@@ -659,6 +680,7 @@ extern "C" vp_status vp_nu_session_create(const vp_plan* p, const vp_options* o,
     d.out = x->res;
     d.dw = o->data_weight;  // interp writes the spread's input to d.pre
     d.loss = x->loss;
+    x->schedule(false);
     *out = ns_.release();
     return VP_OK;
 }
@@ -720,7 +742,9 @@ extern "C" vp_status vp_nu_session_read(vp_nu_session* x, vp_c64* volume_out, vp
     if (objective) {
         vp_session* s = x->s.get();
         const vp_plan* p = s->plan;
-        e = x->forward(nullptr);
+        x->schedule(true);
+        e = x->forward(nullptr, true);
+        x->schedule(false);
         KArgs a{};
         a.one = s->desc;
         a.tasks = s->lists.vox; a.ntasks = s->lists.n_vox; a.dpart = s->dpart;

@@ -117,3 +117,19 @@ def test_fit_on_axis_aligned_blades_is_the_cartesian_fit():
     c = O.reconstruct(geom, ygrid, 4, tv_weight=0.01, data_weight=1.5)
     assert np.allclose(a["vol"], c["vol"], atol=1e-10)
     assert math.isclose(a["final_loss"], c["final_loss"], rel_tol=1e-10)
+
+
+@pytest.mark.parametrize("schedule", ["cyclic", "random"])
+def test_one_blade_fit_on_axis_aligned_blades_is_the_cartesian_one(schedule):
+    rng = np.random.default_rng(7)
+    n = 12
+    geom = _geom(n=n, angles=(0.0, math.pi / 2), lines=(4, 6))
+    ygrid = O.blade_masks(geom) * _crandn(rng, 2, n, n)
+    y = []
+    for b in range(2):
+        kx, ky = N.blade_samples(n, float(geom.angle_rad[b]), int(geom.lines[b]))
+        y.append(ygrid[b][np.rint(ky).astype(int) % n, np.rint(kx).astype(int) % n])
+    a = N.reconstruct_nu(geom, y, 5, tv_weight=0.01, schedule=schedule, seed=9)
+    c = O.reconstruct(geom, ygrid, 5, tv_weight=0.01, schedule=schedule, seed=9)
+    assert np.allclose(a["vol"], c["vol"], atol=1e-10)
+    assert math.isclose(a["final_loss"], c["final_loss"], rel_tol=1e-10)
