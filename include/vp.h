@@ -284,6 +284,17 @@ vp_status vp_nu_reconstruct(const vp_plan* plan, const vp_options* opts, const v
 vp_status vp_tv_grad(const vp_plan* plan, const vp_c64* d_vol, float tv_weight, float l1_weight, float tv_eps,
                      vp_c64* d_grad, int32_t accumulate, void* stream);
 
+/* One optimiser step of Section 4.3 on caller-held state: g = d_grad (the data-term
+ * gradient as dL/dRe + i dL/dIm, e.g. from vp_adjoint, weighted by the caller) +
+ * tv_weight grad TV(d_vol) + l1_weight grad L1(d_vol) (weights and eps from opts), then
+ * opts' optimiser: Adam with the bias corrections of step t >= 1 and the moments d_m,
+ * d_v (each [T][S][n][n] of (re, im) pairs, updated in place; NULL allowed for GD) or GD.
+ * The new volume goes to d_vol_out, which must not overlap d_vol (the TV stencil reads
+ * the old one). The same per-voxel arithmetic as the update of vp_reconstruct. Device
+ * pointers on the plan's device, asynchronous on `stream`. */
+vp_status vp_step(const vp_plan* plan, const vp_options* opts, const vp_c64* d_vol, const vp_c64* d_grad,
+                  vp_c64* d_m, vp_c64* d_v, int64_t t, vp_c64* d_vol_out, void* stream);
+
 /* Section 4.3 render at phi = 0 and the Section 6 split: d_proj[t] = sum over
  * all bins, d_water = bins [0, split), d_fat = bins [split, S); split_bin < 0
  * means S/2. Any output may be NULL. */

@@ -114,6 +114,7 @@ _PROTOS = {
     "vp_baseline": (c_int32, [_P, _P, c_int32, c_int32, c_int32, _P, _P]),
     "vp_nu_forward": (c_int32, [_P, _P, _P, _P, _P]),
     "vp_nu_adjoint": (c_int32, [_P, _P, _P, c_int32, _P]),
+    "vp_step": (c_int32, [_P, POINTER(vp_options), _P, _P, _P, _P, c_int64, _P, _P]),
     "vp_nu_reconstruct": (c_int32, [_P, POINTER(vp_options), _P, _P, _P, _P, _P, _P, POINTER(c_double)]),
     "vp_nu_session_create": (c_int32, [_P, POINTER(vp_options), _P, _P, POINTER(c_void_p)]),
     "vp_nu_session_step": (c_int32, [_P, c_int32, c_int32]),
@@ -402,6 +403,20 @@ def vp_nu_reconstruct(plan: Plan, samples: np.ndarray, opts: Optional[vp_options
     check(lib().vp_nu_reconstruct(plan.handle, byref(opts), _hp(y), _hp(i), _hp(vol), *[_hp(o) for o in outs],
                                   byref(loss)))
     return dict(vol=vol, proj=outs[0], water=outs[1], fat=outs[2], final_loss=float(loss.value))
+
+
+def vp_step(plan: Plan, opts: vp_options, vol, grad, m=None, v=None, t: int = 1, out=None, stream=None):
+    """One optimiser step on GPU tensors: returns the new volume (m and v update in place)."""
+    import torch
+
+    if out is None:
+        out = torch.empty_like(vol)
+    check(lib().vp_step(plan.handle, byref(opts), _dev(vol, plan.volume_shape, "vol"),
+                        _dev(grad, plan.volume_shape, "grad"),
+                        None if m is None else _dev(m, plan.volume_shape, "m"),
+                        None if v is None else _dev(v, plan.volume_shape, "v"), int(t),
+                        _dev(out, plan.volume_shape, "out"), _stream(stream)))
+    return out
 
 
 NU_STAGES = ("project", "rows_fwd", "cols_fwd", "interp", "spread", "cols_inv", "rows_inv", "gather_update")

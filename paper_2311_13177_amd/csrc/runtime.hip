@@ -810,6 +810,59 @@ extern "C" vp_status vp_tv_grad(const vp_plan* p, const vp_c64* d_vol, float tv_
     return hip_status(e, "vp_tv_grad");
 }
 
+namespace {
+__global__ void k_set_counter(int* p, int v) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *p = v;
+}
+}  // namespace
+
+extern "C" vp_status vp_step(const vp_plan* p, const vp_options* o, const vp_c64* d_vol, const vp_c64* d_grad,
+                             vp_c64* d_m, vp_c64* d_v, int64_t t, vp_c64* d_vol_out, void* stream) {
+    clear_error();
+    if (!p || !o || !d_vol || !d_grad || !d_vol_out) return fail(VP_ERR_ARG, "vp_step: NULL argument");
+    vp_status st = check_options(p, o);
+    if (st != VP_OK) return st;
+    if (o->optimizer == VP_OPT_ADAM && (!d_m || !d_v)) return fail(VP_ERR_ARG, "vp_step: Adam needs d_m and d_v");
+    if (t < 1 || t > 0x7fffffff) return fail(VP_ERR_ARG, "vp_step: t must be in [1, 2^31 - 1]");
+    const uintptr_t bytes = (uintptr_t)p->voxels() * sizeof(float2);
+    const uintptr_t a0 = (uintptr_t)d_vol, b0 = (uintptr_t)d_vol_out;
+    if (a0 < b0 + bytes && b0 < a0 + bytes) return fail(VP_ERR_ARG, "vp_step: d_vol_out overlaps d_vol");
+    OpScope sc(p, stream);
+    if ((st = sc.begin(false)) != VP_OK) return st;
+    // the update pass of the current shape, or of four bins per wave where the shape fuses it
+    Tiles tl = sc.lay->tiles;
+    if (tl.upd_sc == 0) tl.upd_sc = 4;
+    const Layout* lay = nullptr;
+    const DeviceLayout* dl = nullptr;
+    if ((st = plan_layout(p, tl, &lay)) != VP_OK || (st = device_layout(p, sc.t, lay, &dl)) != VP_OK) return st;
+    KArgs a{};
+    fill_desc(p, sc.t, lay, dl, &a.one);
+    set_hyper(&a.one, o);
+    a.one.schedule = VP_SCHED_ALL_BLADES;
+    // the pass reads vol[s & 1] and writes vol[(s + 1) & 1] at step counter s = t - 1
+    const int s0 = (int)(t - 1);
+    a.one.vol[s0 & 1] = (float2*)d_vol;
+    a.one.vol[(s0 + 1) & 1] = (float2*)d_vol_out;
+    a.one.grad = (float2*)d_grad;
+    a.one.m = (float2*)d_m;
+    a.one.v = (float2*)d_v;
+    a.one.step_limit = 0x7fffffff;
+    int* cnt = nullptr;
+    hipError_t e = hipMallocAsync((void**)&cnt, 256, sc.s);
+    if (e != hipSuccess) return hip_status(e, "vp_step counter");
+    hipLaunchKernelGGL(k_set_counter, dim3(1), dim3(64), 0, sc.s, cnt, s0);
+    e = hipGetLastError();
+    a.one.step = cnt;
+    const StageLists L = plan_lists(p, sc.t, lay, dl);
+    a.epi = epi_for(o->optimizer, o->tv_weight, o->l1_weight);
+    a.tasks = L.upd;
+    a.ntasks = L.n_upd;
+    if (e == hipSuccess) e = launch_update(a, tl.upd_sc, sc.s);
+    const hipError_t fe = hipFreeAsync(cnt, sc.s);
+    if (e == hipSuccess) e = fe;
+    return hip_status(e, "vp_step");
+}
+
 extern "C" vp_status vp_render(const vp_plan* p, const vp_c64* d_vol, int32_t split_bin, vp_c64* d_proj,
                                vp_c64* d_water, vp_c64* d_fat, void* stream) {
     clear_error();

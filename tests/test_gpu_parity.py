@@ -320,3 +320,63 @@ def test_batch_equals_solo_bitwise(gpu_lib):
         assert np.array_equal(r["vol"], solo["vol"])
         assert np.array_equal(r["proj"], solo["proj"])
         assert r["final_loss"] == solo["final_loss"]
+
+
+@pytest.mark.parametrize("name", ["static_48", "dynamic_40"])
+def test_step_operator_matches_oracle(gpu_lib, name):
+    """vp_step: data gradient + TV + L1, then Adam with step t's bias corrections (three
+    steps, moments carried on the device) or GD, against the oracle's update."""
+    import torch
+    from paper_2311_13177_amd import binding as B
+
+    case = small(name)
+    plan = B.Plan.from_geometry(case.geometry())
+    vol = _random_volume(case, seed=8) * 0.1
+    grads = [_random_volume(case, seed=20 + t) * 0.05 for t in range(3)]
+    opts = B.vp_options_default(tv_weight=1e-2, l1_weight=1e-3, lr=1e-2)
+    cur = _t(vol)
+    m = torch.zeros_like(cur)
+    v = torch.zeros_like(cur)
+    ref = vol.astype(np.complex128)
+    mr = np.zeros(ref.shape + (2,))
+    vr = np.zeros(ref.shape + (2,))
+    for t in range(1, 4):
+        cur = B.vp_step(plan, opts, cur, _t(grads[t - 1]), m, v, t)
+        g = (grads[t - 1].astype(np.complex128) + opts.tv_weight * O.tv_grad(ref, opts.tv_eps)
+             + opts.l1_weight * O.l1_grad(ref, opts.tv_eps))
+        ref, mr, vr = O.adam_update(ref, g, mr, vr, t, opts.lr, opts.beta1, opts.beta2, opts.adam_eps)
+    assert rel(_np(cur), ref) < FWD_TOL
+    assert rel(_np(m), mr[..., 0] + 1j * mr[..., 1]) < FWD_TOL
+    assert rel(_np(v), vr[..., 0] + 1j * vr[..., 1]) < FWD_TOL
+    gd = B.vp_options_default(tv_weight=1e-2, optimizer=B.VP_OPT_GD, lr=0.3)
+    got = _np(B.vp_step(plan, gd, _t(vol), _t(grads[0])))
+    v64 = vol.astype(np.complex128)
+    want = v64 - 0.3 * (grads[0].astype(np.complex128) + 1e-2 * O.tv_grad(v64, gd.tv_eps))
+    assert rel(got, want) < FWD_TOL
+    # errors: overlapping output, Adam without moments, t < 1
+    x = _t(vol)
+    for kw in (dict(out=x), dict(m=None), dict(t=0)):
+        args = dict(m=m, v=v, t=1)
+        args.update(kw)
+        with pytest.raises(B.VPError) as ex:
+            B.vp_step(plan, opts, x, _t(grads[0]), **args)
+        assert ex.value.status == B.VP_ERR_ARG
+
+
+def test_operator_loop_equals_reconstruct(gpu_lib):
+    """GD driven from Python through vp_forward, vp_adjoint and vp_step follows the fused
+    reconstruction (same operators, different fusion: rounding-level agreement)."""
+    import torch
+    from paper_2311_13177_amd import binding as B
+
+    case = small("dynamic_40")
+    y = O.simulate_measurements(case)
+    plan = B.Plan.from_geometry(case.geometry())
+    gd = B.vp_options_default(n_steps=4, optimizer=B.VP_OPT_GD, lr=0.5 / (case.n_spec * case.n_blades))
+    want = B.vp_reconstruct(plan, y, gd)
+    vol = torch.zeros(plan.volume_shape, dtype=torch.complex64, device="cuda")
+    dy = _t(y)
+    for t in range(1, 5):
+        r = B.vp_forward(plan, vol, dy)
+        vol = B.vp_step(plan, gd, vol, B.vp_adjoint(plan, r), t=t)
+    assert rel(_np(vol), want["vol"]) < 1e-5
