@@ -43,6 +43,7 @@ def parse_args(argv=None):
     ap.add_argument("--no-kplanes", action="store_true", help="skip the K-Planes dynamic model leg")
     ap.add_argument("--no-dynamic", action="store_true", help="skip the dynamic 192^2 x 32 x 16 leg")
     ap.add_argument("--no-nu", action="store_true", help="skip the blade-aligned sampling fit leg")
+    ap.add_argument("--no-shard", action="store_true", help="skip the one-GPU share of a spectral split")
     ap.add_argument("--batch-slices", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--no-serve", action="store_true", help="skip the served-stream leg")
@@ -307,6 +308,49 @@ def nu_leg(B, name, steps, warmup):
             "quality": {"psnr_db": round(float(np.mean(p_fit)), 2), "steps": case.n_steps}}
 
 
+def shard_leg(B, name, gpus, steps, warmup):
+    """One GPU's share of a spectral split of one volume over `gpus` GPUs (the sharding
+    design): the workload's geometry restricted to the last S / gpus bins (the largest
+    shifts, so the widest halos), stepped as one slice. Each GPU would also run the blade
+    DFT passes on the all-reduced blade images (counted here, redundantly per GPU) and
+    swap one TV halo plane with each spectral neighbour; the all-reduce itself is not
+    run (one GPU) and is reported as an estimate over xGMI."""
+    import numpy as np
+    import torch
+
+    from synth import configs
+
+    case = configs.CONFIGS[name]()
+    g = case.geometry()
+    S = case.n_spec
+    share = S // gpus
+    g["n_spec"] = share
+    g["spec_shift_px"] = np.asarray(g["spec_shift_px"])[S - share:]
+    plan = B.Plan.from_geometry(g)
+    rng = np.random.default_rng(case.seed)
+    y = ((rng.standard_normal(plan.blade_shape) + 1j * rng.standard_normal(plan.blade_shape))
+         * plan.masks()).astype(np.complex64)
+    opts = B.vp_options_default(n_steps=case.n_steps, tv_weight=case.tv_weight, lr=case.lr, device=0, autotune=1)
+    plan.tune(opts)
+    sess = B.Session(plan, y, opts)
+    sess.step(warmup, use_graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sess.step(steps, use_graph=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    stages = sess.stage_times(max(3, steps // 4))
+    sess.close()
+    # ring all-reduce of the B blade images (complex64) over 7 xGMI links of about 153 GB/s
+    ar_bytes = 8 * case.n_blades * case.n * case.n
+    ring_us = 2 * (gpus - 1) / gpus * ar_bytes / 153e9 * 1e6
+    return {"workload": f"{name} geometry, bins {S - share}..{S - 1} of {S} (one GPU of a {gpus}-way spectral split)",
+            "ms_per_step": round(el * 1e3 / steps, 5), "steps": steps,
+            "stage_ms": {k: round(v, 5) for k, v in stages.items()},
+            "allreduce_bytes": ar_bytes, "allreduce_ring_us_estimate": round(ring_us, 1),
+            "note": "measured on one GPU; the collective is an estimate, not run"}
+
+
 def served_leg(B, n_req, steps_static, steps_dynamic, seed=5000, slots=8):
     """A Poisson request stream of mixed static/dynamic reconstructions through the server."""
     import numpy as np
@@ -557,6 +601,8 @@ def main(argv=None):
         out["kplanes_192"] = kplanes_leg(B, max(20, args.steps // 8), 3)
     if not args.no_nu:
         out["nu_256"] = nu_leg(B, "static_256", max(20, args.steps // 4), 3)
+    if not args.no_shard:
+        out["shard_share_192"] = shard_leg(B, "dynamic_192", 8, max(20, args.steps // 4), 3)
     if not args.no_batch:
         out["batched"] = batched_leg(B, args.batch_slices, args.batch_steps)
     if not args.no_serve:
