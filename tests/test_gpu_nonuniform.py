@@ -266,3 +266,51 @@ def test_full_size_gd_descends(gpu_lib):
         vals.append(sess.read(objective=True)["objective"])
     sess.close()
     assert all(b < a for a, b in zip(vals, vals[1:])), vals
+
+
+def _ragged(n, lines, n_time):
+    case = configs.small_case(n=n, n_spec=3, n_blades=len(lines), lines=max(lines), n_time=n_time)
+    g = case.geometry()
+    g["lines"] = np.asarray(lines, dtype=np.int32)
+    return g
+
+
+@pytest.mark.parametrize("n,lines,n_time", [(50, (6, 11, 9, 14, 7), 1), (45, (8, 9, 8), 1), (36, (5, 12, 7, 10), 3)])
+def test_ragged_lines_and_odd_sizes(gpu_lib, n, lines, n_time):
+    # blades of different line counts (the [B][Lmax][n] arrays carry padding lines) and an
+    # odd image size (centring by floor(n/2)); padding lines are written as zero by the
+    # forward and ignored by the adjoint and the fit
+    import torch
+    from paper_2311_13177_amd import binding as B
+
+    g = _ragged(n, lines, n_time)
+    plan = B.Plan.from_geometry(g)
+    geom = O.Geometry.from_dict(g)
+    shp = B.nu_shape(plan)
+    assert shp == (len(lines), max(lines), n)
+    rng = np.random.default_rng(n)
+    vol = (rng.standard_normal(plan.volume_shape) + 1j * rng.standard_normal(plan.volume_shape)).astype(np.complex64)
+    v64 = vol.astype(np.complex128)
+    got = B.vp_nu_forward(plan, torch.from_numpy(vol).cuda()).cpu().numpy()
+    assert _rel(got, _pack(N.forward_nu(v64, geom, exact=False), shp)) <= 1e-4
+    assert _rel(got, _pack(N.forward_nu(v64, geom, exact=True), shp)) <= 1e-4
+    for b, L in enumerate(lines):
+        assert not np.any(got[b, L:])
+    s = (rng.standard_normal(shp) + 1j * rng.standard_normal(shp)).astype(np.complex64)
+    ys = [-s[b, :L].astype(np.complex128) for b, L in enumerate(lines)]
+    for b, L in enumerate(lines):
+        s[b, L:] = 1e3 + 7j  # padding: must be ignored
+    adj = B.vp_nu_adjoint(plan, torch.from_numpy(s).cuda()).cpu().numpy()
+    want, _ = N.gradient_nu(np.zeros(plan.volume_shape, dtype=np.complex128), geom, ys, exact=False)
+    assert _rel(adj, want) <= 1e-4
+    # a short GD fit on the definition's samples of a random volume
+    y = N.forward_nu(v64 * 0.1, geom, exact=True)
+    packed = _pack(y, shp).astype(np.complex64)
+    for b, L in enumerate(lines):
+        packed[b, L:] = -5.0  # padding again
+    opts = B.vp_options_default(n_steps=5, optimizer=1, lr=0.5 / (3 * len(lines)))
+    fit = B.vp_nu_reconstruct(plan, packed, opts)
+    ref = N.reconstruct_nu(geom, y, 5, tv_weight=opts.tv_weight, tv_eps=opts.tv_eps, lr=opts.lr, optimizer="gd",
+                           exact=False)
+    assert _rel(fit["vol"], ref["vol"]) < 1e-4
+    assert abs(fit["final_loss"] - ref["final_loss"]) <= 1e-3 * abs(ref["final_loss"])
