@@ -4,8 +4,9 @@
 blade (Section 4.2 of the paper) through ``vp_forward``; its backward applies the
 hand-written adjoint ``vp_adjoint`` (mask, unitary inverse DFT, transposed shear
 gather), so ``loss.backward()`` yields dL/dRe + i dL/dIm of the volume, torch's
-convention for complex parameters. Both directions run on the caller's current
-stream; torch only provides the memory.
+convention for complex parameters. ``BladeAlignedForward`` does the same for samples on
+each blade's rotated lattice (the gridding operators). Both directions run on the
+caller's current stream; torch only provides the memory.
 """
 
 from __future__ import annotations
@@ -48,6 +49,25 @@ class Regulariser(torch.autograd.Function):
         grad = grad_out.contiguous().clone()
         B.vp_tv_grad(plan, vol.contiguous(), tv_w, l1_w, eps, grad, accumulate=True)
         return grad, None, None, None, None
+
+
+class BladeAlignedForward(torch.autograd.Function):
+    """The lifted model sampled on each blade's own rotated lattice (``vp_nu_forward``,
+    samples [B][Lmax][n], lines beyond a blade's count zero) minus y; its backward is the
+    exact transpose ``vp_nu_adjoint`` (padding lines of the incoming gradient ignored)."""
+
+    @staticmethod
+    def forward(ctx, vol: torch.Tensor, plan: "B.Plan", y: torch.Tensor | None = None) -> torch.Tensor:
+        ctx.plan = plan
+        return B.vp_nu_forward(plan, vol.contiguous(), None if y is None else y.contiguous())
+
+    @staticmethod
+    def backward(ctx, grad_out: torch.Tensor):
+        return B.vp_nu_adjoint(ctx.plan, grad_out.contiguous()), None, None
+
+
+def blade_aligned_forward(vol: torch.Tensor, plan: "B.Plan", y: torch.Tensor | None = None) -> torch.Tensor:
+    return BladeAlignedForward.apply(vol, plan, y)
 
 
 def lifted_forward(vol: torch.Tensor, plan: "B.Plan", y: torch.Tensor | None = None) -> torch.Tensor:

@@ -95,3 +95,42 @@ def test_regulariser_function_matches_oracle(gpu_lib):
     g_or, _ = O.gradient(v0.astype(np.complex128), geom, y, 1e-2, 1e-3, 1e-3)
     g = vol.grad.cpu().numpy().astype(np.complex128)
     assert np.linalg.norm(g - g_or) <= 1e-4 * np.linalg.norm(g_or)
+
+
+def test_blade_aligned_autograd_matches_oracle_and_fd(gpu_lib):
+    # loss = 0.5 sum |A_nu vol - y|^2 through BladeAlignedForward: its gradient against the
+    # oracle's gridding gradient, and a central difference of the loss along a random
+    # direction (exact for a quadratic up to rounding)
+    import torch
+
+    from oracle import nonuniform as N
+    from paper_2311_13177_amd import autograd as AG
+    from paper_2311_13177_amd import binding as B
+
+    case = configs.small_case(n=48, n_spec=4, n_time=3, n_blades=5, lines=10)
+    plan = B.Plan.from_geometry(case.geometry())
+    geom = O.Geometry.from_dict(case.geometry())
+    rng = np.random.default_rng(31)
+    vol = _rand(rng, plan.volume_shape, 0.3)
+    shp = B.nu_shape(plan)
+    y = _rand(rng, shp)
+    x = _t(vol).requires_grad_(True)
+    r = AG.blade_aligned_forward(x, plan, _t(y))
+    loss = 0.5 * torch.sum(torch.view_as_real(r).to(torch.float64) ** 2)
+    loss.backward()
+    g = x.grad.cpu().numpy().astype(np.complex128)
+    want, val = N.gradient_nu(vol.astype(np.complex128), geom, [y[b].astype(np.complex128) for b in range(shp[0])],
+                              exact=False)
+    assert np.linalg.norm(g - want) <= 1e-4 * np.linalg.norm(want)
+    assert abs(float(loss.detach()) - val) <= 1e-4 * val
+    d = _rand(rng, plan.volume_shape)
+    h = 1e-2
+
+    def f(v):
+        with torch.no_grad():
+            rr = B.vp_nu_forward(plan, _t(v), _t(y)).cpu().numpy().astype(np.complex128)
+        return 0.5 * float(np.sum(np.abs(rr) ** 2))
+
+    fd = (f(vol + h * d) - f(vol - h * d)) / (2 * h)
+    an = float(np.sum((np.conj(g) * d.astype(np.complex128)).real))
+    assert abs(fd - an) <= 1e-3 * abs(an)
