@@ -3,7 +3,10 @@
 Decode is a product of six interpolated FP32 factors summed over features and scales
 (relative error about 1e-6), so it is held to 1e-5 relative over the whole volume; the
 gradient goes through the FP32 DFTs as well and takes the operator tolerance, 1e-4;
-short fits compare the parameters (GD, 1e-4) and the rendered frames (Adam, 1e-3).
+short fits compare the parameters (GD, 1e-4) and the rendered frames (Adam, 1e-3). At the
+benchmark's full size the decode is compared at two blade times and the gradient by
+central differences along directions that move one grid (exact for the then quadratic
+objective).
 """
 
 import math
@@ -151,3 +154,49 @@ def test_degenerate_grids_and_a_single_blade(gpu_lib):
         gr, obj, _ = B.vp_kplanes_gradient(plan, model, dp, torch.from_numpy(np.ascontiguousarray(y)).cuda())
         wv, wg, _ = K.objective_and_gradient(p.astype(np.complex128), _kp_geom(geom), y, cfg, 0.01, 0.02, 0.005, 1e-2)
         assert _rel(gr.cpu().numpy(), wg) <= 1e-4 and math.isclose(obj, wv, rel_tol=1e-5), (F, Rt, res)
+
+
+def test_full_size_decode_and_gradient(gpu_lib):
+    # the benchmark's model on the dynamic 192^2 x 32-bin, 32-blade geometry (F 8, 16 time
+    # nodes, scales 192 and 96), in the benchmark's launch configuration: the decoded
+    # volume at two blade times against the oracle, and the gradient against a central
+    # difference of the GPU objective along a random direction
+    import torch
+    from paper_2311_13177_amd import binding as B
+
+    case = configs.dynamic_192()
+    plan = B.Plan.from_geometry(case.geometry())
+    geom = O.Geometry.from_dict(case.geometry())
+    res = (case.n, case.n // 2)
+    cfg = K.KPConfig(features=8, time_res=case.n_time, spatial_res=res)
+    model = B.vp_kplanes.make(8, case.n_time, res, 1e-1, 1e-2, 1e-3, 1e-3)
+    count = B.kplanes_param_count(plan, model)
+    assert count == K.layout(case.n_spec, cfg)[2]
+    rng = np.random.default_rng(41)
+    p = ((rng.standard_normal(count) + 1j * rng.standard_normal(count)) * 0.3).astype(np.complex64)
+    dp = torch.from_numpy(p).cuda()
+    times = [float(geom.blade_time[3]), float(geom.blade_time[17])]
+    got = B.vp_kplanes_decode(plan, model, dp, times).cpu().numpy()
+    for i, tau in enumerate(times):
+        want = K.decode(p.astype(np.complex128), case.n, case.n_spec, cfg, tau)
+        assert _rel(got[i], want) < 1e-5
+    # without the regularisers the decoded volume is linear in any single grid (and in the
+    # weights a), so the objective is exactly quadratic along a direction that moves only
+    # one of them and the central difference is exact up to rounding
+    plain = B.vp_kplanes.make(8, case.n_time, res, 0.0, 0.0, 0.0, 1e-3)
+    y = torch.from_numpy(O.simulate_measurements(case)).cuda()
+    g, obj, _ = B.vp_kplanes_gradient(plan, plain, dp, y)
+    g = g.cpu().numpy().astype(np.complex128)
+    scales, a_off, _ = K.layout(case.n_spec, cfg)
+
+    def f(q):
+        return B.vp_kplanes_gradient(plan, plain, torch.from_numpy(q.astype(np.complex64)).cuda(), y)[1]
+
+    for lo, hi in ((a_off, a_off + 8), scales[1]["xy"][0:1] + (scales[1]["xy"][0] + int(np.prod(scales[1]["xy"][1])),),
+                   scales[0]["st"][0:1] + (scales[0]["st"][0] + int(np.prod(scales[0]["st"][1])),)):
+        d = np.zeros(count, dtype=np.complex64)
+        d[lo:hi] = (rng.standard_normal(hi - lo) + 1j * rng.standard_normal(hi - lo)).astype(np.complex64)
+        slope = float(np.sum((np.conj(g) * d).real))
+        h = 0.05 * obj / abs(slope)
+        fd = (f(p + h * d) - f(p - h * d)) / (2 * h)
+        assert abs(fd - slope) <= 1e-3 * abs(slope), (lo, hi, fd, slope)
