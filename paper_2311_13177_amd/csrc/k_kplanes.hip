@@ -382,54 +382,52 @@ __global__ __launch_bounds__(kThreads) void k_kp_grad_x(const KPDesc d) {
     }
 }
 
-// gY[c][b][s][y][f] = sum_x conj(Z XA) G[b][s][y][x]: one wave per 32/F consecutive rows
-// (b, s, y), lanes over x; the wave's 64 partial sums per lane (rows x features x re/im)
-// are reduced across lanes by recursive halving, each step sending the half a lane gives
-// up to its partner, so that lane L ends with the total of value L (a fixed order).
+// gY[c][b][s][y][f] = sum_x conj(Z XA) G[b][s][y][x]: one wave per block of 32 / F rows,
+// RB consecutive (b, s) by RY consecutive y (each Z value serves the RB (b, s), each XA
+// value the RY rows), lanes over x; the wave's 64 partial sums per lane (rows x features x
+// re/im) are reduced across lanes by recursive halving, each step sending the half a lane
+// gives up to its partner, so that lane L ends with the total of value L (a fixed order).
 template <int F>
 __global__ __launch_bounds__(kThreads) void k_kp_grad_y(const KPDesc d) {
     constexpr int RW = 32 / F;  // rows per wave: 2 F RW = 64 values
-    const int n = d.n, S = d.S;
+    constexpr int RY = RW >= 16 ? 4 : (RW >= 4 ? 2 : 1);
+    constexpr int RB = RW / RY;
+    const int n = d.n;
     const int lane = threadIdx.x & 63;
-    const long long rows = (long long)d.B * S * n;
-    const long long groups = (rows + RW - 1) / RW;
+    const int nbs = d.B * d.S;
+    const long long nyb = (n + RY - 1) / RY, nbb = (nbs + RB - 1) / RB;
+    const long long groups = nbb * nyb;
     for (long long gi = (long long)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); gi < groups;
          gi += (long long)gridDim.x * (kThreads / 64)) {
-        // the wave's rows usually share one (b, s), and with it their XA values (per x):
-        // then those are loaded once per column for all RW rows
-        const long long row0 = gi * RW;
-        const bool one_bs = (min(row0 + RW, rows) - 1) / n == row0 / n;
+        const int y0 = (int)(gi % nyb) * RY;
+        const int bs0 = (int)(gi / nyb) * RB;
         for (int c = 0; c < d.ns; ++c) {
             float v[64];
 #pragma unroll
             for (int i = 0; i < 64; ++i) v[i] = 0.f;
             for (int x = lane; x < n; x += 64) {
-                float2 xs[F];
-                if (one_bs) {
-                    const float2* xa = d.XA + (((long long)c * d.B * S + row0 / n) * n + x) * F;
+                float2 zr[RY][F], xr[RB][F];
 #pragma unroll
-                    for (int f = 0; f < F; ++f) xs[f] = xa[f];
+                for (int q = 0; q < RY; ++q) {
+                    const float2* z = d.Z + (((long long)c * n + min(y0 + q, n - 1)) * n + x) * F;
+#pragma unroll
+                    for (int f = 0; f < F; ++f) zr[q][f] = z[f];
+                }
+#pragma unroll
+                for (int q = 0; q < RB; ++q) {
+                    const float2* xa = d.XA + (((long long)c * nbs + min(bs0 + q, nbs - 1)) * n + x) * F;
+#pragma unroll
+                    for (int f = 0; f < F; ++f) xr[q][f] = xa[f];
                 }
 #pragma unroll
                 for (int r = 0; r < RW; ++r) {
-                    const long long row = row0 + r;
-                    if (row < rows) {
-                        const int y = (int)(row % n);
-                        const long long cb = (long long)c * d.B * S + row / n;
-                        const float2 g = d.G[row * n + x];
-                        const float2* z = d.Z + (((long long)c * n + y) * n + x) * F;
-                        float2 xr[F];
-                        if (one_bs) {
-#pragma unroll
-                            for (int f = 0; f < F; ++f) xr[f] = xs[f];
-                        } else {
-                            const float2* xa = d.XA + (cb * n + x) * F;
-#pragma unroll
-                            for (int f = 0; f < F; ++f) xr[f] = xa[f];
-                        }
+                    const int rb = r / RY, ry = r % RY;
+                    if (bs0 + rb < nbs && y0 + ry < n) {
+                        const float2 g = d.G[((long long)(bs0 + rb) * n + y0 + ry) * n + x];
 #pragma unroll
                         for (int f = 0; f < F; ++f) {
-                            const float2 t = cjmad(cmul(z[f], xr[f]), g, make_float2(v[(r * F + f) * 2], v[(r * F + f) * 2 + 1]));
+                            const float2 t = cjmad(cmul(zr[ry][f], xr[rb][f]), g,
+                                                   make_float2(v[(r * F + f) * 2], v[(r * F + f) * 2 + 1]));
                             v[(r * F + f) * 2] = t.x;
                             v[(r * F + f) * 2 + 1] = t.y;
                         }
@@ -447,12 +445,10 @@ __global__ __launch_bounds__(kThreads) void k_kp_grad_y(const KPDesc d) {
                 }
             }
             // lane L holds value L: row L / (2F), feature (L / 2) % F, component L % 2
-            const long long row = gi * RW + lane / (2 * F);
-            if (row < rows) {
-                const int y = (int)(row % n);
-                const long long bs = row / n;
-                const long long cb = (long long)c * d.B * S + bs;
-                float* out = reinterpret_cast<float*>(d.gY + (cb * n + y) * F);
+            const int r = lane / (2 * F), rb = r / RY, ry = r % RY;
+            if (bs0 + rb < nbs && y0 + ry < n) {
+                const long long cb = (long long)c * nbs + bs0 + rb;
+                float* out = reinterpret_cast<float*>(d.gY + (cb * n + y0 + ry) * F);
                 out[lane % (2 * F)] = v[0];
             }
         }
@@ -802,8 +798,9 @@ hipError_t kp_launch_back_x(const KPDesc& d, hipStream_t s) {
     return hipGetLastError();
 }
 hipError_t kp_launch_back_y(const KPDesc& d, hipStream_t s) {
-    const long long rows = (long long)d.B * d.S * d.n;
-    const long long groups = (rows + 32 / d.F - 1) / (32 / d.F);
+    // as the kernel's blocks of RB (b, s) by RY rows, RB RY = 32 / F
+    const int rw = 32 / d.F, ry = rw >= 16 ? 4 : (rw >= 4 ? 2 : 1), rb = rw / ry;
+    const long long groups = ((long long)(d.B * d.S + rb - 1) / rb) * ((d.n + ry - 1) / ry);
     const long long blocks = (groups + kThreads / 64 - 1) / (kThreads / 64);
     KP_F_SWITCH(k_kp_grad_y, dim3((unsigned)(blocks > (1 << 20) ? (1 << 20) : blocks)));
     return hipGetLastError();
