@@ -311,11 +311,13 @@ __global__ __launch_bounds__(kThreads) void k_kp_grad_z_sum(const KPDesc d) {
 }
 
 // gXA[c][b][s][x][f] = sum_y conj(Z Yf) G[b][s][y][x]. A wave task is (kGxBs consecutive
-// (b, s), 64 columns): each Z value (per pixel) serves all kGxBs of them, and the Yf values
-// (per row, the same in every lane) are loaded 64 / F rows at a time spread over the lanes.
-// Each sum runs over y in order. One (b, s) per task: sharing Z across two halves the
-// tasks, and the pass needs the waves more than the loads.
-constexpr int kGxBs = 1;
+// (b, s), 64 columns, one of kGxYs row ranges): each Z value (per pixel) serves all kGxBs
+// (b, s), and the Yf values (per row, the same in every lane) are loaded 64 / F rows at a
+// time spread over the lanes. The row split keeps the waves of one (b, s) per task while
+// Z is shared; each range's sum runs over y in order into its own part of gXA, and
+// k_kp_gx_sum adds the parts in order.
+constexpr int kGxBs = 2;
+constexpr int kGxYs = 2;  // row ranges
 
 template <int F>
 __global__ __launch_bounds__(kThreads) void k_kp_grad_x(const KPDesc d) {
@@ -326,10 +328,13 @@ __global__ __launch_bounds__(kThreads) void k_kp_grad_x(const KPDesc d) {
     const int nseg = (n + 63) / 64, ngr = (nbs + kGxBs - 1) / kGxBs;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const long long W = (long long)ngr * nseg;
+    const long long W = (long long)ngr * nseg * kGxYs;
+    const int rq = (n + kGxYs - 1) / kGxYs;
     for (long long w = (long long)blockIdx.x * (kThreads / 64) + wave; w < W; w += (long long)gridDim.x * (kThreads / 64)) {
         const int seg = (int)(w % nseg);
-        const int bs0 = (int)(w / nseg) * kGxBs;
+        const int half = (int)((w / nseg) % kGxYs);
+        const int bs0 = (int)(w / ((long long)nseg * kGxYs)) * kGxBs;
+        const int ya = min(n, half * rq), yb = min(n, ya + rq);
         const int x = seg * 64 + lane;
         const bool live = x < n;
         const int xs = live ? x : 0;
@@ -339,19 +344,19 @@ __global__ __launch_bounds__(kThreads) void k_kp_grad_x(const KPDesc d) {
             for (int j = 0; j < kGxBs; ++j)
 #pragma unroll
                 for (int f = 0; f < F; ++f) acc[j][f] = make_float2(0.f, 0.f);
-            for (int y0 = 0; y0 < n; y0 += YB) {
+            for (int y0 = ya; y0 < yb; y0 += YB) {
                 float2 yl[kGxBs];
                 const int yy = y0 + lane / F;
 #pragma unroll
                 for (int j = 0; j < kGxBs; ++j) {
                     const int bs = bs0 + j;
                     yl[j] = make_float2(0.f, 0.f);
-                    if (bs < nbs && yy < n) yl[j] = d.Yf[(((long long)c * nbs + bs) * n + yy) * F + lane % F];
+                    if (bs < nbs && yy < yb) yl[j] = d.Yf[(((long long)c * nbs + bs) * n + yy) * F + lane % F];
                 }
 #pragma unroll
                 for (int t = 0; t < YB; ++t) {
                     const int y = y0 + t;
-                    if (y < n) {
+                    if (y < yb) {
                         float2 z[F];
                         const float2* zp = d.Z + (((long long)c * n + y) * n + xs) * F;
 #pragma unroll
@@ -372,13 +377,23 @@ __global__ __launch_bounds__(kThreads) void k_kp_grad_x(const KPDesc d) {
 #pragma unroll
                 for (int j = 0; j < kGxBs; ++j) {
                     if (bs0 + j < nbs) {
-                        float2* out = d.gXA + (((long long)c * nbs + bs0 + j) * n + x) * F;
+                        float2* out = d.gXA + (long long)half * d.ns * nbs * n * F + (((long long)c * nbs + bs0 + j) * n + x) * F;
 #pragma unroll
                         for (int f = 0; f < F; ++f) out[f] = acc[j][f];
                     }
                 }
             }
         }
+    }
+}
+
+// gXA (part 0) = the sum of the kGxYs row-range parts, in order
+__global__ __launch_bounds__(kThreads) void k_kp_gx_sum(const KPDesc d) {
+    const long long per = (long long)d.ns * d.B * d.S * d.n * d.F;
+    for (long long e = gtid(); e < per; e += gstride()) {
+        float2 v = d.gXA[e];
+        for (int h = 1; h < kGxYs; ++h) v = cadd(v, d.gXA[h * per + e]);
+        d.gXA[e] = v;
     }
 }
 
@@ -794,7 +809,8 @@ hipError_t kp_launch_back_z(const KPDesc& d, hipStream_t s) {
     return hipGetLastError();
 }
 hipError_t kp_launch_back_x(const KPDesc& d, hipStream_t s) {
-    KP_F_SWITCH(k_kp_grad_x, dim3(grid_of((long long)((d.B * d.S + kGxBs - 1) / kGxBs) * ((d.n + 63) / 64) * 64)));
+    KP_F_SWITCH(k_kp_grad_x, dim3(grid_of((long long)((d.B * d.S + kGxBs - 1) / kGxBs) * ((d.n + 63) / 64) * 64 * kGxYs)));
+    hipLaunchKernelGGL(k_kp_gx_sum, dim3(grid_of((long long)d.ns * d.B * d.S * d.n * d.F)), dim3(kThreads), 0, s, d);
     return hipGetLastError();
 }
 hipError_t kp_launch_back_y(const KPDesc& d, hipStream_t s) {

@@ -183,7 +183,7 @@ hipError_t kp_device(KPTables* t, DevArena* ar, bool with_grad, hipStream_t s) {
         // xy-gradient pass
         d.zchunks = (int)std::max<size_t>(1, std::min<size_t>(B * S, (524288 + n * n - 1) / (n * n)));
         ok(ar->alloc(&d.zpart, (size_t)d.zchunks * ns * n * n * F));
-        ok(ar->alloc(&d.gXA, ns * B * S * n * F));
+        ok(ar->alloc(&d.gXA, 2 * ns * B * S * n * F));
         ok(ar->alloc(&d.gY, ns * B * S * n * F));
         ok(ar->alloc(&d.gXs, ns * S * n * F));
         ok(ar->alloc(&d.gYs, ns * S * n * F));

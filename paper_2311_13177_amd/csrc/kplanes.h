@@ -53,7 +53,8 @@ struct KPDesc {
     float2* qs;          // [ns][B][S][F]
     float2* Z;           // [ns][n][n][F]
     float2 *XA, *Yf;     // [ns][B][S][n][F]
-    float2 *gZ, *gXA, *gY;
+    float2 *gZ, *gY;
+    float2* gXA;         // [2][ns][B][S][n][F]: row-range partial sums, summed into part 0
     float2* zpart;       // [zchunks][ns][n][n][F] partial sums of gZ over (b, s) chunks
     int zchunks;
     float2 *gXs, *gYs, *gqx, *gqy, *gqs, *h;  // h: [ns][B][S][F]
