@@ -6,11 +6,14 @@
  * CVPR 2024). Its operations follow the paper's statement of the problem:
  *
  *   volume V[t][s][y][x]    complex, Section 4.1 (static grid; a dense grid of T
- *                           time knots stands in for the dynamic model)
+ *                           time knots for dynamic scans, or the paper's complex
+ *                           K-Planes model through the vp_kplanes_* calls)
  *   forward  A V            Section 4.2: for every blade b, sum over spectral bins
  *                           s of the bin's image shifted by delta_s along the
  *                           blade's readout direction (bilinear, zero outside the
- *                           grid), unitary 2D DFT, blade k-space mask
+ *                           grid), unitary 2D DFT, blade k-space mask (or the
+ *                           blade-aligned samples of Section 7's non-uniform DFT,
+ *                           vp_nu_* calls)
  *   objective               Section 4.3: 0.5 sum_b |M_b(A V)_b - M_b y_b|^2
  *                           + tv_weight TV(V) + l1_weight L1(V)
  *   optimiser               Section 4.3: Adam (or plain gradient descent)
@@ -153,7 +156,7 @@ typedef struct {
 
 /* Fills defaults: tv_weight 1e-3, l1_weight 0, tv_eps 1e-3, n_steps 200, Adam
  * with lr 1e-2, betas (0.9, 0.999), eps 1e-8, all-blades schedule, split S/2,
- * device 0, automatic tile shape without tuning. */
+ * device 0, automatic tile shape without tuning, seed 0, data_weight 1. */
 vp_status vp_options_default(vp_options* opts);
 
 /* Static description of a status code; never NULL. */
