@@ -314,3 +314,32 @@ def test_ragged_lines_and_odd_sizes(gpu_lib, n, lines, n_time):
                            exact=False)
     assert _rel(fit["vol"], ref["vol"]) < 1e-4
     assert abs(fit["final_loss"] - ref["final_loss"]) <= 1e-3 * abs(ref["final_loss"])
+
+
+@pytest.mark.parametrize("n,lines,n_spec", [(16, (1,), 1), (24, (24, 3), 2), (30, (1, 30, 7), 1)])
+def test_degenerate_blades(gpu_lib, n, lines, n_spec):
+    # one-line blades, blades as wide as the image (L = n), a single bin
+    import torch
+    from paper_2311_13177_amd import binding as B
+
+    case = configs.small_case(n=n, n_spec=n_spec, n_blades=len(lines), lines=max(lines))
+    g = case.geometry()
+    g["lines"] = np.asarray(lines, dtype=np.int32)
+    plan = B.Plan.from_geometry(g)
+    geom = O.Geometry.from_dict(g)
+    shp = B.nu_shape(plan)
+    rng = np.random.default_rng(n + len(lines))
+    vol = (rng.standard_normal(plan.volume_shape) + 1j * rng.standard_normal(plan.volume_shape)).astype(np.complex64)
+    v64 = vol.astype(np.complex128)
+    got = B.vp_nu_forward(plan, torch.from_numpy(vol).cuda()).cpu().numpy()
+    assert _rel(got, _pack(N.forward_nu(v64, geom, exact=True), shp)) <= 1e-4
+    s = (rng.standard_normal(shp) + 1j * rng.standard_normal(shp)).astype(np.complex64)
+    for b, L in enumerate(lines):
+        s[b, L:] = 0
+    adj = B.vp_nu_adjoint(plan, torch.from_numpy(s).cuda()).cpu().numpy()
+    ys = [-s[b, :L].astype(np.complex128) for b, L in enumerate(lines)]
+    want, _ = N.gradient_nu(np.zeros(plan.volume_shape, dtype=np.complex128), geom, ys, exact=True)
+    assert _rel(adj, want) <= 1e-4
+    # all-zero samples: the fit stays at zero (zero data gradient, TV of zero is zero)
+    fit = B.vp_nu_reconstruct(plan, np.zeros(shp, dtype=np.complex64), B.vp_options_default(n_steps=3))
+    assert not np.any(fit["vol"]) and fit["final_loss"] == 0.0
