@@ -273,6 +273,12 @@ vp_status vp_nu_session_stage_times(vp_nu_session* session, int32_t n_steps, dou
 vp_status vp_nu_session_read(vp_nu_session* session, vp_c64* volume_out, vp_c64* proj_out, vp_c64* water_out,
                              vp_c64* fat_out, double* objective);
 
+/* Checkpoint and resume, as vp_session_get_state / vp_session_set_state: the volume,
+ * the Adam moments and the step count (a resumed fit continues bit for bit). */
+vp_status vp_nu_session_get_state(vp_nu_session* session, vp_c64* volume, vp_c64* m, vp_c64* v, int64_t* step);
+vp_status vp_nu_session_set_state(vp_nu_session* session, const vp_c64* volume, const vp_c64* m, const vp_c64* v,
+                                  int64_t step);
+
 vp_status vp_nu_session_destroy(vp_nu_session* session);
 
 /* One synchronous fit on blade-aligned samples: create, opts->n_steps steps, read

@@ -121,6 +121,8 @@ _PROTOS = {
     "vp_nu_session_stage_times": (c_int32, [_P, c_int32, POINTER(c_double)]),
     "vp_nu_session_read": (c_int32, [_P, _P, _P, _P, _P, POINTER(c_double)]),
     "vp_nu_session_destroy": (c_int32, [_P]),
+    "vp_nu_session_get_state": (c_int32, [_P, _P, _P, _P, POINTER(c_int64)]),
+    "vp_nu_session_set_state": (c_int32, [_P, _P, _P, _P, c_int64]),
     "vp_psnr": (c_int32, [_P, _P, c_int64, c_int32, _P, _P]),
     "vp_session_create": (c_int32, [_P, POINTER(vp_options), _P, _P, POINTER(_P)]),
     "vp_session_step": (c_int32, [_P, c_int32, c_int32]),
@@ -453,6 +455,20 @@ class NuSession:
         if objective:
             res["objective"] = obj.value
         return res
+
+    def get_state(self) -> dict:
+        p = self.plan
+        vol, m, v = (np.empty(p.volume_shape, np.complex64) for _ in range(3))
+        st = c_int64()
+        check(lib().vp_nu_session_get_state(self.handle, _hp(vol), _hp(m), _hp(v), byref(st)))
+        return dict(vol=vol, m=m, v=v, step=int(st.value))
+
+    def set_state(self, state: dict) -> None:
+        p = self.plan
+        vol = _host_c64(state["vol"], p.volume_shape)
+        m = _host_c64(state.get("m"), p.volume_shape)
+        v = _host_c64(state.get("v"), p.volume_shape)
+        check(lib().vp_nu_session_set_state(self.handle, _hp(vol), _hp(m), _hp(v), int(state["step"])))
 
     def close(self) -> None:
         if getattr(self, "handle", None):

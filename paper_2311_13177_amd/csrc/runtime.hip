@@ -770,6 +770,24 @@ extern "C" vp_status vp_nu_session_read(vp_nu_session* x, vp_c64* volume_out, vp
     return session_read(x->s.get(), volume_out, proj_out, water_out, fat_out);
 }
 
+extern "C" vp_status vp_nu_session_get_state(vp_nu_session* x, vp_c64* volume, vp_c64* m, vp_c64* v,
+                                             int64_t* step) {
+    if (!x) {
+        clear_error();
+        return fail(VP_ERR_ARG, "vp_nu_session_get_state: NULL session");
+    }
+    return vp_session_get_state(x->s.get(), volume, m, v, step);
+}
+
+extern "C" vp_status vp_nu_session_set_state(vp_nu_session* x, const vp_c64* volume, const vp_c64* m,
+                                             const vp_c64* v, int64_t step) {
+    if (!x) {
+        clear_error();
+        return fail(VP_ERR_ARG, "vp_nu_session_set_state: NULL session");
+    }
+    return vp_session_set_state(x->s.get(), volume, m, v, step);
+}
+
 extern "C" vp_status vp_nu_session_destroy(vp_nu_session* x) {
     delete x;
     return VP_OK;

@@ -343,3 +343,28 @@ def test_degenerate_blades(gpu_lib, n, lines, n_spec):
     # all-zero samples: the fit stays at zero (zero data gradient, TV of zero is zero)
     fit = B.vp_nu_reconstruct(plan, np.zeros(shp, dtype=np.complex64), B.vp_options_default(n_steps=3))
     assert not np.any(fit["vol"]) and fit["final_loss"] == 0.0
+
+
+def test_checkpoint_resume_is_bitwise(gpu_lib):
+    # stop after 4 steps, checkpoint, continue in a fresh session: the same bits as 9
+    # uninterrupted steps (random one-blade schedule, so the step counter matters too)
+    from paper_2311_13177_amd import binding as B
+
+    case = configs.small_case(**FIT_CASES["dynamic_40"])
+    plan = B.Plan.from_geometry(case.geometry())
+    y = _pack(N.simulate_samples(case), B.nu_shape(plan)).astype(np.complex64)
+    opts = B.vp_options_default(lr=1e-2, schedule=B.VP_SCHED_RANDOM, seed=77)
+    a = B.NuSession(plan, y, opts)
+    a.step(4)
+    state = a.get_state()
+    a.step(5)
+    want = a.read(objective=True)
+    a.close()
+    assert state["step"] == 4
+    b = B.NuSession(plan, y, opts)
+    b.set_state(state)
+    b.step(5)
+    got = b.read(objective=True)
+    assert b.get_state()["step"] == 9
+    b.close()
+    assert np.array_equal(got["vol"], want["vol"]) and got["objective"] == want["objective"]
