@@ -478,6 +478,14 @@ vp_status vp_kplanes_session_read(vp_kplanes_session* session, vp_c64* params_ou
  * gradients, regularisers and update. */
 vp_status vp_kplanes_session_stage_times(vp_kplanes_session* session, int32_t n_steps, double* stage_ms);
 
+/* Checkpoint and resume: the parameter vector, its Adam moments (each [count] complex,
+ * (re, im) pairs) and the step count, to and from host buffers; set_state with NULL
+ * moments starts them at zero. A resumed fit continues bit for bit. */
+vp_status vp_kplanes_session_get_state(vp_kplanes_session* session, vp_c64* params, vp_c64* m, vp_c64* v,
+                                       int64_t* step);
+vp_status vp_kplanes_session_set_state(vp_kplanes_session* session, const vp_c64* params, const vp_c64* m,
+                                       const vp_c64* v, int64_t step);
+
 vp_status vp_kplanes_session_destroy(vp_kplanes_session* session);
 
 /* Whole fit: session_create, opts->n_steps graph-replayed steps, session_read, destroy. */

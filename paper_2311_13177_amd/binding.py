@@ -121,6 +121,8 @@ _PROTOS = {
     "vp_nu_session_stage_times": (c_int32, [_P, c_int32, POINTER(c_double)]),
     "vp_nu_session_read": (c_int32, [_P, _P, _P, _P, _P, POINTER(c_double)]),
     "vp_nu_session_destroy": (c_int32, [_P]),
+    "vp_kplanes_session_get_state": (c_int32, [_P, _P, _P, _P, POINTER(c_int64)]),
+    "vp_kplanes_session_set_state": (c_int32, [_P, _P, _P, _P, c_int64]),
     "vp_nu_session_get_state": (c_int32, [_P, _P, _P, _P, POINTER(c_int64)]),
     "vp_nu_session_set_state": (c_int32, [_P, _P, _P, _P, c_int64]),
     "vp_psnr": (c_int32, [_P, _P, c_int64, c_int32, _P, _P]),
@@ -749,6 +751,18 @@ class KPlanesSession:
         if objective:
             res["objective"] = obj.value
         return res
+
+    def get_state(self) -> dict:
+        p, m, v = (np.empty(self.count, np.complex64) for _ in range(3))
+        st = c_int64()
+        check(lib().vp_kplanes_session_get_state(self.handle, _hp(p), _hp(m), _hp(v), byref(st)))
+        return dict(params=p, m=m, v=v, step=int(st.value))
+
+    def set_state(self, state: dict) -> None:
+        p = _host_c64(state["params"], (self.count,))
+        m = _host_c64(state.get("m"), (self.count,))
+        v = _host_c64(state.get("v"), (self.count,))
+        check(lib().vp_kplanes_session_set_state(self.handle, _hp(p), _hp(m), _hp(v), int(state["step"])))
 
     def stage_times(self, n_steps: int = 10):
         ms = (c_double * 6)()

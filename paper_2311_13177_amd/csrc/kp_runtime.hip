@@ -606,6 +606,49 @@ extern "C" vp_status vp_kplanes_session_stage_times(vp_kplanes_session* s, int32
     return VP_OK;
 }
 
+namespace {
+bool params_finite(const vp_c64* a, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(a[i].re) || !std::isfinite(a[i].im)) return false;
+    return true;
+}
+}  // namespace
+
+extern "C" vp_status vp_kplanes_session_get_state(vp_kplanes_session* s, vp_c64* params, vp_c64* m, vp_c64* v,
+                                                  int64_t* step) {
+    clear_error();
+    if (!s) return fail(VP_ERR_ARG, "vp_kplanes_session_get_state: NULL session");
+    hipError_t e = hipSetDevice(s->device);
+    const KPDesc& d = s->tab.d;
+    const size_t pb = (size_t)d.n_params * sizeof(float2);
+    if (e == hipSuccess && params) e = hipMemcpyAsync(params, d.params, pb, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess && m) e = hipMemcpyAsync(m, d.m, pb, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess && v) e = hipMemcpyAsync(v, d.v, pb, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e == hipSuccess && step) *step = s->steps_done;
+    return hip_status(e, "vp_kplanes_session_get_state");
+}
+
+extern "C" vp_status vp_kplanes_session_set_state(vp_kplanes_session* s, const vp_c64* params, const vp_c64* m,
+                                                  const vp_c64* v, int64_t step) {
+    clear_error();
+    if (!s || !params || step < 0 || step > 0x7ffffffe)
+        return fail(VP_ERR_ARG, "vp_kplanes_session_set_state: bad argument");
+    const KPDesc& d = s->tab.d;
+    if (!params_finite(params, (size_t)d.n_params))
+        return fail(VP_ERR_NONFINITE, "vp_kplanes_session_set_state: non-finite parameters");
+    hipError_t e = hipSetDevice(s->device);
+    const size_t pb = (size_t)d.n_params * sizeof(float2);
+    const int st32 = (int)step;
+    if (e == hipSuccess) e = hipMemcpyAsync((void*)d.params, params, pb, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = m ? hipMemcpyAsync(d.m, m, pb, hipMemcpyHostToDevice, s->stream) : hipMemsetAsync(d.m, 0, pb, s->stream);
+    if (e == hipSuccess) e = v ? hipMemcpyAsync(d.v, v, pb, hipMemcpyHostToDevice, s->stream) : hipMemsetAsync(d.v, 0, pb, s->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(s->step_dev, &st32, sizeof st32, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e == hipSuccess) s->steps_done = step;
+    return hip_status(e, "vp_kplanes_session_set_state");
+}
+
 extern "C" vp_status vp_kplanes_session_destroy(vp_kplanes_session* s) {
     if (s) {
         (void)hipSetDevice(s->device);

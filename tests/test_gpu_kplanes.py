@@ -200,3 +200,26 @@ def test_full_size_decode_and_gradient(gpu_lib):
         h = 0.05 * obj / abs(slope)
         fd = (f(p + h * d) - f(p - h * d)) / (2 * h)
         assert abs(fd - slope) <= 1e-3 * abs(slope), (lo, hi, fd, slope)
+
+
+def test_checkpoint_resume_is_bitwise(gpu_lib):
+    # Adam, stop after 3 steps, checkpoint, continue in a fresh session for 4 more: the
+    # same bits as 7 uninterrupted steps
+    B, torch, case, plan, geom, cfg, model, y = _setup("dyn_64", regs=(1e-2, 1e-2, 1e-3))
+    c = CASES["dyn_64"]
+    init = init_params(case.n_spec, c["F"], c["Rt"], c["res"], seed=5)
+    opts = B.vp_options_default(lr=1e-2)
+    a = B.KPlanesSession(plan, model, y, init, opts)
+    a.step(3)
+    state = a.get_state()
+    a.step(4)
+    want = a.read(objective=True)
+    a.close()
+    assert state["step"] == 3
+    b = B.KPlanesSession(plan, model, y, init, opts)
+    b.set_state(state)
+    b.step(4)
+    got = b.read(objective=True)
+    assert b.get_state()["step"] == 7
+    b.close()
+    assert np.array_equal(got["params"], want["params"]) and got["objective"] == want["objective"]
