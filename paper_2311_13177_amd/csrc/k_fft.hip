@@ -9,7 +9,7 @@ namespace vp {
 
 // ------------------------------------------------------------------ DFT in LDS
 //
-// Mixed-radix Stockham autosort (radices 2, 3, 4, 5), in place: in every stage each
+// Mixed-radix Stockham autosort (radices 2, 3, 4, 5, and 8 in the compile-time variants), in place: in every stage each
 // thread reads the inputs of its butterflies into registers, the block synchronises,
 // and each thread writes its outputs. `count` transforms of length n live in LDS:
 // element j of transform f at buf[f * fstride + j * estride], with n * count <= E *
@@ -57,6 +57,27 @@ __device__ __forceinline__ void butterfly(float2 (&x)[R]) {
         x[2] = cadd(p2, q2);
         x[3] = csub(p2, q2);
         x[4] = csub(p1, q1);
+    } else if constexpr (R == 8) {
+        // two 4-point DFTs (even and odd inputs), the odd ones times w^k with w the
+        // eighth root of unity of the transform's sign, then the 2-point combination:
+        // X[k] = E[k] + w^k O[k], X[k + 4] = E[k] - w^k O[k]
+        float2 e[4] = {x[0], x[2], x[4], x[6]};
+        float2 o[4] = {x[1], x[3], x[5], x[7]};
+        butterfly<DIR, 4>(e);
+        butterfly<DIR, 4>(o);
+        const float c = 0.70710678118654752440f;  // 1 / sqrt(2)
+        const float d = (float)DIR;
+        const float2 o1 = make_float2(c * (o[1].x - d * o[1].y), c * (o[1].y + d * o[1].x));
+        const float2 o2 = mul_i<DIR>(o[2]);
+        const float2 o3 = make_float2(c * (-o[3].x - d * o[3].y), c * (-o[3].y + d * o[3].x));
+        x[0] = cadd(e[0], o[0]);
+        x[4] = csub(e[0], o[0]);
+        x[1] = cadd(e[1], o1);
+        x[5] = csub(e[1], o1);
+        x[2] = cadd(e[2], o2);
+        x[6] = csub(e[2], o2);
+        x[3] = cadd(e[3], o3);
+        x[7] = csub(e[3], o3);
     }
 }
 
@@ -124,10 +145,18 @@ __device__ void lds_fft(float2* buf, const float2* tw, int n, int count, int fst
 }
 
 // Compile-time variant for the common lengths: the radix sequence, strides and index
-// arithmetic are constants (the same factorisation as the plan: 4s, then 2s, 3s, 5s,
-// so results equal the runtime variant's bit for bit).
+// arithmetic are constants. The factorisation is the plan's (4s, then 2s, 3s, 5s), so
+// results equal the runtime variant's bit for bit, except for 512 points (only the
+// oversampled grids of blade-aligned sampling), which take radix-8 stages (8 8 8: three
+// barrier-separated stages instead of five; measured faster there, and not at 256). A
+// given length always takes the same variant, whatever the kernel or batch.
 __host__ __device__ constexpr int ct_radix(int n, int i) {
     int st = 0;
+    if (n == 512) {
+        for (; st < 3; ++st)
+            if (st == i) return 8;
+        return 0;
+    }
     while (n % 4 == 0) { if (st == i) return 4; n /= 4; ++st; }
     while (n % 2 == 0) { if (st == i) return 2; n /= 2; ++st; }
     while (n % 3 == 0) { if (st == i) return 3; n /= 3; ++st; }
