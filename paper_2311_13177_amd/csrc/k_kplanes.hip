@@ -472,16 +472,15 @@ __global__ __launch_bounds__(kThreads) void k_kp_grad_y(const KPDesc d) {
 
 // ------------------------------------------------------------------ chain to the grids
 
-// Independent sums over one index each:
+// Independent sums over one index each, a thread per output:
 //   gXs[c][s][x][f] = sum_b conj(a qx qs) gXA        gqx[c][b][x][f] = sum_s conj(a Xs qs) gXA
-//   h[c][b][s][f]   = sum_x conj(Xs qx) gXA          gqs = conj(a) h
 //   gYs[c][s][y][f] = sum_b conj(qy) gY              gqy[c][b][y][f] = sum_s conj(Ys) gY
+// (h and gqs, with far fewer outputs and a longer sum, are k_kp_chain_h's)
 __global__ __launch_bounds__(kThreads) void k_kp_chain1(const KPDesc d) {
     const int n = d.n, S = d.S, B = d.B, F = d.F;
     const long long n_sn = (long long)d.ns * S * n * F;   // gXs, gYs
     const long long n_bn = (long long)d.ns * B * n * F;   // gqx, gqy
-    const long long n_bs = (long long)d.ns * B * S * F;   // h, gqs
-    const long long total = 2 * n_sn + 2 * n_bn + n_bs;
+    const long long total = 2 * n_sn + 2 * n_bn;
     for (long long e = gtid(); e < total; e += gstride()) {
         float2 acc = make_float2(0.f, 0.f);
         if (e < 2 * n_sn) {
@@ -517,18 +516,36 @@ __global__ __launch_bounds__(kThreads) void k_kp_chain1(const KPDesc d) {
                 acc = cjmad(w, gv, acc);
             }
             (isx ? d.gqx : d.gqy)[r] = acc;
-        } else {
-            const long long r = e - 2 * n_sn - 2 * n_bn;
-            const int f = (int)(r % F);
-            const long long cbs = r / F;
-            const int s = (int)(cbs % S);
-            const int b = (int)((cbs / S) % B);
-            const int c = (int)(cbs / ((long long)S * B));
-            for (int x = 0; x < n; ++x) {
-                const float2 w = cmul(d.Xs[(((long long)c * S + s) * n + x) * F + f],
-                                      d.qx[(((long long)c * B + b) * n + x) * F + f]);
-                acc = cjmad(w, d.gXA[(cbs * n + x) * F + f], acc);
-            }
+        }
+    }
+}
+
+// h[c][b][s][f] = sum_x conj(Xs qx) gXA and gqs = conj(a) h: a wave per output, lane l
+// summing x = l, l + 64, ... in order, then the wave's 64 partial sums by a fixed
+// butterfly (every lane ends with the same total)
+__global__ __launch_bounds__(kThreads) void k_kp_chain_h(const KPDesc d) {
+    const int n = d.n, S = d.S, B = d.B, F = d.F;
+    const long long n_bs = (long long)d.ns * B * S * F;
+    const int lane = threadIdx.x & 63;
+    for (long long r = (long long)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); r < n_bs;
+         r += (long long)gridDim.x * (kThreads / 64)) {
+        const int f = (int)(r % F);
+        const long long cbs = r / F;
+        const int s = (int)(cbs % S);
+        const int b = (int)((cbs / S) % B);
+        const int c = (int)(cbs / ((long long)S * B));
+        float2 acc = make_float2(0.f, 0.f);
+        for (int x = lane; x < n; x += 64) {
+            const float2 w = cmul(d.Xs[(((long long)c * S + s) * n + x) * F + f],
+                                  d.qx[(((long long)c * B + b) * n + x) * F + f]);
+            acc = cjmad(w, d.gXA[(cbs * n + x) * F + f], acc);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            acc.x += __shfl_xor(acc.x, o);
+            acc.y += __shfl_xor(acc.y, o);
+        }
+        if (lane == 0) {
             d.h[r] = acc;
             d.gqs[r] = cjmad(d.params[d.a_off + f], acc, make_float2(0.f, 0.f));
         }
@@ -830,8 +847,9 @@ hipError_t kp_launch_back(const KPDesc& d, hipStream_t s) {
 #undef KP_F_SWITCH
 
 hipError_t kp_launch_chain(const KPDesc& d, hipStream_t s) {
-    const long long total = 2LL * d.ns * d.S * d.n * d.F + 2LL * d.ns * d.B * d.n * d.F + (long long)d.ns * d.B * d.S * d.F;
+    const long long total = 2LL * d.ns * d.S * d.n * d.F + 2LL * d.ns * d.B * d.n * d.F;
     hipLaunchKernelGGL(k_kp_chain1, dim3(grid_of(total)), dim3(kThreads), 0, s, d);
+    hipLaunchKernelGGL(k_kp_chain_h, dim3(grid_of((long long)d.ns * d.B * d.S * d.F * 64)), dim3(kThreads), 0, s, d);
     hipLaunchKernelGGL(k_kp_chain_a, dim3(d.F), dim3(kThreads), 0, s, d);
     hipLaunchKernelGGL(k_kp_grid, dim3(grid_of(d.n_params)), dim3(kThreads), 0, s, d);
     return hipGetLastError();
