@@ -32,8 +32,9 @@ struct UpdateArgs {
 // same operands as a per-voxel evaluation, so the result is the same either way. The s
 // weights of the first and last bins' outer differences are zero, so they are added
 // unconditionally; the sums start from -0, which adds exactly.
-template <int SCM, int PPT, int EPI>
-__device__ __forceinline__ void update_column(const float2 (&acc)[SCM][PPT], const float2* __restrict__ Vin,
+template <int SCM, int PPT, int EPI, bool PRE>
+__device__ __forceinline__ void update_column(const float2 (&acc)[SCM][PPT], const float2 (&pm)[SCM][PPT],
+                                              const float2 (&pv)[SCM][PPT], const float2* __restrict__ Vin,
                                               float2* __restrict__ Vout, float2* __restrict__ Mm,
                                               float2* __restrict__ Mv, const UpdateArgs& u) {
     constexpr int WR = PPT + 2;
@@ -104,8 +105,8 @@ __device__ __forceinline__ void update_column(const float2 (&acc)[SCM][PPT], con
             for (int i = 0; i < PPT; ++i) {
                 mm[i] = vv[i] = tp[i] = tn[i] = zero;
                 if (adam) {
-                    mm[i] = ld(rM, rb[i + 1], so);
-                    vv[i] = ld(rW, rb[i + 1], so);
+                    mm[i] = PRE ? pm[q][i] : ld(rM, rb[i + 1], so);
+                    vv[i] = PRE ? pv[q][i] : ld(rW, rb[i + 1], so);
                 }
                 if (tv && u.kt > 0) tp[i] = ld(rP, rb[i + 1], so);
                 if (tv && u.kt + 1 < u.T) tn[i] = ld(rN, rb[i + 1], so);
@@ -166,11 +167,40 @@ __device__ __forceinline__ void update_column(const float2 (&acc)[SCM][PPT], con
     }
 }
 
+// Adam moments of a lane's voxels (the values update_column would load for them),
+// loaded ahead so that their latency overlaps the gather; zero where update_column
+// does not use them.
+template <int SCM, int PPT, int EPI>
+__device__ __forceinline__ void load_moments(const KArgs& a, int slice, int kt, int y0, int x0, int lane, int sw,
+                                             int ns, float2 (&pm)[SCM][PPT], float2 (&pv)[SCM][PPT]) {
+    const int n = DF(n), S = DF(S);
+    const bool adam = EPI == EPI_ADAM_TV || DF(optimizer) == VP_OPT_ADAM;
+    const int nn = n * n, kvol = S * nn;
+    const size_t kbase = (size_t)kt * kvol;
+    const __amdgpu_buffer_rsrc_t rM = plane_rsrc(DF(m) + kbase, adam ? kvol : 0);
+    const __amdgpu_buffer_rsrc_t rW = plane_rsrc(DF(v) + kbase, adam ? kvol : 0);
+    const int xc = min(x0 + lane, n - 1);
+#pragma unroll
+    for (int q = 0; q < SCM; ++q)
+#pragma unroll
+        for (int i = 0; i < PPT; ++i) {
+            pm[q][i] = pv[q][i] = make_float2(0.f, 0.f);
+            const int y = y0 + i;
+            if (adam && q < ns && y < n) {
+                const int vo = (y * n + xc) * (int)sizeof(float2), so = (sw + q) * nn * (int)sizeof(float2);
+                pm[q][i] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rM, vo, so, 0));
+                pv[q][i] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rW, vo, so, 0));
+            }
+        }
+}
+
 // Regulariser gradient and optimiser update of a lane's voxels (update_column) with the
 // slice's hyperparameters (the step counter is advanced by k_advance after the pass).
-template <int SCM, int PPT, int EPI>
+// PRE: the moments come from load_moments (pm, pv) instead of being loaded here.
+template <int SCM, int PPT, int EPI, bool PRE>
 __device__ __forceinline__ void update_and_finish(const KArgs& a, int slice, int* stepp, int st,
-                                                  const float2 (&acc)[SCM][PPT], int kt, int y0, int x0,
+                                                  const float2 (&acc)[SCM][PPT], const float2 (&pm)[SCM][PPT],
+                                                  const float2 (&pv)[SCM][PPT], int kt, int y0, int x0,
                                                   int lane, int sw, int ns) {
     const float2* const Vin = stepp ? DF(vol[st & 1]) : DF(vol[0]);
     float2* const Vout = DF(vol[(st + 1) & 1]);
@@ -190,7 +220,7 @@ __device__ __forceinline__ void update_and_finish(const KArgs& a, int slice, int
         u.step_size = lr / bc1;
         u.inv_bc2s = 1.f / sqrtf(bc2);
     }
-    update_column<SCM, PPT, EPI>(acc, Vin, Vout, DF(m), DF(v), u);
+    update_column<SCM, PPT, EPI, PRE>(acc, pm, pv, Vin, Vout, DF(m), DF(v), u);
 }
 
 // ------------------------------------------------------------------ adjoint gather + update
@@ -265,6 +295,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
             for (int p = 0; p < P; ++p) planes[p] = cur[p] < e1 ? work + (size_t)ent[cur[p]].blade * nparts * nn : nullptr;
             if (cur[0] < e1) sg.fetch(planes, (int)nn, pre);
         }
+        // Adam moments loaded ahead where the registers allow (at most 128 with spills
+        // of a few registers at most; larger tiles load them in the epilogue)
+        constexpr bool kPre = MODE == GATHER_STEP && PPT == 2 && SCM <= 4;
+        float2 pm[SCM][PPT], pv[SCM][PPT];
+        if (kPre) load_moments<SCM, PPT, EPI>(a, slice, kt, y0, x0, lane, sw, ns, pm, pv);
         for (int it = 0; cur[0] < e1; ++it) {
             float2* buf = sm + (it & 1) * P * RE;
             sg.store(buf, pre);
@@ -351,7 +386,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
                 }
             }
         } else {
-            update_and_finish<SCM, PPT, EPI>(a, slice, stepp, st, acc, kt, y0, x0, lane, sw, ns);
+            update_and_finish<SCM, PPT, EPI, kPre>(a, slice, stepp, st, acc, pm, pv, kt, y0, x0, lane, sw, ns);
         }
     }
 }
@@ -386,7 +421,7 @@ __global__ __launch_bounds__(kThreads) void k_update(const KArgs a) {
         float2 acc[SC][1];
 #pragma unroll
         for (int q = 0; q < SC; ++q) acc[q][0] = G[(size_t)min(sw + q, S - 1) * nn + off];
-        update_and_finish<SC, 1, EPI>(a, slice, stepp, st, acc, kt, y, x0, lane, sw, ns);
+        update_and_finish<SC, 1, EPI, false>(a, slice, stepp, st, acc, acc, acc, kt, y, x0, lane, sw, ns);
     }
 }
 
