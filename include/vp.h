@@ -121,14 +121,17 @@ enum { VP_SCHED_ALL_BLADES = 0, VP_SCHED_CYCLIC = 1, VP_SCHED_RANDOM = 2 };
  * spectral bins per wave of a gather item, in {1, 2, 4, 8}, with gath_rows *
  * gath_bins <= 16; upd_bins: 0 runs the regulariser and optimiser update inside
  * the gather kernel, 2, 4 or 8 runs it as a separate pass (that many bins per
- * wave) over a stored data gradient (one more volume-sized device buffer). A tile
- * is 64 columns wide. */
+ * wave) over a stored data gradient (one more volume-sized device buffer);
+ * gath_waves: waves per gather item, 4 or 8 (0 means 4), which share the item's
+ * staged blade regions, so an item covers gath_waves * gath_bins bins. A tile is
+ * 64 columns wide. All fields 0: the plan's own (or autotuned) shape. */
 typedef struct {
     int32_t proj_rows;
     int32_t proj_parts;
     int32_t gath_rows;
     int32_t gath_bins;
     int32_t upd_bins;
+    int32_t gath_waves;
 } vp_tiles;
 
 typedef struct {

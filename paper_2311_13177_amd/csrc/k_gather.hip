@@ -229,8 +229,8 @@ __device__ __forceinline__ void update_and_finish(const KArgs& a, int slice, int
 //   w_e * (w00 g[y-oy][x-ox] + w01 g[y-oy][x-ox-1] + w10 g[y-oy-1][x-ox] + w11 g[y-oy-1][x-ox-1]),
 // the exact transpose of k_project's taps (zero outside the grid), accumulated tap by
 // tap with the products w_e w.. from the plan's per-entry tap table. Work item: (knot,
-// tile of 64 x PPT, chunk of 4 * SCM bins); wave w owns bins s0 + w * SCM ... s0 + w * SCM
-// + SCM - 1.
+// tile of 64 x PPT, chunk of NW * SCM bins), NW waves (4 or 8) sharing the staged blade
+// regions; wave w owns bins s0 + w * SCM ... s0 + w * SCM + SCM - 1.
 // MODE = GATHER_STORE writes (or adds to) the gradient; GATHER_STEP adds the TV/L1
 // gradient and applies the optimiser, reading volume[step & 1] and writing the other
 // copy.
@@ -240,8 +240,8 @@ __device__ __forceinline__ void update_and_finish(const KArgs& a, int slice, int
 
 // At least four waves per SIMD (at most 128 VGPRs): enough loads in flight for the
 // streaming epilogue; more waves would force spills.
-template <int MODE, int PPT, int SCM, int SE, int P, int EPI>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_gather(const KArgs a) {
+template <int MODE, int PPT, int SCM, int SE, int P, int EPI, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) void k_gather(const KArgs a) {
     extern __shared__ float2 sm[];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -257,7 +257,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
         const size_t nn = (size_t)n * n;
         const int txn = (n + kTileW - 1) / kTileW;
         const int y0 = (tk->b / txn) * PPT, x0 = (tk->b % txn) * kTileW;
-        const int sw = tk->c * 4 * SCM + wave * SCM;
+        const int sw = tk->c * NW * SCM + wave * SCM;
         const int ns = max(0, min(SCM, S - sw));
         const AS4 KnotInfo* ki = cst(DF(knots)) + kt;
         const int kox = ki->ox_max, koy = ki->oy_max;
@@ -273,7 +273,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
         for (int q = 0; q < SCM; ++q)
 #pragma unroll
             for (int i = 0; i < PPT; ++i) acc[q][i] = make_float2(0.f, 0.f);
-        Stager<SE, P> sg;
+        Stager<SE, P, 64 * NW> sg;
         sg.init(RH, RW, y0 - koy - 1, x0 - kox - 1, n);
         float2 pre[P][SE];
         // the knot's active parts in plan order, P per phase: cur[] this phase, nxt[] the next
@@ -429,27 +429,35 @@ __global__ __launch_bounds__(kThreads) void k_update(const KArgs a) {
 
 static inline int grid_for(int ntasks) { return ntasks < 1 ? 1 : (ntasks > (1 << 20) ? (1 << 20) : ntasks); }
 
+// The staging depth (planes per phase, elements per thread) follows the region size as
+// for 256 threads; 512 threads need half the elements each (rounded up).
 template <int MODE, int PPT, int SCM, int EPI>
-static void gather_variant(const KArgs& a, int re, hipStream_t s) {
-    const dim3 g(grid_for(a.ntasks)), b(kThreads);
+static void gather_variant(const KArgs& a, int waves, int re, hipStream_t s) {
+    const dim3 g(grid_for(a.ntasks)), b(64 * waves);
     const int depth = stage_depth(re);
     const size_t lds = stage_lds_bytes(re);
-    if (depth == 5) hipLaunchKernelGGL((k_gather<MODE, PPT, SCM, 5, 3, EPI>), g, b, lds, s, a);
-    else if (depth == 8) hipLaunchKernelGGL((k_gather<MODE, PPT, SCM, 8, 2, EPI>), g, b, lds, s, a);
-    else hipLaunchKernelGGL((k_gather<MODE, PPT, SCM, 16, 1, EPI>), g, b, lds, s, a);
+    if (waves == 8) {
+        if (depth == 5) hipLaunchKernelGGL((k_gather<MODE, PPT, SCM, 3, 3, EPI, 8>), g, b, lds, s, a);
+        else if (depth == 8) hipLaunchKernelGGL((k_gather<MODE, PPT, SCM, 4, 2, EPI, 8>), g, b, lds, s, a);
+        else hipLaunchKernelGGL((k_gather<MODE, PPT, SCM, 8, 1, EPI, 8>), g, b, lds, s, a);
+    } else {
+        if (depth == 5) hipLaunchKernelGGL((k_gather<MODE, PPT, SCM, 5, 3, EPI, 4>), g, b, lds, s, a);
+        else if (depth == 8) hipLaunchKernelGGL((k_gather<MODE, PPT, SCM, 8, 2, EPI, 4>), g, b, lds, s, a);
+        else hipLaunchKernelGGL((k_gather<MODE, PPT, SCM, 16, 1, EPI, 4>), g, b, lds, s, a);
+    }
 }
 
 template <int MODE>
-static hipError_t gather_mode(const KArgs& a, int rows, int sc, int re, hipStream_t s) {
+static hipError_t gather_mode(const KArgs& a, int rows, int sc, int waves, int re, hipStream_t s) {
 #define GV(R, C)                                                     \
     case R * 16 + C:                                                 \
         if constexpr (MODE == GATHER_STEP) {                         \
             if (a.epi == EPI_ADAM_TV)                                \
-                gather_variant<MODE, R, C, EPI_ADAM_TV>(a, re, s);   \
+                gather_variant<MODE, R, C, EPI_ADAM_TV>(a, waves, re, s);   \
             else                                                     \
-                gather_variant<MODE, R, C, EPI_GENERIC>(a, re, s);   \
+                gather_variant<MODE, R, C, EPI_GENERIC>(a, waves, re, s);   \
         } else {                                                     \
-            gather_variant<MODE, R, C, EPI_GENERIC>(a, re, s);       \
+            gather_variant<MODE, R, C, EPI_GENERIC>(a, waves, re, s);       \
         }                                                            \
         break
     switch (rows * 16 + sc) {
@@ -478,11 +486,12 @@ hipError_t launch_update(const KArgs& a, int sc, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_gather(const KArgs& a, int mode, int rows, int sc, int re, hipStream_t s) {
+hipError_t launch_gather(const KArgs& a, int mode, int rows, int sc, int waves, int re, hipStream_t s) {
     if (a.ntasks <= 0) return hipSuccess;
-    if (!gath_tiles_ok(rows, sc) || re < 1 || re > kStageMax * kThreads) return hipErrorInvalidValue;
-    return mode == GATHER_STEP ? gather_mode<GATHER_STEP>(a, rows, sc, re, s)
-                               : gather_mode<GATHER_STORE>(a, rows, sc, re, s);
+    if (!gath_tiles_ok(rows, sc) || !gath_waves_ok(waves) || re < 1 || re > kStageMax * kThreads)
+        return hipErrorInvalidValue;
+    return mode == GATHER_STEP ? gather_mode<GATHER_STEP>(a, rows, sc, waves, re, s)
+                               : gather_mode<GATHER_STORE>(a, rows, sc, waves, re, s);
 }
 
 }  // namespace vp

@@ -101,14 +101,14 @@ __device__ __forceinline__ float2 buffer_c64(__amdgpu_buffer_rsrc_t r, int idx) 
 // ------------------------------------------------------------------ LDS staging
 //
 // A rectangular region (rows x cols) of an n x n image, origin (gy0, gx0), is staged
-// into LDS with zeros outside the image. Each thread owns region elements
-// threadIdx.x + k * kThreads (k < SE); their image offsets are computed once per work
+// into LDS with zeros outside the image by the NT threads of a work item. Each thread
+// owns region elements threadIdx.x + k * NT (k < SE); their image offsets are computed once per work
 // item, and the next plane's values are loaded into registers while the current plane
 // is being consumed (double-buffered LDS, one barrier per plane).
 
 // P planes (images of the same size, same region) are staged per phase; plane p of a
 // phase occupies buf[p * re, (p + 1) * re). A null plane pointer stages zeros.
-template <int SE, int P>
+template <int SE, int P, int NT = kThreads>
 struct Stager {
     int off[SE];
     int re;
@@ -116,7 +116,7 @@ struct Stager {
         re = rows * cols;
 #pragma unroll
         for (int k = 0; k < SE; ++k) {
-            const int i = threadIdx.x + k * kThreads;
+            const int i = threadIdx.x + k * NT;
             int o = -1;
             if (i < re) {
                 const int r = i / cols, c = i - (i / cols) * cols;
@@ -142,7 +142,7 @@ struct Stager {
         for (int p = 0; p < P; ++p)
 #pragma unroll
             for (int k = 0; k < SE; ++k)
-                if (off[k] != -2) buf[p * re + threadIdx.x + k * kThreads] = pre[p][k];
+                if (off[k] != -2) buf[p * re + threadIdx.x + k * NT] = pre[p][k];
     }
 };
 

@@ -225,7 +225,7 @@ vp_status dense_setup(const vp_plan* p, DenseStep* ds, const vp_options* o = nul
     if (st == VP_OK && !tuned_tiles(ds->q, ds->tabs->device, o ? o->optimizer : VP_OPT_ADAM, &t) && o &&
         o->autotune) {
         vp_options to = *o;
-        to.tiles = vp_tiles{0, 0, 0, 0, 0};
+        to.tiles = vp_tiles{0, 0, 0, 0, 0, 0};
         st = tune_plan(ds->q, &to, &t);
     }
     if (st == VP_OK) st = plan_layout(ds->q, t, &ds->lay);
@@ -256,7 +256,7 @@ hipError_t dense_adjoint(const DenseStep& ds, hipStream_t s) {
     a.tasks = L.rows; a.ntasks = L.n_rows;
     if ((e = launch_rows(a, 1, L.fft_n, L.lds_rows, s)) != hipSuccess) return e;
     a.tasks = L.gath; a.ntasks = L.n_gath; a.accumulate = 0;
-    return launch_gather(a, GATHER_STORE, L.tiles.gath_rows, L.tiles.gath_sc, L.re_gath, s);
+    return launch_gather(a, GATHER_STORE, L.tiles.gath_rows, L.tiles.gath_sc, L.tiles.gath_w, L.re_gath, s);
 }
 
 double host_objective(const std::vector<float>& lp, const std::vector<double>& rp, double* data) {

@@ -103,9 +103,10 @@ static int region(int rows, int ox_min, int ox_max, int oy_min, int oy_max) {
 // are ordered tile-major, then knot, then bin chunk, so that the items sharing a tile's
 // blade regions and its neighbouring knots run side by side (see xcd_item).
 static vp_status build_layout(const vp_plan* p, const Tiles& t, Layout* L) {
-    if (!proj_tiles_ok(t.proj_rows, t.proj_gw) || !gath_tiles_ok(t.gath_rows, t.gath_sc) || !upd_tiles_ok(t.upd_sc))
-        return fail(VP_ERR_UNSUPPORTED, "tile shape (%d, %d, %d, %d, %d) is not compiled", t.proj_rows, t.proj_gw,
-                    t.gath_rows, t.gath_sc, t.upd_sc);
+    if (!proj_tiles_ok(t.proj_rows, t.proj_gw) || !gath_tiles_ok(t.gath_rows, t.gath_sc) || !upd_tiles_ok(t.upd_sc) ||
+        !gath_waves_ok(t.gath_w))
+        return fail(VP_ERR_UNSUPPORTED, "tile shape (%d, %d, %d, %d, %d, %d) is not compiled", t.proj_rows, t.proj_gw,
+                    t.gath_rows, t.gath_sc, t.upd_sc, t.gath_w);
     const int n = p->n, S = p->S, T = p->T;
     L->tiles = t;
     L->groups.clear();
@@ -139,7 +140,7 @@ static vp_status build_layout(const vp_plan* p, const Tiles& t, Layout* L) {
     for (int ty = 0; ty < typ; ++ty)
         for (int tx = 0; tx < txn; ++tx)
             for (int gi = 0; gi < (int)L->groups.size(); ++gi) L->t_proj.push_back(Task{0, gi, ty, tx});
-    const int nch = ceil_div(S, 4 * t.gath_sc);
+    const int nch = ceil_div(S, t.gath_w * t.gath_sc);
     for (int ty = 0; ty < tyg; ++ty)
         for (int tx = 0; tx < txn; ++tx)
             for (int kt = 0; kt < T; ++kt)
@@ -227,7 +228,7 @@ extern "C" vp_status vp_options_default(vp_options* o) {
     o->schedule = VP_SCHED_ALL_BLADES;
     o->split_bin = -1;
     o->device = 0;
-    o->tiles = vp_tiles{0, 0, 0, 0};
+    o->tiles = vp_tiles{0, 0, 0, 0, 0, 0};
     o->autotune = 0;
     o->seed = 0;
     o->data_weight = 1.0f;

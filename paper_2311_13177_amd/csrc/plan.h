@@ -21,7 +21,8 @@ void clear_error();
 struct Tiles {
     int proj_rows = 2, proj_gw = 1, gath_rows = 2, gath_sc = 1;
     int upd_sc = 0;  // 0: update fused into the gather; else bins per wave of the update pass
-    int key() const { return proj_rows | proj_gw << 4 | gath_rows << 8 | gath_sc << 12 | upd_sc << 16; }
+    int gath_w = 4;  // waves per gather item
+    int key() const { return proj_rows | proj_gw << 4 | gath_rows << 8 | gath_sc << 12 | upd_sc << 16 | gath_w << 20; }
     bool operator==(const Tiles& o) const { return key() == o.key(); }
 };
 

@@ -15,7 +15,8 @@ hipError_t launch_project(const KArgs& a, int rows, int gw, int re, hipStream_t 
 // n: the common length of every slice of the launch (0 if they differ).
 hipError_t launch_rows(const KArgs& a, int dir, int n, size_t lds, hipStream_t s);
 hipError_t launch_cols(const KArgs& a, int n, size_t lds, hipStream_t s);
-hipError_t launch_gather(const KArgs& a, int mode, int rows, int sc, int re, hipStream_t s);
+// waves: 4 or 8 per work item (the layout's gath_w: its bin chunks hold waves * sc bins)
+hipError_t launch_gather(const KArgs& a, int mode, int rows, int sc, int waves, int re, hipStream_t s);
 hipError_t launch_update(const KArgs& a, int sc, hipStream_t s);
 hipError_t launch_advance(const KArgs& a, int nslices, hipStream_t s);
 hipError_t launch_tv_grad(const KArgs& a, hipStream_t s);

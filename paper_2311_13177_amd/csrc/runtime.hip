@@ -172,11 +172,11 @@ vp_status check_options(const vp_plan* p, const vp_options* o) {
         return fail(VP_ERR_ARG, "options: betas must lie in [0, 1)");
     if (o->split_bin > p->S) return fail(VP_ERR_ARG, "options: split_bin above n_spec");
     const vp_tiles& t = o->tiles;
-    const bool none = !t.proj_rows && !t.proj_parts && !t.gath_rows && !t.gath_bins && !t.upd_bins;
+    const bool none = !t.proj_rows && !t.proj_parts && !t.gath_rows && !t.gath_bins && !t.upd_bins && !t.gath_waves;
     if (!none && (!proj_tiles_ok(t.proj_rows, t.proj_parts) || !gath_tiles_ok(t.gath_rows, t.gath_bins) ||
-                  !upd_tiles_ok(t.upd_bins)))
-        return fail(VP_ERR_UNSUPPORTED, "options: tile shape (%d, %d, %d, %d, %d) is not compiled", t.proj_rows,
-                    t.proj_parts, t.gath_rows, t.gath_bins, t.upd_bins);
+                  !upd_tiles_ok(t.upd_bins) || (t.gath_waves != 0 && !gath_waves_ok(t.gath_waves))))
+        return fail(VP_ERR_UNSUPPORTED, "options: tile shape (%d, %d, %d, %d, %d, %d) is not compiled", t.proj_rows,
+                    t.proj_parts, t.gath_rows, t.gath_bins, t.upd_bins, t.gath_waves);
     return VP_OK;
 }
 
@@ -205,10 +205,10 @@ void launch_step(const KArgs& base, const StageLists& L, hipStream_t s, hipError
     MARK(4);
     a.tasks = L.gath; a.ntasks = L.n_gath;
     if (L.tiles.upd_sc == 0) {
-        e = launch_gather(a, GATHER_STEP, L.tiles.gath_rows, L.tiles.gath_sc, L.re_gath, s);
+        e = launch_gather(a, GATHER_STEP, L.tiles.gath_rows, L.tiles.gath_sc, L.tiles.gath_w, L.re_gath, s);
     } else {
         a.accumulate = 0;
-        e = launch_gather(a, GATHER_STORE, L.tiles.gath_rows, L.tiles.gath_sc, L.re_gath, s);
+        e = launch_gather(a, GATHER_STORE, L.tiles.gath_rows, L.tiles.gath_sc, L.tiles.gath_w, L.re_gath, s);
         a.tasks = L.upd; a.ntasks = L.n_upd;
         if (e == hipSuccess) e = launch_update(a, L.tiles.upd_sc, s);
     }
@@ -328,7 +328,7 @@ extern "C" vp_status vp_adjoint(const vp_plan* p, const vp_c64* d_kres, vp_c64* 
     a.tasks = L.rows; a.ntasks = L.n_rows;
     if ((e = launch_rows(a, 1, L.fft_n, L.lds_rows, sc.s)) != hipSuccess) return hip_status(e, "vp_adjoint rows");
     a.tasks = L.gath; a.ntasks = L.n_gath;
-    if ((e = launch_gather(a, GATHER_STORE, L.tiles.gath_rows, L.tiles.gath_sc, L.re_gath, sc.s)) != hipSuccess)
+    if ((e = launch_gather(a, GATHER_STORE, L.tiles.gath_rows, L.tiles.gath_sc, L.tiles.gath_w, L.re_gath, sc.s)) != hipSuccess)
         return hip_status(e, "vp_adjoint gather");
     return VP_OK;
 }
@@ -529,7 +529,7 @@ extern "C" vp_status vp_nu_adjoint(const vp_plan* p, const vp_c64* d_samples, vp
     a.accumulate = accumulate != 0;
     const StageLists L = plan_lists(p, sc.t, sc.lay, sc.dl);
     a.tasks = L.gath; a.ntasks = L.n_gath;
-    if ((e = launch_gather(a, GATHER_STORE, L.tiles.gath_rows, L.tiles.gath_sc, L.re_gath, sc.s)) != hipSuccess)
+    if ((e = launch_gather(a, GATHER_STORE, L.tiles.gath_rows, L.tiles.gath_sc, L.tiles.gath_w, L.re_gath, sc.s)) != hipSuccess)
         return hip_status(e, "vp_nu_adjoint gather");
     return VP_OK;
 }
@@ -621,9 +621,9 @@ struct vp_nu_session {
         a.tasks = L.gath; a.ntasks = L.n_gath;
         if (r == hipSuccess) {
             if (L.tiles.upd_sc == 0) {
-                r = launch_gather(a, GATHER_STEP, L.tiles.gath_rows, L.tiles.gath_sc, L.re_gath, str);
+                r = launch_gather(a, GATHER_STEP, L.tiles.gath_rows, L.tiles.gath_sc, L.tiles.gath_w, L.re_gath, str);
             } else {
-                r = launch_gather(a, GATHER_STORE, L.tiles.gath_rows, L.tiles.gath_sc, L.re_gath, str);
+                r = launch_gather(a, GATHER_STORE, L.tiles.gath_rows, L.tiles.gath_sc, L.tiles.gath_w, L.re_gath, str);
                 a.tasks = L.upd; a.ntasks = L.n_upd;
                 if (r == hipSuccess) r = launch_update(a, L.tiles.upd_sc, str);
             }
