@@ -544,7 +544,8 @@ def measure_workload(case, B, steps, warmup):
                    "n_blades": case.n_blades, "lines": int(case.lines[0]), "steps_per_recon": case.n_steps,
                    "optimizer": "adam", "schedule": "all blades per step",
                    "tiles": {"proj_rows": tiles[0], "proj_parts": tiles[1], "gath_rows": tiles[2],
-                             "gath_bins": tiles[3], "upd_bins": tiles[4], "gath_waves": tiles[5]},
+                             "gath_bins": tiles[3], "upd_bins": tiles[4], "gath_waves": tiles[5],
+                             "proj_waves": tiles[6]},
                    "tune_s": round(tune_s, 4)},
         "recon_wall_s": round(recon_s, 4),
         "stage_ms": {k: round(v, 5) for k, v in stages.items()},

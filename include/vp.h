@@ -123,8 +123,10 @@ enum { VP_SCHED_ALL_BLADES = 0, VP_SCHED_CYCLIC = 1, VP_SCHED_RANDOM = 2 };
  * the gather kernel, 2, 4 or 8 runs it as a separate pass (that many bins per
  * wave) over a stored data gradient (one more volume-sized device buffer);
  * gath_waves: waves per gather item, 4 or 8 (0 means 4), which share the item's
- * staged blade regions, so an item covers gath_waves * gath_bins bins. A tile is
- * 64 columns wide. All fields 0: the plan's own (or autotuned) shape. */
+ * staged blade regions, so an item covers gath_waves * gath_bins bins; proj_waves:
+ * waves per projection item, 4 or 8 (0 means 4), which share the item's staged
+ * volume regions, so an item projects proj_waves * proj_parts blade parts. A tile
+ * is 64 columns wide. All fields 0: the plan's own (or autotuned) shape. */
 typedef struct {
     int32_t proj_rows;
     int32_t proj_parts;
@@ -132,6 +134,7 @@ typedef struct {
     int32_t gath_bins;
     int32_t upd_bins;
     int32_t gath_waves;
+    int32_t proj_waves;
 } vp_tiles;
 
 typedef struct {

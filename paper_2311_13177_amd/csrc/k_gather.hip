@@ -488,7 +488,7 @@ hipError_t launch_update(const KArgs& a, int sc, hipStream_t s) {
 
 hipError_t launch_gather(const KArgs& a, int mode, int rows, int sc, int waves, int re, hipStream_t s) {
     if (a.ntasks <= 0) return hipSuccess;
-    if (!gath_tiles_ok(rows, sc) || !gath_waves_ok(waves) || re < 1 || re > kStageMax * kThreads)
+    if (!gath_tiles_ok(rows, sc) || !item_waves_ok(waves) || re < 1 || re > kStageMax * kThreads)
         return hipErrorInvalidValue;
     return mode == GATHER_STEP ? gather_mode<GATHER_STEP>(a, rows, sc, waves, re, s)
                                : gather_mode<GATHER_STORE>(a, rows, sc, waves, re, s);

@@ -7,12 +7,13 @@ namespace vp {
 // ------------------------------------------------------------------ projection
 //
 // P_b[y][x] = sum_s sum_taps w * V_s[y + oy + (0|1)][x + ox + (0|1)]   (Section 4.2)
-// Work item: (part group, tile row, tile column), tile = 64 columns x PPT rows.
-// Part e of the group belongs to wave e % 4, slot e / 4. Each lane owns one column and
-// accumulates PPT rows for each of its GW parts over the bins in ascending order.
+// Work item: (part group, tile row, tile column), tile = 64 columns x PPT rows, NW waves
+// (4 or 8) sharing the staged volume regions. Part e of the group belongs to wave
+// e % NW, slot e / NW. Each lane owns one column and accumulates PPT rows for each of
+// its GW parts over the bins in ascending order.
 
-template <int GW, int PPT, int SE, int P>
-__global__ __launch_bounds__(kThreads) void k_project(const KArgs a) {
+template <int GW, int PPT, int SE, int P, int NW>
+__global__ __launch_bounds__(64 * NW) void k_project(const KArgs a) {
     extern __shared__ float2 sm[];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -39,7 +40,7 @@ __global__ __launch_bounds__(kThreads) void k_project(const KArgs a) {
         bool act[GW];
 #pragma unroll
         for (int j = 0; j < GW; ++j) {
-            const int e = j * 4 + wave;
+            const int e = j * NW + wave;
             act[j] = false;
             eb[j] = 0;
             ep[j] = 0;
@@ -54,7 +55,7 @@ __global__ __launch_bounds__(kThreads) void k_project(const KArgs a) {
         for (int j = 0; j < GW; ++j)
 #pragma unroll
             for (int i = 0; i < PPT; ++i) acc[j][i] = make_float2(0.f, 0.f);
-        Stager<SE, P> sg;
+        Stager<SE, P, 64 * NW> sg;
         sg.init(RH, RW, y0 + oymin, x0 + oxmin, n);
         float2 pre[P][SE];
         {
@@ -134,22 +135,31 @@ __global__ __launch_bounds__(kThreads) void k_project(const KArgs a) {
 
 static inline int grid_for(int ntasks) { return ntasks < 1 ? 1 : (ntasks > (1 << 20) ? (1 << 20) : ntasks); }
 
+// The staging depth (planes per phase, elements per thread) follows the region size as
+// for 256 threads; 512 threads need half the elements each (rounded up).
 template <int GW, int PPT>
-static void project_variant(const KArgs& a, int re, hipStream_t s) {
-    const dim3 g(grid_for(a.ntasks)), b(kThreads);
+static void project_variant(const KArgs& a, int waves, int re, hipStream_t s) {
+    const dim3 g(grid_for(a.ntasks)), b(64 * waves);
     const int depth = stage_depth(re);
     const size_t lds = stage_lds_bytes(re);
-    if (depth == 5) hipLaunchKernelGGL((k_project<GW, PPT, 5, 3>), g, b, lds, s, a);
-    else if (depth == 8) hipLaunchKernelGGL((k_project<GW, PPT, 8, 2>), g, b, lds, s, a);
-    else hipLaunchKernelGGL((k_project<GW, PPT, 16, 1>), g, b, lds, s, a);
+    if (waves == 8) {
+        if (depth == 5) hipLaunchKernelGGL((k_project<GW, PPT, 3, 3, 8>), g, b, lds, s, a);
+        else if (depth == 8) hipLaunchKernelGGL((k_project<GW, PPT, 4, 2, 8>), g, b, lds, s, a);
+        else hipLaunchKernelGGL((k_project<GW, PPT, 8, 1, 8>), g, b, lds, s, a);
+    } else {
+        if (depth == 5) hipLaunchKernelGGL((k_project<GW, PPT, 5, 3, 4>), g, b, lds, s, a);
+        else if (depth == 8) hipLaunchKernelGGL((k_project<GW, PPT, 8, 2, 4>), g, b, lds, s, a);
+        else hipLaunchKernelGGL((k_project<GW, PPT, 16, 1, 4>), g, b, lds, s, a);
+    }
 }
 
-hipError_t launch_project(const KArgs& a, int rows, int gw, int re, hipStream_t s) {
+hipError_t launch_project(const KArgs& a, int rows, int gw, int waves, int re, hipStream_t s) {
     if (a.ntasks <= 0) return hipSuccess;
-    if (!proj_tiles_ok(rows, gw) || re < 1 || re > kStageMax * kThreads) return hipErrorInvalidValue;
+    if (!proj_tiles_ok(rows, gw) || !item_waves_ok(waves) || re < 1 || re > kStageMax * kThreads)
+        return hipErrorInvalidValue;
 #define PV(R, G)                                          \
     case R * 16 + G:                                      \
-        if constexpr (proj_tiles_ok(R, G)) project_variant<G, R>(a, re, s); \
+        if constexpr (proj_tiles_ok(R, G)) project_variant<G, R>(a, waves, re, s); \
         break
     switch (rows * 16 + gw) {
         PV(1, 1); PV(1, 2); PV(1, 4); PV(1, 8);

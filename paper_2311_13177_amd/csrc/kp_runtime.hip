@@ -225,7 +225,7 @@ vp_status dense_setup(const vp_plan* p, DenseStep* ds, const vp_options* o = nul
     if (st == VP_OK && !tuned_tiles(ds->q, ds->tabs->device, o ? o->optimizer : VP_OPT_ADAM, &t) && o &&
         o->autotune) {
         vp_options to = *o;
-        to.tiles = vp_tiles{0, 0, 0, 0, 0, 0};
+        to.tiles = vp_tiles{0, 0, 0, 0, 0, 0, 0};
         st = tune_plan(ds->q, &to, &t);
     }
     if (st == VP_OK) st = plan_layout(ds->q, t, &ds->lay);
@@ -242,7 +242,7 @@ hipError_t dense_forward(const DenseStep& ds, hipStream_t s) {
     const StageLists& L = ds.L;
     hipError_t e;
     a.tasks = L.proj; a.ntasks = L.n_proj;
-    if ((e = launch_project(a, L.tiles.proj_rows, L.tiles.proj_gw, L.re_proj, s)) != hipSuccess) return e;
+    if ((e = launch_project(a, L.tiles.proj_rows, L.tiles.proj_gw, L.tiles.proj_w, L.re_proj, s)) != hipSuccess) return e;
     a.tasks = L.rows; a.ntasks = L.n_rows;
     if ((e = launch_rows(a, -1, L.fft_n, L.lds_rows, s)) != hipSuccess) return e;
     a.tasks = L.cols; a.ntasks = L.n_cols; a.mode = COL_STEP;

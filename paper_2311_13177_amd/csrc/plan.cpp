@@ -104,16 +104,16 @@ static int region(int rows, int ox_min, int ox_max, int oy_min, int oy_max) {
 // blade regions and its neighbouring knots run side by side (see xcd_item).
 static vp_status build_layout(const vp_plan* p, const Tiles& t, Layout* L) {
     if (!proj_tiles_ok(t.proj_rows, t.proj_gw) || !gath_tiles_ok(t.gath_rows, t.gath_sc) || !upd_tiles_ok(t.upd_sc) ||
-        !gath_waves_ok(t.gath_w))
-        return fail(VP_ERR_UNSUPPORTED, "tile shape (%d, %d, %d, %d, %d, %d) is not compiled", t.proj_rows, t.proj_gw,
-                    t.gath_rows, t.gath_sc, t.upd_sc, t.gath_w);
+        !item_waves_ok(t.gath_w) || !item_waves_ok(t.proj_w))
+        return fail(VP_ERR_UNSUPPORTED, "tile shape (%d, %d, %d, %d, %d, %d, %d) is not compiled", t.proj_rows,
+                    t.proj_gw, t.gath_rows, t.gath_sc, t.upd_sc, t.gath_w, t.proj_w);
     const int n = p->n, S = p->S, T = p->T;
     L->tiles = t;
     L->groups.clear();
     L->t_proj.clear();
     L->t_gath.clear();
     L->t_upd.clear();
-    const int group_parts = 4 * t.proj_gw;
+    const int group_parts = t.proj_w * t.proj_gw;
     for (int kt = 0; kt < T; ++kt) {
         for (int e0 = p->knot_ptr[kt]; e0 < p->knot_ptr[kt + 1]; e0 += group_parts) {
             ProjGroup gr{};
@@ -228,7 +228,7 @@ extern "C" vp_status vp_options_default(vp_options* o) {
     o->schedule = VP_SCHED_ALL_BLADES;
     o->split_bin = -1;
     o->device = 0;
-    o->tiles = vp_tiles{0, 0, 0, 0, 0, 0};
+    o->tiles = vp_tiles{0, 0, 0, 0, 0, 0, 0};
     o->autotune = 0;
     o->seed = 0;
     o->data_weight = 1.0f;

@@ -22,7 +22,10 @@ struct Tiles {
     int proj_rows = 2, proj_gw = 1, gath_rows = 2, gath_sc = 1;
     int upd_sc = 0;  // 0: update fused into the gather; else bins per wave of the update pass
     int gath_w = 4;  // waves per gather item
-    int key() const { return proj_rows | proj_gw << 4 | gath_rows << 8 | gath_sc << 12 | upd_sc << 16 | gath_w << 20; }
+    int proj_w = 4;  // waves per projection item
+    int key() const {
+        return proj_rows | proj_gw << 4 | gath_rows << 8 | gath_sc << 12 | upd_sc << 16 | gath_w << 20 | proj_w << 24;
+    }
     bool operator==(const Tiles& o) const { return key() == o.key(); }
 };
 

@@ -11,7 +11,8 @@ namespace vp {
 
 // Kernel launchers (kernels.hip).
 // re: largest staged region (elements) over the work items' slices.
-hipError_t launch_project(const KArgs& a, int rows, int gw, int re, hipStream_t s);
+// waves: 4 or 8 per work item (the layout's proj_w: its groups hold waves * gw parts)
+hipError_t launch_project(const KArgs& a, int rows, int gw, int waves, int re, hipStream_t s);
 // n: the common length of every slice of the launch (0 if they differ).
 hipError_t launch_rows(const KArgs& a, int dir, int n, size_t lds, hipStream_t s);
 hipError_t launch_cols(const KArgs& a, int n, size_t lds, hipStream_t s);

@@ -172,11 +172,13 @@ vp_status check_options(const vp_plan* p, const vp_options* o) {
         return fail(VP_ERR_ARG, "options: betas must lie in [0, 1)");
     if (o->split_bin > p->S) return fail(VP_ERR_ARG, "options: split_bin above n_spec");
     const vp_tiles& t = o->tiles;
-    const bool none = !t.proj_rows && !t.proj_parts && !t.gath_rows && !t.gath_bins && !t.upd_bins && !t.gath_waves;
+    const bool none = !t.proj_rows && !t.proj_parts && !t.gath_rows && !t.gath_bins && !t.upd_bins && !t.gath_waves &&
+                      !t.proj_waves;
     if (!none && (!proj_tiles_ok(t.proj_rows, t.proj_parts) || !gath_tiles_ok(t.gath_rows, t.gath_bins) ||
-                  !upd_tiles_ok(t.upd_bins) || (t.gath_waves != 0 && !gath_waves_ok(t.gath_waves))))
-        return fail(VP_ERR_UNSUPPORTED, "options: tile shape (%d, %d, %d, %d, %d, %d) is not compiled", t.proj_rows,
-                    t.proj_parts, t.gath_rows, t.gath_bins, t.upd_bins, t.gath_waves);
+                  !upd_tiles_ok(t.upd_bins) || (t.gath_waves != 0 && !item_waves_ok(t.gath_waves)) ||
+                  (t.proj_waves != 0 && !item_waves_ok(t.proj_waves))))
+        return fail(VP_ERR_UNSUPPORTED, "options: tile shape (%d, %d, %d, %d, %d, %d, %d) is not compiled",
+                    t.proj_rows, t.proj_parts, t.gath_rows, t.gath_bins, t.upd_bins, t.gath_waves, t.proj_waves);
     return VP_OK;
 }
 
@@ -192,7 +194,7 @@ void launch_step(const KArgs& base, const StageLists& L, hipStream_t s, hipError
     } while (0)
     MARK(0);
     a.tasks = L.proj; a.ntasks = L.n_proj;
-    if ((e = launch_project(a, L.tiles.proj_rows, L.tiles.proj_gw, L.re_proj, s)) != hipSuccess) { *err = e; return; }
+    if ((e = launch_project(a, L.tiles.proj_rows, L.tiles.proj_gw, L.tiles.proj_w, L.re_proj, s)) != hipSuccess) { *err = e; return; }
     MARK(1);
     a.tasks = L.rows; a.ntasks = L.n_rows;
     if ((e = launch_rows(a, -1, L.fft_n, L.lds_rows, s)) != hipSuccess) { *err = e; return; }
@@ -300,7 +302,7 @@ extern "C" vp_status vp_forward(const vp_plan* p, const vp_c64* d_vol, const vp_
     const StageLists L = plan_lists(p, sc.t, sc.lay, sc.dl);
     hipError_t e;
     a.tasks = L.proj; a.ntasks = L.n_proj;
-    if ((e = launch_project(a, L.tiles.proj_rows, L.tiles.proj_gw, L.re_proj, sc.s)) != hipSuccess)
+    if ((e = launch_project(a, L.tiles.proj_rows, L.tiles.proj_gw, L.tiles.proj_w, L.re_proj, sc.s)) != hipSuccess)
         return hip_status(e, "vp_forward project");
     a.tasks = L.rows; a.ntasks = L.n_rows;
     if ((e = launch_rows(a, -1, L.fft_n, L.lds_rows, sc.s)) != hipSuccess) return hip_status(e, "vp_forward rows");
@@ -494,7 +496,7 @@ extern "C" vp_status vp_nu_forward(const vp_plan* p, const vp_c64* d_vol, const 
     const StageLists L = plan_lists(p, sc.t, sc.lay, sc.dl);
     hipError_t e;
     a.tasks = L.proj; a.ntasks = L.n_proj;
-    if ((e = launch_project(a, L.tiles.proj_rows, L.tiles.proj_gw, L.re_proj, sc.s)) != hipSuccess)
+    if ((e = launch_project(a, L.tiles.proj_rows, L.tiles.proj_gw, L.tiles.proj_w, L.re_proj, sc.s)) != hipSuccess)
         return hip_status(e, "vp_nu_forward project");
     nu.d.work = sc.work;
     nu.d.y = (const float2*)d_y;
@@ -593,7 +595,7 @@ struct vp_nu_session {
         }
         a.tasks = L.proj; a.ntasks = L.n_proj;
         hipError_t r = ev ? hipEventRecord(ev[0], str) : hipSuccess;
-        if (r == hipSuccess) r = launch_project(a, L.tiles.proj_rows, L.tiles.proj_gw, L.re_proj, str);
+        if (r == hipSuccess) r = launch_project(a, L.tiles.proj_rows, L.tiles.proj_gw, L.tiles.proj_w, L.re_proj, str);
         if (r == hipSuccess && ev) r = hipEventRecord(ev[1], str);
         if (r == hipSuccess) r = nu.pass(NuScope::ROWS_FWD);
         if (r == hipSuccess && ev) r = hipEventRecord(ev[2], str);
@@ -1068,7 +1070,7 @@ vp_status session_objective_enqueue(vp_session* s, hipStream_t stream) {
     a.one.step_limit = 0x7fffffff;
     const StageLists& L = s->lists;
     a.tasks = L.proj; a.ntasks = L.n_proj;
-    if ((e = launch_project(a, L.tiles.proj_rows, L.tiles.proj_gw, L.re_proj, stream)) != hipSuccess)
+    if ((e = launch_project(a, L.tiles.proj_rows, L.tiles.proj_gw, L.tiles.proj_w, L.re_proj, stream)) != hipSuccess)
         return hip_status(e, "objective");
     a.tasks = L.rows; a.ntasks = L.n_rows;
     if ((e = launch_rows(a, -1, L.fft_n, L.lds_rows, stream)) != hipSuccess) return hip_status(e, "objective");

@@ -79,8 +79,9 @@ bool tuned_tiles(const vp_plan* p, int device, int optimizer, Tiles* out) {
 
 vp_status tiles_for(const vp_plan* p, const vp_options* o, Tiles* out) {
     const vp_tiles& t = o->tiles;
-    if (t.proj_rows || t.proj_parts || t.gath_rows || t.gath_bins || t.upd_bins || t.gath_waves) {
-        *out = Tiles{t.proj_rows, t.proj_parts, t.gath_rows, t.gath_bins, t.upd_bins, t.gath_waves ? t.gath_waves : 4};
+    if (t.proj_rows || t.proj_parts || t.gath_rows || t.gath_bins || t.upd_bins || t.gath_waves || t.proj_waves) {
+        *out = Tiles{t.proj_rows, t.proj_parts, t.gath_rows,                  t.gath_bins,
+                     t.upd_bins,  t.gath_waves ? t.gath_waves : 4, t.proj_waves ? t.proj_waves : 4};
         return VP_OK;
     }
     if (tuned_tiles(p, o->device, o->optimizer, out)) return VP_OK;
@@ -103,7 +104,7 @@ vp_status tune_plan(const vp_plan* p, const vp_options* o, Tiles* out) {
     }
     vp_options so = *o;
     so.tiles = vp_tiles{p->base_tiles.proj_rows, p->base_tiles.proj_gw, p->base_tiles.gath_rows,
-                        p->base_tiles.gath_sc, 0, p->base_tiles.gath_w};
+                        p->base_tiles.gath_sc, 0, p->base_tiles.gath_w, p->base_tiles.proj_w};
     so.autotune = 0;
     vp_session* raw = nullptr;
     st = session_alloc(p, &so, zeros.data(), nullptr, nullptr, &raw);
@@ -113,35 +114,42 @@ vp_status tune_plan(const vp_plan* p, const vp_options* o, Tiles* out) {
 
     Tiles best = p->base_tiles;
     best.upd_sc = 0;
-    // projection: every compiled (rows, parts per wave) that keeps all four waves busy
-    const int gw_cap = std::min(8, pow2_at_least((std::max(1, p->max_knot_parts) + 3) / 4));
+    // projection: every compiled (rows, parts per wave) with four and with eight waves per
+    // item that keeps every wave busy (eight only where a knot has more than four parts)
     float best_ms = FLT_MAX;
-    for (int rows = 1; rows <= 8; rows *= 2) {
-        for (int gw = 1; gw <= gw_cap; gw *= 2) {
-            if (!proj_tiles_ok(rows, gw)) continue;
-            Tiles t = p->base_tiles;
-            t.proj_rows = rows;
-            t.proj_gw = gw;
-            const Layout* L = nullptr;
-            const DeviceLayout* dl = nullptr;
-            if (plan_layout(p, t, &L) != VP_OK) {
-                clear_error();
-                continue;
-            }
-            if ((st = device_layout(p, tabs, L, &dl)) != VP_OK) return st;
-            KArgs a{};
-            a.one = s->desc;
-            a.one.groups = dl->groups;
-            a.tasks = dl->t_proj;
-            a.ntasks = (int)L->t_proj.size();
-            float ms = 0.f;
-            st = time_launches(
-                s->stream, kReps, [&] { return launch_project(a, rows, gw, L->re_proj, s->stream); }, &ms);
-            if (st != VP_OK) return st;
-            if (ms < best_ms) {
-                best_ms = ms;
-                best.proj_rows = rows;
-                best.proj_gw = gw;
+    for (int waves = 4; waves <= 8; waves += 4) {
+        if (waves == 8 && p->max_knot_parts <= 4) break;
+        const int gw_cap = std::min(8, pow2_at_least((std::max(1, p->max_knot_parts) + waves - 1) / waves));
+        for (int rows = 1; rows <= 8; rows *= 2) {
+            for (int gw = 1; gw <= gw_cap; gw *= 2) {
+                if (!proj_tiles_ok(rows, gw)) continue;
+                Tiles t = p->base_tiles;
+                t.proj_rows = rows;
+                t.proj_gw = gw;
+                t.proj_w = waves;
+                const Layout* L = nullptr;
+                const DeviceLayout* dl = nullptr;
+                if (plan_layout(p, t, &L) != VP_OK) {
+                    clear_error();
+                    continue;
+                }
+                if ((st = device_layout(p, tabs, L, &dl)) != VP_OK) return st;
+                KArgs a{};
+                a.one = s->desc;
+                a.one.groups = dl->groups;
+                a.tasks = dl->t_proj;
+                a.ntasks = (int)L->t_proj.size();
+                float ms = 0.f;
+                st = time_launches(
+                    s->stream, kReps,
+                    [&] { return launch_project(a, rows, gw, waves, L->re_proj, s->stream); }, &ms);
+                if (st != VP_OK) return st;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best.proj_rows = rows;
+                    best.proj_gw = gw;
+                    best.proj_w = waves;
+                }
             }
         }
     }
@@ -239,7 +247,7 @@ vp_status tune_plan(const vp_plan* p, const vp_options* o, Tiles* out) {
 using namespace vp;
 
 static vp_tiles to_abi(const Tiles& t) {
-    return vp_tiles{t.proj_rows, t.proj_gw, t.gath_rows, t.gath_sc, t.upd_sc, t.gath_w};
+    return vp_tiles{t.proj_rows, t.proj_gw, t.gath_rows, t.gath_sc, t.upd_sc, t.gath_w, t.proj_w};
 }
 
 extern "C" vp_status vp_plan_tune(const vp_plan* p, const vp_options* o, vp_tiles* out) {

@@ -38,8 +38,8 @@ __host__ __device__ constexpr bool proj_tiles_ok(int rows, int gw) {
 __host__ __device__ constexpr bool gath_tiles_ok(int rows, int sc) {
     return pow2_le(rows, 4) && rows >= 2 && pow2_le(sc, 8) && rows * sc <= 16;
 }
-// Waves per gather item (the waves share the item's staged blade regions).
-__host__ __device__ constexpr bool gath_waves_ok(int w) { return w == 4 || w == 8; }
+// Waves per projection or gather item (the waves share the item's staged regions).
+__host__ __device__ constexpr bool item_waves_ok(int w) { return w == 4 || w == 8; }
 // The optimiser update runs fused into the gather (0) or as a separate pass over the
 // stored data gradient with 2, 4 or 8 bins per wave.
 __host__ __device__ constexpr bool upd_tiles_ok(int sc) { return sc == 0 || sc == 2 || sc == 4 || sc == 8; }
