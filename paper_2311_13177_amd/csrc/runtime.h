@@ -59,7 +59,7 @@ vp_status tune_plan(const vp_plan* p, const vp_options* o, Tiles* out);
 // gather + update, step counter advance) for the descriptors `base` refers to.
 // With `ev` (kStages + 1 events) an event is recorded before each stage and after the last.
 void launch_step(const KArgs& base, const StageLists& L, hipStream_t s, hipError_t* err, hipEvent_t* ev = nullptr);
-constexpr int kStages = 5;
+constexpr int kStages = 6;
 // Per-slice device counter block: the step counter (int at offset 0).
 constexpr size_t kCounterBytes = 256;
 

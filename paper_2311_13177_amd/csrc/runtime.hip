@@ -214,12 +214,13 @@ void launch_step(const KArgs& base, const StageLists& L, hipStream_t s, hipError
         a.tasks = L.upd; a.ntasks = L.n_upd;
         if (e == hipSuccess) e = launch_update(a, L.tiles.upd_sc, s);
     }
-    if (e == hipSuccess) e = launch_advance(base, L.n_slices, s);
     if (e != hipSuccess) {
         *err = e;
         return;
     }
     MARK(5);
+    if ((e = launch_advance(base, L.n_slices, s)) != hipSuccess) { *err = e; return; }
+    MARK(6);
 #undef MARK
     *err = hipSuccess;
 }
