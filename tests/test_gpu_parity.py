@@ -293,6 +293,26 @@ def test_graph_equals_eager_and_resume_is_bitwise(gpu_lib):
     assert np.array_equal(d.read()["vol"], ra["vol"])
 
 
+def test_stage_times_are_real_steps(gpu_lib):
+    # the profiled steps are ordinary steps: six positive stage means, and the state after
+    # them equals that of the same number of graph-replayed steps, bit for bit
+    from paper_2311_13177_amd import binding as B
+
+    case = small("dynamic_40")
+    y = O.simulate_measurements(case)
+    plan = B.Plan.from_geometry(case.geometry())
+    opts = B.vp_options_default(n_steps=9)
+    a = B.Session(plan, y, opts)
+    a.step(4, use_graph=True)
+    st = a.stage_times(5)
+    assert tuple(st) == B.Session.STAGES
+    assert all(np.isfinite(v) and v > 0 for v in st.values())
+    b = B.Session(plan, y, opts)
+    b.step(9, use_graph=True)
+    assert a.steps_done == 9
+    assert np.array_equal(a.read()["vol"], b.read()["vol"])
+
+
 def test_nonfinite_measurement_rejected(gpu_lib):
     from paper_2311_13177_amd import binding as B
 
