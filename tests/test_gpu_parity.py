@@ -225,6 +225,8 @@ def test_reconstruct_static_64_full(gpu_lib):
 def test_reconstruct_full_size_first_steps(gpu_lib, name):
     """Full-size workloads in the benchmark's launch configuration, first steps only.
 
+    The plan's own tile shape is checked against the oracle, and the autotuned shape (the
+    one bench.py times, eight-wave items at 256^2) must give the same bits.
     Gradient descent keeps the dynamics linear, so FP32 rounding is not amplified and
     the whole volume must agree to the operator tolerance. With Adam the rendered
     image is compared: Adam normalises Re and Im separately, and with a real-valued
@@ -253,6 +255,10 @@ def test_reconstruct_full_size_first_steps(gpu_lib, name):
     # the phantom lives) must already meet the image tolerance
     assert rel(got["vol"].real, want["vol"].real) < RECON_TOL
     assert rel(got["proj"].real, want["proj"].real) < RECON_TOL
+    tuned_opts = B.vp_options_default(n_steps=steps, tv_weight=case.tv_weight, lr=case.lr, autotune=1)
+    tuned = B.vp_reconstruct(plan, y, tuned_opts)
+    print(f"{name} tuned shape {plan.tiles(tuned_opts)}")
+    assert np.array_equal(tuned["vol"], got["vol"]) and tuned["final_loss"] == got["final_loss"]
 
 
 def test_reconstruct_dynamic_converged(gpu_lib):
