@@ -175,6 +175,22 @@ def test_one_blade_schedules_match_the_oracle(gpu_lib, name, optimizer, schedule
     assert abs(got["final_loss"] - want["final_loss"]) <= 1e-3 * abs(want["final_loss"])
 
 
+@pytest.mark.parametrize("name", sorted(FIT_CASES))
+def test_fit_is_the_same_for_every_tile_shape(gpu_lib, name):
+    # the blade-aligned fit runs the Cartesian projection and gather kernels: four- and
+    # eight-wave items, fused or separate update, give the same bits
+    from paper_2311_13177_amd import binding as B
+
+    case = configs.small_case(**FIT_CASES[name])
+    plan = B.Plan.from_geometry(case.geometry())
+    packed = _pack(N.simulate_samples(case), B.nu_shape(plan)).astype(np.complex64)
+    ref = B.vp_nu_reconstruct(plan, packed, B.vp_options_default(n_steps=6))
+    for sh in [(4, 1, 4, 2, 0, 8, 8), (2, 2, 2, 4, 0, 8, 4), (8, 1, 2, 8, 0, 4, 8), (1, 1, 4, 1, 4, 8, 8)]:
+        got = B.vp_nu_reconstruct(plan, packed, B.vp_options_default(n_steps=6, tiles=sh))
+        assert all(np.array_equal(got[k], ref[k]) for k in ("vol", "proj", "water", "fat")), sh
+        assert got["final_loss"] == ref["final_loss"], sh
+
+
 def test_fit_rejects_bad_samples(gpu_lib):
     from paper_2311_13177_amd import binding as B
 
