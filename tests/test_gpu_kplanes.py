@@ -127,6 +127,21 @@ def test_graph_equals_eager_and_stage_times(gpu_lib):
     b.close()
 
 
+def test_autotuned_blade_passes_give_the_same_bits(gpu_lib):
+    # the per-blade plan's autotuned tile shape (the one bench.py times) against its own
+    # heuristic shape: the blade passes cut the work differently, the sums stay the same
+    B, torch, case, plan, geom, cfg, model, y = _setup("dyn_64", (0.01, 0.02, 0.005))
+    init = init_params(geom.n_spec, cfg.features, cfg.time_res, cfg.spatial_res, seed=6)
+    a = B.KPlanesSession(plan, model, y, init, B.vp_options_default(lr=1e-2))
+    b = B.KPlanesSession(plan, model, y, init, B.vp_options_default(lr=1e-2, autotune=1))
+    a.step(4, use_graph=True)
+    b.step(4, use_graph=True)
+    ra, rb = a.read((0.5,), objective=True), b.read((0.5,), objective=True)
+    assert np.array_equal(ra["params"], rb["params"]) and ra["objective"] == rb["objective"]
+    a.close()
+    b.close()
+
+
 def test_degenerate_grids_and_a_single_blade(gpu_lib):
     # one time node, an x/y axis of a single node, and a plan of one blade (its per-blade
     # plan is static); decode and gradient still follow the oracle
