@@ -174,19 +174,23 @@ template <int SCM, int PPT, int EPI>
 __device__ __forceinline__ void load_moments(const KArgs& a, int slice, int kt, int y0, int x0, int lane, int sw,
                                              int ns, float2 (&pm)[SCM][PPT], float2 (&pv)[SCM][PPT]) {
     const int n = DF(n), S = DF(S);
-    const bool adam = EPI == EPI_ADAM_TV || DF(optimizer) == VP_OPT_ADAM;
+#pragma unroll
+    for (int q = 0; q < SCM; ++q)
+#pragma unroll
+        for (int i = 0; i < PPT; ++i) pm[q][i] = pv[q][i] = make_float2(0.f, 0.f);
+    // gradient descent keeps no moments (the arrays may be absent)
+    if (!(EPI == EPI_ADAM_TV || DF(optimizer) == VP_OPT_ADAM)) return;
     const int nn = n * n, kvol = S * nn;
     const size_t kbase = (size_t)kt * kvol;
-    const __amdgpu_buffer_rsrc_t rM = plane_rsrc(DF(m) + kbase, adam ? kvol : 0);
-    const __amdgpu_buffer_rsrc_t rW = plane_rsrc(DF(v) + kbase, adam ? kvol : 0);
+    const __amdgpu_buffer_rsrc_t rM = plane_rsrc(DF(m) + kbase, kvol);
+    const __amdgpu_buffer_rsrc_t rW = plane_rsrc(DF(v) + kbase, kvol);
     const int xc = min(x0 + lane, n - 1);
 #pragma unroll
     for (int q = 0; q < SCM; ++q)
 #pragma unroll
         for (int i = 0; i < PPT; ++i) {
-            pm[q][i] = pv[q][i] = make_float2(0.f, 0.f);
             const int y = y0 + i;
-            if (adam && q < ns && y < n) {
+            if (q < ns && y < n) {
                 const int vo = (y * n + xc) * (int)sizeof(float2), so = (sw + q) * nn * (int)sizeof(float2);
                 pm[q][i] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rM, vo, so, 0));
                 pv[q][i] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rW, vo, so, 0));
