@@ -222,11 +222,12 @@ extern "C" vp_status vp_batch_reconstruct(int32_t n, const vp_plan* const* plans
             o.autotune = 0;
             const vp_tiles& ot = o.tiles;
             const Layout* lay = nullptr;
-            if (have_shape && !ot.proj_rows && !ot.proj_parts && !ot.gath_rows && !ot.gath_bins && !ot.upd_bins && !ot.gath_waves &&
-                !ot.proj_waves) {
+            const bool unset = !ot.proj_rows && !ot.proj_parts && !ot.gath_rows && !ot.gath_bins && !ot.upd_bins &&
+                               !ot.gath_waves && !ot.proj_waves;
+            if (have_shape && unset) {
                 if (plan_layout(plans[i], shape, &lay) == VP_OK)
                     o.tiles = vp_tiles{shape.proj_rows, shape.proj_gw, shape.gath_rows, shape.gath_sc,
-                                       shape.upd_sc,    shape.gath_w,  shape.proj_w};
+                                       shape.upd_sc, shape.gath_w, shape.proj_w};
                 else
                     clear_error();
             }

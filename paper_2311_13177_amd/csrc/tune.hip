@@ -80,8 +80,8 @@ bool tuned_tiles(const vp_plan* p, int device, int optimizer, Tiles* out) {
 vp_status tiles_for(const vp_plan* p, const vp_options* o, Tiles* out) {
     const vp_tiles& t = o->tiles;
     if (t.proj_rows || t.proj_parts || t.gath_rows || t.gath_bins || t.upd_bins || t.gath_waves || t.proj_waves) {
-        *out = Tiles{t.proj_rows, t.proj_parts, t.gath_rows,                  t.gath_bins,
-                     t.upd_bins,  t.gath_waves ? t.gath_waves : 4, t.proj_waves ? t.proj_waves : 4};
+        *out = Tiles{t.proj_rows, t.proj_parts, t.gath_rows, t.gath_bins, t.upd_bins,
+                     t.gath_waves ? t.gath_waves : 4, t.proj_waves ? t.proj_waves : 4};
         return VP_OK;
     }
     if (tuned_tiles(p, o->device, o->optimizer, out)) return VP_OK;
