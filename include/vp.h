@@ -374,10 +374,10 @@ vp_status vp_session_set_state(vp_session* session, const vp_c64* volume, const 
 
 /* Profiling: runs n_steps more steps eagerly on the session stream with a HIP
  * event recorded before and after every stage, and writes the mean duration in
- * milliseconds of each stage to stage_ms[6]: projection, forward row DFT,
- * column pass (DFT, mask, residual, inverse DFT), inverse row DFT, the gather
- * with the regulariser gradient and optimiser update, and the step counter's
- * advance (a one-block kernel). */
+ * milliseconds of each stage to stage_ms[5]: projection, forward row DFT,
+ * column pass (DFT, mask, residual, inverse DFT), inverse row DFT, and the
+ * gather with the regulariser gradient and optimiser update (whose first block
+ * also advances the step counter). */
 vp_status vp_session_stage_times(vp_session* session, int32_t n_steps, double* stage_ms);
 
 vp_status vp_session_destroy(vp_session* session);

@@ -559,7 +559,7 @@ class Session:
         check(lib().vp_session_read(self.handle, _hp(vol), *[_hp(o) for o in outs]))
         return dict(vol=vol, proj=outs[0], water=outs[1], fat=outs[2])
 
-    STAGES = ("project", "rows_fwd", "cols", "rows_inv", "gather_update", "advance")
+    STAGES = ("project", "rows_fwd", "cols", "rows_inv", "gather_update")
 
     def stage_times(self, n_steps: int) -> dict:
         """Mean milliseconds per stage over n_steps eager steps (HIP events on the session stream)."""

@@ -199,7 +199,7 @@ __device__ __forceinline__ void load_moments(const KArgs& a, int slice, int kt, 
 }
 
 // Regulariser gradient and optimiser update of a lane's voxels (update_column) with the
-// slice's hyperparameters (the step counter is advanced by k_advance after the pass).
+// slice's hyperparameters (block 0 of the step's last kernel advances the step counter).
 // PRE: the moments come from load_moments (pm, pv) instead of being loaded here.
 template <int SCM, int PPT, int EPI, bool PRE>
 __device__ __forceinline__ void update_and_finish(const KArgs& a, int slice, int* stepp, int st,
@@ -249,11 +249,12 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
     extern __shared__ float2 sm[];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (a.advance) step_advance(a);
     for (int ti = xcd_item(blockIdx.x, gridDim.x); ti < a.ntasks; ti += gridDim.x) {
         const AS4 Task* tk = cst(a.tasks) + ti;
         const int slice = tk->slice;
         int* const stepp = DF(step);
-        const int st = read_step(stepp);
+        const int st = read_step_at(stepp, a.snap);
         if (stepp && st >= DF(step_limit)) continue;
         const int n = DF(n), S = DF(S), T = DF(T), B = DF(B), nparts = DF(nparts), sched = DF(schedule);
         const unsigned sseed = DF(sched_seed);
@@ -407,11 +408,12 @@ template <int SC, int EPI>
 __global__ __launch_bounds__(kThreads) void k_update(const KArgs a) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (a.advance) step_advance(a);
     for (int ti = xcd_item(blockIdx.x, gridDim.x); ti < a.ntasks; ti += gridDim.x) {
         const AS4 Task* tk = cst(a.tasks) + ti;
         const int slice = tk->slice;
         int* const stepp = DF(step);
-        const int st = read_step(stepp);
+        const int st = read_step_at(stepp, a.snap);
         if (stepp && st >= DF(step_limit)) continue;
         const int n = DF(n), S = DF(S);
         const int kt = tk->a;

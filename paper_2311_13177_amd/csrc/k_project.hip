@@ -17,6 +17,7 @@ __global__ __launch_bounds__(64 * NW) void k_project(const KArgs a) {
     extern __shared__ float2 sm[];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (a.snap) step_snapshot(a);
     for (int ti = xcd_item(blockIdx.x, gridDim.x); ti < a.ntasks; ti += gridDim.x) {
         const AS4 Task* tk = cst(a.tasks) + ti;
         const int slice = tk->slice;

@@ -125,20 +125,6 @@ __global__ __launch_bounds__(kThreads) void k_render(const KArgs a) {
     }
 }
 
-// Ends an optimiser step: advances the step counter of every slice below its step
-// limit. Launched after the step's last kernel, so every work item of the step has read
-// the counter; no work item waits for, or counts, the others.
-__global__ __launch_bounds__(kThreads) void k_advance(const KArgs a) {
-    for (int slice = blockIdx.x * blockDim.x + threadIdx.x; slice < a.ntasks; slice += gridDim.x * blockDim.x) {
-        int* const stepp = a.descs ? a.descs[slice].step : a.one.step;
-        const int limit = a.descs ? a.descs[slice].step_limit : a.one.step_limit;
-        if (stepp) {
-            const int st = *stepp;
-            if (st < limit) *stepp = st + 1;
-        }
-    }
-}
-
 // ------------------------------------------------------------------ launchers
 
 static inline int grid_for(int ntasks) { return ntasks < 1 ? 1 : (ntasks > (1 << 20) ? (1 << 20) : ntasks); }
@@ -151,13 +137,6 @@ hipError_t launch_tv_grad(const KArgs& a, hipStream_t s) {
 hipError_t launch_reg_value(const KArgs& a, hipStream_t s) {
     if (a.ntasks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_reg_value, dim3(grid_for(a.ntasks)), dim3(kThreads), 0, s, a);
-    return hipGetLastError();
-}
-hipError_t launch_advance(const KArgs& a, int nslices, hipStream_t s) {
-    if (nslices <= 0) return hipSuccess;
-    KArgs b = a;
-    b.ntasks = nslices;
-    hipLaunchKernelGGL(k_advance, dim3((nslices + kThreads - 1) / kThreads), dim3(kThreads), 0, s, b);
     return hipGetLastError();
 }
 hipError_t launch_render(const KArgs& a, hipStream_t s) {

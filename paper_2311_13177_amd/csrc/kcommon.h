@@ -63,6 +63,36 @@ __device__ __forceinline__ bool active_blade(int sched, unsigned seed, const int
     return (unsigned long long)b == splitmix64(x) % (unsigned long long)B;
 }
 __device__ __forceinline__ int read_step(const int* stepp) { return stepp ? *cst(stepp) : 0; }
+// The step as the step's last kernel reads it (a.snap): the copy its first kernel took,
+// while block 0 of the last kernel advances the counter itself.
+__device__ __forceinline__ int read_step_at(const int* stepp, int snap) {
+    return stepp ? *cst(snap ? stepp + kSnapWord : stepp) : 0;
+}
+
+// Block 0 of a step's first kernel: copy each slice's step counter to its snapshot word.
+// No kernel of the step writes the counter before the last one, and only the last one
+// reads the snapshot.
+__device__ __forceinline__ void step_snapshot(const KArgs& a) {
+    if (blockIdx.x != 0) return;
+    for (int slice = threadIdx.x; slice < a.nslices; slice += blockDim.x) {
+        int* const stepp = a.descs ? a.descs[slice].step : a.one.step;
+        if (stepp) stepp[kSnapWord] = *stepp;
+    }
+}
+// Block 0 of a step's last kernel: advance each slice's counter below its step limit,
+// from the snapshot. Every work item of this kernel reads the snapshot, none the counter,
+// so the new value is seen only by the kernels of the next step.
+__device__ __forceinline__ void step_advance(const KArgs& a) {
+    if (blockIdx.x != 0) return;
+    for (int slice = threadIdx.x; slice < a.nslices; slice += blockDim.x) {
+        int* const stepp = a.descs ? a.descs[slice].step : a.one.step;
+        const int limit = a.descs ? a.descs[slice].step_limit : a.one.step_limit;
+        if (stepp) {
+            const int st = stepp[kSnapWord];
+            if (st < limit) *stepp = st + 1;
+        }
+    }
+}
 
 // Charbonnier weight d / sqrt(|d|^2 + eps^2): the gradient of sqrt(|d|^2 + eps^2) - eps.
 // The hardware reciprocal square root (about 1 ulp). Callers pass eps2 = max(eps^2,

@@ -19,7 +19,6 @@ hipError_t launch_cols(const KArgs& a, int n, size_t lds, hipStream_t s);
 // waves: 4 or 8 per work item (the layout's gath_w: its bin chunks hold waves * sc bins)
 hipError_t launch_gather(const KArgs& a, int mode, int rows, int sc, int waves, int re, hipStream_t s);
 hipError_t launch_update(const KArgs& a, int sc, hipStream_t s);
-hipError_t launch_advance(const KArgs& a, int nslices, hipStream_t s);
 hipError_t launch_tv_grad(const KArgs& a, hipStream_t s);
 hipError_t launch_reg_value(const KArgs& a, hipStream_t s);
 hipError_t launch_render(const KArgs& a, hipStream_t s);
@@ -56,12 +55,15 @@ bool tuned_tiles(const vp_plan* p, int device, int optimizer, Tiles* out);
 // Measures the candidate tile shapes on the current device and records the fastest.
 vp_status tune_plan(const vp_plan* p, const vp_options* o, Tiles* out);
 // Enqueues one optimiser step (project, row DFT, column pass, inverse row DFT,
-// gather + update, step counter advance) for the descriptors `base` refers to.
+// gather + update, the last also advancing the step counters) for the descriptors
+// `base` refers to.
 // With `ev` (kStages + 1 events) an event is recorded before each stage and after the last.
 void launch_step(const KArgs& base, const StageLists& L, hipStream_t s, hipError_t* err, hipEvent_t* ev = nullptr);
-constexpr int kStages = 6;
-// Per-slice device counter block: the step counter (int at offset 0).
+constexpr int kStages = 5;
+// Per-slice device counter block: the step counter (int at offset 0) and its snapshot
+// (int kSnapWord).
 constexpr size_t kCounterBytes = 256;
+static_assert(kCounterBytes >= (kSnapWord + 1) * sizeof(int), "counter block holds the snapshot");
 
 vp_status hip_status(hipError_t e, const char* what);
 vp_status check_options(const vp_plan* p, const vp_options* o);

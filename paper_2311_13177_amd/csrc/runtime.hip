@@ -193,8 +193,13 @@ void launch_step(const KArgs& base, const StageLists& L, hipStream_t s, hipError
         if (ev && (e = hipEventRecord(ev[i], s)) != hipSuccess) { *err = e; return; }  \
     } while (0)
     MARK(0);
+    // the projection snapshots the step counters, the last kernel reads the snapshot and
+    // advances them (step_snapshot, step_advance)
+    a.nslices = L.n_slices;
+    a.snap = 1;
     a.tasks = L.proj; a.ntasks = L.n_proj;
     if ((e = launch_project(a, L.tiles.proj_rows, L.tiles.proj_gw, L.tiles.proj_w, L.re_proj, s)) != hipSuccess) { *err = e; return; }
+    a.snap = 0;
     MARK(1);
     a.tasks = L.rows; a.ntasks = L.n_rows;
     if ((e = launch_rows(a, -1, L.fft_n, L.lds_rows, s)) != hipSuccess) { *err = e; return; }
@@ -206,12 +211,14 @@ void launch_step(const KArgs& base, const StageLists& L, hipStream_t s, hipError
     if ((e = launch_rows(a, 1, L.fft_n, L.lds_rows, s)) != hipSuccess) { *err = e; return; }
     MARK(4);
     a.tasks = L.gath; a.ntasks = L.n_gath;
+    a.snap = 1;
     if (L.tiles.upd_sc == 0) {
+        a.advance = 1;
         e = launch_gather(a, GATHER_STEP, L.tiles.gath_rows, L.tiles.gath_sc, L.tiles.gath_w, L.re_gath, s);
     } else {
         a.accumulate = 0;
         e = launch_gather(a, GATHER_STORE, L.tiles.gath_rows, L.tiles.gath_sc, L.tiles.gath_w, L.re_gath, s);
-        a.tasks = L.upd; a.ntasks = L.n_upd;
+        a.tasks = L.upd; a.ntasks = L.n_upd; a.advance = 1;
         if (e == hipSuccess) e = launch_update(a, L.tiles.upd_sc, s);
     }
     if (e != hipSuccess) {
@@ -219,8 +226,6 @@ void launch_step(const KArgs& base, const StageLists& L, hipStream_t s, hipError
         return;
     }
     MARK(5);
-    if ((e = launch_advance(base, L.n_slices, s)) != hipSuccess) { *err = e; return; }
-    MARK(6);
 #undef MARK
     *err = hipSuccess;
 }
@@ -595,6 +600,8 @@ struct vp_nu_session {
             a.one.step_limit = 0x7fffffff;
         }
         a.tasks = L.proj; a.ntasks = L.n_proj;
+        a.snap = 1;  // snapshot of the step counter for the step's last kernel
+        a.nslices = 1;
         hipError_t r = ev ? hipEventRecord(ev[0], str) : hipSuccess;
         if (r == hipSuccess) r = launch_project(a, L.tiles.proj_rows, L.tiles.proj_gw, L.tiles.proj_w, L.re_proj, str);
         if (r == hipSuccess && ev) r = hipEventRecord(ev[1], str);
@@ -622,16 +629,18 @@ struct vp_nu_session {
         a.one = s->desc;
         a.epi = L.epi;
         a.tasks = L.gath; a.ntasks = L.n_gath;
+        a.snap = 1;  // the last kernel reads the snapshot and advances the counter
+        a.nslices = 1;
         if (r == hipSuccess) {
             if (L.tiles.upd_sc == 0) {
+                a.advance = 1;
                 r = launch_gather(a, GATHER_STEP, L.tiles.gath_rows, L.tiles.gath_sc, L.tiles.gath_w, L.re_gath, str);
             } else {
                 r = launch_gather(a, GATHER_STORE, L.tiles.gath_rows, L.tiles.gath_sc, L.tiles.gath_w, L.re_gath, str);
-                a.tasks = L.upd; a.ntasks = L.n_upd;
+                a.tasks = L.upd; a.ntasks = L.n_upd; a.advance = 1;
                 if (r == hipSuccess) r = launch_update(a, L.tiles.upd_sc, str);
             }
         }
-        if (r == hipSuccess) r = launch_advance(a, 1, str);
         if (r == hipSuccess && ev) r = hipEventRecord(ev[kNuStages], str);
         return r;
     }

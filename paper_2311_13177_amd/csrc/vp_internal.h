@@ -170,7 +170,17 @@ struct KArgs {
                                  // in the frame: only rows [0, m - m/2) and [n - m/2, n) are
                                  // nonzero on input (forward) or needed on output (inverse)
     NuEdge nue;                  // with live_n != 0: the row passes' blade-image ends
+    // A fit step's first kernel (snap) copies the step counters of slices 0 .. nslices - 1
+    // to their snapshot words; its last kernel (snap) reads the step from the snapshot and,
+    // with advance, its block 0 advances the counters (step_snapshot, step_advance).
+    int snap;
+    int advance;
+    int nslices;
 };
+
+// The allocation of a fit's step counter holds, kSnapWord ints after the counter, the
+// copy of the counter that the step's last kernel reads.
+constexpr int kSnapWord = 32;
 
 // Column pass modes.
 // COL_INVERSE (column and inverse row pass): in-place unscaled inverse DFT of the frames at

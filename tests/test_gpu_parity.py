@@ -300,7 +300,7 @@ def test_graph_equals_eager_and_resume_is_bitwise(gpu_lib):
 
 
 def test_stage_times_are_real_steps(gpu_lib):
-    # the profiled steps are ordinary steps: six positive stage means, and the state after
+    # the profiled steps are ordinary steps: five positive stage means, and the state after
     # them equals that of the same number of graph-replayed steps, bit for bit
     from paper_2311_13177_amd import binding as B
 
