@@ -249,7 +249,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
     extern __shared__ float2 sm[];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (a.advance) step_advance(a);
+    // only a fused step ends a step here (a storing gather leaves it to the update pass);
+    // compiled into the step variants alone, so the storing ones keep their registers
+    if constexpr (MODE == GATHER_STEP) {
+        if (a.advance) step_advance(a);
+    }
     for (int ti = xcd_item(blockIdx.x, gridDim.x); ti < a.ntasks; ti += gridDim.x) {
         const AS4 Task* tk = cst(a.tasks) + ti;
         const int slice = tk->slice;
