@@ -411,6 +411,25 @@ typedef struct {
 vp_status vp_batch_reconstruct(int32_t n, const vp_plan* const* plans, const vp_options* const* opts,
                                const vp_c64* const* kspace, vp_result* const* results);
 
+/* A resident batch: the slices of vp_batch_reconstruct uploaded once and stepped
+ * together, for callers that step, time or read a batch in parts. vp_batch_create
+ * uploads every slice (kspace[i] host [B_i][n_i][n_i]) to opts[0]->device, picks the
+ * batch's tile shape as vp_batch_reconstruct does and builds the concatenated work
+ * lists; a slice that cannot be set up is reported by vp_batch_read (the call returns
+ * its status, the others still run). *out stays NULL if no slice could be set up.
+ * vp_batch_step runs n_steps batched steps (use_graph != 0: one captured step replayed;
+ * slice i stops at opts[i]->n_steps) and waits. vp_batch_stage_times runs n_steps more
+ * eagerly with a HIP event around each stage (stage_ms[5] as in vp_session_stage_times,
+ * each stage one launch over all slices). vp_batch_read copies slice i's outputs and its
+ * objective into *result (NULL output pointers skip). */
+typedef struct vp_batch vp_batch;
+vp_status vp_batch_create(int32_t n, const vp_plan* const* plans, const vp_options* const* opts,
+                          const vp_c64* const* kspace, vp_batch** out);
+vp_status vp_batch_step(vp_batch* batch, int32_t n_steps, int32_t use_graph);
+vp_status vp_batch_stage_times(vp_batch* batch, int32_t n_steps, double* stage_ms);
+vp_status vp_batch_read(vp_batch* batch, int32_t i, vp_result* result);
+vp_status vp_batch_destroy(vp_batch* batch);
+
 /* ------------------------------------------------------------------ K-Planes dynamic model */
 
 /* The complex K-Planes volume model of Section 4.1 (its equation and the paragraph

@@ -73,8 +73,3 @@ def blade_aligned_forward(vol: torch.Tensor, plan: "B.Plan", y: torch.Tensor | N
 def lifted_forward(vol: torch.Tensor, plan: "B.Plan", y: torch.Tensor | None = None) -> torch.Tensor:
     return LiftedForward.apply(vol, plan, y)
 
-
-def data_loss(vol: torch.Tensor, plan: "B.Plan", y: torch.Tensor) -> torch.Tensor:
-    """0.5 * sum |M (A vol) - M y|^2 as a differentiable scalar (float64 accumulation)."""
-    r = lifted_forward(vol, plan, y)
-    return 0.5 * torch.sum(torch.view_as_real(r).to(torch.float64) ** 2)

@@ -139,6 +139,11 @@ _PROTOS = {
     "vp_reconstruct": (c_int32, [_P, POINTER(vp_options), _P, _P, _P, _P, _P, _P, POINTER(c_double)]),
     "vp_batch_reconstruct": (c_int32, [c_int32, POINTER(_P), POINTER(POINTER(vp_options)), POINTER(_P),
                                        POINTER(POINTER(vp_result))]),
+    "vp_batch_create": (c_int32, [c_int32, POINTER(_P), POINTER(POINTER(vp_options)), POINTER(_P), POINTER(_P)]),
+    "vp_batch_step": (c_int32, [_P, c_int32, c_int32]),
+    "vp_batch_stage_times": (c_int32, [_P, c_int32, POINTER(c_double)]),
+    "vp_batch_read": (c_int32, [_P, c_int32, POINTER(vp_result)]),
+    "vp_batch_destroy": (c_int32, [_P]),
     "vp_kplanes_param_count": (c_int32, [_P, POINTER(vp_kplanes), POINTER(c_int64)]),
     "vp_kplanes_decode": (c_int32, [_P, POINTER(vp_kplanes), _P, POINTER(c_double), c_int32, _P, _P]),
     "vp_kplanes_gradient": (c_int32, [_P, POINTER(vp_kplanes), _P, _P, _P, POINTER(c_double),
@@ -678,6 +683,51 @@ def vp_batch_reconstruct(plans: Sequence[Plan], kspaces: Sequence[np.ndarray],
     if status != VP_OK and all(r["status"] == VP_OK for r in out):
         check(status)
     return out
+
+
+class Batch:
+    """A resident batch of slices (vp_batch_*): created once, stepped, timed and read."""
+
+    STAGES = ("project", "rows_fwd", "cols", "rows_inv", "gather_update")
+
+    def __init__(self, plans: Sequence[Plan], kspaces: Sequence[np.ndarray], opts: Sequence[vp_options]):
+        n = len(plans)
+        self.plans = list(plans)
+        ks = [_host_c64(k, p.blade_shape) for p, k in zip(plans, kspaces)]
+        self._opts = list(opts)
+        plan_arr = (c_void_p * n)(*[p.handle.value for p in plans])
+        opt_arr = (POINTER(vp_options) * n)(*[ctypes.pointer(o) for o in self._opts])
+        k_arr = (c_void_p * n)(*[k.ctypes.data for k in ks])
+        h = c_void_p()
+        st = lib().vp_batch_create(n, plan_arr, opt_arr, k_arr, byref(h))
+        self.handle = h if h.value else None
+        if self.handle is None:
+            check(st)
+
+    def step(self, n_steps: int, use_graph: bool = True) -> None:
+        check(lib().vp_batch_step(self.handle, int(n_steps), int(bool(use_graph))))
+
+    def stage_times(self, n_steps: int) -> dict:
+        out = (c_double * len(self.STAGES))()
+        check(lib().vp_batch_stage_times(self.handle, int(n_steps), out))
+        return dict(zip(self.STAGES, list(out)))
+
+    def read(self, i: int) -> dict:
+        p = self.plans[i]
+        vol = np.empty(p.volume_shape, np.complex64)
+        rend = [np.empty(p.render_shape, np.complex64) for _ in range(3)]
+        res = vp_result(volume_out=vol.ctypes.data, proj_out=rend[0].ctypes.data, water_out=rend[1].ctypes.data,
+                        fat_out=rend[2].ctypes.data)
+        st = lib().vp_batch_read(self.handle, int(i), byref(res))
+        return dict(vol=vol, proj=rend[0], water=rend[1], fat=rend[2], final_loss=float(res.final_loss),
+                    steps_done=int(res.steps_done), status=int(st))
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            lib().vp_batch_destroy(self.handle)
+        self.handle = None
+
+    __del__ = close
 
 
 # ------------------------------------------------------------------ K-Planes dynamic model

@@ -2,11 +2,14 @@
 // one launch per stage over the concatenated work lists of every slice, with the whole
 // step captured once in a HIP graph and replayed. Each slice keeps its own device
 // step counter and stops at its own step count; its arithmetic is the same as alone.
+// vp_batch keeps such a group resident (create, step, stage times, read, destroy);
+// vp_batch_reconstruct is one pass through it.
 
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <memory>
+#include <new>
 #include <vector>
 
 #include "plan.h"
@@ -175,28 +178,47 @@ vp_status group_run(SliceGroup* g, int n_steps, bool use_graph) {
 
 using namespace vp;
 
-extern "C" vp_status vp_batch_reconstruct(int32_t n, const vp_plan* const* plans, const vp_options* const* opts,
-                                          const vp_c64* const* kspace, vp_result* const* results) {
+// A resident batch: the slices' sessions on one stream, grouped for batched launches.
+struct vp_batch {
+    vp::SliceGroup g;
+    std::vector<std::unique_ptr<vp_session>> owned;
+    std::vector<vp_session*> sessions;   // admitted slices, in input order
+    std::vector<int> limits;             // their step counts
+    std::vector<int> slot_of;            // input index -> slot in sessions (-1: failed)
+    std::vector<vp_status> status;       // per input slice
+    int max_steps = 0;
+    int64_t steps_run = 0;               // batched steps enqueued so far
+    ~vp_batch() {
+        if (g.stream) {
+            (void)hipSetDevice(g.device);
+            (void)hipStreamSynchronize(g.stream);
+        }
+        owned.clear();
+        g.drop_graph();
+        if (g.stream) (void)hipStreamDestroy(g.stream);
+        g.stream = nullptr;
+    }
+};
+
+extern "C" vp_status vp_batch_create(int32_t n, const vp_plan* const* plans, const vp_options* const* opts,
+                                     const vp_c64* const* kspace, vp_batch** out) {
     clear_error();
-    if (n < 0 || (n > 0 && (!plans || !opts || !kspace || !results)))
-        return fail(VP_ERR_ARG, "vp_batch_reconstruct: bad argument");
-    if (n == 0) return VP_OK;
+    if (!out || n < 1 || !plans || !opts || !kspace) return fail(VP_ERR_ARG, "vp_batch_create: bad argument");
     for (int i = 0; i < n; ++i)
-        if (!plans[i] || !opts[i] || !kspace[i] || !results[i])
-            return fail(VP_ERR_ARG, "vp_batch_reconstruct: NULL entry %d", i);
+        if (!plans[i] || !opts[i] || !kspace[i]) return fail(VP_ERR_ARG, "vp_batch_create: NULL entry %d", i);
     const int device = opts[0]->device;
     hipError_t e = hipSetDevice(device);
     if (e != hipSuccess) return hip_status(e, "hipSetDevice");
-    SliceGroup g;
-    g.device = device;
-    e = hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking);
-    if (e != hipSuccess) return hip_status(e, "hipStreamCreate");
-    std::vector<std::unique_ptr<vp_session>> owned;
-    std::vector<vp_session*> sessions;
-    std::vector<int> limits;
-    std::vector<int> slot_of(n, -1);
-    vp_status first_err = VP_OK;
-    int max_steps = 0;
+    std::unique_ptr<vp_batch> b(new (std::nothrow) vp_batch());
+    if (!b) return fail(VP_ERR_NOMEM, "vp_batch_create: out of host memory");
+    b->g.device = device;
+    e = hipStreamCreateWithFlags(&b->g.stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        b->g.stream = nullptr;
+        return hip_status(e, "hipStreamCreate");
+    }
+    b->slot_of.assign(n, -1);
+    b->status.assign(n, VP_OK);
     // One tile shape serves the whole batch: when any slice asks for tuning, the
     // largest slice is tuned (once per plan sizes) and every slice whose regions fit
     // takes its shape.
@@ -215,70 +237,145 @@ extern "C" vp_status vp_batch_reconstruct(int32_t n, const vp_plan* const* plans
         have_shape = check_options(plans[big], &ob) == VP_OK && tiles_for(plans[big], &ob, &shape) == VP_OK;
         if (!have_shape) clear_error();
     }
-    {
-        for (int i = 0; i < n; ++i) {
-            vp_options o = *opts[i];
-            o.device = device;
-            o.autotune = 0;
-            const vp_tiles& ot = o.tiles;
-            const Layout* lay = nullptr;
-            const bool unset = !ot.proj_rows && !ot.proj_parts && !ot.gath_rows && !ot.gath_bins && !ot.upd_bins &&
-                               !ot.gath_waves && !ot.proj_waves;
-            if (have_shape && unset) {
-                if (plan_layout(plans[i], shape, &lay) == VP_OK)
-                    o.tiles = vp_tiles{shape.proj_rows, shape.proj_gw, shape.gath_rows, shape.gath_sc,
-                                       shape.upd_sc, shape.gath_w, shape.proj_w};
-                else
-                    clear_error();
-            }
-            vp_session* s = nullptr;
-            vp_status st = session_alloc(plans[i], &o, kspace[i], nullptr, g.stream, &s);
-            results[i]->status = st;
-            results[i]->steps_done = 0;
-            results[i]->final_loss = 0.0;
-            if (st != VP_OK) {
-                if (first_err == VP_OK) first_err = st;
-                continue;
-            }
-            slot_of[i] = (int)sessions.size();
-            owned.emplace_back(s);
-            sessions.push_back(s);
-            limits.push_back(o.n_steps);
-            max_steps = std::max(max_steps, o.n_steps);
+    vp_status first_err = VP_OK;
+    for (int i = 0; i < n; ++i) {
+        vp_options o = *opts[i];
+        o.device = device;
+        o.autotune = 0;
+        const vp_tiles& ot = o.tiles;
+        const Layout* lay = nullptr;
+        const bool unset = !ot.proj_rows && !ot.proj_parts && !ot.gath_rows && !ot.gath_bins && !ot.upd_bins &&
+                           !ot.gath_waves && !ot.proj_waves;
+        if (have_shape && unset) {
+            if (plan_layout(plans[i], shape, &lay) == VP_OK)
+                o.tiles = vp_tiles{shape.proj_rows, shape.proj_gw, shape.gath_rows, shape.gath_sc,
+                                   shape.upd_sc, shape.gath_w, shape.proj_w};
+            else
+                clear_error();
         }
-        if (!sessions.empty()) {
-            vp_status st = group_build(&g, sessions, limits);
-            if (st == VP_OK) st = group_run(&g, max_steps, true);
-            if (st == VP_OK) st = hip_status(hipStreamSynchronize(g.stream), "batched steps");
-            if (st != VP_OK) {
-                owned.clear();
-                (void)hipStreamDestroy(g.stream);
-                g.stream = nullptr;
-                return st;
-            }
-            for (int i = 0; i < n; ++i) {
-                const int k = slot_of[i];
-                if (k < 0) continue;
-                vp_session* s = sessions[k];
-                s->steps_done = limits[k];
-                double obj = 0.0;
-                vp_status st2 = session_objective(s, &obj, nullptr);
-                vp_result* r = results[i];
-                r->final_loss = obj;
-                r->steps_done = limits[k];
-                const vp_status rs = session_read(s, r->volume_out, r->proj_out, r->water_out, r->fat_out);
-                if (st2 == VP_OK) st2 = rs;
-                r->status = st2;
-                if (st2 != VP_OK && first_err == VP_OK) first_err = st2;
-            }
+        vp_session* s = nullptr;
+        const vp_status st = session_alloc(plans[i], &o, kspace[i], nullptr, b->g.stream, &s);
+        b->status[i] = st;
+        if (st != VP_OK) {
+            if (first_err == VP_OK) first_err = st;
+            continue;
         }
+        b->slot_of[i] = (int)b->sessions.size();
+        b->owned.emplace_back(s);
+        b->sessions.push_back(s);
+        b->limits.push_back(o.n_steps);
+        b->max_steps = std::max(b->max_steps, o.n_steps);
     }
-    owned.clear();
-    if (g.gexec) {
-        (void)hipGraphExecDestroy(g.gexec);
-        g.gexec = nullptr;
+    if (b->sessions.empty()) return first_err;
+    const vp_status st = group_build(&b->g, b->sessions, b->limits);
+    if (st != VP_OK) return st;
+    *out = b.release();
+    return first_err == VP_OK ? VP_OK : first_err;
+}
+
+extern "C" vp_status vp_batch_step(vp_batch* b, int32_t n_steps, int32_t use_graph) {
+    clear_error();
+    if (!b || n_steps < 0) return fail(VP_ERR_ARG, "vp_batch_step: bad argument");
+    hipError_t e = hipSetDevice(b->g.device);
+    if (e != hipSuccess) return hip_status(e, "hipSetDevice");
+    vp_status st = group_run(&b->g, n_steps, use_graph != 0);
+    if (st == VP_OK) st = hip_status(hipStreamSynchronize(b->g.stream), "batched steps");
+    if (st != VP_OK) return st;
+    b->steps_run += n_steps;
+    for (size_t k = 0; k < b->sessions.size(); ++k)
+        b->sessions[k]->steps_done = std::min<int64_t>(b->limits[k], b->steps_run);
+    return VP_OK;
+}
+
+extern "C" vp_status vp_batch_stage_times(vp_batch* b, int32_t n_steps, double* stage_ms) {
+    clear_error();
+    if (!b || !stage_ms || n_steps < 1 || n_steps > 100000) return fail(VP_ERR_ARG, "vp_batch_stage_times: bad argument");
+    hipError_t e = hipSetDevice(b->g.device);
+    if (e != hipSuccess) return hip_status(e, "hipSetDevice");
+    const int ne = (kStages + 1) * n_steps;
+    std::vector<hipEvent_t> ev(ne, nullptr);
+    vp_status st = VP_OK;
+    for (int i = 0; i < ne && st == VP_OK; ++i) st = hip_status(hipEventCreate(&ev[i]), "hipEventCreate");
+    KArgs a{};
+    a.descs = b->g.d_descs;
+    for (int k = 0; k < n_steps && st == VP_OK; ++k) {
+        launch_step(a, b->g.lists, b->g.stream, &e, &ev[(size_t)k * (kStages + 1)]);
+        st = hip_status(e, "stage-timed batched step");
     }
-    (void)hipStreamDestroy(g.stream);
-    g.stream = nullptr;
+    if (st == VP_OK) st = hip_status(hipStreamSynchronize(b->g.stream), "stage-timed batched steps");
+    if (st == VP_OK) {
+        b->steps_run += n_steps;
+        for (size_t k = 0; k < b->sessions.size(); ++k)
+            b->sessions[k]->steps_done = std::min<int64_t>(b->limits[k], b->steps_run);
+    }
+    for (int j = 0; j < kStages; ++j) stage_ms[j] = 0.0;
+    for (int k = 0; k < n_steps && st == VP_OK; ++k)
+        for (int j = 0; j < kStages && st == VP_OK; ++j) {
+            float ms = 0.f;
+            hipEvent_t* bv = &ev[(size_t)k * (kStages + 1)];
+            st = hip_status(hipEventElapsedTime(&ms, bv[j], bv[j + 1]), "hipEventElapsedTime");
+            stage_ms[j] += ms / n_steps;
+        }
+    for (hipEvent_t x : ev)
+        if (x) (void)hipEventDestroy(x);
+    return st;
+}
+
+extern "C" vp_status vp_batch_read(vp_batch* b, int32_t i, vp_result* r) {
+    clear_error();
+    if (!b || !r || i < 0 || i >= (int)b->slot_of.size()) return fail(VP_ERR_ARG, "vp_batch_read: bad argument");
+    if (b->slot_of[i] < 0) {
+        r->status = b->status[i];
+        r->steps_done = 0;
+        r->final_loss = 0.0;
+        return r->status;
+    }
+    hipError_t e = hipSetDevice(b->g.device);
+    if (e != hipSuccess) return hip_status(e, "hipSetDevice");
+    vp_session* s = b->sessions[b->slot_of[i]];
+    double obj = 0.0;
+    vp_status st = session_objective(s, &obj, nullptr);
+    const vp_status rs = session_read(s, r->volume_out, r->proj_out, r->water_out, r->fat_out);
+    if (st == VP_OK) st = rs;
+    r->final_loss = obj;
+    r->steps_done = s->steps_done;
+    r->status = st;
+    return st;
+}
+
+extern "C" vp_status vp_batch_destroy(vp_batch* b) {
+    delete b;
+    return VP_OK;
+}
+
+extern "C" vp_status vp_batch_reconstruct(int32_t n, const vp_plan* const* plans, const vp_options* const* opts,
+                                          const vp_c64* const* kspace, vp_result* const* results) {
+    clear_error();
+    if (n < 0 || (n > 0 && (!plans || !opts || !kspace || !results)))
+        return fail(VP_ERR_ARG, "vp_batch_reconstruct: bad argument");
+    if (n == 0) return VP_OK;
+    for (int i = 0; i < n; ++i)
+        if (!plans[i] || !opts[i] || !kspace[i] || !results[i])
+            return fail(VP_ERR_ARG, "vp_batch_reconstruct: NULL entry %d", i);
+    for (int i = 0; i < n; ++i) {
+        results[i]->status = VP_OK;
+        results[i]->steps_done = 0;
+        results[i]->final_loss = 0.0;
+    }
+    vp_batch* raw = nullptr;
+    const vp_status cst = vp_batch_create(n, plans, opts, kspace, &raw);
+    if (!raw) {
+        // no slice could be set up (or the group failed): report per-slice allocation errors
+        for (int i = 0; i < n; ++i) results[i]->status = cst;
+        return cst;
+    }
+    std::unique_ptr<vp_batch> b(raw);
+    vp_status first_err = cst;
+    vp_status st = vp_batch_step(b.get(), b->max_steps, 1);
+    if (st != VP_OK) return st;
+    for (int i = 0; i < n; ++i) {
+        st = vp_batch_read(b.get(), i, results[i]);
+        if (st != VP_OK && first_err == VP_OK) first_err = st;
+    }
     return first_err;
 }

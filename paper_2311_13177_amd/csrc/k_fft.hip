@@ -265,7 +265,7 @@ __device__ void fft_cols_any(float2* buf, const float2* tw, int n, int nstage, i
 template <int DIR, int NC>
 __global__ __launch_bounds__(kThreads) void k_rows(const KArgs a) {
     extern __shared__ float2 sm[];
-    for (int ti = blockIdx.x; ti < a.ntasks; ti += gridDim.x) {
+    for (int ti = xcd_item(blockIdx.x, gridDim.x); ti < a.ntasks; ti += gridDim.x) {
         const AS4 Task* tk = cst(a.tasks) + ti;
         const int slice = tk->slice;
         int* const stepp = DF(step);
@@ -359,7 +359,12 @@ template <int NC>
 __global__ __launch_bounds__(kThreads) void k_cols(const KArgs a) {
     extern __shared__ float2 sm[];
     __shared__ float red[kThreads / 64];
-    for (int ti = blockIdx.x; ti < a.ntasks; ti += gridDim.x) {
+    // Compile-time lengths keep each thread's measurement values and mask bytes in
+    // registers (loaded with the strip, used after the forward DFT); the generic length
+    // stages them in LDS beside the strip.
+    constexpr bool kRegs = NC != 0;
+    constexpr int kEpt = kRegs ? (NC * fft_cols_per_item(NC) + kThreads - 1) / kThreads : 1;
+    for (int ti = xcd_item(blockIdx.x, gridDim.x); ti < a.ntasks; ti += gridDim.x) {
         const AS4 Task* tk = cst(a.tasks) + ti;
         const int slice = tk->slice;
         int* const stepp = DF(step);
@@ -372,16 +377,21 @@ __global__ __launch_bounds__(kThreads) void k_cols(const KArgs a) {
             if (a.mode == COL_STEP && threadIdx.x == 0) loss_part[b * n_col_items + tk->b] = 0.f;
             continue;
         }
-        const int n = DF(n), nparts = DF(nparts), nstage = DF(nstage), code = DF(radix_code);
+        const int n = kRegs ? NC : DF(n);
+        const int nparts = DF(nparts), nstage = DF(nstage), code = DF(radix_code);
         const size_t nn = (size_t)n * n;
         const int cb = fft_cols_per_item(n);
         const int c0 = tk->b * cb, cols = min(cb, n - c0);
-        // LDS: the strip (cb columns of n), the twiddles, and the strip's measurement and
-        // mask, all loaded in one pass so that their latencies overlap
+        const int ne = n * cb;
+        // LDS: the strip (cb columns of n) and the twiddles (plus, for the generic length,
+        // the strip's measurement and mask), all loaded in one pass so that their
+        // latencies overlap
         float2* A = sm;
         float2* tw = sm + cb * n;
         float2* Y = tw + n;
         uint8_t* M = reinterpret_cast<uint8_t*>(Y + cb * n);
+        float2 yr[kEpt];
+        uint8_t mr[kEpt];
         float2* img = DF(work) + (size_t)b * nparts * nn;
         const float2* twg = DF(tw);
         const bool raw = a.mode == COL_INVERSE || a.mode == COL_RAW_FWD;
@@ -394,10 +404,11 @@ __global__ __launch_bounds__(kThreads) void k_cols(const KArgs a) {
         // rows of a centred image of size live_n (all rows when 0)
         const int lv = raw ? a.live_n : 0, lv_lo = lv - lv / 2, lv_hi = n - lv / 2;
         for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = twg[i];
-        for (int i = threadIdx.x; i < n * cb; i += blockDim.x) {
+        auto load = [&](int i, float2& w, uint8_t& m) {
             const int y = i / cb, c = i - (i / cb) * cb;
-            float2 v = make_float2(0.f, 0.f), w = v;
-            uint8_t m = 0;
+            float2 v = make_float2(0.f, 0.f);
+            w = v;
+            m = 0;
             if (c < cols) {
                 const size_t gi = (size_t)y * n + c0 + c;
                 if (raw) {
@@ -410,9 +421,24 @@ __global__ __launch_bounds__(kThreads) void k_cols(const KArgs a) {
                 }
             }
             A[i] = v;
-            if (!raw) {
-                Y[i] = w;
-                M[i] = m;
+        };
+        if constexpr (kRegs) {
+#pragma unroll
+            for (int k = 0; k < kEpt; ++k) {
+                const int i = threadIdx.x + k * kThreads;
+                yr[k] = make_float2(0.f, 0.f);
+                mr[k] = 0;
+                if (kEpt * kThreads == NC * fft_cols_per_item(NC) || i < ne) load(i, yr[k], mr[k]);
+            }
+        } else {
+            for (int i = threadIdx.x; i < ne; i += blockDim.x) {
+                float2 w;
+                uint8_t m;
+                load(i, w, m);
+                if (!raw) {
+                    Y[i] = w;
+                    M[i] = m;
+                }
             }
         }
         __syncthreads();
@@ -422,17 +448,17 @@ __global__ __launch_bounds__(kThreads) void k_cols(const KArgs a) {
         const float dw = a.mode == COL_STEP ? DF(data_w) : 1.0f;
         const float sc_res = dw * sc;
         float lsum = 0.f;
-        for (int i = threadIdx.x; i < n * cb && !raw; i += blockDim.x) {
+        auto mask_res = [&](int i, float2 yv, uint8_t mv) {
             const int y = i / cb, c = i - (i / cb) * cb;
             float2 v = make_float2(0.f, 0.f);
             if (c < cols) {
-                const bool on = M[i] != 0;
+                const bool on = mv != 0;
                 const float2 x = A[i];
                 if (a.mode == COL_ADJOINT) {
                     if (on) v = cscale(x, sc);
                 } else {
                     float2 r = make_float2(0.f, 0.f);
-                    if (on) r = csub(cscale(x, sc), Y[i]);
+                    if (on) r = csub(cscale(x, sc), yv);
                     if (a.mode == COL_FORWARD) {
                         a.out0[(size_t)b * nn + (size_t)y * n + c0 + c] = r;
                     } else {
@@ -443,13 +469,24 @@ __global__ __launch_bounds__(kThreads) void k_cols(const KArgs a) {
                 }
             }
             A[i] = v;
+        };
+        if (!raw) {
+            if constexpr (kRegs) {
+#pragma unroll
+                for (int k = 0; k < kEpt; ++k) {
+                    const int i = threadIdx.x + k * kThreads;
+                    if (kEpt * kThreads == NC * fft_cols_per_item(NC) || i < ne) mask_res(i, yr[k], mr[k]);
+                }
+            } else {
+                for (int i = threadIdx.x; i < ne; i += blockDim.x) mask_res(i, Y[i], M[i]);
+            }
         }
         __syncthreads();
         if (a.mode != COL_FORWARD) {
             if (a.mode != COL_RAW_FWD) fft_cols_any<1, NC>(A, tw, n, nstage, code);
             // a raw inverse pass feeding a centred crop writes only its rows
             const bool all = a.mode != COL_INVERSE || lv == 0;
-            for (int i = threadIdx.x; i < n * cb; i += blockDim.x) {
+            for (int i = threadIdx.x; i < ne; i += blockDim.x) {
                 const int y = i / cb, c = i - (i / cb) * cb;
                 if (c < cols && (all || y < lv_lo || y >= lv_hi)) dst[(size_t)y * n + c0 + c] = A[i];
             }
@@ -489,6 +526,10 @@ hipError_t launch_rows(const KArgs& a, int dir, int n, size_t lds, hipStream_t s
 hipError_t launch_cols(const KArgs& a, int n, size_t lds, hipStream_t s) {
     if (a.ntasks <= 0) return hipSuccess;
     const dim3 g(grid_for(a.ntasks)), b(kThreads);
+    // the compile-time lengths hold the measurement and mask in registers: LDS for the
+    // strip and the twiddles only
+    if (n == 64 || n == 128 || n == 192 || n == 256 || n == 320 || n == 384 || n == 512)
+        lds = (size_t)fft_cols_raw_lds(n);
 #define CV(N)                                                  \
     case N:                                                    \
         hipLaunchKernelGGL((k_cols<N>), g, b, lds, s, a);      \

@@ -137,9 +137,12 @@ static vp_status build_layout(const vp_plan* p, const Tiles& t, Layout* L) {
                     t.proj_rows, t.proj_gw, t.gath_rows, t.gath_sc);
     const int txn = ceil_div(n, kTileW);
     const int typ = ceil_div(n, t.proj_rows), tyg = ceil_div(n, t.gath_rows);
-    for (int ty = 0; ty < typ; ++ty)
-        for (int tx = 0; tx < txn; ++tx)
-            for (int gi = 0; gi < (int)L->groups.size(); ++gi) L->t_proj.push_back(Task{0, gi, ty, tx});
+    // group-major (knot-major): the tiles of one knot's group in row order, so the items
+    // an XCD runs at once are vertically and horizontally adjacent tiles of one knot,
+    // whose staged halos overlap in its L2 (no two knots share a staged region)
+    for (int gi = 0; gi < (int)L->groups.size(); ++gi)
+        for (int ty = 0; ty < typ; ++ty)
+            for (int tx = 0; tx < txn; ++tx) L->t_proj.push_back(Task{0, gi, ty, tx});
     const int nch = ceil_div(S, t.gath_w * t.gath_sc);
     for (int ty = 0; ty < tyg; ++ty)
         for (int tx = 0; tx < txn; ++tx)

@@ -66,7 +66,7 @@ constexpr int kVoxItem = 4096;
 // items that a blade set spreads over the whole chip.
 __host__ __device__ constexpr int fft_rows_per_item(int n) { return 1024 / n < 1 ? 1 : (1024 / n > 16 ? 16 : 1024 / n); }
 __host__ __device__ constexpr int fft_cols_per_item(int n) {
-    return n == 512 ? 8 : (n > 256 ? 4 : (n == 256 ? 8 : 16));
+    return n == 512 ? 8 : (n > 256 ? 4 : (n == 256 || n == 192 ? 8 : 16));
 }
 // LDS of a column item without the measurement and mask strips (the raw passes)
 __host__ __device__ constexpr int fft_cols_raw_lds(int n) { return (fft_cols_per_item(n) * n + n) * 8; }

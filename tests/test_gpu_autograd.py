@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from parity import assert_close
 from synth import configs
 
 pytestmark = pytest.mark.gpu
@@ -19,6 +20,17 @@ def _t(x):
     import torch
 
     return torch.from_numpy(np.ascontiguousarray(x, dtype=np.complex64)).to("cuda")
+
+
+def data_loss(vol, plan, y):
+    """The test's loss: 0.5 * sum |M (A vol) - M y|^2 over the residual the library returns
+    (float64 accumulation in torch; the objective itself is the test's, not the library's)."""
+    import torch
+
+    from paper_2311_13177_amd import autograd as AG
+
+    r = AG.lifted_forward(vol, plan, y)
+    return 0.5 * torch.sum(torch.view_as_real(r).to(torch.float64) ** 2)
 
 
 def _rand(rng, shape, scale=1.0):
@@ -43,19 +55,19 @@ def test_autograd_gradient_fd_and_oracle(gpu_lib, name):
     v0 = _rand(rng, plan.volume_shape, 0.05)
     vol = _t(v0).requires_grad_(True)
     yt = _t(y)
-    loss = AG.data_loss(vol, plan, yt)
+    loss = data_loss(vol, plan, yt)
     loss.backward()
     g = vol.grad.cpu().numpy().astype(np.complex128)
     g_or, ld_or = O.gradient(v0.astype(np.complex128), geom, y, 0.0, 1e-3)
-    assert np.linalg.norm(g - g_or) <= 1e-4 * np.linalg.norm(g_or)
+    assert_close(g, g_or, 1e-4)
     assert abs(loss.item() - ld_or) <= 1e-4 * ld_or
     # central finite difference along random directions
     with torch.no_grad():
         for k in range(2):
             h = _rand(rng, plan.volume_shape, 0.05)
             ht = _t(h)
-            lp = AG.data_loss(vol + ht, plan, yt).item()
-            lm = AG.data_loss(vol - ht, plan, yt).item()
+            lp = data_loss(vol + ht, plan, yt).item()
+            lm = data_loss(vol - ht, plan, yt).item()
             fd = (lp - lm) / 2.0
             an = float(np.real(np.vdot(g, h.astype(np.complex128))))
             assert abs(fd - an) <= 1e-3 * max(abs(an), 1e-12) + 1e-6 * abs(lp), (fd, an)
@@ -90,11 +102,11 @@ def test_regulariser_function_matches_oracle(gpu_lib):
     y = O.simulate_measurements(case)
     v0 = _rand(rng, plan.volume_shape, 0.05)
     vol = _t(v0).requires_grad_(True)
-    loss = AG.data_loss(AG.Regulariser.apply(vol, plan, 1e-2, 1e-3, 1e-3), plan, _t(y))
+    loss = data_loss(AG.Regulariser.apply(vol, plan, 1e-2, 1e-3, 1e-3), plan, _t(y))
     loss.backward()
     g_or, _ = O.gradient(v0.astype(np.complex128), geom, y, 1e-2, 1e-3, 1e-3)
     g = vol.grad.cpu().numpy().astype(np.complex128)
-    assert np.linalg.norm(g - g_or) <= 1e-4 * np.linalg.norm(g_or)
+    assert_close(g, g_or, 1e-4)
 
 
 def test_blade_aligned_autograd_matches_oracle_and_fd(gpu_lib):
@@ -121,7 +133,7 @@ def test_blade_aligned_autograd_matches_oracle_and_fd(gpu_lib):
     g = x.grad.cpu().numpy().astype(np.complex128)
     want, val = N.gradient_nu(vol.astype(np.complex128), geom, [y[b].astype(np.complex128) for b in range(shp[0])],
                               exact=False)
-    assert np.linalg.norm(g - want) <= 1e-4 * np.linalg.norm(want)
+    assert_close(g, want, 1e-4)
     assert abs(float(loss.detach()) - val) <= 1e-4 * val
     d = _rand(rng, plan.volume_shape)
     h = 1e-2

@@ -104,3 +104,24 @@ def test_server_errors_and_cancel(gpu_lib):
         srv.poll(first)
     assert ei.value.status == B.VP_ERR_NOT_FOUND
     srv.close()
+
+
+def test_resident_batch_in_parts_equals_solo(gpu_lib):
+    # a resident batch stepped in parts (graph replays, eager stage-timed steps, more graph
+    # replays) reaches each slice's own step count and equals its solo fit bit for bit;
+    # slices that stop earlier stay where they stopped
+    from paper_2311_13177_amd import binding as B
+
+    probs = _problems(B, [5, 9, 7, 9, 3])
+    solo = [B.vp_reconstruct(p, y, o) for _, p, y, o in probs]
+    batch = B.Batch([p for _, p, _, _ in probs], [y for _, _, y, _ in probs], [o for _, _, _, o in probs])
+    batch.step(3, use_graph=True)
+    st = batch.stage_times(2)
+    assert tuple(st) == B.Batch.STAGES and all(v > 0 for v in st.values())
+    batch.step(4, use_graph=True)
+    for i, (s, (_, _, _, o)) in enumerate(zip(solo, probs)):
+        r = batch.read(i)
+        assert r["status"] == 0 and r["steps_done"] == min(o.n_steps, 9)
+        if o.n_steps <= 9:
+            assert _same(r, s)
+    batch.close()

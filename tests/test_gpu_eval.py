@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from parity import both_bounds
 from synth import configs
 
 pytestmark = pytest.mark.gpu
@@ -25,7 +26,9 @@ CASES = {
 
 
 def _rel(a, b):
-    return np.linalg.norm(a - b) / np.linalg.norm(b)
+    # both bounds of tests/parity.py in one number: a tolerance on it bounds the relative
+    # L2 error and the largest element error relative to the largest reference magnitude
+    return both_bounds(a, b)
 
 
 def _setup(name):

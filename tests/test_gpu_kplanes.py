@@ -15,6 +15,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from parity import both_bounds
 from oracle import kplanes as K
 from synth import configs
 from synth.kplanes_init import init_params
@@ -31,7 +32,9 @@ CASES = {
 
 
 def _rel(a, b):
-    return float(np.linalg.norm(np.asarray(a) - b) / np.linalg.norm(b))
+    # both bounds of tests/parity.py in one number: a tolerance on it bounds the relative
+    # L2 error and the largest element error relative to the largest reference magnitude
+    return both_bounds(a, b)
 
 
 def _setup(name, regs=(0.0, 0.0, 0.0)):

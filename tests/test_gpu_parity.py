@@ -1,27 +1,48 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle.
 
-Tolerances (relative L2 over the whole array): 1e-4 for the forward model, its
-adjoint and the regulariser gradient; 1e-3 for reconstructions after many Adam
-steps, where FP32 rounding of the gradient is amplified by Adam's per-coordinate
-normalisation.
+Every comparison bounds both the relative L2 error over the whole array and the
+largest element error relative to the largest reference magnitude (tests/parity.py).
+Tolerances: 1e-4 for the forward model, its adjoint, the regulariser gradient and
+gradient-descent fits (linear dynamics). Adam fits: 1e-3, or twice the oracle's own
+spread where that is larger. The spread is how far the FP64 oracle's fit itself moves
+when the measurements are perturbed at the level of FP32 rounding (y (1 + 2^-20 z)):
+Adam normalises every real component separately, so a gradient component near zero
+moves by about lr whichever sign rounding gives it, and in the later steps of the
+under-determined fit such differences grow. The spread is measured live for the small
+cases and stored by tests/golden/make_converged.py for the full-size workloads.
 """
+
+import os
 
 import numpy as np
 import pytest
 
 import oracle as O
+from parity import assert_close, max_rel, rel
 from synth import configs
 
 pytestmark = pytest.mark.gpu
 
 FWD_TOL = 1e-4
 RECON_TOL = 1e-3
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+SPREAD_LOG2 = -20     # perturbation of y that measures the oracle's own spread
+SPREAD_FACTOR = 2.0   # Adam tolerance: this many times the spread (at least RECON_TOL)
 
 
-def rel(a, b):
-    a = np.asarray(a, dtype=np.complex128)
-    b = np.asarray(b, dtype=np.complex128)
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+def adam_tol(spread: float) -> float:
+    return max(RECON_TOL, SPREAD_FACTOR * spread)
+
+
+def stored_spread(name: str, step: int) -> tuple[float, float, float]:
+    """The oracle's spread (rel L2 of proj, max element of proj, objective) at a
+    checkpoint of a full-size workload, from the stored 2^-20 perturbation run."""
+    import json
+
+    with open(os.path.join(GOLDEN, f"converged_{name}_spread.json")) as fh:
+        d = json.load(fh)
+    k, c = SPREAD_LOG2, str(step)
+    return (d[f"rel_l2_2^{k}"][c], d[f"max_elem_2^{k}"][c], d[f"objective_rel_2^{k}"][c])
 
 
 def _t(x):
@@ -76,19 +97,19 @@ def test_forward_and_adjoint_small(gpu_lib, name):
     # forward with and without measurement
     got = _np(B.vp_forward(plan, _t(vol)))
     want = O.forward(vol.astype(np.complex128), geom)
-    assert rel(got, want) < FWD_TOL
+    assert_close(got, want, FWD_TOL, "forward")
     got_r = _np(B.vp_forward(plan, _t(vol), _t(y)))
     want_r = O.residual(vol.astype(np.complex128), geom, y)
-    assert rel(got_r, want_r) < FWD_TOL
+    assert_close(got_r, want_r, FWD_TOL, "residual")
     # adjoint of an arbitrary k-space array (the mask is part of the operator)
     k = _random_kspace(case)
     got_a = _np(B.vp_adjoint(plan, _t(k)))
     want_a = O.adjoint(k.astype(np.complex128), geom)
-    assert rel(got_a, want_a) < FWD_TOL
+    assert_close(got_a, want_a, FWD_TOL, "adjoint")
     # accumulate adds
     g = _t(got_a)
     B.vp_adjoint(plan, _t(k), g, accumulate=True)
-    assert rel(_np(g), 2 * want_a) < FWD_TOL
+    assert_close(_np(g), 2 * want_a, FWD_TOL, "adjoint accumulated")
 
 
 @pytest.mark.parametrize("name", ["static_64", "static_256", "dynamic_192"])
@@ -101,10 +122,66 @@ def test_forward_and_adjoint_full_size(gpu_lib, name):
     vol = _random_volume(case, seed=3)
     got = _np(B.vp_forward(plan, _t(vol)))
     want = O.forward(vol.astype(np.complex128), geom)
-    assert rel(got, want) < FWD_TOL
+    assert_close(got, want, FWD_TOL, "forward")
     k = _random_kspace(case, seed=4)
     got_a = _np(B.vp_adjoint(plan, _t(k)))
-    assert rel(got_a, O.adjoint(k.astype(np.complex128), geom)) < FWD_TOL
+    assert_close(got_a, O.adjoint(k.astype(np.complex128), geom), FWD_TOL, "adjoint")
+
+
+# DFT lengths and depths of the batched and served workloads (n = 128, 320, 384; S up to
+# 64): f = n/64 px of fat shift as in those workloads, so the larger shifts also take the
+# deeper staging variants of the projection and gather.
+LARGE = {
+    "static_128": dict(n=128, n_spec=16, n_blades=8, lines=16, f=2.0),
+    "dynamic_320": dict(n=320, n_spec=64, n_time=8, n_blades=10, lines=24, f=5.0),
+    "dynamic_384": dict(n=384, n_spec=32, n_time=16, n_blades=16, lines=32, f=6.0),
+}
+
+
+@pytest.mark.parametrize("name", list(LARGE))
+@pytest.mark.parametrize("op", ["forward", "adjoint"])
+def test_forward_adjoint_served_sizes(gpu_lib, name, op):
+    from paper_2311_13177_amd import binding as B
+
+    case = configs.small_case(**LARGE[name])
+    plan = B.Plan.from_geometry(case.geometry())
+    geom = O.Geometry.from_dict(case.geometry())
+    if op == "forward":
+        vol = _random_volume(case, seed=13)
+        got = _np(B.vp_forward(plan, _t(vol)))
+        want = O.forward(vol.astype(np.complex128), geom)
+    else:
+        k = _random_kspace(case, seed=14)
+        got = _np(B.vp_adjoint(plan, _t(k)))
+        want = O.adjoint(k.astype(np.complex128), geom)
+    r, m = assert_close(got, want, FWD_TOL, f"{name} {op}")
+    print(f"{name} {op}: rel {r:.2e} max elem {m:.2e}")
+
+
+# Three gradient-descent steps on the whole volume at the same DFT lengths. The FP64
+# oracle takes minutes per step at the served depths (S 64 x T 8 at 320^2 is 52M voxels),
+# so the 320^2 and 384^2 fits keep the length and the shift range and take fewer bins,
+# knots and blades; S = 64 runs at 320^2 with two knots.
+GD3 = {
+    "static_128": LARGE["static_128"],
+    "dynamic_320_s64": dict(n=320, n_spec=64, n_time=2, n_blades=4, lines=24, f=5.0),
+    "dynamic_384_t4": dict(n=384, n_spec=8, n_time=4, n_blades=6, lines=32, f=6.0),
+}
+
+
+@pytest.mark.parametrize("name", list(GD3))
+def test_gd_three_steps_served_sizes(gpu_lib, name):
+    from paper_2311_13177_amd import binding as B
+
+    case = configs.small_case(**GD3[name])
+    y = O.simulate_measurements(case)
+    plan = B.Plan.from_geometry(case.geometry())
+    gd = B.vp_options_default(n_steps=3, optimizer=B.VP_OPT_GD, lr=0.5 / (case.n_spec * case.n_blades))
+    got = B.vp_reconstruct(plan, y, gd)
+    want = _oracle_recon(case, y, gd, 3)
+    r, m = assert_close(got["vol"], want["vol"], FWD_TOL, f"{name} gd volume")
+    print(f"{name} gd 3 steps: rel {r:.2e} max elem {m:.2e}")
+    assert abs(got["final_loss"] - want["final_loss"]) <= FWD_TOL * abs(want["final_loss"])
 
 
 @pytest.mark.parametrize("name", ["static_48", "dynamic_40"])
@@ -135,10 +212,12 @@ def test_tv_grad_and_render(gpu_lib, name):
     for tv_w, l1_w, eps in ((1e-3, 0.0, 1e-3), (0.5, 0.25, 0.05)):
         got = _np(B.vp_tv_grad(plan, _t(vol), tv_w, l1_w, eps))
         want = tv_w * O.tv_grad(v64, eps) + l1_w * O.l1_grad(v64, eps)
-        assert rel(got, want) < FWD_TOL
+        assert_close(got, want, FWD_TOL, f"tv/l1 gradient {tv_w} {l1_w} {eps}")
     proj, water, fat = (_np(t) for t in B.vp_render(plan, _t(vol), 2))
     p0, w0, f0 = O.render(v64, 2)
-    assert rel(proj, p0) < 1e-6 and rel(water, w0) < 1e-6 and rel(fat, f0) < 1e-6
+    assert_close(proj, p0, 1e-6, "proj")
+    assert_close(water, w0, 1e-6, "water")
+    assert_close(fat, f0, 1e-6, "fat")
     assert np.array_equal(water + fat, proj)
 
 
@@ -149,6 +228,29 @@ def _oracle_recon(case, y, opts, steps):
                          optimizer="adam" if opts.optimizer == 0 else "gd",
                          schedule={0: "all", 1: "cyclic", 2: "random"}[opts.schedule], split_bin=opts.split_bin,
                          seed=opts.seed, data_weight=opts.data_weight)
+
+
+def _perturbed(y):
+    rng = np.random.default_rng(12345)
+    z = rng.standard_normal(y.shape) + 1j * rng.standard_normal(y.shape)
+    return y.astype(np.complex128) * (1.0 + 2.0 ** SPREAD_LOG2 * z)
+
+
+def check_fit(case, y, opts, steps, got, keys=("proj", "vol", "water", "fat")):
+    """The GPU fit against the oracle's: GD at the operator tolerance; Adam at RECON_TOL
+    or twice the oracle's own spread under y (1 + 2^-20 z), measured here."""
+    want = _oracle_recon(case, y, opts, steps)
+    if opts.optimizer == 1:
+        tol = {k: (FWD_TOL, FWD_TOL) for k in keys}
+        tol_obj = FWD_TOL
+    else:
+        alt = _oracle_recon(case, _perturbed(y), opts, steps)
+        tol = {k: (adam_tol(rel(alt[k], want[k])), adam_tol(max_rel(alt[k], want[k]))) for k in keys}
+        tol_obj = adam_tol(abs(alt["final_loss"] - want["final_loss"]) / abs(want["final_loss"]))
+    for k in keys:
+        assert_close(got[k], want[k], tol[k][0], k, elem_tol=tol[k][1])
+    assert abs(got["final_loss"] - want["final_loss"]) <= tol_obj * abs(want["final_loss"])
+    return want
 
 
 @pytest.mark.parametrize("name,optimizer,steps,schedule", [
@@ -168,11 +270,7 @@ def test_reconstruct_small(gpu_lib, name, optimizer, steps, schedule):
     lr = 1e-2 if optimizer == 0 else 0.5 / (case.n_spec * case.n_blades)
     opts = B.vp_options_default(n_steps=steps, optimizer=optimizer, lr=lr, schedule=schedule, l1_weight=1e-4)
     got = B.vp_reconstruct(plan, y, opts)
-    want = _oracle_recon(case, y, opts, steps)
-    assert rel(got["proj"], want["proj"]) < RECON_TOL
-    assert rel(got["vol"], want["vol"]) < RECON_TOL
-    assert rel(got["water"], want["water"]) < RECON_TOL and rel(got["fat"], want["fat"]) < RECON_TOL
-    assert abs(got["final_loss"] - want["final_loss"]) <= 1e-3 * abs(want["final_loss"])
+    check_fit(case, y, opts, steps, got)
 
 
 @pytest.mark.parametrize("name,optimizer,steps,seed,weight", [
@@ -194,10 +292,7 @@ def test_random_schedule_and_data_weight(gpu_lib, name, optimizer, steps, seed, 
     opts = B.vp_options_default(n_steps=steps, optimizer=optimizer, lr=lr, schedule=sched, seed=seed,
                                 data_weight=weight)
     got = B.vp_reconstruct(plan, y, opts)
-    want = _oracle_recon(case, y, opts, steps)
-    assert rel(got["proj"], want["proj"]) < RECON_TOL
-    assert rel(got["vol"], want["vol"]) < RECON_TOL
-    assert abs(got["final_loss"] - want["final_loss"]) <= 1e-3 * abs(want["final_loss"])
+    check_fit(case, y, opts, steps, got, keys=("proj", "vol"))
     # graph replays draw the same blades as eager steps
     s1, s2 = B.Session(plan, y, opts), B.Session(plan, y, opts)
     s1.step(steps, use_graph=True)
@@ -217,7 +312,9 @@ def test_reconstruct_static_64_full(gpu_lib):
     opts = B.vp_options_default(n_steps=case.n_steps, tv_weight=case.tv_weight, lr=case.lr)
     got = B.vp_reconstruct(plan, y, opts)
     want = _oracle_recon(case, y, opts, case.n_steps)
-    assert rel(got["proj"], want["proj"]) < RECON_TOL
+    # well conditioned at 200 steps: the oracle's own spread is below 1e-4 here, so the
+    # image tolerance applies as it stands
+    assert_close(got["proj"], want["proj"], RECON_TOL, "proj")
     assert abs(got["final_loss"] - want["final_loss"]) <= 1e-3 * abs(want["final_loss"])
 
 
@@ -226,12 +323,9 @@ def test_reconstruct_full_size_first_steps(gpu_lib, name):
     """Full-size workloads in the benchmark's launch configuration, first steps only.
 
     The plan's own tile shape is checked against the oracle, and the autotuned shape (the
-    one bench.py times, eight-wave items at 256^2) must give the same bits.
-    Gradient descent keeps the dynamics linear, so FP32 rounding is not amplified and
-    the whole volume must agree to the operator tolerance. With Adam the rendered
-    image is compared: Adam normalises Re and Im separately, and with a real-valued
-    phantom the imaginary gradients sit at the noise level, where FP32 rounding of the
-    complex DFT is a large relative error that Adam turns into steps of size lr.
+    one bench.py times) must give the same bits. Gradient descent keeps the dynamics
+    linear, so the whole volume must agree to the operator tolerance. With Adam the
+    complex render is compared at the image tolerance.
     """
     from paper_2311_13177_amd import binding as B
 
@@ -243,22 +337,54 @@ def test_reconstruct_full_size_first_steps(gpu_lib, name):
                               lr=0.5 / (case.n_spec * case.n_blades))
     got = B.vp_reconstruct(plan, y, gd)
     want = _oracle_recon(case, y, gd, steps)
-    assert rel(got["vol"], want["vol"]) < FWD_TOL
+    assert_close(got["vol"], want["vol"], FWD_TOL, "gd volume")
     assert abs(got["final_loss"] - want["final_loss"]) <= FWD_TOL * abs(want["final_loss"])
     adam = B.vp_options_default(n_steps=steps, tv_weight=case.tv_weight, lr=case.lr)
     got = B.vp_reconstruct(plan, y, adam)
     want = _oracle_recon(case, y, adam, steps)
-    print(f"{name} adam {steps} steps: rel vol {rel(got['vol'], want['vol']):.2e} "
-          f"re {rel(got['vol'].real, want['vol'].real):.2e} proj {rel(got['proj'], want['proj']):.2e}")
-    # after three Adam steps every component has moved by about lr whatever its gradient,
-    # so the noise-level imaginary part weighs as much as the signal; the real part (where
-    # the phantom lives) must already meet the image tolerance
-    assert rel(got["vol"].real, want["vol"].real) < RECON_TOL
-    assert rel(got["proj"].real, want["proj"].real) < RECON_TOL
+    sr, se, so = stored_spread(name, steps)
+    print(f"{name} adam {steps} steps: proj rel {rel(got['proj'], want['proj']):.2e} (oracle spread {sr:.2e}), "
+          f"max elem {max_rel(got['proj'], want['proj']):.2e} (spread {se:.2e})")
+    assert_close(got["proj"], want["proj"], adam_tol(sr), "adam proj", elem_tol=adam_tol(se))
+    assert abs(got["final_loss"] - want["final_loss"]) <= adam_tol(so) * abs(want["final_loss"])
     tuned_opts = B.vp_options_default(n_steps=steps, tv_weight=case.tv_weight, lr=case.lr, autotune=1)
     tuned = B.vp_reconstruct(plan, y, tuned_opts)
     print(f"{name} tuned shape {plan.tiles(tuned_opts)}")
     assert np.array_equal(tuned["vol"], got["vol"]) and tuned["final_loss"] == got["final_loss"]
+
+
+@pytest.mark.parametrize("name", ["static_256", "dynamic_192"])
+def test_reconstruct_full_size_converged(gpu_lib, name):
+    """The full fit of the 256^2 (500 steps) and dynamic 192^2 (800 steps) workloads in the
+    benchmark's (autotuned) launch configuration against the oracle's renders, stored by
+    tests/golden/make_converged.py from the FP64 oracle alone: at step 100, where the fit
+    is well conditioned, and at the last step, each at RECON_TOL or twice the oracle's own
+    spread there (the objective likewise)."""
+    from paper_2311_13177_amd import binding as B
+
+    ref = np.load(os.path.join(GOLDEN, f"converged_{name}.npz"))  # plain arrays (allow_pickle off)
+    case = configs.CONFIGS[name]()
+    assert int(ref["steps"]) == case.n_steps
+    y = O.simulate_measurements(case)
+    plan = B.Plan.from_geometry(case.geometry())
+    opts = B.vp_options_default(n_steps=case.n_steps, tv_weight=case.tv_weight, lr=case.lr, autotune=1)
+    sess = B.Session(plan, y, opts)
+    sess.step(100, use_graph=True)
+    mid = sess.read()["proj"]
+    sess.step(case.n_steps - 100, use_graph=True)
+    got = sess.read()["proj"]
+    obj = sess.objective()[0]
+    sess.close()
+    for step, g, w in ((100, mid, ref["proj_step100"]), (case.n_steps, got, ref["proj"])):
+        w = w.astype(np.complex128)
+        sr, se, _ = stored_spread(name, step)
+        print(f"{name} step {step} (shape {plan.tiles(opts)}): proj rel {rel(g, w):.2e} (oracle spread "
+              f"{sr:.2e}), max elem {max_rel(g, w):.2e} (spread {se:.2e})")
+        assert_close(g, w, adam_tol(sr), f"proj at step {step}", elem_tol=adam_tol(se))
+    want_obj = float(ref["final_loss"])
+    so = stored_spread(name, case.n_steps)[2]
+    print(f"{name} objective {obj:.6e} vs {want_obj:.6e} (oracle spread {so:.2e})")
+    assert abs(obj - want_obj) <= adam_tol(so) * abs(want_obj)
 
 
 def test_reconstruct_dynamic_converged(gpu_lib):
@@ -270,10 +396,8 @@ def test_reconstruct_dynamic_converged(gpu_lib):
     plan = B.Plan.from_geometry(case.geometry())
     opts = B.vp_options_default(n_steps=150)
     got = B.vp_reconstruct(plan, y, opts)
-    want = _oracle_recon(case, y, opts, 150)
+    want = check_fit(case, y, opts, 150, got, keys=("proj",))
     print(f"dynamic 64 converged: proj {rel(got['proj'], want['proj']):.2e} vol {rel(got['vol'], want['vol']):.2e}")
-    assert rel(got["proj"], want["proj"]) < RECON_TOL
-    assert abs(got["final_loss"] - want["final_loss"]) <= 1e-3 * abs(want["final_loss"])
 
 
 def test_graph_equals_eager_and_resume_is_bitwise(gpu_lib):
@@ -371,14 +495,14 @@ def test_step_operator_matches_oracle(gpu_lib, name):
         g = (grads[t - 1].astype(np.complex128) + opts.tv_weight * O.tv_grad(ref, opts.tv_eps)
              + opts.l1_weight * O.l1_grad(ref, opts.tv_eps))
         ref, mr, vr = O.adam_update(ref, g, mr, vr, t, opts.lr, opts.beta1, opts.beta2, opts.adam_eps)
-    assert rel(_np(cur), ref) < FWD_TOL
-    assert rel(_np(m), mr[..., 0] + 1j * mr[..., 1]) < FWD_TOL
-    assert rel(_np(v), vr[..., 0] + 1j * vr[..., 1]) < FWD_TOL
+    assert_close(_np(cur), ref, FWD_TOL, "volume")
+    assert_close(_np(m), mr[..., 0] + 1j * mr[..., 1], FWD_TOL, "first moments")
+    assert_close(_np(v), vr[..., 0] + 1j * vr[..., 1], FWD_TOL, "second moments")
     gd = B.vp_options_default(tv_weight=1e-2, optimizer=B.VP_OPT_GD, lr=0.3)
     got = _np(B.vp_step(plan, gd, _t(vol), _t(grads[0])))
     v64 = vol.astype(np.complex128)
     want = v64 - 0.3 * (grads[0].astype(np.complex128) + 1e-2 * O.tv_grad(v64, gd.tv_eps))
-    assert rel(got, want) < FWD_TOL
+    assert_close(got, want, FWD_TOL, "gd step")
     # errors: overlapping output, Adam without moments, t < 1
     x = _t(vol)
     for kw in (dict(out=x), dict(m=None), dict(t=0)):
@@ -405,4 +529,4 @@ def test_operator_loop_equals_reconstruct(gpu_lib):
     for t in range(1, 5):
         r = B.vp_forward(plan, vol, dy)
         vol = B.vp_step(plan, gd, vol, B.vp_adjoint(plan, r), t=t)
-    assert rel(_np(vol), want["vol"]) < 1e-5
+    assert_close(_np(vol), want["vol"], 1e-5, "operator loop")

@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from parity import assert_close
 from synth import configs
 
 pytestmark = pytest.mark.gpu
@@ -56,7 +57,7 @@ def test_every_shape_gives_the_same_bits(gpu_lib, name):
     # and the common result is the method's (GD: linear dynamics, the operator tolerance)
     geom = O.Geometry.from_dict(case.geometry())
     want = O.reconstruct(geom, y, 9, optimizer="gd")
-    assert np.linalg.norm(ref["vol"] - want["vol"]) <= 1e-4 * np.linalg.norm(want["vol"])
+    assert_close(ref["vol"], want["vol"], 1e-4)
 
 
 def test_batch_of_different_shapes_equals_solo(gpu_lib):
@@ -94,7 +95,7 @@ def test_tuner_records_a_shape_that_sessions_and_operators_use(gpu_lib):
     B.vp_forward(plan, d_vol, None, d_out)
     want = O.forward(vol.astype(np.complex128), O.Geometry.from_dict(case.geometry()))
     got = d_out.cpu().numpy()
-    assert np.linalg.norm(got - want) <= 1e-4 * np.linalg.norm(want)
+    assert_close(got, want, 1e-4)
 
 
 def test_autotune_option_tunes_once(gpu_lib):
