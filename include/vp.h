@@ -232,6 +232,20 @@ vp_status vp_plan_tiles(const vp_plan* plan, const vp_options* opts, vp_tiles* o
  * and released on the stream. */
 vp_status vp_forward(const vp_plan* plan, const vp_c64* d_vol, const vp_c64* d_y, vp_c64* d_out, void* stream);
 
+/* vp_forward without any allocation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid it): the
+ * same kernels and results as vp_forward, bit for bit, with the blade work images in a
+ * fixed 32 MiB device array that the library keeps on each device it runs on until the
+ * process ends. It calls no allocator: the plan's device tables must already be on the
+ * current device (any earlier vp_forward, vp_adjoint, session or reconstruction of the
+ * plan there uploads them). Every call on one device shares that device's array, so
+ * calls that overlap on one device (concurrent streams or threads) race; calls ordered
+ * on one stream do not. Errors: VP_ERR_ARG for NULL pointers; VP_ERR_UNSUPPORTED when
+ * the plan needs more than 32 MiB of blade images (B * n * n complex values, twice that
+ * when T > 1); VP_ERR_STATE when the plan's tables are not on the current device. */
+vp_status vp_forward_noalloc(const vp_plan* plan, const vp_c64* d_vol, const vp_c64* d_y, vp_c64* d_out,
+                             void* stream);
+
 /* d_grad[T][S][n][n] (+)= A^H d_kres: blade mask, unitary inverse DFT and the
  * transpose of the sheared projection (a gather, no atomics), with dynamic
  * blades split onto their two knots with weights (1-a, a). For a real loss

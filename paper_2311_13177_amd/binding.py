@@ -109,6 +109,7 @@ _PROTOS = {
     "vp_plan_tune": (c_int32, [_P, POINTER(vp_options), POINTER(vp_tiles)]),
     "vp_plan_tiles": (c_int32, [_P, POINTER(vp_options), POINTER(vp_tiles)]),
     "vp_forward": (c_int32, [_P, _P, _P, _P, _P]),
+    "vp_forward_noalloc": (c_int32, [_P, _P, _P, _P, _P]),
     "vp_adjoint": (c_int32, [_P, _P, _P, c_int32, _P]),
     "vp_tv_grad": (c_int32, [_P, _P, c_float, c_float, c_float, _P, c_int32, _P]),
     "vp_render": (c_int32, [_P, _P, c_int32, _P, _P, _P, _P]),
@@ -334,6 +335,15 @@ def vp_forward(plan: Plan, vol, y=None, out=None, stream=None):
     check(lib().vp_forward(plan.handle, _dev(vol, plan.volume_shape, "vol"),
                            None if y is None else _dev(y, plan.blade_shape, "y"),
                            _dev(out, plan.blade_shape, "out"), _stream(stream)))
+    return out
+
+
+def vp_forward_noalloc(plan: Plan, vol, out, y=None, stream=None):
+    """vp_forward into the caller's `out` with no device allocation (the library's fixed
+    scratch array holds the blade images); returns out."""
+    check(lib().vp_forward_noalloc(plan.handle, _dev(vol, plan.volume_shape, "vol"),
+                                   None if y is None else _dev(y, plan.blade_shape, "y"),
+                                   _dev(out, plan.blade_shape, "out"), _stream(stream)))
     return out
 
 

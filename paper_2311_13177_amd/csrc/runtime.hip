@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -338,6 +339,98 @@ extern "C" vp_status vp_adjoint(const vp_plan* p, const vp_c64* d_kres, vp_c64* 
     a.tasks = L.gath; a.ntasks = L.n_gath;
     if ((e = launch_gather(a, GATHER_STORE, L.tiles.gath_rows, L.tiles.gath_sc, L.tiles.gath_w, L.re_gath, sc.s)) != hipSuccess)
         return hip_status(e, "vp_adjoint gather");
+    return VP_OK;
+}
+
+// ------------------------------------------------------------------ forward without allocation
+//
+// vp_forward_noalloc runs vp_forward's kernels with the blade work images in a
+// file-scope device array instead of stream-ordered memory. Each device holds its own
+// copy of the array at its own address: host code takes that address from
+// hipGetSymbolAddress (once per device, on the first call there) and passes it to the
+// kernels; the array's name is never used as a device address on the host.
+
+namespace {
+
+constexpr size_t kScratchBytes = size_t(32) << 20;  // 32 MiB per device
+__device__ __align__(256) float2 scratch[kScratchBytes / sizeof(float2)];
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+float2* g_scratch_ptr[kScratchDevices] = {};
+
+// This device's copy of the scratch array (the current device is `dev`).
+vp_status scratch_address(int dev, float2** out) {
+    if (dev < 0 || dev >= kScratchDevices) return fail(VP_ERR_DEVICE, "vp_forward_noalloc: device %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return hip_status(e != hipSuccess ? e : hipErrorInvalidSymbol, "scratch address");
+        g_scratch_ptr[dev] = (float2*)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return VP_OK;
+}
+
+// The device tables and the layout an operator call would use on `dev`, when both exist
+// already: nothing is built, uploaded or allocated here.
+vp_status existing_tables(const vp_plan* p, int dev, const DeviceTables** t, const Layout** lay,
+                          const DeviceLayout** dl) {
+    Tiles want = p->base_tiles;
+    (void)tuned_tiles(p, dev, VP_OPT_ADAM, &want);
+    std::lock_guard<std::mutex> lk(p->mu);
+    auto it = p->dev.find(dev);
+    if (it == p->dev.end())
+        return fail(VP_ERR_STATE, "vp_forward_noalloc: the plan has no tables on device %d yet", dev);
+    const DeviceTables* tab = it->second.get();
+    for (const Tiles& tl : {want, p->base_tiles}) {
+        auto hl = p->layouts.find(tl.key());
+        auto dlit = tab->layouts.find(tl.key());
+        if (hl != p->layouts.end() && dlit != tab->layouts.end()) {
+            *t = tab;
+            *lay = hl->second.get();
+            *dl = dlit->second.get();
+            return VP_OK;
+        }
+    }
+    return fail(VP_ERR_STATE, "vp_forward_noalloc: the plan's launch tables are not on device %d yet", dev);
+}
+
+}  // namespace
+
+extern "C" vp_status vp_forward_noalloc(const vp_plan* p, const vp_c64* d_vol, const vp_c64* d_y, vp_c64* d_out,
+                                        void* stream) {
+    clear_error();
+    if (!p || !d_vol || !d_out) return fail(VP_ERR_ARG, "vp_forward_noalloc: NULL argument");
+    const size_t bytes = (size_t)p->nparts * p->blade_px() * sizeof(float2);
+    if (bytes > kScratchBytes)
+        return fail(VP_ERR_UNSUPPORTED, "vp_forward_noalloc: %zu bytes of blade images exceed the %zu-byte scratch",
+                    bytes, kScratchBytes);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_status(e, "hipGetDevice");
+    const DeviceTables* t = nullptr;
+    const Layout* lay = nullptr;
+    const DeviceLayout* dl = nullptr;
+    vp_status st = existing_tables(p, dev, &t, &lay, &dl);
+    if (st != VP_OK) return st;
+    float2* work = nullptr;
+    if ((st = scratch_address(dev, &work)) != VP_OK) return st;
+    const hipStream_t s = (hipStream_t)stream;
+    KArgs a{};
+    fill_desc(p, t, lay, dl, &a.one);
+    a.one.vol[0] = (float2*)d_vol;
+    a.one.y = (const float2*)d_y;
+    a.one.work = work;
+    const StageLists L = plan_lists(p, t, lay, dl);
+    a.tasks = L.proj; a.ntasks = L.n_proj;
+    if ((e = launch_project(a, L.tiles.proj_rows, L.tiles.proj_gw, L.tiles.proj_w, L.re_proj, s)) != hipSuccess)
+        return hip_status(e, "vp_forward_noalloc project");
+    a.tasks = L.rows; a.ntasks = L.n_rows;
+    if ((e = launch_rows(a, -1, L.fft_n, L.lds_rows, s)) != hipSuccess) return hip_status(e, "vp_forward_noalloc rows");
+    a.tasks = L.cols; a.ntasks = L.n_cols; a.mode = COL_FORWARD; a.out0 = (float2*)d_out;
+    if ((e = launch_cols(a, L.fft_n, L.lds_cols, s)) != hipSuccess) return hip_status(e, "vp_forward_noalloc cols");
     return VP_OK;
 }
 
