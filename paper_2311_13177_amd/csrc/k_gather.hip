@@ -81,6 +81,21 @@ __device__ __forceinline__ void update_column(const float2 (&acc)[SCM][PPT], con
             for (int k = 0; k < WR; ++k) w[k] = zero;
         }
     };
+    // x halos of the tile's rows: lane i < PPT reads column x0 - 1 of row y0 + i and lane
+    // 32 + i column x0 + 64 (out of range, hence zero, past the grid's border or its last
+    // row); lanes 0 and 63 take them by readlane, so one load per bin serves every row
+    int hb = kBufferOut;
+    if (u.lane < PPT) {
+        const int y = u.y0 + u.lane;
+        if (y < n && u.x0 > 0) hb = (y * n + u.x0 - 1) * (int)sizeof(float2);
+    } else if (u.lane >= 32 && u.lane < 32 + PPT) {
+        const int y = u.y0 + u.lane - 32;
+        if (y < n && u.x0 + 64 < n) hb = (y * n + u.x0 + 64) * (int)sizeof(float2);
+    }
+    auto lane_val = [](float2 v, int l) {
+        return make_float2(__builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v.x), l)),
+                           __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v.y), l)));
+    };
     if (u.ns <= 0) return;
     // win[k]: rows of bin sw - 1 + k; the loop over bins is unrolled, so bin q reads
     // win[q], win[q + 1], win[q + 2] in place (no register copies between bins)
@@ -99,7 +114,8 @@ __device__ __forceinline__ void update_column(const float2 (&acc)[SCM][PPT], con
             const float2(&cv)[WR] = win[q + 1];
             const float2(&nv)[WR] = win[q + 2];
             const int so = s * nn * (int)sizeof(float2);
-            // moments and time neighbours first, so their loads overlap the arithmetic
+            // moments, time neighbours and x halos first, so their loads overlap the arithmetic
+            const float2 hv = ld(rV, hb, so);
             float2 mm[PPT], vv[PPT], tp[PPT], tn[PPT];
 #pragma unroll
             for (int i = 0; i < PPT; ++i) {
@@ -124,8 +140,9 @@ __device__ __forceinline__ void update_column(const float2 (&acc)[SCM][PPT], con
                     const int vo = rb[i + 1];
                     const float2 v0 = cv[i + 1];
                     float2 left = shfl_up1(v0), right = shfl_down1(v0);
-                    if (u.lane == 0) left = u.x0 > 0 ? ld(rV, vo - (int)sizeof(float2), so) : zero;
-                    if (u.lane == 63) right = u.x0 + 64 < n ? ld(rV, vo + (int)sizeof(float2), so) : zero;
+                    const float2 hl = lane_val(hv, i), hr = lane_val(hv, 32 + i);
+                    if (u.lane == 0) left = hl;
+                    if (u.lane == 63) right = hr;
                     float2 g = nzero;
                     if (tv) {
                         if (u.kt > 0) g = cadd(g, charb_w(csub(v0, tp[i]), eps2));
@@ -351,6 +368,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
                     for (int q = 0; q < SCM; ++q) {
                         if (q < ns) {
                             const float w00 = tw[q][0], w01 = tw[q][1], w10 = tw[q][2], w11 = tw[q][3];
+                            // row of g[y - oy][.] for pixel row 0, column of g[.][x - ox]
                             // row of g[y - oy][.] for pixel row 0, column of g[.][x - ox]
                             const float2* L = buf + p * RE + (koy - toy[q] + 1) * RW + (kox - tox[q] + 1) + lane;
                             float2 u0 = L[-RW], u1 = L[-RW - 1];
