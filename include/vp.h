@@ -417,8 +417,10 @@ typedef struct {
 } vp_result;
 
 /* Many independent slices, possibly of different sizes, reconstructed together
- * on opts[0]->device: each step is one persistent launch per stage over all
- * slices, captured once in a HIP graph and replayed. Every slice's result is
+ * on opts[0]->device: each step is one launch per stage over the concatenated work
+ * items of all slices (a block per work item, each reading its slice's descriptor
+ * from a device table; the hardware dispatcher balances the uneven items), the whole
+ * step captured once in a HIP graph and replayed. Every slice's result is
  * the one vp_reconstruct gives it alone (bit for bit: summation orders do not
  * depend on the batch). Per-slice status goes to results[i]->status; the call
  * returns the first failure, if any. */
@@ -536,11 +538,16 @@ vp_status vp_kplanes_reconstruct(const vp_plan* plan, const vp_kplanes* model, c
 
 /* ------------------------------------------------------------------ serving */
 
-/* A reconstruction server on one device: requests are admitted while the sum
- * of their vp_plan_device_bytes stays within hbm_budget and at most max_slots
- * run at once; all admitted requests advance together, one step per
- * super-step, and new requests join between super-steps (continuous batching).
- * The server is thread-safe. */
+/* A reconstruction server on one device: requests are admitted in arrival order
+ * while the sum of their vp_plan_device_bytes stays within hbm_budget and at most
+ * max_slots are resident; an admitted request keeps its state on the device until it
+ * finishes. The oldest resident requests with work left (up to four, and only until
+ * their volumes reach 8M voxels, at least one) each replay their own captured step on
+ * their own stream, eight steps per enqueued super-step with up to two super-steps in
+ * flight each, so their work overlaps on the device; requests that arrive meanwhile
+ * are admitted (their state uploaded) as slots and memory free up and start stepping
+ * as soon as an older one finishes (continuous batching). A request's result does not
+ * depend on the mix it ran in. The server is thread-safe. */
 vp_status vp_server_create(int32_t device, uint64_t hbm_budget, int32_t max_slots, vp_server** out);
 
 /* Queues a request. The inputs are copied before the call returns (plan is

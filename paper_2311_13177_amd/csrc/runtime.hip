@@ -186,6 +186,12 @@ vp_status check_options(const vp_plan* p, const vp_options* o) {
 // ------------------------------------------------------------------ launch sequences
 
 void launch_step(const KArgs& base, const StageLists& L, hipStream_t s, hipError_t* err, hipEvent_t* ev) {
+    // the projection takes the step counters' snapshot and the step's last kernel advances
+    // them from it: both launches must have work items (every plan has, by construction)
+    if (L.n_proj <= 0 || (L.tiles.upd_sc == 0 ? L.n_gath <= 0 : L.n_upd <= 0)) {
+        *err = hipErrorInvalidValue;
+        return;
+    }
     KArgs a = base;
     a.epi = L.epi;
     hipError_t e;
