@@ -505,7 +505,8 @@ def copy_probe():
 
 
 # Source files of each kernel family (plus the shared device headers).
-KERNEL_SOURCES = {"k_gather": ["k_gather.hip"], "k_update": ["k_gather.hip"], "k_project": ["k_project.hip"],
+KERNEL_SOURCES = {"k_gather": ["k_gather.hip"], "k_gather_res": ["k_gather.hip"], "k_update": ["k_gather.hip"],
+                  "k_project": ["k_project.hip"],
                   "k_rows": ["k_fft.hip"], "k_cols": ["k_fft.hip"]}
 
 
@@ -608,7 +609,8 @@ def measure_workload(case, B, steps, warmup):
     dom = max(stages, key=lambda k: stages[k])
     dur_s = stages[dom] * 1e-3
     kernel_names = {"project": "k_project", "rows_fwd": "k_rows<-1>", "cols": "k_cols", "rows_inv": "k_rows<1>",
-                    "gather_update": "k_gather<1>" if tiles[4] == 0 else "k_gather<0>+k_update"}
+                    "gather_update": ("k_gather_res" if tiles[7] else "k_gather<1>") if tiles[4] == 0
+                    else "k_gather<0>+k_update"}
     bytes_l = stage_bytes[dom]
     flops_l = stage_flops.get(dom, 0)
     ai = flops_l / bytes_l
@@ -633,7 +635,7 @@ def measure_workload(case, B, steps, warmup):
                    "optimizer": "adam", "schedule": "all blades per step",
                    "tiles": {"proj_rows": tiles[0], "proj_parts": tiles[1], "gath_rows": tiles[2],
                              "gath_bins": tiles[3], "upd_bins": tiles[4], "gath_waves": tiles[5],
-                             "proj_waves": tiles[6]},
+                             "proj_waves": tiles[6], "gath_resident": tiles[7]},
                    "tune_s": round(tune_s, 4)},
         "recon_wall_s": round(recon_s, 4),
         "stage_ms": {k: round(v, 5) for k, v in stages.items()},

@@ -119,14 +119,18 @@ enum { VP_SCHED_ALL_BLADES = 0, VP_SCHED_CYCLIC = 1, VP_SCHED_RANDOM = 2 };
  * blade parts per wave of a projection item, in {1, 2, 4, 8}, with proj_rows *
  * proj_parts <= 16; gath_rows: rows of a gather tile, in {2, 4}; gath_bins:
  * spectral bins per wave of a gather item, in {1, 2, 4, 8}, with gath_rows *
- * gath_bins <= 16; upd_bins: 0 runs the regulariser and optimiser update inside
+ * gath_bins <= 16 unless gath_resident is 1; upd_bins: 0 runs the regulariser and optimiser update inside
  * the gather kernel, 2, 4 or 8 runs it as a separate pass (that many bins per
  * wave) over a stored data gradient (one more volume-sized device buffer);
  * gath_waves: waves per gather item, 4 or 8 (0 means 4), which share the item's
  * staged blade regions, so an item covers gath_waves * gath_bins bins; proj_waves:
  * waves per projection item, 4 or 8 (0 means 4), which share the item's staged
- * volume regions, so an item projects proj_waves * proj_parts blade parts. A tile
- * is 64 columns wide. All fields 0: the plan's own (or autotuned) shape. */
+ * volume regions, so an item projects proj_waves * proj_parts blade parts;
+ * gath_resident: 1 stages every blade part feeding a knot at once and interleaves
+ * each bin's gather with that bin's update (needs upd_bins 0, at most 32 parts per
+ * knot, staged regions of at most 1024 elements and 64 KiB of LDS per item;
+ * VP_ERR_UNSUPPORTED otherwise), 0 stages the parts a few at a time. A tile is 64
+ * columns wide. All fields 0: the plan's own (or autotuned) shape. */
 typedef struct {
     int32_t proj_rows;
     int32_t proj_parts;
@@ -135,6 +139,7 @@ typedef struct {
     int32_t upd_bins;
     int32_t gath_waves;
     int32_t proj_waves;
+    int32_t gath_resident;
 } vp_tiles;
 
 typedef struct {

@@ -51,11 +51,11 @@ class vp_geometry(ctypes.Structure):
 
 class vp_tiles(ctypes.Structure):
     _fields_ = [("proj_rows", c_int32), ("proj_parts", c_int32), ("gath_rows", c_int32), ("gath_bins", c_int32),
-                ("upd_bins", c_int32), ("gath_waves", c_int32), ("proj_waves", c_int32)]
+                ("upd_bins", c_int32), ("gath_waves", c_int32), ("proj_waves", c_int32), ("gath_resident", c_int32)]
 
     def as_tuple(self):
         return (self.proj_rows, self.proj_parts, self.gath_rows, self.gath_bins, self.upd_bins, self.gath_waves,
-                self.proj_waves)
+                self.proj_waves, self.gath_resident)
 
 
 class vp_options(ctypes.Structure):
@@ -215,8 +215,8 @@ def _hp(a: Optional[np.ndarray]):
 # ------------------------------------------------------------------ options
 
 def vp_options_default(**overrides) -> vp_options:
-    """Default options with fields overridden by keyword; `tiles` takes a 4- to 7-tuple
-    (proj_rows, proj_parts, gath_rows, gath_bins[, upd_bins[, gath_waves[, proj_waves]]])."""
+    """Default options with fields overridden by keyword; `tiles` takes a 4- to 8-tuple
+    (proj_rows, proj_parts, gath_rows, gath_bins[, upd_bins[, gath_waves[, proj_waves[, gath_resident]]]])."""
     o = vp_options()
     check(lib().vp_options_default(byref(o)))
     for k, v in overrides.items():

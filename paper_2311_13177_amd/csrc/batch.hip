@@ -49,6 +49,7 @@ static Tiles group_tiles(const std::vector<vp_session*>& sessions) {
             clear_error();
             t.proj_rows = 2;
             t.gath_rows = 2;
+            t.gath_res = 0;
             break;
         }
     }
@@ -95,6 +96,7 @@ vp_status group_build(SliceGroup* g, const std::vector<vp_session*>& sessions, c
         L.lds_rows = std::max(L.lds_rows, p->lds_rows);
         L.lds_cols = std::max(L.lds_cols, p->lds_cols);
         L.re_gath = std::max(L.re_gath, lay->re_gath);
+        L.lds_res = std::max(L.lds_res, lay->lds_res);
     }
     std::vector<Task>& all = g->h_tasks;
     all.clear();
@@ -245,11 +247,11 @@ extern "C" vp_status vp_batch_create(int32_t n, const vp_plan* const* plans, con
         const vp_tiles& ot = o.tiles;
         const Layout* lay = nullptr;
         const bool unset = !ot.proj_rows && !ot.proj_parts && !ot.gath_rows && !ot.gath_bins && !ot.upd_bins &&
-                           !ot.gath_waves && !ot.proj_waves;
+                           !ot.gath_waves && !ot.proj_waves && !ot.gath_resident;
         if (have_shape && unset) {
             if (plan_layout(plans[i], shape, &lay) == VP_OK)
                 o.tiles = vp_tiles{shape.proj_rows, shape.proj_gw, shape.gath_rows, shape.gath_sc,
-                                   shape.upd_sc, shape.gath_w, shape.proj_w};
+                                   shape.upd_sc, shape.gath_w, shape.proj_w, shape.gath_res};
             else
                 clear_error();
         }

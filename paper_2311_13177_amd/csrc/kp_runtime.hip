@@ -225,7 +225,7 @@ vp_status dense_setup(const vp_plan* p, DenseStep* ds, const vp_options* o = nul
     if (st == VP_OK && !tuned_tiles(ds->q, ds->tabs->device, o ? o->optimizer : VP_OPT_ADAM, &t) && o &&
         o->autotune) {
         vp_options to = *o;
-        to.tiles = vp_tiles{0, 0, 0, 0, 0, 0, 0};
+        to.tiles = vp_tiles{0, 0, 0, 0, 0, 0, 0, 0};
         st = tune_plan(ds->q, &to, &t);
     }
     if (st == VP_OK) st = plan_layout(ds->q, t, &ds->lay);

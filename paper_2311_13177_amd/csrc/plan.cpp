@@ -103,10 +103,11 @@ static int region(int rows, int ox_min, int ox_max, int oy_min, int oy_max) {
 // are ordered tile-major, then knot, then bin chunk, so that the items sharing a tile's
 // blade regions and its neighbouring knots run side by side (see xcd_item).
 static vp_status build_layout(const vp_plan* p, const Tiles& t, Layout* L) {
-    if (!proj_tiles_ok(t.proj_rows, t.proj_gw) || !gath_tiles_ok(t.gath_rows, t.gath_sc) || !upd_tiles_ok(t.upd_sc) ||
-        !item_waves_ok(t.gath_w) || !item_waves_ok(t.proj_w))
-        return fail(VP_ERR_UNSUPPORTED, "tile shape (%d, %d, %d, %d, %d, %d, %d) is not compiled", t.proj_rows,
-                    t.proj_gw, t.gath_rows, t.gath_sc, t.upd_sc, t.gath_w, t.proj_w);
+    if (!proj_tiles_ok(t.proj_rows, t.proj_gw) || !gath_tiles_ok(t.gath_rows, t.gath_sc, t.gath_res == 1) || !upd_tiles_ok(t.upd_sc) ||
+        !item_waves_ok(t.gath_w) || !item_waves_ok(t.proj_w) || (t.gath_res != 0 && t.gath_res != 1) ||
+        (t.gath_res && t.upd_sc))
+        return fail(VP_ERR_UNSUPPORTED, "tile shape (%d, %d, %d, %d, %d, %d, %d, %d) is not compiled", t.proj_rows,
+                    t.proj_gw, t.gath_rows, t.gath_sc, t.upd_sc, t.gath_w, t.proj_w, t.gath_res);
     const int n = p->n, S = p->S, T = p->T;
     L->tiles = t;
     L->groups.clear();
@@ -135,6 +136,21 @@ static vp_status build_layout(const vp_plan* p, const Tiles& t, Layout* L) {
     if (L->re_proj > kStageMax * kThreads || L->re_gath > kStageMax * kThreads)
         return fail(VP_ERR_UNSUPPORTED, "tile shape (%d, %d, %d, %d): staged region exceeds the LDS staging",
                     t.proj_rows, t.proj_gw, t.gath_rows, t.gath_sc);
+    L->lds_res = 0;
+    if (t.gath_res) {
+        // every part of a knot resident at once: part j of knot kt at [j * region, (j + 1) * region)
+        for (int kt = 0; kt < T; ++kt) {
+            const KnotInfo& ki = p->knots[kt];
+            const int np = p->knot_ptr[kt + 1] - p->knot_ptr[kt];
+            const int re = region(t.gath_rows, ki.ox_min, ki.ox_max, ki.oy_min, ki.oy_max);
+            if (np > kResMaxParts || re > kResRegion)
+                return fail(VP_ERR_UNSUPPORTED, "resident gather: knot %d has %d parts of %d elements", kt, np, re);
+            L->lds_res = std::max(L->lds_res, (size_t)np * (size_t)re * sizeof(float2));
+        }
+        if (L->lds_res > kResLds)
+            return fail(VP_ERR_UNSUPPORTED, "resident gather: %zu bytes of LDS", L->lds_res);
+        L->lds_res = std::max<size_t>(L->lds_res, 8);
+    }
     const int txn = ceil_div(n, kTileW);
     const int typ = ceil_div(n, t.proj_rows), tyg = ceil_div(n, t.gath_rows);
     // group-major (knot-major): the tiles of one knot's group in row order, so the items
@@ -144,10 +160,24 @@ static vp_status build_layout(const vp_plan* p, const Tiles& t, Layout* L) {
         for (int ty = 0; ty < typ; ++ty)
             for (int tx = 0; tx < txn; ++tx) L->t_proj.push_back(Task{0, gi, ty, tx});
     const int nch = ceil_div(S, t.gath_w * t.gath_sc);
-    for (int ty = 0; ty < tyg; ++ty)
-        for (int tx = 0; tx < txn; ++tx)
+    if (!t.gath_res) {
+        for (int ty = 0; ty < tyg; ++ty)
+            for (int tx = 0; tx < txn; ++tx)
+                for (int kt = 0; kt < T; ++kt)
+                    for (int ch = 0; ch < nch; ++ch) L->t_gath.push_back(Task{0, kt, ty * txn + tx, ch});
+    } else {
+        // Resident-parts items walk their bins in step from the start, so the items that
+        // re-read each other's rows should start together: bands of tile rows, and within
+        // a band knot by knot, put the tiles above and below (y halos) a few items apart
+        // and the neighbouring knots (the time differences) one band-knot apart, instead
+        // of the y neighbours a whole row of knots apart.
+        const int band = std::max(1, std::min(tyg, ceil_div(16, txn * nch)));
+        for (int ty0 = 0; ty0 < tyg; ty0 += band)
             for (int kt = 0; kt < T; ++kt)
-                for (int ch = 0; ch < nch; ++ch) L->t_gath.push_back(Task{0, kt, ty * txn + tx, ch});
+                for (int ty = ty0; ty < std::min(tyg, ty0 + band); ++ty)
+                    for (int tx = 0; tx < txn; ++tx)
+                        for (int ch = 0; ch < nch; ++ch) L->t_gath.push_back(Task{0, kt, ty * txn + tx, ch});
+    }
     if (t.upd_sc) {
         const int nuc = ceil_div(S, t.upd_sc), tyu = ceil_div(n, 4);
         for (int ty = 0; ty < tyu; ++ty)
@@ -231,7 +261,7 @@ extern "C" vp_status vp_options_default(vp_options* o) {
     o->schedule = VP_SCHED_ALL_BLADES;
     o->split_bin = -1;
     o->device = 0;
-    o->tiles = vp_tiles{0, 0, 0, 0, 0, 0, 0};
+    o->tiles = vp_tiles{0, 0, 0, 0, 0, 0, 0, 0};
     o->autotune = 0;
     o->seed = 0;
     o->data_weight = 1.0f;

@@ -23,8 +23,10 @@ struct Tiles {
     int upd_sc = 0;  // 0: update fused into the gather; else bins per wave of the update pass
     int gath_w = 4;  // waves per gather item
     int proj_w = 4;  // waves per projection item
+    int gath_res = 0;  // 1: the resident-parts gather (every part of a knot staged at once)
     int key() const {
-        return proj_rows | proj_gw << 4 | gath_rows << 8 | gath_sc << 12 | upd_sc << 16 | gath_w << 20 | proj_w << 24;
+        return proj_rows | proj_gw << 4 | gath_rows << 8 | gath_sc << 12 | upd_sc << 16 | gath_w << 20 | proj_w << 24 |
+               gath_res << 28;
     }
     bool operator==(const Tiles& o) const { return key() == o.key(); }
 };
@@ -35,6 +37,7 @@ struct Layout {
     std::vector<ProjGroup> groups;
     std::vector<Task> t_proj, t_gath, t_upd;
     int re_proj = 0, re_gath = 0;  // largest staged region (elements) of an item
+    size_t lds_res = 0;            // resident-parts gather: LDS bytes of the largest knot
 };
 
 // A layout's tables on one device.

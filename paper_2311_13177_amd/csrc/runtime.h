@@ -18,6 +18,9 @@ hipError_t launch_rows(const KArgs& a, int dir, int n, size_t lds, hipStream_t s
 hipError_t launch_cols(const KArgs& a, int n, size_t lds, hipStream_t s);
 // waves: 4 or 8 per work item (the layout's gath_w: its bin chunks hold waves * sc bins)
 hipError_t launch_gather(const KArgs& a, int mode, int rows, int sc, int waves, int re, hipStream_t s);
+// The fused step's resident-parts gather (GATHER_STEP only): lds bytes of the largest
+// knot's parts (Layout::lds_res).
+hipError_t launch_gather_res(const KArgs& a, int rows, int sc, int waves, size_t lds, hipStream_t s);
 hipError_t launch_update(const KArgs& a, int sc, hipStream_t s);
 hipError_t launch_tv_grad(const KArgs& a, hipStream_t s);
 hipError_t launch_reg_value(const KArgs& a, hipStream_t s);
@@ -42,6 +45,7 @@ struct StageLists {
     int fft_n = 0;  // common length of every slice (0 if they differ)
     size_t lds_rows = 0, lds_cols = 0;
     int re_proj = 0, re_gath = 0;  // largest staged regions (elements)
+    size_t lds_res = 0;            // resident-parts gather: LDS bytes of the largest knot
     int epi = EPI_GENERIC;         // optimiser epilogue every slice of the step can take
 };
 

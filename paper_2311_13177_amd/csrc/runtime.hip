@@ -174,12 +174,14 @@ vp_status check_options(const vp_plan* p, const vp_options* o) {
     if (o->split_bin > p->S) return fail(VP_ERR_ARG, "options: split_bin above n_spec");
     const vp_tiles& t = o->tiles;
     const bool none = !t.proj_rows && !t.proj_parts && !t.gath_rows && !t.gath_bins && !t.upd_bins && !t.gath_waves &&
-                      !t.proj_waves;
-    if (!none && (!proj_tiles_ok(t.proj_rows, t.proj_parts) || !gath_tiles_ok(t.gath_rows, t.gath_bins) ||
+                      !t.proj_waves && !t.gath_resident;
+    if (!none && (!proj_tiles_ok(t.proj_rows, t.proj_parts) || !gath_tiles_ok(t.gath_rows, t.gath_bins, t.gath_resident == 1) ||
                   !upd_tiles_ok(t.upd_bins) || (t.gath_waves != 0 && !item_waves_ok(t.gath_waves)) ||
-                  (t.proj_waves != 0 && !item_waves_ok(t.proj_waves))))
-        return fail(VP_ERR_UNSUPPORTED, "options: tile shape (%d, %d, %d, %d, %d, %d, %d) is not compiled",
-                    t.proj_rows, t.proj_parts, t.gath_rows, t.gath_bins, t.upd_bins, t.gath_waves, t.proj_waves);
+                  (t.proj_waves != 0 && !item_waves_ok(t.proj_waves)) || (t.gath_resident != 0 && t.gath_resident != 1) ||
+                  (t.gath_resident && t.upd_bins)))
+        return fail(VP_ERR_UNSUPPORTED, "options: tile shape (%d, %d, %d, %d, %d, %d, %d, %d) is not compiled",
+                    t.proj_rows, t.proj_parts, t.gath_rows, t.gath_bins, t.upd_bins, t.gath_waves, t.proj_waves,
+                    t.gath_resident);
     return VP_OK;
 }
 
@@ -221,7 +223,9 @@ void launch_step(const KArgs& base, const StageLists& L, hipStream_t s, hipError
     a.snap = 1;
     if (L.tiles.upd_sc == 0) {
         a.advance = 1;
-        e = launch_gather(a, GATHER_STEP, L.tiles.gath_rows, L.tiles.gath_sc, L.tiles.gath_w, L.re_gath, s);
+        e = L.tiles.gath_res
+                ? launch_gather_res(a, L.tiles.gath_rows, L.tiles.gath_sc, L.tiles.gath_w, L.lds_res, s)
+                : launch_gather(a, GATHER_STEP, L.tiles.gath_rows, L.tiles.gath_sc, L.tiles.gath_w, L.re_gath, s);
     } else {
         a.accumulate = 0;
         e = launch_gather(a, GATHER_STORE, L.tiles.gath_rows, L.tiles.gath_sc, L.tiles.gath_w, L.re_gath, s);
@@ -249,6 +253,7 @@ StageLists plan_lists(const vp_plan* p, const DeviceTables* t, const Layout* lay
     L.tiles = lay->tiles;
     L.fft_n = p->n;
     L.re_proj = lay->re_proj; L.lds_rows = p->lds_rows; L.lds_cols = p->lds_cols; L.re_gath = lay->re_gath;
+    L.lds_res = lay->lds_res;
     return L;
 }
 
@@ -733,7 +738,10 @@ struct vp_nu_session {
         if (r == hipSuccess) {
             if (L.tiles.upd_sc == 0) {
                 a.advance = 1;
-                r = launch_gather(a, GATHER_STEP, L.tiles.gath_rows, L.tiles.gath_sc, L.tiles.gath_w, L.re_gath, str);
+                r = L.tiles.gath_res
+                        ? launch_gather_res(a, L.tiles.gath_rows, L.tiles.gath_sc, L.tiles.gath_w, L.lds_res, str)
+                        : launch_gather(a, GATHER_STEP, L.tiles.gath_rows, L.tiles.gath_sc, L.tiles.gath_w, L.re_gath,
+                                        str);
             } else {
                 r = launch_gather(a, GATHER_STORE, L.tiles.gath_rows, L.tiles.gath_sc, L.tiles.gath_w, L.re_gath, str);
                 a.tasks = L.upd; a.ntasks = L.n_upd; a.advance = 1;

@@ -79,9 +79,10 @@ bool tuned_tiles(const vp_plan* p, int device, int optimizer, Tiles* out) {
 
 vp_status tiles_for(const vp_plan* p, const vp_options* o, Tiles* out) {
     const vp_tiles& t = o->tiles;
-    if (t.proj_rows || t.proj_parts || t.gath_rows || t.gath_bins || t.upd_bins || t.gath_waves || t.proj_waves) {
+    if (t.proj_rows || t.proj_parts || t.gath_rows || t.gath_bins || t.upd_bins || t.gath_waves || t.proj_waves ||
+        t.gath_resident) {
         *out = Tiles{t.proj_rows, t.proj_parts, t.gath_rows, t.gath_bins, t.upd_bins,
-                     t.gath_waves ? t.gath_waves : 4, t.proj_waves ? t.proj_waves : 4};
+                     t.gath_waves ? t.gath_waves : 4, t.proj_waves ? t.proj_waves : 4, t.gath_resident};
         return VP_OK;
     }
     if (tuned_tiles(p, o->device, o->optimizer, out)) return VP_OK;
@@ -104,7 +105,7 @@ vp_status tune_plan(const vp_plan* p, const vp_options* o, Tiles* out) {
     }
     vp_options so = *o;
     so.tiles = vp_tiles{p->base_tiles.proj_rows, p->base_tiles.proj_gw, p->base_tiles.gath_rows,
-                        p->base_tiles.gath_sc, 0, p->base_tiles.gath_w, p->base_tiles.proj_w};
+                        p->base_tiles.gath_sc, 0, p->base_tiles.gath_w, p->base_tiles.proj_w, 0};
     so.autotune = 0;
     vp_session* raw = nullptr;
     st = session_alloc(p, &so, zeros.data(), nullptr, nullptr, &raw);
@@ -159,41 +160,51 @@ vp_status tune_plan(const vp_plan* p, const vp_options* o, Tiles* out) {
     if ((st = session_ensure_grad(s.get())) != VP_OK) return st;
     float fused_ms = FLT_MAX, store_ms = FLT_MAX, upd_ms = FLT_MAX;
     Tiles fused = best, split = best;
+    // (the fused update also with every part of a knot resident, where the layout allows it)
     for (int mode = GATHER_STORE; mode <= GATHER_STEP; ++mode) {
-        for (int waves = 4; waves <= 8; waves += 4) {
-            // bins per wave up to the first power of two that covers S with every wave
-            const int sc_cap = std::min(8, pow2_at_least((p->S + waves - 1) / waves));
-            for (int rows = 2; rows <= 4; rows *= 2) {
-                for (int sc = 1; sc <= sc_cap; sc *= 2) {
-                    if (!gath_tiles_ok(rows, sc)) continue;
-                    Tiles t = p->base_tiles;
-                    t.gath_rows = rows;
-                    t.gath_sc = sc;
-                    t.gath_w = waves;
-                    const Layout* L = nullptr;
-                    const DeviceLayout* dl = nullptr;
-                    if (plan_layout(p, t, &L) != VP_OK) {
-                        clear_error();
-                        continue;
-                    }
-                    if ((st = device_layout(p, tabs, L, &dl)) != VP_OK) return st;
-                    KArgs a{};
-                    a.one = s->desc;
-                    a.epi = s->lists.epi;
-                    a.tasks = dl->t_gath;
-                    a.ntasks = (int)L->t_gath.size();
-                    float ms = 0.f;
-                    st = time_launches(
-                        s->stream, kReps,
-                        [&] { return launch_gather(a, mode, rows, sc, waves, L->re_gath, s->stream); }, &ms);
-                    if (st != VP_OK) return st;
-                    float& bm = mode == GATHER_STEP ? fused_ms : store_ms;
-                    Tiles& bt = mode == GATHER_STEP ? fused : split;
-                    if (ms < bm) {
-                        bm = ms;
-                        bt.gath_rows = rows;
-                        bt.gath_sc = sc;
-                        bt.gath_w = waves;
+        for (int res = 0; res <= (mode == GATHER_STEP ? 1 : 0); ++res) {
+            for (int waves = 4; waves <= 8; waves += 4) {
+                // bins per wave up to the first power of two that covers S with every wave
+                const int sc_cap = std::min(8, pow2_at_least((p->S + waves - 1) / waves));
+                for (int rows = 2; rows <= 4; rows *= 2) {
+                    for (int sc = 1; sc <= sc_cap; sc *= 2) {
+                        if (!gath_tiles_ok(rows, sc, res == 1)) continue;
+                        Tiles t = p->base_tiles;
+                        t.gath_rows = rows;
+                        t.gath_sc = sc;
+                        t.gath_w = waves;
+                        t.upd_sc = 0;
+                        t.gath_res = res;
+                        const Layout* L = nullptr;
+                        const DeviceLayout* dl = nullptr;
+                        if (plan_layout(p, t, &L) != VP_OK) {
+                            clear_error();
+                            continue;
+                        }
+                        if ((st = device_layout(p, tabs, L, &dl)) != VP_OK) return st;
+                        KArgs a{};
+                        a.one = s->desc;
+                        a.epi = s->lists.epi;
+                        a.tasks = dl->t_gath;
+                        a.ntasks = (int)L->t_gath.size();
+                        float ms = 0.f;
+                        st = time_launches(
+                            s->stream, kReps,
+                            [&] {
+                                return res ? launch_gather_res(a, rows, sc, waves, L->lds_res, s->stream)
+                                           : launch_gather(a, mode, rows, sc, waves, L->re_gath, s->stream);
+                            },
+                            &ms);
+                        if (st != VP_OK) return st;
+                        float& bm = mode == GATHER_STEP ? fused_ms : store_ms;
+                        Tiles& bt = mode == GATHER_STEP ? fused : split;
+                        if (ms < bm) {
+                            bm = ms;
+                            bt.gath_rows = rows;
+                            bt.gath_sc = sc;
+                            bt.gath_w = waves;
+                            bt.gath_res = res;
+                        }
                     }
                 }
             }
@@ -227,11 +238,13 @@ vp_status tune_plan(const vp_plan* p, const vp_options* o, Tiles* out) {
         best.gath_sc = split.gath_sc;
         best.gath_w = split.gath_w;
         best.upd_sc = split.upd_sc;
+        best.gath_res = 0;
     } else {
         best.gath_rows = fused.gath_rows;
         best.gath_sc = fused.gath_sc;
         best.gath_w = fused.gath_w;
         best.upd_sc = 0;
+        best.gath_res = fused.gath_res;
     }
     if ((e = hipStreamSynchronize(s->stream)) != hipSuccess) return hip_status(e, "autotune");
     {
@@ -247,7 +260,7 @@ vp_status tune_plan(const vp_plan* p, const vp_options* o, Tiles* out) {
 using namespace vp;
 
 static vp_tiles to_abi(const Tiles& t) {
-    return vp_tiles{t.proj_rows, t.proj_gw, t.gath_rows, t.gath_sc, t.upd_sc, t.gath_w, t.proj_w};
+    return vp_tiles{t.proj_rows, t.proj_gw, t.gath_rows, t.gath_sc, t.upd_sc, t.gath_w, t.proj_w, t.gath_res};
 }
 
 extern "C" vp_status vp_plan_tune(const vp_plan* p, const vp_options* o, vp_tiles* out) {

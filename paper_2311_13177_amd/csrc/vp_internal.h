@@ -35,14 +35,21 @@ __host__ __device__ constexpr bool pow2_le(int v, int hi) { return v >= 1 && v <
 __host__ __device__ constexpr bool proj_tiles_ok(int rows, int gw) {
     return pow2_le(rows, 8) && pow2_le(gw, 8) && rows * gw <= 16;
 }
-__host__ __device__ constexpr bool gath_tiles_ok(int rows, int sc) {
-    return pow2_le(rows, 4) && rows >= 2 && pow2_le(sc, 8) && rows * sc <= 16;
+// (The resident-parts gather keeps one bin's sums at a time, so it also takes 4 x 8.)
+__host__ __device__ constexpr bool gath_tiles_ok(int rows, int sc, bool resident = false) {
+    return pow2_le(rows, 4) && rows >= 2 && pow2_le(sc, 8) && (resident || rows * sc <= 16);
 }
 // Waves per projection or gather item (the waves share the item's staged regions).
 __host__ __device__ constexpr bool item_waves_ok(int w) { return w == 4 || w == 8; }
 // The optimiser update runs fused into the gather (0) or as a separate pass over the
 // stored data gradient with 2, 4 or 8 bins per wave.
 __host__ __device__ constexpr bool upd_tiles_ok(int sc) { return sc == 0 || sc == 2 || sc == 4 || sc == 8; }
+// Resident-parts gather (tile field gath_res): every blade part of a knot is staged at
+// once. A layout may take it where each knot's region is at most kResRegion elements, it
+// has at most kResMaxParts parts, and all of them fit kResLds bytes of LDS.
+constexpr int kResRegion = 1024;
+constexpr int kResMaxParts = 32;
+constexpr size_t kResLds = 65536;
 // Staged region elements per thread (register prefetch depth of the LDS staging).
 constexpr int kStageMax = 16;
 // A staged region of re elements (re <= kStageMax * kThreads) is loaded several planes

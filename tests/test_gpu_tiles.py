@@ -22,6 +22,9 @@ SHAPES = [
     # eight waves per gather or projection item
     (2, 1, 2, 4, 0, 8), (4, 2, 4, 1, 0, 8), (2, 2, 2, 8, 0, 8), (1, 1, 4, 2, 2, 8),
     (4, 1, 2, 4, 0, 8, 8), (1, 2, 2, 2, 0, 4, 8), (8, 1, 4, 1, 4, 8, 8),
+    # every part of a knot resident in LDS, each bin gathered and updated in turn
+    (2, 1, 2, 4, 0, 4, 4, 1), (4, 2, 4, 2, 0, 8, 4, 1), (1, 1, 2, 8, 0, 8, 8, 1), (2, 2, 4, 1, 0, 4, 4, 1),
+    (8, 1, 2, 1, 0, 8, 4, 1),
 ]
 
 CASES = {
@@ -79,9 +82,10 @@ def test_tuner_records_a_shape_that_sessions_and_operators_use(gpu_lib):
     case, plan, y = _problem(B, "dynamic_72", 0)
     before = B.vp_reconstruct(plan, y, B.vp_options_default(n_steps=6))
     tuned = plan.tune(B.vp_options_default())
-    pr, pp, gr, gb, ub, gw, pw = tuned
+    pr, pp, gr, gb, ub, gw, pw, res = tuned
     assert pr in (1, 2, 4, 8) and pp in (1, 2, 4, 8) and pr * pp <= 16 and pw in (4, 8)
     assert gr in (2, 4) and gb in (1, 2, 4, 8) and gr * gb <= 16 and ub in (0, 2, 4, 8) and gw in (4, 8)
+    assert res in (0, 1) and not (res and ub)
     assert plan.tiles(B.vp_options_default()) == tuned
     # a second plan of the same sizes picks the recorded shape up
     again = B.Plan.from_geometry(case.geometry())

@@ -162,9 +162,10 @@ def test_product_does_not_import_oracle():
 
 
 def _tiles_ok(t):
-    pr, pp, gr, gb, ub, gw, pw = t
+    pr, pp, gr, gb, ub, gw, pw, res = t
     return (pr in (1, 2, 4, 8) and pp in (1, 2, 4, 8) and pr * pp <= 16 and gr in (2, 4)
-            and gb in (1, 2, 4, 8) and gr * gb <= 16 and ub in (0, 2, 4, 8) and gw in (4, 8) and pw in (4, 8))
+            and gb in (1, 2, 4, 8) and gr * gb <= 16 and ub in (0, 2, 4, 8) and gw in (4, 8) and pw in (4, 8)
+            and res in (0, 1) and not (res and ub))
 
 
 @pytest.mark.parametrize("name", ["static_64", "static_256", "dynamic_192"])
@@ -174,15 +175,34 @@ def test_builtin_tile_shape_without_a_device(B, name):
     t = plan.tiles(B.vp_options_default())
     assert _tiles_ok(t)
     # an explicit shape is taken as given
-    assert plan.tiles(B.vp_options_default(tiles=(8, 1, 4, 4, 8))) == (8, 1, 4, 4, 8, 4, 4)
-    assert plan.tiles(B.vp_options_default(tiles=(2, 2, 2, 4, 0, 8))) == (2, 2, 2, 4, 0, 8, 4)
-    assert plan.tiles(B.vp_options_default(tiles=(4, 1, 2, 4, 0, 0, 8))) == (4, 1, 2, 4, 0, 4, 8)
+    assert plan.tiles(B.vp_options_default(tiles=(8, 1, 4, 4, 8))) == (8, 1, 4, 4, 8, 4, 4, 0)
+    assert plan.tiles(B.vp_options_default(tiles=(2, 2, 2, 4, 0, 8))) == (2, 2, 2, 4, 0, 8, 4, 0)
+    assert plan.tiles(B.vp_options_default(tiles=(4, 1, 2, 4, 0, 0, 8))) == (4, 1, 2, 4, 0, 4, 8, 0)
+
+
+@pytest.mark.parametrize("name,fits", [("static_64", True), ("dynamic_192", True), ("static_256", False)])
+def test_resident_gather_shape_where_the_parts_fit(B, name, fits):
+    """The resident-parts gather stages every part of a knot at once: a plan takes it when
+    the largest knot's parts fit 64 KiB of LDS (five parts of at most 666 elements in the
+    dynamic 192^2 workload) and refuses it otherwise (twelve parts of 836 elements, 80 KiB,
+    at 256^2), and never with a separate update pass."""
+    plan = _plan(B, configs.CONFIGS[name]())
+    shape = (2, 1, 2, 8, 0, 4, 4, 1)
+    if fits:
+        assert plan.tiles(B.vp_options_default(tiles=shape)) == shape
+    else:
+        with pytest.raises(B.VPError) as ei:
+            plan.tiles(B.vp_options_default(tiles=shape))
+        assert ei.value.status == B.VP_ERR_UNSUPPORTED
+    with pytest.raises(B.VPError) as ei:
+        plan.tiles(B.vp_options_default(tiles=(2, 1, 2, 8, 4, 4, 4, 1)))
+    assert ei.value.status == B.VP_ERR_UNSUPPORTED
 
 
 @pytest.mark.parametrize("tiles", [(3, 1, 2, 1, 0), (8, 4, 2, 1, 0), (2, 1, 1, 1, 0), (2, 1, 4, 8, 0),
                                    (2, 1, 2, 16, 0), (2, 1, 2, 1, 3), (0, 0, 0, 0, 4), (2, 1, 2, 1, 0, 2),
                                    (2, 1, 2, 1, 0, 16), (0, 0, 0, 0, 0, 8), (2, 1, 2, 1, 0, 4, 6),
-                                   (0, 0, 0, 0, 0, 0, 8)])
+                                   (0, 0, 0, 0, 0, 0, 8), (2, 1, 2, 1, 0, 4, 4, 2), (2, 1, 2, 1, 2, 4, 4, 1)])
 def test_uncompiled_tile_shapes_are_rejected(B, tiles):
     plan = _plan(B, configs.static_64())
     with pytest.raises(B.VPError) as ei:
