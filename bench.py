@@ -409,8 +409,12 @@ def shard_leg(B, name, gpus, steps, warmup):
 
 
 def _digest(r):
-    """A result's volume bytes (hashed) and objective: equal digests are bitwise equal results."""
-    return hashlib.sha256(r["vol"].tobytes()).hexdigest(), r["final_loss"]
+    """A result's rendered images (hashed) and objective: equal digests are bitwise equal
+    results as a client receives them (the renders are fixed sums of the volume's bins)."""
+    h = hashlib.sha256()
+    for k in ("proj", "water", "fat"):
+        h.update(r[k].tobytes())
+    return h.hexdigest(), r["final_loss"]
 
 
 def served_leg(B, n_req, steps_static, steps_dynamic, seed=5000, slots=8):
@@ -430,19 +434,24 @@ def served_leg(B, n_req, steps_static, steps_dynamic, seed=5000, slots=8):
                                  tv_weight=c.tv_weight, lr=c.lr) for c in cases]
     B.vp_reconstruct(probs[0][0], probs[0][1], B.vp_options_default(n_steps=2))
     _warm_plans(probs, B)
+    # every pass returns what a client of the served stream receives: the rendered image,
+    # water and fat images and the objective (the volume stays on the device)
     t0 = time.perf_counter()
-    solo = [_digest(B.vp_reconstruct(p, y, o)) for (p, y), o in zip(probs, opts)]
+    solo = [_digest(B.vp_reconstruct(p, y, o, volume=False)) for (p, y), o in zip(probs, opts)]
     t_plain = time.perf_counter() - t0
     progress(f"served: plain loop {t_plain:.1f} s")
     # the plain loop as the baseline definition has it: one request at a time, kernels
     # launched eagerly (no graph), nothing overlapped
     t0 = time.perf_counter()
+    eager = []
     for (p, y), o in zip(probs, opts):
         sess = B.Session(p, y, o)
         sess.step(o.n_steps, use_graph=False)
-        sess.objective()
-        sess.read()
+        obj = sess.objective()[0]
+        r = sess.read(volume=False)
         sess.close()
+        r["final_loss"] = obj
+        eager.append(_digest(r))
     t_eager = time.perf_counter() - t0
     progress(f"served: eager plain loop {t_eager:.1f} s")
     free, _ = torch.cuda.mem_get_info()
@@ -451,7 +460,7 @@ def served_leg(B, n_req, steps_static, steps_dynamic, seed=5000, slots=8):
     srv = B.Server(device=0, hbm_budget=budget, max_slots=slots)
     t0 = time.perf_counter()
     ids = [srv.submit(p, y, o) for (p, y), o in zip(probs, opts)]
-    closed = [_digest(srv.wait(i)) for i in ids]
+    closed = [_digest(srv.wait(i, volume=False)) for i in ids]
     t_closed = time.perf_counter() - t0
     srv.close()
     progress(f"served: closed loop {t_closed:.1f} s")
@@ -468,11 +477,11 @@ def served_leg(B, n_req, steps_static, steps_dynamic, seed=5000, slots=8):
         if target > now:
             time.sleep(target - now)
         ids.append(srv.submit(p, y, o))
-    served = [_digest(srv.wait(i)) for i in ids]
+    served = [_digest(srv.wait(i, volume=False)) for i in ids]
     t_open = time.perf_counter() - t0
     st = srv.stats()
     srv.close()
-    same = solo == served and [d[0] for d in solo] == [d[0] for d in closed]
+    same = solo == served and solo == closed and [d[0] for d in solo] == [d[0] for d in eager]
     full = steps_static == 200 and steps_dynamic == 800
     return {"workload": f"{n_req} requests (seeds {seed}+i): n 128-384, S 16-64, 8-32 blades, T in {{1,8,16}}; "
                         f"{steps_static} steps static / {steps_dynamic} dynamic"
@@ -484,7 +493,9 @@ def served_leg(B, n_req, steps_static, steps_dynamic, seed=5000, slots=8):
             "speedup_vs_plain_loop": round(t_plain / t_closed, 3),
             "speedup_vs_plain_loop_eager": round(t_eager / t_closed, 3),
             "plain_loops": "plain_loop: vp_reconstruct per request (upload, graph-replayed steps, objective, "
-                           "read-back); plain_loop_eager: the same with kernels launched eagerly, no graph",
+                           "read-back of the rendered image, water and fat images); plain_loop_eager: the same "
+                           "with kernels launched eagerly, no graph; every pass reads back the same renders "
+                           "and objective, and their digests must agree bit for bit",
             "closed_loop_rps": round(capacity, 3), "arrival_rate_rps": round(rate, 3),
             "open_loop_s": round(t_open, 3), "p50_ms": round(st["p50_us"] / 1e3, 2),
             "p99_ms": round(st["p99_us"] / 1e3, 2), "served_rps": round(st["throughput_rps"], 3),

@@ -567,9 +567,9 @@ class Session:
         check(lib().vp_session_steps_done(self.handle, byref(v)))
         return int(v.value)
 
-    def read(self):
+    def read(self, volume: bool = True):
         p = self.plan
-        vol = np.empty(p.volume_shape, np.complex64)
+        vol = np.empty(p.volume_shape, np.complex64) if volume else None
         outs = [np.empty(p.render_shape, np.complex64) for _ in range(3)]
         check(lib().vp_session_read(self.handle, _hp(vol), *[_hp(o) for o in outs]))
         return dict(vol=vol, proj=outs[0], water=outs[1], fat=outs[2])
@@ -605,11 +605,12 @@ class Session:
 
 
 def vp_reconstruct(plan: Plan, kspace: np.ndarray, opts: Optional[vp_options] = None,
-                   init: Optional[np.ndarray] = None) -> dict:
+                   init: Optional[np.ndarray] = None, volume: bool = True) -> dict:
+    """A whole reconstruction; volume=False copies back only the renders and the objective."""
     opts = opts if opts is not None else vp_options_default()
     k = _host_c64(kspace, plan.blade_shape)
     i = _host_c64(init, plan.volume_shape)
-    vol = np.empty(plan.volume_shape, np.complex64)
+    vol = np.empty(plan.volume_shape, np.complex64) if volume else None
     outs = [np.empty(plan.render_shape, np.complex64) for _ in range(3)]
     loss = c_double()
     check(lib().vp_reconstruct(plan.handle, byref(opts), _hp(k), _hp(i), _hp(vol), *[_hp(o) for o in outs],
@@ -651,12 +652,14 @@ class Server:
     def cancel(self, rid: int) -> None:
         check(lib().vp_server_cancel(self.handle, int(rid)))
 
-    def wait(self, rid: int, timeout_us: int = -1, raise_on_error: bool = True) -> dict:
+    def wait(self, rid: int, timeout_us: int = -1, raise_on_error: bool = True, volume: bool = True) -> dict:
+        """The request's result; with volume=False only the renders and the objective are
+        copied back (the volume stays on the device until it is released)."""
         plan = self._plans[rid]
-        vol = np.empty(plan.volume_shape, np.complex64)
+        vol = np.empty(plan.volume_shape, np.complex64) if volume else None
         rend = [np.empty(plan.render_shape, np.complex64) for _ in range(3)]
-        res = vp_result(volume_out=vol.ctypes.data, proj_out=rend[0].ctypes.data, water_out=rend[1].ctypes.data,
-                        fat_out=rend[2].ctypes.data)
+        res = vp_result(volume_out=vol.ctypes.data if volume else None, proj_out=rend[0].ctypes.data,
+                        water_out=rend[1].ctypes.data, fat_out=rend[2].ctypes.data)
         st = lib().vp_server_wait(self.handle, int(rid), int(timeout_us), byref(res))
         if st != VP_ERR_TIMEOUT:
             self._plans.pop(rid, None)

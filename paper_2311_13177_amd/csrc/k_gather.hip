@@ -2,6 +2,7 @@
 // optimiser update (Sections 4.2 and 4.3).
 
 #include "kcommon.h"
+#include "runtime.h"
 
 namespace vp {
 
@@ -505,13 +506,15 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
 // k_gather (parts in plan order, the four taps in order, then ColumnStream's update), so
 // the two kernels give the same bits.
 constexpr int kResTapGroup = 4;  // parts whose taps are loaded together
-template <int PPT, int SCM, int SE, int PG, int EPI, int NW, int WPE>
+template <int MODE, int PPT, int SCM, int SE, int PG, int EPI, int NW, int WPE>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE))) void k_gather_res(const KArgs a) {
     extern __shared__ float2 sm[];
     constexpr int NT = 64 * NW, WR = PPT + 2;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (a.advance) step_advance(a);
+    if constexpr (MODE == GATHER_STEP) {
+        if (a.advance) step_advance(a);
+    }
     for (int ti = xcd_item(blockIdx.x, gridDim.x); ti < a.ntasks; ti += gridDim.x) {
         const AS4 Task* tk = cst(a.tasks) + ti;
         const int slice = tk->slice;
@@ -539,8 +542,9 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE))) 
         unsigned act = 0;
         for (int j = 0; j < np; ++j)
             if (active_blade(sched, sseed, stepp, st, B, ent[e0 + j].blade)) act |= 1u << j;
-        // every active part's region of the tile, part j at sm[j * RE]: PG parts' loads in
-        // flight at a time, each thread holding region elements threadIdx.x + k * NT
+        // every active part's region of the tile, part j at sm[j * RE] (an inactive part's
+        // region is zeros): PG parts' loads in flight at a time, each thread holding region
+        // elements threadIdx.x + k * NT
         {
             Stager<SE, PG, NT> sg;
             sg.init(RH, RW, y0 - koy - 1, x0 - kox - 1, n);
@@ -562,7 +566,75 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE))) 
             }
         }
         __syncthreads();
-        if (ns > 0) {
+        // The data gradient of bin s: parts in plan order, taps
+        // w00 g[y-oy][x-ox] + w01 g[y-oy][x-ox-1] + w10 g[y-oy-1][x-ox] + w11 g[y-oy-1][x-ox-1].
+        // Parts go kResTapGroup at a time, every load of a group issued before any is used.
+        // A group's slots past the last part repeat the last part with zero weights, and an
+        // inactive part's region is zeros: such terms add a zero to the sum, which leaves it
+        // unchanged bit for bit (it starts at +0 and a sum of finite products is never -0),
+        // so the sum equals the one over the active parts alone.
+        auto gather_bin = [&](int s, float2 (&acc)[PPT]) {
+#pragma unroll
+            for (int i = 0; i < PPT; ++i) acc[i] = make_float2(0.f, 0.f);
+            const AS4 ShearEntry* const tb = ktap + (size_t)e0 * S + s;
+            for (int j0 = 0; j0 < np; j0 += kResTapGroup) {
+                int tof[kResTapGroup];
+                float tw[kResTapGroup][4];
+#pragma unroll
+                for (int p = 0; p < kResTapGroup; ++p) {
+                    const bool real = j0 + p < np;
+                    const int j = real ? j0 + p : np - 1;
+                    const AS4 ShearEntry* sh = tb + j * S;
+                    tof[p] = j * RE + (koy - sh->oy + 1) * RW + (kox - sh->ox + 1);
+                    tw[p][0] = real ? sh->w00 : 0.f;
+                    tw[p][1] = real ? sh->w01 : 0.f;
+                    tw[p][2] = real ? sh->w10 : 0.f;
+                    tw[p][3] = real ? sh->w11 : 0.f;
+                }
+#pragma unroll
+                for (int p = 0; p < kResTapGroup; ++p) {
+                    const float2* L = sm + tof[p] + lane;
+                    float2 u0 = L[-RW], u1 = L[-RW - 1];
+#pragma unroll
+                    for (int i = 0; i < PPT; ++i) {
+                        const float2 v0 = L[i * RW], v1 = L[i * RW - 1];
+                        float2 t = acc[i];
+                        t = cfma(tw[p][0], v0, t);
+                        t = cfma(tw[p][1], v1, t);
+                        t = cfma(tw[p][2], u0, t);
+                        t = cfma(tw[p][3], u1, t);
+                        acc[i] = t;
+                        u0 = v0;
+                        u1 = v1;
+                    }
+                }
+            }
+        };
+        if constexpr (MODE == GATHER_STORE) {
+            // write (or add to) the gradient, as k_gather<GATHER_STORE> does
+            float2* const grad = DF(grad);
+            const int x = x0 + lane;
+#pragma unroll
+            for (int q = 0; q < SCM; ++q) {
+                if (q < ns) {
+                    const int s = sw + q;
+                    float2 acc[PPT];
+                    gather_bin(s, acc);
+                    if (x < n) {
+#pragma unroll
+                        for (int i = 0; i < PPT; ++i) {
+                            const int y = y0 + i;
+                            if (y < n) {
+                                const size_t idx = (((size_t)kt * S + s) * n + y) * n + x;
+                                float2 g = acc[i];
+                                if (a.accumulate) g = cadd(grad[idx], g);
+                                grad[idx] = g;
+                            }
+                        }
+                    }
+                }
+            }
+        } else if (ns > 0) {
             const float2* const Vin = stepp ? DF(vol[st & 1]) : DF(vol[0]);
             float2* const Vout = DF(vol[(st + 1) & 1]);
             const UpdateArgs u = update_args(a, slice, st, kt, y0, x0, lane, sw, ns);
@@ -592,50 +664,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE))) 
                     }
                     float2 hv, mm[PPT], vv[PPT], tp[PPT], tn[PPT];
                     cs.load_bin(u, s, true, hv, mm, vv, tp, tn);
-                    // the bin's data gradient: parts in plan order, taps
-                    // w00 g[y-oy][x-ox] + w01 g[y-oy][x-ox-1] + w10 g[y-oy-1][x-ox] + w11 g[y-oy-1][x-ox-1]
-                    // Parts go kResTapGroup at a time, every load of a group issued before
-                    // any is used. A group's slots past the last part repeat the last part
-                    // with zero weights, and an inactive part's region was staged as zeros:
-                    // such terms add a zero to the sum, which leaves it unchanged bit for bit
-                    // (it starts at +0 and a sum of finite products is never -0), so the sum
-                    // equals the one over the active parts alone.
                     float2 acc[PPT];
-#pragma unroll
-                    for (int i = 0; i < PPT; ++i) acc[i] = make_float2(0.f, 0.f);
-                    const AS4 ShearEntry* const tb = ktap + (size_t)e0 * S + s;
-                    for (int j0 = 0; j0 < np; j0 += kResTapGroup) {
-                        int tof[kResTapGroup];
-                        float tw[kResTapGroup][4];
-#pragma unroll
-                        for (int p = 0; p < kResTapGroup; ++p) {
-                            const bool real = j0 + p < np;
-                            const int j = real ? j0 + p : np - 1;
-                            const AS4 ShearEntry* sh = tb + j * S;
-                            tof[p] = j * RE + (koy - sh->oy + 1) * RW + (kox - sh->ox + 1);
-                            tw[p][0] = real ? sh->w00 : 0.f;
-                            tw[p][1] = real ? sh->w01 : 0.f;
-                            tw[p][2] = real ? sh->w10 : 0.f;
-                            tw[p][3] = real ? sh->w11 : 0.f;
-                        }
-#pragma unroll
-                        for (int p = 0; p < kResTapGroup; ++p) {
-                            const float2* L = sm + tof[p] + lane;
-                            float2 u0 = L[-RW], u1 = L[-RW - 1];
-#pragma unroll
-                            for (int i = 0; i < PPT; ++i) {
-                                const float2 v0 = L[i * RW], v1 = L[i * RW - 1];
-                                float2 t = acc[i];
-                                t = cfma(tw[p][0], v0, t);
-                                t = cfma(tw[p][1], v1, t);
-                                t = cfma(tw[p][2], u0, t);
-                                t = cfma(tw[p][3], u1, t);
-                                acc[i] = t;
-                                u0 = v0;
-                                u1 = v1;
-                            }
-                        }
-                    }
+                    gather_bin(s, acc);
                     float2 wsn[PPT];
                     cs.next_s_weights(u, s, cw, nw, wsn);
                     cs.update_bin(u, s, cw, wsp, wsn, acc, hv, mm, vv, tp, tn);
@@ -751,24 +781,25 @@ hipError_t launch_update(const KArgs& a, int sc, hipStream_t s) {
 
 // Resident-parts variants: PG parts staged per phase, SE elements per thread covering
 // kResRegion elements of a part's region.
-template <int PPT, int SCM, int EPI>
+template <int MODE, int PPT, int SCM, int EPI>
 static void gather_res_variant(const KArgs& a, int waves, size_t lds, hipStream_t s) {
     const dim3 g(grid_for(a.ntasks)), b(64 * waves);
     // two-row tiles fit five waves per SIMD (at most 102 VGPRs), four-row tiles four
     constexpr int WPE = PPT == 2 ? 5 : 4;
     if (waves == 8)
-        hipLaunchKernelGGL((k_gather_res<PPT, SCM, kResRegion / 512, 4, EPI, 8, WPE>), g, b, lds, s, a);
+        hipLaunchKernelGGL((k_gather_res<MODE, PPT, SCM, kResRegion / 512, 4, EPI, 8, WPE>), g, b, lds, s, a);
     else
-        hipLaunchKernelGGL((k_gather_res<PPT, SCM, kResRegion / 256, 4, EPI, 4, WPE>), g, b, lds, s, a);
+        hipLaunchKernelGGL((k_gather_res<MODE, PPT, SCM, kResRegion / 256, 4, EPI, 4, WPE>), g, b, lds, s, a);
 }
 
-hipError_t launch_gather_res(const KArgs& a, int rows, int sc, int waves, size_t lds, hipStream_t s) {
+hipError_t launch_gather_res(const KArgs& a, int mode, int rows, int sc, int waves, size_t lds, hipStream_t s) {
     if (a.ntasks <= 0) return hipSuccess;
     if (!gath_tiles_ok(rows, sc, true) || !item_waves_ok(waves) || lds < 8 || lds > kResLds) return hipErrorInvalidValue;
-#define RV(R, C)                                                                              \
-    case R * 16 + C:                                                                          \
-        if (a.epi == EPI_ADAM_TV) gather_res_variant<R, C, EPI_ADAM_TV>(a, waves, lds, s);    \
-        else gather_res_variant<R, C, EPI_GENERIC>(a, waves, lds, s);                         \
+#define RV(R, C)                                                                                      \
+    case R * 16 + C:                                                                                  \
+        if (mode == GATHER_STORE) gather_res_variant<GATHER_STORE, R, C, EPI_GENERIC>(a, waves, lds, s); \
+        else if (a.epi == EPI_ADAM_TV) gather_res_variant<GATHER_STEP, R, C, EPI_ADAM_TV>(a, waves, lds, s); \
+        else gather_res_variant<GATHER_STEP, R, C, EPI_GENERIC>(a, waves, lds, s);                       \
         break
     switch (rows * 16 + sc) {
         RV(2, 1); RV(2, 2); RV(2, 4); RV(2, 8);
@@ -777,6 +808,12 @@ hipError_t launch_gather_res(const KArgs& a, int rows, int sc, int waves, size_t
     }
 #undef RV
     return hipGetLastError();
+}
+
+hipError_t launch_gather_lists(const KArgs& a, int mode, const StageLists& L, hipStream_t s) {
+    return L.tiles.gath_res
+               ? launch_gather_res(a, mode, L.tiles.gath_rows, L.tiles.gath_sc, L.tiles.gath_w, L.lds_res, s)
+               : launch_gather(a, mode, L.tiles.gath_rows, L.tiles.gath_sc, L.tiles.gath_w, L.re_gath, s);
 }
 
 hipError_t launch_gather(const KArgs& a, int mode, int rows, int sc, int waves, int re, hipStream_t s) {

@@ -256,7 +256,7 @@ hipError_t dense_adjoint(const DenseStep& ds, hipStream_t s) {
     a.tasks = L.rows; a.ntasks = L.n_rows;
     if ((e = launch_rows(a, 1, L.fft_n, L.lds_rows, s)) != hipSuccess) return e;
     a.tasks = L.gath; a.ntasks = L.n_gath; a.accumulate = 0;
-    return launch_gather(a, GATHER_STORE, L.tiles.gath_rows, L.tiles.gath_sc, L.tiles.gath_w, L.re_gath, s);
+    return launch_gather_lists(a, GATHER_STORE, L, s);
 }
 
 double host_objective(const std::vector<float>& lp, const std::vector<double>& rp, double* data) {

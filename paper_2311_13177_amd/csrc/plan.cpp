@@ -195,12 +195,19 @@ static int pow2_ceil(int v) {
 }
 
 Tiles heuristic_tiles(const vp_plan* p) {
+    // Eight-wave items over tall tiles, the shapes the tuner mostly picks on this device:
+    // a projection item projects 8 * proj_gw parts of one knot over 8 rows (4 below n =
+    // 192); a gather item covers 8 * gath_sc bins (all of S up to 64) over 4 rows, with
+    // every part of its knot resident in LDS (the plan falls back to parts staged a few at
+    // a time where they do not fit).
     Tiles t;
-    // every wave of a projection group busy; enough gather items to fill the chip
-    t.proj_gw = std::min(8, pow2_ceil(ceil_div(std::max(1, p->max_knot_parts), 4)));
-    t.proj_rows = 2;
-    t.gath_rows = 2;
-    t.gath_sc = std::min(8, pow2_ceil(ceil_div(p->S, 4)));
+    t.proj_w = 8;
+    t.proj_rows = p->n >= 192 ? 8 : 4;
+    t.proj_gw = p->max_knot_parts > 8 ? 2 : 1;
+    t.gath_w = 8;
+    t.gath_rows = 4;
+    t.gath_sc = std::min(8, pow2_ceil(ceil_div(p->S, 8)));
+    t.gath_res = 1;
     return t;
 }
 
@@ -524,6 +531,14 @@ static vp_status plan_create(const vp_geometry* g, bool per_blade, vp_plan** out
         const Layout* L = nullptr;
         vp_status st = plan_layout(p.get(), p->base_tiles, &L);
         if (st != VP_OK) {
+            // the knot's parts do not fit at once: stage them a few at a time
+            clear_error();
+            p->base_tiles.gath_res = 0;
+            p->base_tiles.gath_sc = std::min(p->base_tiles.gath_sc, 16 / p->base_tiles.gath_rows);
+            st = plan_layout(p.get(), p->base_tiles, &L);
+        }
+        if (st != VP_OK) {
+            clear_error();
             p->base_tiles = Tiles{};
             st = plan_layout(p.get(), p->base_tiles, &L);
         }

@@ -18,9 +18,8 @@ hipError_t launch_rows(const KArgs& a, int dir, int n, size_t lds, hipStream_t s
 hipError_t launch_cols(const KArgs& a, int n, size_t lds, hipStream_t s);
 // waves: 4 or 8 per work item (the layout's gath_w: its bin chunks hold waves * sc bins)
 hipError_t launch_gather(const KArgs& a, int mode, int rows, int sc, int waves, int re, hipStream_t s);
-// The fused step's resident-parts gather (GATHER_STEP only): lds bytes of the largest
-// knot's parts (Layout::lds_res).
-hipError_t launch_gather_res(const KArgs& a, int rows, int sc, int waves, size_t lds, hipStream_t s);
+// The resident-parts gather: lds bytes of the largest knot's parts (Layout::lds_res).
+hipError_t launch_gather_res(const KArgs& a, int mode, int rows, int sc, int waves, size_t lds, hipStream_t s);
 hipError_t launch_update(const KArgs& a, int sc, hipStream_t s);
 hipError_t launch_tv_grad(const KArgs& a, hipStream_t s);
 hipError_t launch_reg_value(const KArgs& a, hipStream_t s);
@@ -50,6 +49,8 @@ struct StageLists {
 };
 
 StageLists plan_lists(const vp_plan* p, const DeviceTables* t, const Layout* L, const DeviceLayout* dl);
+// The gather of a step's layout (resident-parts or staged a few parts at a time).
+hipError_t launch_gather_lists(const KArgs& a, int mode, const StageLists& L, hipStream_t s);
 // Tile shape for a plan under options: explicit tiles from the options, else the tuned
 // shape recorded for this plan's sizes on the device (tuning first when the options ask
 // for it and none is recorded), else the plan's heuristic shape.

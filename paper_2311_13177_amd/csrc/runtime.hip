@@ -223,12 +223,10 @@ void launch_step(const KArgs& base, const StageLists& L, hipStream_t s, hipError
     a.snap = 1;
     if (L.tiles.upd_sc == 0) {
         a.advance = 1;
-        e = L.tiles.gath_res
-                ? launch_gather_res(a, L.tiles.gath_rows, L.tiles.gath_sc, L.tiles.gath_w, L.lds_res, s)
-                : launch_gather(a, GATHER_STEP, L.tiles.gath_rows, L.tiles.gath_sc, L.tiles.gath_w, L.re_gath, s);
+        e = launch_gather_lists(a, GATHER_STEP, L, s);
     } else {
         a.accumulate = 0;
-        e = launch_gather(a, GATHER_STORE, L.tiles.gath_rows, L.tiles.gath_sc, L.tiles.gath_w, L.re_gath, s);
+        e = launch_gather_lists(a, GATHER_STORE, L, s);
         a.tasks = L.upd; a.ntasks = L.n_upd; a.advance = 1;
         if (e == hipSuccess) e = launch_update(a, L.tiles.upd_sc, s);
     }
@@ -348,7 +346,7 @@ extern "C" vp_status vp_adjoint(const vp_plan* p, const vp_c64* d_kres, vp_c64* 
     a.tasks = L.rows; a.ntasks = L.n_rows;
     if ((e = launch_rows(a, 1, L.fft_n, L.lds_rows, sc.s)) != hipSuccess) return hip_status(e, "vp_adjoint rows");
     a.tasks = L.gath; a.ntasks = L.n_gath;
-    if ((e = launch_gather(a, GATHER_STORE, L.tiles.gath_rows, L.tiles.gath_sc, L.tiles.gath_w, L.re_gath, sc.s)) != hipSuccess)
+    if ((e = launch_gather_lists(a, GATHER_STORE, L, sc.s)) != hipSuccess)
         return hip_status(e, "vp_adjoint gather");
     return VP_OK;
 }
@@ -641,7 +639,7 @@ extern "C" vp_status vp_nu_adjoint(const vp_plan* p, const vp_c64* d_samples, vp
     a.accumulate = accumulate != 0;
     const StageLists L = plan_lists(p, sc.t, sc.lay, sc.dl);
     a.tasks = L.gath; a.ntasks = L.n_gath;
-    if ((e = launch_gather(a, GATHER_STORE, L.tiles.gath_rows, L.tiles.gath_sc, L.tiles.gath_w, L.re_gath, sc.s)) != hipSuccess)
+    if ((e = launch_gather_lists(a, GATHER_STORE, L, sc.s)) != hipSuccess)
         return hip_status(e, "vp_nu_adjoint gather");
     return VP_OK;
 }
@@ -738,12 +736,9 @@ struct vp_nu_session {
         if (r == hipSuccess) {
             if (L.tiles.upd_sc == 0) {
                 a.advance = 1;
-                r = L.tiles.gath_res
-                        ? launch_gather_res(a, L.tiles.gath_rows, L.tiles.gath_sc, L.tiles.gath_w, L.lds_res, str)
-                        : launch_gather(a, GATHER_STEP, L.tiles.gath_rows, L.tiles.gath_sc, L.tiles.gath_w, L.re_gath,
-                                        str);
+                r = launch_gather_lists(a, GATHER_STEP, L, str);
             } else {
-                r = launch_gather(a, GATHER_STORE, L.tiles.gath_rows, L.tiles.gath_sc, L.tiles.gath_w, L.re_gath, str);
+                r = launch_gather_lists(a, GATHER_STORE, L, str);
                 a.tasks = L.upd; a.ntasks = L.n_upd; a.advance = 1;
                 if (r == hipSuccess) r = launch_update(a, L.tiles.upd_sc, str);
             }
@@ -968,7 +963,11 @@ extern "C" vp_status vp_step(const vp_plan* p, const vp_options* o, const vp_c64
     if ((st = sc.begin(false)) != VP_OK) return st;
     // the update pass of the current shape, or of four bins per wave where the shape fuses it
     Tiles tl = sc.lay->tiles;
-    if (tl.upd_sc == 0) tl.upd_sc = 4;
+    if (tl.upd_sc == 0) {
+        tl.upd_sc = 4;
+        tl.gath_res = 0;
+        tl.gath_sc = std::min(tl.gath_sc, 16 / tl.gath_rows);
+    }
     const Layout* lay = nullptr;
     const DeviceLayout* dl = nullptr;
     if ((st = plan_layout(p, tl, &lay)) != VP_OK || (st = device_layout(p, sc.t, lay, &dl)) != VP_OK) return st;

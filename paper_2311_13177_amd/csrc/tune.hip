@@ -105,7 +105,8 @@ vp_status tune_plan(const vp_plan* p, const vp_options* o, Tiles* out) {
     }
     vp_options so = *o;
     so.tiles = vp_tiles{p->base_tiles.proj_rows, p->base_tiles.proj_gw, p->base_tiles.gath_rows,
-                        p->base_tiles.gath_sc, 0, p->base_tiles.gath_w, p->base_tiles.proj_w, 0};
+                        p->base_tiles.gath_sc, 0, p->base_tiles.gath_w, p->base_tiles.proj_w,
+                        p->base_tiles.gath_res};
     so.autotune = 0;
     vp_session* raw = nullptr;
     st = session_alloc(p, &so, zeros.data(), nullptr, nullptr, &raw);
@@ -191,7 +192,7 @@ vp_status tune_plan(const vp_plan* p, const vp_options* o, Tiles* out) {
                         st = time_launches(
                             s->stream, kReps,
                             [&] {
-                                return res ? launch_gather_res(a, rows, sc, waves, L->lds_res, s->stream)
+                                return res ? launch_gather_res(a, mode, rows, sc, waves, L->lds_res, s->stream)
                                            : launch_gather(a, mode, rows, sc, waves, L->re_gath, s->stream);
                             },
                             &ms);
@@ -213,6 +214,8 @@ vp_status tune_plan(const vp_plan* p, const vp_options* o, Tiles* out) {
     for (int usc = 2; usc <= 8; usc *= 2) {
         Tiles t = p->base_tiles;
         t.upd_sc = usc;
+        t.gath_res = 0;
+        t.gath_sc = std::min(t.gath_sc, 16 / t.gath_rows);
         const Layout* L = nullptr;
         const DeviceLayout* dl = nullptr;
         if (plan_layout(p, t, &L) != VP_OK) {
