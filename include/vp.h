@@ -115,9 +115,9 @@ enum { VP_SCHED_ALL_BLADES = 0, VP_SCHED_CYCLIC = 1, VP_SCHED_RANDOM = 2 };
  * volume starts at zero unless an initial volume is given. split_bin < 0 means S/2. */
 /* Tile shape of the projection, gather and update kernels: how the work is cut
  * into work items, never what is computed (every shape gives the same results bit
- * for bit). proj_rows: rows of a projection tile, in {1, 2, 4, 8}; proj_parts:
+ * for bit). proj_rows: rows of a projection tile, in {1, 2, 4, 8, 12}; proj_parts:
  * blade parts per wave of a projection item, in {1, 2, 4, 8}, with proj_rows *
- * proj_parts <= 16; gath_rows: rows of a gather tile, in {2, 4}; gath_bins:
+ * proj_parts <= 16 (12 rows: one part); gath_rows: rows of a gather tile, in {2, 4}; gath_bins:
  * spectral bins per wave of a gather item, in {1, 2, 4, 8}, with gath_rows *
  * gath_bins <= 16 unless gath_resident is 1; upd_bins: 0 runs the regulariser and optimiser update inside
  * the gather kernel, 2, 4 or 8 runs it as a separate pass (that many bins per

@@ -166,7 +166,7 @@ hipError_t launch_project(const KArgs& a, int rows, int gw, int waves, int re, h
         PV(1, 1); PV(1, 2); PV(1, 4); PV(1, 8);
         PV(2, 1); PV(2, 2); PV(2, 4); PV(2, 8);
         PV(4, 1); PV(4, 2); PV(4, 4);
-        PV(8, 1); PV(8, 2);
+        PV(8, 1); PV(8, 2); PV(12, 1);
         default: return hipErrorInvalidValue;
     }
 #undef PV

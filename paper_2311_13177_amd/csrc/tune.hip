@@ -122,7 +122,7 @@ vp_status tune_plan(const vp_plan* p, const vp_options* o, Tiles* out) {
     for (int waves = 4; waves <= 8; waves += 4) {
         if (waves == 8 && p->max_knot_parts <= 4) break;
         const int gw_cap = std::min(8, pow2_at_least((std::max(1, p->max_knot_parts) + waves - 1) / waves));
-        for (int rows = 1; rows <= 8; rows *= 2) {
+        for (int rows : {1, 2, 4, 8, 12}) {
             for (int gw = 1; gw <= gw_cap; gw *= 2) {
                 if (!proj_tiles_ok(rows, gw)) continue;
                 Tiles t = p->base_tiles;

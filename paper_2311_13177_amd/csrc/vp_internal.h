@@ -32,8 +32,10 @@ constexpr int kThreads = 256;
 constexpr int kTileW = 64;
 constexpr int kXcds = 8;  // accelerator complex dies, each with its own L2
 __host__ __device__ constexpr bool pow2_le(int v, int hi) { return v >= 1 && v <= hi && (v & (v - 1)) == 0; }
+// (Twelve-row projection tiles too, one part per wave: at n = 192 they make exactly one
+// round of items on the chip.)
 __host__ __device__ constexpr bool proj_tiles_ok(int rows, int gw) {
-    return pow2_le(rows, 8) && pow2_le(gw, 8) && rows * gw <= 16;
+    return (pow2_le(rows, 8) || (rows == 12 && gw == 1)) && pow2_le(gw, 8) && rows * gw <= 16;
 }
 // (The resident-parts gather keeps one bin's sums at a time, so it also takes 4 x 8.)
 __host__ __device__ constexpr bool gath_tiles_ok(int rows, int sc, bool resident = false) {

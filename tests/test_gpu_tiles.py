@@ -25,6 +25,8 @@ SHAPES = [
     # every part of a knot resident in LDS, each bin gathered and updated in turn
     (2, 1, 2, 4, 0, 4, 4, 1), (4, 2, 4, 2, 0, 8, 4, 1), (1, 1, 2, 8, 0, 8, 8, 1), (2, 2, 4, 1, 0, 4, 4, 1),
     (8, 1, 2, 1, 0, 8, 4, 1),
+    # twelve-row projection tiles
+    (12, 1, 2, 2, 0, 4, 8), (12, 1, 4, 8, 0, 8, 4, 1),
 ]
 
 CASES = {
