@@ -43,6 +43,9 @@ def parse_args(argv=None):
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--config", default="dynamic_192", choices=["static_64", "static_256", "dynamic_192"])
+    ap.add_argument("--tiles", default=None,
+                    help="tile shape of the headline workload, comma-separated vp_tiles fields, instead of "
+                         "autotuning (e.g. to profile one variant in several passes)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="approximate CPU oracle time budget")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain-loop leg")
@@ -538,9 +541,18 @@ def kernel_digest(kernel=None):
     return h.hexdigest()[:16]
 
 
-def counters_for(workload, kernel_name):
+TILE_FIELDS = ("proj_rows", "proj_parts", "gath_rows", "gath_bins", "upd_bins", "gath_waves", "proj_waves",
+               "gath_resident")
+# The tile fields that select a kernel family's variant (the DFT passes have none).
+FAMILY_TILES = {"k_gather": ("gath_rows", "gath_bins", "upd_bins", "gath_waves", "gath_resident"),
+                "k_gather_res": ("gath_rows", "gath_bins", "upd_bins", "gath_waves", "gath_resident"),
+                "k_project": ("proj_rows", "proj_parts", "proj_waves")}
+
+
+def counters_for(workload, kernel_name, tiles=None):
     """HBM bytes per launch (scaled FETCH_SIZE + WRITE_SIZE) from the committed counter
-    summary of this workload, or None once the kernel's sources have changed since."""
+    summary of this workload, or None once the kernel's sources have changed since, or
+    when the counters were taken on another variant (tile shape) than the one timed."""
     path = os.path.join(ROOT, "profiles", "counters.json")
     if not os.path.exists(path):
         return None
@@ -549,6 +561,12 @@ def counters_for(workload, kernel_name):
     entry = data.get(f"{workload}/{kernel_name}")
     if not entry or entry.get("kernels_sha") != kernel_digest(kernel_name):
         return None
+    fam = kernel_name.split("<")[0]
+    if tiles is not None and fam in FAMILY_TILES:
+        now = dict(zip(TILE_FIELDS, tiles))
+        then = entry.get("tiles") or {}
+        if any(then.get(f) != now.get(f) for f in FAMILY_TILES[fam]):
+            return None
     return entry.get("bytes_per_launch")
 
 
@@ -583,18 +601,23 @@ def quality(case, plan, B, y, rec):
             "steps": case.n_steps}
 
 
-def measure_workload(case, B, steps, warmup):
-    """Autotuned steps of one workload: throughput, per-stage times and the roofline of
-    the dominant stage's kernel."""
+def measure_workload(case, B, steps, warmup, tiles=None):
+    """Autotuned steps of one workload (or steps of the tile shape given): throughput,
+    per-stage times and the roofline of the dominant stage's kernel."""
     import torch
 
     plan = B.Plan.from_geometry(case.geometry())
     y = gpu_measurements(case, plan, B)
-    opts = B.vp_options_default(n_steps=case.n_steps, tv_weight=case.tv_weight, lr=case.lr, device=0,
-                                autotune=1)
-    # tile shapes picked by the autotuner (recorded for this plan's sizes; not timed below)
     t0 = time.perf_counter()
-    tiles = plan.tune(opts)
+    if tiles is None:
+        opts = B.vp_options_default(n_steps=case.n_steps, tv_weight=case.tv_weight, lr=case.lr, device=0,
+                                    autotune=1)
+        # tile shapes picked by the autotuner (recorded for this plan's sizes; not timed below)
+        tiles = plan.tune(opts)
+    else:
+        opts = B.vp_options_default(n_steps=case.n_steps, tv_weight=case.tv_weight, lr=case.lr, device=0,
+                                    tiles=tiles)
+        tiles = plan.tiles(opts)
     tune_s = time.perf_counter() - t0
 
     # whole reconstruction wall time (upload, n_steps graph-replayed steps, objective, download)
@@ -633,7 +656,7 @@ def measure_workload(case, B, steps, warmup):
         ach = bytes_l / dur_s / 1e9
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4)}
-    roof["traffic"] = counters_for(case.name, kernel_names[dom])
+    roof["traffic"] = counters_for(case.name, kernel_names[dom], tiles)
     roof["kernel"] = kernel_names[dom]
     roof["kernel_ms"] = round(stages[dom], 5)
     roof["algorithmic_bytes_per_launch"] = bytes_l
@@ -644,9 +667,7 @@ def measure_workload(case, B, steps, warmup):
         "config": {"workload": case.name, "n": case.n, "n_spec": case.n_spec, "n_time": case.n_time,
                    "n_blades": case.n_blades, "lines": int(case.lines[0]), "steps_per_recon": case.n_steps,
                    "optimizer": "adam", "schedule": "all blades per step",
-                   "tiles": {"proj_rows": tiles[0], "proj_parts": tiles[1], "gath_rows": tiles[2],
-                             "gath_bins": tiles[3], "upd_bins": tiles[4], "gath_waves": tiles[5],
-                             "proj_waves": tiles[6], "gath_resident": tiles[7]},
+                   "tiles": dict(zip(TILE_FIELDS, tiles)),
                    "tune_s": round(tune_s, 4)},
         "recon_wall_s": round(recon_s, 4),
         "stage_ms": {k: round(v, 5) for k, v in stages.items()},
@@ -674,7 +695,8 @@ def main(argv=None):
     torch.cuda.set_device(0)
     case = configs.CONFIGS[args.config]()
     progress(f"headline {case.name}")
-    m = measure_workload(case, B, args.steps, args.warmup)
+    forced = None if args.tiles is None else tuple(int(x) for x in args.tiles.split(","))
+    m = measure_workload(case, B, args.steps, args.warmup, forced)
 
     out = {
         "metric": METRIC,
