@@ -128,7 +128,7 @@ enum { VP_SCHED_ALL_BLADES = 0, VP_SCHED_CYCLIC = 1, VP_SCHED_RANDOM = 2 };
  * volume regions, so an item projects proj_waves * proj_parts blade parts;
  * gath_resident: 1 stages every blade part feeding a knot at once and interleaves
  * each bin's gather with that bin's update (needs upd_bins 0, at most 32 parts per
- * knot, staged regions of at most 1024 elements and 64 KiB of LDS per item;
+ * knot, staged regions of at most 2048 elements and 64 KiB of LDS per item;
  * VP_ERR_UNSUPPORTED otherwise), 0 stages the parts a few at a time. A tile is 64
  * columns wide. All fields 0: the plan's own (or autotuned) shape. */
 typedef struct {

@@ -49,7 +49,7 @@ __host__ __device__ constexpr bool upd_tiles_ok(int sc) { return sc == 0 || sc =
 // Resident-parts gather (tile field gath_res): every blade part of a knot is staged at
 // once. A layout may take it where each knot's region is at most kResRegion elements, it
 // has at most kResMaxParts parts, and all of them fit kResLds bytes of LDS.
-constexpr int kResRegion = 1024;
+constexpr int kResRegion = 2048;
 constexpr int kResMaxParts = 32;
 constexpr size_t kResLds = 65536;
 // Staged region elements per thread (register prefetch depth of the LDS staging).
