@@ -1,7 +1,9 @@
 """Write the converged-image fixtures of the full-size workloads from the FP64 oracle.
 
-For the static 256^2 workload (S 32, 12 blades, 500 Adam steps) and the dynamic 192^2
-workload (S 32, T 16, 32 blades, 800 Adam steps) this runs the oracle's fit of
+For the static 256^2 workload (S 32, 12 blades, 500 Adam steps), the dynamic 192^2
+workload (S 32, T 16, 32 blades, 800 Adam steps), a slice of the 64-slice batch or a
+request of the served stream (each with its own steps and settings) this runs the
+oracle's fit of
 Section 4.3 from zero on the seeded measurements and stores the rendered complex
 image (Section 4.3, the render at phi = 0) and the final objective:
 
@@ -89,9 +91,19 @@ def max_rel(a, b) -> float:
     return float(np.max(np.abs(a - b)) / max(float(np.max(np.abs(b))), 1e-300))
 
 
+def case_for(name: str):
+    """A named workload, a slice of the 64-slice batch (batch_<j>) or a request of the
+    served stream (serve_<i>)."""
+    if name.startswith("batch_"):
+        return configs.batch_slice(int(name[6:]))
+    if name.startswith("serve_"):
+        return configs.serving_request(int(name[6:]))
+    return configs.CONFIGS[name]()
+
+
 def _fit_worker(args):
     name, log2 = args
-    case = configs.CONFIGS[name]()
+    case = case_for(name)
     y = O.simulate_measurements(case)
     label = name
     if log2 is not None:
@@ -105,12 +117,12 @@ def _fit_worker(args):
 def main() -> None:
     _keep_freed_memory()
     ap = argparse.ArgumentParser()
-    ap.add_argument("workload", choices=["static_256", "dynamic_192", "static_64"])
+    ap.add_argument("workload", help="static_64, static_256, dynamic_192, batch_<j> or serve_<i>")
     ap.add_argument("--spread", action="store_true",
                     help="also fit the perturbed measurements (in a second process) and report the spread")
     args = ap.parse_args()
     name = args.workload
-    case = configs.CONFIGS[name]()
+    case = case_for(name)
     jobs = [(name, None)] + ([(name, k) for k in PERTURB_LOG2] if args.spread else [])
     if len(jobs) == 1:
         results = [_fit_worker(jobs[0])]

@@ -125,3 +125,45 @@ def test_resident_batch_in_parts_equals_solo(gpu_lib):
         if o.n_steps <= 9:
             assert _same(r, s)
     batch.close()
+
+
+def _workload(B, case, **overrides):
+    plan = B.Plan.from_geometry(case.geometry())
+    y = O.simulate_measurements(case)
+    opts = B.vp_options_default(n_steps=case.n_steps, tv_weight=case.tv_weight, lr=case.lr, **overrides)
+    return plan, y, opts
+
+
+def test_batched_slice_matches_the_oracle_fit(gpu_lib):
+    """Slice 3 of the 64-slice batch (128^2, S 16, 16 blades, 200 Adam steps), fitted in a
+    batch beside slice 6, against the FP64 oracle's fit of that slice stored by
+    tests/golden/make_converged.py (render and objective, at twice the oracle's own spread
+    or 1e-3)."""
+    from parity import check_converged
+    from paper_2311_13177_amd import binding as B
+
+    probs = [_workload(B, configs.batch_slice(j), autotune=1) for j in (3, 6)]
+    got = B.vp_batch_reconstruct([p for p, _, _ in probs], [y for _, y, _ in probs], [o for _, _, o in probs])
+    assert got[0]["status"] == 0 and got[0]["steps_done"] == 200
+    r = check_converged("batch_3", got[0]["proj"], got[0]["final_loss"])
+    print("batch_3", r)
+
+
+def test_served_requests_match_the_oracle_fits(gpu_lib):
+    """Two requests of the served stream at their own sizes and full step counts, a static
+    one (request 17: 128^2, S 16, 16 blades, 200 steps) and a dynamic one (request 4:
+    128^2, S 16, T 8, 24 blades, 800 steps), served together with a third request, against
+    the FP64 oracle's fits stored by tests/golden/make_converged.py."""
+    from parity import check_converged
+    from paper_2311_13177_amd import binding as B
+
+    names = {17: "serve_17", 4: "serve_4"}
+    probs = {i: _workload(B, configs.serving_request(i)) for i in (17, 4, 9)}
+    srv = B.Server(hbm_budget=8 << 30, max_slots=4)
+    ids = {i: srv.submit(p, y, o) for i, (p, y, o) in probs.items()}
+    got = {i: srv.wait(rid, volume=False) for i, rid in ids.items()}
+    srv.close()
+    for i, name in names.items():
+        assert got[i]["status"] == 0 and got[i]["steps_done"] == probs[i][2].n_steps
+        r = check_converged(name, got[i]["proj"], got[i]["final_loss"])
+        print(name, r)

@@ -18,34 +18,12 @@ import numpy as np
 import pytest
 
 import oracle as O
-from parity import assert_close, max_rel, rel
+from parity import GOLDEN, RECON_TOL, SPREAD_LOG2, adam_tol, assert_close, max_rel, rel, stored_spread
 from synth import configs
 
 pytestmark = pytest.mark.gpu
 
 FWD_TOL = 1e-4
-RECON_TOL = 1e-3
-GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
-SPREAD_LOG2 = -20     # perturbation of y that measures the oracle's own spread
-SPREAD_FACTOR = 2.0   # Adam tolerance: this many times the spread (at least RECON_TOL)
-
-
-def adam_tol(spread: float) -> float:
-    return max(RECON_TOL, SPREAD_FACTOR * spread)
-
-
-def stored_spread(name: str, step: int) -> tuple[float, float, float]:
-    """The oracle's spread (rel L2 of proj, max element of proj, objective) at a
-    checkpoint of a full-size workload, from the stored 2^-20 perturbation run."""
-    import json
-
-    path = os.path.join(GOLDEN, f"converged_{name}_spread.json")
-    if not os.path.exists(path):
-        pytest.skip(f"{path} not generated (tests/golden/make_converged.py {name} --spread)")
-    with open(path) as fh:
-        d = json.load(fh)
-    k, c = SPREAD_LOG2, str(step)
-    return (d[f"rel_l2_2^{k}"][c], d[f"max_elem_2^{k}"][c], d[f"objective_rel_2^{k}"][c])
 
 
 def _t(x):
