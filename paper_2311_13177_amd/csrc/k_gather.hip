@@ -780,26 +780,34 @@ hipError_t launch_update(const KArgs& a, int sc, hipStream_t s) {
 }
 
 // Resident-parts variants: PG parts staged per phase, SE elements per thread covering
-// kResRegion elements of a part's region.
+// the largest region re (at most kResRegion elements): the steps take half the elements
+// per thread (fewer staging registers) where the regions are at most half as large.
 template <int MODE, int PPT, int SCM, int EPI>
-static void gather_res_variant(const KArgs& a, int waves, size_t lds, hipStream_t s) {
+static void gather_res_variant(const KArgs& a, int waves, int re, size_t lds, hipStream_t s) {
     const dim3 g(grid_for(a.ntasks)), b(64 * waves);
     // two-row tiles fit five waves per SIMD (at most 102 VGPRs), four-row tiles four
     constexpr int WPE = PPT == 2 ? 5 : 4;
-    if (waves == 8)
-        hipLaunchKernelGGL((k_gather_res<MODE, PPT, SCM, kResRegion / 512, 4, EPI, 8, WPE>), g, b, lds, s, a);
-    else
-        hipLaunchKernelGGL((k_gather_res<MODE, PPT, SCM, kResRegion / 256, 4, EPI, 4, WPE>), g, b, lds, s, a);
+    const bool half = MODE == GATHER_STEP && re <= kResRegion / 2;
+    if (waves == 8) {
+        if (half) hipLaunchKernelGGL((k_gather_res<MODE, PPT, SCM, kResRegion / 1024, 4, EPI, 8, WPE>), g, b, lds, s, a);
+        else hipLaunchKernelGGL((k_gather_res<MODE, PPT, SCM, kResRegion / 512, 4, EPI, 8, WPE>), g, b, lds, s, a);
+    } else {
+        if (half) hipLaunchKernelGGL((k_gather_res<MODE, PPT, SCM, kResRegion / 512, 4, EPI, 4, WPE>), g, b, lds, s, a);
+        else hipLaunchKernelGGL((k_gather_res<MODE, PPT, SCM, kResRegion / 256, 4, EPI, 4, WPE>), g, b, lds, s, a);
+    }
 }
 
-hipError_t launch_gather_res(const KArgs& a, int mode, int rows, int sc, int waves, size_t lds, hipStream_t s) {
+hipError_t launch_gather_res(const KArgs& a, int mode, int rows, int sc, int waves, int re, size_t lds,
+                             hipStream_t s) {
     if (a.ntasks <= 0) return hipSuccess;
-    if (!gath_tiles_ok(rows, sc, true) || !item_waves_ok(waves) || lds < 8 || lds > kResLds) return hipErrorInvalidValue;
-#define RV(R, C)                                                                                      \
-    case R * 16 + C:                                                                                  \
-        if (mode == GATHER_STORE) gather_res_variant<GATHER_STORE, R, C, EPI_GENERIC>(a, waves, lds, s); \
-        else if (a.epi == EPI_ADAM_TV) gather_res_variant<GATHER_STEP, R, C, EPI_ADAM_TV>(a, waves, lds, s); \
-        else gather_res_variant<GATHER_STEP, R, C, EPI_GENERIC>(a, waves, lds, s);                       \
+    if (!gath_tiles_ok(rows, sc, true) || !item_waves_ok(waves) || re < 1 || re > kResRegion || lds < 8 ||
+        lds > kResLds)
+        return hipErrorInvalidValue;
+#define RV(R, C)                                                                                          \
+    case R * 16 + C:                                                                                      \
+        if (mode == GATHER_STORE) gather_res_variant<GATHER_STORE, R, C, EPI_GENERIC>(a, waves, re, lds, s); \
+        else if (a.epi == EPI_ADAM_TV) gather_res_variant<GATHER_STEP, R, C, EPI_ADAM_TV>(a, waves, re, lds, s); \
+        else gather_res_variant<GATHER_STEP, R, C, EPI_GENERIC>(a, waves, re, lds, s);                       \
         break
     switch (rows * 16 + sc) {
         RV(2, 1); RV(2, 2); RV(2, 4); RV(2, 8);
@@ -812,7 +820,7 @@ hipError_t launch_gather_res(const KArgs& a, int mode, int rows, int sc, int wav
 
 hipError_t launch_gather_lists(const KArgs& a, int mode, const StageLists& L, hipStream_t s) {
     return L.tiles.gath_res
-               ? launch_gather_res(a, mode, L.tiles.gath_rows, L.tiles.gath_sc, L.tiles.gath_w, L.lds_res, s)
+               ? launch_gather_res(a, mode, L.tiles.gath_rows, L.tiles.gath_sc, L.tiles.gath_w, L.re_gath, L.lds_res, s)
                : launch_gather(a, mode, L.tiles.gath_rows, L.tiles.gath_sc, L.tiles.gath_w, L.re_gath, s);
 }
 

@@ -19,7 +19,8 @@ hipError_t launch_cols(const KArgs& a, int n, size_t lds, hipStream_t s);
 // waves: 4 or 8 per work item (the layout's gath_w: its bin chunks hold waves * sc bins)
 hipError_t launch_gather(const KArgs& a, int mode, int rows, int sc, int waves, int re, hipStream_t s);
 // The resident-parts gather: lds bytes of the largest knot's parts (Layout::lds_res).
-hipError_t launch_gather_res(const KArgs& a, int mode, int rows, int sc, int waves, size_t lds, hipStream_t s);
+// re: largest staged region (elements) of the layout (re_gath).
+hipError_t launch_gather_res(const KArgs& a, int mode, int rows, int sc, int waves, int re, size_t lds, hipStream_t s);
 hipError_t launch_update(const KArgs& a, int sc, hipStream_t s);
 hipError_t launch_tv_grad(const KArgs& a, hipStream_t s);
 hipError_t launch_reg_value(const KArgs& a, hipStream_t s);

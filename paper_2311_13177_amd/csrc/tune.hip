@@ -192,7 +192,7 @@ vp_status tune_plan(const vp_plan* p, const vp_options* o, Tiles* out) {
                         st = time_launches(
                             s->stream, kReps,
                             [&] {
-                                return res ? launch_gather_res(a, mode, rows, sc, waves, L->lds_res, s->stream)
+                                return res ? launch_gather_res(a, mode, rows, sc, waves, L->re_gath, L->lds_res, s->stream)
                                            : launch_gather(a, mode, rows, sc, waves, L->re_gath, s->stream);
                             },
                             &ms);
