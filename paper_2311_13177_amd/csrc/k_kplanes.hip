@@ -121,13 +121,8 @@ __global__ __launch_bounds__(kThreads) void k_kp_prod(const KPDesc d) {
 // vol[b][s][y][x] = sum_c sum_f Z[c][y][x][f] XA[c][b][s][x][f] Yf[c][b][s][y][f]
 constexpr int kDecBins = 4;
 
-// Lane l's complex value, read by every lane (v_readlane: a wave-uniform value in SGPRs,
-// no memory access). Values that are the same for a whole wave are loaded spread over its
-// lanes, one vector load for up to 64 of them, and read back this way.
-__device__ __forceinline__ float2 lane_c(float2 v, int l) {
-    return make_float2(__builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v.x), l)),
-                       __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v.y), l)));
-}
+// Values that are the same for a whole wave are loaded spread over its lanes, one vector
+// load for up to 64 of them, and read back with lane_f2.
 constexpr int kDecRows = 4;
 
 // A wave task is (blade, kDecBins bins, kDecRows rows, 64 columns): its XA values (per
@@ -195,7 +190,7 @@ __global__ __launch_bounds__(kThreads) void k_kp_decode(const KPDesc d) {
 #pragma unroll
                         for (int f = 0; f < F; ++f) {
                             const int ei = ((r * kKpMaxScales + c) * kDecBins + k) * F + f;
-                            v[r][k] = cmad(cmul(z[f], xa[k][f]), lane_c(yl[ei / 64], ei % 64), v[r][k]);
+                            v[r][k] = cmad(cmul(z[f], xa[k][f]), lane_f2(yl[ei / 64], ei % 64), v[r][k]);
                         }
                     }
                 }
@@ -276,7 +271,7 @@ __global__ __launch_bounds__(kThreads) void k_kp_grad_z(const KPDesc d) {
                                 if (c < d.ns) {
 #pragma unroll
                                     for (int f = 0; f < F; ++f)
-                                        acc[r][c][f] = cjmad(cmul(xa[c][f], lane_c(yl, u * NYB + (r * kKpMaxScales + c) * F + f)),
+                                        acc[r][c][f] = cjmad(cmul(xa[c][f], lane_f2(yl, u * NYB + (r * kKpMaxScales + c) * F + f)),
                                                              g, acc[r][c][f]);
                                 }
                             }
@@ -367,7 +362,7 @@ __global__ __launch_bounds__(kThreads) void k_kp_grad_x(const KPDesc d) {
                                 const float2 g = d.G[(long long)(bs0 + j) * nn + (long long)y * n + xs];
 #pragma unroll
                                 for (int f = 0; f < F; ++f)
-                                    acc[j][f] = cjmad(cmul(z[f], lane_c(yl[j], t * F + f)), g, acc[j][f]);
+                                    acc[j][f] = cjmad(cmul(z[f], lane_f2(yl[j], t * F + f)), g, acc[j][f]);
                             }
                         }
                     }

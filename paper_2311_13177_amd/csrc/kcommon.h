@@ -138,6 +138,21 @@ __device__ __forceinline__ float2 buffer_c64(__amdgpu_buffer_rsrc_t r, int idx) 
 
 // P planes (images of the same size, same region) are staged per phase; plane p of a
 // phase occupies buf[p * re, (p + 1) * re). A null plane pointer stages zeros.
+// Whole-wave lane shifts by one (DPP wave_shr / wave_shl): lane i receives lane i - 1
+// (shfl_up1) or lane i + 1 (shfl_down1); the lane without a source reads zero.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float2 shfl_up1(float2 v) { return make_float2(dpp_f<0x138>(v.x), dpp_f<0x138>(v.y)); }
+__device__ __forceinline__ float2 shfl_down1(float2 v) { return make_float2(dpp_f<0x130>(v.x), dpp_f<0x130>(v.y)); }
+// Lane l's value of v, for the whole wave (v_readlane: a wave-uniform value in SGPRs, no
+// memory access).
+__device__ __forceinline__ float2 lane_f2(float2 v, int l) {
+    return make_float2(__builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v.x), l)),
+                       __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v.y), l)));
+}
+
 template <int SE, int P, int NT = kThreads>
 struct Stager {
     int off[SE];
