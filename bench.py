@@ -519,7 +519,8 @@ def copy_probe():
 
 
 # Source files of each kernel family (plus the shared device headers).
-KERNEL_SOURCES = {"k_gather": ["k_gather.hip"], "k_gather_res": ["k_gather.hip"], "k_update": ["k_gather.hip"],
+KERNEL_SOURCES = {"k_gather": ["k_gather.hip", "update.h"], "k_gather_res": ["k_gather_res.hip", "update.h"],
+                  "k_update": ["k_gather.hip", "update.h"],
                   "k_project": ["k_project.hip"],
                   "k_rows": ["k_fft.hip"], "k_cols": ["k_fft.hip"]}
 

@@ -13,7 +13,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB_PATH = os.path.join(PKG, "libvp.so")
 
-SOURCES = ["plan.cpp", "k_fft.hip", "k_project.hip", "k_gather.hip", "k_vox.hip", "k_eval.hip", "k_kplanes.hip", "k_nu.hip", "runtime.hip", "batch.hip",
+SOURCES = ["plan.cpp", "k_fft.hip", "k_project.hip", "k_gather.hip", "k_gather_res.hip", "k_vox.hip", "k_eval.hip", "k_kplanes.hip", "k_nu.hip", "runtime.hip", "batch.hip",
            "tune.hip", "kp_runtime.hip", "server.cpp"]
 
 HIP_FLAGS = [

@@ -142,8 +142,12 @@ vp_status group_build(SliceGroup* g, const std::vector<vp_session*>& sessions, c
     L.upd = g->d_tasks + off[6]; L.n_upd = (int)upd.size();
     L.n_slices = ns;
     L.epi = EPI_ADAM_TV;
-    for (const vp_session* se : sessions)
+    uint64_t nvox = 0;
+    for (const vp_session* se : sessions) {
         if (se->lists.epi != EPI_ADAM_TV) L.epi = EPI_GENERIC;
+        nvox += se->plan->voxels();
+    }
+    L.stream = stream_for(nvox, VP_OPT_ADAM);
     g->lists = L;
     return VP_OK;
 }

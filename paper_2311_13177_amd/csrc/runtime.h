@@ -47,9 +47,14 @@ struct StageLists {
     int re_proj = 0, re_gath = 0;  // largest staged regions (elements)
     size_t lds_res = 0;            // resident-parts gather: LDS bytes of the largest knot
     int epi = EPI_GENERIC;         // optimiser epilogue every slice of the step can take
+    int stream = 0;                // the step's state exceeds kStreamState (EPI_STREAM)
 };
 
 StageLists plan_lists(const vp_plan* p, const DeviceTables* t, const Layout* L, const DeviceLayout* dl);
+// Whether a step over `voxels` voxels (summed over its slices) streams its state.
+inline int stream_for(uint64_t voxels, int optimizer) {
+    return voxels * sizeof(float2) * (optimizer == VP_OPT_ADAM ? 4u : 2u) > kStreamState ? 1 : 0;
+}
 // The gather of a step's layout (resident-parts or staged a few parts at a time).
 hipError_t launch_gather_lists(const KArgs& a, int mode, const StageLists& L, hipStream_t s);
 // Tile shape for a plan under options: explicit tiles from the options, else the tuned

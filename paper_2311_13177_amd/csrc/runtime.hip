@@ -196,6 +196,7 @@ void launch_step(const KArgs& base, const StageLists& L, hipStream_t s, hipError
     }
     KArgs a = base;
     a.epi = L.epi;
+    a.stream = L.stream;
     hipError_t e;
 #define MARK(i)                                                                         \
     do {                                                                                \
@@ -730,6 +731,7 @@ struct vp_nu_session {
         KArgs a{};
         a.one = s->desc;
         a.epi = L.epi;
+        a.stream = L.stream;
         a.tasks = L.gath; a.ntasks = L.n_gath;
         a.snap = 1;  // the last kernel reads the snapshot and advances the counter
         a.nslices = 1;
@@ -991,6 +993,7 @@ extern "C" vp_status vp_step(const vp_plan* p, const vp_options* o, const vp_c64
     a.one.step = cnt;
     const StageLists L = plan_lists(p, sc.t, lay, dl);
     a.epi = epi_for(o->optimizer, o->tv_weight, o->l1_weight);
+    a.stream = stream_for(p->voxels(), o->optimizer);
     a.tasks = L.upd;
     a.ntasks = L.n_upd;
     if (e == hipSuccess) e = launch_update(a, tl.upd_sc, sc.s);
@@ -1114,6 +1117,7 @@ vp_status session_alloc(const vp_plan* p, const vp_options* o, const vp_c64* ksp
     s->desc.step = s->step_dev;
     s->lists = plan_lists(p, s->tabs, s->layout, s->dlayout);
     s->lists.epi = epi_for(o->optimizer, o->tv_weight, o->l1_weight);
+    s->lists.stream = stream_for(p->voxels(), o->optimizer);
     if (tl.upd_sc && (st = session_ensure_grad(s.get())) != VP_OK) return st;
     *out = s.release();
     return VP_OK;

@@ -186,6 +186,7 @@ vp_status tune_plan(const vp_plan* p, const vp_options* o, Tiles* out) {
                         KArgs a{};
                         a.one = s->desc;
                         a.epi = s->lists.epi;
+                        a.stream = s->lists.stream;
                         a.tasks = dl->t_gath;
                         a.ntasks = (int)L->t_gath.size();
                         float ms = 0.f;
@@ -226,6 +227,7 @@ vp_status tune_plan(const vp_plan* p, const vp_options* o, Tiles* out) {
         KArgs a{};
         a.one = s->desc;
         a.epi = s->lists.epi;
+        a.stream = s->lists.stream;
         a.tasks = dl->t_upd;
         a.ntasks = (int)L->t_upd.size();
         float ms = 0.f;

@@ -175,6 +175,7 @@ struct KArgs {
     const float2* in0;
     double* dpart;
     int epi;                     // optimiser epilogue of GATHER_STEP and the update pass (EPI_*)
+    int stream;                  // with epi == EPI_ADAM_TV: take the EPI_STREAM variant
     int live_n;                  // COL_RAW_FWD / COL_INVERSE: 0, or the size m of a centred image
                                  // in the frame: only rows [0, m - m/2) and [n - m/2, n) are
                                  // nonzero on input (forward) or needed on output (inverse)
@@ -205,8 +206,19 @@ constexpr int kNuTable = 4096;
 enum { GATHER_STORE = 0, GATHER_STEP = 1 };
 // Optimiser epilogue variants: EPI_GENERIC takes the optimiser and the regulariser
 // weights from each slice's descriptor at run time; EPI_ADAM_TV is the same arithmetic
-// compiled for slices that all run Adam with TV on and L1 off.
-enum { EPI_GENERIC = 0, EPI_ADAM_TV = 1 };
+// compiled for slices that all run Adam with TV on and L1 off. EPI_STREAM (with
+// EPI_ADAM_TV) makes the update's moment loads and its stores non-temporal, for steps
+// whose state exceeds kStreamState; it changes no result.
+enum { EPI_GENERIC = 0, EPI_ADAM_TV = 1, EPI_STREAM = 2 };
+__host__ __device__ constexpr bool epi_fast(int e) { return (e & EPI_ADAM_TV) != 0; }
+// cache-policy operand of the update's streamed loads and stores (2: non-temporal)
+__host__ __device__ constexpr int epi_cache(int e) { return (e & EPI_STREAM) ? 2 : 0; }
+// A step whose optimiser state (both volume copies and the Adam moments) exceeds the
+// 256 MiB Infinity Cache streams it (EPI_STREAM): the state cannot stay cached from one
+// step to the next, and keeping the moments and the new values out of the caches leaves
+// them to the volume planes that neighbouring work items read again. A smaller state
+// stays cached between steps and is not streamed.
+constexpr size_t kStreamState = (size_t)256 << 20;
 __host__ __device__ constexpr int epi_for(int optimizer, float tv_w, float l1_w) {
     return (optimizer == VP_OPT_ADAM && tv_w != 0.f && l1_w == 0.f) ? EPI_ADAM_TV : EPI_GENERIC;
 }
