@@ -88,9 +88,12 @@ __device__ __forceinline__ void voxel_update(const UpdateArgs& u, bool tv, bool 
 template <int PPT, int EPI>
 struct ColumnStream {
     static constexpr int WR = PPT + 2;  // window rows y0 - 1 .. y0 + PPT
-    // the moments are read once and the moments and values written once per step:
-    // streamed (non-temporal) when the step's state does not fit the caches (EPI_STREAM),
-    // so they do not push out the volume planes that neighbouring items read again
+    // the moments are read once and the moments and values written once per step, and an
+    // item's loads of the previous knot's planes are the last of the three reads of those
+    // planes (by that knot's own item and the items of the knots on either side) in every
+    // work-list order: these accesses are streamed (non-temporal) when the step's state
+    // does not fit the caches (EPI_STREAM), so they do not push out the planes that other
+    // items read again
     static constexpr int CP = epi_cache(EPI);
     int nn, x;
     bool tv, adam, l1;
@@ -161,7 +164,7 @@ struct ColumnStream {
                 mm[i] = buf_ld<CP>(rM, rb[i + 1], so);
                 vv[i] = buf_ld<CP>(rW, rb[i + 1], so);
             }
-            if (tv && u.kt > 0) tp[i] = buf_ld(rP, rb[i + 1], so);
+            if (tv && u.kt > 0) tp[i] = buf_ld<CP>(rP, rb[i + 1], so);
             if (tv && u.kt + 1 < u.T) tn[i] = buf_ld(rN, rb[i + 1], so);
         }
     }
