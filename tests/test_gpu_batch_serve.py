@@ -167,3 +167,26 @@ def test_served_requests_match_the_oracle_fits(gpu_lib):
         assert got[i]["status"] == 0 and got[i]["steps_done"] == probs[i][2].n_steps
         r = check_converged(name, got[i]["proj"], got[i]["final_loss"])
         print(name, r)
+
+
+def test_streamed_batch_equals_cached_solo(gpu_lib):
+    """A step whose state (both volume copies and the Adam moments) exceeds the 256 MiB
+    Infinity Cache streams its update: the moment loads, the update's stores and the
+    previous knot's plane loads carry the non-temporal cache hint. That changes no result.
+    The batch of a 192^2 x 32 x 16 slice (604 MB of state) and a 64^2 slice streams, the
+    64^2 slice alone (4 MB) does not, and its results must agree bit for bit, with the
+    batch in its own tile shape, in the phased gather and with the separate update pass
+    (each kernel's streamed variant)."""
+    from paper_2311_13177_amd import binding as B
+
+    cases = [configs.CONFIGS["dynamic_192"](), configs.CONFIGS["static_64"]()]
+    plans = [B.Plan.from_geometry(c.geometry()) for c in cases]
+    ys = [O.simulate_measurements(c) for c in cases]
+    steps = [12, 9]
+    solo = [B.vp_reconstruct(p, y, B.vp_options_default(n_steps=st)) for p, y, st in zip(plans, ys, steps)]
+    for tiles in (None, (2, 2, 4, 2, 0, 8, 8, 0), (4, 1, 4, 4, 4, 8, 8, 0)):
+        extra = {} if tiles is None else dict(tiles=tiles)
+        opts = [B.vp_options_default(n_steps=st, **extra) for st in steps]
+        got = B.vp_batch_reconstruct(plans, ys, opts)
+        for g, s in zip(got, solo):
+            assert g["status"] == 0 and _same(g, s), tiles
