@@ -207,16 +207,17 @@ enum { GATHER_STORE = 0, GATHER_STEP = 1 };
 // Optimiser epilogue variants: EPI_GENERIC takes the optimiser and the regulariser
 // weights from each slice's descriptor at run time; EPI_ADAM_TV is the same arithmetic
 // compiled for slices that all run Adam with TV on and L1 off. EPI_STREAM (with
-// EPI_ADAM_TV) makes the update's moment loads and its stores non-temporal, for steps
-// whose state exceeds kStreamState; it changes no result.
+// EPI_ADAM_TV) makes the update's moment loads, its stores and its loads of the previous
+// knot's planes non-temporal, for steps whose state exceeds kStreamState; it changes no
+// result.
 enum { EPI_GENERIC = 0, EPI_ADAM_TV = 1, EPI_STREAM = 2 };
 __host__ __device__ constexpr bool epi_fast(int e) { return (e & EPI_ADAM_TV) != 0; }
 // cache-policy operand of the update's streamed loads and stores (2: non-temporal)
 __host__ __device__ constexpr int epi_cache(int e) { return (e & EPI_STREAM) ? 2 : 0; }
 // A step whose optimiser state (both volume copies and the Adam moments) exceeds the
 // 256 MiB Infinity Cache streams it (EPI_STREAM): the state cannot stay cached from one
-// step to the next, and keeping the moments and the new values out of the caches leaves
-// them to the volume planes that neighbouring work items read again. A smaller state
+// step to the next, and keeping the data read or written for the last time out of the
+// caches leaves them to the volume planes that neighbouring work items read again. A smaller state
 // stays cached between steps and is not streamed.
 constexpr size_t kStreamState = (size_t)256 << 20;
 __host__ __device__ constexpr int epi_for(int optimizer, float tv_w, float l1_w) {
